@@ -1,0 +1,186 @@
+/*
+ * snapmd -- batched SNAP + Finnis-Sinclair Langevin propagation for adaptive parareal,
+ * hand-written HIP for MI355X (gfx950), FP64 throughout.
+ *
+ * The method (Gorynina, Legoll, Lelievre, Perez, "Combining machine-learned and
+ * empirical force fields with the parareal algorithm") integrates the Langevin
+ * equation of its "Algorithm" section with a fine propagator F (L steps on the
+ * fine potential) and a coarse propagator C (L steps on the coarse potential) that
+ * share their Gaussian increments, and corrects a coarse sweep with the jumps
+ * F - C ("Parareal method", "Adaptive parareal method").  This library provides:
+ *
+ *   snap_forces       SNAP forces (fine potential of the "MD settings" section)
+ *   eam_forces        Finnis-Sinclair EAM forces (coarse potential)
+ *   langevin_steps    BAOAB Langevin steps for a ragged batch of systems
+ *   parareal_iterate  one corrected iteration of adaptive parareal on a window
+ *   snap_beta_grad    dE/dbeta and d(force loss)/dbeta (SNAP coefficient gradients)
+ *
+ * Conventions (every entry point):
+ *   - Units: metal (A, ps, eV, amu, K).  Momenta are p = m v (amu A / ps).
+ *   - Per-atom arrays are DEVICE pointers, SoA: x[3][n_atoms] (x row, y row, z row),
+ *     likewise p and f.  Positions may be unwrapped; periodic boundaries are applied
+ *     by minimum image in each system's orthorhombic box.
+ *   - Parameter structs and the batch descriptor hold small HOST arrays; they are
+ *     copied (and validated) at each call, and need not outlive it.
+ *   - The caller owns every array it passes; the library never frees or retains a
+ *     caller pointer past the call.  The library owns its context workspace.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = default stream) and is
+ *     asynchronous, except where a function says it synchronises.
+ *   - Return value: SNAPMD_OK (0) or a negative SNAPMD_E* code; snapmd_last_error()
+ *     then describes the failure.  No C++ exception crosses this boundary.
+ *     Errors detected on the device (neighbour overflow, non-finite state) are
+ *     latched in the context and reported by the next synchronising call
+ *     (parareal_iterate, snapmd_sync).
+ *   - A context is not thread safe; calls on one context must not overlap.
+ */
+#ifndef SNAPMD_H
+#define SNAPMD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct snapmd_ctx snapmd_ctx;
+
+enum {
+    SNAPMD_OK = 0,
+    SNAPMD_EINVAL = -1,       /* invalid argument (message names it)            */
+    SNAPMD_ENOMEM = -2,       /* device allocation failed                       */
+    SNAPMD_EHIP = -3,         /* HIP runtime error                              */
+    SNAPMD_EUNSUPPORTED = -4, /* twojmax outside {2, 4, 6, 8}                   */
+    SNAPMD_ENONFINITE = -5,   /* NaN/Inf in a propagated state (message: slab)  */
+    SNAPMD_EOVERFLOW = -6     /* an atom has more than SNAPMD_MAX_NEIGH neighbours */
+};
+
+#define SNAPMD_MAX_NEIGH 64   /* neighbours per atom within the cutoff           */
+#define SNAPMD_ACCUMULATE 1u  /* flags: add into f / e_atom instead of overwriting */
+
+/* Create a context on HIP device `hip_device`.  Returns SNAPMD_OK and *out, or an
+ * error (then *out is NULL). */
+int snapmd_create(snapmd_ctx **out, int hip_device);
+/* Release the context and its device workspace (NULL is a no-op). */
+void snapmd_destroy(snapmd_ctx *ctx);
+/* Message of the last error on this context ("" if none).  Owned by the context. */
+const char *snapmd_last_error(const snapmd_ctx *ctx);
+/* Synchronise `stream` and report any error latched by device-side checks. */
+int snapmd_sync(snapmd_ctx *ctx, void *stream);
+
+/* Ragged batch of independent periodic systems stored back to back.
+ * offset[s] .. offset[s+1]-1 are the atoms of system s (offset[0] = 0,
+ * nondecreasing); box[3*s + 0..2] are its orthorhombic edges. */
+typedef struct {
+    int32_t n_sys;
+    const int32_t *offset; /* host [n_sys + 1] */
+    const double *box;     /* host [3 * n_sys] */
+} snapmd_batch;
+
+/* SNAP (spectral neighbour analysis potential; the paper's fine force field,
+ * "MD settings" section, defined by Thompson et al.):
+ *   E_i = beta[0] + sum_k beta[k] B_k(i),  k over the canonical (j1, j2, j) triples
+ *   0 <= 2j2 <= 2j1 <= 2j <= twojmax (lexicographic order), B_k the bispectrum of
+ *   the neighbour density of atom i within rcut (switching function
+ *   (cos(pi (r - rmin0)/(rcut - rmin0)) + 1)/2, self term and unit weights).
+ * Requirements: twojmax in {2, 4, 6, 8}; n_coeff = number of canonical triples
+ * (5, 14, 30, 55); 0 < rfac0 < 1; 0 <= rmin0 < rcut; rcut < min(box)/2. */
+typedef struct {
+    int32_t twojmax;
+    double rcut, rfac0, rmin0;
+    int32_t n_coeff;
+    const double *beta; /* host [n_coeff + 1]; beta[0] = constant term */
+} snapmd_snap;
+
+/* Finnis-Sinclair EAM (the coarse potential; the paper's EAM of its "MD settings"
+ * section is replaced by this tungsten parameterisation):
+ *   E = sum_i [ -A sqrt(rho_i) + 1/2 sum_j V(r_ij) ],  rho_i = sum_j phi(r_ij),
+ *   phi(r) = (r - d)^2 for r < d,  V(r) = (r - c)^2 (c0 + c1 r + c2 r^2) for r < c.
+ * Requirements: d > 0, c > 0, max(d, c) < min(box)/2. */
+typedef struct {
+    double A, d, c, c0, c1, c2;
+} snapmd_fs;
+
+/* Langevin integration (the equation of the paper's "Algorithm" section with masses:
+ * dq = p/m dt, dp = -grad V dt - gamma p dt + sqrt(2 gamma m kB T) dW), discretised
+ * by BAOAB: half kick, half drift, exact Ornstein-Uhlenbeck step, half drift, force,
+ * half kick -- one force evaluation per step.  The Gaussian increment of atom i
+ * (local index within its system) at global step n is drawn from Philox4x64-10
+ * with key (seed, 0) and counter (noise_id[s], n, i, 0) through Box-Muller, so a fine
+ * and a coarse run of the same slab see identical noise (paper, "Parareal method"). */
+typedef struct {
+    double dt;                     /* ps, > 0                           */
+    double gamma;                  /* 1/ps, >= 0                        */
+    double mass;                   /* amu, > 0 (one species)            */
+    const double *T_sys;           /* host [n_sys] temperatures, K >= 0 */
+    uint64_t seed;
+    const int64_t *step0_sys;      /* host [n_sys] global step of the first step */
+    const int32_t *noise_id_sys;   /* host [n_sys] noise stream ids (>= 0)       */
+    int32_t scheme;                /* 0 = BAOAB (only value accepted)            */
+} snapmd_langevin;
+
+enum { SNAPMD_POT_FS = 0, SNAPMD_POT_FS_SNAP = 1 };
+
+/* SNAP forces of every system of the batch.
+ * x: device [3][n_atoms] positions.  f: device [3][n_atoms] forces (eV/A), overwritten
+ * (or added to with SNAPMD_ACCUMULATE).  e_atom: device [n_atoms] SNAP energies (eV)
+ * or NULL.  Asynchronous on `stream`. */
+int snap_forces(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *batch,
+                const double *x, double *f, double *e_atom, uint32_t flags, void *stream);
+
+/* Finnis-Sinclair forces of every system (same layout and flags as snap_forces). */
+int eam_forces(snapmd_ctx *ctx, const snapmd_fs *fs, const snapmd_batch *batch, const double *x,
+               double *f, double *e_atom, uint32_t flags, void *stream);
+
+/* Advance every system of the batch by n_steps BAOAB steps in place.
+ * potential: SNAPMD_POT_FS (coarse: FS only; snap may be NULL) or SNAPMD_POT_FS_SNAP
+ * (fine: FS + SNAP).  The force is evaluated from x at the start (the propagators of
+ * the paper's "Parareal method" section restart at every slab).  x, p: device
+ * [3][n_atoms], updated.  f_out: device [3][n_atoms] force at the final positions,
+ * or NULL.  Asynchronous on `stream`. */
+int langevin_steps(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, const snapmd_fs *fs,
+                   const snapmd_batch *batch, const snapmd_langevin *lang, int32_t n_steps,
+                   double *x, double *p, double *f_out, void *stream);
+
+/* One corrected iteration of (adaptive) parareal for ONE trajectory of n_atoms atoms
+ * ("Adaptive parareal method": the body of its inner while loop) on the window
+ * [n_in, *n_fi]:
+ *   prev_n := cur_n for n_in <= n <= *n_fi;
+ *   J_n := F(prev_n) - C(prev_n) for n_in <= n < *n_fi, all slabs at once;
+ *   for n = n_in .. *n_fi - 1:  cur_{n+1} := C(cur_n) + J_n;
+ *       delta := sum_{m=n_in+1}^{n+1} |cur_m - prev_m| / sum_{m=n_in+1}^{n+1} |prev_m|
+ *       (Euclidean norms of the 3 n_atoms position vectors);
+ *       if delta > delta_expl: *n_fi := max(n, n_in + 1); stop.
+ * Slab n covers global steps n*L .. n*L + L - 1 of noise stream lang->noise_id_sys[0]
+ * (lang->step0_sys, T_sys[0] used for every slab; step0_sys is ignored).
+ * q_cur, p_cur: device [n_slots][3][n_atoms] (n_slots > *n_fi), states cur_n; read
+ * on [n_in, *n_fi], written on (n_in, *n_fi].  q_prev, p_prev: device, same shape,
+ * receive prev_n on [n_in, *n_fi].  batch must hold exactly one system (its box).
+ * delta_expl = +inf gives the classical algorithm.  Writes *delta_out and possibly
+ * *n_fi (host).  Synchronises `stream` once; returns SNAPMD_ENONFINITE if a state
+ * became non-finite (the message names the slab). */
+int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs,
+                     const snapmd_batch *batch, const snapmd_langevin *lang, int32_t L,
+                     int32_t n_in, int32_t *n_fi, double *q_prev, double *p_prev, double *q_cur,
+                     double *p_cur, double delta_expl, double *delta_out, void *stream);
+
+/* Gradients of the SNAP model with respect to its coefficients beta (for a
+ * force-matching fit; the loss is the caller's):
+ *   dEdbeta[k]  = sum_i B_k(i)                    (k = 1..K; dEdbeta[0] = n_atoms)
+ *   gradF[k]    = sum_i w_i . dF_i/dbeta_k = -sum_i w_i . d(sum_j B_k(j))/dx_i
+ * for a per-atom weight field w (e.g. the loss gradient dLoss/dF).
+ * x, w: device [3][n_atoms]; dEdbeta, gradF: device [n_coeff + 1], overwritten
+ * (per system totals are summed over the batch).  Asynchronous on `stream`. */
+int snap_beta_grad(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *batch,
+                   const double *x, const double *w, double *dEdbeta, double *gradF,
+                   void *stream);
+
+/* Bispectrum components of every atom (the features E_i is linear in):
+ * B: device [n_coeff][n_atoms], B[k-1][i] = B_k(i) for k = 1..n_coeff (same order as
+ * beta[1..]).  Asynchronous on `stream`. */
+int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *batch,
+                      const double *x, double *B, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNAPMD_H */

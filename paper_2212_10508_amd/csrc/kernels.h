@@ -1,0 +1,68 @@
+// Device-side argument bundles and kernel launchers of snapmd (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snapmd {
+
+// Ragged batch resident on the device.
+struct BatchDev {
+    int N = 0;              // total atoms
+    int n_sys = 0;
+    const int *off = nullptr;     // [n_sys + 1]
+    const double *box = nullptr;  // [3 * n_sys]
+};
+
+struct FsParams {
+    double A, d, c, c0, c1, c2;
+};
+
+struct SnapGeoParams {
+    double rcut, rfac0, rmin0;
+};
+
+// SNAP coefficient-dependent tables on the device.
+struct SnapDev {
+    int J = 0, K = 0, nh = 0;
+    SnapGeoParams gp{};
+    double beta0 = 0.0;
+    const double *nrm = nullptr, *ymult = nullptr;
+    const int *ystart = nullptr;
+    const uint32_t *yidx = nullptr;
+    const double *ycoef = nullptr;  // CG product * beta tilde
+    const int *bstart = nullptr, *bel = nullptr;
+    const uint32_t *bidx = nullptr;
+    const double *bcg = nullptr;
+};
+
+struct LangevinDev {
+    double dt, c1, mass;
+    uint64_t seed;
+    const double *sig = nullptr;       // [n_sys] sqrt((1 - c1^2) m kB T / mvv2e)
+    const int64_t *step0 = nullptr;    // [n_sys]
+    const int *noise_id = nullptr;     // [n_sys]
+};
+
+// Per-evaluation scratch (owned by the context).
+struct Work {
+    size_t Pcap = 0;        // pair capacity (N * kMaxNeigh)
+    int *nbr = nullptr, *cnt = nullptr, *poff = nullptr, *pair_i = nullptr, *pair_j = nullptr, *rev = nullptr;
+    int *status = nullptr;  // device error bits: 1 neighbour overflow, 4 asymmetric list
+    double *rho = nullptr;
+    double *geo = nullptr;  // [20][Pcap]
+    double *dedr = nullptr; // [3][Pcap]
+    double2 *u = nullptr, *ytil = nullptr;  // [nh][N]
+};
+
+void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, hipStream_t st);
+void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w, double *f, double *e_atom,
+               int accumulate, hipStream_t st);
+void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
+                 double *e_atom, int accumulate, hipStream_t st);
+void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st);
+void launch_bispectrum(const BatchDev &bd, const SnapDev &sd, Work &w, double *B, hipStream_t st);
+void launch_baoab_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
+                      hipStream_t st);
+void launch_baoab_post(const BatchDev &bd, double *p, const double *f, double dt, hipStream_t st);
+
+}  // namespace snapmd

@@ -1,0 +1,679 @@
+// HIP kernels of snapmd for gfx950 (CDNA4), FP64 throughout.
+//
+// Per force evaluation of a ragged batch (atoms of all systems back to back):
+//   neighbours : k_neigh_build (brute force within the atom's own system, minimum
+//                image) -> k_scan (prefix sums) -> k_compact (atom-major pair list,
+//                CSR) -> k_reverse (index of the opposite pair)
+//   FS EAM     : k_fs_rho -> k_fs_force (deterministic gather over the full list)
+//   SNAP       : k_pair_geo (Cayley-Klein parameters, switching function and their
+//                gradients, once per pair) -> k_density<J,C> (u, one column chain of
+//                the Wigner-D polynomials per lane) -> k_adjoint (Y by the coupling
+//                program, energy by Euler's identity) -> k_dedr<J> (per pair
+//                dE_i/dr_ij = Re sum conj(Y~) d(f_c P)) -> k_gather (F_k = sum over
+//                pairs (g_kj - g_jk), no atomics, deterministic)
+//   BAOAB      : k_baoab_pre (B A O A with Philox4x64-10 Gaussians) / k_baoab_post (B)
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+#include "snapmd_internal.h"
+
+namespace snapmd {
+
+#define KB_EV 8.617333262145179e-5
+#define MVV2E 1.0364269652680506e-4
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a*b + c*d
+__device__ __forceinline__ double2 cmul2(double2 a, double2 b, double2 c, double2 d) {
+    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, fma(c.x, d.x, -c.y * d.y))),
+                        fma(a.x, b.y, fma(a.y, b.x, fma(c.x, d.y, c.y * d.x))));
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+__device__ __forceinline__ int sys_of(const int *__restrict__ off, int n_sys, int i) {
+    int lo = 0, hi = n_sys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double mimg(double d, double L) { return d - L * rint(d / L); }
+
+// ---------------------------------------------------------------------------
+// Neighbour lists
+// ---------------------------------------------------------------------------
+__global__ void k_neigh_build(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
+                              const double *__restrict__ x, double rc2, int *__restrict__ nbr,
+                              int *__restrict__ cnt, int *__restrict__ status) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int s = sys_of(off, n_sys, i);
+    const int j0 = off[s], j1 = off[s + 1];
+    const double Lx = box[3 * s], Ly = box[3 * s + 1], Lz = box[3 * s + 2];
+    const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
+    int c = 0;
+    for (int j = j0; j < j1; ++j) {
+        if (j == i) continue;
+        const double dx = mimg(x[j] - xi, Lx), dy = mimg(x[N + j] - yi, Ly), dz = mimg(x[2 * N + j] - zi, Lz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < rc2) {
+            if (c < kMaxNeigh) nbr[(size_t)i * kMaxNeigh + c] = j;
+            ++c;
+        }
+    }
+    if (c > kMaxNeigh) {
+        atomicOr(status, 1);
+        c = kMaxNeigh;
+    }
+    cnt[i] = c;
+}
+
+// Exclusive prefix sum of cnt[0..N) into poff[0..N] (one workgroup of 1024 threads).
+__global__ void __launch_bounds__(1024) k_scan(int N, const int *__restrict__ cnt, int *__restrict__ poff) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int chunk = (N + 1023) / 1024;
+    const int b = t * chunk, e = min(N, b + chunk);
+    int s = 0;
+    for (int i = b; i < e; ++i) s += cnt[i];
+    part[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int v = (t >= d) ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - s;  // exclusive
+    for (int i = b; i < e; ++i) {
+        poff[i] = run;
+        run += cnt[i];
+    }
+    if (t == 1023) poff[N] = part[1023];
+}
+
+__global__ void k_compact(int N, const int *__restrict__ nbr, const int *__restrict__ cnt,
+                          const int *__restrict__ poff, int *__restrict__ pair_i, int *__restrict__ pair_j) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int p0 = poff[i], c = cnt[i];
+    for (int t = 0; t < c; ++t) {
+        pair_i[p0 + t] = i;
+        pair_j[p0 + t] = nbr[(size_t)i * kMaxNeigh + t];
+    }
+}
+
+__global__ void k_reverse(int N, const int *__restrict__ poff, const int *__restrict__ pair_i,
+                          const int *__restrict__ pair_j, int *__restrict__ rev, int *__restrict__ status) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= poff[N]) return;
+    const int i = pair_i[p], j = pair_j[p];
+    int r = -1;
+    for (int t = poff[j]; t < poff[j + 1]; ++t)
+        if (pair_j[t] == i) { r = t; break; }
+    if (r < 0) { atomicOr(status, 4); r = p; }
+    rev[p] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Finnis-Sinclair EAM
+// ---------------------------------------------------------------------------
+__global__ void k_fs_rho(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
+                         const double *__restrict__ x, const int *__restrict__ poff,
+                         const int *__restrict__ pair_j, double d, double *__restrict__ rho) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int s = sys_of(off, n_sys, i);
+    const double Lx = box[3 * s], Ly = box[3 * s + 1], Lz = box[3 * s + 2];
+    const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
+    double acc = 0.0;
+    for (int p = poff[i]; p < poff[i + 1]; ++p) {
+        const int j = pair_j[p];
+        const double dx = mimg(x[j] - xi, Lx), dy = mimg(x[N + j] - yi, Ly), dz = mimg(x[2 * N + j] - zi, Lz);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (r < d) acc += (r - d) * (r - d);
+    }
+    rho[i] = acc;
+}
+
+__global__ void k_fs_force(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
+                           const double *__restrict__ x, const int *__restrict__ poff,
+                           const int *__restrict__ pair_j, FsParams fp, const double *__restrict__ rho,
+                           double *__restrict__ f, double *__restrict__ e_atom, int accumulate) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int s = sys_of(off, n_sys, i);
+    const double Lx = box[3 * s], Ly = box[3 * s + 1], Lz = box[3 * s + 2];
+    const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
+    const double ri = rho[i];
+    const double dFi = ri > 0.0 ? -fp.A / (2.0 * sqrt(ri)) : 0.0;
+    double fx = 0.0, fy = 0.0, fz = 0.0, ep = 0.0;
+    for (int p = poff[i]; p < poff[i + 1]; ++p) {
+        const int j = pair_j[p];
+        const double dx = mimg(x[j] - xi, Lx), dy = mimg(x[N + j] - yi, Ly), dz = mimg(x[2 * N + j] - zi, Lz);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        double dEdr = 0.0;
+        if (r < fp.c) {
+            const double t = r - fp.c, poly = fp.c0 + r * (fp.c1 + r * fp.c2);
+            ep += 0.5 * t * t * poly;
+            dEdr += 2.0 * t * poly + t * t * (fp.c1 + 2.0 * fp.c2 * r);
+        }
+        if (r < fp.d) {
+            const double rj = rho[j];
+            const double dFj = rj > 0.0 ? -fp.A / (2.0 * sqrt(rj)) : 0.0;
+            dEdr += (dFi + dFj) * 2.0 * (r - fp.d);
+        }
+        if (r < fp.c || r < fp.d) {
+            const double w = dEdr / r;
+            fx += w * dx;
+            fy += w * dy;
+            fz += w * dz;
+        }
+    }
+    if (accumulate) {
+        f[i] += fx; f[N + i] += fy; f[2 * N + i] += fz;
+    } else {
+        f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
+    }
+    if (e_atom) {
+        const double e = -fp.A * sqrt(ri) + ep;
+        e_atom[i] = accumulate ? e_atom[i] + e : e;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SNAP: per-pair geometry
+//   theta0 = rfac0 pi (r - rmin0)/(rcut - rmin0); a = cos theta0 - i z sin(theta0)/r,
+//   b = (y - i x) sin(theta0)/r;  f_c = (cos(pi (r - rmin0)/(rcut - rmin0)) + 1)/2.
+// geo layout (SoA, stride Pcap): 0 ar, 1 ai, 2 br, 3 bi, 4 fc,
+//   5..7 d(ar)/dx_al, 8..10 d(ai), 11..13 d(br), 14..16 d(bi), 17..19 d(fc)
+// ---------------------------------------------------------------------------
+__global__ void k_pair_geo(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
+                           const double *__restrict__ x, const int *__restrict__ poff,
+                           const int *__restrict__ pair_i, const int *__restrict__ pair_j, SnapGeoParams sp,
+                           double *__restrict__ geo, size_t Pcap) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= poff[N]) return;
+    const int i = pair_i[p], j = pair_j[p];
+    const int s = sys_of(off, n_sys, i);
+    double d[3];
+    d[0] = mimg(x[j] - x[i], box[3 * s]);
+    d[1] = mimg(x[N + j] - x[N + i], box[3 * s + 1]);
+    d[2] = mimg(x[2 * N + j] - x[2 * N + i], box[3 * s + 2]);
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double g[20];
+#pragma unroll
+    for (int q = 0; q < 20; ++q) g[q] = 0.0;
+    g[0] = 1.0;
+    if (r < sp.rcut) {
+        const double w = M_PI / (sp.rcut - sp.rmin0);
+        const double c = sp.rfac0 * w;
+        double sth, cth, sph, cph;
+        sincos(c * (r - sp.rmin0), &sth, &cth);
+        sincos(w * (r - sp.rmin0), &sph, &cph);
+        const double rinv = 1.0 / r;
+        const double sr = sth * rinv;                                // sin(theta0)/r
+        const double dsr = (c * cth * r - sth) * rinv * rinv;        // d(sr)/dr
+        g[0] = cth;
+        g[1] = -d[2] * sr;
+        g[2] = d[1] * sr;
+        g[3] = -d[0] * sr;
+        g[4] = 0.5 * (cph + 1.0);
+        const double dfdr = -0.5 * w * sph;
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+            const double u = d[al] * rinv;                           // dr/dx_al
+            g[5 + al] = -sth * c * u;
+            g[8 + al] = -d[2] * dsr * u - (al == 2 ? sr : 0.0);
+            g[11 + al] = d[1] * dsr * u + (al == 1 ? sr : 0.0);
+            g[14 + al] = -d[0] * dsr * u - (al == 0 ? sr : 0.0);
+            g[17 + al] = dfdr * u;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 20; ++q) geo[q * Pcap + p] = g[q];
+}
+
+// ---------------------------------------------------------------------------
+// Column chains of the Wigner-D polynomials P^n[k][l] for a fixed column l.
+// advance: level n -> n+1 in place (descending k):  P[k] = b P[k-1] + conj(a) P[k].
+// mirror : at odd level n = 2l-1, column l-1 -> column l:
+//          P_l[k] = (-1)^(l-k) conj(P_{l-1}[n-k]).
+// ---------------------------------------------------------------------------
+template <int J, int N>
+__device__ __forceinline__ void chain_advance(double2 (&P)[J + 1], double2 b, double2 ab) {
+    P[N + 1] = cmul(b, P[N]);
+#pragma unroll
+    for (int k = N; k >= 1; --k) P[k] = cmul2(b, P[k - 1], ab, P[k]);
+    P[0] = cmul(ab, P[0]);
+}
+
+template <int J, int N>
+__device__ __forceinline__ void chain_advance_d(double2 (&P)[J + 1], double2 (&dP)[3][J + 1], double2 b,
+                                                double2 ab, const double2 (&db)[3], const double2 (&dab)[3]) {
+#pragma unroll
+    for (int al = 0; al < 3; ++al) dP[al][N + 1] = cmul2(db[al], P[N], b, dP[al][N]);
+    P[N + 1] = cmul(b, P[N]);
+#pragma unroll
+    for (int k = N; k >= 1; --k) {
+#pragma unroll
+        for (int al = 0; al < 3; ++al)
+            dP[al][k] = cadd(cmul2(db[al], P[k - 1], b, dP[al][k - 1]), cmul2(dab[al], P[k], ab, dP[al][k]));
+        P[k] = cmul2(b, P[k - 1], ab, P[k]);
+    }
+#pragma unroll
+    for (int al = 0; al < 3; ++al) dP[al][0] = cmul2(dab[al], P[0], ab, dP[al][0]);
+    P[0] = cmul(ab, P[0]);
+}
+
+template <int J, int L>  // n = 2L-1 (odd), column L-1 -> L, in place
+__device__ __forceinline__ void chain_mirror(double2 (&P)[J + 1]) {
+    constexpr int n = 2 * L - 1;
+#pragma unroll
+    for (int k = 0; 2 * k < n; ++k) {
+        const double2 lo = P[k], hi = P[n - k];
+        const double sk = ((L - k) & 1) ? -1.0 : 1.0;            // (-1)^(L-k)
+        const double sh = ((L - (n - k)) & 1) ? -1.0 : 1.0;      // (-1)^(L-(n-k))
+        P[k] = make_double2(sk * hi.x, -sk * hi.y);
+        P[n - k] = make_double2(sh * lo.x, -sh * lo.y);
+    }
+}
+
+// acc index of (n, k) in chain C: elements of levels 2C .. n-1 come first
+__host__ __device__ constexpr int chain_acc_idx(int C, int n, int k) {
+    int o = 0;
+    for (int m = 2 * C; m < n; ++m) o += m + 1;
+    return o + k;
+}
+
+template <int J, int C, int N>
+__device__ __forceinline__ void density_step(double2 (&P)[J + 1], double2 (&acc)[chain_acc_idx(C, J + 1, 0)],
+                                             double2 b, double2 ab, double fc) {
+    if constexpr (N > 2 * C) chain_advance<J, N - 1>(P, b, ab);
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+        acc[chain_acc_idx(C, N, k)].x = fma(fc, P[k].x, acc[chain_acc_idx(C, N, k)].x);
+        acc[chain_acc_idx(C, N, k)].y = fma(fc, P[k].y, acc[chain_acc_idx(C, N, k)].y);
+    }
+    if constexpr (N < J) density_step<J, C, N + 1>(P, acc, b, ab, fc);
+}
+
+template <int J, int C, int c>  // staircase: column c at level 2c -> column c+1 at level 2c+2
+__device__ __forceinline__ void staircase(double2 (&P)[J + 1], double2 b, double2 ab) {
+    if constexpr (c < C) {
+        chain_advance<J, 2 * c>(P, b, ab);
+        chain_mirror<J, c + 1>(P);
+        chain_advance<J, 2 * c + 1>(P, b, ab);
+        staircase<J, C, c + 1>(P, b, ab);
+    }
+}
+
+// u (half storage, [e][N] double2) for column C of every atom: lane = atom.
+template <int J, int C>
+__device__ void density_column(int N, const int *__restrict__ poff, const double *__restrict__ geo, size_t Pcap,
+                               const double *__restrict__ nrm, double2 *__restrict__ u) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    constexpr int NA = chain_acc_idx(C, J + 1, 0);
+    double2 acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = make_double2(0.0, 0.0);
+    const int p1 = poff[i + 1];
+    for (int p = poff[i]; p < p1; ++p) {
+        const double fc = geo[4 * Pcap + p];
+        if (fc == 0.0) continue;
+        const double2 a = make_double2(geo[p], geo[Pcap + p]);
+        const double2 b = make_double2(geo[2 * Pcap + p], geo[3 * Pcap + p]);
+        const double2 ab = cconj(a);
+        double2 P[J + 1];
+        P[0] = make_double2(1.0, 0.0);
+        staircase<J, C, 0>(P, b, ab);
+        density_step<J, C, 2 * C>(P, acc, b, ab, fc);
+    }
+#pragma unroll
+    for (int n = 2 * C; n <= J; ++n)
+#pragma unroll
+        for (int k = 0; k <= n; ++k) {
+            const int e = half_idx(n, k, C);
+            const double s = nrm[e];
+            const double2 v = acc[chain_acc_idx(C, n, k)];
+            u[(size_t)e * N + i] = make_double2((k == C ? 1.0 : 0.0) + s * v.x, s * v.y);
+        }
+}
+
+template <int J>
+__global__ void __launch_bounds__(128) k_density(int N, const int *__restrict__ poff, const double *__restrict__ geo,
+                                                 size_t Pcap, const double *__restrict__ nrm,
+                                                 double2 *__restrict__ u) {
+    switch (blockIdx.y) {
+        case 0: density_column<J, 0>(N, poff, geo, Pcap, nrm, u); break;
+        case 1: if constexpr (J >= 2) density_column<J, 1>(N, poff, geo, Pcap, nrm, u); break;
+        case 2: if constexpr (J >= 4) density_column<J, 2>(N, poff, geo, Pcap, nrm, u); break;
+        case 3: if constexpr (J >= 6) density_column<J, 3>(N, poff, geo, Pcap, nrm, u); break;
+        case 4: if constexpr (J >= 8) density_column<J, 4>(N, poff, geo, Pcap, nrm, u); break;
+        default: break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint by the coupling program (lane = atom):
+//   Y_e = sum_t coef_t op1(u[h1]) op2(u[h2]),  Y~_e = Y_e * Nrm_e * mult_e,
+//   E_i = beta0 + (1/3) sum_e mult_e Re(conj(Y_e) u_e)   (Euler, E cubic in u).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_adjoint(int N, int nh, const double2 *__restrict__ u,
+                                                 const int *__restrict__ ystart, const uint32_t *__restrict__ yidx,
+                                                 const double *__restrict__ ycoef, const double *__restrict__ nrm,
+                                                 const double *__restrict__ ymult, double beta0,
+                                                 double2 *__restrict__ ytil, double *__restrict__ e_atom,
+                                                 int accumulate_e) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double esum = 0.0;
+    for (int e = 0; e < nh; ++e) {
+        const int t0 = ystart[e], t1 = ystart[e + 1];
+        double2 acc = make_double2(0.0, 0.0);
+        for (int t = t0; t < t1; ++t) {
+            const uint32_t w = yidx[t];
+            double2 a = u[(size_t)(w & 0xfffu) * N + i];
+            double2 b = u[(size_t)((w >> 12) & 0xfffu) * N + i];
+            if (w & (1u << 24)) a.y = -a.y;
+            if (w & (1u << 25)) b.y = -b.y;
+            const double c = ycoef[t];
+            acc.x = fma(c, a.x * b.x - a.y * b.y, acc.x);
+            acc.y = fma(c, a.x * b.y + a.y * b.x, acc.y);
+        }
+        const double m = ymult[e];
+        const double2 ue = u[(size_t)e * N + i];
+        esum += m * (acc.x * ue.x + acc.y * ue.y);
+        const double s = m * nrm[e];
+        ytil[(size_t)e * N + i] = make_double2(s * acc.x, s * acc.y);
+    }
+    if (e_atom) {
+        const double en = beta0 + esum / 3.0;
+        e_atom[i] = accumulate_e ? e_atom[i] + en : en;
+    }
+}
+
+// Bispectrum by the coupling program (lane = atom): B[t][i].
+__global__ void __launch_bounds__(256) k_bispectrum(int N, int K, const double2 *__restrict__ u,
+                                                    const int *__restrict__ bstart, const uint32_t *__restrict__ bidx,
+                                                    const int *__restrict__ bel, const double *__restrict__ bcg,
+                                                    double *__restrict__ B) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int t = 0; t < K; ++t) {
+        double acc = 0.0;
+        for (int q = bstart[t]; q < bstart[t + 1]; ++q) {
+            const uint32_t w = bidx[q];
+            double2 a = u[(size_t)(w & 0xfffu) * N + i];
+            double2 b = u[(size_t)((w >> 12) & 0xfffu) * N + i];
+            if (w & (1u << 24)) a.y = -a.y;
+            if (w & (1u << 25)) b.y = -b.y;
+            const double2 ue = u[(size_t)bel[q] * N + i];
+            const double2 z = cmul(a, b);
+            acc = fma(bcg[q], ue.x * z.x + ue.y * z.y, acc);
+        }
+        B[(size_t)t * N + i] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dE_i/dr_ij per pair: lane = pair.  Column chains l = 0..J/2 of P and dP/dx_al,
+// the column at level 2l+1 saved as the seed of chain l+1 (mirror).
+//   S0 = sum Re(conj(Y~) P),  S_al = sum Re(conj(Y~) dP_al),  g_al = dfc_al S0 + fc S_al
+// ---------------------------------------------------------------------------
+template <int J, int C, int N>
+__device__ __forceinline__ void dedr_level(double2 (&P)[J + 1], double2 (&dP)[3][J + 1], double2 (&sP)[J + 1],
+                                           double2 (&sdP)[3][J + 1], double2 b, double2 ab,
+                                           const double2 (&db)[3], const double2 (&dab)[3],
+                                           const double2 *__restrict__ yt, int Natoms, double &S0,
+                                           double (&S)[3]) {
+    if constexpr (N > 2 * C) chain_advance_d<J, N - 1>(P, dP, b, ab, db, dab);
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+        if (2 * C == N && 2 * k > N) continue;  // mirrored half of the middle column
+        const double2 y = yt[(size_t)half_idx(N, k, C) * Natoms];
+        S0 = fma(y.x, P[k].x, fma(y.y, P[k].y, S0));
+#pragma unroll
+        for (int al = 0; al < 3; ++al) S[al] = fma(y.x, dP[al][k].x, fma(y.y, dP[al][k].y, S[al]));
+    }
+    if constexpr (N == 2 * C + 1 && 2 * C + 2 <= J) {
+#pragma unroll
+        for (int k = 0; k <= N; ++k) {
+            sP[k] = P[k];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) sdP[al][k] = dP[al][k];
+        }
+    }
+    if constexpr (N < J) dedr_level<J, C, N + 1>(P, dP, sP, sdP, b, ab, db, dab, yt, Natoms, S0, S);
+}
+
+template <int J, int C>
+__device__ __forceinline__ void dedr_chain(double2 (&P)[J + 1], double2 (&dP)[3][J + 1], double2 (&sP)[J + 1],
+                                           double2 (&sdP)[3][J + 1], double2 b, double2 ab,
+                                           const double2 (&db)[3], const double2 (&dab)[3],
+                                           const double2 *__restrict__ yt, int Natoms, double &S0,
+                                           double (&S)[3]) {
+    if constexpr (C == 0) {
+        P[0] = make_double2(1.0, 0.0);
+#pragma unroll
+        for (int al = 0; al < 3; ++al) dP[al][0] = make_double2(0.0, 0.0);
+    } else {
+        constexpr int n = 2 * C - 1;
+#pragma unroll
+        for (int k = 0; k <= n; ++k) {
+            P[k] = sP[k];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) dP[al][k] = sdP[al][k];
+        }
+        chain_mirror<J, C>(P);
+#pragma unroll
+        for (int al = 0; al < 3; ++al) chain_mirror<J, C>(dP[al]);
+        chain_advance_d<J, n>(P, dP, b, ab, db, dab);
+    }
+    dedr_level<J, C, 2 * C>(P, dP, sP, sdP, b, ab, db, dab, yt, Natoms, S0, S);
+    if constexpr (2 * C + 2 <= J) dedr_chain<J, C + 1>(P, dP, sP, sdP, b, ab, db, dab, yt, Natoms, S0, S);
+}
+
+template <int J>
+__global__ void __launch_bounds__(64) k_dedr(int N, const int *__restrict__ poff, const int *__restrict__ pair_i,
+                                             const double *__restrict__ geo, size_t Pcap,
+                                             const double2 *__restrict__ ytil, double *__restrict__ dedr) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= poff[N]) return;
+    const double fc = geo[4 * Pcap + p];
+    if (fc == 0.0) {
+        dedr[p] = 0.0;
+        dedr[Pcap + p] = 0.0;
+        dedr[2 * Pcap + p] = 0.0;
+        return;
+    }
+    const int i = pair_i[p];
+    const double2 a = make_double2(geo[p], geo[Pcap + p]);
+    const double2 b = make_double2(geo[2 * Pcap + p], geo[3 * Pcap + p]);
+    const double2 ab = cconj(a);
+    double2 db[3], dab[3];
+    double dfc[3];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        dab[al] = make_double2(geo[(5 + al) * Pcap + p], -geo[(8 + al) * Pcap + p]);
+        db[al] = make_double2(geo[(11 + al) * Pcap + p], geo[(14 + al) * Pcap + p]);
+        dfc[al] = geo[(17 + al) * Pcap + p];
+    }
+    double2 P[J + 1], dP[3][J + 1], sP[J + 1], sdP[3][J + 1];
+    double S0 = 0.0, S[3] = {0.0, 0.0, 0.0};
+    dedr_chain<J, 0>(P, dP, sP, sdP, b, ab, db, dab, ytil + i, N, S0, S);
+#pragma unroll
+    for (int al = 0; al < 3; ++al) dedr[al * Pcap + p] = fma(dfc[al], S0, fc * S[al]);
+}
+
+// F_k (+)= sum_{p in pairs(k)} (g_p - g_rev(p))
+__global__ void k_gather(int N, const int *__restrict__ poff, const int *__restrict__ rev,
+                         const double *__restrict__ dedr, size_t Pcap, double *__restrict__ f, int accumulate) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int p = poff[k]; p < poff[k + 1]; ++p) {
+        const int q = rev[p];
+        g0 += dedr[p] - dedr[q];
+        g1 += dedr[Pcap + p] - dedr[Pcap + q];
+        g2 += dedr[2 * Pcap + p] - dedr[2 * Pcap + q];
+    }
+    if (accumulate) {
+        f[k] += g0; f[N + k] += g1; f[2 * N + k] += g2;
+    } else {
+        f[k] = g0; f[N + k] = g1; f[2 * N + k] = g2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t (&c)[4], uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ void gauss3(uint64_t seed, uint64_t noise_id, uint64_t step, uint64_t atom,
+                                       double &g0, double &g1, double &g2) {
+    uint64_t c[4] = {noise_id, step, atom, 0};
+    philox4x64_10(c, seed, 0);
+    const double two53 = 1.0 / 9007199254740992.0;
+    const double u1 = 1.0 - (double)(c[0] >> 11) * two53;
+    const double u2 = (double)(c[1] >> 11) * two53;
+    const double u3 = 1.0 - (double)(c[2] >> 11) * two53;
+    const double u4 = (double)(c[3] >> 11) * two53;
+    const double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u3));
+    double s2, c2, s4, c4;
+    sincos(2.0 * M_PI * u2, &s2, &c2);
+    sincos(2.0 * M_PI * u4, &s4, &c4);
+    g0 = r1 * c2;
+    g1 = r1 * s2;
+    g2 = r2 * c4;
+}
+
+// B (half kick), A (half drift), O (exact OU), A (half drift)
+__global__ void k_baoab_pre(int N, int n_sys, const int *__restrict__ off, double *__restrict__ x,
+                            double *__restrict__ p, const double *__restrict__ f, LangevinDev ld, int s_step) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int s = sys_of(off, n_sys, i);
+    const uint64_t gstep = (uint64_t)(ld.step0[s] + s_step);
+    double g[3];
+    gauss3(ld.seed, (uint64_t)ld.noise_id[s], gstep, (uint64_t)(i - off[s]), g[0], g[1], g[2]);
+    const double hk = 0.5 * ld.dt / MVV2E, hd = 0.5 * ld.dt / ld.mass, sig = ld.sig[s];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        double pp = p[al * N + i] + hk * f[al * N + i];
+        double xx = x[al * N + i] + hd * pp;
+        pp = ld.c1 * pp + sig * g[al];
+        xx = xx + hd * pp;
+        p[al * N + i] = pp;
+        x[al * N + i] = xx;
+    }
+}
+
+__global__ void k_baoab_post(int N, double *__restrict__ p, const double *__restrict__ f, double dt) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 3 * N) return;
+    p[q] = p[q] + (0.5 * dt / MVV2E) * f[q];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, hipStream_t st) {
+    const int N = bd.N;
+    hipLaunchKernelGGL(k_neigh_build, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, rc * rc,
+                       w.nbr, w.cnt, w.status);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, N, w.cnt, w.poff);
+    hipLaunchKernelGGL(k_compact, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.nbr, w.cnt, w.poff, w.pair_i, w.pair_j);
+    hipLaunchKernelGGL(k_reverse, dim3(nblk(w.Pcap, 256)), dim3(256), 0, st, N, w.poff, w.pair_i, w.pair_j, w.rev,
+                       w.status);
+}
+
+void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w, double *f, double *e_atom,
+               int accumulate, hipStream_t st) {
+    const int N = bd.N;
+    hipLaunchKernelGGL(k_fs_rho, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, w.poff,
+                       w.pair_j, fp.d, w.rho);
+    hipLaunchKernelGGL(k_fs_force, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, w.poff,
+                       w.pair_j, fp, w.rho, f, e_atom, accumulate);
+}
+
+template <int J>
+static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
+                          double *e_atom, int accumulate, hipStream_t st) {
+    const int N = bd.N;
+    hipLaunchKernelGGL(k_pair_geo, dim3(nblk(w.Pcap, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
+                       w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
+    hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 128), J / 2 + 1), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap,
+                       sd.nrm, w.u);
+    hipLaunchKernelGGL(k_adjoint, dim3(nblk(N, 256)), dim3(256), 0, st, N, sd.nh, w.u, sd.ystart, sd.yidx, sd.ycoef,
+                       sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate);
+    hipLaunchKernelGGL(k_dedr<J>, dim3(nblk(w.Pcap, 64)), dim3(64), 0, st, N, w.poff, w.pair_i, w.geo, w.Pcap,
+                       w.ytil, w.dedr);
+    hipLaunchKernelGGL(k_gather, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.poff, w.rev, w.dedr, w.Pcap, f,
+                       accumulate);
+}
+
+void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
+                 double *e_atom, int accumulate, hipStream_t st) {
+    switch (J) {
+        case 2: launch_snap_J<2>(bd, x, sd, w, f, e_atom, accumulate, st); break;
+        case 4: launch_snap_J<4>(bd, x, sd, w, f, e_atom, accumulate, st); break;
+        case 6: launch_snap_J<6>(bd, x, sd, w, f, e_atom, accumulate, st); break;
+        case 8: launch_snap_J<8>(bd, x, sd, w, f, e_atom, accumulate, st); break;
+        default: break;
+    }
+}
+
+void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st) {
+    const int N = bd.N;
+    hipLaunchKernelGGL(k_pair_geo, dim3(nblk(w.Pcap, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
+                       w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
+    switch (J) {
+        case 2: hipLaunchKernelGGL(k_density<2>, dim3(nblk(N, 128), 2), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
+        case 4: hipLaunchKernelGGL(k_density<4>, dim3(nblk(N, 128), 3), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
+        case 6: hipLaunchKernelGGL(k_density<6>, dim3(nblk(N, 128), 4), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
+        case 8: hipLaunchKernelGGL(k_density<8>, dim3(nblk(N, 128), 5), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
+        default: break;
+    }
+}
+
+void launch_bispectrum(const BatchDev &bd, const SnapDev &sd, Work &w, double *B, hipStream_t st) {
+    const int N = bd.N;
+    hipLaunchKernelGGL(k_bispectrum, dim3(nblk(N, 256)), dim3(256), 0, st, N, sd.K, w.u, sd.bstart, sd.bidx, sd.bel,
+                       sd.bcg, B);
+}
+
+void launch_baoab_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_baoab_pre, dim3(nblk(bd.N, 256)), dim3(256), 0, st, bd.N, bd.n_sys, bd.off, x, p, f, ld,
+                       s_step);
+}
+
+void launch_baoab_post(const BatchDev &bd, double *p, const double *f, double dt, hipStream_t st) {
+    hipLaunchKernelGGL(k_baoab_post, dim3(nblk(3 * (size_t)bd.N, 256)), dim3(256), 0, st, bd.N, p, f, dt);
+}
+
+}  // namespace snapmd

@@ -1,0 +1,288 @@
+"""Thin Python binding of the snapmd C ABI (include/snapmd.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of ``libsnapmd.so``; this module converts
+torch tensors (device memory, current HIP stream) and NumPy arrays (small host
+parameter arrays) into the C structs and checks return codes.  There is no CPU
+fallback: if the library is missing, importing the entry points raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsnapmd.so")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ENONFINITE, EOVERFLOW = 0, -1, -2, -3, -4, -5, -6
+MAX_NEIGH = 64
+ACCUMULATE = 1
+POT_FS, POT_FS_SNAP = 0, 1
+
+
+class SnapmdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("snapmd error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Batch(C.Structure):
+    _fields_ = [("n_sys", C.c_int32), ("offset", C.POINTER(C.c_int32)), ("box", C.POINTER(C.c_double))]
+
+
+class Snap(C.Structure):
+    _fields_ = [("twojmax", C.c_int32), ("rcut", C.c_double), ("rfac0", C.c_double), ("rmin0", C.c_double),
+                ("n_coeff", C.c_int32), ("beta", C.POINTER(C.c_double))]
+
+
+class Fs(C.Structure):
+    _fields_ = [("A", C.c_double), ("d", C.c_double), ("c", C.c_double), ("c0", C.c_double),
+                ("c1", C.c_double), ("c2", C.c_double)]
+
+
+class Langevin(C.Structure):
+    _fields_ = [("dt", C.c_double), ("gamma", C.c_double), ("mass", C.c_double),
+                ("T_sys", C.POINTER(C.c_double)), ("seed", C.c_uint64),
+                ("step0_sys", C.POINTER(C.c_int64)), ("noise_id_sys", C.POINTER(C.c_int32)),
+                ("scheme", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsnapmd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("snapmd HIP library not built: run `python -m paper_2212_10508_amd.build` "
+                          "(expected %s)" % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    P, i32, u32, d = C.c_void_p, C.c_int32, C.c_uint32, C.c_double
+    L.snapmd_create.argtypes = [C.POINTER(P), C.c_int]
+    L.snapmd_create.restype = C.c_int
+    L.snapmd_destroy.argtypes = [P]
+    L.snapmd_destroy.restype = None
+    L.snapmd_last_error.argtypes = [P]
+    L.snapmd_last_error.restype = C.c_char_p
+    L.snapmd_sync.argtypes = [P, P]
+    L.snapmd_sync.restype = C.c_int
+    L.snap_forces.argtypes = [P, C.POINTER(Snap), C.POINTER(Batch), P, P, P, u32, P]
+    L.snap_forces.restype = C.c_int
+    L.eam_forces.argtypes = [P, C.POINTER(Fs), C.POINTER(Batch), P, P, P, u32, P]
+    L.eam_forces.restype = C.c_int
+    L.langevin_steps.argtypes = [P, C.c_int, C.POINTER(Snap), C.POINTER(Fs), C.POINTER(Batch),
+                                 C.POINTER(Langevin), i32, P, P, P, P]
+    L.langevin_steps.restype = C.c_int
+    L.parareal_iterate.argtypes = [P, C.POINTER(Snap), C.POINTER(Fs), C.POINTER(Batch), C.POINTER(Langevin),
+                                   i32, i32, C.POINTER(i32), P, P, P, P, d, C.POINTER(d), P]
+    L.parareal_iterate.restype = C.c_int
+    L.snap_beta_grad.argtypes = [P, C.POINTER(Snap), C.POINTER(Batch), P, P, P, P, P]
+    L.snap_beta_grad.restype = C.c_int
+    L.snapmd_bispectrum.argtypes = [P, C.POINTER(Snap), C.POINTER(Batch), P, P, P]
+    L.snapmd_bispectrum.restype = C.c_int
+    _lib = L
+    return L
+
+
+# ----------------------------------------------------------------------------
+# marshalling helpers
+# ----------------------------------------------------------------------------
+def _dev(t, name, shape=None, dtype=torch.float64):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) torch tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous %s tensor" % (name, dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s (got %s)" % (name, tuple(shape), tuple(t.shape)))
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class _Keep:
+    """Holds the NumPy arrays referenced by a C struct for the duration of a call."""
+
+    def __init__(self):
+        self.refs = []
+
+    def arr(self, a, dtype, ctype):
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.refs.append(a)
+        return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def make_batch(keep, offset, box):
+    offset = np.asarray(offset, np.int32)
+    box = np.asarray(box, np.float64).reshape(-1)
+    return Batch(len(offset) - 1, keep.arr(offset, np.int32, C.c_int32), keep.arr(box, np.float64, C.c_double))
+
+
+def make_snap(keep, J, beta, rcut=4.73, rfac0=0.99363, rmin0=0.0):
+    beta = np.asarray(beta, np.float64)
+    return Snap(J, rcut, rfac0, rmin0, len(beta) - 1, keep.arr(beta, np.float64, C.c_double))
+
+
+def make_fs(fs):
+    return Fs(fs["A"], fs["d"], fs["c"], fs["c0"], fs["c1"], fs["c2"])
+
+
+def make_langevin(keep, n_sys, dt, gamma, mass, T, seed, step0, noise_id):
+    T = np.broadcast_to(np.asarray(T, np.float64), (n_sys,))
+    step0 = np.broadcast_to(np.asarray(step0, np.int64), (n_sys,))
+    noise_id = np.broadcast_to(np.asarray(noise_id, np.int32), (n_sys,))
+    return Langevin(dt, gamma, mass, keep.arr(T, np.float64, C.c_double), seed,
+                    keep.arr(step0, np.int64, C.c_int64), keep.arr(noise_id, np.int32, C.c_int32), 0)
+
+
+# ----------------------------------------------------------------------------
+# context and entry points
+# ----------------------------------------------------------------------------
+class Context:
+    """A snapmd context on one HIP device (owns the library workspace)."""
+
+    def __init__(self, device=0):
+        L = lib()
+        h = C.c_void_p()
+        rc = L.snapmd_create(C.byref(h), int(device))
+        if rc != OK:
+            raise SnapmdError(rc, "snapmd_create(%d) failed" % device)
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().snapmd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != OK:
+            raise SnapmdError(rc, lib().snapmd_last_error(self.h).decode())
+
+    def sync(self, stream=None):
+        self._check(lib().snapmd_sync(self.h, _stream(stream)))
+
+    # -- forces ------------------------------------------------------------
+    def snap_forces(self, x, offset, box, J, beta, f=None, e_atom=None, accumulate=False, rcut=4.73,
+                    rfac0=0.99363, rmin0=0.0, stream=None):
+        N = int(offset[-1])
+        k = _Keep()
+        b, s = make_batch(k, offset, box), make_snap(k, J, beta, rcut, rfac0, rmin0)
+        if f is None:
+            f = torch.empty((3, N), dtype=torch.float64, device=x.device)
+        self._check(lib().snap_forces(self.h, C.byref(s), C.byref(b), _dev(x, "x", (3, N)), _dev(f, "f", (3, N)),
+                                      _dev(e_atom, "e_atom", (N,)), ACCUMULATE if accumulate else 0,
+                                      _stream(stream)))
+        return f
+
+    def eam_forces(self, x, offset, box, fs, f=None, e_atom=None, accumulate=False, stream=None):
+        N = int(offset[-1])
+        k = _Keep()
+        b, p = make_batch(k, offset, box), make_fs(fs)
+        if f is None:
+            f = torch.empty((3, N), dtype=torch.float64, device=x.device)
+        self._check(lib().eam_forces(self.h, C.byref(p), C.byref(b), _dev(x, "x", (3, N)), _dev(f, "f", (3, N)),
+                                     _dev(e_atom, "e_atom", (N,)), ACCUMULATE if accumulate else 0,
+                                     _stream(stream)))
+        return f
+
+    def bispectrum(self, x, offset, box, J, beta, rcut=4.73, rfac0=0.99363, rmin0=0.0, stream=None):
+        N = int(offset[-1])
+        k = _Keep()
+        b, s = make_batch(k, offset, box), make_snap(k, J, beta, rcut, rfac0, rmin0)
+        B = torch.empty((len(beta) - 1, N), dtype=torch.float64, device=x.device)
+        self._check(lib().snapmd_bispectrum(self.h, C.byref(s), C.byref(b), _dev(x, "x", (3, N)),
+                                            _dev(B, "B"), _stream(stream)))
+        return B
+
+    # -- dynamics ----------------------------------------------------------
+    def langevin_steps(self, potential, x, p, offset, box, n_steps, *, dt, gamma, mass, T, seed, step0,
+                       noise_id, fs, J=None, beta=None, f_out=None, rcut=4.73, rfac0=0.99363, rmin0=0.0,
+                       stream=None):
+        N = int(offset[-1])
+        S = len(offset) - 1
+        k = _Keep()
+        b = make_batch(k, offset, box)
+        s = make_snap(k, J, beta, rcut, rfac0, rmin0) if potential == POT_FS_SNAP else None
+        p_fs = make_fs(fs)
+        lg = make_langevin(k, S, dt, gamma, mass, T, seed, step0, noise_id)
+        self._check(lib().langevin_steps(self.h, potential, C.byref(s) if s is not None else None,
+                                         C.byref(p_fs), C.byref(b), C.byref(lg), int(n_steps),
+                                         _dev(x, "x", (3, N)), _dev(p, "p", (3, N)),
+                                         _dev(f_out, "f_out", (3, N)), _stream(stream)))
+
+    def parareal_iterate(self, q_prev, p_prev, q_cur, p_cur, box, L, n_in, n_fi, delta_expl, *, dt, gamma,
+                         mass, T, seed, noise_id, fs, J, beta, rcut=4.73, rfac0=0.99363, rmin0=0.0,
+                         stream=None):
+        """Returns (delta, n_fi_after)."""
+        nslots, three, N = q_cur.shape
+        k = _Keep()
+        b = make_batch(k, [0, N], box)
+        s = make_snap(k, J, beta, rcut, rfac0, rmin0)
+        p_fs = make_fs(fs)
+        lg = make_langevin(k, 1, dt, gamma, mass, T, seed, 0, noise_id)
+        nfi = C.c_int32(int(n_fi))
+        delta = C.c_double(0.0)
+        shape = (nslots, 3, N)
+        self._check(lib().parareal_iterate(self.h, C.byref(s), C.byref(p_fs), C.byref(b), C.byref(lg), int(L),
+                                           int(n_in), C.byref(nfi), _dev(q_prev, "q_prev", shape),
+                                           _dev(p_prev, "p_prev", shape), _dev(q_cur, "q_cur", shape),
+                                           _dev(p_cur, "p_cur", shape), float(delta_expl), C.byref(delta),
+                                           _stream(stream)))
+        return delta.value, nfi.value
+
+    def snap_beta_grad(self, x, w, offset, box, J, beta, rcut=4.73, rfac0=0.99363, rmin0=0.0, stream=None):
+        """Returns (dE/dbeta [K+1], sum_i w_i . dF_i/dbeta [K+1]) as device tensors."""
+        N = int(offset[-1])
+        K1 = len(beta)
+        k = _Keep()
+        b, s = make_batch(k, offset, box), make_snap(k, J, beta, rcut, rfac0, rmin0)
+        dE = torch.empty(K1, dtype=torch.float64, device=x.device)
+        gF = torch.empty(K1, dtype=torch.float64, device=x.device)
+        self._check(lib().snap_beta_grad(self.h, C.byref(s), C.byref(b), _dev(x, "x", (3, N)),
+                                         _dev(w, "w", (3, N)), _dev(dE, "dE"), _dev(gF, "gF"),
+                                         _stream(stream)))
+        return dE, gF
+
+
+_default = {}
+
+
+def context(device=0):
+    """Process-wide context per device."""
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def snap_forces(x, offset, box, J, beta, **kw):
+    return context(x.device.index or 0).snap_forces(x, offset, box, J, beta, **kw)
+
+
+def eam_forces(x, offset, box, fs, **kw):
+    return context(x.device.index or 0).eam_forces(x, offset, box, fs, **kw)
+
+
+def langevin_steps(potential, x, p, offset, box, n_steps, **kw):
+    return context(x.device.index or 0).langevin_steps(potential, x, p, offset, box, n_steps, **kw)
+
+
+def parareal_iterate(q_prev, p_prev, q_cur, p_cur, box, L, n_in, n_fi, delta_expl, **kw):
+    return context(q_cur.device.index or 0).parareal_iterate(q_prev, p_prev, q_cur, p_cur, box, L, n_in,
+                                                             n_fi, delta_expl, **kw)
+
+
+def snap_beta_grad(x, w, offset, box, J, beta, **kw):
+    return context(x.device.index or 0).snap_beta_grad(x, w, offset, box, J, beta, **kw)
