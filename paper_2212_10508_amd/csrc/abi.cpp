@@ -37,6 +37,9 @@ struct SnapDevTables {
     uint32_t *yidx = nullptr, *bidx = nullptr;
     std::vector<double> beta;  // coefficients ycoef was built for
     std::vector<double> ycoef_host;
+    AdjointHost adj;
+    double *adj_cgm = nullptr, *adj_coef = nullptr;
+    int *adj_coef_off = nullptr, *adj_roles = nullptr;
 };
 
 }  // namespace
@@ -220,6 +223,26 @@ int prepare_snap(snapmd_ctx *ctx, const snapmd_snap *s, double min_half_box, Sna
         }
         if ((rc = upload(ctx, D.ycoef, D.ycoef_host.data(), D.ycoef_host.size(), st))) return rc;
     }
+    {
+        AdjointHost &A = D.adj;
+        const int oldJ = A.J;
+        adjoint_tables(J, s->beta, A);
+        if (oldJ != J) {
+            if ((rc = dalloc(ctx, &D.adj_cgm, A.cgm.size())) || (rc = dalloc(ctx, &D.adj_roles, A.roles.size())) ||
+                (rc = dalloc(ctx, &D.adj_coef, A.coef.size())) ||
+                (rc = dalloc(ctx, &D.adj_coef_off, A.coef_off.size())))
+                return rc;
+            HIPCHK(hipMemcpy(D.adj_cgm, A.cgm.data(), A.cgm.size() * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(D.adj_roles, A.roles.data(), A.roles.size() * sizeof(int), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(D.adj_coef_off, A.coef_off.data(), A.coef_off.size() * sizeof(int),
+                             hipMemcpyHostToDevice));
+        }
+        if (A.coef_changed) {
+            if ((rc = upload(ctx, D.adj_coef, A.coef.data(), A.coef.size(), st))) return rc;
+            A.coef_changed = false;
+        }
+        sd.adj = AdjointDev{D.adj_cgm, D.adj_coef, D.adj_coef_off, D.adj_roles, A.role_len};
+    }
     sd.J = J;
     sd.K = T.K;
     sd.nh = T.nh;
@@ -277,6 +300,7 @@ int snapmd_create(snapmd_ctx **out, int hip_device) {
     if (hipSetDevice(hip_device) != hipSuccess) return SNAPMD_EHIP;
     snapmd_ctx *ctx = new snapmd_ctx();
     ctx->device = hip_device;
+    adjoint_init_attributes();
     if (dalloc(ctx, &ctx->w.status, 1) != SNAPMD_OK || hipMemset(ctx->w.status, 0, sizeof(int)) != hipSuccess) {
         snapmd_destroy(ctx);
         return SNAPMD_ENOMEM;

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace snapmd {
 
 // Ragged batch resident on the device.
@@ -21,6 +23,23 @@ struct SnapGeoParams {
     double rcut, rfac0, rmin0;
 };
 
+// Tables of the LDS-staged adjoint kernel (host copies, built per twojmax / beta).
+struct AdjointHost {
+    int J = -1;
+    std::vector<double> cgm;       // row-pair motif coupling constants (beta free)
+    std::vector<double> coef;      // beta~ * C^{j m}_{j1 m1, j2 m2} per (2m, block, m1, j)
+    std::vector<int> coef_off;     // [(2J+1) * n_blocks] start of each (2m, block) run
+    std::vector<int> roles;        // [8][role_len] output rows 2m of each wave (> J ends)
+    int role_len = 0;
+    std::vector<double> beta;
+    bool coef_changed = false;
+};
+struct AdjointDev {
+    const double *cgm = nullptr, *coef = nullptr;
+    const int *coef_off = nullptr, *roles = nullptr;
+    int role_len = 0;
+};
+
 // SNAP coefficient-dependent tables on the device.
 struct SnapDev {
     int J = 0, K = 0, nh = 0;
@@ -33,6 +52,7 @@ struct SnapDev {
     const int *bstart = nullptr, *bel = nullptr;
     const uint32_t *bidx = nullptr;
     const double *bcg = nullptr;
+    AdjointDev adj;
 };
 
 struct LangevinDev {
@@ -60,6 +80,10 @@ void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w,
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
                  double *e_atom, int accumulate, hipStream_t st);
 void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st);
+void adjoint_tables(int J, const double *beta, AdjointHost &A);
+void adjoint_init_attributes();
+void launch_adjoint(int J, const AdjointDev &ad, int N, const double2 *u, const double *nrm, const double *ymult,
+                    double beta0, double2 *ytil, double *e_atom, int accumulate, hipStream_t st);
 void launch_bispectrum(const BatchDev &bd, const SnapDev &sd, Work &w, double *B, hipStream_t st);
 void launch_baoab_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
                       hipStream_t st);

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "device_util.h"
 #include "kernels.h"
 #include "snapmd_internal.h"
 
@@ -22,29 +23,6 @@ namespace snapmd {
 
 #define KB_EV 8.617333262145179e-5
 #define MVV2E 1.0364269652680506e-4
-
-// ---------------------------------------------------------------------------
-// small helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// a*b + c*d
-__device__ __forceinline__ double2 cmul2(double2 a, double2 b, double2 c, double2 d) {
-    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, fma(c.x, d.x, -c.y * d.y))),
-                        fma(a.x, b.y, fma(a.y, b.x, fma(c.x, d.y, c.y * d.x))));
-}
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-
-__device__ __forceinline__ int sys_of(const int *__restrict__ off, int n_sys, int i) {
-    int lo = 0, hi = n_sys - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= i) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 __device__ __forceinline__ double mimg(double d, double L) { return d - L * rint(d / L); }
 
@@ -289,10 +267,9 @@ __device__ __forceinline__ void chain_mirror(double2 (&P)[J + 1]) {
 }
 
 // acc index of (n, k) in chain C: elements of levels 2C .. n-1 come first
+// (sum_{m=2C}^{n-1} (m+1) in closed form)
 __host__ __device__ constexpr int chain_acc_idx(int C, int n, int k) {
-    int o = 0;
-    for (int m = 2 * C; m < n; ++m) o += m + 1;
-    return o + k;
+    return n * (n + 1) / 2 - C * (2 * C + 1) + k;
 }
 
 template <int J, int C, int N>
@@ -628,8 +605,7 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
                        w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
     hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 128), J / 2 + 1), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap,
                        sd.nrm, w.u);
-    hipLaunchKernelGGL(k_adjoint, dim3(nblk(N, 256)), dim3(256), 0, st, N, sd.nh, w.u, sd.ystart, sd.yidx, sd.ycoef,
-                       sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate);
+    launch_adjoint(J, sd.adj, N, w.u, sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate, st);
     hipLaunchKernelGGL(k_dedr<J>, dim3(nblk(w.Pcap, 64)), dim3(64), 0, st, N, w.poff, w.pair_i, w.geo, w.Pcap,
                        w.ytil, w.dedr);
     hipLaunchKernelGGL(k_gather, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.poff, w.rev, w.dedr, w.Pcap, f,

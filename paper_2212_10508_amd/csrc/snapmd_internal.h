@@ -24,10 +24,12 @@ namespace snapmd {
 constexpr int kMaxJ = 8;
 constexpr int kMaxNeigh = 64;
 
+// half_off(n) = sum_{m<n} (m+1)(floor(m/2)+1), in closed form so that it folds to a
+// constant wherever n is one (levels m = 2i and 2i+1 contribute (i+1)(4i+3)).
 __host__ __device__ constexpr int half_off(int n) {
-    int o = 0;
-    for (int m = 0; m < n; ++m) o += (m + 1) * (m / 2 + 1);
-    return o;
+    const int q = n / 2;
+    const int pairs = 4 * ((q - 1) * q * (2 * q - 1) / 6) + 7 * (q * (q - 1) / 2) + 3 * q;
+    return pairs + ((n & 1) ? (2 * q + 1) * (q + 1) : 0);
 }
 __host__ __device__ constexpr int half_idx(int n, int k, int l) { return half_off(n) + l * (n + 1) + k; }
 __host__ __device__ constexpr int n_half(int J) { return half_off(J + 1); }
