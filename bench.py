@@ -1,0 +1,202 @@
+#!/usr/bin/env python
+"""Benchmark of the batched SNAP + Langevin fine propagator inside adaptive parareal.
+
+One step = one corrected parareal iteration (parareal_iterate) on a window of 64 slabs
+of one 1025-atom tungsten trajectory (8x8x8 bcc + <111> dumbbell, 0.05 A jitter),
+SNAP twojmax 8 (55 coefficients) on top of Finnis-Sinclair, L = 100 BAOAB steps of
+1 fs per slab at 1000 K: the fine propagation of all 64 slabs batched in one launch
+sequence, the coarse propagation of the same slabs, the jumps, and the sequential
+corrected coarse sweep.  value = fine atom-steps per second of the whole iteration
+(64 * 1025 * 100 / seconds per iteration), inputs resident in HBM.
+
+Also reported: the fine batch alone, the same fine propagation run slab by slab
+(the per-slab form), the roofline of the dominant kernel (HIP events on the launch
+stream, algorithmic FLOPs from the operation counts of the design doc), and the CPU oracle
+timed on a bounded sample on the host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CUs x 128 FLOP/clk x 2.4 GHz
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def snap_counts(J):
+    """(nU_half, nZel, nZterm) index-set sizes for twojmax J."""
+    nUh = sum((n + 1) * (n // 2 + 1) for n in range(J + 1))
+    nZel = nZt = 0
+    for n1 in range(J + 1):
+        for n2 in range(n1 + 1):
+            for n in range(n1 - n2, min(J, n1 + n2) + 1, 2):
+                nZel += (n + 1) * (n // 2 + 1)
+                off = (n1 + n2 - n) // 2
+                for k in range(n + 1):
+                    for l in range(n // 2 + 1):
+                        for k1 in range(n1 + 1):
+                            k2 = k - k1 + off
+                            if not 0 <= k2 <= n2:
+                                continue
+                            for l1 in range(n1 + 1):
+                                if 0 <= l - l1 + off <= n2:
+                                    nZt += 1
+    return nUh, nZel, nZt
+
+
+def cpu_baseline(wl, J, nsteps=3):
+    from oracle import oracle as O
+    from paper_2212_10508_amd import workloads as W
+    x, p = wl["xs"][0], wl["ps"][0]
+    snap = dict(J=J, beta=wl["beta"], rcut=W.SNAP_RCUT, rfac0=W.SNAP_RFAC0, rmin0=0.0)
+    t0 = time.time()
+    O.langevin(x, p, wl["box"], potential=O.POT_FS_SNAP, nsteps=nsteps, dt=wl["dt"], gamma=wl["gamma"],
+               mass=wl["mass"], T=wl["T"], seed=1, noise_id=0, step0=0, snap=snap, fs=W.FS_W)
+    dt = time.time() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+    return {"value": x.shape[1] * nsteps / dt, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
+            "sample": "one 1025-atom slab, %d fine BAOAB steps (%d force evaluations), twojmax 8, "
+                      "adjoint route, OpenMP over atoms; %.1f s" % (nsteps, nsteps + 1, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--slabs", type=int, default=64)
+    ap.add_argument("--L", type=int, default=100)
+    ap.add_argument("--per-slab-sample", type=int, default=4, help="slabs timed one by one")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one MI355X: the propagator runs on a single GPU "
+              "(multi-GPU slab sharding is a design note only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2212_10508_amd import snapmd as S
+    from paper_2212_10508_amd import workloads as W
+
+    J = 8
+    S_slabs, L = args.slabs, args.L
+    wl = W.slabs_1025(n_slabs=1, seed=1, J=J)
+    x0, p0, box, beta = wl["xs"][0], wl["ps"][0], wl["box"], wl["beta"]
+    n = x0.shape[1]
+    kw = dict(dt=wl["dt"], gamma=wl["gamma"], mass=wl["mass"], T=wl["T"], seed=1, noise_id=0, fs=W.FS_W,
+              J=J, beta=beta)
+    ctx = S.context(0)
+    dev = "cuda:0"
+    q_cur = torch.zeros((S_slabs + 1, 3, n), dtype=torch.float64, device=dev)
+    p_cur, q_prev, p_prev = torch.zeros_like(q_cur), torch.zeros_like(q_cur), torch.zeros_like(q_cur)
+    q_cur[0] = torch.tensor(x0, device=dev)
+    p_cur[0] = torch.tensor(p0, device=dev)
+    kw_c = {k: v for k, v in kw.items() if k not in ("J", "beta")}
+    log("init: coarse sweep over %d slabs" % S_slabs)
+    ctx.parareal_iterate(None, None, q_cur, p_cur, box, L, 0, S_slabs, 1e300, **kw_c)
+    q_start, p_start = q_cur.clone(), p_cur.clone()
+
+    def iteration():
+        d, nfi = ctx.parareal_iterate(q_prev, p_prev, q_cur, p_cur, box, L, 0, S_slabs, 1e300, **kw)
+        assert nfi == S_slabs
+        return d
+
+    for w in range(args.warmup):
+        d = iteration()
+        log("warmup %d: delta %.3e" % (w, d))
+    q_cur.copy_(q_start)
+    p_cur.copy_(p_start)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        d = iteration()
+        log("step %d: delta %.3e" % (k, d))
+    torch.cuda.synchronize()
+    t_it = (time.perf_counter() - t0) / args.steps
+    prof = {name: ctx.profile_read(kid) for name, kid in
+            (("dedr", S.Context.PROF_DEDR), ("adjoint", S.Context.PROF_ADJOINT),
+             ("density", S.Context.PROF_DENSITY), ("neigh", S.Context.PROF_NEIGH))}
+    ctx.profile(False)
+    fine_atom_steps = S_slabs * n * L
+    value = fine_atom_steps / t_it
+
+    # fine batch alone and the per-slab form (same kernels, one slab per call)
+    Xb = q_start[:S_slabs].permute(1, 0, 2).reshape(3, S_slabs * n).contiguous()
+    Pb = p_start[:S_slabs].permute(1, 0, 2).reshape(3, S_slabs * n).contiguous()
+    off = np.arange(S_slabs + 1, dtype=np.int32) * n
+    boxes = np.tile(box, (S_slabs, 1))
+    step0 = np.arange(S_slabs) * L
+    xb, pb = Xb.clone(), Pb.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.langevin_steps(S.POT_FS_SNAP, xb, pb, off, boxes, L, step0=step0, **{k: v for k, v in kw.items()})
+    torch.cuda.synchronize()
+    t_fine = time.perf_counter() - t0
+    ctx.snap_forces(Xb, off, boxes, J, beta)
+    n_pairs = ctx.pair_count()
+    ns = min(args.per_slab_sample, S_slabs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(ns):
+        xs = q_start[s].clone()
+        ps = p_start[s].clone()
+        ctx.langevin_steps(S.POT_FS_SNAP, xs, ps, [0, n], box, L, step0=s * L, **kw)
+    torch.cuda.synchronize()
+    t_slab = (time.perf_counter() - t0) / ns
+
+    # roofline of the dominant SNAP kernel (algorithmic FP64 FLOPs per launch / avg duration)
+    nUh, nZel, nZt = snap_counts(J)
+    atoms = S_slabs * n
+    flops = {"dedr": 136.0 * nUh * n_pairs, "adjoint": (8.0 * nZt + 4.0 * nZel) * atoms,
+             "density": 22.0 * nUh * n_pairs}
+    kname = {"dedr": "k_dedr<8> (SNAP dE/dr, adjoint contraction)",
+             "adjoint": "k_adjoint_lds<8> (SNAP adjoint Y)", "density": "k_density<8> (SNAP density u)"}
+    dom = max(("dedr", "adjoint", "density"), key=lambda k: prof[k][0])
+    avg_ms = prof[dom][0] / max(prof[dom][1], 1)
+    achieved = flops[dom] / (avg_ms * 1e-3) / 1e12
+    kernels = {k: {"avg_ms": prof[k][0] / max(prof[k][1], 1), "launches": prof[k][1],
+                   "tflops": (flops[k] / (prof[k][0] / max(prof[k][1], 1) * 1e-3) / 1e12) if k in flops else None}
+               for k in prof}
+
+    out = {
+        "metric": "SNAP+Langevin atom-steps/s, all slabs batched vs per-slab, FP64 @1e-10 force tol",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_it * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "parareal iteration, 64 slabs x 1025-atom W bcc + <111> SIA, SNAP twojmax 8 "
+                               "+ Finnis-Sinclair fine / FS coarse, L=100 BAOAB steps, 1 fs, 1000 K",
+                   "atoms": n, "slabs": S_slabs, "L": L, "twojmax": J, "pairs": n_pairs,
+                   "mean_neighbours": n_pairs / atoms},
+        "roofline": {"bound": "alu", "kernel": kname[dom], "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None},
+        "fine_batch_atom_steps_per_s": fine_atom_steps / t_fine,
+        "per_slab_atom_steps_per_s": n * L / t_slab,
+        "batched_vs_per_slab": (fine_atom_steps / t_fine) / (n * L / t_slab),
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(W.slabs_1025(n_slabs=1, seed=1, J=J), J)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

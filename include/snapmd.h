@@ -157,7 +157,12 @@ int langevin_steps(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, cons
  * receive prev_n on [n_in, *n_fi].  batch must hold exactly one system (its box).
  * delta_expl = +inf gives the classical algorithm.  Writes *delta_out and possibly
  * *n_fi (host).  Synchronises `stream` once; returns SNAPMD_ENONFINITE if a state
- * became non-finite (the message names the slab). */
+ * became non-finite (the message names the slab).
+ * Initialisation of a new time window (the coarse propagation that starts each
+ * window of the adaptive algorithm): pass q_prev = p_prev = NULL; then only
+ * cur_{n+1} := C(cur_n) for n_in <= n < *n_fi is done, *delta_out = 0, snap may be NULL.
+ * The coarse sweep keeps a Verlet list with a 0.5 A skin: max(d, c) + 0.5 must be
+ * below half the smallest box edge. */
 int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs,
                      const snapmd_batch *batch, const snapmd_langevin *lang, int32_t L,
                      int32_t n_in, int32_t *n_fi, double *q_prev, double *p_prev, double *q_cur,
@@ -179,6 +184,18 @@ int snap_beta_grad(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch 
  * beta[1..]).  Asynchronous on `stream`. */
 int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *batch,
                       const double *x, double *B, void *stream);
+
+/* Measurement support (not part of the propagation):
+ * snapmd_profile(ctx, 1) starts recording HIP events around the SNAP kernels and the
+ * neighbour build on the stream they are launched on (clears earlier records; 0 stops).
+ * snapmd_profile_read synchronises the device and returns, for kernel id
+ * 0 = SNAP dE/dr, 1 = SNAP adjoint, 2 = SNAP density, 3 = neighbour build,
+ * the summed duration (ms) and the number of launches recorded. */
+int snapmd_profile(snapmd_ctx *ctx, int enable);
+int snapmd_profile_read(snapmd_ctx *ctx, int kernel, double *total_ms, int64_t *launches);
+/* Number of neighbour pairs (both directions) of the last neighbour build, after a
+ * device synchronisation. */
+int snapmd_pair_count(snapmd_ctx *ctx, int64_t *n_pairs);
 
 #ifdef __cplusplus
 }

@@ -62,6 +62,12 @@ struct snapmd_ctx {
     DBuf<int> d_noise;
     std::map<int, SnapDevTables> snap;
     std::vector<void *> allocs;
+    // parareal buffers
+    DBuf<double> pr_xf, pr_pf, pr_xc, pr_pc;     // [3][S*N] fine / coarse copies of prev slabs
+    DBuf<double> sw_x, sw_p, sw_f, sw_rho, sw_ref, sw_out;
+    DBuf<int> sw_nbr, sw_cnt;
+    double *h_out = nullptr;                      // pinned [4]
+    KernelProf prof;
 };
 
 namespace {
@@ -282,9 +288,50 @@ void enqueue_forces(snapmd_ctx *ctx, int potential, const BatchDev &bd, const do
     double rc = 0.0;
     if (fp) rc = std::max(fp->d, fp->c);
     if (potential == SNAPMD_POT_FS_SNAP) rc = std::max(rc, sd->gp.rcut);
+    ctx->prof.begin(PROF_NEIGH, st);
     launch_neighbors(bd, x, rc, ctx->w, st);
+    ctx->prof.end(st);
     launch_fs(bd, x, *fp, ctx->w, f, e_atom, 0, st);
-    if (potential == SNAPMD_POT_FS_SNAP) launch_snap(sd->J, bd, x, *sd, ctx->w, f, e_atom, 1, st);
+    if (potential == SNAPMD_POT_FS_SNAP) launch_snap(sd->J, bd, x, *sd, ctx->w, f, e_atom, 1, st, &ctx->prof);
+}
+
+// n_steps BAOAB steps of the batch in place (force evaluated at the start).
+void run_langevin(snapmd_ctx *ctx, int potential, const BatchDev &bd, const FsParams &fp, const SnapDev &sd,
+                  const LangevinDev &ld, int n_steps, double *x, double *p, hipStream_t st) {
+    double *f = ctx->d_f;
+    enqueue_forces(ctx, potential, bd, x, &fp, &sd, f, nullptr, st);
+    for (int s = 0; s < n_steps; ++s) {
+        launch_baoab_pre(bd, x, p, f, ld, s, st);
+        enqueue_forces(ctx, potential, bd, x, &fp, &sd, f, nullptr, st);
+        launch_baoab_post(bd, p, f, ld.dt, st);
+    }
+}
+
+// Per-system Langevin arrays (sigma, step offsets, noise ids) uploaded to the context.
+int prepare_langevin(snapmd_ctx *ctx, const snapmd_langevin *lang, int S, const std::vector<double> &T,
+                     const std::vector<int64_t> &step0, const std::vector<int> &nid, LangevinDev &ld,
+                     hipStream_t st) {
+    const double c1 = std::exp(-lang->gamma * lang->dt);
+    std::vector<double> sig(S);
+    for (int s = 0; s < S; ++s) sig[s] = std::sqrt((1.0 - c1 * c1) * lang->mass * kKB * T[s] / kMVV2E);
+    int rc;
+    if ((rc = ensure(ctx, ctx->d_sig, S)) || (rc = ensure(ctx, ctx->d_step0, S)) || (rc = ensure(ctx, ctx->d_noise, S)))
+        return rc;
+    if ((rc = upload(ctx, ctx->d_sig.p, sig.data(), S, st))) return rc;
+    if ((rc = upload(ctx, ctx->d_step0.p, step0.data(), S, st))) return rc;
+    if ((rc = upload(ctx, ctx->d_noise.p, nid.data(), S, st))) return rc;
+    ld = LangevinDev{lang->dt, c1, lang->mass, lang->seed, ctx->d_sig.p, ctx->d_step0.p, ctx->d_noise.p};
+    return SNAPMD_OK;
+}
+
+int check_lang(snapmd_ctx *ctx, const snapmd_langevin *lang) {
+    if (!lang) return fail(ctx, SNAPMD_EINVAL, "lang is NULL");
+    if (lang->scheme != 0) return fail(ctx, SNAPMD_EINVAL, "only scheme 0 (BAOAB) is supported");
+    if (!(lang->dt > 0.0) || !(lang->gamma >= 0.0) || !(lang->mass > 0.0))
+        return fail(ctx, SNAPMD_EINVAL, "need dt > 0, gamma >= 0, mass > 0");
+    if (!lang->T_sys || !lang->step0_sys || !lang->noise_id_sys)
+        return fail(ctx, SNAPMD_EINVAL, "lang.T_sys, step0_sys and noise_id_sys must be set");
+    return SNAPMD_OK;
 }
 
 }  // namespace
@@ -313,6 +360,8 @@ void snapmd_destroy(snapmd_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     for (void *p : ctx->allocs) (void)hipFree(p);
+    if (ctx->h_out) (void)hipHostFree(ctx->h_out);
+    for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -378,50 +427,190 @@ int langevin_steps(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, cons
         return fail(ctx, SNAPMD_EINVAL, "potential must be SNAPMD_POT_FS or SNAPMD_POT_FS_SNAP");
     if (!x || !p) return fail(ctx, SNAPMD_EINVAL, "x and p must be device pointers");
     if (n_steps < 0) return fail(ctx, SNAPMD_EINVAL, "n_steps must be >= 0");
-    if (!lang) return fail(ctx, SNAPMD_EINVAL, "lang is NULL");
-    if (lang->scheme != 0) return fail(ctx, SNAPMD_EINVAL, "only scheme 0 (BAOAB) is supported");
-    if (!(lang->dt > 0.0) || !(lang->gamma >= 0.0) || !(lang->mass > 0.0))
-        return fail(ctx, SNAPMD_EINVAL, "need dt > 0, gamma >= 0, mass > 0");
+    int rc;
+    if ((rc = check_lang(ctx, lang))) return rc;
     BatchDev bd;
     double mh;
     FsParams fp;
     SnapDev sd;
-    int rc;
     if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
     if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
     if (potential == SNAPMD_POT_FS_SNAP && (rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
     const int S = bd.n_sys;
-    if (!lang->T_sys || !lang->step0_sys || !lang->noise_id_sys)
-        return fail(ctx, SNAPMD_EINVAL, "lang.T_sys, step0_sys and noise_id_sys must be set");
-    const double c1 = std::exp(-lang->gamma * lang->dt);
-    std::vector<double> sig(S);
+    std::vector<double> T(lang->T_sys, lang->T_sys + S);
+    std::vector<int64_t> step0(lang->step0_sys, lang->step0_sys + S);
+    std::vector<int> nid(lang->noise_id_sys, lang->noise_id_sys + S);
     for (int s = 0; s < S; ++s) {
-        if (!(lang->T_sys[s] >= 0.0)) return fail(ctx, SNAPMD_EINVAL, "T_sys[%d] must be >= 0", s);
-        if (lang->noise_id_sys[s] < 0) return fail(ctx, SNAPMD_EINVAL, "noise_id_sys[%d] must be >= 0", s);
-        sig[s] = std::sqrt((1.0 - c1 * c1) * lang->mass * kKB * lang->T_sys[s] / kMVV2E);
+        if (!(T[s] >= 0.0)) return fail(ctx, SNAPMD_EINVAL, "T_sys[%d] must be >= 0", s);
+        if (nid[s] < 0) return fail(ctx, SNAPMD_EINVAL, "noise_id_sys[%d] must be >= 0", s);
     }
-    if ((rc = ensure(ctx, ctx->d_sig, S)) || (rc = ensure(ctx, ctx->d_step0, S)) || (rc = ensure(ctx, ctx->d_noise, S)))
-        return rc;
-    if ((rc = upload(ctx, ctx->d_sig.p, sig.data(), S, st))) return rc;
-    if ((rc = upload(ctx, ctx->d_step0.p, lang->step0_sys, S, st))) return rc;
-    if ((rc = upload(ctx, ctx->d_noise.p, lang->noise_id_sys, S, st))) return rc;
+    LangevinDev ld;
+    if ((rc = prepare_langevin(ctx, lang, S, T, step0, nid, ld, st))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
-    LangevinDev ld{lang->dt, c1, lang->mass, lang->seed, ctx->d_sig.p, ctx->d_step0.p, ctx->d_noise.p};
-    double *f = ctx->d_f;
-    enqueue_forces(ctx, potential, bd, x, &fp, &sd, f, nullptr, st);
-    for (int s = 0; s < n_steps; ++s) {
-        launch_baoab_pre(bd, x, p, f, ld, s, st);
-        enqueue_forces(ctx, potential, bd, x, &fp, &sd, f, nullptr, st);
-        launch_baoab_post(bd, p, f, lang->dt, st);
-    }
-    if (f_out) HIPCHK(hipMemcpyAsync(f_out, f, 3 * (size_t)bd.N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    run_langevin(ctx, potential, bd, fp, sd, ld, n_steps, x, p, st);
+    if (f_out)
+        HIPCHK(hipMemcpyAsync(f_out, ctx->d_f, 3 * (size_t)bd.N * sizeof(double), hipMemcpyDeviceToDevice, st));
     return check_launch(ctx);
 }
 
-int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *, const snapmd_fs *, const snapmd_batch *,
-                     const snapmd_langevin *, int32_t, int32_t, int32_t *, double *, double *, double *, double *,
-                     double, double *, void *) {
-    return fail(ctx, SNAPMD_EUNSUPPORTED, "parareal_iterate: not built yet");
+int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, const snapmd_batch *batch,
+                     const snapmd_langevin *lang, int32_t L, int32_t n_in, int32_t *n_fi, double *q_prev,
+                     double *p_prev, double *q_cur, double *p_cur, double delta_expl, double *delta_out,
+                     void *stream) {
+    if (!ctx) return SNAPMD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc;
+    if ((rc = check_lang(ctx, lang))) return rc;
+    if (!batch || batch->n_sys != 1) return fail(ctx, SNAPMD_EINVAL, "parareal_iterate needs a batch of one system");
+    if (!n_fi || !delta_out) return fail(ctx, SNAPMD_EINVAL, "n_fi and delta_out must be host pointers");
+    if (L < 1) return fail(ctx, SNAPMD_EINVAL, "L must be >= 1");
+    if (n_in < 0 || *n_fi <= n_in) return fail(ctx, SNAPMD_EINVAL, "need 0 <= n_in < n_fi (got %d, %d)", n_in, *n_fi);
+    if (!q_cur || !p_cur) return fail(ctx, SNAPMD_EINVAL, "q_cur and p_cur must be device pointers");
+    const bool init = (q_prev == nullptr);
+    if (!init && !p_prev) return fail(ctx, SNAPMD_EINVAL, "p_prev must be set with q_prev");
+    if (!(delta_expl >= 0.0)) return fail(ctx, SNAPMD_EINVAL, "delta_expl must be >= 0");
+    if (!(lang->T_sys[0] >= 0.0) || lang->noise_id_sys[0] < 0)
+        return fail(ctx, SNAPMD_EINVAL, "need T_sys[0] >= 0 and noise_id_sys[0] >= 0");
+    const int N = batch->offset[1];
+    if (batch->offset[0] != 0 || N < 1) return fail(ctx, SNAPMD_EINVAL, "the system needs at least one atom");
+    const int S = *n_fi - n_in;
+    const double *box = batch->box;
+    double mh = 0.5 * std::min(box[0], std::min(box[1], box[2]));
+    FsParams fp;
+    if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
+    const double skin = 0.5;
+    if (!(std::max(fp.d, fp.c) + skin < mh))
+        return fail(ctx, SNAPMD_EINVAL, "FS cutoff + skin must be < half the smallest box edge");
+    SnapDev sd;
+    const size_t SN3 = 3 * (size_t)S * N;
+    // sweep scratch
+    if ((rc = ensure(ctx, ctx->sw_x, 3 * (size_t)N)) || (rc = ensure(ctx, ctx->sw_p, 3 * (size_t)N)) ||
+        (rc = ensure(ctx, ctx->sw_f, 3 * (size_t)N)) || (rc = ensure(ctx, ctx->sw_ref, 3 * (size_t)N)) ||
+        (rc = ensure(ctx, ctx->sw_rho, (size_t)N)) || (rc = ensure(ctx, ctx->sw_nbr, (size_t)N * kMaxNeigh)) ||
+        (rc = ensure(ctx, ctx->sw_cnt, (size_t)N)) || (rc = ensure(ctx, ctx->sw_out, 4)))
+        return rc;
+    if (!ctx->h_out) HIPCHK(hipHostMalloc((void **)&ctx->h_out, 4 * sizeof(double), hipHostMallocDefault));
+    const double c1 = std::exp(-lang->gamma * lang->dt);
+    SweepLaunch sw{};
+    sw.N = N;
+    sw.box[0] = box[0];
+    sw.box[1] = box[1];
+    sw.box[2] = box[2];
+    sw.fp = fp;
+    sw.skin = skin;
+    sw.dt = lang->dt;
+    sw.c1 = c1;
+    sw.mass = lang->mass;
+    sw.sig = std::sqrt((1.0 - c1 * c1) * lang->mass * kKB * lang->T_sys[0] / kMVV2E);
+    sw.seed = lang->seed;
+    sw.noise_id = (uint64_t)lang->noise_id_sys[0];
+    sw.L = L;
+    sw.n_in = n_in;
+    sw.n_fi = *n_fi;
+    sw.mode = init ? 0 : 1;
+    sw.delta_expl = delta_expl;
+    sw.q_cur = q_cur;
+    sw.p_cur = p_cur;
+    sw.q_prev = q_prev;
+    sw.p_prev = p_prev;
+    sw.wx = ctx->sw_x.p;
+    sw.wp = ctx->sw_p.p;
+    sw.wf = ctx->sw_f.p;
+    sw.wrho = ctx->sw_rho.p;
+    sw.xref = ctx->sw_ref.p;
+    sw.nbr = ctx->sw_nbr.p;
+    sw.cnt = ctx->sw_cnt.p;
+    sw.out = ctx->sw_out.p;
+    HIPCHK(hipMemsetAsync(ctx->sw_out.p, 0, 4 * sizeof(double), st));
+    if (!init) {
+        // prev_n := cur_n on [n_in, n_fi]
+        const size_t slot = 3 * (size_t)N;
+        HIPCHK(hipMemcpyAsync(q_prev + n_in * slot, q_cur + n_in * slot, (S + 1) * slot * sizeof(double),
+                              hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(p_prev + n_in * slot, p_cur + n_in * slot, (S + 1) * slot * sizeof(double),
+                              hipMemcpyDeviceToDevice, st));
+        // the batch: S copies of the system, slab s starting at global step (n_in + s) L
+        std::vector<int> off(S + 1);
+        std::vector<double> boxes(3 * S);
+        for (int s = 0; s <= S; ++s) off[s] = s * N;
+        for (int s = 0; s < S; ++s)
+            for (int a = 0; a < 3; ++a) boxes[3 * s + a] = box[a];
+        snapmd_batch sb{S, off.data(), boxes.data()};
+        BatchDev bd;
+        double mh2;
+        if ((rc = prepare_batch(ctx, &sb, bd, mh2, st))) return rc;
+        if ((rc = prepare_snap(ctx, snap, mh2, sd, st))) return rc;
+        std::vector<double> T(S, lang->T_sys[0]);
+        std::vector<int64_t> step0(S);
+        std::vector<int> nid(S, lang->noise_id_sys[0]);
+        for (int s = 0; s < S; ++s) step0[s] = (int64_t)(n_in + s) * L;
+        LangevinDev ld;
+        if ((rc = prepare_langevin(ctx, lang, S, T, step0, nid, ld, st))) return rc;
+        if ((rc = ensure(ctx, ctx->pr_xf, SN3)) || (rc = ensure(ctx, ctx->pr_pf, SN3)) ||
+            (rc = ensure(ctx, ctx->pr_xc, SN3)) || (rc = ensure(ctx, ctx->pr_pc, SN3)))
+            return rc;
+        const double *qs = q_prev + n_in * slot, *ps = p_prev + n_in * slot;
+        launch_slabs_to_batch(S, N, qs, ctx->pr_xf.p, st);
+        launch_slabs_to_batch(S, N, ps, ctx->pr_pf.p, st);
+        launch_slabs_to_batch(S, N, qs, ctx->pr_xc.p, st);
+        launch_slabs_to_batch(S, N, ps, ctx->pr_pc.p, st);
+        run_langevin(ctx, SNAPMD_POT_FS_SNAP, bd, fp, sd, ld, L, ctx->pr_xf.p, ctx->pr_pf.p, st);
+        run_langevin(ctx, SNAPMD_POT_FS, bd, fp, sd, ld, L, ctx->pr_xc.p, ctx->pr_pc.p, st);
+        launch_jumps(SN3, ctx->pr_xf.p, ctx->pr_xc.p, st);
+        launch_jumps(SN3, ctx->pr_pf.p, ctx->pr_pc.p, st);
+        sw.jq = ctx->pr_xf.p;
+        sw.jp = ctx->pr_pf.p;
+    }
+    launch_coarse_sweep(sw, st);
+    if ((rc = check_launch(ctx))) return rc;
+    HIPCHK(hipMemcpyAsync(ctx->h_out, ctx->sw_out.p, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if ((rc = snapmd_sync(ctx, stream))) return rc;
+    if (ctx->h_out[3] != 0.0) return fail(ctx, SNAPMD_EOVERFLOW, "an atom has more than %d neighbours", kMaxNeigh);
+    if (ctx->h_out[2] >= 0.0)
+        return fail(ctx, SNAPMD_ENONFINITE, "state became non-finite in slab %d", (int)ctx->h_out[2]);
+    *delta_out = ctx->h_out[0];
+    *n_fi = (int32_t)ctx->h_out[1];
+    return SNAPMD_OK;
+}
+
+int snapmd_profile(snapmd_ctx *ctx, int enable) {
+    if (!ctx) return SNAPMD_EINVAL;
+    ctx->prof.enabled = enable ? 1 : 0;
+    ctx->prof.reset();
+    return SNAPMD_OK;
+}
+
+int snapmd_profile_read(snapmd_ctx *ctx, int kernel, double *total_ms, int64_t *launches) {
+    if (!ctx || !total_ms || !launches) return SNAPMD_EINVAL;
+    if (kernel < 0 || kernel >= PROF_N) return fail(ctx, SNAPMD_EINVAL, "unknown kernel id %d", kernel);
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    double tot = 0.0;
+    int64_t n = 0;
+    for (size_t q = 0; q < ctx->prof.ids.size() && q < ctx->prof.ev1.size(); ++q) {
+        if (ctx->prof.ids[q] != kernel) continue;
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->prof.ev0[q], ctx->prof.ev1[q]));
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    *launches = n;
+    return SNAPMD_OK;
+}
+
+int snapmd_pair_count(snapmd_ctx *ctx, int64_t *n_pairs) {
+    if (!ctx || !n_pairs) return SNAPMD_EINVAL;
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    int v = 0;
+    if (ctx->cap_atoms && !ctx->h_off.empty()) {
+        const int N = ctx->h_off.back();
+        HIPCHK(hipMemcpy(&v, ctx->w.poff + N, sizeof(int), hipMemcpyDeviceToHost));
+    }
+    *n_pairs = v;
+    return SNAPMD_OK;
 }
 
 int snap_beta_grad(snapmd_ctx *ctx, const snapmd_snap *, const snapmd_batch *, const double *, const double *,

@@ -74,11 +74,68 @@ struct Work {
     double2 *u = nullptr, *ytil = nullptr;  // [nh][N]
 };
 
+// Optional per-kernel timing with HIP events on the launch stream (for the roofline).
+enum { PROF_DEDR = 0, PROF_ADJOINT = 1, PROF_DENSITY = 2, PROF_NEIGH = 3, PROF_N = 4 };
+struct KernelProf {
+    int enabled = 0;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<int> ids;
+    std::vector<hipEvent_t> ev0, ev1;
+    hipEvent_t get() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            (void)hipEventCreate(&e);
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void begin(int id, hipStream_t st) {
+        if (!enabled) return;
+        hipEvent_t e = get();
+        (void)hipEventRecord(e, st);
+        ids.push_back(id);
+        ev0.push_back(e);
+    }
+    void end(hipStream_t st) {
+        if (!enabled) return;
+        hipEvent_t e = get();
+        (void)hipEventRecord(e, st);
+        ev1.push_back(e);
+    }
+    void reset() {
+        used = 0;
+        ids.clear();
+        ev0.clear();
+        ev1.clear();
+    }
+};
+
+// Arguments of the persistent coarse sweep of a parareal iteration.
+struct SweepLaunch {
+    int N;
+    double box[3];
+    FsParams fp;
+    double skin;
+    double dt, c1, mass, sig;
+    uint64_t seed, noise_id;
+    int L, n_in, n_fi, mode;
+    double delta_expl;
+    double *q_cur, *p_cur;
+    const double *q_prev, *p_prev, *jq, *jp;
+    double *wx, *wp, *wf, *wrho, *xref;
+    int *nbr, *cnt;
+    double *out;
+};
+void launch_slabs_to_batch(int S, int N, const double *slots, double *out, hipStream_t st);
+void launch_jumps(size_t n, double *a, const double *b, hipStream_t st);
+void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st);
+
 void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, hipStream_t st);
 void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w, double *f, double *e_atom,
                int accumulate, hipStream_t st);
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
-                 double *e_atom, int accumulate, hipStream_t st);
+                 double *e_atom, int accumulate, hipStream_t st, KernelProf *prof = nullptr);
 void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st);
 void adjoint_tables(int J, const double *beta, AdjointHost &A);
 void adjoint_init_attributes();

@@ -599,26 +599,34 @@ void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w,
 
 template <int J>
 static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
-                          double *e_atom, int accumulate, hipStream_t st) {
+                          double *e_atom, int accumulate, hipStream_t st, KernelProf *prof) {
     const int N = bd.N;
+    KernelProf dummy;
+    KernelProf &pf = prof ? *prof : dummy;
     hipLaunchKernelGGL(k_pair_geo, dim3(nblk(w.Pcap, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
                        w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
+    pf.begin(PROF_DENSITY, st);
     hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 128), J / 2 + 1), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap,
                        sd.nrm, w.u);
+    pf.end(st);
+    pf.begin(PROF_ADJOINT, st);
     launch_adjoint(J, sd.adj, N, w.u, sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate, st);
+    pf.end(st);
+    pf.begin(PROF_DEDR, st);
     hipLaunchKernelGGL(k_dedr<J>, dim3(nblk(w.Pcap, 64)), dim3(64), 0, st, N, w.poff, w.pair_i, w.geo, w.Pcap,
                        w.ytil, w.dedr);
+    pf.end(st);
     hipLaunchKernelGGL(k_gather, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.poff, w.rev, w.dedr, w.Pcap, f,
                        accumulate);
 }
 
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
-                 double *e_atom, int accumulate, hipStream_t st) {
+                 double *e_atom, int accumulate, hipStream_t st, KernelProf *prof) {
     switch (J) {
-        case 2: launch_snap_J<2>(bd, x, sd, w, f, e_atom, accumulate, st); break;
-        case 4: launch_snap_J<4>(bd, x, sd, w, f, e_atom, accumulate, st); break;
-        case 6: launch_snap_J<6>(bd, x, sd, w, f, e_atom, accumulate, st); break;
-        case 8: launch_snap_J<8>(bd, x, sd, w, f, e_atom, accumulate, st); break;
+        case 2: launch_snap_J<2>(bd, x, sd, w, f, e_atom, accumulate, st, prof); break;
+        case 4: launch_snap_J<4>(bd, x, sd, w, f, e_atom, accumulate, st, prof); break;
+        case 6: launch_snap_J<6>(bd, x, sd, w, f, e_atom, accumulate, st, prof); break;
+        case 8: launch_snap_J<8>(bd, x, sd, w, f, e_atom, accumulate, st, prof); break;
         default: break;
     }
 }

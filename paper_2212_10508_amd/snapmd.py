@@ -82,6 +82,12 @@ def lib():
     L.snap_beta_grad.restype = C.c_int
     L.snapmd_bispectrum.argtypes = [P, C.POINTER(Snap), C.POINTER(Batch), P, P, P]
     L.snapmd_bispectrum.restype = C.c_int
+    L.snapmd_profile.argtypes = [P, C.c_int]
+    L.snapmd_profile.restype = C.c_int
+    L.snapmd_profile_read.argtypes = [P, C.c_int, C.POINTER(d), C.POINTER(C.c_int64)]
+    L.snapmd_profile_read.restype = C.c_int
+    L.snapmd_pair_count.argtypes = [P, C.POINTER(C.c_int64)]
+    L.snapmd_pair_count.restype = C.c_int
     _lib = L
     return L
 
@@ -224,24 +230,44 @@ class Context:
                                          _dev(f_out, "f_out", (3, N)), _stream(stream)))
 
     def parareal_iterate(self, q_prev, p_prev, q_cur, p_cur, box, L, n_in, n_fi, delta_expl, *, dt, gamma,
-                         mass, T, seed, noise_id, fs, J, beta, rcut=4.73, rfac0=0.99363, rmin0=0.0,
+                         mass, T, seed, noise_id, fs, J=None, beta=None, rcut=4.73, rfac0=0.99363, rmin0=0.0,
                          stream=None):
-        """Returns (delta, n_fi_after)."""
+        """Returns (delta, n_fi_after).  q_prev = p_prev = None: window initialisation."""
         nslots, three, N = q_cur.shape
         k = _Keep()
         b = make_batch(k, [0, N], box)
-        s = make_snap(k, J, beta, rcut, rfac0, rmin0)
+        s = make_snap(k, J, beta, rcut, rfac0, rmin0) if beta is not None else None
         p_fs = make_fs(fs)
         lg = make_langevin(k, 1, dt, gamma, mass, T, seed, 0, noise_id)
         nfi = C.c_int32(int(n_fi))
         delta = C.c_double(0.0)
         shape = (nslots, 3, N)
-        self._check(lib().parareal_iterate(self.h, C.byref(s), C.byref(p_fs), C.byref(b), C.byref(lg), int(L),
-                                           int(n_in), C.byref(nfi), _dev(q_prev, "q_prev", shape),
-                                           _dev(p_prev, "p_prev", shape), _dev(q_cur, "q_cur", shape),
+        self._check(lib().parareal_iterate(self.h, C.byref(s) if s is not None else None, C.byref(p_fs),
+                                           C.byref(b), C.byref(lg), int(L),
+                                           int(n_in), C.byref(nfi), _dev(q_prev, "q_prev", shape) if q_prev is not None else None,
+                                           _dev(p_prev, "p_prev", shape) if p_prev is not None else None,
+                                           _dev(q_cur, "q_cur", shape),
                                            _dev(p_cur, "p_cur", shape), float(delta_expl), C.byref(delta),
                                            _stream(stream)))
         return delta.value, nfi.value
+
+    # -- measurement ---------------------------------------------------------
+    PROF_DEDR, PROF_ADJOINT, PROF_DENSITY, PROF_NEIGH = 0, 1, 2, 3
+
+    def profile(self, enable=True):
+        self._check(lib().snapmd_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self, kernel):
+        """(total ms, launches) of HIP-event-timed launches of `kernel` since profile(True)."""
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        self._check(lib().snapmd_profile_read(self.h, int(kernel), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def pair_count(self):
+        n = C.c_int64(0)
+        self._check(lib().snapmd_pair_count(self.h, C.byref(n)))
+        return n.value
 
     def snap_beta_grad(self, x, w, offset, box, J, beta, rcut=4.73, rfac0=0.99363, rmin0=0.0, stream=None):
         """Returns (dE/dbeta [K+1], sum_i w_i . dF_i/dbeta [K+1]) as device tensors."""

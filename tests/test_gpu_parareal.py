@@ -1,0 +1,127 @@
+"""Parareal on the GPU (parareal_iterate through the C ABI) against the oracle's
+literal drivers and against the GPU's own sequential fine trajectory."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import parareal as OPR
+from paper_2212_10508_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+QTOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_10508_amd import snapmd
+    return snapmd
+
+
+def _setup(J=2, L=4, seed=5):
+    x, box = W.bcc_sia(4, jitter=0.05, seed=seed)
+    p = W.maxwell_momenta(x.shape[1], 1000.0, seed=seed)
+    beta = W.snap_beta(J, seed=seed, scale=2e-2)
+    kw = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=99, noise_id=1, fs=W.FS_W, J=J, beta=beta)
+    snap = dict(J=J, beta=beta, rcut=W.SNAP_RCUT, rfac0=W.SNAP_RFAC0, rmin0=0.0)
+    prop = OPR.Propagators(box=box, L=L, dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=99, noise_id=1,
+                           snap=snap, fs=W.FS_W)
+    return x, p, box, kw, prop
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def test_window_initialisation_is_sequential_coarse(S):
+    x, p, box, kw, prop = _setup()
+    N, L = 4, 4
+    ctx = S.context()
+    q = torch.zeros((N + 1, 3, x.shape[1]), dtype=torch.float64, device="cuda")
+    pp = torch.zeros_like(q)
+    q[0] = dev(x)
+    pp[0] = dev(p)
+    kw2 = dict(kw)
+    kw2.pop("J"), kw2.pop("beta")
+    delta, nfi = ctx.parareal_iterate(None, None, q, pp, box, L, 0, N, 1e100, **kw2)
+    assert delta == 0.0 and nfi == N
+    ref = [(x, p)]
+    for n in range(N):
+        ref.append(prop.C(ref[-1], n))
+    qh = q.cpu().numpy()
+    for n in range(N + 1):
+        assert np.abs(qh[n] - ref[n][0]).max() < QTOL
+
+
+def test_classical_parareal_matches_oracle(S):
+    from paper_2212_10508_amd import parareal as PR
+    x, p, box, kw, prop = _setup()
+    N, L = 4, 4
+    ctx = S.context()
+    log = []
+    q, pq, nad, kc = PR.adaptive_parareal(ctx, dev(x), dev(p), box, N, L, 1e-10, 1e100, log=log, **kw)
+    tref, k_ref, _ = OPR.parareal_classic(prop, x, p, N, delta_conv=1e-10)
+    assert nad == 1 and kc == [k_ref]
+    qh = q.cpu().numpy()
+    for n in range(N + 1):
+        assert np.abs(qh[n] - tref[n][0]).max() < QTOL
+    # converged parareal equals the GPU's own sequential fine run
+    qs, _ = PR.sequential_fine(ctx, dev(x), dev(p), box, N, L, **kw)
+    assert torch.max(torch.abs(qs - q)).item() < 1e-9
+
+
+def test_iterate_k_exact_on_first_k_slabs(S):
+    """After k corrected iterations, slabs 0..k equal the sequential fine trajectory."""
+    from paper_2212_10508_amd import parareal as PR
+    x, p, box, kw, prop = _setup(seed=7)
+    N, L = 4, 4
+    ctx = S.context()
+    n = x.shape[1]
+    qs, _ = PR.sequential_fine(ctx, dev(x), dev(p), box, N, L, **kw)
+    q = torch.zeros((N + 1, 3, n), dtype=torch.float64, device="cuda")
+    pp, qp, ppv = torch.zeros_like(q), torch.zeros_like(q), torch.zeros_like(q)
+    q[0], pp[0] = dev(x), dev(p)
+    ctx.parareal_iterate(None, None, q, pp, box, L, 0, N, 1e100, **kw)
+    scale = torch.max(torch.abs(qs)).item()
+    for k in range(1, N + 1):
+        ctx.parareal_iterate(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
+        err = [torch.max(torch.abs(q[m] - qs[m])).item() for m in range(N + 1)]
+        assert max(err[:k + 1]) < 1e-12 * scale, (k, err)
+    assert err[N] < 1e-12 * scale
+
+
+def test_adaptive_shortening_matches_oracle(S):
+    from paper_2212_10508_amd import parareal as PR
+    x, p, box, kw, prop = _setup(seed=6)
+    N, L = 5, 4
+    ctx = S.context()
+    log = []
+    q, pq, nad, kc = PR.adaptive_parareal(ctx, dev(x), dev(p), box, N, L, 1e-12, 1e-7, log=log, **kw)
+    olog = []
+    tref, nad_ref, kc_ref = OPR.parareal_adaptive(prop, x, p, N, 1e-12, 1e-7, log=olog)
+    assert nad > 1 and (nad, kc) == (nad_ref, kc_ref)
+    assert [(a["n_in"], a["n_fi"], a["n_fi_after"]) for a in log] == \
+           [(a["n_in"], a["n_fi"], a["n_fi_after"]) for a in olog]
+    qh = q.cpu().numpy()
+    for n in range(N + 1):
+        assert np.abs(qh[n] - tref[n][0]).max() < QTOL
+    assert PR.adaptive_cost(log, N, 100.0, 1.0) == OPR.adaptive_cost(olog, N, 100.0, 1.0)
+
+
+def test_nonfinite_state_is_reported(S):
+    x, p, box, kw, prop = _setup()
+    N, L = 3, 2
+    ctx = S.context()
+    n = x.shape[1]
+    q = torch.zeros((N + 1, 3, n), dtype=torch.float64, device="cuda")
+    pp = torch.zeros_like(q)
+    q[0], pp[0] = dev(x), dev(p)
+    pp[0, 1, 5] = float("nan")          # poisoned initial momentum (host-side injection)
+    kw2 = dict(kw)
+    kw2.pop("J"), kw2.pop("beta")
+    with pytest.raises(S.SnapmdError) as e:
+        ctx.parareal_iterate(None, None, q, pp, box, L, 0, N, 1e100, **kw2)
+    assert e.value.code == S.ENONFINITE and "slab 0" in str(e.value)
