@@ -68,7 +68,28 @@ def cpu_baseline(wl, J, nsteps=3):
                       "adjoint route, OpenMP over atoms; %.1f s" % (nsteps, nsteps + 1, dt)}
 
 
+def summarize_trace(path, top=16):
+    """Group a rocprofv3 kernel_trace.csv by (kernel, grid size): calls, mean and total time."""
+    import csv
+    from collections import defaultdict
+    groups = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        name = r.get("Kernel_Name") or r.get("Name")
+        grid = r.get("Grid_Size") or r.get("Grid_Size_X") or "?"
+        groups[(name, grid)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    tot = sum(sum(v) for v in groups.values())
+    rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]
+    print("%-52s %12s %7s %12s %12s %6s" % ("kernel", "grid", "calls", "avg_us", "total_ms", "pct"))
+    for (name, grid), v in rows:
+        short = name.replace("snapmd::", "").split("(")[0][:52]
+        print("%-52s %12s %7d %12.2f %12.2f %6.2f" % (short, grid, len(v), sum(v) / len(v), sum(v) / 1e3,
+                                                    100 * sum(v) / tot))
+
+
 def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--summarize-trace":
+        summarize_trace(sys.argv[2])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)

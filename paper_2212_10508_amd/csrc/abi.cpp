@@ -348,6 +348,7 @@ int snapmd_create(snapmd_ctx **out, int hip_device) {
     snapmd_ctx *ctx = new snapmd_ctx();
     ctx->device = hip_device;
     adjoint_init_attributes();
+    sweep_init_attributes();
     if (dalloc(ctx, &ctx->w.status, 1) != SNAPMD_OK || hipMemset(ctx->w.status, 0, sizeof(int)) != hipSuccess) {
         snapmd_destroy(ctx);
         return SNAPMD_ENOMEM;

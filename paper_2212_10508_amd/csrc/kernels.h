@@ -130,6 +130,7 @@ struct SweepLaunch {
 void launch_slabs_to_batch(int S, int N, const double *slots, double *out, hipStream_t st);
 void launch_jumps(size_t n, double *a, const double *b, hipStream_t st);
 void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st);
+void sweep_init_attributes();
 
 void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, hipStream_t st);
 void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w, double *f, double *e_atom,

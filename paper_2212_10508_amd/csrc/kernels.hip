@@ -584,7 +584,7 @@ void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, h
                        w.nbr, w.cnt, w.status);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, N, w.cnt, w.poff);
     hipLaunchKernelGGL(k_compact, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.nbr, w.cnt, w.poff, w.pair_i, w.pair_j);
-    hipLaunchKernelGGL(k_reverse, dim3(nblk(w.Pcap, 256)), dim3(256), 0, st, N, w.poff, w.pair_i, w.pair_j, w.rev,
+    hipLaunchKernelGGL(k_reverse, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, w.poff, w.pair_i, w.pair_j, w.rev,
                        w.status);
 }
 
@@ -603,7 +603,7 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     const int N = bd.N;
     KernelProf dummy;
     KernelProf &pf = prof ? *prof : dummy;
-    hipLaunchKernelGGL(k_pair_geo, dim3(nblk(w.Pcap, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
+    hipLaunchKernelGGL(k_pair_geo, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
                        w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
     pf.begin(PROF_DENSITY, st);
     hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 128), J / 2 + 1), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap,
@@ -613,7 +613,7 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     launch_adjoint(J, sd.adj, N, w.u, sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate, st);
     pf.end(st);
     pf.begin(PROF_DEDR, st);
-    hipLaunchKernelGGL(k_dedr<J>, dim3(nblk(w.Pcap, 64)), dim3(64), 0, st, N, w.poff, w.pair_i, w.geo, w.Pcap,
+    hipLaunchKernelGGL(k_dedr<J>, dim3(nblk((size_t)N * kMaxNeigh, 64)), dim3(64), 0, st, N, w.poff, w.pair_i, w.geo, w.Pcap,
                        w.ytil, w.dedr);
     pf.end(st);
     hipLaunchKernelGGL(k_gather, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.poff, w.rev, w.dedr, w.Pcap, f,
@@ -633,7 +633,7 @@ void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, 
 
 void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st) {
     const int N = bd.N;
-    hipLaunchKernelGGL(k_pair_geo, dim3(nblk(w.Pcap, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
+    hipLaunchKernelGGL(k_pair_geo, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
                        w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
     switch (J) {
         case 2: hipLaunchKernelGGL(k_density<2>, dim3(nblk(N, 128), 2), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;

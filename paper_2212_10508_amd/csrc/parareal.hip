@@ -272,6 +272,227 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep(SweepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// LDS-resident sweep for small systems (N <= kSweepLdsMaxAtoms): positions, rho and a
+// uint16 Verlet list live in LDS, momenta / forces / reference positions of the (at
+// most kSweepAtomsPerThread) atoms a thread owns live in its registers.
+// ---------------------------------------------------------------------------
+constexpr int kSweepLdsNeigh = 40;
+constexpr int kSweepAtomsPerThread = 2;
+constexpr int kSweepLdsMaxAtoms = kSweepThreads * kSweepAtomsPerThread;
+
+size_t sweep_lds_bytes(int N) {
+    return (size_t)N * (3 * sizeof(double) + sizeof(double) + kSweepLdsNeigh * sizeof(uint16_t)) +
+           kSweepThreads * sizeof(double);
+}
+
+using SwReg = double[kSweepAtomsPerThread][3];
+
+__device__ __forceinline__ void swl_build(const SweepArgs &a, const double *__restrict__ xs, uint16_t *__restrict__ nb,
+                                          int (&cn)[kSweepAtomsPerThread], SwReg &xr, int &overflow) {
+    const int N = a.N, tid = threadIdx.x;
+    const double rcl = fmax(a.fp.d, a.fp.c) + a.skin, rcl2 = rcl * rcl;
+#pragma unroll
+    for (int q = 0; q < kSweepAtomsPerThread; ++q) {
+        const int i = tid + q * kSweepThreads;
+        if (i >= N) continue;
+        const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
+        int c = 0;
+        for (int j = 0; j < N; ++j) {
+            if (j == i) continue;
+            const double dx = mimg_s(xs[j] - xi, a.Lx), dy = mimg_s(xs[N + j] - yi, a.Ly),
+                         dz = mimg_s(xs[2 * N + j] - zi, a.Lz);
+            if (dx * dx + dy * dy + dz * dz < rcl2) {
+                if (c < kSweepLdsNeigh) nb[c * N + i] = (uint16_t)j;
+                ++c;
+            }
+        }
+        if (c > kSweepLdsNeigh) {
+            overflow = 1;
+            c = kSweepLdsNeigh;
+        }
+        cn[q] = c;
+        xr[q][0] = xi;
+        xr[q][1] = yi;
+        xr[q][2] = zi;
+    }
+}
+
+// rho into LDS, barrier, forces into registers, barrier
+__device__ __forceinline__ void swl_force(const SweepArgs &a, const double *__restrict__ xs, double *__restrict__ rho,
+                                          const uint16_t *__restrict__ nb, const int (&cn)[kSweepAtomsPerThread],
+                                          SwReg &fr) {
+    const int N = a.N, tid = threadIdx.x;
+    const FsParams fp = a.fp;
+#pragma unroll
+    for (int q = 0; q < kSweepAtomsPerThread; ++q) {
+        const int i = tid + q * kSweepThreads;
+        if (i >= N) continue;
+        const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
+        double acc = 0.0;
+        for (int t = 0; t < cn[q]; ++t) {
+            const int j = nb[t * N + i];
+            const double dx = mimg_s(xs[j] - xi, a.Lx), dy = mimg_s(xs[N + j] - yi, a.Ly),
+                         dz = mimg_s(xs[2 * N + j] - zi, a.Lz);
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r < fp.d) acc += (r - fp.d) * (r - fp.d);
+        }
+        rho[i] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kSweepAtomsPerThread; ++q) {
+        const int i = tid + q * kSweepThreads;
+        if (i >= N) continue;
+        const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
+        const double ri = rho[i];
+        const double dFi = ri > 0.0 ? -fp.A / (2.0 * sqrt(ri)) : 0.0;
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int t = 0; t < cn[q]; ++t) {
+            const int j = nb[t * N + i];
+            const double dx = mimg_s(xs[j] - xi, a.Lx), dy = mimg_s(xs[N + j] - yi, a.Ly),
+                         dz = mimg_s(xs[2 * N + j] - zi, a.Lz);
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double dEdr = 0.0;
+            if (r < fp.c) {
+                const double tt = r - fp.c, poly = fp.c0 + r * (fp.c1 + r * fp.c2);
+                dEdr += 2.0 * tt * poly + tt * tt * (fp.c1 + 2.0 * fp.c2 * r);
+            }
+            if (r < fp.d) {
+                const double rj = rho[j];
+                const double dFj = rj > 0.0 ? -fp.A / (2.0 * sqrt(rj)) : 0.0;
+                dEdr += (dFi + dFj) * 2.0 * (r - fp.d);
+            }
+            if (r < fp.c || r < fp.d) {
+                const double w = dEdr / r;
+                fx += w * dx;
+                fy += w * dy;
+                fz += w * dz;
+            }
+        }
+        fr[q][0] = fx;
+        fr[q][1] = fy;
+        fr[q][2] = fz;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
+    extern __shared__ double sm[];
+    const int N = a.N;
+    double *red = sm;                                      // [1024]
+    double *xs = sm + kSweepThreads;                       // [3][N]
+    double *rho = xs + 3 * N;                              // [N]
+    uint16_t *nb = reinterpret_cast<uint16_t *>(rho + N);  // [kSweepLdsNeigh][N]
+    const int tid = threadIdx.x;
+    const size_t SN = (size_t)(a.n_fi - a.n_in) * N;
+    double pr[kSweepAtomsPerThread][3], fr[kSweepAtomsPerThread][3], xr[kSweepAtomsPerThread][3];
+    int cn[kSweepAtomsPerThread];
+#pragma unroll
+    for (int q = 0; q < kSweepAtomsPerThread; ++q) {
+        const int i = tid + q * kSweepThreads;
+        cn[q] = 0;
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+            fr[q][al] = 0.0;
+            xr[q][al] = 0.0;
+            pr[q][al] = 0.0;
+            if (i < N) {
+                xs[al * N + i] = a.q_cur[((size_t)a.n_in * 3 + al) * N + i];
+                pr[q][al] = a.p_cur[((size_t)a.n_in * 3 + al) * N + i];
+            }
+        }
+    }
+    __syncthreads();
+    int overflow = 0;
+    double num = 0.0, den = 0.0, delta = 0.0;
+    int nfi_new = a.n_fi, bad = -1;
+    const double hk = 0.5 * a.dt / SW_MVV2E, hd = 0.5 * a.dt / a.mass;
+    for (int n = a.n_in; n < a.n_fi; ++n) {
+        swl_build(a, xs, nb, cn, xr, overflow);
+        __syncthreads();
+        swl_force(a, xs, rho, nb, cn, fr);
+        for (int l = 0; l < a.L; ++l) {
+            const uint64_t gstep = (uint64_t)n * (uint64_t)a.L + (uint64_t)l;
+            double dmax = 0.0;
+#pragma unroll
+            for (int q = 0; q < kSweepAtomsPerThread; ++q) {
+                const int i = tid + q * kSweepThreads;
+                if (i >= N) continue;
+                double g[3];
+                sweep_gauss3(a.seed, a.noise_id, gstep, (uint64_t)i, g[0], g[1], g[2]);
+                double d2 = 0.0;
+#pragma unroll
+                for (int al = 0; al < 3; ++al) {
+                    double pp = pr[q][al] + hk * fr[q][al];
+                    double xx = xs[al * N + i] + hd * pp;
+                    pp = a.c1 * pp + a.sig * g[al];
+                    xx = xx + hd * pp;
+                    pr[q][al] = pp;
+                    xs[al * N + i] = xx;
+                    const double dd = xx - xr[q][al];
+                    d2 += dd * dd;
+                }
+                dmax = fmax(dmax, d2);
+            }
+            const double m = block_max(dmax, red);
+            if (4.0 * m > a.skin * a.skin) {
+                swl_build(a, xs, nb, cn, xr, overflow);
+                __syncthreads();
+            }
+            swl_force(a, xs, rho, nb, cn, fr);
+#pragma unroll
+            for (int q = 0; q < kSweepAtomsPerThread; ++q)
+#pragma unroll
+                for (int al = 0; al < 3; ++al) pr[q][al] = pr[q][al] + hk * fr[q][al];
+        }
+        const size_t s = (size_t)(n - a.n_in);
+        double d2 = 0.0, p2 = 0.0, fin = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSweepAtomsPerThread; ++q) {
+            const int i = tid + q * kSweepThreads;
+            if (i >= N) continue;
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                double xq = xs[al * N + i], pq = pr[q][al];
+                if (a.mode == 1) {
+                    xq += a.jq[al * SN + s * N + i];
+                    pq += a.jp[al * SN + s * N + i];
+                    const double pv = a.q_prev[((size_t)(n + 1) * 3 + al) * N + i];
+                    d2 += (xq - pv) * (xq - pv);
+                    p2 += pv * pv;
+                }
+                fin += xq * 0.0 + pq * 0.0;
+                xs[al * N + i] = xq;
+                pr[q][al] = pq;
+                a.q_cur[((size_t)(n + 1) * 3 + al) * N + i] = xq;
+                a.p_cur[((size_t)(n + 1) * 3 + al) * N + i] = pq;
+            }
+        }
+        const double sfin = block_sum(fin, red);
+        if (!isfinite(sfin)) {
+            bad = n;
+            break;
+        }
+        if (a.mode == 1) {
+            const double sd = block_sum(d2, red), sp = block_sum(p2, red);
+            num += sqrt(sd);
+            den += sqrt(sp);
+            delta = den > 0.0 ? num / den : 0.0;
+            if (delta > a.delta_expl) {
+                nfi_new = max(n, a.n_in + 1);
+                break;
+            }
+        }
+    }
+    if (overflow) a.out[3] = 1.0;
+    if (tid == 0) {
+        a.out[0] = delta;
+        a.out[1] = (double)nfi_new;
+        a.out[2] = (double)bad;
+    }
+}
+
+// ---------------------------------------------------------------------------
 void launch_slabs_to_batch(int S, int N, const double *slots, double *out, hipStream_t st) {
     const size_t tot = (size_t)3 * S * N;
     if (tot == 0) return;
@@ -316,7 +537,16 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     a.nbr = s.nbr;
     a.cnt = s.cnt;
     a.out = s.out;
-    hipLaunchKernelGGL(k_coarse_sweep, dim3(1), dim3(kSweepThreads), 0, st, a);
+    if (s.N <= kSweepLdsMaxAtoms && sweep_lds_bytes(s.N) <= 160 * 1024) {
+        hipLaunchKernelGGL(k_coarse_sweep_lds, dim3(1), dim3(kSweepThreads), sweep_lds_bytes(s.N), st, a);
+    } else {
+        hipLaunchKernelGGL(k_coarse_sweep, dim3(1), dim3(kSweepThreads), 0, st, a);
+    }
+}
+
+void sweep_init_attributes() {
+    (void)hipFuncSetAttribute((const void *)k_coarse_sweep_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
 }
 
 }  // namespace snapmd
