@@ -67,6 +67,8 @@ struct snapmd_ctx {
     DBuf<double> sw_x, sw_p, sw_f, sw_rho, sw_ref, sw_out;
     DBuf<int> sw_nbr, sw_cnt;
     double *h_out = nullptr;                      // pinned [4]
+    DBuf<double> sw_noise;                        // Gaussians of the current window
+    std::vector<double> noise_key;                // (n_in, S, L, N, seed, noise_id) it holds
     KernelProf prof;
 };
 
@@ -139,6 +141,7 @@ int ensure_atoms(snapmd_ctx *ctx, size_t N) {
     if ((rc = dalloc(ctx, &w.u, (size_t)n_half(kMaxJ) * cap))) return rc;
     if ((rc = dalloc(ctx, &w.ytil, (size_t)n_half(kMaxJ) * cap))) return rc;
     if ((rc = dalloc(ctx, &ctx->d_f, 3 * cap))) return rc;
+    if ((rc = dalloc(ctx, &w.xref, 3 * cap))) return rc;
     ctx->cap_atoms = cap;
     return SNAPMD_OK;
 }
@@ -283,13 +286,15 @@ int check_launch(snapmd_ctx *ctx) {
 }
 
 // Force of the chosen potential at x into f (overwrite), e_atom (nullable, overwrite).
+constexpr double kSkin = 0.3;  // Verlet skin of the batched path (A)
+
 void enqueue_forces(snapmd_ctx *ctx, int potential, const BatchDev &bd, const double *x, const FsParams *fp,
-                    const SnapDev *sd, double *f, double *e_atom, hipStream_t st) {
+                    const SnapDev *sd, double *f, double *e_atom, hipStream_t st, bool fresh = true) {
     double rc = 0.0;
     if (fp) rc = std::max(fp->d, fp->c);
     if (potential == SNAPMD_POT_FS_SNAP) rc = std::max(rc, sd->gp.rcut);
     ctx->prof.begin(PROF_NEIGH, st);
-    launch_neighbors(bd, x, rc, ctx->w, st);
+    launch_neighbors(bd, x, rc, ctx->w, st, fresh, kSkin);
     ctx->prof.end(st);
     launch_fs(bd, x, *fp, ctx->w, f, e_atom, 0, st);
     if (potential == SNAPMD_POT_FS_SNAP) launch_snap(sd->J, bd, x, *sd, ctx->w, f, e_atom, 1, st, &ctx->prof);
@@ -302,7 +307,7 @@ void run_langevin(snapmd_ctx *ctx, int potential, const BatchDev &bd, const FsPa
     enqueue_forces(ctx, potential, bd, x, &fp, &sd, f, nullptr, st);
     for (int s = 0; s < n_steps; ++s) {
         launch_baoab_pre(bd, x, p, f, ld, s, st);
-        enqueue_forces(ctx, potential, bd, x, &fp, &sd, f, nullptr, st);
+        enqueue_forces(ctx, potential, bd, x, &fp, &sd, f, nullptr, st, false);
         launch_baoab_post(bd, p, f, ld.dt, st);
     }
 }
@@ -349,7 +354,8 @@ int snapmd_create(snapmd_ctx **out, int hip_device) {
     ctx->device = hip_device;
     adjoint_init_attributes();
     sweep_init_attributes();
-    if (dalloc(ctx, &ctx->w.status, 1) != SNAPMD_OK || hipMemset(ctx->w.status, 0, sizeof(int)) != hipSuccess) {
+    if (dalloc(ctx, &ctx->w.status, 1) != SNAPMD_OK || hipMemset(ctx->w.status, 0, sizeof(int)) != hipSuccess ||
+        dalloc(ctx, &ctx->w.flag, 1) != SNAPMD_OK || hipMemset(ctx->w.flag, 0, sizeof(int)) != hipSuccess) {
         snapmd_destroy(ctx);
         return SNAPMD_ENOMEM;
     }
@@ -395,7 +401,7 @@ int snap_forces(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *ba
     if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
     if ((rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
-    launch_neighbors(bd, x, snap->rcut, ctx->w, st);
+    launch_neighbors(bd, x, snap->rcut, ctx->w, st, true, kSkin);
     launch_snap(sd.J, bd, x, sd, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st);
     return check_launch(ctx);
 }
@@ -413,7 +419,7 @@ int eam_forces(snapmd_ctx *ctx, const snapmd_fs *fs, const snapmd_batch *batch, 
     if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
     if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
-    launch_neighbors(bd, x, std::max(fp.d, fp.c), ctx->w, st);
+    launch_neighbors(bd, x, std::max(fp.d, fp.c), ctx->w, st, true, kSkin);
     launch_fs(bd, x, fp, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st);
     return check_launch(ctx);
 }
@@ -524,6 +530,17 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     sw.cnt = ctx->sw_cnt.p;
     sw.out = ctx->sw_out.p;
     HIPCHK(hipMemsetAsync(ctx->sw_out.p, 0, 4 * sizeof(double), st));
+    {
+        // Gaussians of every (slab, step, atom) of the window, shared by all iterations
+        const std::vector<double> key{(double)n_in, (double)S, (double)L, (double)N, (double)lang->seed,
+                                      (double)lang->noise_id_sys[0]};
+        if (key != ctx->noise_key) {
+            if ((rc = ensure(ctx, ctx->sw_noise, (size_t)S * L * 3 * N))) return rc;
+            launch_noise_table(S, L, N, n_in, lang->seed, (uint64_t)lang->noise_id_sys[0], ctx->sw_noise.p, st);
+            ctx->noise_key = key;
+        }
+        sw.noise = ctx->sw_noise.p;
+    }
     if (!init) {
         // prev_n := cur_n on [n_in, n_fi]
         const size_t slot = 3 * (size_t)N;
@@ -634,7 +651,7 @@ int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_bat
     if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
     if ((rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
-    launch_neighbors(bd, x, snap->rcut, ctx->w, st);
+    launch_neighbors(bd, x, snap->rcut, ctx->w, st, true, kSkin);
     launch_snap_density(sd.J, bd, x, sd, ctx->w, st);
     launch_bispectrum(bd, sd, ctx->w, B, st);
     return check_launch(ctx);

@@ -68,6 +68,8 @@ struct Work {
     size_t Pcap = 0;        // pair capacity (N * kMaxNeigh)
     int *nbr = nullptr, *cnt = nullptr, *poff = nullptr, *pair_i = nullptr, *pair_j = nullptr, *rev = nullptr;
     int *status = nullptr;  // device error bits: 1 neighbour overflow, 4 asymmetric list
+    int *flag = nullptr;    // rebuild request of the Verlet list
+    double *xref = nullptr; // [3][N] positions at the last build
     double *rho = nullptr;
     double *geo = nullptr;  // [20][Pcap]
     double *dedr = nullptr; // [3][Pcap]
@@ -126,13 +128,17 @@ struct SweepLaunch {
     double *wx, *wp, *wf, *wrho, *xref;
     int *nbr, *cnt;
     double *out;
+    const double *noise;  // [S][L][3][N], S = n_fi - n_in
 };
 void launch_slabs_to_batch(int S, int N, const double *slots, double *out, hipStream_t st);
 void launch_jumps(size_t n, double *a, const double *b, hipStream_t st);
 void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st);
 void sweep_init_attributes();
+void launch_noise_table(int S, int L, int N, int n_in, uint64_t seed, uint64_t noise_id, double *noise,
+                        hipStream_t st);
 
-void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, hipStream_t st);
+void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, hipStream_t st, bool force,
+                      double skin);
 void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w, double *f, double *e_atom,
                int accumulate, hipStream_t st);
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,

@@ -24,24 +24,28 @@ namespace snapmd {
 #define KB_EV 8.617333262145179e-5
 #define MVV2E 1.0364269652680506e-4
 
-__device__ __forceinline__ double mimg(double d, double L) { return d - L * rint(d / L); }
+__device__ __forceinline__ double mimg(double d, double L, double iL) { return d - L * rint(d * iL); }
 
 // ---------------------------------------------------------------------------
 // Neighbour lists
 // ---------------------------------------------------------------------------
 __global__ void k_neigh_build(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
                               const double *__restrict__ x, double rc2, int *__restrict__ nbr,
-                              int *__restrict__ cnt, int *__restrict__ status) {
+                              int *__restrict__ cnt, int *__restrict__ status, const int *__restrict__ flag,
+                              double *__restrict__ xref) {
+    if (*flag == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int s = sys_of(off, n_sys, i);
     const int j0 = off[s], j1 = off[s + 1];
     const double Lx = box[3 * s], Ly = box[3 * s + 1], Lz = box[3 * s + 2];
+    const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
     const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
     int c = 0;
     for (int j = j0; j < j1; ++j) {
         if (j == i) continue;
-        const double dx = mimg(x[j] - xi, Lx), dy = mimg(x[N + j] - yi, Ly), dz = mimg(x[2 * N + j] - zi, Lz);
+        const double dx = mimg(x[j] - xi, Lx, iLx), dy = mimg(x[N + j] - yi, Ly, iLy),
+                     dz = mimg(x[2 * N + j] - zi, Lz, iLz);
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < rc2) {
             if (c < kMaxNeigh) nbr[(size_t)i * kMaxNeigh + c] = j;
@@ -53,10 +57,27 @@ __global__ void k_neigh_build(int N, int n_sys, const int *__restrict__ off, con
         c = kMaxNeigh;
     }
     cnt[i] = c;
+    xref[i] = xi;
+    xref[N + i] = yi;
+    xref[2 * N + i] = zi;
 }
 
+// Request a rebuild (flag = 1) when some atom moved more than half the skin since the
+// last build.
+__global__ void k_check_disp(int N, const double *__restrict__ x, const double *__restrict__ xref, double lim2,
+                             int *__restrict__ flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double dx = x[i] - xref[i], dy = x[N + i] - xref[N + i], dz = x[2 * N + i] - xref[2 * N + i];
+    if (!(dx * dx + dy * dy + dz * dz <= lim2)) atomicOr(flag, 1);   // NaN also rebuilds
+}
+
+__global__ void k_set_flag(int *__restrict__ flag, int v) { *flag = v; }
+
 // Exclusive prefix sum of cnt[0..N) into poff[0..N] (one workgroup of 1024 threads).
-__global__ void __launch_bounds__(1024) k_scan(int N, const int *__restrict__ cnt, int *__restrict__ poff) {
+__global__ void __launch_bounds__(1024) k_scan(int N, const int *__restrict__ cnt, int *__restrict__ poff,
+                                              const int *__restrict__ flag) {
+    if (*flag == 0) return;
     __shared__ int part[1024];
     const int t = threadIdx.x;
     const int chunk = (N + 1023) / 1024;
@@ -80,7 +101,9 @@ __global__ void __launch_bounds__(1024) k_scan(int N, const int *__restrict__ cn
 }
 
 __global__ void k_compact(int N, const int *__restrict__ nbr, const int *__restrict__ cnt,
-                          const int *__restrict__ poff, int *__restrict__ pair_i, int *__restrict__ pair_j) {
+                          const int *__restrict__ poff, int *__restrict__ pair_i, int *__restrict__ pair_j,
+                          const int *__restrict__ flag) {
+    if (*flag == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int p0 = poff[i], c = cnt[i];
@@ -91,7 +114,9 @@ __global__ void k_compact(int N, const int *__restrict__ nbr, const int *__restr
 }
 
 __global__ void k_reverse(int N, const int *__restrict__ poff, const int *__restrict__ pair_i,
-                          const int *__restrict__ pair_j, int *__restrict__ rev, int *__restrict__ status) {
+                          const int *__restrict__ pair_j, int *__restrict__ rev, int *__restrict__ status,
+                          const int *__restrict__ flag) {
+    if (*flag == 0) return;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= poff[N]) return;
     const int i = pair_i[p], j = pair_j[p];
@@ -112,11 +137,12 @@ __global__ void k_fs_rho(int N, int n_sys, const int *__restrict__ off, const do
     if (i >= N) return;
     const int s = sys_of(off, n_sys, i);
     const double Lx = box[3 * s], Ly = box[3 * s + 1], Lz = box[3 * s + 2];
+    const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
     const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
     double acc = 0.0;
     for (int p = poff[i]; p < poff[i + 1]; ++p) {
         const int j = pair_j[p];
-        const double dx = mimg(x[j] - xi, Lx), dy = mimg(x[N + j] - yi, Ly), dz = mimg(x[2 * N + j] - zi, Lz);
+        const double dx = mimg(x[j] - xi, Lx, iLx), dy = mimg(x[N + j] - yi, Ly, iLy), dz = mimg(x[2 * N + j] - zi, Lz, iLz);
         const double r = sqrt(dx * dx + dy * dy + dz * dz);
         if (r < d) acc += (r - d) * (r - d);
     }
@@ -131,13 +157,14 @@ __global__ void k_fs_force(int N, int n_sys, const int *__restrict__ off, const 
     if (i >= N) return;
     const int s = sys_of(off, n_sys, i);
     const double Lx = box[3 * s], Ly = box[3 * s + 1], Lz = box[3 * s + 2];
+    const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
     const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
     const double ri = rho[i];
     const double dFi = ri > 0.0 ? -fp.A / (2.0 * sqrt(ri)) : 0.0;
     double fx = 0.0, fy = 0.0, fz = 0.0, ep = 0.0;
     for (int p = poff[i]; p < poff[i + 1]; ++p) {
         const int j = pair_j[p];
-        const double dx = mimg(x[j] - xi, Lx), dy = mimg(x[N + j] - yi, Ly), dz = mimg(x[2 * N + j] - zi, Lz);
+        const double dx = mimg(x[j] - xi, Lx, iLx), dy = mimg(x[N + j] - yi, Ly, iLy), dz = mimg(x[2 * N + j] - zi, Lz, iLz);
         const double r = sqrt(dx * dx + dy * dy + dz * dz);
         double dEdr = 0.0;
         if (r < fp.c) {
@@ -184,9 +211,9 @@ __global__ void k_pair_geo(int N, int n_sys, const int *__restrict__ off, const 
     const int i = pair_i[p], j = pair_j[p];
     const int s = sys_of(off, n_sys, i);
     double d[3];
-    d[0] = mimg(x[j] - x[i], box[3 * s]);
-    d[1] = mimg(x[N + j] - x[N + i], box[3 * s + 1]);
-    d[2] = mimg(x[2 * N + j] - x[2 * N + i], box[3 * s + 2]);
+    d[0] = mimg(x[j] - x[i], box[3 * s], 1.0 / box[3 * s]);
+    d[1] = mimg(x[N + j] - x[N + i], box[3 * s + 1], 1.0 / box[3 * s + 1]);
+    d[2] = mimg(x[2 * N + j] - x[2 * N + i], box[3 * s + 2], 1.0 / box[3 * s + 2]);
     const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     double g[20];
 #pragma unroll
@@ -578,14 +605,27 @@ __global__ void k_baoab_post(int N, double *__restrict__ p, const double *__rest
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
-void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, hipStream_t st) {
+// Verlet list: built with rc + skin when forced or when an atom has moved more than
+// skin/2 since the last build (decided on the device); the pair kernels apply the exact
+// cutoffs, so the list only decides which pairs are examined.
+void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, hipStream_t st, bool force,
+                      double skin) {
     const int N = bd.N;
-    hipLaunchKernelGGL(k_neigh_build, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, rc * rc,
-                       w.nbr, w.cnt, w.status);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, N, w.cnt, w.poff);
-    hipLaunchKernelGGL(k_compact, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.nbr, w.cnt, w.poff, w.pair_i, w.pair_j);
-    hipLaunchKernelGGL(k_reverse, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, w.poff, w.pair_i, w.pair_j, w.rev,
-                       w.status);
+    if (force) {
+        hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, st, w.flag, 1);
+    } else {
+        hipLaunchKernelGGL(k_check_disp, dim3(nblk(N, 256)), dim3(256), 0, st, N, x, w.xref, 0.25 * skin * skin,
+                           w.flag);
+    }
+    const double rl = rc + skin;
+    hipLaunchKernelGGL(k_neigh_build, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, rl * rl,
+                       w.nbr, w.cnt, w.status, w.flag, w.xref);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, N, w.cnt, w.poff, w.flag);
+    hipLaunchKernelGGL(k_compact, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.nbr, w.cnt, w.poff, w.pair_i, w.pair_j,
+                       w.flag);
+    hipLaunchKernelGGL(k_reverse, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, w.poff, w.pair_i,
+                       w.pair_j, w.rev, w.status, w.flag);
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, st, w.flag, 0);
 }
 
 void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w, double *f, double *e_atom,

@@ -25,7 +25,7 @@ namespace snapmd {
 #define SW_MVV2E 1.0364269652680506e-4
 constexpr int kSweepThreads = 1024;
 
-__device__ __forceinline__ double mimg_s(double d, double L) { return d - L * rint(d / L); }
+__device__ __forceinline__ double mimg_s(double d, double L, double iL) { return d - L * rint(d * iL); }
 
 __global__ void k_slabs_to_batch(int S, int N, const double *__restrict__ slots, double *__restrict__ out) {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -70,7 +70,7 @@ __device__ __forceinline__ double block_max(double v, double *red) {
 
 struct SweepArgs {
     int N;
-    double Lx, Ly, Lz;
+    double Lx, Ly, Lz, iLx, iLy, iLz;
     FsParams fp;
     double skin;
     double dt, c1, mass, sig;
@@ -83,6 +83,7 @@ struct SweepArgs {
     double *wx, *wp, *wf, *wrho, *xref;    // [3N], [3N], [3N], [N], [3N]
     int *nbr, *cnt;                        // [N][kMaxNeigh], [N]
     double *out;                           // [0] delta, [1] n_fi after, [2] bad slab (-1 none), [3] overflow
+    const double *noise;                   // [S][L][3][N] Gaussians of the window's slabs
 };
 
 __device__ void sweep_build(const SweepArgs &a) {
@@ -93,8 +94,8 @@ __device__ void sweep_build(const SweepArgs &a) {
         int c = 0;
         for (int j = 0; j < N; ++j) {
             if (j == i) continue;
-            const double dx = mimg_s(a.wx[j] - xi, a.Lx), dy = mimg_s(a.wx[N + j] - yi, a.Ly),
-                         dz = mimg_s(a.wx[2 * N + j] - zi, a.Lz);
+            const double dx = mimg_s(a.wx[j] - xi, a.Lx, a.iLx), dy = mimg_s(a.wx[N + j] - yi, a.Ly, a.iLy),
+                         dz = mimg_s(a.wx[2 * N + j] - zi, a.Lz, a.iLz);
             if (dx * dx + dy * dy + dz * dz < rc2) {
                 if (c < kMaxNeigh) a.nbr[(size_t)i * kMaxNeigh + c] = j;
                 ++c;
@@ -110,14 +111,17 @@ __device__ void sweep_build(const SweepArgs &a) {
 __device__ void sweep_force(const SweepArgs &a) {
     const int N = a.N;
     const FsParams fp = a.fp;
+    const double d2c = fp.d * fp.d, rc2f = fmax(fp.d, fp.c) * fmax(fp.d, fp.c);
     for (int i = threadIdx.x; i < N; i += kSweepThreads) {
         const double xi = a.wx[i], yi = a.wx[N + i], zi = a.wx[2 * N + i];
         double acc = 0.0;
         for (int t = 0; t < a.cnt[i]; ++t) {
             const int j = a.nbr[(size_t)i * kMaxNeigh + t];
-            const double dx = mimg_s(a.wx[j] - xi, a.Lx), dy = mimg_s(a.wx[N + j] - yi, a.Ly),
-                         dz = mimg_s(a.wx[2 * N + j] - zi, a.Lz);
-            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double dx = mimg_s(a.wx[j] - xi, a.Lx, a.iLx), dy = mimg_s(a.wx[N + j] - yi, a.Ly, a.iLy),
+                         dz = mimg_s(a.wx[2 * N + j] - zi, a.Lz, a.iLz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 >= d2c) continue;
+            const double r = sqrt(r2);
             if (r < fp.d) acc += (r - fp.d) * (r - fp.d);
         }
         a.wrho[i] = acc;
@@ -130,9 +134,11 @@ __device__ void sweep_force(const SweepArgs &a) {
         double fx = 0.0, fy = 0.0, fz = 0.0;
         for (int t = 0; t < a.cnt[i]; ++t) {
             const int j = a.nbr[(size_t)i * kMaxNeigh + t];
-            const double dx = mimg_s(a.wx[j] - xi, a.Lx), dy = mimg_s(a.wx[N + j] - yi, a.Ly),
-                         dz = mimg_s(a.wx[2 * N + j] - zi, a.Lz);
-            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double dx = mimg_s(a.wx[j] - xi, a.Lx, a.iLx), dy = mimg_s(a.wx[N + j] - yi, a.Ly, a.iLy),
+                         dz = mimg_s(a.wx[2 * N + j] - zi, a.Lz, a.iLz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 >= rc2f) continue;
+            const double r = sqrt(r2);
             double dEdr = 0.0;
             if (r < fp.c) {
                 const double tt = r - fp.c, poly = fp.c0 + r * (fp.c1 + r * fp.c2);
@@ -201,11 +207,13 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep(SweepArgs a) {
         __syncthreads();
         sweep_force(a);
         for (int l = 0; l < a.L; ++l) {
-            const uint64_t gstep = (uint64_t)n * (uint64_t)a.L + (uint64_t)l;
             double dmax = 0.0;
             for (int i = threadIdx.x; i < N; i += kSweepThreads) {
                 double g[3];
-                sweep_gauss3(a.seed, a.noise_id, gstep, (uint64_t)i, g[0], g[1], g[2]);
+                const double *gz = a.noise + ((size_t)((n - a.n_in) * a.L + l) * 3) * N + i;
+                g[0] = gz[0];
+                g[1] = gz[N];
+                g[2] = gz[2 * N];
                 double d2 = 0.0;
 #pragma unroll
                 for (int al = 0; al < 3; ++al) {
@@ -299,8 +307,8 @@ __device__ __forceinline__ void swl_build(const SweepArgs &a, const double *__re
         int c = 0;
         for (int j = 0; j < N; ++j) {
             if (j == i) continue;
-            const double dx = mimg_s(xs[j] - xi, a.Lx), dy = mimg_s(xs[N + j] - yi, a.Ly),
-                         dz = mimg_s(xs[2 * N + j] - zi, a.Lz);
+            const double dx = mimg_s(xs[j] - xi, a.Lx, a.iLx), dy = mimg_s(xs[N + j] - yi, a.Ly, a.iLy),
+                         dz = mimg_s(xs[2 * N + j] - zi, a.Lz, a.iLz);
             if (dx * dx + dy * dy + dz * dz < rcl2) {
                 if (c < kSweepLdsNeigh) nb[c * N + i] = (uint16_t)j;
                 ++c;
@@ -317,26 +325,38 @@ __device__ __forceinline__ void swl_build(const SweepArgs &a, const double *__re
     }
 }
 
-// rho into LDS, barrier, forces into registers, barrier
-__device__ __forceinline__ void swl_force(const SweepArgs &a, const double *__restrict__ xs, double *__restrict__ rho,
+// Embedding derivative F'(rho) = -A / (2 sqrt(rho)) of every atom into LDS, barrier,
+// forces into registers, barrier.  Neighbour loops are unrolled by 4 so that the LDS
+// reads of independent neighbours overlap.
+__device__ __forceinline__ void swl_force(const SweepArgs &a, const double *__restrict__ xs, double *__restrict__ dfe,
                                           const uint16_t *__restrict__ nb, const int (&cn)[kSweepAtomsPerThread],
                                           SwReg &fr) {
     const int N = a.N, tid = threadIdx.x;
     const FsParams fp = a.fp;
+    const double d2c = fp.d * fp.d, rc2f = fmax(fp.d, fp.c) * fmax(fp.d, fp.c);
 #pragma unroll
     for (int q = 0; q < kSweepAtomsPerThread; ++q) {
         const int i = tid + q * kSweepThreads;
         if (i >= N) continue;
         const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
         double acc = 0.0;
-        for (int t = 0; t < cn[q]; ++t) {
-            const int j = nb[t * N + i];
-            const double dx = mimg_s(xs[j] - xi, a.Lx), dy = mimg_s(xs[N + j] - yi, a.Ly),
-                         dz = mimg_s(xs[2 * N + j] - zi, a.Lz);
-            const double r = sqrt(dx * dx + dy * dy + dz * dz);
-            if (r < fp.d) acc += (r - fp.d) * (r - fp.d);
+        const int c = cn[q];
+        for (int t0 = 0; t0 < c; t0 += 4) {
+            int jj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) jj[u] = (t0 + u < c) ? (int)nb[(t0 + u) * N + i] : i;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = jj[u];
+                const double dx = mimg_s(xs[j] - xi, a.Lx, a.iLx), dy = mimg_s(xs[N + j] - yi, a.Ly, a.iLy),
+                             dz = mimg_s(xs[2 * N + j] - zi, a.Lz, a.iLz);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (j == i || r2 >= d2c) continue;
+                const double r = sqrt(r2);
+                acc += (r - fp.d) * (r - fp.d);
+            }
         }
-        rho[i] = acc;
+        dfe[i] = acc > 0.0 ? -fp.A / (2.0 * sqrt(acc)) : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -344,25 +364,27 @@ __device__ __forceinline__ void swl_force(const SweepArgs &a, const double *__re
         const int i = tid + q * kSweepThreads;
         if (i >= N) continue;
         const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
-        const double ri = rho[i];
-        const double dFi = ri > 0.0 ? -fp.A / (2.0 * sqrt(ri)) : 0.0;
+        const double dFi = dfe[i];
         double fx = 0.0, fy = 0.0, fz = 0.0;
-        for (int t = 0; t < cn[q]; ++t) {
-            const int j = nb[t * N + i];
-            const double dx = mimg_s(xs[j] - xi, a.Lx), dy = mimg_s(xs[N + j] - yi, a.Ly),
-                         dz = mimg_s(xs[2 * N + j] - zi, a.Lz);
-            const double r = sqrt(dx * dx + dy * dy + dz * dz);
-            double dEdr = 0.0;
-            if (r < fp.c) {
-                const double tt = r - fp.c, poly = fp.c0 + r * (fp.c1 + r * fp.c2);
-                dEdr += 2.0 * tt * poly + tt * tt * (fp.c1 + 2.0 * fp.c2 * r);
-            }
-            if (r < fp.d) {
-                const double rj = rho[j];
-                const double dFj = rj > 0.0 ? -fp.A / (2.0 * sqrt(rj)) : 0.0;
-                dEdr += (dFi + dFj) * 2.0 * (r - fp.d);
-            }
-            if (r < fp.c || r < fp.d) {
+        const int c = cn[q];
+        for (int t0 = 0; t0 < c; t0 += 4) {
+            int jj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) jj[u] = (t0 + u < c) ? (int)nb[(t0 + u) * N + i] : i;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = jj[u];
+                const double dx = mimg_s(xs[j] - xi, a.Lx, a.iLx), dy = mimg_s(xs[N + j] - yi, a.Ly, a.iLy),
+                             dz = mimg_s(xs[2 * N + j] - zi, a.Lz, a.iLz);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (j == i || r2 >= rc2f) continue;
+                const double r = sqrt(r2);
+                double dEdr = 0.0;
+                if (r < fp.c) {
+                    const double tt = r - fp.c, poly = fp.c0 + r * (fp.c1 + r * fp.c2);
+                    dEdr += 2.0 * tt * poly + tt * tt * (fp.c1 + 2.0 * fp.c2 * r);
+                }
+                if (r < fp.d) dEdr += (dFi + dfe[j]) * 2.0 * (r - fp.d);
                 const double w = dEdr / r;
                 fx += w * dx;
                 fy += w * dy;
@@ -407,19 +429,40 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
     double num = 0.0, den = 0.0, delta = 0.0;
     int nfi_new = a.n_fi, bad = -1;
     const double hk = 0.5 * a.dt / SW_MVV2E, hd = 0.5 * a.dt / a.mass;
+    bool built = false;
     for (int n = a.n_in; n < a.n_fi; ++n) {
-        swl_build(a, xs, nb, cn, xr, overflow);
-        __syncthreads();
+        // the list is rebuilt only if some atom moved more than skin/2 since the last build
+        double dmax0 = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSweepAtomsPerThread; ++q) {
+            const int i = tid + q * kSweepThreads;
+            if (i >= N) continue;
+            double d2 = 0.0;
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                const double dd = xs[al * N + i] - xr[q][al];
+                d2 += dd * dd;
+            }
+            dmax0 = fmax(dmax0, d2);
+        }
+        const double m0 = block_max(dmax0, red);
+        if (!built || !(4.0 * m0 <= a.skin * a.skin)) {
+            swl_build(a, xs, nb, cn, xr, overflow);
+            __syncthreads();
+            built = true;
+        }
         swl_force(a, xs, rho, nb, cn, fr);
         for (int l = 0; l < a.L; ++l) {
-            const uint64_t gstep = (uint64_t)n * (uint64_t)a.L + (uint64_t)l;
             double dmax = 0.0;
 #pragma unroll
             for (int q = 0; q < kSweepAtomsPerThread; ++q) {
                 const int i = tid + q * kSweepThreads;
                 if (i >= N) continue;
                 double g[3];
-                sweep_gauss3(a.seed, a.noise_id, gstep, (uint64_t)i, g[0], g[1], g[2]);
+                const double *gz = a.noise + ((size_t)((n - a.n_in) * a.L + l) * 3) * N + i;
+                g[0] = gz[0];
+                g[1] = gz[N];
+                g[2] = gz[2 * N];
                 double d2 = 0.0;
 #pragma unroll
                 for (int al = 0; al < 3; ++al) {
@@ -492,6 +535,31 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
     }
 }
 
+// Gaussians of every (slab, step, atom) of a window: noise[s][l][al][i] for global step
+// (n_in + s) L + l, drawn exactly as the batched propagators draw them.
+__global__ void k_noise_table(int S, int L, int N, int n_in, uint64_t seed, uint64_t noise_id,
+                              double *__restrict__ noise) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (size_t)S * L * N) return;
+    const int i = (int)(q % N);
+    const size_t sl = q / N;  // s * L + l
+    const uint64_t gstep = (uint64_t)n_in * (uint64_t)L + (uint64_t)sl;
+    double g0, g1, g2;
+    sweep_gauss3(seed, noise_id, gstep, (uint64_t)i, g0, g1, g2);
+    double *o = noise + sl * 3 * N + i;
+    o[0] = g0;
+    o[N] = g1;
+    o[2 * N] = g2;
+}
+
+void launch_noise_table(int S, int L, int N, int n_in, uint64_t seed, uint64_t noise_id, double *noise,
+                        hipStream_t st) {
+    const size_t tot = (size_t)S * L * N;
+    if (tot == 0) return;
+    hipLaunchKernelGGL(k_noise_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, S, L, N, n_in, seed,
+                       noise_id, noise);
+}
+
 // ---------------------------------------------------------------------------
 void launch_slabs_to_batch(int S, int N, const double *slots, double *out, hipStream_t st) {
     const size_t tot = (size_t)3 * S * N;
@@ -510,6 +578,10 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     a.Lx = s.box[0];
     a.Ly = s.box[1];
     a.Lz = s.box[2];
+    a.iLx = 1.0 / s.box[0];
+    a.iLy = 1.0 / s.box[1];
+    a.iLz = 1.0 / s.box[2];
+    a.noise = s.noise;
     a.fp = s.fp;
     a.skin = s.skin;
     a.dt = s.dt;
