@@ -68,6 +68,7 @@ struct snapmd_ctx {
     DBuf<int> sw_nbr, sw_cnt;
     double *h_out = nullptr;                      // pinned [4]
     DBuf<double> sw_noise;                        // Gaussians of the current window
+    DBuf<double> gB;                              // [K][N] bispectrum / its variation
     std::vector<double> noise_key;                // (n_in, S, L, N, seed, noise_id) it holds
     KernelProf prof;
 };
@@ -631,9 +632,35 @@ int snapmd_pair_count(snapmd_ctx *ctx, int64_t *n_pairs) {
     return SNAPMD_OK;
 }
 
-int snap_beta_grad(snapmd_ctx *ctx, const snapmd_snap *, const snapmd_batch *, const double *, const double *,
-                   double *, double *, void *) {
-    return fail(ctx, SNAPMD_EUNSUPPORTED, "snap_beta_grad: not built yet");
+int snap_beta_grad(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *batch, const double *x,
+                   const double *w, double *dEdbeta, double *gradF, void *stream) {
+    if (!ctx) return SNAPMD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!x || !w || !dEdbeta || !gradF) return fail(ctx, SNAPMD_EINVAL, "x, w, dEdbeta and gradF must be device pointers");
+    BatchDev bd;
+    double mh;
+    SnapDev sd;
+    int rc;
+    if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
+    if ((rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
+    const int N = bd.N, K = sd.K;
+    launch_set_value(dEdbeta, (double)N, st);
+    launch_set_value(gradF, 0.0, st);
+    if (N == 0) {
+        HIPCHK(hipMemsetAsync(dEdbeta + 1, 0, K * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(gradF + 1, 0, K * sizeof(double), st));
+        return check_launch(ctx);
+    }
+    if ((rc = ensure(ctx, ctx->gB, (size_t)K * N))) return rc;
+    launch_neighbors(bd, x, snap->rcut, ctx->w, st, true, kSkin);
+    launch_snap_density(sd.J, bd, x, sd, ctx->w, st);           // u (and the pair geometry)
+    launch_bispectrum(bd, sd, ctx->w, ctx->gB.p, st);           // B[k][i]
+    launch_reduce_rows(K, N, ctx->gB.p, 1.0, dEdbeta + 1, st);
+    launch_jvp_density(sd.J, N, ctx->w, w, sd.nrm, ctx->w.ytil, st);  // du along w
+    launch_bispectrum_jvp(N, sd, ctx->w.u, ctx->w.ytil, ctx->gB.p, st);
+    launch_reduce_rows(K, N, ctx->gB.p, -1.0, gradF + 1, st);
+    return check_launch(ctx);
 }
 
 // Bispectrum of every atom, B[t][i] (device, [K][n_atoms]); used by tests and the

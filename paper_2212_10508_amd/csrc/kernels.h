@@ -149,6 +149,12 @@ void adjoint_init_attributes();
 void launch_adjoint(int J, const AdjointDev &ad, int N, const double2 *u, const double *nrm, const double *ymult,
                     double beta0, double2 *ytil, double *e_atom, int accumulate, hipStream_t st);
 void launch_bispectrum(const BatchDev &bd, const SnapDev &sd, Work &w, double *B, hipStream_t st);
+void launch_jvp_density(int J, int N, const Work &w, const double *wf, const double *nrm, double2 *du,
+                        hipStream_t st);
+void launch_bispectrum_jvp(int N, const SnapDev &sd, const double2 *u, const double2 *du, double *dB,
+                           hipStream_t st);
+void launch_reduce_rows(int rows, int N, const double *in, double scale, double *out, hipStream_t st);
+void launch_set_value(double *p, double v, hipStream_t st);
 void launch_baoab_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
                       hipStream_t st);
 void launch_baoab_post(const BatchDev &bd, double *p, const double *f, double dt, hipStream_t st);
