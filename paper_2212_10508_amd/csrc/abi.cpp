@@ -69,6 +69,11 @@ struct snapmd_ctx {
     double *h_out = nullptr;                      // pinned [4]
     DBuf<double> sw_noise;                        // Gaussians of the current window
     DBuf<double> gB;                              // [K][N] bispectrum / its variation
+    // cell grids of the current batch for the last list cutoff
+    DBuf<int4> d_cells;
+    std::vector<double> cell_key;
+    int n_cells = 0;
+    bool any_cells = false;
     std::vector<double> noise_key;                // (n_in, S, L, N, seed, noise_id) it holds
     KernelProf prof;
 };
@@ -143,6 +148,8 @@ int ensure_atoms(snapmd_ctx *ctx, size_t N) {
     if ((rc = dalloc(ctx, &w.ytil, (size_t)n_half(kMaxJ) * cap))) return rc;
     if ((rc = dalloc(ctx, &ctx->d_f, 3 * cap))) return rc;
     if ((rc = dalloc(ctx, &w.xref, 3 * cap))) return rc;
+    if ((rc = dalloc(ctx, &w.cell_of, cap))) return rc;
+    if ((rc = dalloc(ctx, &w.cell_atoms, cap))) return rc;
     ctx->cap_atoms = cap;
     return SNAPMD_OK;
 }
@@ -289,13 +296,65 @@ int check_launch(snapmd_ctx *ctx) {
 // Force of the chosen potential at x into f (overwrite), e_atom (nullable, overwrite).
 constexpr double kSkin = 0.3;  // Verlet skin of the batched path (A)
 
+// Cell grids (cell edge >= list cutoff rl, >= 3 cells per edge, else brute force) of the
+// current batch; rebuilt when the batch or the cutoff changes.
+int prepare_cells(snapmd_ctx *ctx, BatchDev &bd, double rl, hipStream_t st) {
+    std::vector<double> key(ctx->h_box.begin(), ctx->h_box.end());
+    key.insert(key.end(), ctx->h_off.begin(), ctx->h_off.end());
+    key.push_back(rl);
+    if (key != ctx->cell_key) {
+        const int S = (int)ctx->h_off.size() - 1;
+        std::vector<int4> ci(S);
+        int C = 0;
+        bool any = false;
+        for (int s = 0; s < S; ++s) {
+            int n3[3];
+            for (int a = 0; a < 3; ++a) n3[a] = (int)std::floor(ctx->h_box[3 * s + a] / rl);
+            const int natoms = ctx->h_off[s + 1] - ctx->h_off[s];
+            // cells pay off only for systems well above a few hundred atoms
+            if (n3[0] >= 3 && n3[1] >= 3 && n3[2] >= 3 && natoms >= 2000) {
+                ci[s] = make_int4(n3[0], n3[1], n3[2], C);
+                C += n3[0] * n3[1] * n3[2];
+                any = true;
+            } else {
+                ci[s] = make_int4(0, 0, 0, C);
+            }
+        }
+        int rc;
+        if ((rc = ensure(ctx, ctx->d_cells, (size_t)S))) return rc;
+        if ((rc = upload(ctx, ctx->d_cells.p, ci.data(), S, st))) return rc;
+        Work &w = ctx->w;
+        if (any && (size_t)C + 1 > w.cap_cells) {
+            if ((rc = dalloc(ctx, &w.cell_cnt, C + 1)) || (rc = dalloc(ctx, &w.cell_fill, C + 1)) ||
+                (rc = dalloc(ctx, &w.cell_start, C + 1)))
+                return rc;
+            w.cap_cells = C + 1;
+        }
+        ctx->n_cells = C;
+        ctx->any_cells = any;
+        ctx->cell_key = key;
+    }
+    bd.cells = ctx->any_cells ? ctx->d_cells.p : nullptr;
+    bd.n_cells = ctx->any_cells ? ctx->n_cells : 0;
+    return SNAPMD_OK;
+}
+
+// launch_neighbors with the cell grids of the batch
+int neighbors(snapmd_ctx *ctx, const BatchDev &bd0, const double *x, double rc, bool force, hipStream_t st) {
+    BatchDev bd = bd0;
+    int r;
+    if ((r = prepare_cells(ctx, bd, rc + kSkin, st))) return r;
+    launch_neighbors(bd, x, rc, ctx->w, st, force, kSkin);
+    return SNAPMD_OK;
+}
+
 void enqueue_forces(snapmd_ctx *ctx, int potential, const BatchDev &bd, const double *x, const FsParams *fp,
                     const SnapDev *sd, double *f, double *e_atom, hipStream_t st, bool fresh = true) {
     double rc = 0.0;
     if (fp) rc = std::max(fp->d, fp->c);
     if (potential == SNAPMD_POT_FS_SNAP) rc = std::max(rc, sd->gp.rcut);
     ctx->prof.begin(PROF_NEIGH, st);
-    launch_neighbors(bd, x, rc, ctx->w, st, fresh, kSkin);
+    (void)neighbors(ctx, bd, x, rc, fresh, st);
     ctx->prof.end(st);
     launch_fs(bd, x, *fp, ctx->w, f, e_atom, 0, st);
     if (potential == SNAPMD_POT_FS_SNAP) launch_snap(sd->J, bd, x, *sd, ctx->w, f, e_atom, 1, st, &ctx->prof);
@@ -402,7 +461,7 @@ int snap_forces(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *ba
     if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
     if ((rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
-    launch_neighbors(bd, x, snap->rcut, ctx->w, st, true, kSkin);
+    if ((rc = neighbors(ctx, bd, x, snap->rcut, true, st))) return rc;
     launch_snap(sd.J, bd, x, sd, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st);
     return check_launch(ctx);
 }
@@ -420,7 +479,7 @@ int eam_forces(snapmd_ctx *ctx, const snapmd_fs *fs, const snapmd_batch *batch, 
     if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
     if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
-    launch_neighbors(bd, x, std::max(fp.d, fp.c), ctx->w, st, true, kSkin);
+    if ((rc = neighbors(ctx, bd, x, std::max(fp.d, fp.c), true, st))) return rc;
     launch_fs(bd, x, fp, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st);
     return check_launch(ctx);
 }
@@ -535,7 +594,7 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         // Gaussians of every (slab, step, atom) of the window, shared by all iterations
         const std::vector<double> key{(double)n_in, (double)S, (double)L, (double)N, (double)lang->seed,
                                       (double)lang->noise_id_sys[0]};
-        if (key != ctx->noise_key) {
+        if (sweep_fits_lds(N) && key != ctx->noise_key) {
             if ((rc = ensure(ctx, ctx->sw_noise, (size_t)S * L * 3 * N))) return rc;
             launch_noise_table(S, L, N, n_in, lang->seed, (uint64_t)lang->noise_id_sys[0], ctx->sw_noise.p, st);
             ctx->noise_key = key;
@@ -581,16 +640,60 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         sw.jq = ctx->pr_xf.p;
         sw.jp = ctx->pr_pf.p;
     }
-    launch_coarse_sweep(sw, st);
-    if ((rc = check_launch(ctx))) return rc;
-    HIPCHK(hipMemcpyAsync(ctx->h_out, ctx->sw_out.p, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-    if ((rc = snapmd_sync(ctx, stream))) return rc;
-    if (ctx->h_out[3] != 0.0) return fail(ctx, SNAPMD_EOVERFLOW, "an atom has more than %d neighbours", kMaxNeigh);
-    if (ctx->h_out[2] >= 0.0)
-        return fail(ctx, SNAPMD_ENONFINITE, "state became non-finite in slab %d", (int)ctx->h_out[2]);
-    *delta_out = ctx->h_out[0];
-    *n_fi = (int32_t)ctx->h_out[1];
-    return SNAPMD_OK;
+    if (sweep_fits_lds(N)) {
+        launch_coarse_sweep(sw, st);
+        if ((rc = check_launch(ctx))) return rc;
+        HIPCHK(hipMemcpyAsync(ctx->h_out, ctx->sw_out.p, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+        if ((rc = snapmd_sync(ctx, stream))) return rc;
+        if (ctx->h_out[3] != 0.0) return fail(ctx, SNAPMD_EOVERFLOW, "an atom has more than %d neighbours", kMaxNeigh);
+        if (ctx->h_out[2] >= 0.0)
+            return fail(ctx, SNAPMD_ENONFINITE, "state became non-finite in slab %d", (int)ctx->h_out[2]);
+        *delta_out = ctx->h_out[0];
+        *n_fi = (int32_t)ctx->h_out[1];
+        return SNAPMD_OK;
+    }
+    // Large systems: the same sweep driven from the host with the batched kernels, one
+    // small synchronisation per slab for the relative error and the early stop.
+    {
+        const size_t slot = 3 * (size_t)N;
+        HIPCHK(hipMemcpyAsync(sw.wx, q_cur + n_in * slot, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(sw.wp, p_cur + n_in * slot, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
+        int off1[2] = {0, N};
+        snapmd_batch b1{1, off1, box};
+        BatchDev bd1;
+        double mh1;
+        if ((rc = prepare_batch(ctx, &b1, bd1, mh1, st))) return rc;
+        double num = 0.0, den = 0.0, delta = 0.0;
+        int nfi_new = *n_fi;
+        for (int n = n_in; n < *n_fi; ++n) {
+            std::vector<double> T1(1, lang->T_sys[0]);
+            std::vector<int64_t> s1(1, (int64_t)n * L);
+            std::vector<int> id1(1, lang->noise_id_sys[0]);
+            LangevinDev ld1;
+            if ((rc = prepare_langevin(ctx, lang, 1, T1, s1, id1, ld1, st))) return rc;
+            run_langevin(ctx, SNAPMD_POT_FS, bd1, fp, sd, ld1, L, sw.wx, sw.wp, st);
+            launch_slab_end(N, init ? 0 : 1, SN3 / 3, (size_t)(n - n_in), sw.wx, sw.wp, sw.jq, sw.jp,
+                            init ? nullptr : q_prev + (size_t)(n + 1) * slot, q_cur + (size_t)(n + 1) * slot,
+                            p_cur + (size_t)(n + 1) * slot, ctx->sw_out.p, st);
+            if ((rc = check_launch(ctx))) return rc;
+            HIPCHK(hipMemcpyAsync(ctx->h_out, ctx->sw_out.p, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+            if ((rc = snapmd_sync(ctx, stream))) return rc;
+            if (!std::isfinite(ctx->h_out[2]))
+                return fail(ctx, SNAPMD_ENONFINITE, "state became non-finite in slab %d", n);
+            if (!init) {
+                num += std::sqrt(ctx->h_out[0]);
+                den += std::sqrt(ctx->h_out[1]);
+                delta = den > 0.0 ? num / den : 0.0;
+                if (delta > delta_expl) {
+                    nfi_new = std::max(n, n_in + 1);
+                    break;
+                }
+            }
+        }
+        *delta_out = delta;
+        *n_fi = nfi_new;
+        return SNAPMD_OK;
+    }
 }
 
 int snapmd_profile(snapmd_ctx *ctx, int enable) {
@@ -653,7 +756,7 @@ int snap_beta_grad(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch 
         return check_launch(ctx);
     }
     if ((rc = ensure(ctx, ctx->gB, (size_t)K * N))) return rc;
-    launch_neighbors(bd, x, snap->rcut, ctx->w, st, true, kSkin);
+    if ((rc = neighbors(ctx, bd, x, snap->rcut, true, st))) return rc;
     launch_snap_density(sd.J, bd, x, sd, ctx->w, st);           // u (and the pair geometry)
     launch_bispectrum(bd, sd, ctx->w, ctx->gB.p, st);           // B[k][i]
     launch_reduce_rows(K, N, ctx->gB.p, 1.0, dEdbeta + 1, st);
@@ -678,7 +781,7 @@ int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_bat
     if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
     if ((rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
-    launch_neighbors(bd, x, snap->rcut, ctx->w, st, true, kSkin);
+    if ((rc = neighbors(ctx, bd, x, snap->rcut, true, st))) return rc;
     launch_snap_density(sd.J, bd, x, sd, ctx->w, st);
     launch_bispectrum(bd, sd, ctx->w, B, st);
     return check_launch(ctx);

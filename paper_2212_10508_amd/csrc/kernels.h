@@ -13,6 +13,8 @@ struct BatchDev {
     int n_sys = 0;
     const int *off = nullptr;     // [n_sys + 1]
     const double *box = nullptr;  // [3 * n_sys]
+    const int4 *cells = nullptr;  // [n_sys] (nx, ny, nz, first cell); nx = 0: brute force
+    int n_cells = 0;
 };
 
 struct FsParams {
@@ -69,6 +71,8 @@ struct Work {
     int *nbr = nullptr, *cnt = nullptr, *poff = nullptr, *pair_i = nullptr, *pair_j = nullptr, *rev = nullptr;
     int *status = nullptr;  // device error bits: 1 neighbour overflow, 4 asymmetric list
     int *flag = nullptr;    // rebuild request of the Verlet list
+    int *cell_of = nullptr, *cell_cnt = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_atoms = nullptr;
+    size_t cap_cells = 0;
     double *xref = nullptr; // [3][N] positions at the last build
     double *rho = nullptr;
     double *geo = nullptr;  // [20][Pcap]
@@ -134,6 +138,9 @@ void launch_slabs_to_batch(int S, int N, const double *slots, double *out, hipSt
 void launch_jumps(size_t n, double *a, const double *b, hipStream_t st);
 void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st);
 void sweep_init_attributes();
+bool sweep_fits_lds(int N);
+void launch_slab_end(int N, int mode, size_t SN, size_t s, double *xs, double *ps, const double *jq, const double *jp,
+                     const double *qprev_next, double *qcur_next, double *pcur_next, double *part, hipStream_t st);
 void launch_noise_table(int S, int L, int N, int n_in, uint64_t seed, uint64_t noise_id, double *noise,
                         hipStream_t st);
 

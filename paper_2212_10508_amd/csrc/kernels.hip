@@ -29,10 +29,26 @@ __device__ __forceinline__ double mimg(double d, double L, double iL) { return d
 // ---------------------------------------------------------------------------
 // Neighbour lists
 // ---------------------------------------------------------------------------
+// Candidate j of atom i: minimum image, squared distance below rc2.
+__device__ __forceinline__ void nb_try(int i, int j, double xi, double yi, double zi, const double *__restrict__ x,
+                                       int N, double Lx, double Ly, double Lz, double iLx, double iLy, double iLz,
+                                       double rc2, int *__restrict__ nbr, int &c) {
+    const double dx = mimg(x[j] - xi, Lx, iLx), dy = mimg(x[N + j] - yi, Ly, iLy), dz = mimg(x[2 * N + j] - zi, Lz, iLz);
+    if (dx * dx + dy * dy + dz * dz < rc2) {
+        if (c < kMaxNeigh) nbr[(size_t)i * kMaxNeigh + c] = j;
+        ++c;
+    }
+}
+
+// Full list of atom i: with cells (27-cell stencil of its system's grid, atoms of a cell
+// in ascending index order) when the system has >= 3 cells per edge, else all atoms of
+// its system.
 __global__ void k_neigh_build(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
                               const double *__restrict__ x, double rc2, int *__restrict__ nbr,
                               int *__restrict__ cnt, int *__restrict__ status, const int *__restrict__ flag,
-                              double *__restrict__ xref) {
+                              double *__restrict__ xref, const int4 *__restrict__ cells,
+                              const int *__restrict__ cell_of, const int *__restrict__ cell_start,
+                              const int *__restrict__ cell_atoms) {
     if (*flag == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
@@ -42,15 +58,27 @@ __global__ void k_neigh_build(int N, int n_sys, const int *__restrict__ off, con
     const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
     const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
     int c = 0;
-    for (int j = j0; j < j1; ++j) {
-        if (j == i) continue;
-        const double dx = mimg(x[j] - xi, Lx, iLx), dy = mimg(x[N + j] - yi, Ly, iLy),
-                     dz = mimg(x[2 * N + j] - zi, Lz, iLz);
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < rc2) {
-            if (c < kMaxNeigh) nbr[(size_t)i * kMaxNeigh + c] = j;
-            ++c;
+    const int4 ci = cells ? cells[s] : make_int4(0, 0, 0, 0);
+    if (ci.x >= 3) {
+        const int me = cell_of[i] - ci.w;
+        const int iz = me % ci.z, iy = (me / ci.z) % ci.y, ix = me / (ci.z * ci.y);
+        for (int ax = -1; ax <= 1; ++ax) {
+            const int cx = (ix + ax + ci.x) % ci.x;
+            for (int ay = -1; ay <= 1; ++ay) {
+                const int cy = (iy + ay + ci.y) % ci.y;
+                for (int az = -1; az <= 1; ++az) {
+                    const int cz = (iz + az + ci.z) % ci.z;
+                    const int cc = ci.w + (cx * ci.y + cy) * ci.z + cz;
+                    for (int q = cell_start[cc]; q < cell_start[cc + 1]; ++q) {
+                        const int j = cell_atoms[q];
+                        if (j != i) nb_try(i, j, xi, yi, zi, x, N, Lx, Ly, Lz, iLx, iLy, iLz, rc2, nbr, c);
+                    }
+                }
+            }
         }
+    } else {
+        for (int j = j0; j < j1; ++j)
+            if (j != i) nb_try(i, j, xi, yi, zi, x, N, Lx, Ly, Lz, iLx, iLy, iLz, rc2, nbr, c);
     }
     if (c > kMaxNeigh) {
         atomicOr(status, 1);
@@ -60,6 +88,71 @@ __global__ void k_neigh_build(int N, int n_sys, const int *__restrict__ off, con
     xref[i] = xi;
     xref[N + i] = yi;
     xref[2 * N + i] = zi;
+}
+
+// Cell binning (only when a rebuild is requested): cells[s] = (nx, ny, nz, first cell)
+// with nx = 0 for systems searched by brute force.
+__global__ void k_cell_zero(int C, int *__restrict__ cnt, int *__restrict__ fill, const int *__restrict__ flag) {
+    if (*flag == 0) return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < C) {
+        cnt[c] = 0;
+        fill[c] = 0;
+    }
+}
+
+__global__ void k_cell_assign(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
+                              const double *__restrict__ x, const int4 *__restrict__ cells, int *__restrict__ cell_of,
+                              int *__restrict__ cnt, const int *__restrict__ flag) {
+    if (*flag == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int s = sys_of(off, n_sys, i);
+    const int4 ci = cells[s];
+    if (ci.x < 3) {
+        cell_of[i] = -1;
+        return;
+    }
+    int idx[3];
+    const int n3[3] = {ci.x, ci.y, ci.z};
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        const double f = x[al * N + i] / box[3 * s + al];
+        const double fr = f - floor(f);
+        int k = (int)(fr * n3[al]);
+        idx[al] = k < 0 ? 0 : (k >= n3[al] ? n3[al] - 1 : k);
+    }
+    const int c = ci.w + (idx[0] * ci.y + idx[1]) * ci.z + idx[2];
+    cell_of[i] = c;
+    atomicAdd(&cnt[c], 1);
+}
+
+__global__ void k_cell_fill(int N, const int *__restrict__ cell_of, const int *__restrict__ cell_start,
+                            int *__restrict__ fill, int *__restrict__ cell_atoms, const int *__restrict__ flag) {
+    if (*flag == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int c = cell_of[i];
+    if (c < 0) return;
+    cell_atoms[cell_start[c] + atomicAdd(&fill[c], 1)] = i;
+}
+
+// ascending atom order inside every cell, so that neighbour lists are deterministic
+__global__ void k_cell_sort(int C, const int *__restrict__ cell_start, int *__restrict__ cell_atoms,
+                            const int *__restrict__ flag) {
+    if (*flag == 0) return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const int b = cell_start[c], e = cell_start[c + 1];
+    for (int q = b + 1; q < e; ++q) {
+        const int v = cell_atoms[q];
+        int r = q - 1;
+        while (r >= b && cell_atoms[r] > v) {
+            cell_atoms[r + 1] = cell_atoms[r];
+            --r;
+        }
+        cell_atoms[r + 1] = v;
+    }
 }
 
 // Request a rebuild (flag = 1) when some atom moved more than half the skin since the
@@ -618,8 +711,19 @@ void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, h
                            w.flag);
     }
     const double rl = rc + skin;
+    if (bd.cells && bd.n_cells > 0) {
+        const int C = bd.n_cells;
+        hipLaunchKernelGGL(k_cell_zero, dim3(nblk(C, 256)), dim3(256), 0, st, C, w.cell_cnt, w.cell_fill, w.flag);
+        hipLaunchKernelGGL(k_cell_assign, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
+                           bd.cells, w.cell_of, w.cell_cnt, w.flag);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, C, w.cell_cnt, w.cell_start, w.flag);
+        hipLaunchKernelGGL(k_cell_fill, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.cell_of, w.cell_start, w.cell_fill,
+                           w.cell_atoms, w.flag);
+        hipLaunchKernelGGL(k_cell_sort, dim3(nblk(C, 256)), dim3(256), 0, st, C, w.cell_start, w.cell_atoms, w.flag);
+    }
     hipLaunchKernelGGL(k_neigh_build, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, rl * rl,
-                       w.nbr, w.cnt, w.status, w.flag, w.xref);
+                       w.nbr, w.cnt, w.status, w.flag, w.xref, (bd.cells && bd.n_cells > 0) ? bd.cells : nullptr,
+                       w.cell_of, w.cell_start, w.cell_atoms);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, N, w.cnt, w.poff, w.flag);
     hipLaunchKernelGGL(k_compact, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.nbr, w.cnt, w.poff, w.pair_i, w.pair_j,
                        w.flag);

@@ -560,6 +560,50 @@ void launch_noise_table(int S, int L, int N, int n_in, uint64_t seed, uint64_t n
                        noise_id, noise);
 }
 
+// End of slab n for the host-driven sweep of large systems: cur_{n+1} = state (+ J_n),
+// written to the slab slot and back into the running state; partial sums of
+// |cur - prev|^2, |prev|^2 and a non-finite probe into part[0..2] (one workgroup, fixed
+// reduction order).
+__global__ void __launch_bounds__(1024) k_slab_end(int N, int mode, size_t SN, size_t s, double *__restrict__ xs,
+                                                   double *__restrict__ ps, const double *__restrict__ jq,
+                                                   const double *__restrict__ jp,
+                                                   const double *__restrict__ qprev_next,
+                                                   double *__restrict__ qcur_next, double *__restrict__ pcur_next,
+                                                   double *__restrict__ part) {
+    __shared__ double red[kSweepThreads];
+    double d2 = 0.0, p2 = 0.0, fin = 0.0;
+    for (int i = threadIdx.x; i < N; i += kSweepThreads)
+        for (int al = 0; al < 3; ++al) {
+            double xq = xs[al * N + i], pq = ps[al * N + i];
+            if (mode == 1) {
+                xq += jq[al * SN + s * N + i];
+                pq += jp[al * SN + s * N + i];
+                const double pv = qprev_next[al * N + i];
+                d2 += (xq - pv) * (xq - pv);
+                p2 += pv * pv;
+            }
+            fin += xq * 0.0 + pq * 0.0;
+            xs[al * N + i] = xq;
+            ps[al * N + i] = pq;
+            qcur_next[al * N + i] = xq;
+            pcur_next[al * N + i] = pq;
+        }
+    const double a = block_sum(d2, red), b = block_sum(p2, red), c = block_sum(fin, red);
+    if (threadIdx.x == 0) {
+        part[0] = a;
+        part[1] = b;
+        part[2] = c;
+    }
+}
+
+void launch_slab_end(int N, int mode, size_t SN, size_t s, double *xs, double *ps, const double *jq, const double *jp,
+                     const double *qprev_next, double *qcur_next, double *pcur_next, double *part, hipStream_t st) {
+    hipLaunchKernelGGL(k_slab_end, dim3(1), dim3(kSweepThreads), 0, st, N, mode, SN, s, xs, ps, jq, jp, qprev_next,
+                       qcur_next, pcur_next, part);
+}
+
+bool sweep_fits_lds(int N) { return N <= kSweepLdsMaxAtoms && sweep_lds_bytes(N) <= 160 * 1024; }
+
 // ---------------------------------------------------------------------------
 void launch_slabs_to_batch(int S, int N, const double *slots, double *out, hipStream_t st) {
     const size_t tot = (size_t)3 * S * N;
@@ -609,7 +653,7 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     a.nbr = s.nbr;
     a.cnt = s.cnt;
     a.out = s.out;
-    if (s.N <= kSweepLdsMaxAtoms && sweep_lds_bytes(s.N) <= 160 * 1024) {
+    if (sweep_fits_lds(s.N)) {
         hipLaunchKernelGGL(k_coarse_sweep_lds, dim3(1), dim3(kSweepThreads), sweep_lds_bytes(s.N), st, a);
     } else {
         hipLaunchKernelGGL(k_coarse_sweep, dim3(1), dim3(kSweepThreads), 0, st, a);
