@@ -168,9 +168,10 @@ def main():
     ns = min(args.per_slab_sample, S_slabs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    xs, ps = q_start[0].clone(), p_start[0].clone()
     for s in range(ns):
-        xs = q_start[s].clone()
-        ps = p_start[s].clone()
+        xs.copy_(q_start[s])
+        ps.copy_(p_start[s])
         ctx.langevin_steps(S.POT_FS_SNAP, xs, ps, [0, n], box, L, step0=s * L, **kw)
     torch.cuda.synchronize()
     t_slab = (time.perf_counter() - t0) / ns

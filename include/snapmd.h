@@ -185,12 +185,22 @@ int snap_beta_grad(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch 
 int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *batch,
                       const double *x, double *B, void *stream);
 
+/* Launch mode of langevin_steps and of the fine and coarse propagation of
+ * parareal_iterate.  enable = 1 (the default): the n_steps launch sequence is captured
+ * once into a hipGraph, cached per context (keyed by sizes, parameters and device
+ * pointers; at most 16 kept, least recently used dropped; every cached graph is dropped
+ * when the context reallocates a work buffer) and replayed on the caller's stream.
+ * enable = 0: kernels are launched one by one.  Results are identical either way.
+ * While snapmd_profile is on, SNAP propagation is launched one by one. */
+int snapmd_use_graphs(snapmd_ctx *ctx, int enable);
+
 /* Measurement support (not part of the propagation):
  * snapmd_profile(ctx, 1) starts recording HIP events around the SNAP kernels and the
  * neighbour build on the stream they are launched on (clears earlier records; 0 stops).
  * snapmd_profile_read synchronises the device and returns, for kernel id
  * 0 = SNAP dE/dr, 1 = SNAP adjoint, 2 = SNAP density, 3 = neighbour build,
- * the summed duration (ms) and the number of launches recorded. */
+ * the summed duration (ms) and the number of launches recorded.  Neighbour builds
+ * replayed from a captured graph (FS-only propagation) are not recorded. */
 int snapmd_profile(snapmd_ctx *ctx, int enable);
 int snapmd_profile_read(snapmd_ctx *ctx, int kernel, double *total_ms, int64_t *launches);
 /* Number of neighbour pairs (both directions) of the last neighbour build, after a

@@ -76,6 +76,16 @@ struct snapmd_ctx {
     bool any_cells = false;
     std::vector<double> noise_key;                // (n_in, S, L, N, seed, noise_id) it holds
     KernelProf prof;
+    // captured launch sequences of run_langevin, keyed by everything baked into them
+    int use_graphs = 1;
+    struct GraphEntry {
+        std::vector<uint64_t> key;
+        hipGraphExec_t exec;
+        uint64_t last_use;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;
+    uint64_t graph_clock = 0;
 };
 
 namespace {
@@ -97,9 +107,16 @@ int fail(snapmd_ctx *c, int code, const char *fmt, ...) {
             return fail(ctx, SNAPMD_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));   \
     } while (0)
 
+void drop_graphs(snapmd_ctx *ctx) {
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    ctx->graphs.clear();
+}
+
+// (Re)allocate a device buffer.  Freeing one invalidates every captured graph.
 template <class T>
 int dalloc(snapmd_ctx *ctx, T **p, size_t n) {
     if (*p) {
+        drop_graphs(ctx);
         (void)hipFree(*p);
         ctx->allocs.erase(std::remove(ctx->allocs.begin(), ctx->allocs.end(), (void *)*p), ctx->allocs.end());
         *p = nullptr;
@@ -372,6 +389,64 @@ void run_langevin(snapmd_ctx *ctx, int potential, const BatchDev &bd, const FsPa
     }
 }
 
+// run_langevin through a cached hipGraph: the whole launch sequence of n_steps steps is
+// captured once per key (pointers, sizes, parameters baked into the kernel arguments)
+// and replayed afterwards.  The captured sequence contains kernels only.
+int run_langevin_graph(snapmd_ctx *ctx, int potential, const BatchDev &bd, const FsParams &fp, const SnapDev &sd,
+                       const LangevinDev &ld, int n_steps, double *x, double *p, hipStream_t st) {
+    // SNAP propagation stays eager while kernel timing is on (the events time each launch)
+    if (!ctx->use_graphs || (ctx->prof.enabled && potential == SNAPMD_POT_FS_SNAP)) {
+        run_langevin(ctx, potential, bd, fp, sd, ld, n_steps, x, p, st);
+        return SNAPMD_OK;
+    }
+    auto u = [](const void *q) { return (uint64_t)(uintptr_t)q; };
+    auto d = [](double v) {
+        uint64_t b;
+        std::memcpy(&b, &v, sizeof b);
+        return b;
+    };
+    std::vector<uint64_t> key{(uint64_t)potential, (uint64_t)bd.N, (uint64_t)bd.n_sys, u(bd.off), u(bd.box),
+                              u(bd.cells), (uint64_t)bd.n_cells, (uint64_t)n_steps, u(x), u(p), u(ctx->d_f),
+                              u(ctx->w.nbr), u(ctx->w.geo), u(ctx->w.u), u(ctx->w.ytil), u(ctx->w.xref),
+                              u(ctx->w.cell_cnt), d(fp.A), d(fp.d), d(fp.c), d(fp.c0), d(fp.c1), d(fp.c2),
+                              d(ld.dt), d(ld.c1), d(ld.mass), ld.seed, u(ld.sig), u(ld.step0), u(ld.noise_id)};
+    if (potential == SNAPMD_POT_FS_SNAP) {
+        const uint64_t sk[] = {(uint64_t)sd.J, d(sd.gp.rcut), d(sd.gp.rfac0), d(sd.gp.rmin0), d(sd.beta0),
+                               u(sd.nrm), u(sd.adj.coef), u(sd.adj.cgm), u(sd.adj.roles)};
+        key.insert(key.end(), sk, sk + 9);
+    }
+    ++ctx->graph_clock;
+    for (auto &g : ctx->graphs)
+        if (g.key == key) {
+            g.last_use = ctx->graph_clock;
+            HIPCHK(hipGraphLaunch(g.exec, st));
+            return SNAPMD_OK;
+        }
+    // captured on a stream of the context (the caller's may be the null stream), then
+    // launched on the caller's stream
+    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph;
+    HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int prof_on = ctx->prof.enabled;
+    ctx->prof.enabled = 0;  // no event records inside a graph
+    run_langevin(ctx, potential, bd, fp, sd, ld, n_steps, x, p, ctx->cap_stream);
+    ctx->prof.enabled = prof_on;
+    HIPCHK(hipStreamEndCapture(ctx->cap_stream, &graph));
+    hipGraphExec_t exec;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(ctx, SNAPMD_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    if (ctx->graphs.size() >= 16) {
+        auto it = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                   [](const auto &a, const auto &b) { return a.last_use < b.last_use; });
+        (void)hipGraphExecDestroy(it->exec);
+        ctx->graphs.erase(it);
+    }
+    ctx->graphs.push_back({key, exec, ctx->graph_clock});
+    HIPCHK(hipGraphLaunch(exec, st));
+    return SNAPMD_OK;
+}
+
 // Per-system Langevin arrays (sigma, step offsets, noise ids) uploaded to the context.
 int prepare_langevin(snapmd_ctx *ctx, const snapmd_langevin *lang, int S, const std::vector<double> &T,
                      const std::vector<int64_t> &step0, const std::vector<int> &nid, LangevinDev &ld,
@@ -428,6 +503,8 @@ void snapmd_destroy(snapmd_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     for (void *p : ctx->allocs) (void)hipFree(p);
     if (ctx->h_out) (void)hipHostFree(ctx->h_out);
+    drop_graphs(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
     delete ctx;
 }
@@ -514,7 +591,10 @@ int langevin_steps(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, cons
     LangevinDev ld;
     if ((rc = prepare_langevin(ctx, lang, S, T, step0, nid, ld, st))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
-    run_langevin(ctx, potential, bd, fp, sd, ld, n_steps, x, p, st);
+    if ((rc = prepare_cells(ctx, bd, (potential == SNAPMD_POT_FS_SNAP ? std::max(sd.gp.rcut, std::max(fp.d, fp.c))
+                                                                       : std::max(fp.d, fp.c)) + kSkin, st)))
+        return rc;
+    if ((rc = run_langevin_graph(ctx, potential, bd, fp, sd, ld, n_steps, x, p, st))) return rc;
     if (f_out)
         HIPCHK(hipMemcpyAsync(f_out, ctx->d_f, 3 * (size_t)bd.N * sizeof(double), hipMemcpyDeviceToDevice, st));
     return check_launch(ctx);
@@ -633,8 +713,12 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         launch_slabs_to_batch(S, N, ps, ctx->pr_pf.p, st);
         launch_slabs_to_batch(S, N, qs, ctx->pr_xc.p, st);
         launch_slabs_to_batch(S, N, ps, ctx->pr_pc.p, st);
-        run_langevin(ctx, SNAPMD_POT_FS_SNAP, bd, fp, sd, ld, L, ctx->pr_xf.p, ctx->pr_pf.p, st);
-        run_langevin(ctx, SNAPMD_POT_FS, bd, fp, sd, ld, L, ctx->pr_xc.p, ctx->pr_pc.p, st);
+        if ((rc = prepare_cells(ctx, bd, std::max(sd.gp.rcut, std::max(fp.d, fp.c)) + kSkin, st))) return rc;
+        if ((rc = run_langevin_graph(ctx, SNAPMD_POT_FS_SNAP, bd, fp, sd, ld, L, ctx->pr_xf.p, ctx->pr_pf.p, st)))
+            return rc;
+        if ((rc = prepare_cells(ctx, bd, std::max(fp.d, fp.c) + kSkin, st))) return rc;
+        if ((rc = run_langevin_graph(ctx, SNAPMD_POT_FS, bd, fp, sd, ld, L, ctx->pr_xc.p, ctx->pr_pc.p, st)))
+            return rc;
         launch_jumps(SN3, ctx->pr_xf.p, ctx->pr_xc.p, st);
         launch_jumps(SN3, ctx->pr_pf.p, ctx->pr_pc.p, st);
         sw.jq = ctx->pr_xf.p;
@@ -694,6 +778,12 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         *n_fi = nfi_new;
         return SNAPMD_OK;
     }
+}
+
+int snapmd_use_graphs(snapmd_ctx *ctx, int enable) {
+    if (!ctx) return SNAPMD_EINVAL;
+    ctx->use_graphs = enable ? 1 : 0;
+    return SNAPMD_OK;
 }
 
 int snapmd_profile(snapmd_ctx *ctx, int enable) {

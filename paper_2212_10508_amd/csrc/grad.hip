@@ -87,9 +87,11 @@ __device__ void jvp_column(int N, const int *__restrict__ poff, const int *__res
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = make_double2(0.0, 0.0);
     const double wi0 = w[i], wi1 = w[N + i], wi2 = w[2 * N + i];
-    const int p1 = poff[i + 1];
-    for (int p = poff[i]; p < p1; ++p) {
-        const double fc = geo[4 * Pcap + p];
+    const int p0 = poff[i], p1 = poff[i + 1];
+    double nfc = p0 < p1 ? geo[4 * Pcap + p0] : 0.0;
+    for (int p = p0; p < p1; ++p) {
+        const double fc = nfc;
+        if (p + 1 < p1) nfc = geo[4 * Pcap + p + 1];  // next pair's switch value in flight
         if (fc == 0.0) continue;
         const int j = pair_j[p];
         // the pair vector is x_j - x_i: its variation along the field is w_j - w_i

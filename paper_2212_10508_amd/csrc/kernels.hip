@@ -414,28 +414,49 @@ __device__ __forceinline__ void staircase(double2 (&P)[J + 1], double2 b, double
     }
 }
 
-// u (half storage, [e][N] double2) for column C of every atom: lane = atom.
+// u (half storage, [e][N] double2) for column C: one wave per tile of 64 atoms
+// (lane = atom).  The tile's pairs are contiguous in the CSR list; their a, b and f_c
+// are staged in LDS in chunks of kDensityChunk pairs with coalesced loads, and every
+// lane then walks its own atom's pairs from LDS.
+constexpr int kDensityChunk = 512;
+
 template <int J, int C>
-__device__ void density_column(int N, const int *__restrict__ poff, const double *__restrict__ geo, size_t Pcap,
-                               const double *__restrict__ nrm, double2 *__restrict__ u) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+__device__ void density_tile(int N, const int *__restrict__ poff, const double *__restrict__ geo, size_t Pcap,
+                             const double *__restrict__ nrm, double2 *__restrict__ u, double *__restrict__ sg) {
+    const int lane = threadIdx.x;
+    const int a0 = blockIdx.x * 64;
+    const int i = a0 + lane;
     constexpr int NA = chain_acc_idx(C, J + 1, 0);
     double2 acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = make_double2(0.0, 0.0);
-    const int p1 = poff[i + 1];
-    for (int p = poff[i]; p < p1; ++p) {
-        const double fc = geo[4 * Pcap + p];
-        if (fc == 0.0) continue;
-        const double2 a = make_double2(geo[p], geo[Pcap + p]);
-        const double2 b = make_double2(geo[2 * Pcap + p], geo[3 * Pcap + p]);
-        const double2 ab = cconj(a);
-        double2 P[J + 1];
-        P[0] = make_double2(1.0, 0.0);
-        staircase<J, C, 0>(P, b, ab);
-        density_step<J, C, 2 * C>(P, acc, b, ab, fc);
+    const int P0 = poff[a0], P1 = poff[min(a0 + 64, N)];
+    const int pb = i < N ? poff[i] : 0, pe = i < N ? poff[i + 1] : 0;
+    for (int c0 = P0; c0 < P1; c0 += kDensityChunk) {
+        const int c1 = min(c0 + kDensityChunk, P1);
+        __syncthreads();
+        for (int q = lane; q < c1 - c0; q += 64) {
+            sg[q] = geo[c0 + q];
+            sg[kDensityChunk + q] = geo[Pcap + c0 + q];
+            sg[2 * kDensityChunk + q] = geo[2 * Pcap + c0 + q];
+            sg[3 * kDensityChunk + q] = geo[3 * Pcap + c0 + q];
+            sg[4 * kDensityChunk + q] = geo[4 * Pcap + c0 + q];
+        }
+        __syncthreads();
+        const int qe = min(pe, c1) - c0;
+        for (int q = max(pb, c0) - c0; q < qe; ++q) {
+            const double fc = sg[4 * kDensityChunk + q];
+            if (fc == 0.0) continue;
+            const double2 a = make_double2(sg[q], sg[kDensityChunk + q]);
+            const double2 b = make_double2(sg[2 * kDensityChunk + q], sg[3 * kDensityChunk + q]);
+            const double2 ab = cconj(a);
+            double2 P[J + 1];
+            P[0] = make_double2(1.0, 0.0);
+            staircase<J, C, 0>(P, b, ab);
+            density_step<J, C, 2 * C>(P, acc, b, ab, fc);
+        }
     }
+    if (i >= N) return;
 #pragma unroll
     for (int n = 2 * C; n <= J; ++n)
 #pragma unroll
@@ -448,15 +469,16 @@ __device__ void density_column(int N, const int *__restrict__ poff, const double
 }
 
 template <int J>
-__global__ void __launch_bounds__(128) k_density(int N, const int *__restrict__ poff, const double *__restrict__ geo,
-                                                 size_t Pcap, const double *__restrict__ nrm,
-                                                 double2 *__restrict__ u) {
+__global__ void __launch_bounds__(64) k_density(int N, const int *__restrict__ poff, const double *__restrict__ geo,
+                                                size_t Pcap, const double *__restrict__ nrm,
+                                                double2 *__restrict__ u) {
+    __shared__ double sg[5 * kDensityChunk];
     switch (blockIdx.y) {
-        case 0: density_column<J, 0>(N, poff, geo, Pcap, nrm, u); break;
-        case 1: if constexpr (J >= 2) density_column<J, 1>(N, poff, geo, Pcap, nrm, u); break;
-        case 2: if constexpr (J >= 4) density_column<J, 2>(N, poff, geo, Pcap, nrm, u); break;
-        case 3: if constexpr (J >= 6) density_column<J, 3>(N, poff, geo, Pcap, nrm, u); break;
-        case 4: if constexpr (J >= 8) density_column<J, 4>(N, poff, geo, Pcap, nrm, u); break;
+        case 0: density_tile<J, 0>(N, poff, geo, Pcap, nrm, u, sg); break;
+        case 1: if constexpr (J >= 2) density_tile<J, 1>(N, poff, geo, Pcap, nrm, u, sg); break;
+        case 2: if constexpr (J >= 4) density_tile<J, 2>(N, poff, geo, Pcap, nrm, u, sg); break;
+        case 3: if constexpr (J >= 6) density_tile<J, 3>(N, poff, geo, Pcap, nrm, u, sg); break;
+        case 4: if constexpr (J >= 8) density_tile<J, 4>(N, poff, geo, Pcap, nrm, u, sg); break;
         default: break;
     }
 }
@@ -750,7 +772,7 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     hipLaunchKernelGGL(k_pair_geo, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
                        w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
     pf.begin(PROF_DENSITY, st);
-    hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 128), J / 2 + 1), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap,
+    hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 64), J / 2 + 1), dim3(64), 0, st, N, w.poff, w.geo, w.Pcap,
                        sd.nrm, w.u);
     pf.end(st);
     pf.begin(PROF_ADJOINT, st);
@@ -780,10 +802,10 @@ void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapD
     hipLaunchKernelGGL(k_pair_geo, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
                        w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
     switch (J) {
-        case 2: hipLaunchKernelGGL(k_density<2>, dim3(nblk(N, 128), 2), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
-        case 4: hipLaunchKernelGGL(k_density<4>, dim3(nblk(N, 128), 3), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
-        case 6: hipLaunchKernelGGL(k_density<6>, dim3(nblk(N, 128), 4), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
-        case 8: hipLaunchKernelGGL(k_density<8>, dim3(nblk(N, 128), 5), dim3(128), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
+        case 2: hipLaunchKernelGGL(k_density<2>, dim3(nblk(N, 64), 2), dim3(64), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
+        case 4: hipLaunchKernelGGL(k_density<4>, dim3(nblk(N, 64), 3), dim3(64), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
+        case 6: hipLaunchKernelGGL(k_density<6>, dim3(nblk(N, 64), 4), dim3(64), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
+        case 8: hipLaunchKernelGGL(k_density<8>, dim3(nblk(N, 64), 5), dim3(64), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
         default: break;
     }
 }

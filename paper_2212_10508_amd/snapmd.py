@@ -82,6 +82,8 @@ def lib():
     L.snap_beta_grad.restype = C.c_int
     L.snapmd_bispectrum.argtypes = [P, C.POINTER(Snap), C.POINTER(Batch), P, P, P]
     L.snapmd_bispectrum.restype = C.c_int
+    L.snapmd_use_graphs.argtypes = [P, C.c_int]
+    L.snapmd_use_graphs.restype = C.c_int
     L.snapmd_profile.argtypes = [P, C.c_int]
     L.snapmd_profile.restype = C.c_int
     L.snapmd_profile_read.argtypes = [P, C.c_int, C.POINTER(d), C.POINTER(C.c_int64)]
@@ -253,6 +255,10 @@ class Context:
 
     # -- measurement ---------------------------------------------------------
     PROF_DEDR, PROF_ADJOINT, PROF_DENSITY, PROF_NEIGH = 0, 1, 2, 3
+
+    def use_graphs(self, enable=True):
+        """Replay captured hipGraphs of the Langevin launch sequences (default on)."""
+        self._check(lib().snapmd_use_graphs(self.h, 1 if enable else 0))
 
     def profile(self, enable=True):
         self._check(lib().snapmd_profile(self.h, 1 if enable else 0))

@@ -1,0 +1,90 @@
+"""Captured-graph replay of the Langevin launch sequence against one-by-one launches.
+
+The same kernels run either way, so replays must reproduce the eager trajectory bit
+for bit.  Each graph is replayed several times with eager work and synchronisations
+between the replays, and every replay is checked."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2212_10508_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_10508_amd import snapmd
+    return snapmd
+
+
+def _batch(n_sys=3, seed=11):
+    xs, ps = [], []
+    for s in range(n_sys):
+        x, box = W.bcc_sia(4, jitter=0.05, seed=seed + s)
+        xs.append(x)
+        ps.append(W.maxwell_momenta(x.shape[1], 1000.0, seed=seed + s))
+    n = xs[0].shape[1]
+    X = np.concatenate(xs, axis=1)
+    P = np.concatenate(ps, axis=1)
+    off = np.arange(n_sys + 1, dtype=np.int32) * n
+    return X, P, off, np.tile(box, (n_sys, 1))
+
+
+@pytest.mark.parametrize("pot", ["fs", "fs_snap"])
+def test_graph_replays_match_eager(S, pot):
+    J = 6
+    X, P, off, boxes = _batch()
+    beta = W.snap_beta(J, seed=2, scale=2e-2)
+    potential = S.POT_FS_SNAP if pot == "fs_snap" else S.POT_FS
+    kw = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=5, noise_id=0, fs=W.FS_W, J=J, beta=beta)
+    ctx = S.Context(0)
+    L = 7
+    ctx.use_graphs(False)
+    ref = []
+    xe, pe = torch.tensor(X, device="cuda"), torch.tensor(P, device="cuda")
+    for r in range(3):
+        ctx.langevin_steps(potential, xe, pe, off, boxes, L, step0=[r * L] * 3, **kw)
+        torch.cuda.synchronize()
+        ref.append((xe.clone(), pe.clone()))
+    ctx.use_graphs(True)
+    xg, pg = torch.tensor(X, device="cuda"), torch.tensor(P, device="cuda")
+    for r in range(3):
+        ctx.langevin_steps(potential, xg, pg, off, boxes, L, step0=[r * L] * 3, **kw)
+        torch.cuda.synchronize()
+        # eager work on the same context between replays
+        f = ctx.eam_forces(xg.clone(), off, boxes, W.FS_W)
+        torch.cuda.synchronize()
+        assert torch.isfinite(f).all()
+        assert torch.equal(xg, ref[r][0]) and torch.equal(pg, ref[r][1]), r
+
+
+def test_graph_parareal_iterations_match_eager(S):
+    J = 2
+    x, box = W.bcc_sia(4, jitter=0.05, seed=4)
+    p = W.maxwell_momenta(x.shape[1], 1000.0, seed=4)
+    beta = W.snap_beta(J, seed=4, scale=2e-2)
+    kw = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=9, noise_id=0, fs=W.FS_W, J=J, beta=beta)
+    kwc = {k: v for k, v in kw.items() if k not in ("J", "beta")}
+    N, L, n = 4, 5, x.shape[1]
+    out = {}
+    for graphs in (False, True):
+        ctx = S.Context(0)
+        ctx.use_graphs(graphs)
+        q = torch.zeros((N + 1, 3, n), dtype=torch.float64, device="cuda")
+        pp, qp, ppv = torch.zeros_like(q), torch.zeros_like(q), torch.zeros_like(q)
+        q[0] = torch.tensor(x, device="cuda")
+        pp[0] = torch.tensor(p, device="cuda")
+        ctx.parareal_iterate(None, None, q, pp, box, L, 0, N, 1e100, **kwc)
+        hist = []
+        for k in range(3):
+            d, _ = ctx.parareal_iterate(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
+            torch.cuda.synchronize()
+            hist.append((d, q.clone(), pp.clone()))
+        out[graphs] = hist
+    for (d0, q0, p0), (d1, q1, p1) in zip(out[False], out[True]):
+        assert d0 == d1
+        assert torch.equal(q0, q1) and torch.equal(p0, p1)
