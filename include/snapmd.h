@@ -161,8 +161,8 @@ int langevin_steps(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, cons
  * Initialisation of a new time window (the coarse propagation that starts each
  * window of the adaptive algorithm): pass q_prev = p_prev = NULL; then only
  * cur_{n+1} := C(cur_n) for n_in <= n < *n_fi is done, *delta_out = 0, snap may be NULL.
- * The coarse sweep keeps a Verlet list with a 0.5 A skin: max(d, c) + 0.5 must be
- * below half the smallest box edge. */
+ * The coarse sweep keeps a Verlet list with a 0.5 A skin and stores each listed
+ * pair's periodic image: max(d, c) + 1.0 must be below half the smallest box edge. */
 int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs,
                      const snapmd_batch *batch, const snapmd_langevin *lang, int32_t L,
                      int32_t n_in, int32_t *n_fi, double *q_prev, double *p_prev, double *q_cur,

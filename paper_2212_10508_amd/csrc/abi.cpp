@@ -53,9 +53,9 @@ struct snapmd_ctx {
     std::vector<int> h_off;
     std::vector<double> h_box;
     // workspace
-    size_t cap_atoms = 0;
-    Work w;
-    double *d_f = nullptr;  // force scratch [3][N]
+    size_t cap_atoms = 0, cap_atoms_c = 0;
+    Work w, wc;                                   // SNAP / second-stream Finnis-Sinclair workspaces
+    double *d_f = nullptr, *d_fc = nullptr;       // their force scratch [3][N]
     // per-system Langevin arrays
     DBuf<double> d_sig;
     DBuf<int64_t> d_step0;
@@ -64,16 +64,17 @@ struct snapmd_ctx {
     std::vector<void *> allocs;
     // parareal buffers
     DBuf<double> pr_xf, pr_pf, pr_xc, pr_pc;     // [3][S*N] fine / coarse copies of prev slabs
-    DBuf<double> sw_x, sw_p, sw_f, sw_rho, sw_ref, sw_out;
-    DBuf<int> sw_nbr, sw_cnt;
-    double *h_out = nullptr;                      // pinned [4]
+    DBuf<double> sw_x, sw_p, sw_out;
+    double *h_out = nullptr;                      // pinned [16]: sweep results [0, 8), sweep init [8, 16)
     DBuf<double> sw_noise;                        // Gaussians of the current window
     DBuf<double> gB;                              // [K][N] bispectrum / its variation
-    // cell grids of the current batch for the last list cutoff
-    DBuf<int4> d_cells;
-    std::vector<double> cell_key;
-    int n_cells = 0;
-    bool any_cells = false;
+    // cell grids of the current batch for the last list cutoff, one set per workspace
+    struct CellState {
+        DBuf<int4> d_cells;
+        std::vector<double> key;
+        int n_cells = 0;
+        bool any = false;
+    } cs, csc;
     std::vector<double> noise_key;                // (n_in, S, L, N, seed, noise_id) it holds
     KernelProf prof;
     // captured launch sequences of run_langevin, keyed by everything baked into them
@@ -85,6 +86,8 @@ struct snapmd_ctx {
     };
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
+    hipStream_t sweep_stream = nullptr;  // the coarse sweep, overlapping the batched propagation
+    std::vector<hipEvent_t> pipe_ev;
     uint64_t graph_clock = 0;
 };
 
@@ -168,6 +171,30 @@ int ensure_atoms(snapmd_ctx *ctx, size_t N) {
     if ((rc = dalloc(ctx, &w.cell_of, cap))) return rc;
     if ((rc = dalloc(ctx, &w.cell_atoms, cap))) return rc;
     ctx->cap_atoms = cap;
+    return SNAPMD_OK;
+}
+
+// Workspace of the Finnis-Sinclair propagation that runs beside the SNAP one (its own
+// neighbour lists and force buffer; the error bits are shared).
+int ensure_atoms_coarse(snapmd_ctx *ctx, size_t N) {
+    Work &w = ctx->wc;
+    w.status = ctx->w.status;
+    int rc;
+    if (!w.flag) {
+        if ((rc = dalloc(ctx, &w.flag, 1))) return rc;
+        HIPCHK(hipMemset(w.flag, 0, sizeof(int)));
+    }
+    if (N <= ctx->cap_atoms_c) return SNAPMD_OK;
+    size_t cap = std::max<size_t>(N, 64);
+    w.Pcap = cap * kMaxNeigh;
+    if ((rc = dalloc(ctx, &w.nbr, cap * kMaxNeigh)) || (rc = dalloc(ctx, &w.cnt, cap)) ||
+        (rc = dalloc(ctx, &w.poff, cap + 1)) || (rc = dalloc(ctx, &w.pair_i, w.Pcap)) ||
+        (rc = dalloc(ctx, &w.pair_j, w.Pcap)) || (rc = dalloc(ctx, &w.rev, w.Pcap)) ||
+        (rc = dalloc(ctx, &w.rho, cap)) || (rc = dalloc(ctx, &ctx->d_fc, 3 * cap)) ||
+        (rc = dalloc(ctx, &w.xref, 3 * cap)) || (rc = dalloc(ctx, &w.cell_of, cap)) ||
+        (rc = dalloc(ctx, &w.cell_atoms, cap)))
+        return rc;
+    ctx->cap_atoms_c = cap;
     return SNAPMD_OK;
 }
 
@@ -311,15 +338,36 @@ int check_launch(snapmd_ctx *ctx) {
 }
 
 // Force of the chosen potential at x into f (overwrite), e_atom (nullable, overwrite).
-constexpr double kSkin = 0.3;  // Verlet skin of the batched path (A)
+constexpr double kSkin = 0.3;       // Verlet skin of the batched path (A)
+constexpr double kSweepSkin = 0.5;  // Verlet skin of the LDS-resident coarse sweep (A)
+constexpr int kPipeChunks = 4;      // at most this many slab chunks per parareal iteration
+
+// Chunk sizes of a parareal iteration over S slabs: at most kPipeChunks chunks with
+// sizes in the ratio G : G-1 : ... : 1, so that the sweep starts early on a large first
+// chunk and the sweep left after the last propagation is short.
+std::vector<int> chunk_plan(int S) {
+    const int G = std::min(S, kPipeChunks);
+    const int W = G * (G + 1) / 2;
+    std::vector<int> sz(G);
+    int used = 0;
+    for (int c = 0; c < G; ++c) {
+        sz[c] = std::max(1, S * (G - c) / W);
+        used += sz[c];
+    }
+    for (int c = 0; used > S; c = (c + 1) % G)  // trim (only possible when S < W)
+        if (sz[c] > 1) { --sz[c]; --used; }
+    for (int c = 0; used < S; c = (c + 1) % G) { ++sz[c]; ++used; }
+    return sz;
+}
 
 // Cell grids (cell edge >= list cutoff rl, >= 3 cells per edge, else brute force) of the
 // current batch; rebuilt when the batch or the cutoff changes.
-int prepare_cells(snapmd_ctx *ctx, BatchDev &bd, double rl, hipStream_t st) {
+int prepare_cells(snapmd_ctx *ctx, Work &w, BatchDev &bd, double rl, hipStream_t st) {
+    snapmd_ctx::CellState &cs = (&w == &ctx->wc) ? ctx->csc : ctx->cs;
     std::vector<double> key(ctx->h_box.begin(), ctx->h_box.end());
     key.insert(key.end(), ctx->h_off.begin(), ctx->h_off.end());
     key.push_back(rl);
-    if (key != ctx->cell_key) {
+    if (key != cs.key) {
         const int S = (int)ctx->h_off.size() - 1;
         std::vector<int4> ci(S);
         int C = 0;
@@ -338,53 +386,56 @@ int prepare_cells(snapmd_ctx *ctx, BatchDev &bd, double rl, hipStream_t st) {
             }
         }
         int rc;
-        if ((rc = ensure(ctx, ctx->d_cells, (size_t)S))) return rc;
-        if ((rc = upload(ctx, ctx->d_cells.p, ci.data(), S, st))) return rc;
-        Work &w = ctx->w;
-        if (any && (size_t)C + 1 > w.cap_cells) {
-            if ((rc = dalloc(ctx, &w.cell_cnt, C + 1)) || (rc = dalloc(ctx, &w.cell_fill, C + 1)) ||
-                (rc = dalloc(ctx, &w.cell_start, C + 1)))
-                return rc;
-            w.cap_cells = C + 1;
-        }
-        ctx->n_cells = C;
-        ctx->any_cells = any;
-        ctx->cell_key = key;
+        if ((rc = ensure(ctx, cs.d_cells, (size_t)S))) return rc;
+        if ((rc = upload(ctx, cs.d_cells.p, ci.data(), S, st))) return rc;
+        cs.n_cells = C;
+        cs.any = any;
+        cs.key = key;
     }
-    bd.cells = ctx->any_cells ? ctx->d_cells.p : nullptr;
-    bd.n_cells = ctx->any_cells ? ctx->n_cells : 0;
+    if (cs.any && (size_t)cs.n_cells + 1 > w.cap_cells) {
+        const int C = cs.n_cells;
+        int rc;
+        if ((rc = dalloc(ctx, &w.cell_cnt, C + 1)) || (rc = dalloc(ctx, &w.cell_fill, C + 1)) ||
+            (rc = dalloc(ctx, &w.cell_start, C + 1)))
+            return rc;
+        w.cap_cells = C + 1;
+    }
+    bd.cells = cs.any ? cs.d_cells.p : nullptr;
+    bd.n_cells = cs.any ? cs.n_cells : 0;
     return SNAPMD_OK;
 }
 
 // launch_neighbors with the cell grids of the batch
-int neighbors(snapmd_ctx *ctx, const BatchDev &bd0, const double *x, double rc, bool force, hipStream_t st) {
+int neighbors(snapmd_ctx *ctx, Work &w, const BatchDev &bd0, const double *x, double rc, bool force,
+              hipStream_t st) {
     BatchDev bd = bd0;
     int r;
-    if ((r = prepare_cells(ctx, bd, rc + kSkin, st))) return r;
-    launch_neighbors(bd, x, rc, ctx->w, st, force, kSkin);
+    if ((r = prepare_cells(ctx, w, bd, rc + kSkin, st))) return r;
+    launch_neighbors(bd, x, rc, w, st, force, kSkin);
     return SNAPMD_OK;
 }
 
-void enqueue_forces(snapmd_ctx *ctx, int potential, const BatchDev &bd, const double *x, const FsParams *fp,
-                    const SnapDev *sd, double *f, double *e_atom, hipStream_t st, bool fresh = true) {
+void enqueue_forces(snapmd_ctx *ctx, Work &w, int potential, const BatchDev &bd, const double *x,
+                    const FsParams *fp, const SnapDev *sd, double *f, double *e_atom, hipStream_t st,
+                    bool fresh = true) {
     double rc = 0.0;
     if (fp) rc = std::max(fp->d, fp->c);
     if (potential == SNAPMD_POT_FS_SNAP) rc = std::max(rc, sd->gp.rcut);
     ctx->prof.begin(PROF_NEIGH, st);
-    (void)neighbors(ctx, bd, x, rc, fresh, st);
+    (void)neighbors(ctx, w, bd, x, rc, fresh, st);
     ctx->prof.end(st);
-    launch_fs(bd, x, *fp, ctx->w, f, e_atom, 0, st);
-    if (potential == SNAPMD_POT_FS_SNAP) launch_snap(sd->J, bd, x, *sd, ctx->w, f, e_atom, 1, st, &ctx->prof);
+    launch_fs(bd, x, *fp, w, f, e_atom, 0, st);
+    if (potential == SNAPMD_POT_FS_SNAP) launch_snap(sd->J, bd, x, *sd, w, f, e_atom, 1, st, &ctx->prof);
 }
 
-// n_steps BAOAB steps of the batch in place (force evaluated at the start).
-void run_langevin(snapmd_ctx *ctx, int potential, const BatchDev &bd, const FsParams &fp, const SnapDev &sd,
-                  const LangevinDev &ld, int n_steps, double *x, double *p, hipStream_t st) {
-    double *f = ctx->d_f;
-    enqueue_forces(ctx, potential, bd, x, &fp, &sd, f, nullptr, st);
+// n_steps BAOAB steps of the batch in place (force evaluated at the start), with the
+// workspace w and the force buffer f.
+void run_langevin(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
+                  const SnapDev &sd, const LangevinDev &ld, int n_steps, double *x, double *p, hipStream_t st) {
+    enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, nullptr, st);
     for (int s = 0; s < n_steps; ++s) {
         launch_baoab_pre(bd, x, p, f, ld, s, st);
-        enqueue_forces(ctx, potential, bd, x, &fp, &sd, f, nullptr, st, false);
+        enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, nullptr, st, false);
         launch_baoab_post(bd, p, f, ld.dt, st);
     }
 }
@@ -392,12 +443,21 @@ void run_langevin(snapmd_ctx *ctx, int potential, const BatchDev &bd, const FsPa
 // run_langevin through a cached hipGraph: the whole launch sequence of n_steps steps is
 // captured once per key (pointers, sizes, parameters baked into the kernel arguments)
 // and replayed afterwards.  The captured sequence contains kernels only.
-int run_langevin_graph(snapmd_ctx *ctx, int potential, const BatchDev &bd, const FsParams &fp, const SnapDev &sd,
-                       const LangevinDev &ld, int n_steps, double *x, double *p, hipStream_t st) {
+int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
+                       const SnapDev &sd, const LangevinDev &ld, int n_steps, double *x, double *p,
+                       hipStream_t st) {
     // SNAP propagation stays eager while kernel timing is on (the events time each launch)
     if (!ctx->use_graphs || (ctx->prof.enabled && potential == SNAPMD_POT_FS_SNAP)) {
-        run_langevin(ctx, potential, bd, fp, sd, ld, n_steps, x, p, st);
+        run_langevin(ctx, w, f, potential, bd, fp, sd, ld, n_steps, x, p, st);
         return SNAPMD_OK;
+    }
+    {
+        // cell grids and their buffers are set up outside any capture
+        BatchDev bc = bd;
+        const double rl = (potential == SNAPMD_POT_FS_SNAP ? std::max(sd.gp.rcut, std::max(fp.d, fp.c))
+                                                           : std::max(fp.d, fp.c)) + kSkin;
+        int rc;
+        if ((rc = prepare_cells(ctx, w, bc, rl, st))) return rc;
     }
     auto u = [](const void *q) { return (uint64_t)(uintptr_t)q; };
     auto d = [](double v) {
@@ -406,9 +466,8 @@ int run_langevin_graph(snapmd_ctx *ctx, int potential, const BatchDev &bd, const
         return b;
     };
     std::vector<uint64_t> key{(uint64_t)potential, (uint64_t)bd.N, (uint64_t)bd.n_sys, u(bd.off), u(bd.box),
-                              u(bd.cells), (uint64_t)bd.n_cells, (uint64_t)n_steps, u(x), u(p), u(ctx->d_f),
-                              u(ctx->w.nbr), u(ctx->w.geo), u(ctx->w.u), u(ctx->w.ytil), u(ctx->w.xref),
-                              u(ctx->w.cell_cnt), d(fp.A), d(fp.d), d(fp.c), d(fp.c0), d(fp.c1), d(fp.c2),
+                              u(bd.cells), (uint64_t)bd.n_cells, (uint64_t)n_steps, u(x), u(p), u(f),
+                              u(w.nbr), u(w.geo), u(w.u), u(w.ytil), u(w.xref), u(w.cell_cnt), u(w.flag), d(fp.A), d(fp.d), d(fp.c), d(fp.c0), d(fp.c1), d(fp.c2),
                               d(ld.dt), d(ld.c1), d(ld.mass), ld.seed, u(ld.sig), u(ld.step0), u(ld.noise_id)};
     if (potential == SNAPMD_POT_FS_SNAP) {
         const uint64_t sk[] = {(uint64_t)sd.J, d(sd.gp.rcut), d(sd.gp.rfac0), d(sd.gp.rmin0), d(sd.beta0),
@@ -429,14 +488,14 @@ int run_langevin_graph(snapmd_ctx *ctx, int potential, const BatchDev &bd, const
     HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
     const int prof_on = ctx->prof.enabled;
     ctx->prof.enabled = 0;  // no event records inside a graph
-    run_langevin(ctx, potential, bd, fp, sd, ld, n_steps, x, p, ctx->cap_stream);
+    run_langevin(ctx, w, f, potential, bd, fp, sd, ld, n_steps, x, p, ctx->cap_stream);
     ctx->prof.enabled = prof_on;
     HIPCHK(hipStreamEndCapture(ctx->cap_stream, &graph));
     hipGraphExec_t exec;
     hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(ctx, SNAPMD_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
-    if (ctx->graphs.size() >= 16) {
+    if (ctx->graphs.size() >= 32) {
         auto it = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
                                    [](const auto &a, const auto &b) { return a.last_use < b.last_use; });
         (void)hipGraphExecDestroy(it->exec);
@@ -461,6 +520,19 @@ int prepare_langevin(snapmd_ctx *ctx, const snapmd_langevin *lang, int S, const 
     if ((rc = upload(ctx, ctx->d_step0.p, step0.data(), S, st))) return rc;
     if ((rc = upload(ctx, ctx->d_noise.p, nid.data(), S, st))) return rc;
     ld = LangevinDev{lang->dt, c1, lang->mass, lang->seed, ctx->d_sig.p, ctx->d_step0.p, ctx->d_noise.p};
+    return SNAPMD_OK;
+}
+
+// Gaussians of every (slab, step, atom) of the window for the LDS-resident sweep, kept
+// while the window (and the noise stream) stays the same.
+int launch_noise_sweep(snapmd_ctx *ctx, int n_in, int S, int L, int N, const snapmd_langevin *lang, hipStream_t st) {
+    const std::vector<double> key{(double)n_in, (double)S, (double)L, (double)N, (double)lang->seed,
+                                  (double)lang->noise_id_sys[0]};
+    if (key == ctx->noise_key) return SNAPMD_OK;
+    int rc;
+    if ((rc = ensure(ctx, ctx->sw_noise, (size_t)S * L * 3 * N))) return rc;
+    launch_noise_table(S, L, N, n_in, lang->seed, (uint64_t)lang->noise_id_sys[0], ctx->sw_noise.p, st);
+    ctx->noise_key = key;
     return SNAPMD_OK;
 }
 
@@ -505,6 +577,8 @@ void snapmd_destroy(snapmd_ctx *ctx) {
     if (ctx->h_out) (void)hipHostFree(ctx->h_out);
     drop_graphs(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->sweep_stream) (void)hipStreamDestroy(ctx->sweep_stream);
+    for (hipEvent_t e : ctx->pipe_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
     delete ctx;
 }
@@ -538,7 +612,7 @@ int snap_forces(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *ba
     if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
     if ((rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
-    if ((rc = neighbors(ctx, bd, x, snap->rcut, true, st))) return rc;
+    if ((rc = neighbors(ctx, ctx->w, bd, x, snap->rcut, true, st))) return rc;
     launch_snap(sd.J, bd, x, sd, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st);
     return check_launch(ctx);
 }
@@ -556,7 +630,7 @@ int eam_forces(snapmd_ctx *ctx, const snapmd_fs *fs, const snapmd_batch *batch, 
     if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
     if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
-    if ((rc = neighbors(ctx, bd, x, std::max(fp.d, fp.c), true, st))) return rc;
+    if ((rc = neighbors(ctx, ctx->w, bd, x, std::max(fp.d, fp.c), true, st))) return rc;
     launch_fs(bd, x, fp, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st);
     return check_launch(ctx);
 }
@@ -591,10 +665,7 @@ int langevin_steps(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, cons
     LangevinDev ld;
     if ((rc = prepare_langevin(ctx, lang, S, T, step0, nid, ld, st))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
-    if ((rc = prepare_cells(ctx, bd, (potential == SNAPMD_POT_FS_SNAP ? std::max(sd.gp.rcut, std::max(fp.d, fp.c))
-                                                                       : std::max(fp.d, fp.c)) + kSkin, st)))
-        return rc;
-    if ((rc = run_langevin_graph(ctx, potential, bd, fp, sd, ld, n_steps, x, p, st))) return rc;
+    if ((rc = run_langevin_graph(ctx, ctx->w, ctx->d_f, potential, bd, fp, sd, ld, n_steps, x, p, st))) return rc;
     if (f_out)
         HIPCHK(hipMemcpyAsync(f_out, ctx->d_f, 3 * (size_t)bd.N * sizeof(double), hipMemcpyDeviceToDevice, st));
     return check_launch(ctx);
@@ -626,18 +697,17 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     double mh = 0.5 * std::min(box[0], std::min(box[1], box[2]));
     FsParams fp;
     if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
-    const double skin = 0.5;
-    if (!(std::max(fp.d, fp.c) + skin < mh))
-        return fail(ctx, SNAPMD_EINVAL, "FS cutoff + skin must be < half the smallest box edge");
+    const double skin = kSweepSkin;
+    if (!(std::max(fp.d, fp.c) + 2.0 * skin < mh))
+        return fail(ctx, SNAPMD_EINVAL, "FS cutoff + %g A must be < half the smallest box edge", 2.0 * skin);
     SnapDev sd;
     const size_t SN3 = 3 * (size_t)S * N;
     // sweep scratch
-    if ((rc = ensure(ctx, ctx->sw_x, 3 * (size_t)N)) || (rc = ensure(ctx, ctx->sw_p, 3 * (size_t)N)) ||
-        (rc = ensure(ctx, ctx->sw_f, 3 * (size_t)N)) || (rc = ensure(ctx, ctx->sw_ref, 3 * (size_t)N)) ||
-        (rc = ensure(ctx, ctx->sw_rho, (size_t)N)) || (rc = ensure(ctx, ctx->sw_nbr, (size_t)N * kMaxNeigh)) ||
-        (rc = ensure(ctx, ctx->sw_cnt, (size_t)N)) || (rc = ensure(ctx, ctx->sw_out, 4)))
+    if ((rc = ensure(ctx, ctx->sw_out, 8))) return rc;
+    if (!sweep_fits_lds(N) &&
+        ((rc = ensure(ctx, ctx->sw_x, 3 * (size_t)N)) || (rc = ensure(ctx, ctx->sw_p, 3 * (size_t)N))))
         return rc;
-    if (!ctx->h_out) HIPCHK(hipHostMalloc((void **)&ctx->h_out, 4 * sizeof(double), hipHostMallocDefault));
+    if (!ctx->h_out) HIPCHK(hipHostMalloc((void **)&ctx->h_out, 16 * sizeof(double), hipHostMallocDefault));
     const double c1 = std::exp(-lang->gamma * lang->dt);
     SweepLaunch sw{};
     sw.N = N;
@@ -656,31 +726,21 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     sw.n_in = n_in;
     sw.n_fi = *n_fi;
     sw.mode = init ? 0 : 1;
+    sw.n_win = n_in;
     sw.delta_expl = delta_expl;
     sw.q_cur = q_cur;
     sw.p_cur = p_cur;
     sw.q_prev = q_prev;
     sw.p_prev = p_prev;
-    sw.wx = ctx->sw_x.p;
-    sw.wp = ctx->sw_p.p;
-    sw.wf = ctx->sw_f.p;
-    sw.wrho = ctx->sw_rho.p;
-    sw.xref = ctx->sw_ref.p;
-    sw.nbr = ctx->sw_nbr.p;
-    sw.cnt = ctx->sw_cnt.p;
     sw.out = ctx->sw_out.p;
-    HIPCHK(hipMemsetAsync(ctx->sw_out.p, 0, 4 * sizeof(double), st));
     {
-        // Gaussians of every (slab, step, atom) of the window, shared by all iterations
-        const std::vector<double> key{(double)n_in, (double)S, (double)L, (double)N, (double)lang->seed,
-                                      (double)lang->noise_id_sys[0]};
-        if (sweep_fits_lds(N) && key != ctx->noise_key) {
-            if ((rc = ensure(ctx, ctx->sw_noise, (size_t)S * L * 3 * N))) return rc;
-            launch_noise_table(S, L, N, n_in, lang->seed, (uint64_t)lang->noise_id_sys[0], ctx->sw_noise.p, st);
-            ctx->noise_key = key;
-        }
-        sw.noise = ctx->sw_noise.p;
+        // sweep state carried over the launches of this call
+        double *h0 = ctx->h_out + 8;
+        const double init_out[8] = {0.0, (double)*n_fi, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        std::memcpy(h0, init_out, sizeof init_out);
+        HIPCHK(hipMemcpyAsync(ctx->sw_out.p, h0, 8 * sizeof(double), hipMemcpyHostToDevice, st));
     }
+    const bool lds_sweep = sweep_fits_lds(N);
     if (!init) {
         // prev_n := cur_n on [n_in, n_fi]
         const size_t slot = 3 * (size_t)N;
@@ -708,28 +768,90 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         if ((rc = ensure(ctx, ctx->pr_xf, SN3)) || (rc = ensure(ctx, ctx->pr_pf, SN3)) ||
             (rc = ensure(ctx, ctx->pr_xc, SN3)) || (rc = ensure(ctx, ctx->pr_pc, SN3)))
             return rc;
+        if ((rc = ensure_atoms_coarse(ctx, (size_t)S * N))) return rc;
+        // The slabs are propagated in chunks of consecutive slabs (chunk c occupies
+        // [3][S_c N] at offset 3 N s0 of the batch buffers).  The SNAP propagation of the
+        // chunks runs on the caller's stream; the Finnis-Sinclair propagation, the jumps
+        // and (LDS-resident case) the sweep run on a second stream, the sweep over chunk c
+        // as soon as the SNAP propagation of chunk c is done, overlapping the later chunks.
+        const std::vector<int> plan = lds_sweep ? chunk_plan(S) : std::vector<int>{S};
+        if (!ctx->sweep_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->sweep_stream, hipStreamNonBlocking));
+        for (int c = (int)ctx->pipe_ev.size(); c <= kPipeChunks + 1; ++c) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            ctx->pipe_ev.push_back(e);
+        }
+        hipStream_t s2 = ctx->sweep_stream;
+        if (lds_sweep) {
+            if ((rc = launch_noise_sweep(ctx, n_in, S, L, N, lang, st))) return rc;
+            sw.noise = ctx->sw_noise.p;
+        }
         const double *qs = q_prev + n_in * slot, *ps = p_prev + n_in * slot;
-        launch_slabs_to_batch(S, N, qs, ctx->pr_xf.p, st);
-        launch_slabs_to_batch(S, N, ps, ctx->pr_pf.p, st);
-        launch_slabs_to_batch(S, N, qs, ctx->pr_xc.p, st);
-        launch_slabs_to_batch(S, N, ps, ctx->pr_pc.p, st);
-        if ((rc = prepare_cells(ctx, bd, std::max(sd.gp.rcut, std::max(fp.d, fp.c)) + kSkin, st))) return rc;
-        if ((rc = run_langevin_graph(ctx, SNAPMD_POT_FS_SNAP, bd, fp, sd, ld, L, ctx->pr_xf.p, ctx->pr_pf.p, st)))
-            return rc;
-        if ((rc = prepare_cells(ctx, bd, std::max(fp.d, fp.c) + kSkin, st))) return rc;
-        if ((rc = run_langevin_graph(ctx, SNAPMD_POT_FS, bd, fp, sd, ld, L, ctx->pr_xc.p, ctx->pr_pc.p, st)))
-            return rc;
-        launch_jumps(SN3, ctx->pr_xf.p, ctx->pr_xc.p, st);
-        launch_jumps(SN3, ctx->pr_pf.p, ctx->pr_pc.p, st);
+        auto chunk_of = [&](int c, int s0, BatchDev &bc, LangevinDev &lc) {
+            const int nc = plan[c];
+            bc = bd;
+            bc.N = nc * N;
+            bc.n_sys = nc;
+            lc = ld;
+            lc.sig += s0;
+            lc.step0 += s0;
+            lc.noise_id += s0;
+            return nc;
+        };
+        HIPCHK(hipEventRecord(ctx->pipe_ev[kPipeChunks + 1], st));
+        HIPCHK(hipStreamWaitEvent(s2, ctx->pipe_ev[kPipeChunks + 1], 0));
+        for (int c = 0, s0 = 0; c < (int)plan.size(); s0 += plan[c], ++c) {  // coarse (second stream)
+            BatchDev bc;
+            LangevinDev lc;
+            const int nc = chunk_of(c, s0, bc, lc);
+            const size_t o = 3 * (size_t)N * s0;
+            launch_slabs_to_batch(nc, N, qs + s0 * slot, ctx->pr_xc.p + o, s2);
+            launch_slabs_to_batch(nc, N, ps + s0 * slot, ctx->pr_pc.p + o, s2);
+            if ((rc = run_langevin_graph(ctx, ctx->wc, ctx->d_fc, SNAPMD_POT_FS, bc, fp, sd, lc, L, ctx->pr_xc.p + o,
+                                         ctx->pr_pc.p + o, s2)))
+                return rc;
+        }
+        for (int c = 0, s0 = 0; c < (int)plan.size(); s0 += plan[c], ++c) {
+            BatchDev bc;
+            LangevinDev lc;
+            const int nc = chunk_of(c, s0, bc, lc);
+            const size_t o = 3 * (size_t)N * s0;
+            launch_slabs_to_batch(nc, N, qs + s0 * slot, ctx->pr_xf.p + o, st);
+            launch_slabs_to_batch(nc, N, ps + s0 * slot, ctx->pr_pf.p + o, st);
+            if ((rc = run_langevin_graph(ctx, ctx->w, ctx->d_f, SNAPMD_POT_FS_SNAP, bc, fp, sd, lc, L,
+                                         ctx->pr_xf.p + o, ctx->pr_pf.p + o, st)))
+                return rc;
+            HIPCHK(hipEventRecord(ctx->pipe_ev[c], st));
+            HIPCHK(hipStreamWaitEvent(s2, ctx->pipe_ev[c], 0));
+            launch_jumps(3 * (size_t)nc * N, ctx->pr_xf.p + o, ctx->pr_xc.p + o, s2);
+            launch_jumps(3 * (size_t)nc * N, ctx->pr_pf.p + o, ctx->pr_pc.p + o, s2);
+            if (lds_sweep) {
+                SweepLaunch sc = sw;
+                sc.n_in = n_in + s0;
+                sc.n_fi = n_in + s0 + nc;
+                sc.jq = ctx->pr_xf.p + o;
+                sc.jp = ctx->pr_pf.p + o;
+                sc.noise = sw.noise + (size_t)s0 * L * 3 * N;
+                launch_coarse_sweep(sc, s2);
+                if ((rc = check_launch(ctx))) return rc;
+            }
+        }
+        HIPCHK(hipEventRecord(ctx->pipe_ev[kPipeChunks], s2));
+        HIPCHK(hipStreamWaitEvent(st, ctx->pipe_ev[kPipeChunks], 0));
         sw.jq = ctx->pr_xf.p;
         sw.jp = ctx->pr_pf.p;
-    }
-    if (sweep_fits_lds(N)) {
+    } else if (lds_sweep) {
+        if ((rc = launch_noise_sweep(ctx, n_in, S, L, N, lang, st))) return rc;
+        sw.noise = ctx->sw_noise.p;
         launch_coarse_sweep(sw, st);
         if ((rc = check_launch(ctx))) return rc;
-        HIPCHK(hipMemcpyAsync(ctx->h_out, ctx->sw_out.p, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    if (lds_sweep) {
+        HIPCHK(hipMemcpyAsync(ctx->h_out, ctx->sw_out.p, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
         if ((rc = snapmd_sync(ctx, stream))) return rc;
-        if (ctx->h_out[3] != 0.0) return fail(ctx, SNAPMD_EOVERFLOW, "an atom has more than %d neighbours", kMaxNeigh);
+        if (ctx->h_out[3] != 0.0)
+            return fail(ctx, SNAPMD_EOVERFLOW, "an atom of the coarse sweep has more than its list capacity of "
+                                               "neighbours");
         if (ctx->h_out[2] >= 0.0)
             return fail(ctx, SNAPMD_ENONFINITE, "state became non-finite in slab %d", (int)ctx->h_out[2]);
         *delta_out = ctx->h_out[0];
@@ -740,8 +862,9 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     // small synchronisation per slab for the relative error and the early stop.
     {
         const size_t slot = 3 * (size_t)N;
-        HIPCHK(hipMemcpyAsync(sw.wx, q_cur + n_in * slot, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(sw.wp, p_cur + n_in * slot, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
+        double *wx = ctx->sw_x.p, *wp = ctx->sw_p.p;
+        HIPCHK(hipMemcpyAsync(wx, q_cur + n_in * slot, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(wp, p_cur + n_in * slot, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
         int off1[2] = {0, N};
         snapmd_batch b1{1, off1, box};
         BatchDev bd1;
@@ -755,8 +878,8 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
             std::vector<int> id1(1, lang->noise_id_sys[0]);
             LangevinDev ld1;
             if ((rc = prepare_langevin(ctx, lang, 1, T1, s1, id1, ld1, st))) return rc;
-            run_langevin(ctx, SNAPMD_POT_FS, bd1, fp, sd, ld1, L, sw.wx, sw.wp, st);
-            launch_slab_end(N, init ? 0 : 1, SN3 / 3, (size_t)(n - n_in), sw.wx, sw.wp, sw.jq, sw.jp,
+            run_langevin(ctx, ctx->w, ctx->d_f, SNAPMD_POT_FS, bd1, fp, sd, ld1, L, wx, wp, st);
+            launch_slab_end(N, init ? 0 : 1, SN3 / 3, (size_t)(n - n_in), wx, wp, sw.jq, sw.jp,
                             init ? nullptr : q_prev + (size_t)(n + 1) * slot, q_cur + (size_t)(n + 1) * slot,
                             p_cur + (size_t)(n + 1) * slot, ctx->sw_out.p, st);
             if ((rc = check_launch(ctx))) return rc;
@@ -846,7 +969,7 @@ int snap_beta_grad(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch 
         return check_launch(ctx);
     }
     if ((rc = ensure(ctx, ctx->gB, (size_t)K * N))) return rc;
-    if ((rc = neighbors(ctx, bd, x, snap->rcut, true, st))) return rc;
+    if ((rc = neighbors(ctx, ctx->w, bd, x, snap->rcut, true, st))) return rc;
     launch_snap_density(sd.J, bd, x, sd, ctx->w, st);           // u (and the pair geometry)
     launch_bispectrum(bd, sd, ctx->w, ctx->gB.p, st);           // B[k][i]
     launch_reduce_rows(K, N, ctx->gB.p, 1.0, dEdbeta + 1, st);
@@ -871,7 +994,7 @@ int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_bat
     if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
     if ((rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
-    if ((rc = neighbors(ctx, bd, x, snap->rcut, true, st))) return rc;
+    if ((rc = neighbors(ctx, ctx->w, bd, x, snap->rcut, true, st))) return rc;
     launch_snap_density(sd.J, bd, x, sd, ctx->w, st);
     launch_bispectrum(bd, sd, ctx->w, B, st);
     return check_launch(ctx);

@@ -15,6 +15,16 @@ __device__ __forceinline__ double2 cmul2(double2 a, double2 b, double2 c, double
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// 1/sqrt(r2) for a normal r2 > 0: the hardware estimate (about 24 bits) refined by two
+// Newton steps y <- y + y (1 - r2 y^2) / 2 (below one ulp); r = r2 * rsqrt_nr(r2).
+__device__ __forceinline__ double rsqrt_nr(double r2) {
+    double y = __builtin_amdgcn_rsq(r2);
+    double e = fma(-r2 * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-r2 * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
 __device__ __forceinline__ int sys_of(const int *__restrict__ off, int n_sys, int i) {
     int lo = 0, hi = n_sys - 1;
     while (lo < hi) {

@@ -125,12 +125,10 @@ struct SweepLaunch {
     double skin;
     double dt, c1, mass, sig;
     uint64_t seed, noise_id;
-    int L, n_in, n_fi, mode;
+    int L, n_in, n_fi, mode, n_win;
     double delta_expl;
     double *q_cur, *p_cur;
     const double *q_prev, *p_prev, *jq, *jp;
-    double *wx, *wp, *wf, *wrho, *xref;
-    int *nbr, *cnt;
     double *out;
     const double *noise;  // [S][L][3][N], S = n_fi - n_in
 };

@@ -236,8 +236,9 @@ __global__ void k_fs_rho(int N, int n_sys, const int *__restrict__ off, const do
     for (int p = poff[i]; p < poff[i + 1]; ++p) {
         const int j = pair_j[p];
         const double dx = mimg(x[j] - xi, Lx, iLx), dy = mimg(x[N + j] - yi, Ly, iLy), dz = mimg(x[2 * N + j] - zi, Lz, iLz);
-        const double r = sqrt(dx * dx + dy * dy + dz * dz);
-        if (r < d) acc += (r - d) * (r - d);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double r = r2 * rsqrt_nr(r2);
+        if (r2 < d * d) acc += (r - d) * (r - d);
     }
     rho[i] = acc;
 }
@@ -258,7 +259,8 @@ __global__ void k_fs_force(int N, int n_sys, const int *__restrict__ off, const 
     for (int p = poff[i]; p < poff[i + 1]; ++p) {
         const int j = pair_j[p];
         const double dx = mimg(x[j] - xi, Lx, iLx), dy = mimg(x[N + j] - yi, Ly, iLy), dz = mimg(x[2 * N + j] - zi, Lz, iLz);
-        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double ir = rsqrt_nr(r2), r = r2 * ir;
         double dEdr = 0.0;
         if (r < fp.c) {
             const double t = r - fp.c, poly = fp.c0 + r * (fp.c1 + r * fp.c2);
@@ -271,7 +273,7 @@ __global__ void k_fs_force(int N, int n_sys, const int *__restrict__ off, const 
             dEdr += (dFi + dFj) * 2.0 * (r - fp.d);
         }
         if (r < fp.c || r < fp.d) {
-            const double w = dEdr / r;
+            const double w = dEdr * ir;
             fx += w * dx;
             fy += w * dy;
             fz += w * dz;

@@ -2,7 +2,7 @@
 //
 //   k_slabs_to_batch : slab states [slot][3][N] -> batch layout [3][S*N] (S slabs)
 //   k_jumps          : J = F(prev) - C(prev) in batch layout (in place into the fine copy)
-//   k_coarse_sweep   : the sequential part of a parareal iteration in ONE persistent
+//   k_coarse_sweep_lds : the sequential part of a parareal iteration in ONE persistent
 //                      workgroup: for n = n_in .. n_fi-1, cur_{n+1} = C(cur_n) + J_n with
 //                      C = L BAOAB steps on the Finnis-Sinclair potential (force at the
 //                      slab start, same noise counters as the batched propagators), the
@@ -42,32 +42,6 @@ __global__ void k_jumps(size_t n, double *__restrict__ a, const double *__restri
     if (q < n) a[q] = a[q] - b[q];
 }
 
-// block-wide reduction helpers (1024 threads, red has 1024 doubles)
-__device__ __forceinline__ double block_sum(double v, double *red) {
-    const int t = threadIdx.x;
-    red[t] = v;
-    __syncthreads();
-    for (int s = kSweepThreads / 2; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
-}
-__device__ __forceinline__ double block_max(double v, double *red) {
-    const int t = threadIdx.x;
-    red[t] = v;
-    __syncthreads();
-    for (int s = kSweepThreads / 2; s > 0; s >>= 1) {
-        if (t < s) red[t] = fmax(red[t], red[t + s]);
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
-}
-
 struct SweepArgs {
     int N;
     double Lx, Ly, Lz, iLx, iLy, iLz;
@@ -75,93 +49,18 @@ struct SweepArgs {
     double skin;
     double dt, c1, mass, sig;
     uint64_t seed, noise_id;
-    int L, n_in, n_fi, mode;  // mode 0: initialise (no jumps), 1: corrected sweep
+    int L, n_in, n_fi, mode;  // slabs n_in .. n_fi-1; mode 0: initialise (no jumps), 1: corrected
+    int n_win;                // first slab of the window (the early stop keeps at least n_win + 1)
     double delta_expl;
     double *q_cur, *p_cur;                 // [slot][3][N]
     const double *q_prev, *p_prev;         // [slot][3][N] (mode 1)
     const double *jq, *jp;                 // [3][S*N], S = n_fi - n_in (mode 1)
-    double *wx, *wp, *wf, *wrho, *xref;    // [3N], [3N], [3N], [N], [3N]
-    int *nbr, *cnt;                        // [N][kMaxNeigh], [N]
-    double *out;                           // [0] delta, [1] n_fi after, [2] bad slab (-1 none), [3] overflow
-    const double *noise;                   // [S][L][3][N] Gaussians of the window's slabs
+    // [0] delta, [1] n_fi after, [2] bad slab (-1 none), [3] overflow, [4] sum |cur - prev|,
+    // [5] sum |prev|, [6] stopped: carried from one launch to the next over the slabs of a
+    // window, initialised by the host
+    double *out;
+    const double *noise;                   // [S][L][3][N] Gaussians of slabs n_in .. n_fi-1
 };
-
-__device__ void sweep_build(const SweepArgs &a) {
-    const int N = a.N;
-    const double rc = fmax(a.fp.d, a.fp.c) + a.skin, rc2 = rc * rc;
-    for (int i = threadIdx.x; i < N; i += kSweepThreads) {
-        const double xi = a.wx[i], yi = a.wx[N + i], zi = a.wx[2 * N + i];
-        int c = 0;
-        for (int j = 0; j < N; ++j) {
-            if (j == i) continue;
-            const double dx = mimg_s(a.wx[j] - xi, a.Lx, a.iLx), dy = mimg_s(a.wx[N + j] - yi, a.Ly, a.iLy),
-                         dz = mimg_s(a.wx[2 * N + j] - zi, a.Lz, a.iLz);
-            if (dx * dx + dy * dy + dz * dz < rc2) {
-                if (c < kMaxNeigh) a.nbr[(size_t)i * kMaxNeigh + c] = j;
-                ++c;
-            }
-        }
-        if (c > kMaxNeigh) { a.out[3] = 1.0; c = kMaxNeigh; }
-        a.cnt[i] = c;
-        a.xref[i] = xi; a.xref[N + i] = yi; a.xref[2 * N + i] = zi;
-    }
-}
-
-// Finnis-Sinclair force on every atom into wf (same expressions as the batched kernels).
-__device__ void sweep_force(const SweepArgs &a) {
-    const int N = a.N;
-    const FsParams fp = a.fp;
-    const double d2c = fp.d * fp.d, rc2f = fmax(fp.d, fp.c) * fmax(fp.d, fp.c);
-    for (int i = threadIdx.x; i < N; i += kSweepThreads) {
-        const double xi = a.wx[i], yi = a.wx[N + i], zi = a.wx[2 * N + i];
-        double acc = 0.0;
-        for (int t = 0; t < a.cnt[i]; ++t) {
-            const int j = a.nbr[(size_t)i * kMaxNeigh + t];
-            const double dx = mimg_s(a.wx[j] - xi, a.Lx, a.iLx), dy = mimg_s(a.wx[N + j] - yi, a.Ly, a.iLy),
-                         dz = mimg_s(a.wx[2 * N + j] - zi, a.Lz, a.iLz);
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 >= d2c) continue;
-            const double r = sqrt(r2);
-            if (r < fp.d) acc += (r - fp.d) * (r - fp.d);
-        }
-        a.wrho[i] = acc;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < N; i += kSweepThreads) {
-        const double xi = a.wx[i], yi = a.wx[N + i], zi = a.wx[2 * N + i];
-        const double ri = a.wrho[i];
-        const double dFi = ri > 0.0 ? -fp.A / (2.0 * sqrt(ri)) : 0.0;
-        double fx = 0.0, fy = 0.0, fz = 0.0;
-        for (int t = 0; t < a.cnt[i]; ++t) {
-            const int j = a.nbr[(size_t)i * kMaxNeigh + t];
-            const double dx = mimg_s(a.wx[j] - xi, a.Lx, a.iLx), dy = mimg_s(a.wx[N + j] - yi, a.Ly, a.iLy),
-                         dz = mimg_s(a.wx[2 * N + j] - zi, a.Lz, a.iLz);
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 >= rc2f) continue;
-            const double r = sqrt(r2);
-            double dEdr = 0.0;
-            if (r < fp.c) {
-                const double tt = r - fp.c, poly = fp.c0 + r * (fp.c1 + r * fp.c2);
-                dEdr += 2.0 * tt * poly + tt * tt * (fp.c1 + 2.0 * fp.c2 * r);
-            }
-            if (r < fp.d) {
-                const double rj = a.wrho[j];
-                const double dFj = rj > 0.0 ? -fp.A / (2.0 * sqrt(rj)) : 0.0;
-                dEdr += (dFi + dFj) * 2.0 * (r - fp.d);
-            }
-            if (r < fp.c || r < fp.d) {
-                const double w = dEdr / r;
-                fx += w * dx;
-                fy += w * dy;
-                fz += w * dz;
-            }
-        }
-        a.wf[i] = fx;
-        a.wf[N + i] = fy;
-        a.wf[2 * N + i] = fz;
-    }
-    __syncthreads();
-}
 
 __device__ __forceinline__ void sweep_gauss3(uint64_t seed, uint64_t noise_id, uint64_t step, uint64_t atom,
                                              double &g0, double &g1, double &g2) {
@@ -189,60 +88,401 @@ __device__ __forceinline__ void sweep_gauss3(uint64_t seed, uint64_t noise_id, u
     g2 = r2 * c4;
 }
 
-__global__ void __launch_bounds__(1024) k_coarse_sweep(SweepArgs a) {
-    __shared__ double red[kSweepThreads];
-    const int N = a.N;
-    const size_t SN = (size_t)(a.n_fi - a.n_in) * N;
-    for (int i = threadIdx.x; i < N; i += kSweepThreads)
-        for (int al = 0; al < 3; ++al) {
-            a.wx[al * N + i] = a.q_cur[((size_t)a.n_in * 3 + al) * N + i];
-            a.wp[al * N + i] = a.p_cur[((size_t)a.n_in * 3 + al) * N + i];
-        }
+// ---------------------------------------------------------------------------
+// LDS-resident sweep (N <= kSweepLdsMaxAtoms): positions, F'(rho) and a uint16 Verlet
+// list live in LDS; momenta, forces and reference positions of the atoms a thread owns
+// live in its registers.  Thread t owns atom t.  Atoms beyond the first 1024 are owned
+// by a second round of threads (t + 1024) or, when there are at most 16 of them, one
+// per wave, the wave's lanes then sharing that atom's neighbour list.
+// The rho pass marks the list entries within the force cutoff; the force pass of the
+// same step visits only those.
+// ---------------------------------------------------------------------------
+constexpr int kSweepLdsNeigh = 48;
+constexpr int kSweepNbRows = kSweepLdsNeigh + 3;  // a thread's list is padded to a multiple of 4
+constexpr int kSweepLdsMaxAtoms = 2048;
+constexpr int kSpillMax = kSweepThreads / 64;
+
+// positions, F'(rho), list, the momenta / forces / reference positions of the atoms
+// beyond the first 1024 (their owners keep them in LDS), reduction partials
+size_t sweep_lds_bytes(int N) {
+    const size_t NS = N > kSweepThreads ? (size_t)(N - kSweepThreads) : 0;
+    return (size_t)N * (3 * sizeof(double) + sizeof(double) + kSweepNbRows * sizeof(uint16_t)) +
+           NS * 9 * sizeof(double) + kSpillMax * sizeof(double);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+// workgroup reductions through kSpillMax wave partials (fixed order, every thread gets the result)
+__device__ __forceinline__ double wg_sum(double v, double *red) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    double num = 0.0, den = 0.0, delta = 0.0;
-    int nfi_new = a.n_fi, bad = -1;
-    const double hk = 0.5 * a.dt / SW_MVV2E, hd = 0.5 * a.dt / a.mass;
-    for (int n = a.n_in; n < a.n_fi; ++n) {
-        sweep_build(a);
+    double r = red[0];
+#pragma unroll
+    for (int w = 1; w < kSpillMax; ++w) r += red[w];
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ double wg_max(double v, double *red) {
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int w = 1; w < kSpillMax; ++w) r = fmax(r, red[w]);
+    __syncthreads();
+    return r;
+}
+
+// separation x_j - x_i (minimum image) of list entry j
+__device__ __forceinline__ void swl_sep(const SweepArgs &a, const double *__restrict__ xs, int N, int j, double xi,
+                                        double yi, double zi, double &dx, double &dy, double &dz) {
+    dx = mimg_s(xs[j] - xi, a.Lx, a.iLx);
+    dy = mimg_s(xs[N + j] - yi, a.Ly, a.iLy);
+    dz = mimg_s(xs[2 * N + j] - zi, a.Lz, a.iLz);
+}
+
+// list test of the pair (i, j): within the list radius
+__device__ __forceinline__ bool swl_pair(const SweepArgs &a, const double *__restrict__ xs, int N, int j, double xi,
+                                         double yi, double zi, double rcl2) {
+    double dx, dy, dz;
+    swl_sep(a, xs, N, j, xi, yi, zi, dx, dy, dz);
+    return dx * dx + dy * dy + dz * dz < rcl2;
+}
+
+// list of atom i by one thread (j ascending); returns the count (capped, overflow flagged)
+__device__ __forceinline__ int swl_build_thread(const SweepArgs &a, const double *__restrict__ xs,
+                                                uint16_t *__restrict__ nb, int i, double rcl2, int &overflow) {
+    const int N = a.N;
+    const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
+    int c = 0;
+    for (int j = 0; j < N; ++j) {
+        if (j != i && swl_pair(a, xs, N, j, xi, yi, zi, rcl2)) {
+            if (c < kSweepLdsNeigh) nb[c * N + i] = (uint16_t)j;
+            ++c;
+        }
+    }
+    if (c > kSweepLdsNeigh) {
+        overflow = 1;
+        c = kSweepLdsNeigh;
+    }
+    // rows c .. c+2 repeat the last entry (read, never counted, by the unrolled passes)
+    const uint16_t last = c > 0 ? nb[(c - 1) * N + i] : (uint16_t)i;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) nb[(c + t) * N + i] = last;
+    return c;
+}
+
+// list of atom i by a whole wave (lanes scan 64 j at a time, ballot compaction keeps j ascending)
+__device__ __forceinline__ int swl_build_wave(const SweepArgs &a, const double *__restrict__ xs,
+                                              uint16_t *__restrict__ nb, int i, double rcl2, int &overflow) {
+    const int N = a.N, lane = threadIdx.x & 63;
+    const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
+    const uint64_t below = (1ull << lane) - 1ull;
+    int c = 0;
+    for (int base = 0; base < N; base += 64) {
+        const int j = base + lane;
+        const int hit = (j < N && j != i) ? (int)swl_pair(a, xs, N, j, xi, yi, zi, rcl2) : 0;
+        const uint64_t m = __ballot(hit);
+        const int pos = c + __popcll(m & below);
+        if (hit && pos < kSweepLdsNeigh) nb[pos * N + i] = (uint16_t)j;
+        c += __popcll(m);
+    }
+    if (c > kSweepLdsNeigh) {
+        overflow = 1;
+        c = kSweepLdsNeigh;
+    }
+    return c;
+}
+
+// rho pass of atom i by one thread: F'(rho_i) into dfe[i]; mask of the entries within
+// the force cutoff (positions do not change before the force pass of the same step).
+// The unrolled body is branch-free (entries past the count repeat the last one and
+// add nothing) so that the LDS reads of four neighbours are in flight together.
+__device__ __forceinline__ uint64_t swl_rho_thread(const SweepArgs &a, const double *__restrict__ xs,
+                                                   double *__restrict__ dfe, const uint16_t *__restrict__ nb, int i,
+                                                   int c) {
+    const int N = a.N;
+    const FsParams fp = a.fp;
+    const double d2c = fp.d * fp.d, rc2f = fmax(fp.d, fp.c) * fmax(fp.d, fp.c);
+    const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
+    double acc = 0.0;
+    uint64_t mk = 0;
+    for (int t0 = 0; t0 < c; t0 += 4) {
+        int e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) e[u] = (int)nb[__umul24(t0 + u, N) + i];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool valid = t0 + u < c;
+            double dx, dy, dz;
+            swl_sep(a, xs, N, e[u], xi, yi, zi, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            mk |= (valid && r2 < rc2f) ? (1ull << (t0 + u)) : 0ull;
+            const double r = r2 * rsqrt_nr(r2);
+            acc += (valid && r2 < d2c) ? (r - fp.d) * (r - fp.d) : 0.0;
+        }
+    }
+    dfe[i] = acc > 0.0 ? -fp.A / (2.0 * sqrt(acc)) : 0.0;
+    return mk;
+}
+
+// pair force term w = (dE/dr) / r of a pair at distance r (ir = 1/r)
+__device__ __forceinline__ double swl_w(const FsParams &fp, double r, double ir, double dFi, double dFj) {
+    const double tt = r - fp.c, poly = fp.c0 + r * (fp.c1 + r * fp.c2);
+    const double pc = r < fp.c ? 2.0 * tt * poly + tt * tt * (fp.c1 + 2.0 * fp.c2 * r) : 0.0;
+    const double pd = r < fp.d ? (dFi + dFj) * 2.0 * (r - fp.d) : 0.0;
+    return (pc + pd) * ir;
+}
+
+// force pass of atom i by one thread over the masked entries (branch-free groups of 4)
+__device__ __forceinline__ void swl_force_thread(const SweepArgs &a, const double *__restrict__ xs,
+                                                 const double *__restrict__ dfe, const uint16_t *__restrict__ nb,
+                                                 int i, uint64_t m, double (&f)[3]) {
+    const int N = a.N;
+    const FsParams fp = a.fp;
+    const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
+    const double dFi = dfe[i];
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    while (m) {
+        int e[4];
+        bool v[4];
+        int t = __builtin_ctzll(m);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[u] = m != 0;
+            t = v[u] ? __builtin_ctzll(m) : t;
+            m &= m - 1ull;
+            e[u] = (int)nb[__umul24(t, N) + i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double dx, dy, dz;
+            const int j = e[u];
+            swl_sep(a, xs, N, j, xi, yi, zi, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double ir = rsqrt_nr(r2), r = r2 * ir;
+            const double w = swl_w(fp, r, ir, dFi, dfe[j]);
+            fx += v[u] ? w * dx : 0.0;
+            fy += v[u] ? w * dy : 0.0;
+            fz += v[u] ? w * dz : 0.0;
+        }
+    }
+    f[0] = fx;
+    f[1] = fy;
+    f[2] = fz;
+}
+
+// rho pass of atom i by a whole wave (lane t takes entry t, c <= 64); returns the mask
+__device__ __forceinline__ uint64_t swl_rho_wave(const SweepArgs &a, const double *__restrict__ xs,
+                                                 double *__restrict__ dfe, const uint16_t *__restrict__ nb, int i,
+                                                 int c) {
+    const int N = a.N, lane = threadIdx.x & 63;
+    const FsParams fp = a.fp;
+    const double d2c = fp.d * fp.d, rc2f = fmax(fp.d, fp.c) * fmax(fp.d, fp.c);
+    double v = 0.0;
+    int in = 0;
+    if (lane < c) {
+        double dx, dy, dz;
+        swl_sep(a, xs, N, (int)nb[lane * N + i], xs[i], xs[N + i], xs[2 * N + i], dx, dy, dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        in = r2 < rc2f;
+        if (r2 < d2c) {
+            const double r = r2 * rsqrt_nr(r2);
+            v = (r - fp.d) * (r - fp.d);
+        }
+    }
+    const uint64_t mk = __ballot(in);
+    const double acc = wave_sum(v);
+    if (lane == 0) dfe[i] = acc > 0.0 ? -fp.A / (2.0 * sqrt(acc)) : 0.0;
+    return mk;
+}
+
+// force pass of atom i by a whole wave; every lane receives the force
+__device__ __forceinline__ void swl_force_wave(const SweepArgs &a, const double *__restrict__ xs,
+                                               const double *__restrict__ dfe, const uint16_t *__restrict__ nb, int i,
+                                               uint64_t mk, double (&f)[3]) {
+    const int N = a.N, lane = threadIdx.x & 63;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if ((mk >> lane) & 1ull) {
+        double dx, dy, dz;
+        const int j = (int)nb[lane * N + i];
+        swl_sep(a, xs, N, j, xs[i], xs[N + i], xs[2 * N + i], dx, dy, dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double ir = rsqrt_nr(r2), r = r2 * ir;
+        const double w = swl_w(a.fp, r, ir, dfe[i], dfe[j]);
+        fx = w * dx;
+        fy = w * dy;
+        fz = w * dz;
+    }
+    f[0] = wave_sum(fx);
+    f[1] = wave_sum(fy);
+    f[2] = wave_sum(fz);
+}
+
+__global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
+    extern __shared__ double sm[];
+    if (a.out[6] != 0.0) return;  // an earlier launch of the window stopped early
+    const int N = a.N;
+    const int NS = N > kSweepThreads ? N - kSweepThreads : 0;
+    double *red = sm;                                      // [kSpillMax]
+    double *xs = red + kSpillMax;                          // [3][N]
+    double *dfe = xs + 3 * N;                              // [N]  F'(rho)
+    double *s1 = dfe + N;                                  // [9][NS] p, f, reference x of atoms >= 1024
+    uint16_t *nb = reinterpret_cast<uint16_t *>(s1 + 9 * NS);  // [kSweepNbRows][N]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // second slot: the spill atom of this wave (lane 0 owns it) or atom tid + 1024
+    const bool spill = NS > 0 && NS <= kSpillMax;
+    const int is = kSweepThreads + wv;                     // spill atom of the wave
+    const bool has_s = spill && is < N;                    // wave-uniform
+    const int i1 = spill ? (lane == 0 ? is : N) : tid + kSweepThreads;
+    const bool own0 = tid < N, own1 = i1 < N;
+    double *p1 = s1 + (i1 - kSweepThreads), *f1 = p1 + 3 * NS, *r1 = p1 + 6 * NS;  // [al * NS] (own1 only)
+    const double rcl = fmax(a.fp.d, a.fp.c) + a.skin, rcl2 = rcl * rcl;
+    const size_t SN = (size_t)(a.n_fi - a.n_in) * N;
+    double pr[3], fr[3], xr[3];
+    int cn0 = 0, cn1 = 0;
+    uint64_t mk0 = 0, mk1 = 0;
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        fr[al] = 0.0;
+        xr[al] = 0.0;
+        pr[al] = 0.0;
+        if (own0) {
+            xs[al * N + tid] = a.q_cur[((size_t)a.n_in * 3 + al) * N + tid];
+            pr[al] = a.p_cur[((size_t)a.n_in * 3 + al) * N + tid];
+        }
+        if (own1) {
+            xs[al * N + i1] = a.q_cur[((size_t)a.n_in * 3 + al) * N + i1];
+            p1[al * NS] = a.p_cur[((size_t)a.n_in * 3 + al) * N + i1];
+            f1[al * NS] = 0.0;
+        }
+    }
+    __syncthreads();
+    int overflow = 0;
+    // thread-owned atoms of this thread: tid, and i1 outside the spill mode (one inlined
+    // copy of the per-thread passes, looped over the two slots)
+    const int nslot = (!spill && own1) ? 2 : 1;
+    auto build = [&]() {
+#pragma unroll 1
+        for (int q = 0; q < nslot; ++q) {
+            const int i = q ? i1 : tid;
+            if (i < N) {
+                const int c = swl_build_thread(a, xs, nb, i, rcl2, overflow);
+                if (q) cn1 = c;
+                else cn0 = c;
+            }
+        }
+        if (has_s) cn1 = swl_build_wave(a, xs, nb, is, rcl2, overflow);
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+            if (own0) xr[al] = xs[al * N + tid];
+            if (own1) r1[al * NS] = xs[al * N + i1];
+        }
         __syncthreads();
-        sweep_force(a);
-        for (int l = 0; l < a.L; ++l) {
-            double dmax = 0.0;
-            for (int i = threadIdx.x; i < N; i += kSweepThreads) {
+    };
+    auto forces = [&]() {
+#pragma unroll 1
+        for (int q = 0; q < nslot; ++q) {
+            const int i = q ? i1 : tid;
+            if (i < N) {
+                const uint64_t m = swl_rho_thread(a, xs, dfe, nb, i, q ? cn1 : cn0);
+                if (q) mk1 = m;
+                else mk0 = m;
+            }
+        }
+        if (has_s) mk1 = swl_rho_wave(a, xs, dfe, nb, is, cn1);
+        __syncthreads();
+#pragma unroll 1
+        for (int q = 0; q < nslot; ++q) {
+            const int i = q ? i1 : tid;
+            if (i < N) {
                 double g[3];
-                const double *gz = a.noise + ((size_t)((n - a.n_in) * a.L + l) * 3) * N + i;
-                g[0] = gz[0];
-                g[1] = gz[N];
-                g[2] = gz[2 * N];
-                double d2 = 0.0;
+                swl_force_thread(a, xs, dfe, nb, i, q ? mk1 : mk0, g);
 #pragma unroll
                 for (int al = 0; al < 3; ++al) {
-                    double pp = a.wp[al * N + i] + hk * a.wf[al * N + i];
-                    double xx = a.wx[al * N + i] + hd * pp;
-                    pp = a.c1 * pp + a.sig * g[al];
-                    xx = xx + hd * pp;
-                    a.wp[al * N + i] = pp;
-                    a.wx[al * N + i] = xx;
-                    const double dd = xx - a.xref[al * N + i];
-                    d2 += dd * dd;
+                    if (q) f1[al * NS] = g[al];
+                    else fr[al] = g[al];
                 }
-                dmax = fmax(dmax, d2);
             }
-            const double m = block_max(dmax, red);  // includes the barrier before the list is read
-            if (4.0 * m > a.skin * a.skin) {
-                sweep_build(a);
-                __syncthreads();
-            }
-            sweep_force(a);
-            for (int q = threadIdx.x; q < 3 * N; q += kSweepThreads) a.wp[q] = a.wp[q] + hk * a.wf[q];
-            __syncthreads();
         }
-        // slab end: cur_{n+1} = C(cur_n) (+ J_n)
+        if (has_s) {
+            double g[3];
+            swl_force_wave(a, xs, dfe, nb, is, mk1, g);
+            if (own1)
+#pragma unroll
+                for (int al = 0; al < 3; ++al) f1[al * NS] = g[al];
+        }
+        __syncthreads();
+    };
+    double num = a.out[4], den = a.out[5], delta = a.out[0];
+    int nfi_new = -1, bad = -1;
+    const double hk = 0.5 * a.dt / SW_MVV2E, hd = 0.5 * a.dt / a.mass;
+    bool built = false;
+    for (int n = a.n_in; n < a.n_fi; ++n) {
+        // l = -1: force at the slab start (slab states may have jumped); then L BAOAB steps.
+        // The list is rebuilt only if some atom moved more than skin/2 since the last build.
+        for (int l = -1; l < a.L; ++l) {
+            double d0 = 0.0, d1 = 0.0;
+            const double *gz = a.noise + ((size_t)((n - a.n_in) * a.L + max(l, 0)) * 3) * N;
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                if (own0) {
+                    double xx = xs[al * N + tid];
+                    if (l >= 0) {
+                        double pp = pr[al] + hk * fr[al];
+                        xx = xx + hd * pp;
+                        pp = a.c1 * pp + a.sig * gz[al * N + tid];
+                        xx = xx + hd * pp;
+                        pr[al] = pp;
+                        xs[al * N + tid] = xx;
+                    }
+                    d0 += (xx - xr[al]) * (xx - xr[al]);
+                }
+                if (own1) {
+                    double xx = xs[al * N + i1];
+                    if (l >= 0) {
+                        double pp = p1[al * NS] + hk * f1[al * NS];
+                        xx = xx + hd * pp;
+                        pp = a.c1 * pp + a.sig * gz[al * N + i1];
+                        xx = xx + hd * pp;
+                        p1[al * NS] = pp;
+                        xs[al * N + i1] = xx;
+                    }
+                    d1 += (xx - r1[al * NS]) * (xx - r1[al * NS]);
+                }
+            }
+            const double m = wg_max(fmax(d0, d1), red);
+            if (!built || !(4.0 * m <= a.skin * a.skin)) {
+                build();
+                built = true;
+            }
+            forces();
+            if (l >= 0) {
+#pragma unroll
+                for (int al = 0; al < 3; ++al) {
+                    pr[al] = pr[al] + hk * fr[al];
+                    if (own1) p1[al * NS] = p1[al * NS] + hk * f1[al * NS];
+                }
+            }
+        }
         const size_t s = (size_t)(n - a.n_in);
         double d2 = 0.0, p2 = 0.0, fin = 0.0;
-        for (int i = threadIdx.x; i < N; i += kSweepThreads)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int i = q == 0 ? tid : i1;
+            if (i >= N) continue;
+#pragma unroll
             for (int al = 0; al < 3; ++al) {
-                double xq = a.wx[al * N + i], pq = a.wp[al * N + i];
+                double xq = xs[al * N + i], pq = q == 0 ? pr[al] : p1[al * NS];
                 if (a.mode == 1) {
                     xq += a.jq[al * SN + s * N + i];
                     pq += a.jp[al * SN + s * N + i];
@@ -251,278 +491,25 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep(SweepArgs a) {
                     p2 += pv * pv;
                 }
                 fin += xq * 0.0 + pq * 0.0;  // NaN/Inf propagate into fin
-                a.wx[al * N + i] = xq;
-                a.wp[al * N + i] = pq;
-                a.q_cur[((size_t)(n + 1) * 3 + al) * N + i] = xq;
-                a.p_cur[((size_t)(n + 1) * 3 + al) * N + i] = pq;
-            }
-        const double sfin = block_sum(fin, red);
-        if (!isfinite(sfin)) {
-            bad = n;
-            break;
-        }
-        if (a.mode == 1) {
-            const double sd = block_sum(d2, red), sp = block_sum(p2, red);
-            num += sqrt(sd);
-            den += sqrt(sp);
-            delta = den > 0.0 ? num / den : 0.0;
-            if (delta > a.delta_expl) {
-                nfi_new = max(n, a.n_in + 1);
-                break;
-            }
-        }
-    }
-    if (threadIdx.x == 0) {
-        a.out[0] = delta;
-        a.out[1] = (double)nfi_new;
-        a.out[2] = (double)bad;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// LDS-resident sweep for small systems (N <= kSweepLdsMaxAtoms): positions, rho and a
-// uint16 Verlet list live in LDS, momenta / forces / reference positions of the (at
-// most kSweepAtomsPerThread) atoms a thread owns live in its registers.
-// ---------------------------------------------------------------------------
-constexpr int kSweepLdsNeigh = 40;
-constexpr int kSweepAtomsPerThread = 2;
-constexpr int kSweepLdsMaxAtoms = kSweepThreads * kSweepAtomsPerThread;
-
-size_t sweep_lds_bytes(int N) {
-    return (size_t)N * (3 * sizeof(double) + sizeof(double) + kSweepLdsNeigh * sizeof(uint16_t)) +
-           kSweepThreads * sizeof(double);
-}
-
-using SwReg = double[kSweepAtomsPerThread][3];
-
-__device__ __forceinline__ void swl_build(const SweepArgs &a, const double *__restrict__ xs, uint16_t *__restrict__ nb,
-                                          int (&cn)[kSweepAtomsPerThread], SwReg &xr, int &overflow) {
-    const int N = a.N, tid = threadIdx.x;
-    const double rcl = fmax(a.fp.d, a.fp.c) + a.skin, rcl2 = rcl * rcl;
-#pragma unroll
-    for (int q = 0; q < kSweepAtomsPerThread; ++q) {
-        const int i = tid + q * kSweepThreads;
-        if (i >= N) continue;
-        const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
-        int c = 0;
-        for (int j = 0; j < N; ++j) {
-            if (j == i) continue;
-            const double dx = mimg_s(xs[j] - xi, a.Lx, a.iLx), dy = mimg_s(xs[N + j] - yi, a.Ly, a.iLy),
-                         dz = mimg_s(xs[2 * N + j] - zi, a.Lz, a.iLz);
-            if (dx * dx + dy * dy + dz * dz < rcl2) {
-                if (c < kSweepLdsNeigh) nb[c * N + i] = (uint16_t)j;
-                ++c;
-            }
-        }
-        if (c > kSweepLdsNeigh) {
-            overflow = 1;
-            c = kSweepLdsNeigh;
-        }
-        cn[q] = c;
-        xr[q][0] = xi;
-        xr[q][1] = yi;
-        xr[q][2] = zi;
-    }
-}
-
-// Embedding derivative F'(rho) = -A / (2 sqrt(rho)) of every atom into LDS, barrier,
-// forces into registers, barrier.  Neighbour loops are unrolled by 4 so that the LDS
-// reads of independent neighbours overlap.
-__device__ __forceinline__ void swl_force(const SweepArgs &a, const double *__restrict__ xs, double *__restrict__ dfe,
-                                          const uint16_t *__restrict__ nb, const int (&cn)[kSweepAtomsPerThread],
-                                          SwReg &fr) {
-    const int N = a.N, tid = threadIdx.x;
-    const FsParams fp = a.fp;
-    const double d2c = fp.d * fp.d, rc2f = fmax(fp.d, fp.c) * fmax(fp.d, fp.c);
-#pragma unroll
-    for (int q = 0; q < kSweepAtomsPerThread; ++q) {
-        const int i = tid + q * kSweepThreads;
-        if (i >= N) continue;
-        const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
-        double acc = 0.0;
-        const int c = cn[q];
-        for (int t0 = 0; t0 < c; t0 += 4) {
-            int jj[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) jj[u] = (t0 + u < c) ? (int)nb[(t0 + u) * N + i] : i;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = jj[u];
-                const double dx = mimg_s(xs[j] - xi, a.Lx, a.iLx), dy = mimg_s(xs[N + j] - yi, a.Ly, a.iLy),
-                             dz = mimg_s(xs[2 * N + j] - zi, a.Lz, a.iLz);
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (j == i || r2 >= d2c) continue;
-                const double r = sqrt(r2);
-                acc += (r - fp.d) * (r - fp.d);
-            }
-        }
-        dfe[i] = acc > 0.0 ? -fp.A / (2.0 * sqrt(acc)) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kSweepAtomsPerThread; ++q) {
-        const int i = tid + q * kSweepThreads;
-        if (i >= N) continue;
-        const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
-        const double dFi = dfe[i];
-        double fx = 0.0, fy = 0.0, fz = 0.0;
-        const int c = cn[q];
-        for (int t0 = 0; t0 < c; t0 += 4) {
-            int jj[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) jj[u] = (t0 + u < c) ? (int)nb[(t0 + u) * N + i] : i;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = jj[u];
-                const double dx = mimg_s(xs[j] - xi, a.Lx, a.iLx), dy = mimg_s(xs[N + j] - yi, a.Ly, a.iLy),
-                             dz = mimg_s(xs[2 * N + j] - zi, a.Lz, a.iLz);
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (j == i || r2 >= rc2f) continue;
-                const double r = sqrt(r2);
-                double dEdr = 0.0;
-                if (r < fp.c) {
-                    const double tt = r - fp.c, poly = fp.c0 + r * (fp.c1 + r * fp.c2);
-                    dEdr += 2.0 * tt * poly + tt * tt * (fp.c1 + 2.0 * fp.c2 * r);
-                }
-                if (r < fp.d) dEdr += (dFi + dfe[j]) * 2.0 * (r - fp.d);
-                const double w = dEdr / r;
-                fx += w * dx;
-                fy += w * dy;
-                fz += w * dz;
-            }
-        }
-        fr[q][0] = fx;
-        fr[q][1] = fy;
-        fr[q][2] = fz;
-    }
-    __syncthreads();
-}
-
-__global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
-    extern __shared__ double sm[];
-    const int N = a.N;
-    double *red = sm;                                      // [1024]
-    double *xs = sm + kSweepThreads;                       // [3][N]
-    double *rho = xs + 3 * N;                              // [N]
-    uint16_t *nb = reinterpret_cast<uint16_t *>(rho + N);  // [kSweepLdsNeigh][N]
-    const int tid = threadIdx.x;
-    const size_t SN = (size_t)(a.n_fi - a.n_in) * N;
-    double pr[kSweepAtomsPerThread][3], fr[kSweepAtomsPerThread][3], xr[kSweepAtomsPerThread][3];
-    int cn[kSweepAtomsPerThread];
-#pragma unroll
-    for (int q = 0; q < kSweepAtomsPerThread; ++q) {
-        const int i = tid + q * kSweepThreads;
-        cn[q] = 0;
-#pragma unroll
-        for (int al = 0; al < 3; ++al) {
-            fr[q][al] = 0.0;
-            xr[q][al] = 0.0;
-            pr[q][al] = 0.0;
-            if (i < N) {
-                xs[al * N + i] = a.q_cur[((size_t)a.n_in * 3 + al) * N + i];
-                pr[q][al] = a.p_cur[((size_t)a.n_in * 3 + al) * N + i];
-            }
-        }
-    }
-    __syncthreads();
-    int overflow = 0;
-    double num = 0.0, den = 0.0, delta = 0.0;
-    int nfi_new = a.n_fi, bad = -1;
-    const double hk = 0.5 * a.dt / SW_MVV2E, hd = 0.5 * a.dt / a.mass;
-    bool built = false;
-    for (int n = a.n_in; n < a.n_fi; ++n) {
-        // the list is rebuilt only if some atom moved more than skin/2 since the last build
-        double dmax0 = 0.0;
-#pragma unroll
-        for (int q = 0; q < kSweepAtomsPerThread; ++q) {
-            const int i = tid + q * kSweepThreads;
-            if (i >= N) continue;
-            double d2 = 0.0;
-#pragma unroll
-            for (int al = 0; al < 3; ++al) {
-                const double dd = xs[al * N + i] - xr[q][al];
-                d2 += dd * dd;
-            }
-            dmax0 = fmax(dmax0, d2);
-        }
-        const double m0 = block_max(dmax0, red);
-        if (!built || !(4.0 * m0 <= a.skin * a.skin)) {
-            swl_build(a, xs, nb, cn, xr, overflow);
-            __syncthreads();
-            built = true;
-        }
-        swl_force(a, xs, rho, nb, cn, fr);
-        for (int l = 0; l < a.L; ++l) {
-            double dmax = 0.0;
-#pragma unroll
-            for (int q = 0; q < kSweepAtomsPerThread; ++q) {
-                const int i = tid + q * kSweepThreads;
-                if (i >= N) continue;
-                double g[3];
-                const double *gz = a.noise + ((size_t)((n - a.n_in) * a.L + l) * 3) * N + i;
-                g[0] = gz[0];
-                g[1] = gz[N];
-                g[2] = gz[2 * N];
-                double d2 = 0.0;
-#pragma unroll
-                for (int al = 0; al < 3; ++al) {
-                    double pp = pr[q][al] + hk * fr[q][al];
-                    double xx = xs[al * N + i] + hd * pp;
-                    pp = a.c1 * pp + a.sig * g[al];
-                    xx = xx + hd * pp;
-                    pr[q][al] = pp;
-                    xs[al * N + i] = xx;
-                    const double dd = xx - xr[q][al];
-                    d2 += dd * dd;
-                }
-                dmax = fmax(dmax, d2);
-            }
-            const double m = block_max(dmax, red);
-            if (4.0 * m > a.skin * a.skin) {
-                swl_build(a, xs, nb, cn, xr, overflow);
-                __syncthreads();
-            }
-            swl_force(a, xs, rho, nb, cn, fr);
-#pragma unroll
-            for (int q = 0; q < kSweepAtomsPerThread; ++q)
-#pragma unroll
-                for (int al = 0; al < 3; ++al) pr[q][al] = pr[q][al] + hk * fr[q][al];
-        }
-        const size_t s = (size_t)(n - a.n_in);
-        double d2 = 0.0, p2 = 0.0, fin = 0.0;
-#pragma unroll
-        for (int q = 0; q < kSweepAtomsPerThread; ++q) {
-            const int i = tid + q * kSweepThreads;
-            if (i >= N) continue;
-#pragma unroll
-            for (int al = 0; al < 3; ++al) {
-                double xq = xs[al * N + i], pq = pr[q][al];
-                if (a.mode == 1) {
-                    xq += a.jq[al * SN + s * N + i];
-                    pq += a.jp[al * SN + s * N + i];
-                    const double pv = a.q_prev[((size_t)(n + 1) * 3 + al) * N + i];
-                    d2 += (xq - pv) * (xq - pv);
-                    p2 += pv * pv;
-                }
-                fin += xq * 0.0 + pq * 0.0;
                 xs[al * N + i] = xq;
-                pr[q][al] = pq;
+                if (q == 0) pr[al] = pq;
+                else p1[al * NS] = pq;
                 a.q_cur[((size_t)(n + 1) * 3 + al) * N + i] = xq;
                 a.p_cur[((size_t)(n + 1) * 3 + al) * N + i] = pq;
             }
         }
-        const double sfin = block_sum(fin, red);
+        const double sfin = wg_sum(fin, red);
         if (!isfinite(sfin)) {
             bad = n;
             break;
         }
         if (a.mode == 1) {
-            const double sd = block_sum(d2, red), sp = block_sum(p2, red);
+            const double sd = wg_sum(d2, red), sp = wg_sum(p2, red);
             num += sqrt(sd);
             den += sqrt(sp);
             delta = den > 0.0 ? num / den : 0.0;
             if (delta > a.delta_expl) {
-                nfi_new = max(n, a.n_in + 1);
+                nfi_new = max(n, a.n_win + 1);
                 break;
             }
         }
@@ -530,8 +517,11 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
     if (overflow) a.out[3] = 1.0;
     if (tid == 0) {
         a.out[0] = delta;
-        a.out[1] = (double)nfi_new;
-        a.out[2] = (double)bad;
+        a.out[4] = num;
+        a.out[5] = den;
+        if (nfi_new >= 0) a.out[1] = (double)nfi_new;
+        if (bad >= 0) a.out[2] = (double)bad;
+        if (nfi_new >= 0 || bad >= 0) a.out[6] = 1.0;
     }
 }
 
@@ -570,7 +560,7 @@ __global__ void __launch_bounds__(1024) k_slab_end(int N, int mode, size_t SN, s
                                                    const double *__restrict__ qprev_next,
                                                    double *__restrict__ qcur_next, double *__restrict__ pcur_next,
                                                    double *__restrict__ part) {
-    __shared__ double red[kSweepThreads];
+    __shared__ double red[kSpillMax];
     double d2 = 0.0, p2 = 0.0, fin = 0.0;
     for (int i = threadIdx.x; i < N; i += kSweepThreads)
         for (int al = 0; al < 3; ++al) {
@@ -588,7 +578,7 @@ __global__ void __launch_bounds__(1024) k_slab_end(int N, int mode, size_t SN, s
             qcur_next[al * N + i] = xq;
             pcur_next[al * N + i] = pq;
         }
-    const double a = block_sum(d2, red), b = block_sum(p2, red), c = block_sum(fin, red);
+    const double a = wg_sum(d2, red), b = wg_sum(p2, red), c = wg_sum(fin, red);
     if (threadIdx.x == 0) {
         part[0] = a;
         part[1] = b;
@@ -637,6 +627,7 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     a.L = s.L;
     a.n_in = s.n_in;
     a.n_fi = s.n_fi;
+    a.n_win = s.n_win;
     a.mode = s.mode;
     a.delta_expl = s.delta_expl;
     a.q_cur = s.q_cur;
@@ -645,19 +636,8 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     a.p_prev = s.p_prev;
     a.jq = s.jq;
     a.jp = s.jp;
-    a.wx = s.wx;
-    a.wp = s.wp;
-    a.wf = s.wf;
-    a.wrho = s.wrho;
-    a.xref = s.xref;
-    a.nbr = s.nbr;
-    a.cnt = s.cnt;
     a.out = s.out;
-    if (sweep_fits_lds(s.N)) {
-        hipLaunchKernelGGL(k_coarse_sweep_lds, dim3(1), dim3(kSweepThreads), sweep_lds_bytes(s.N), st, a);
-    } else {
-        hipLaunchKernelGGL(k_coarse_sweep, dim3(1), dim3(kSweepThreads), 0, st, a);
-    }
+    hipLaunchKernelGGL(k_coarse_sweep_lds, dim3(1), dim3(kSweepThreads), sweep_lds_bytes(s.N), st, a);
 }
 
 void sweep_init_attributes() {

@@ -125,3 +125,51 @@ def test_nonfinite_state_is_reported(S):
     with pytest.raises(S.SnapmdError) as e:
         ctx.parareal_iterate(None, None, q, pp, box, L, 0, N, 1e100, **kw2)
     assert e.value.code == S.ENONFINITE and "slab 0" in str(e.value)
+
+
+def _bcc(n1, n2, n3, jitter, seed, dumbbell=False):
+    a = W.A_W
+    cells = np.array([[i, j, k] for i in range(n1) for j in range(n2) for k in range(n3)], dtype=np.float64)
+    sites = ((cells[:, None, :] + np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]])[None]).reshape(-1, 3)) * a
+    if dumbbell:
+        u = a * np.sqrt(3.0) / 6.0 * np.ones(3) / np.sqrt(3.0)
+        sites = np.concatenate([sites[1:], (sites[0] + u)[None], (sites[0] - u)[None]])
+    box = np.array([n1 * a, n2 * a, n3 * a])
+    sites = np.mod(sites + np.random.default_rng(seed).normal(0.0, jitter, sites.shape), box)
+    return np.ascontiguousarray(sites.T), box
+
+
+# sizes around the workgroup of the coarse sweep: 1025 / 1040 atoms (atoms beyond 1024
+# shared by a wave), 1152 (a second round of threads, the largest LDS-resident size),
+# 1176 / 1188 (host-driven sweep)
+@pytest.mark.parametrize("cells,dumbbell", [((8, 8, 8), True), ((8, 5, 13), False), ((9, 8, 8), False),
+                                            ((7, 7, 12), False), ((9, 6, 11), False)])
+def test_sweep_sizes_match_oracle(S, cells, dumbbell):
+    x, box = _bcc(*cells, jitter=0.05, seed=3, dumbbell=dumbbell)
+    n = x.shape[1]
+    p = W.maxwell_momenta(n, 1000.0, seed=3)
+    J, N, L = 2, 2, 5
+    beta = W.snap_beta(J, seed=1, scale=2e-2)
+    kw = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=21, noise_id=2, fs=W.FS_W)
+    ctx = S.context()
+    q = torch.zeros((N + 1, 3, n), dtype=torch.float64, device="cuda")
+    pp, qp, ppv = torch.zeros_like(q), torch.zeros_like(q), torch.zeros_like(q)
+    q[0], pp[0] = dev(x), dev(p)
+    print("sweep size case", cells, n, flush=True)
+    ctx.parareal_iterate(None, None, q, pp, box, L, 0, N, 1e100, **kw)
+    snap = dict(J=J, beta=beta, rcut=W.SNAP_RCUT, rfac0=W.SNAP_RFAC0, rmin0=0.0)
+    prop = OPR.Propagators(box=box, L=L, dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=21, noise_id=2,
+                           snap=snap, fs=W.FS_W)
+    ref = [(x, p)]
+    for m in range(N):
+        ref.append(prop.C(ref[-1], m))
+    qh, ph = q.cpu().numpy(), pp.cpu().numpy()
+    for m in range(N + 1):
+        assert np.abs(qh[m] - ref[m][0]).max() < QTOL, m
+        assert np.abs(ph[m] - ref[m][1]).max() < QTOL * np.abs(ref[m][1]).max(), m
+    # one corrected iteration: slab 1 becomes the fine propagation of slab 0
+    ctx.parareal_iterate(qp, ppv, q, pp, box, L, 0, N, 1e100, J=J, beta=beta, **kw)
+    xf, pf = dev(x), dev(p)
+    ctx.langevin_steps(S.POT_FS_SNAP, xf, pf, [0, n], box, L, step0=0, J=J, beta=beta, **kw)
+    scale = torch.max(torch.abs(xf)).item()
+    assert torch.max(torch.abs(q[1] - xf)).item() < 1e-12 * scale
