@@ -4,15 +4,17 @@
 One step = one corrected parareal iteration (parareal_iterate) on a window of 64 slabs
 of one 1025-atom tungsten trajectory (8x8x8 bcc + <111> dumbbell, 0.05 A jitter),
 SNAP twojmax 8 (55 coefficients) on top of Finnis-Sinclair, L = 100 BAOAB steps of
-1 fs per slab at 1000 K: the fine propagation of all 64 slabs batched in one launch
-sequence, the coarse propagation of the same slabs, the jumps, and the sequential
-corrected coarse sweep.  value = fine atom-steps per second of the whole iteration
-(64 * 1025 * 100 / seconds per iteration), inputs resident in HBM.
+1 fs per slab at 1000 K: the fine propagation of all 64 slabs (batched, in a few slab
+chunks), the coarse propagation of the same slabs, the jumps, and the sequential
+corrected coarse sweep (overlapped with the later chunks).  value = fine atom-steps per
+second of the whole iteration (64 * 1025 * 100 / seconds per iteration), inputs
+resident in HBM.
 
-Also reported: the fine batch alone, the same fine propagation run slab by slab
-(the per-slab form), the roofline of the dominant kernel (HIP events on the launch
-stream, algorithmic FLOPs from the operation counts of the design doc), and the CPU oracle
-timed on a bounded sample on the host's cores.
+Also reported: the roofline of the dominant kernel over the timed region (HIP events
+on the launch stream; algorithmic FLOPs from the operation counts of the SNAP passes,
+with the pair count of the initial state), the fine batch alone and the same fine
+propagation run slab by slab (the per-slab form), and the CPU oracle timed on a
+bounded sample on the host's cores.
 """
 import argparse
 import json
@@ -53,7 +55,7 @@ def snap_counts(J):
     return nUh, nZel, nZt
 
 
-def cpu_baseline(wl, J, nsteps=3):
+def cpu_baseline(wl, J, nsteps=40):
     from oracle import oracle as O
     from paper_2212_10508_amd import workloads as W
     x, p = wl["xs"][0], wl["ps"][0]
@@ -98,6 +100,9 @@ def main():
     ap.add_argument("--L", type=int, default=100)
     ap.add_argument("--per-slab-sample", type=int, default=4, help="slabs timed one by one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the fine-batch-alone and per-slab timings (then every SNAP launch of the "
+                         "process belongs to a parareal iteration, e.g. for a kernel-trace profile)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the propagator runs on a single GPU "
@@ -122,6 +127,13 @@ def main():
     q_cur[0] = torch.tensor(x0, device=dev)
     p_cur[0] = torch.tensor(p0, device=dev)
     kw_c = {k: v for k, v in kw.items() if k not in ("J", "beta")}
+    # pairs within the SNAP cutoff of the initial 64-slab batch (density pass only)
+    Xb0 = torch.tensor(np.tile(x0, (1, S_slabs)), device=dev)
+    off = np.arange(S_slabs + 1, dtype=np.int32) * n
+    boxes = np.tile(box, (S_slabs, 1))
+    ctx.bispectrum(Xb0, off, boxes, J, beta)
+    n_pairs = ctx.pair_count()
+    del Xb0
     log("init: coarse sweep over %d slabs" % S_slabs)
     ctx.parareal_iterate(None, None, q_cur, p_cur, box, L, 0, S_slabs, 1e300, **kw_c)
     q_start, p_start = q_cur.clone(), p_cur.clone()
@@ -151,44 +163,48 @@ def main():
     fine_atom_steps = S_slabs * n * L
     value = fine_atom_steps / t_it
 
-    # fine batch alone and the per-slab form (same kernels, one slab per call)
-    Xb = q_start[:S_slabs].permute(1, 0, 2).reshape(3, S_slabs * n).contiguous()
-    Pb = p_start[:S_slabs].permute(1, 0, 2).reshape(3, S_slabs * n).contiguous()
-    off = np.arange(S_slabs + 1, dtype=np.int32) * n
-    boxes = np.tile(box, (S_slabs, 1))
-    step0 = np.arange(S_slabs) * L
-    xb, pb = Xb.clone(), Pb.clone()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.langevin_steps(S.POT_FS_SNAP, xb, pb, off, boxes, L, step0=step0, **{k: v for k, v in kw.items()})
-    torch.cuda.synchronize()
-    t_fine = time.perf_counter() - t0
-    ctx.snap_forces(Xb, off, boxes, J, beta)
-    n_pairs = ctx.pair_count()
-    ns = min(args.per_slab_sample, S_slabs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    xs, ps = q_start[0].clone(), p_start[0].clone()
-    for s in range(ns):
-        xs.copy_(q_start[s])
-        ps.copy_(p_start[s])
-        ctx.langevin_steps(S.POT_FS_SNAP, xs, ps, [0, n], box, L, step0=s * L, **kw)
-    torch.cuda.synchronize()
-    t_slab = (time.perf_counter() - t0) / ns
-
-    # roofline of the dominant SNAP kernel (algorithmic FP64 FLOPs per launch / avg duration)
+    # roofline of the dominant SNAP kernel: algorithmic FP64 FLOPs of the timed region
+    # (every slab's pairs / atoms once per force evaluation, L + 1 evaluations per slab and
+    # iteration, whatever the chunking) over the kernel's summed launch time
     nUh, nZel, nZt = snap_counts(J)
     atoms = S_slabs * n
-    flops = {"dedr": 136.0 * nUh * n_pairs, "adjoint": (8.0 * nZt + 4.0 * nZel) * atoms,
-             "density": 22.0 * nUh * n_pairs}
+    evals = args.steps * (L + 1)
+    flops = {"dedr": 136.0 * nUh * n_pairs * evals, "adjoint": (8.0 * nZt + 4.0 * nZel) * atoms * evals,
+             "density": 22.0 * nUh * n_pairs * evals}
     kname = {"dedr": "k_dedr<8> (SNAP dE/dr, adjoint contraction)",
              "adjoint": "k_adjoint_lds<8> (SNAP adjoint Y)", "density": "k_density<8> (SNAP density u)"}
     dom = max(("dedr", "adjoint", "density"), key=lambda k: prof[k][0])
-    avg_ms = prof[dom][0] / max(prof[dom][1], 1)
-    achieved = flops[dom] / (avg_ms * 1e-3) / 1e12
     kernels = {k: {"avg_ms": prof[k][0] / max(prof[k][1], 1), "launches": prof[k][1],
-                   "tflops": (flops[k] / (prof[k][0] / max(prof[k][1], 1) * 1e-3) / 1e12) if k in flops else None}
+                   "gflop_per_launch": (flops[k] / max(prof[k][1], 1) / 1e9) if k in flops else None,
+                   "tflops": (flops[k] / (prof[k][0] * 1e-3) / 1e12) if k in flops else None}
                for k in prof}
+    achieved = kernels[dom]["tflops"]
+
+    extras = {}
+    if not args.no_extras:
+        # fine batch alone and the per-slab form (same kernels, one slab per call)
+        Xb = q_start[:S_slabs].permute(1, 0, 2).reshape(3, S_slabs * n).contiguous()
+        Pb = p_start[:S_slabs].permute(1, 0, 2).reshape(3, S_slabs * n).contiguous()
+        step0 = np.arange(S_slabs) * L
+        xb, pb = Xb.clone(), Pb.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.langevin_steps(S.POT_FS_SNAP, xb, pb, off, boxes, L, step0=step0, **kw)
+        torch.cuda.synchronize()
+        t_fine = time.perf_counter() - t0
+        ns = min(args.per_slab_sample, S_slabs)
+        xs, ps = q_start[0].clone(), p_start[0].clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(ns):
+            xs.copy_(q_start[s])
+            ps.copy_(p_start[s])
+            ctx.langevin_steps(S.POT_FS_SNAP, xs, ps, [0, n], box, L, step0=s * L, **kw)
+        torch.cuda.synchronize()
+        t_slab = (time.perf_counter() - t0) / ns
+        extras = {"fine_batch_atom_steps_per_s": fine_atom_steps / t_fine,
+                  "per_slab_atom_steps_per_s": n * L / t_slab,
+                  "batched_vs_per_slab": (fine_atom_steps / t_fine) / (n * L / t_slab)}
 
     out = {
         "metric": "SNAP+Langevin atom-steps/s, all slabs batched vs per-slab, FP64 @1e-10 force tol",
@@ -208,12 +224,11 @@ def main():
                    "atoms": n, "slabs": S_slabs, "L": L, "twojmax": J, "pairs": n_pairs,
                    "mean_neighbours": n_pairs / atoms},
         "roofline": {"bound": "alu", "kernel": kname[dom], "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None},
-        "fine_batch_atom_steps_per_s": fine_atom_steps / t_fine,
-        "per_slab_atom_steps_per_s": n * L / t_slab,
-        "batched_vs_per_slab": (fine_atom_steps / t_fine) / (n * L / t_slab),
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "avg_launch_ms": kernels[dom]["avg_ms"], "gflop_per_launch": kernels[dom]["gflop_per_launch"]},
         "kernels": kernels,
     }
+    out.update(extras)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(W.slabs_1025(n_slabs=1, seed=1, J=J), J)

@@ -188,7 +188,7 @@ int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_bat
 /* Launch mode of langevin_steps and of the fine and coarse propagation of
  * parareal_iterate.  enable = 1 (the default): the n_steps launch sequence is captured
  * once into a hipGraph, cached per context (keyed by sizes, parameters and device
- * pointers; at most 16 kept, least recently used dropped; every cached graph is dropped
+ * pointers; at most 32 kept, least recently used dropped; every cached graph is dropped
  * when the context reallocates a work buffer) and replayed on the caller's stream.
  * enable = 0: kernels are launched one by one.  Results are identical either way.
  * While snapmd_profile is on, SNAP propagation is launched one by one. */
