@@ -163,6 +163,7 @@ int ensure_atoms(snapmd_ctx *ctx, size_t N) {
     if ((rc = dalloc(ctx, &w.rev, w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.rho, cap))) return rc;
     if ((rc = dalloc(ctx, &w.geo, 20 * w.Pcap))) return rc;
+    if ((rc = dalloc(ctx, &w.ell, 5 * w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.dedr, 3 * w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.u, (size_t)n_half(kMaxJ) * cap))) return rc;
     if ((rc = dalloc(ctx, &w.ytil, (size_t)n_half(kMaxJ) * cap))) return rc;
@@ -727,6 +728,17 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     sw.n_fi = *n_fi;
     sw.mode = init ? 0 : 1;
     sw.n_win = n_in;
+    {
+        // cell grid of the sweep's list build: edges >= list radius, >= 3 cells per edge,
+        // at most 512 cells (else every pair is examined)
+        int nc[3];
+        for (int a = 0; a < 3; ++a) nc[a] = (int)std::floor(box[a] / (std::max(fp.d, fp.c) + skin));
+        while ((long)nc[0] * nc[1] * nc[2] > 512) *std::max_element(nc, nc + 3) -= 1;
+        if (nc[0] < 3 || nc[1] < 3 || nc[2] < 3) nc[0] = nc[1] = nc[2] = 0;
+        sw.ncx = nc[0];
+        sw.ncy = nc[1];
+        sw.ncz = nc[2];
+    }
     sw.delta_expl = delta_expl;
     sw.q_cur = q_cur;
     sw.p_cur = p_cur;

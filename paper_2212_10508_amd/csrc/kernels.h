@@ -76,6 +76,7 @@ struct Work {
     double *xref = nullptr; // [3][N] positions at the last build
     double *rho = nullptr;
     double *geo = nullptr;  // [20][Pcap]
+    double *ell = nullptr;  // [5][kMaxNeigh][N] a, b, f_c by (list slot, atom)
     double *dedr = nullptr; // [3][Pcap]
     double2 *u = nullptr, *ytil = nullptr;  // [nh][N]
 };
@@ -126,6 +127,7 @@ struct SweepLaunch {
     double dt, c1, mass, sig;
     uint64_t seed, noise_id;
     int L, n_in, n_fi, mode, n_win;
+    int ncx, ncy, ncz;  // cell grid of the sweep's list build (0: all pairs)
     double delta_expl;
     double *q_cur, *p_cur;
     const double *q_prev, *p_prev, *jq, *jp;

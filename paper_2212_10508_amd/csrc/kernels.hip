@@ -6,8 +6,8 @@
 //                CSR) -> k_reverse (index of the opposite pair)
 //   FS EAM     : k_fs_rho -> k_fs_force (deterministic gather over the full list)
 //   SNAP       : k_pair_geo (Cayley-Klein parameters, switching function and their
-//                gradients, once per pair) -> k_density<J,C> (u, one column chain of
-//                the Wigner-D polynomials per lane) -> k_adjoint (Y by the coupling
+//                gradients, once per pair; a, b, f_c also by list slot) -> k_density<J>
+//                (u, lane = atom, one column chain of the Wigner-D polynomials per wave) -> k_adjoint (Y by the coupling
 //                program, energy by Euler's identity) -> k_dedr<J> (per pair
 //                dE_i/dr_ij = Re sum conj(Y~) d(f_c P)) -> k_gather (F_k = sum over
 //                pairs (g_kj - g_jk), no atomics, deterministic)
@@ -300,7 +300,7 @@ __global__ void k_fs_force(int N, int n_sys, const int *__restrict__ off, const 
 __global__ void k_pair_geo(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
                            const double *__restrict__ x, const int *__restrict__ poff,
                            const int *__restrict__ pair_i, const int *__restrict__ pair_j, SnapGeoParams sp,
-                           double *__restrict__ geo, size_t Pcap) {
+                           double *__restrict__ geo, size_t Pcap, double *__restrict__ ell) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= poff[N]) return;
     const int i = pair_i[p], j = pair_j[p];
@@ -341,6 +341,11 @@ __global__ void k_pair_geo(int N, int n_sys, const int *__restrict__ off, const 
     }
 #pragma unroll
     for (int q = 0; q < 20; ++q) geo[q * Pcap + p] = g[q];
+    // a, b, f_c again in slot-major layout ell[f][t][i] (t = rank of the pair in i's
+    // list) for the density pass, where lane = atom reads slot t of 64 atoms at once
+    const size_t t = (size_t)(p - poff[i]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) ell[((size_t)q * kMaxNeigh + t) * N + i] = g[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -416,47 +421,34 @@ __device__ __forceinline__ void staircase(double2 (&P)[J + 1], double2 b, double
     }
 }
 
-// u (half storage, [e][N] double2) for column C: one wave per tile of 64 atoms
-// (lane = atom).  The tile's pairs are contiguous in the CSR list; their a, b and f_c
-// are staged in LDS in chunks of kDensityChunk pairs with coalesced loads, and every
-// lane then walks its own atom's pairs from LDS.
-constexpr int kDensityChunk = 512;
-
+// u (half storage, [e][N] double2) for column C: one wave per tile of 64 atoms, lane =
+// atom.  Step t reads slot t of the 64 atoms' lists from the slot-major copy of a, b
+// and f_c (one coalesced load per field); slots past an atom's count add nothing.
 template <int J, int C>
-__device__ void density_tile(int N, const int *__restrict__ poff, const double *__restrict__ geo, size_t Pcap,
-                             const double *__restrict__ nrm, double2 *__restrict__ u, double *__restrict__ sg) {
-    const int lane = threadIdx.x;
-    const int a0 = blockIdx.x * 64;
-    const int i = a0 + lane;
+__device__ void density_lane(int N, const int *__restrict__ poff, const double *__restrict__ ell,
+                             const double *__restrict__ nrm, double2 *__restrict__ u) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
     constexpr int NA = chain_acc_idx(C, J + 1, 0);
     double2 acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = make_double2(0.0, 0.0);
-    const int P0 = poff[a0], P1 = poff[min(a0 + 64, N)];
-    const int pb = i < N ? poff[i] : 0, pe = i < N ? poff[i + 1] : 0;
-    for (int c0 = P0; c0 < P1; c0 += kDensityChunk) {
-        const int c1 = min(c0 + kDensityChunk, P1);
-        __syncthreads();
-        for (int q = lane; q < c1 - c0; q += 64) {
-            sg[q] = geo[c0 + q];
-            sg[kDensityChunk + q] = geo[Pcap + c0 + q];
-            sg[2 * kDensityChunk + q] = geo[2 * Pcap + c0 + q];
-            sg[3 * kDensityChunk + q] = geo[3 * Pcap + c0 + q];
-            sg[4 * kDensityChunk + q] = geo[4 * Pcap + c0 + q];
-        }
-        __syncthreads();
-        const int qe = min(pe, c1) - c0;
-        for (int q = max(pb, c0) - c0; q < qe; ++q) {
-            const double fc = sg[4 * kDensityChunk + q];
-            if (fc == 0.0) continue;
-            const double2 a = make_double2(sg[q], sg[kDensityChunk + q]);
-            const double2 b = make_double2(sg[2 * kDensityChunk + q], sg[3 * kDensityChunk + q]);
-            const double2 ab = cconj(a);
-            double2 P[J + 1];
-            P[0] = make_double2(1.0, 0.0);
-            staircase<J, C, 0>(P, b, ab);
-            density_step<J, C, 2 * C>(P, acc, b, ab, fc);
-        }
+    const int cnt = i < N ? poff[i + 1] - poff[i] : 0;
+    int tmax = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tmax = max(tmax, __shfl_xor(tmax, o, 64));
+    const size_t sN = (size_t)kMaxNeigh * N;
+    for (int t = 0; t < tmax; ++t) {
+        const bool v = t < cnt;
+        const size_t q = (size_t)t * N + (v ? i : 0);
+        // past the count: the identity rotation with zero weight (slot contents unused)
+        const double2 a = v ? make_double2(ell[q], ell[sN + q]) : make_double2(1.0, 0.0);
+        const double2 b = v ? make_double2(ell[2 * sN + q], ell[3 * sN + q]) : make_double2(0.0, 0.0);
+        const double fc = v ? ell[4 * sN + q] : 0.0;
+        const double2 ab = cconj(a);
+        double2 P[J + 1];
+        P[0] = make_double2(1.0, 0.0);
+        staircase<J, C, 0>(P, b, ab);
+        density_step<J, C, 2 * C>(P, acc, b, ab, fc);
     }
     if (i >= N) return;
 #pragma unroll
@@ -471,16 +463,14 @@ __device__ void density_tile(int N, const int *__restrict__ poff, const double *
 }
 
 template <int J>
-__global__ void __launch_bounds__(64) k_density(int N, const int *__restrict__ poff, const double *__restrict__ geo,
-                                                size_t Pcap, const double *__restrict__ nrm,
-                                                double2 *__restrict__ u) {
-    __shared__ double sg[5 * kDensityChunk];
+__global__ void __launch_bounds__(64) k_density(int N, const int *__restrict__ poff, const double *__restrict__ ell,
+                                                const double *__restrict__ nrm, double2 *__restrict__ u) {
     switch (blockIdx.y) {
-        case 0: density_tile<J, 0>(N, poff, geo, Pcap, nrm, u, sg); break;
-        case 1: if constexpr (J >= 2) density_tile<J, 1>(N, poff, geo, Pcap, nrm, u, sg); break;
-        case 2: if constexpr (J >= 4) density_tile<J, 2>(N, poff, geo, Pcap, nrm, u, sg); break;
-        case 3: if constexpr (J >= 6) density_tile<J, 3>(N, poff, geo, Pcap, nrm, u, sg); break;
-        case 4: if constexpr (J >= 8) density_tile<J, 4>(N, poff, geo, Pcap, nrm, u, sg); break;
+        case 0: density_lane<J, 0>(N, poff, ell, nrm, u); break;
+        case 1: if constexpr (J >= 2) density_lane<J, 1>(N, poff, ell, nrm, u); break;
+        case 2: if constexpr (J >= 4) density_lane<J, 2>(N, poff, ell, nrm, u); break;
+        case 3: if constexpr (J >= 6) density_lane<J, 3>(N, poff, ell, nrm, u); break;
+        case 4: if constexpr (J >= 8) density_lane<J, 4>(N, poff, ell, nrm, u); break;
         default: break;
     }
 }
@@ -772,10 +762,9 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     KernelProf dummy;
     KernelProf &pf = prof ? *prof : dummy;
     hipLaunchKernelGGL(k_pair_geo, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
-                       w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
+                       w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap, w.ell);
     pf.begin(PROF_DENSITY, st);
-    hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 64), J / 2 + 1), dim3(64), 0, st, N, w.poff, w.geo, w.Pcap,
-                       sd.nrm, w.u);
+    hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 64), J / 2 + 1), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u);
     pf.end(st);
     pf.begin(PROF_ADJOINT, st);
     launch_adjoint(J, sd.adj, N, w.u, sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate, st);
@@ -802,12 +791,12 @@ void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, 
 void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st) {
     const int N = bd.N;
     hipLaunchKernelGGL(k_pair_geo, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
-                       w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
+                       w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap, w.ell);
     switch (J) {
-        case 2: hipLaunchKernelGGL(k_density<2>, dim3(nblk(N, 64), 2), dim3(64), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
-        case 4: hipLaunchKernelGGL(k_density<4>, dim3(nblk(N, 64), 3), dim3(64), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
-        case 6: hipLaunchKernelGGL(k_density<6>, dim3(nblk(N, 64), 4), dim3(64), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
-        case 8: hipLaunchKernelGGL(k_density<8>, dim3(nblk(N, 64), 5), dim3(64), 0, st, N, w.poff, w.geo, w.Pcap, sd.nrm, w.u); break;
+        case 2: hipLaunchKernelGGL(k_density<2>, dim3(nblk(N, 64), 2), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u); break;
+        case 4: hipLaunchKernelGGL(k_density<4>, dim3(nblk(N, 64), 3), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u); break;
+        case 6: hipLaunchKernelGGL(k_density<6>, dim3(nblk(N, 64), 4), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u); break;
+        case 8: hipLaunchKernelGGL(k_density<8>, dim3(nblk(N, 64), 5), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u); break;
         default: break;
     }
 }

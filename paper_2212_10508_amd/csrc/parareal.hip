@@ -51,6 +51,7 @@ struct SweepArgs {
     uint64_t seed, noise_id;
     int L, n_in, n_fi, mode;  // slabs n_in .. n_fi-1; mode 0: initialise (no jumps), 1: corrected
     int n_win;                // first slab of the window (the early stop keeps at least n_win + 1)
+    int ncx, ncy, ncz;        // cell grid of the list build (edges >= list radius), 0: all pairs
     double delta_expl;
     double *q_cur, *p_cur;                 // [slot][3][N]
     const double *q_prev, *p_prev;         // [slot][3][N] (mode 1)
@@ -101,13 +102,38 @@ constexpr int kSweepLdsNeigh = 48;
 constexpr int kSweepNbRows = kSweepLdsNeigh + 3;  // a thread's list is padded to a multiple of 4
 constexpr int kSweepLdsMaxAtoms = 2048;
 constexpr int kSpillMax = kSweepThreads / 64;
+constexpr int kSweepMaxCells = 512;
 
 // positions, F'(rho), list, the momenta / forces / reference positions of the atoms
-// beyond the first 1024 (their owners keep them in LDS), reduction partials
+// beyond the first 1024 (their owners keep them in LDS), reduction partials, cell grid
+// (counts / fill pointers, starts, atoms by cell, cell of each atom)
 size_t sweep_lds_bytes(int N) {
     const size_t NS = N > kSweepThreads ? (size_t)(N - kSweepThreads) : 0;
     return (size_t)N * (3 * sizeof(double) + sizeof(double) + kSweepNbRows * sizeof(uint16_t)) +
-           NS * 9 * sizeof(double) + kSpillMax * sizeof(double);
+           NS * 9 * sizeof(double) + kSpillMax * sizeof(double) + (2 * kSweepMaxCells + 1) * sizeof(int) +
+           (size_t)N * 2 * sizeof(uint16_t) + 8;
+}
+
+struct SwCells {
+    int *cnt, *start;             // [kSweepMaxCells], [kSweepMaxCells + 1]
+    uint16_t *atom, *cid;         // [N] atoms by cell (ascending in each cell), cell of each atom
+};
+
+__device__ __forceinline__ int swl_cell_index(double v, double iL, int n) {
+    double f = v * iL;
+    f -= floor(f);
+    const int c = (int)(f * n);
+    return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+__device__ __forceinline__ int swl_cell_of(const SweepArgs &a, double x, double y, double z) {
+    return (swl_cell_index(x, a.iLx, a.ncx) * a.ncy + swl_cell_index(y, a.iLy, a.ncy)) * a.ncz +
+           swl_cell_index(z, a.iLz, a.ncz);
+}
+// cell cc of the 27-cell stencil (o = 0..26) around cell c (periodic)
+__device__ __forceinline__ int swl_stencil(const SweepArgs &a, int c, int o) {
+    const int cz = c % a.ncz, cy = (c / a.ncz) % a.ncy, cx = c / (a.ncz * a.ncy);
+    const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
+    return (((cx + ox + a.ncx) % a.ncx) * a.ncy + (cy + oy + a.ncy) % a.ncy) * a.ncz + (cz + oz + a.ncz) % a.ncz;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -160,14 +186,29 @@ __device__ __forceinline__ bool swl_pair(const SweepArgs &a, const double *__res
 
 // list of atom i by one thread (j ascending); returns the count (capped, overflow flagged)
 __device__ __forceinline__ int swl_build_thread(const SweepArgs &a, const double *__restrict__ xs,
-                                                uint16_t *__restrict__ nb, int i, double rcl2, int &overflow) {
+                                                uint16_t *__restrict__ nb, const SwCells &cl, int i, double rcl2,
+                                                int &overflow) {
     const int N = a.N;
     const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
     int c = 0;
-    for (int j = 0; j < N; ++j) {
-        if (j != i && swl_pair(a, xs, N, j, xi, yi, zi, rcl2)) {
-            if (c < kSweepLdsNeigh) nb[c * N + i] = (uint16_t)j;
-            ++c;
+    if (a.ncx > 0) {  // the 27 cells around i's cell, atoms of a cell in ascending order
+        const int ci = cl.cid[i];
+        for (int o = 0; o < 27; ++o) {
+            const int cc = swl_stencil(a, ci, o);
+            for (int q = cl.start[cc]; q < cl.start[cc + 1]; ++q) {
+                const int j = cl.atom[q];
+                if (j != i && swl_pair(a, xs, N, j, xi, yi, zi, rcl2)) {
+                    if (c < kSweepLdsNeigh) nb[c * N + i] = (uint16_t)j;
+                    ++c;
+                }
+            }
+        }
+    } else {
+        for (int j = 0; j < N; ++j) {
+            if (j != i && swl_pair(a, xs, N, j, xi, yi, zi, rcl2)) {
+                if (c < kSweepLdsNeigh) nb[c * N + i] = (uint16_t)j;
+                ++c;
+            }
         }
     }
     if (c > kSweepLdsNeigh) {
@@ -183,18 +224,30 @@ __device__ __forceinline__ int swl_build_thread(const SweepArgs &a, const double
 
 // list of atom i by a whole wave (lanes scan 64 j at a time, ballot compaction keeps j ascending)
 __device__ __forceinline__ int swl_build_wave(const SweepArgs &a, const double *__restrict__ xs,
-                                              uint16_t *__restrict__ nb, int i, double rcl2, int &overflow) {
+                                              uint16_t *__restrict__ nb, const SwCells &cl, int i, double rcl2,
+                                              int &overflow) {
     const int N = a.N, lane = threadIdx.x & 63;
     const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
     const uint64_t below = (1ull << lane) - 1ull;
     int c = 0;
-    for (int base = 0; base < N; base += 64) {
-        const int j = base + lane;
-        const int hit = (j < N && j != i) ? (int)swl_pair(a, xs, N, j, xi, yi, zi, rcl2) : 0;
-        const uint64_t m = __ballot(hit);
-        const int pos = c + __popcll(m & below);
-        if (hit && pos < kSweepLdsNeigh) nb[pos * N + i] = (uint16_t)j;
-        c += __popcll(m);
+    // candidates in the order of the thread build: stencil cells, ascending in each
+    const int no = a.ncx > 0 ? 27 : 1;
+    for (int o = 0; o < no; ++o) {
+        int q0 = 0, q1 = N;
+        if (a.ncx > 0) {
+            const int cc = swl_stencil(a, cl.cid[i], o);
+            q0 = cl.start[cc];
+            q1 = cl.start[cc + 1];
+        }
+        for (int base = q0; base < q1; base += 64) {
+            const int q = base + lane;
+            const int j = q < q1 ? (a.ncx > 0 ? (int)cl.atom[q] : q) : i;
+            const int hit = (j != i) ? (int)swl_pair(a, xs, N, j, xi, yi, zi, rcl2) : 0;
+            const uint64_t m = __ballot(hit);
+            const int pos = c + __popcll(m & below);
+            if (hit && pos < kSweepLdsNeigh) nb[pos * N + i] = (uint16_t)j;
+            c += __popcll(m);
+        }
     }
     if (c > kSweepLdsNeigh) {
         overflow = 1;
@@ -338,6 +391,11 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
     double *dfe = xs + 3 * N;                              // [N]  F'(rho)
     double *s1 = dfe + N;                                  // [9][NS] p, f, reference x of atoms >= 1024
     uint16_t *nb = reinterpret_cast<uint16_t *>(s1 + 9 * NS);  // [kSweepNbRows][N]
+    SwCells cl;
+    cl.cnt = reinterpret_cast<int *>(nb + (size_t)kSweepNbRows * N + ((kSweepNbRows * N) & 1));
+    cl.start = cl.cnt + kSweepMaxCells;
+    cl.atom = reinterpret_cast<uint16_t *>(cl.start + kSweepMaxCells + 1);
+    cl.cid = cl.atom + N;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // second slot: the spill atom of this wave (lane 0 owns it) or atom tid + 1024
     const bool spill = NS > 0 && NS <= kSpillMax;
@@ -371,17 +429,80 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
     // thread-owned atoms of this thread: tid, and i1 outside the spill mode (one inlined
     // copy of the per-thread passes, looped over the two slots)
     const int nslot = (!spill && own1) ? 2 : 1;
+    const int NC = a.ncx * a.ncy * a.ncz;
     auto build = [&]() {
+        if (NC > 0) {
+            // cell grid: counts, starts (wave 0), fill, ascending order inside each cell
+            for (int c = tid; c < NC; c += kSweepThreads) cl.cnt[c] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int i = q ? i1 : tid;
+                if (i < N) {
+                    const int c = swl_cell_of(a, xs[i], xs[N + i], xs[2 * N + i]);
+                    cl.cid[i] = (uint16_t)c;
+                    atomicAdd(&cl.cnt[c], 1);
+                }
+            }
+            __syncthreads();
+            if (tid < 64) {
+                constexpr int per = kSweepMaxCells / 64;
+                int loc[per], sum = 0;
+#pragma unroll
+                for (int k = 0; k < per; ++k) {
+                    const int c = tid * per + k;
+                    loc[k] = c < NC ? cl.cnt[c] : 0;
+                    sum += loc[k];
+                }
+                int incl = sum;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int v = __shfl_up(incl, o, 64);
+                    if (tid >= o) incl += v;
+                }
+                int run = incl - sum;
+#pragma unroll
+                for (int k = 0; k < per; ++k) {
+                    const int c = tid * per + k;
+                    if (c < NC) {
+                        cl.start[c] = run;
+                        cl.cnt[c] = run;  // fill pointer
+                    }
+                    run += loc[k];
+                }
+                if (tid == 63) cl.start[NC] = incl;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int i = q ? i1 : tid;
+                if (i < N) cl.atom[atomicAdd(&cl.cnt[cl.cid[i]], 1)] = (uint16_t)i;
+            }
+            __syncthreads();
+            for (int c = tid; c < NC; c += kSweepThreads) {
+                const int b = cl.start[c], e = cl.start[c + 1];
+                for (int q = b + 1; q < e; ++q) {
+                    const uint16_t v = cl.atom[q];
+                    int r = q - 1;
+                    while (r >= b && cl.atom[r] > v) {
+                        cl.atom[r + 1] = cl.atom[r];
+                        --r;
+                    }
+                    cl.atom[r + 1] = v;
+                }
+            }
+            __syncthreads();
+        }
 #pragma unroll 1
         for (int q = 0; q < nslot; ++q) {
             const int i = q ? i1 : tid;
             if (i < N) {
-                const int c = swl_build_thread(a, xs, nb, i, rcl2, overflow);
+                const int c = swl_build_thread(a, xs, nb, cl, i, rcl2, overflow);
                 if (q) cn1 = c;
                 else cn0 = c;
             }
         }
-        if (has_s) cn1 = swl_build_wave(a, xs, nb, is, rcl2, overflow);
+        if (has_s) cn1 = swl_build_wave(a, xs, nb, cl, is, rcl2, overflow);
 #pragma unroll
         for (int al = 0; al < 3; ++al) {
             if (own0) xr[al] = xs[al * N + tid];
@@ -628,6 +749,9 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     a.n_in = s.n_in;
     a.n_fi = s.n_fi;
     a.n_win = s.n_win;
+    a.ncx = s.ncx;
+    a.ncy = s.ncy;
+    a.ncz = s.ncz;
     a.mode = s.mode;
     a.delta_expl = s.delta_expl;
     a.q_cur = s.q_cur;
