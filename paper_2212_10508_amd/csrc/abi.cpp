@@ -65,6 +65,9 @@ struct snapmd_ctx {
     // parareal buffers
     DBuf<double> pr_xf, pr_pf, pr_xc, pr_pc;     // [3][S*N] fine / coarse copies of prev slabs
     DBuf<double> sw_x, sw_p, sw_out;
+    DBuf<double> sw_gx, sw_gdfe, sw_gpart;        // multi-workgroup sweep exchange buffers
+    DBuf<unsigned long long> sw_bar;
+    DBuf<int> sw_abort;
     double *h_out = nullptr;                      // pinned [16]: sweep results [0, 8), sweep init [8, 16)
     DBuf<double> sw_noise;                        // Gaussians of the current window
     DBuf<double> gB;                              // [K][N] bispectrum / its variation
@@ -752,7 +755,32 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         std::memcpy(h0, init_out, sizeof init_out);
         HIPCHK(hipMemcpyAsync(ctx->sw_out.p, h0, 8 * sizeof(double), hipMemcpyHostToDevice, st));
     }
-    const bool lds_sweep = sweep_fits_lds(N);
+    // the sweep on the device: several workgroups exchanging through device memory, or
+    // one LDS-resident workgroup; else driven from the host
+    const int mcK = sweep_mc_workgroups(N);
+    const bool lds_sweep = mcK > 0 || sweep_fits_lds(N);
+    if (mcK > 0) {
+        sw.K = mcK;
+        sw.A = (N + mcK - 1) / mcK;
+        if ((rc = ensure(ctx, ctx->sw_gx, 6 * (size_t)N)) || (rc = ensure(ctx, ctx->sw_gdfe, 2 * (size_t)N)) ||
+            (rc = ensure(ctx, ctx->sw_gpart, 8 * (size_t)mcK)) || (rc = ensure(ctx, ctx->sw_bar, 1)) ||
+            (rc = ensure(ctx, ctx->sw_abort, 1)))
+            return rc;
+        sw.gx = ctx->sw_gx.p;
+        sw.gdfe = ctx->sw_gdfe.p;
+        sw.gpart = ctx->sw_gpart.p;
+        sw.bar = ctx->sw_bar.p;
+        sw.abort = ctx->sw_abort.p;
+    }
+    // barrier counters start from zero at every launch of the multi-workgroup sweep
+    auto sweep_launch = [&](const SweepLaunch &l, hipStream_t s) -> int {
+        if (l.K > 0) {
+            HIPCHK(hipMemsetAsync(l.bar, 0, sizeof(unsigned long long), s));
+            HIPCHK(hipMemsetAsync(l.abort, 0, sizeof(int), s));
+        }
+        launch_coarse_sweep(l, s);
+        return check_launch(ctx);
+    };
     if (!init) {
         // prev_n := cur_n on [n_in, n_fi]
         const size_t slot = 3 * (size_t)N;
@@ -844,8 +872,7 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
                 sc.jq = ctx->pr_xf.p + o;
                 sc.jp = ctx->pr_pf.p + o;
                 sc.noise = sw.noise + (size_t)s0 * L * 3 * N;
-                launch_coarse_sweep(sc, s2);
-                if ((rc = check_launch(ctx))) return rc;
+                if ((rc = sweep_launch(sc, s2))) return rc;
             }
         }
         HIPCHK(hipEventRecord(ctx->pipe_ev[kPipeChunks], s2));
@@ -855,8 +882,7 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     } else if (lds_sweep) {
         if ((rc = launch_noise_sweep(ctx, n_in, S, L, N, lang, st))) return rc;
         sw.noise = ctx->sw_noise.p;
-        launch_coarse_sweep(sw, st);
-        if ((rc = check_launch(ctx))) return rc;
+        if ((rc = sweep_launch(sw, st))) return rc;
     }
     if (lds_sweep) {
         HIPCHK(hipMemcpyAsync(ctx->h_out, ctx->sw_out.p, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -864,6 +890,8 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         if (ctx->h_out[3] != 0.0)
             return fail(ctx, SNAPMD_EOVERFLOW, "an atom of the coarse sweep has more than its list capacity of "
                                                "neighbours");
+        if (ctx->h_out[7] != 0.0)
+            return fail(ctx, SNAPMD_EHIP, "the workgroups of the coarse sweep did not meet at a barrier in time");
         if (ctx->h_out[2] >= 0.0)
             return fail(ctx, SNAPMD_ENONFINITE, "state became non-finite in slab %d", (int)ctx->h_out[2]);
         *delta_out = ctx->h_out[0];

@@ -128,6 +128,10 @@ struct SweepLaunch {
     uint64_t seed, noise_id;
     int L, n_in, n_fi, mode, n_win;
     int ncx, ncy, ncz;  // cell grid of the sweep's list build (0: all pairs)
+    int K, A;           // multi-workgroup sweep: K workgroups of A atoms (K = 0: one workgroup)
+    double *gx, *gdfe, *gpart;
+    unsigned long long *bar;
+    int *abort;
     double delta_expl;
     double *q_cur, *p_cur;
     const double *q_prev, *p_prev, *jq, *jp;
@@ -139,6 +143,7 @@ void launch_jumps(size_t n, double *a, const double *b, hipStream_t st);
 void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st);
 void sweep_init_attributes();
 bool sweep_fits_lds(int N);
+int sweep_mc_workgroups(int N);
 void launch_slab_end(int N, int mode, size_t SN, size_t s, double *xs, double *ps, const double *jq, const double *jp,
                      const double *qprev_next, double *qcur_next, double *pcur_next, double *part, hipStream_t st);
 void launch_noise_table(int S, int L, int N, int n_in, uint64_t seed, uint64_t noise_id, double *noise,

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "device_util.h"
 #include "kernels.h"
 #include "snapmd_internal.h"
@@ -52,6 +54,14 @@ struct SweepArgs {
     int L, n_in, n_fi, mode;  // slabs n_in .. n_fi-1; mode 0: initialise (no jumps), 1: corrected
     int n_win;                // first slab of the window (the early stop keeps at least n_win + 1)
     int ncx, ncy, ncz;        // cell grid of the list build (edges >= list radius), 0: all pairs
+    // multi-workgroup sweep: K workgroups own A consecutive atoms each and exchange
+    // positions and F'(rho) every step through device memory
+    int K, A;
+    double *gx;                   // [2][3][N] positions by step parity
+    double *gdfe;                 // [2][N] F'(rho) by step parity
+    double *gpart;                // [2][K][4] per-workgroup partials by parity
+    unsigned long long *bar;      // barrier arrivals (zero at launch)
+    int *abort;                   // set when a barrier wait runs out (zero at launch)
     double delta_expl;
     double *q_cur, *p_cur;                 // [slot][3][N]
     const double *q_prev, *p_prev;         // [slot][3][N] (mode 1)
@@ -185,9 +195,10 @@ __device__ __forceinline__ bool swl_pair(const SweepArgs &a, const double *__res
 }
 
 // list of atom i by one thread (j ascending); returns the count (capped, overflow flagged)
+// (list entries of atom i: col[t * ns], t = 0, 1, ..)
 __device__ __forceinline__ int swl_build_thread(const SweepArgs &a, const double *__restrict__ xs,
-                                                uint16_t *__restrict__ nb, const SwCells &cl, int i, double rcl2,
-                                                int &overflow) {
+                                                uint16_t *__restrict__ col, int ns, const SwCells &cl, int i,
+                                                double rcl2, int &overflow) {
     const int N = a.N;
     const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
     int c = 0;
@@ -198,7 +209,7 @@ __device__ __forceinline__ int swl_build_thread(const SweepArgs &a, const double
             for (int q = cl.start[cc]; q < cl.start[cc + 1]; ++q) {
                 const int j = cl.atom[q];
                 if (j != i && swl_pair(a, xs, N, j, xi, yi, zi, rcl2)) {
-                    if (c < kSweepLdsNeigh) nb[c * N + i] = (uint16_t)j;
+                    if (c < kSweepLdsNeigh) col[c * ns] = (uint16_t)j;
                     ++c;
                 }
             }
@@ -206,7 +217,7 @@ __device__ __forceinline__ int swl_build_thread(const SweepArgs &a, const double
     } else {
         for (int j = 0; j < N; ++j) {
             if (j != i && swl_pair(a, xs, N, j, xi, yi, zi, rcl2)) {
-                if (c < kSweepLdsNeigh) nb[c * N + i] = (uint16_t)j;
+                if (c < kSweepLdsNeigh) col[c * ns] = (uint16_t)j;
                 ++c;
             }
         }
@@ -216,16 +227,16 @@ __device__ __forceinline__ int swl_build_thread(const SweepArgs &a, const double
         c = kSweepLdsNeigh;
     }
     // rows c .. c+2 repeat the last entry (read, never counted, by the unrolled passes)
-    const uint16_t last = c > 0 ? nb[(c - 1) * N + i] : (uint16_t)i;
+    const uint16_t last = c > 0 ? col[(c - 1) * ns] : (uint16_t)i;
 #pragma unroll
-    for (int t = 0; t < 3; ++t) nb[(c + t) * N + i] = last;
+    for (int t = 0; t < 3; ++t) col[(c + t) * ns] = last;
     return c;
 }
 
 // list of atom i by a whole wave (lanes scan 64 j at a time, ballot compaction keeps j ascending)
 __device__ __forceinline__ int swl_build_wave(const SweepArgs &a, const double *__restrict__ xs,
-                                              uint16_t *__restrict__ nb, const SwCells &cl, int i, double rcl2,
-                                              int &overflow) {
+                                              uint16_t *__restrict__ col, int ns, const SwCells &cl, int i,
+                                              double rcl2, int &overflow) {
     const int N = a.N, lane = threadIdx.x & 63;
     const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
     const uint64_t below = (1ull << lane) - 1ull;
@@ -245,7 +256,7 @@ __device__ __forceinline__ int swl_build_wave(const SweepArgs &a, const double *
             const int hit = (j != i) ? (int)swl_pair(a, xs, N, j, xi, yi, zi, rcl2) : 0;
             const uint64_t m = __ballot(hit);
             const int pos = c + __popcll(m & below);
-            if (hit && pos < kSweepLdsNeigh) nb[pos * N + i] = (uint16_t)j;
+            if (hit && pos < kSweepLdsNeigh) col[pos * ns] = (uint16_t)j;
             c += __popcll(m);
         }
     }
@@ -261,8 +272,8 @@ __device__ __forceinline__ int swl_build_wave(const SweepArgs &a, const double *
 // The unrolled body is branch-free (entries past the count repeat the last one and
 // add nothing) so that the LDS reads of four neighbours are in flight together.
 __device__ __forceinline__ uint64_t swl_rho_thread(const SweepArgs &a, const double *__restrict__ xs,
-                                                   double *__restrict__ dfe, const uint16_t *__restrict__ nb, int i,
-                                                   int c) {
+                                                   double *__restrict__ dfe, const uint16_t *__restrict__ col, int ns,
+                                                   int i, int c) {
     const int N = a.N;
     const FsParams fp = a.fp;
     const double d2c = fp.d * fp.d, rc2f = fmax(fp.d, fp.c) * fmax(fp.d, fp.c);
@@ -272,7 +283,7 @@ __device__ __forceinline__ uint64_t swl_rho_thread(const SweepArgs &a, const dou
     for (int t0 = 0; t0 < c; t0 += 4) {
         int e[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) e[u] = (int)nb[__umul24(t0 + u, N) + i];
+        for (int u = 0; u < 4; ++u) e[u] = (int)col[__umul24(t0 + u, ns)];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const bool valid = t0 + u < c;
@@ -298,8 +309,8 @@ __device__ __forceinline__ double swl_w(const FsParams &fp, double r, double ir,
 
 // force pass of atom i by one thread over the masked entries (branch-free groups of 4)
 __device__ __forceinline__ void swl_force_thread(const SweepArgs &a, const double *__restrict__ xs,
-                                                 const double *__restrict__ dfe, const uint16_t *__restrict__ nb,
-                                                 int i, uint64_t m, double (&f)[3]) {
+                                                 const double *__restrict__ dfe, const uint16_t *__restrict__ col,
+                                                 int ns, int i, uint64_t m, double (&f)[3]) {
     const int N = a.N;
     const FsParams fp = a.fp;
     const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
@@ -314,7 +325,7 @@ __device__ __forceinline__ void swl_force_thread(const SweepArgs &a, const doubl
             v[u] = m != 0;
             t = v[u] ? __builtin_ctzll(m) : t;
             m &= m - 1ull;
-            e[u] = (int)nb[__umul24(t, N) + i];
+            e[u] = (int)col[__umul24(t, ns)];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -336,8 +347,8 @@ __device__ __forceinline__ void swl_force_thread(const SweepArgs &a, const doubl
 
 // rho pass of atom i by a whole wave (lane t takes entry t, c <= 64); returns the mask
 __device__ __forceinline__ uint64_t swl_rho_wave(const SweepArgs &a, const double *__restrict__ xs,
-                                                 double *__restrict__ dfe, const uint16_t *__restrict__ nb, int i,
-                                                 int c) {
+                                                 double *__restrict__ dfe, const uint16_t *__restrict__ col, int ns,
+                                                 int i, int c) {
     const int N = a.N, lane = threadIdx.x & 63;
     const FsParams fp = a.fp;
     const double d2c = fp.d * fp.d, rc2f = fmax(fp.d, fp.c) * fmax(fp.d, fp.c);
@@ -345,7 +356,7 @@ __device__ __forceinline__ uint64_t swl_rho_wave(const SweepArgs &a, const doubl
     int in = 0;
     if (lane < c) {
         double dx, dy, dz;
-        swl_sep(a, xs, N, (int)nb[lane * N + i], xs[i], xs[N + i], xs[2 * N + i], dx, dy, dz);
+        swl_sep(a, xs, N, (int)col[lane * ns], xs[i], xs[N + i], xs[2 * N + i], dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
         in = r2 < rc2f;
         if (r2 < d2c) {
@@ -361,13 +372,13 @@ __device__ __forceinline__ uint64_t swl_rho_wave(const SweepArgs &a, const doubl
 
 // force pass of atom i by a whole wave; every lane receives the force
 __device__ __forceinline__ void swl_force_wave(const SweepArgs &a, const double *__restrict__ xs,
-                                               const double *__restrict__ dfe, const uint16_t *__restrict__ nb, int i,
-                                               uint64_t mk, double (&f)[3]) {
+                                               const double *__restrict__ dfe, const uint16_t *__restrict__ col,
+                                               int ns, int i, uint64_t mk, double (&f)[3]) {
     const int N = a.N, lane = threadIdx.x & 63;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if ((mk >> lane) & 1ull) {
         double dx, dy, dz;
-        const int j = (int)nb[lane * N + i];
+        const int j = (int)col[lane * ns];
         swl_sep(a, xs, N, j, xs[i], xs[N + i], xs[2 * N + i], dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
         const double ir = rsqrt_nr(r2), r = r2 * ir;
@@ -497,12 +508,12 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
         for (int q = 0; q < nslot; ++q) {
             const int i = q ? i1 : tid;
             if (i < N) {
-                const int c = swl_build_thread(a, xs, nb, cl, i, rcl2, overflow);
+                const int c = swl_build_thread(a, xs, nb + i, N, cl, i, rcl2, overflow);
                 if (q) cn1 = c;
                 else cn0 = c;
             }
         }
-        if (has_s) cn1 = swl_build_wave(a, xs, nb, cl, is, rcl2, overflow);
+        if (has_s) cn1 = swl_build_wave(a, xs, nb + is, N, cl, is, rcl2, overflow);
 #pragma unroll
         for (int al = 0; al < 3; ++al) {
             if (own0) xr[al] = xs[al * N + tid];
@@ -515,19 +526,19 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
         for (int q = 0; q < nslot; ++q) {
             const int i = q ? i1 : tid;
             if (i < N) {
-                const uint64_t m = swl_rho_thread(a, xs, dfe, nb, i, q ? cn1 : cn0);
+                const uint64_t m = swl_rho_thread(a, xs, dfe, nb + i, N, i, q ? cn1 : cn0);
                 if (q) mk1 = m;
                 else mk0 = m;
             }
         }
-        if (has_s) mk1 = swl_rho_wave(a, xs, dfe, nb, is, cn1);
+        if (has_s) mk1 = swl_rho_wave(a, xs, dfe, nb + is, N, is, cn1);
         __syncthreads();
 #pragma unroll 1
         for (int q = 0; q < nslot; ++q) {
             const int i = q ? i1 : tid;
             if (i < N) {
                 double g[3];
-                swl_force_thread(a, xs, dfe, nb, i, q ? mk1 : mk0, g);
+                swl_force_thread(a, xs, dfe, nb + i, N, i, q ? mk1 : mk0, g);
 #pragma unroll
                 for (int al = 0; al < 3; ++al) {
                     if (q) f1[al * NS] = g[al];
@@ -537,7 +548,7 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
         }
         if (has_s) {
             double g[3];
-            swl_force_wave(a, xs, dfe, nb, is, mk1, g);
+            swl_force_wave(a, xs, dfe, nb + is, N, is, mk1, g);
             if (own1)
 #pragma unroll
                 for (int al = 0; al < 3; ++al) f1[al * NS] = g[al];
@@ -646,6 +657,288 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Multi-workgroup sweep: the same propagation with the atoms split over K workgroups
+// (one CU each, all on one chiplet: only workgroups with blockIdx % 8 == 0 work).  Every
+// step each workgroup publishes its atoms' positions, waits at a grid barrier, copies all
+// positions into LDS, does the rho pass for its atoms, publishes F'(rho), waits again and
+// does the force pass.  Shared data goes through device-scope loads and stores; the
+// barrier is an arrival counter with a bounded wait (a wait that runs out sets `abort`
+// and every workgroup leaves).  Per-workgroup partial sums are combined in a fixed
+// order, so every workgroup takes the same decisions.
+// ---------------------------------------------------------------------------
+constexpr int kMcSpin = 1 << 22;
+
+__device__ __forceinline__ void st_dev(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// grid barrier number b (0, 1, ..): returns false when the wait ran out or another
+// workgroup gave up
+__device__ __forceinline__ bool mc_barrier(const SweepArgs &a, unsigned long long b, int *flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(a.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long target = (unsigned long long)a.K * (b + 1);
+        int ok = 1;
+        for (int spin = 0;; ++spin) {
+            if (__hip_atomic_load(a.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || spin >= kMcSpin) {
+                __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *flag = ok;
+    }
+    __syncthreads();
+    return *flag != 0;
+}
+
+__global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
+    if (blockIdx.x % 8 != 0) return;
+    extern __shared__ double sm[];
+    if (a.out[6] != 0.0) return;  // an earlier launch of the window stopped early
+    const int N = a.N, K = a.K, A = a.A;
+    const int w = blockIdx.x / 8, a0 = w * A, na = min(N, a0 + A) - a0;
+    const int tid = threadIdx.x;
+    const bool own = tid < na;
+    const int i = a0 + tid;
+    double *xs = sm;                                       // [3][N]
+    double *dfe = xs + 3 * N;                              // [N]
+    int *flag = reinterpret_cast<int *>(dfe + N);          // [2]
+    uint16_t *nb = reinterpret_cast<uint16_t *>(flag + 2); // [kSweepNbRows][A]
+    SwCells cl;
+    cl.cnt = reinterpret_cast<int *>(nb + (size_t)kSweepNbRows * A + ((kSweepNbRows * A) & 1));
+    cl.start = cl.cnt + kSweepMaxCells;
+    cl.atom = reinterpret_cast<uint16_t *>(cl.start + kSweepMaxCells + 1);
+    cl.cid = cl.atom + N;
+    uint16_t *col = nb + tid;
+    const int NC = a.ncx * a.ncy * a.ncz;
+    const double rcl = fmax(a.fp.d, a.fp.c) + a.skin, rcl2 = rcl * rcl;
+    const size_t SN = (size_t)(a.n_fi - a.n_in) * N;
+    const double hk = 0.5 * a.dt / SW_MVV2E, hd = 0.5 * a.dt / a.mass;
+    double pr[3] = {0.0, 0.0, 0.0}, fr[3] = {0.0, 0.0, 0.0}, xr[3] = {0.0, 0.0, 0.0}, xo[3] = {0.0, 0.0, 0.0};
+    int cn = 0, overflow = 0, bad = -1, nfi_new = -1;
+    uint64_t mk = 0;
+    if (own)
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+            xo[al] = a.q_cur[((size_t)a.n_in * 3 + al) * N + i];
+            pr[al] = a.p_cur[((size_t)a.n_in * 3 + al) * N + i];
+        }
+    double num = a.out[4], den = a.out[5], delta = a.out[0];
+    unsigned long long b = 0;
+    int par = 0;
+    bool built = false, alive = true;
+    // exchange: publish own positions (and partials), barrier, gather all positions
+    auto exchange_x = [&](double p0, double p1, double p2, double p3) -> bool {
+        if (own)
+#pragma unroll
+            for (int al = 0; al < 3; ++al) st_dev(a.gx + ((size_t)par * 3 + al) * N + i, xo[al]);
+        if (tid == 0) {
+            double *gp = a.gpart + ((size_t)par * K + w) * 4;
+            st_dev(gp, p0);
+            st_dev(gp + 1, p1);
+            st_dev(gp + 2, p2);
+            st_dev(gp + 3, p3);
+        }
+        if (!mc_barrier(a, b++, flag)) return false;
+        for (int q = tid; q < 3 * N; q += blockDim.x) xs[q] = ld_dev(a.gx + (size_t)par * 3 * N + q);
+        return true;
+    };
+    auto partial = [&](int k) {  // sum over workgroups (fixed order) of partial k
+        double s = 0.0;
+        for (int v = 0; v < K; ++v) s += ld_dev(a.gpart + ((size_t)par * K + v) * 4 + k);
+        return s;
+    };
+    for (int n = a.n_in; n < a.n_fi && alive; ++n) {
+        for (int l = -1; l < a.L; ++l) {
+            const double *gz = a.noise + ((size_t)((n - a.n_in) * a.L + max(l, 0)) * 3) * N;
+            double d2m = 0.0;
+            if (own) {
+#pragma unroll
+                for (int al = 0; al < 3; ++al) {
+                    if (l >= 0) {
+                        double pp = pr[al] + hk * fr[al];
+                        double xx = xo[al] + hd * pp;
+                        pp = a.c1 * pp + a.sig * gz[al * N + i];
+                        xx = xx + hd * pp;
+                        pr[al] = pp;
+                        xo[al] = xx;
+                    }
+                    d2m += (xo[al] - xr[al]) * (xo[al] - xr[al]);
+                }
+            }
+            const double m = wave_max(d2m);
+            double wmax = 0.0;
+            {
+                // workgroup max of the displacement (wave partials through dfe, free here)
+                if ((tid & 63) == 0) dfe[tid >> 6] = m;
+                __syncthreads();
+                for (int v = 0; v < (int)(blockDim.x >> 6); ++v) wmax = fmax(wmax, dfe[v]);
+            }
+            if (!exchange_x(wmax, 0.0, 0.0, 0.0)) { alive = false; break; }
+            double gmax = 0.0;
+            for (int v = 0; v < K; ++v) gmax = fmax(gmax, ld_dev(a.gpart + ((size_t)par * K + v) * 4));
+            __syncthreads();  // xs complete
+            if (!built || !(4.0 * gmax <= a.skin * a.skin)) {
+                if (NC > 0) {
+                    for (int c = tid; c < NC; c += blockDim.x) cl.cnt[c] = 0;
+                    __syncthreads();
+                    for (int q = tid; q < N; q += blockDim.x) {
+                        const int c = swl_cell_of(a, xs[q], xs[N + q], xs[2 * N + q]);
+                        cl.cid[q] = (uint16_t)c;
+                        atomicAdd(&cl.cnt[c], 1);
+                    }
+                    __syncthreads();
+                    if (tid < 64) {
+                        constexpr int per = kSweepMaxCells / 64;
+                        int loc[per], sum = 0;
+#pragma unroll
+                        for (int k = 0; k < per; ++k) {
+                            const int c = tid * per + k;
+                            loc[k] = c < NC ? cl.cnt[c] : 0;
+                            sum += loc[k];
+                        }
+                        int incl = sum;
+#pragma unroll
+                        for (int o = 1; o < 64; o <<= 1) {
+                            const int v = __shfl_up(incl, o, 64);
+                            if (tid >= o) incl += v;
+                        }
+                        int run = incl - sum;
+#pragma unroll
+                        for (int k = 0; k < per; ++k) {
+                            const int c = tid * per + k;
+                            if (c < NC) {
+                                cl.start[c] = run;
+                                cl.cnt[c] = run;
+                            }
+                            run += loc[k];
+                        }
+                        if (tid == 63) cl.start[NC] = incl;
+                    }
+                    __syncthreads();
+                    for (int q = tid; q < N; q += blockDim.x) cl.atom[atomicAdd(&cl.cnt[cl.cid[q]], 1)] = (uint16_t)q;
+                    __syncthreads();
+                    for (int c = tid; c < NC; c += blockDim.x) {
+                        const int bb = cl.start[c], e = cl.start[c + 1];
+                        for (int q = bb + 1; q < e; ++q) {
+                            const uint16_t v = cl.atom[q];
+                            int r = q - 1;
+                            while (r >= bb && cl.atom[r] > v) {
+                                cl.atom[r + 1] = cl.atom[r];
+                                --r;
+                            }
+                            cl.atom[r + 1] = v;
+                        }
+                    }
+                    __syncthreads();
+                }
+                if (own) {
+                    cn = swl_build_thread(a, xs, col, A, cl, i, rcl2, overflow);
+#pragma unroll
+                    for (int al = 0; al < 3; ++al) xr[al] = xo[al];
+                }
+                built = true;
+                __syncthreads();
+            }
+            if (own) mk = swl_rho_thread(a, xs, dfe, col, A, i, cn);
+            if (own) st_dev(a.gdfe + (size_t)par * N + i, dfe[i]);
+            if (!mc_barrier(a, b++, flag)) { alive = false; break; }
+            for (int q = tid; q < N; q += blockDim.x) dfe[q] = ld_dev(a.gdfe + (size_t)par * N + q);
+            __syncthreads();
+            if (own) swl_force_thread(a, xs, dfe, col, A, i, mk, fr);
+            if (l >= 0)
+#pragma unroll
+                for (int al = 0; al < 3; ++al) pr[al] = pr[al] + hk * fr[al];
+            par ^= 1;
+            __syncthreads();  // xs / dfe reads done before the next step overwrites them
+        }
+        if (!alive) break;
+        // slab end: cur_{n+1} = C(cur_n) (+ J_n) for own atoms; partial sums exchanged
+        const size_t s = (size_t)(n - a.n_in);
+        double d2 = 0.0, p2 = 0.0, fin = 0.0;
+        if (own)
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                double xq = xo[al], pq = pr[al];
+                if (a.mode == 1) {
+                    xq += a.jq[al * SN + s * N + i];
+                    pq += a.jp[al * SN + s * N + i];
+                    const double pv = a.q_prev[((size_t)(n + 1) * 3 + al) * N + i];
+                    d2 += (xq - pv) * (xq - pv);
+                    p2 += pv * pv;
+                }
+                fin += xq * 0.0 + pq * 0.0;  // NaN/Inf propagate into fin
+                xo[al] = xq;
+                pr[al] = pq;
+                a.q_cur[((size_t)(n + 1) * 3 + al) * N + i] = xq;
+                a.p_cur[((size_t)(n + 1) * 3 + al) * N + i] = pq;
+            }
+        {
+            const double v0 = wave_sum(d2), v1 = wave_sum(p2), v2 = wave_sum(fin);
+            if ((tid & 63) == 0) {
+                dfe[3 * (tid >> 6)] = v0;
+                dfe[3 * (tid >> 6) + 1] = v1;
+                dfe[3 * (tid >> 6) + 2] = v2;
+            }
+            __syncthreads();
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int v = 0; v < (int)(blockDim.x >> 6); ++v) {
+                s0 += dfe[3 * v];
+                s1 += dfe[3 * v + 1];
+                s2 += dfe[3 * v + 2];
+            }
+            if (tid == 0) {
+                double *gp = a.gpart + ((size_t)par * K + w) * 4;
+                st_dev(gp + 1, s0);
+                st_dev(gp + 2, s1);
+                st_dev(gp + 3, s2);
+            }
+        }
+        if (!mc_barrier(a, b++, flag)) { alive = false; break; }
+        const double sfin = partial(3);
+        if (!isfinite(sfin)) {
+            bad = n;
+            break;
+        }
+        if (a.mode == 1) {
+            num += sqrt(partial(1));
+            den += sqrt(partial(2));
+            delta = den > 0.0 ? num / den : 0.0;
+            if (delta > a.delta_expl) {
+                nfi_new = max(n, a.n_win + 1);
+                break;
+            }
+        }
+        par ^= 1;
+        __syncthreads();
+    }
+    if (overflow) a.out[3] = 1.0;
+    if (w == 0 && tid == 0) {
+        if (!alive) a.out[7] = 1.0;
+        a.out[0] = delta;
+        a.out[4] = num;
+        a.out[5] = den;
+        if (nfi_new >= 0) a.out[1] = (double)nfi_new;
+        if (bad >= 0) a.out[2] = (double)bad;
+        if (nfi_new >= 0 || bad >= 0 || !alive) a.out[6] = 1.0;
+    }
+}
+
+size_t sweep_mc_lds_bytes(int N, int A) {
+    return (size_t)N * 4 * sizeof(double) + 2 * sizeof(int) + (size_t)kSweepNbRows * A * sizeof(uint16_t) + 4 +
+           (2 * kSweepMaxCells + 1) * sizeof(int) + (size_t)N * 2 * sizeof(uint16_t) + 8;
+}
+
 // Gaussians of every (slab, step, atom) of a window: noise[s][l][al][i] for global step
 // (n_in + s) L + l, drawn exactly as the batched propagators draw them.
 __global__ void k_noise_table(int S, int L, int N, int n_in, uint64_t seed, uint64_t noise_id,
@@ -715,6 +1008,15 @@ void launch_slab_end(int N, int mode, size_t SN, size_t s, double *xs, double *p
 
 bool sweep_fits_lds(int N) { return N <= kSweepLdsMaxAtoms && sweep_lds_bytes(N) <= 160 * 1024; }
 
+// workgroups of the multi-workgroup sweep for N atoms (0: not used)
+int sweep_mc_workgroups(int N) {
+    constexpr int K = 8;
+    if (N < 512) return 0;
+    const int A = (N + K - 1) / K;
+    if (A > 512 || N > 65535 || sweep_mc_lds_bytes(N, A) > 160 * 1024) return 0;
+    return K;
+}
+
 // ---------------------------------------------------------------------------
 void launch_slabs_to_batch(int S, int N, const double *slots, double *out, hipStream_t st) {
     const size_t tot = (size_t)3 * S * N;
@@ -752,6 +1054,13 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     a.ncx = s.ncx;
     a.ncy = s.ncy;
     a.ncz = s.ncz;
+    a.K = s.K;
+    a.A = s.A;
+    a.gx = s.gx;
+    a.gdfe = s.gdfe;
+    a.gpart = s.gpart;
+    a.bar = s.bar;
+    a.abort = s.abort;
     a.mode = s.mode;
     a.delta_expl = s.delta_expl;
     a.q_cur = s.q_cur;
@@ -761,11 +1070,20 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     a.jq = s.jq;
     a.jp = s.jp;
     a.out = s.out;
-    hipLaunchKernelGGL(k_coarse_sweep_lds, dim3(1), dim3(kSweepThreads), sweep_lds_bytes(s.N), st, a);
+    if (s.K > 0) {
+        // at least 81 KB of LDS so that no two of the workgroups share a CU
+        const size_t lds = std::max<size_t>(sweep_mc_lds_bytes(s.N, s.A), 81 * 1024);
+        const int T = (s.A + 63) / 64 * 64;
+        hipLaunchKernelGGL(k_coarse_sweep_mc, dim3(8 * s.K), dim3(T), lds, st, a);
+    } else {
+        hipLaunchKernelGGL(k_coarse_sweep_lds, dim3(1), dim3(kSweepThreads), sweep_lds_bytes(s.N), st, a);
+    }
 }
 
 void sweep_init_attributes() {
     (void)hipFuncSetAttribute((const void *)k_coarse_sweep_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_coarse_sweep_mc, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
 }
 

@@ -139,10 +139,11 @@ def _bcc(n1, n2, n3, jitter, seed, dumbbell=False):
     return np.ascontiguousarray(sites.T), box
 
 
-# sizes around the workgroup of the coarse sweep: 1025 / 1040 atoms (atoms beyond 1024
-# shared by a wave), 1078 (a second round of threads), 1152 / 1188 (host-driven sweep)
+# sizes of the three sweep forms: 1025 / 1040 / 1078 / 1152 / 1188 atoms (several
+# workgroups, uneven last share included), 3456 atoms (driven from the host); the
+# one-workgroup sweep is covered by the 129-atom tests above
 @pytest.mark.parametrize("cells,dumbbell", [((8, 8, 8), True), ((8, 5, 13), False), ((7, 7, 11), False),
-                                            ((9, 8, 8), False), ((9, 6, 11), False)])
+                                            ((9, 8, 8), False), ((9, 6, 11), False), ((12, 12, 12), False)])
 def test_sweep_sizes_match_oracle(S, cells, dumbbell):
     x, box = _bcc(*cells, jitter=0.05, seed=3, dumbbell=dumbbell)
     n = x.shape[1]
