@@ -46,6 +46,7 @@ struct SnapDevTables {
 
 struct snapmd_ctx {
     int device = 0;
+    int n_cus = 256;  // compute units of the device
     std::string err;
     // batch
     DBuf<int> d_off;
@@ -344,15 +345,35 @@ int check_launch(snapmd_ctx *ctx) {
 // Force of the chosen potential at x into f (overwrite), e_atom (nullable, overwrite).
 constexpr double kSkin = 0.3;       // Verlet skin of the batched path (A)
 constexpr double kSweepSkin = 0.5;  // Verlet skin of the LDS-resident coarse sweep (A)
-constexpr int kPipeChunks = 4;      // at most this many slab chunks per parareal iteration
 
-// Chunk sizes of a parareal iteration over S slabs: at most kPipeChunks chunks with
-// sizes in the ratio G : G-1 : ... : 1, so that the sweep starts early on a large first
-// chunk and the sweep left after the last propagation is short.
-std::vector<int> chunk_plan(int S) {
-    const int G = std::min(S, kPipeChunks);
+// Chunk sizes of a parareal iteration over S slabs of N atoms.  The SNAP adjoint runs
+// one 64-atom workgroup per CU at a time, so a chunk costs whole rounds: m_r = the most
+// slabs that fit r rounds, counting two CUs per chiplet as taken by the work running
+// beside the propagation (the sweep's workgroups).  Chunks of m_2 slabs, ending with two of m_1 and the
+// remainder, so that the sweep (which starts after the first chunk) keeps pace and the
+// part of it left after the last propagation is short.  Where that gives a single chunk,
+// sizes in the ratio 4 : 3 : 2 : 1 are used instead.
+std::vector<int> chunk_plan(int S, int N, int cus) {
+    const long per = (long)std::max(cus - 16, 8) * 64;
+    const int m1 = (int)std::max(1L, per / std::max(N, 1)), m2 = (int)std::max(1L, 2 * per / std::max(N, 1));
+    std::vector<int> sz;
+    int left = S;
+    if (left > 0) {
+        sz.push_back(std::min(left, m2));
+        left -= sz.back();
+    }
+    while (left > m2 + 2 * m1) {
+        sz.push_back(m2);
+        left -= m2;
+    }
+    while (left > 0) {
+        sz.push_back(std::min(left, m1));
+        left -= sz.back();
+    }
+    if (sz.size() > 1 || S < 2) return sz;
+    const int G = std::min(S, 4);
     const int W = G * (G + 1) / 2;
-    std::vector<int> sz(G);
+    sz.assign(G, 0);
     int used = 0;
     for (int c = 0; c < G; ++c) {
         sz[c] = std::max(1, S * (G - c) / W);
@@ -380,8 +401,8 @@ int prepare_cells(snapmd_ctx *ctx, Work &w, BatchDev &bd, double rl, hipStream_t
             int n3[3];
             for (int a = 0; a < 3; ++a) n3[a] = (int)std::floor(ctx->h_box[3 * s + a] / rl);
             const int natoms = ctx->h_off[s + 1] - ctx->h_off[s];
-            // cells pay off only for systems well above a few hundred atoms
-            if (n3[0] >= 3 && n3[1] >= 3 && n3[2] >= 3 && natoms >= 2000) {
+            // cells pay off for systems above a few hundred atoms
+            if (n3[0] >= 3 && n3[1] >= 3 && n3[2] >= 3 && natoms >= 500) {
                 ci[s] = make_int4(n3[0], n3[1], n3[2], C);
                 C += n3[0] * n3[1] * n3[2];
                 any = true;
@@ -563,6 +584,11 @@ int snapmd_create(snapmd_ctx **out, int hip_device) {
     if (hipSetDevice(hip_device) != hipSuccess) return SNAPMD_EHIP;
     snapmd_ctx *ctx = new snapmd_ctx();
     ctx->device = hip_device;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
+            ctx->n_cus = cus;
+    }
     adjoint_init_attributes();
     sweep_init_attributes();
     if (dalloc(ctx, &ctx->w.status, 1) != SNAPMD_OK || hipMemset(ctx->w.status, 0, sizeof(int)) != hipSuccess ||
@@ -814,9 +840,10 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         // chunks runs on the caller's stream; the Finnis-Sinclair propagation, the jumps
         // and (LDS-resident case) the sweep run on a second stream, the sweep over chunk c
         // as soon as the SNAP propagation of chunk c is done, overlapping the later chunks.
-        const std::vector<int> plan = lds_sweep ? chunk_plan(S) : std::vector<int>{S};
+        const std::vector<int> plan = lds_sweep ? chunk_plan(S, N, ctx->n_cus) : std::vector<int>{S};
         if (!ctx->sweep_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->sweep_stream, hipStreamNonBlocking));
-        for (int c = (int)ctx->pipe_ev.size(); c <= kPipeChunks + 1; ++c) {
+        const int ne = (int)plan.size();  // events: one per chunk, start, end
+        for (int c = (int)ctx->pipe_ev.size(); c < ne + 2; ++c) {
             hipEvent_t e;
             HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
             ctx->pipe_ev.push_back(e);
@@ -838,8 +865,8 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
             lc.noise_id += s0;
             return nc;
         };
-        HIPCHK(hipEventRecord(ctx->pipe_ev[kPipeChunks + 1], st));
-        HIPCHK(hipStreamWaitEvent(s2, ctx->pipe_ev[kPipeChunks + 1], 0));
+        HIPCHK(hipEventRecord(ctx->pipe_ev[ne + 1], st));
+        HIPCHK(hipStreamWaitEvent(s2, ctx->pipe_ev[ne + 1], 0));
         for (int c = 0, s0 = 0; c < (int)plan.size(); s0 += plan[c], ++c) {  // coarse (second stream)
             BatchDev bc;
             LangevinDev lc;
@@ -875,8 +902,8 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
                 if ((rc = sweep_launch(sc, s2))) return rc;
             }
         }
-        HIPCHK(hipEventRecord(ctx->pipe_ev[kPipeChunks], s2));
-        HIPCHK(hipStreamWaitEvent(st, ctx->pipe_ev[kPipeChunks], 0));
+        HIPCHK(hipEventRecord(ctx->pipe_ev[ne], s2));
+        HIPCHK(hipStreamWaitEvent(st, ctx->pipe_ev[ne], 0));
         sw.jq = ctx->pr_xf.p;
         sw.jp = ctx->pr_pf.p;
     } else if (lds_sweep) {

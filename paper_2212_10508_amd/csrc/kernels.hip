@@ -595,20 +595,16 @@ __device__ __forceinline__ void dedr_chain(double2 (&P)[J + 1], double2 (&dP)[3]
     if constexpr (2 * C + 2 <= J) dedr_chain<J, C + 1>(P, dP, sP, sdP, b, ab, db, dab, yt, Natoms, S0, S);
 }
 
+// One wave of 64 consecutive pairs (CSR order, so a few atoms i).  When the wave's
+// pairs belong to at most kDedrAtoms atoms, their Y~ rows are first copied into LDS
+// (coalesced: consecutive lanes take consecutive atoms of one element) and the chains
+// read Y~ from there; otherwise from global memory.
+constexpr int kDedrAtoms = 6;
+
 template <int J>
-__global__ void __launch_bounds__(64) k_dedr(int N, const int *__restrict__ poff, const int *__restrict__ pair_i,
-                                             const double *__restrict__ geo, size_t Pcap,
-                                             const double2 *__restrict__ ytil, double *__restrict__ dedr) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= poff[N]) return;
+__device__ __forceinline__ void dedr_pair(int p, size_t Pcap, const double *__restrict__ geo,
+                                          const double2 *__restrict__ yt, int ystride, double *__restrict__ dedr) {
     const double fc = geo[4 * Pcap + p];
-    if (fc == 0.0) {
-        dedr[p] = 0.0;
-        dedr[Pcap + p] = 0.0;
-        dedr[2 * Pcap + p] = 0.0;
-        return;
-    }
-    const int i = pair_i[p];
     const double2 a = make_double2(geo[p], geo[Pcap + p]);
     const double2 b = make_double2(geo[2 * Pcap + p], geo[3 * Pcap + p]);
     const double2 ab = cconj(a);
@@ -622,9 +618,40 @@ __global__ void __launch_bounds__(64) k_dedr(int N, const int *__restrict__ poff
     }
     double2 P[J + 1], dP[3][J + 1], sP[J + 1], sdP[3][J + 1];
     double S0 = 0.0, S[3] = {0.0, 0.0, 0.0};
-    dedr_chain<J, 0>(P, dP, sP, sdP, b, ab, db, dab, ytil + i, N, S0, S);
+    dedr_chain<J, 0>(P, dP, sP, sdP, b, ab, db, dab, yt, ystride, S0, S);
 #pragma unroll
     for (int al = 0; al < 3; ++al) dedr[al * Pcap + p] = fma(dfc[al], S0, fc * S[al]);
+}
+
+template <int J>
+__global__ void __launch_bounds__(64) k_dedr(int N, const int *__restrict__ poff, const int *__restrict__ pair_i,
+                                             const double *__restrict__ geo, size_t Pcap,
+                                             const double2 *__restrict__ ytil, double *__restrict__ dedr) {
+    constexpr int NH = n_half(J);
+    __shared__ double2 ys[kDedrAtoms * NH];
+    const int P = poff[N];
+    const int p0 = blockIdx.x * 64;
+    if (p0 >= P) return;
+    const int lane = threadIdx.x, p = p0 + lane;
+    const int i0 = pair_i[p0], na = pair_i[min(p0 + 63, P - 1)] - i0 + 1;
+    const bool live = p < P;
+    const int i = live ? pair_i[p] : i0;
+    const double fc = live ? geo[4 * Pcap + p] : 0.0;
+    if (na <= kDedrAtoms) {
+        for (int q = lane; q < na * NH; q += 64) {
+            const int e = q / na, at = q - e * na;
+            ys[q] = ytil[(size_t)e * N + i0 + at];
+        }
+        __syncthreads();
+        if (fc != 0.0) dedr_pair<J>(p, Pcap, geo, ys + (i - i0), na, dedr);
+    } else {
+        if (fc != 0.0) dedr_pair<J>(p, Pcap, geo, ytil + i, N, dedr);
+    }
+    if (live && fc == 0.0) {
+        dedr[p] = 0.0;
+        dedr[Pcap + p] = 0.0;
+        dedr[2 * Pcap + p] = 0.0;
+    }
 }
 
 // F_k (+)= sum_{p in pairs(k)} (g_p - g_rev(p))

@@ -659,12 +659,15 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
 
 // ---------------------------------------------------------------------------
 // Multi-workgroup sweep: the same propagation with the atoms split over K workgroups
-// (one CU each, all on one chiplet: only workgroups with blockIdx % 8 == 0 work).  Every
+// (one CU each; consecutive workgroups land on different chiplets, so the CUs taken from
+// the batched kernels running beside the sweep are spread evenly).  Every
 // step each workgroup publishes its atoms' positions, waits at a grid barrier, copies all
 // positions into LDS, does the rho pass for its atoms, publishes F'(rho), waits again and
-// does the force pass.  Shared data goes through device-scope loads and stores; the
-// barrier is an arrival counter with a bounded wait (a wait that runs out sets `abort`
-// and every workgroup leaves).  Per-workgroup partial sums are combined in a fixed
+// does the force pass.  Shared data are written and read with device-scope accesses
+// (coherent at the device level, so no cache-wide write-back or invalidation is
+// needed); each wave waits for its stores to complete before the workgroup arrives at
+// the barrier, an arrival counter whose wait is bounded (a wait that runs out sets
+// `abort` and every workgroup leaves).  Per-workgroup partial sums are combined in a fixed
 // order, so every workgroup takes the same decisions.
 // ---------------------------------------------------------------------------
 constexpr int kMcSpin = 1 << 22;
@@ -679,9 +682,9 @@ __device__ __forceinline__ double ld_dev(const double *p) {
 // grid barrier number b (0, 1, ..): returns false when the wait ran out or another
 // workgroup gave up
 __device__ __forceinline__ bool mc_barrier(const SweepArgs &a, unsigned long long b, int *flag) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's device-scope stores have completed
     __syncthreads();
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(a.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long target = (unsigned long long)a.K * (b + 1);
         int ok = 1;
@@ -694,19 +697,36 @@ __device__ __forceinline__ bool mc_barrier(const SweepArgs &a, unsigned long lon
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *flag = ok;
     }
     __syncthreads();
     return *flag != 0;
 }
 
+// global -> LDS copy of n doubles by the whole workgroup (device-scope loads, 8 per
+// thread in flight)
+__device__ __forceinline__ void mc_copy(double *__restrict__ dst, const double *__restrict__ src, int n) {
+    const int T = blockDim.x;
+    for (int base = threadIdx.x; base < n; base += 8 * T) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int q = base + k * T;
+            v[k] = q < n ? ld_dev(src + q) : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int q = base + k * T;
+            if (q < n) dst[q] = v[k];
+        }
+    }
+}
+
 __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
-    if (blockIdx.x % 8 != 0) return;
     extern __shared__ double sm[];
     if (a.out[6] != 0.0) return;  // an earlier launch of the window stopped early
     const int N = a.N, K = a.K, A = a.A;
-    const int w = blockIdx.x / 8, a0 = w * A, na = min(N, a0 + A) - a0;
+    const int w = blockIdx.x, a0 = w * A, na = min(N, a0 + A) - a0;
     const int tid = threadIdx.x;
     const bool own = tid < na;
     const int i = a0 + tid;
@@ -750,7 +770,7 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
             st_dev(gp + 3, p3);
         }
         if (!mc_barrier(a, b++, flag)) return false;
-        for (int q = tid; q < 3 * N; q += blockDim.x) xs[q] = ld_dev(a.gx + (size_t)par * 3 * N + q);
+        mc_copy(xs, a.gx + (size_t)par * 3 * N, 3 * N);
         return true;
     };
     auto partial = [&](int k) {  // sum over workgroups (fixed order) of partial k
@@ -853,7 +873,7 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
             if (own) mk = swl_rho_thread(a, xs, dfe, col, A, i, cn);
             if (own) st_dev(a.gdfe + (size_t)par * N + i, dfe[i]);
             if (!mc_barrier(a, b++, flag)) { alive = false; break; }
-            for (int q = tid; q < N; q += blockDim.x) dfe[q] = ld_dev(a.gdfe + (size_t)par * N + q);
+            mc_copy(dfe, a.gdfe + (size_t)par * N, N);
             __syncthreads();
             if (own) swl_force_thread(a, xs, dfe, col, A, i, mk, fr);
             if (l >= 0)
@@ -1074,7 +1094,7 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
         // at least 81 KB of LDS so that no two of the workgroups share a CU
         const size_t lds = std::max<size_t>(sweep_mc_lds_bytes(s.N, s.A), 81 * 1024);
         const int T = (s.A + 63) / 64 * 64;
-        hipLaunchKernelGGL(k_coarse_sweep_mc, dim3(8 * s.K), dim3(T), lds, st, a);
+        hipLaunchKernelGGL(k_coarse_sweep_mc, dim3(s.K), dim3(T), lds, st, a);
     } else {
         hipLaunchKernelGGL(k_coarse_sweep_lds, dim3(1), dim3(kSweepThreads), sweep_lds_bytes(s.N), st, a);
     }
