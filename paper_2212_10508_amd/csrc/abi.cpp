@@ -91,6 +91,8 @@ struct snapmd_ctx {
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
     hipStream_t sweep_stream = nullptr;  // the coarse sweep, overlapping the batched propagation
+    hipStream_t fork_st = nullptr;       // Finnis-Sinclair pass beside the SNAP chain
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<hipEvent_t> pipe_ev;
     uint64_t graph_clock = 0;
 };
@@ -432,35 +434,47 @@ int prepare_cells(snapmd_ctx *ctx, Work &w, BatchDev &bd, double rl, hipStream_t
 
 // launch_neighbors with the cell grids of the batch
 int neighbors(snapmd_ctx *ctx, Work &w, const BatchDev &bd0, const double *x, double rc, bool force,
-              hipStream_t st) {
+              hipStream_t st, bool in_step = false) {
     BatchDev bd = bd0;
     int r;
     if ((r = prepare_cells(ctx, w, bd, rc + kSkin, st))) return r;
-    launch_neighbors(bd, x, rc, w, st, force, kSkin);
+    // within a propagation step the displacement test ran in k_baoab_pre and k_fs_rho
+    // clears the rebuild flag
+    launch_neighbors(bd, x, rc, w, st, force, kSkin, in_step && !force, in_step);
     return SNAPMD_OK;
 }
 
+// Forces of a propagation step (e_atom not wanted).  For FS + SNAP the Finnis-Sinclair
+// pass runs on a second stream beside the SNAP chain, joined before the SNAP gather adds
+// into f.
 void enqueue_forces(snapmd_ctx *ctx, Work &w, int potential, const BatchDev &bd, const double *x,
-                    const FsParams *fp, const SnapDev *sd, double *f, double *e_atom, hipStream_t st,
-                    bool fresh = true) {
+                    const FsParams *fp, const SnapDev *sd, double *f, hipStream_t st, bool fresh = true) {
     double rc = 0.0;
     if (fp) rc = std::max(fp->d, fp->c);
     if (potential == SNAPMD_POT_FS_SNAP) rc = std::max(rc, sd->gp.rcut);
     ctx->prof.begin(PROF_NEIGH, st);
-    (void)neighbors(ctx, w, bd, x, rc, fresh, st);
+    (void)neighbors(ctx, w, bd, x, rc, fresh, st, true);
     ctx->prof.end(st);
-    launch_fs(bd, x, *fp, w, f, e_atom, 0, st);
-    if (potential == SNAPMD_POT_FS_SNAP) launch_snap(sd->J, bd, x, *sd, w, f, e_atom, 1, st, &ctx->prof);
+    if (potential == SNAPMD_POT_FS_SNAP && ctx->fork_st) {
+        (void)hipEventRecord(ctx->ev_fork, st);
+        (void)hipStreamWaitEvent(ctx->fork_st, ctx->ev_fork, 0);
+        launch_fs(bd, x, *fp, w, f, nullptr, 0, ctx->fork_st, true);
+        (void)hipEventRecord(ctx->ev_join, ctx->fork_st);
+        launch_snap(sd->J, bd, x, *sd, w, f, nullptr, 1, st, &ctx->prof, ctx->ev_join);
+    } else {
+        launch_fs(bd, x, *fp, w, f, nullptr, 0, st, true);
+        if (potential == SNAPMD_POT_FS_SNAP) launch_snap(sd->J, bd, x, *sd, w, f, nullptr, 1, st, &ctx->prof);
+    }
 }
 
 // n_steps BAOAB steps of the batch in place (force evaluated at the start), with the
 // workspace w and the force buffer f.
 void run_langevin(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
                   const SnapDev &sd, const LangevinDev &ld, int n_steps, double *x, double *p, hipStream_t st) {
-    enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, nullptr, st);
+    enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st);
     for (int s = 0; s < n_steps; ++s) {
-        launch_baoab_pre(bd, x, p, f, ld, s, st);
-        enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, nullptr, st, false);
+        launch_baoab_pre(bd, x, p, f, ld, s, w, kSkin, st);
+        enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st, false);
         launch_baoab_post(bd, p, f, ld.dt, st);
     }
 }
@@ -591,6 +605,12 @@ int snapmd_create(snapmd_ctx **out, int hip_device) {
     }
     adjoint_init_attributes();
     sweep_init_attributes();
+    if (hipStreamCreateWithFlags(&ctx->fork_st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+        snapmd_destroy(ctx);
+        return SNAPMD_EHIP;
+    }
     if (dalloc(ctx, &ctx->w.status, 1) != SNAPMD_OK || hipMemset(ctx->w.status, 0, sizeof(int)) != hipSuccess ||
         dalloc(ctx, &ctx->w.flag, 1) != SNAPMD_OK || hipMemset(ctx->w.flag, 0, sizeof(int)) != hipSuccess) {
         snapmd_destroy(ctx);
@@ -608,6 +628,9 @@ void snapmd_destroy(snapmd_ctx *ctx) {
     drop_graphs(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->sweep_stream) (void)hipStreamDestroy(ctx->sweep_stream);
+    if (ctx->fork_st) (void)hipStreamDestroy(ctx->fork_st);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     for (hipEvent_t e : ctx->pipe_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
     delete ctx;

@@ -149,12 +149,18 @@ void launch_slab_end(int N, int mode, size_t SN, size_t s, double *xs, double *p
 void launch_noise_table(int S, int L, int N, int n_in, uint64_t seed, uint64_t noise_id, double *noise,
                         hipStream_t st);
 
+// force: rebuild now; checked: the displacement test was done by k_baoab_pre (else a
+// check kernel runs); clear_in_fs: the rebuild flag is cleared by the next k_fs_rho
+// (launch_fs with clear_flag) instead of a kernel of its own
 void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, hipStream_t st, bool force,
-                      double skin);
+                      double skin, bool checked = false, bool clear_in_fs = false);
 void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w, double *f, double *e_atom,
-               int accumulate, hipStream_t st);
+               int accumulate, hipStream_t st, bool clear_flag = false);
+// join (nullable): an event the gather waits for (the Finnis-Sinclair force written into f
+// on another stream)
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
-                 double *e_atom, int accumulate, hipStream_t st, KernelProf *prof = nullptr);
+                 double *e_atom, int accumulate, hipStream_t st, KernelProf *prof = nullptr,
+                 hipEvent_t join = nullptr);
 void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st);
 void adjoint_tables(int J, const double *beta, AdjointHost &A);
 void adjoint_init_attributes();
@@ -168,7 +174,7 @@ void launch_bispectrum_jvp(int N, const SnapDev &sd, const double2 *u, const dou
 void launch_reduce_rows(int rows, int N, const double *in, double scale, double *out, hipStream_t st);
 void launch_set_value(double *p, double v, hipStream_t st);
 void launch_baoab_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
-                      hipStream_t st);
+                      const Work &w, double skin, hipStream_t st);
 void launch_baoab_post(const BatchDev &bd, double *p, const double *f, double dt, hipStream_t st);
 
 }  // namespace snapmd

@@ -225,8 +225,11 @@ __global__ void k_reverse(int N, const int *__restrict__ poff, const int *__rest
 // ---------------------------------------------------------------------------
 __global__ void k_fs_rho(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
                          const double *__restrict__ x, const int *__restrict__ poff,
-                         const int *__restrict__ pair_j, double d, double *__restrict__ rho) {
+                         const int *__restrict__ pair_j, double d, double *__restrict__ rho,
+                         int *__restrict__ clear_flag) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // the neighbour pipeline that read the rebuild flag has finished: clear it for the next step
+    if (clear_flag && i == 0) *clear_flag = 0;
     if (i >= N) return;
     const int s = sys_of(off, n_sys, i);
     const double Lx = box[3 * s], Ly = box[3 * s + 1], Lz = box[3 * s + 2];
@@ -708,8 +711,11 @@ __device__ __forceinline__ void gauss3(uint64_t seed, uint64_t noise_id, uint64_
 }
 
 // B (half kick), A (half drift), O (exact OU), A (half drift)
+// B A O A of one step; also requests a Verlet-list rebuild (flag) when the new position
+// is more than sqrt(lim2) from the one of the last build.
 __global__ void k_baoab_pre(int N, int n_sys, const int *__restrict__ off, double *__restrict__ x,
-                            double *__restrict__ p, const double *__restrict__ f, LangevinDev ld, int s_step) {
+                            double *__restrict__ p, const double *__restrict__ f, LangevinDev ld, int s_step,
+                            const double *__restrict__ xref, double lim2, int *__restrict__ flag) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int s = sys_of(off, n_sys, i);
@@ -717,6 +723,7 @@ __global__ void k_baoab_pre(int N, int n_sys, const int *__restrict__ off, doubl
     double g[3];
     gauss3(ld.seed, (uint64_t)ld.noise_id[s], gstep, (uint64_t)(i - off[s]), g[0], g[1], g[2]);
     const double hk = 0.5 * ld.dt / MVV2E, hd = 0.5 * ld.dt / ld.mass, sig = ld.sig[s];
+    double d2 = 0.0;
 #pragma unroll
     for (int al = 0; al < 3; ++al) {
         double pp = p[al * N + i] + hk * f[al * N + i];
@@ -725,7 +732,10 @@ __global__ void k_baoab_pre(int N, int n_sys, const int *__restrict__ off, doubl
         xx = xx + hd * pp;
         p[al * N + i] = pp;
         x[al * N + i] = xx;
+        const double dd = xx - xref[al * N + i];
+        d2 += dd * dd;
     }
+    if (!(d2 <= lim2)) atomicOr(flag, 1);  // NaN also rebuilds
 }
 
 __global__ void k_baoab_post(int N, double *__restrict__ p, const double *__restrict__ f, double dt) {
@@ -743,11 +753,11 @@ static inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1
 // skin/2 since the last build (decided on the device); the pair kernels apply the exact
 // cutoffs, so the list only decides which pairs are examined.
 void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, hipStream_t st, bool force,
-                      double skin) {
+                      double skin, bool checked, bool clear_in_fs) {
     const int N = bd.N;
     if (force) {
         hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, st, w.flag, 1);
-    } else {
+    } else if (!checked) {
         hipLaunchKernelGGL(k_check_disp, dim3(nblk(N, 256)), dim3(256), 0, st, N, x, w.xref, 0.25 * skin * skin,
                            w.flag);
     }
@@ -770,21 +780,21 @@ void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, h
                        w.flag);
     hipLaunchKernelGGL(k_reverse, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, w.poff, w.pair_i,
                        w.pair_j, w.rev, w.status, w.flag);
-    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, st, w.flag, 0);
+    if (!clear_in_fs) hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, st, w.flag, 0);
 }
 
 void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w, double *f, double *e_atom,
-               int accumulate, hipStream_t st) {
+               int accumulate, hipStream_t st, bool clear_flag) {
     const int N = bd.N;
     hipLaunchKernelGGL(k_fs_rho, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, w.poff,
-                       w.pair_j, fp.d, w.rho);
+                       w.pair_j, fp.d, w.rho, clear_flag ? w.flag : nullptr);
     hipLaunchKernelGGL(k_fs_force, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, w.poff,
                        w.pair_j, fp, w.rho, f, e_atom, accumulate);
 }
 
 template <int J>
 static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
-                          double *e_atom, int accumulate, hipStream_t st, KernelProf *prof) {
+                          double *e_atom, int accumulate, hipStream_t st, KernelProf *prof, hipEvent_t join) {
     const int N = bd.N;
     KernelProf dummy;
     KernelProf &pf = prof ? *prof : dummy;
@@ -800,17 +810,18 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     hipLaunchKernelGGL(k_dedr<J>, dim3(nblk((size_t)N * kMaxNeigh, 64)), dim3(64), 0, st, N, w.poff, w.pair_i, w.geo, w.Pcap,
                        w.ytil, w.dedr);
     pf.end(st);
+    if (join) (void)hipStreamWaitEvent(st, join, 0);  // f written by work on another stream
     hipLaunchKernelGGL(k_gather, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.poff, w.rev, w.dedr, w.Pcap, f,
                        accumulate);
 }
 
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
-                 double *e_atom, int accumulate, hipStream_t st, KernelProf *prof) {
+                 double *e_atom, int accumulate, hipStream_t st, KernelProf *prof, hipEvent_t join) {
     switch (J) {
-        case 2: launch_snap_J<2>(bd, x, sd, w, f, e_atom, accumulate, st, prof); break;
-        case 4: launch_snap_J<4>(bd, x, sd, w, f, e_atom, accumulate, st, prof); break;
-        case 6: launch_snap_J<6>(bd, x, sd, w, f, e_atom, accumulate, st, prof); break;
-        case 8: launch_snap_J<8>(bd, x, sd, w, f, e_atom, accumulate, st, prof); break;
+        case 2: launch_snap_J<2>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join); break;
+        case 4: launch_snap_J<4>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join); break;
+        case 6: launch_snap_J<6>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join); break;
+        case 8: launch_snap_J<8>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join); break;
         default: break;
     }
 }
@@ -835,9 +846,9 @@ void launch_bispectrum(const BatchDev &bd, const SnapDev &sd, Work &w, double *B
 }
 
 void launch_baoab_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
-                      hipStream_t st) {
+                      const Work &w, double skin, hipStream_t st) {
     hipLaunchKernelGGL(k_baoab_pre, dim3(nblk(bd.N, 256)), dim3(256), 0, st, bd.N, bd.n_sys, bd.off, x, p, f, ld,
-                       s_step);
+                       s_step, w.xref, 0.25 * skin * skin, w.flag);
 }
 
 void launch_baoab_post(const BatchDev &bd, double *p, const double *f, double dt, hipStream_t st) {
