@@ -241,6 +241,8 @@ int prepare_batch(snapmd_ctx *ctx, const snapmd_batch *batch, BatchDev &bd, doub
     }
     bd.N = N;
     bd.n_sys = S;
+    bd.max_sys = 0;
+    for (int q = 0; q < S; ++q) bd.max_sys = std::max(bd.max_sys, ctx->h_off[q + 1] - ctx->h_off[q]);
     bd.off = ctx->d_off.p;
     bd.box = ctx->d_box.p;
     return SNAPMD_OK;
@@ -605,6 +607,7 @@ int snapmd_create(snapmd_ctx **out, int hip_device) {
     }
     adjoint_init_attributes();
     sweep_init_attributes();
+    neigh_init_attributes();
     if (hipStreamCreateWithFlags(&ctx->fork_st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {

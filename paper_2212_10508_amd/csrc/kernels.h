@@ -15,6 +15,7 @@ struct BatchDev {
     const double *box = nullptr;  // [3 * n_sys]
     const int4 *cells = nullptr;  // [n_sys] (nx, ny, nz, first cell); nx = 0: brute force
     int n_cells = 0;
+    int max_sys = 0;              // atoms of the largest system
 };
 
 struct FsParams {
@@ -142,6 +143,7 @@ void launch_slabs_to_batch(int S, int N, const double *slots, double *out, hipSt
 void launch_jumps(size_t n, double *a, const double *b, hipStream_t st);
 void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st);
 void sweep_init_attributes();
+void neigh_init_attributes();
 bool sweep_fits_lds(int N);
 int sweep_mc_workgroups(int N);
 void launch_slab_end(int N, int mode, size_t SN, size_t s, double *xs, double *ps, const double *jq, const double *jp,

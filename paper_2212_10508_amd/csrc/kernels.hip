@@ -90,6 +90,153 @@ __global__ void k_neigh_build(int N, int n_sys, const int *__restrict__ off, con
     xref[2 * N + i] = zi;
 }
 
+// Full lists of every atom of a batch of small systems (at most kSysLdsAtoms atoms each):
+// one workgroup per system copies its positions to LDS, bins them into the system's cell
+// grid in LDS (cells[s] = (nx, ny, nz, .), nx = 0 or too many cells: all pairs) with
+// atoms ascending in each cell, and builds each atom's list from the 27-cell stencil.
+constexpr int kSysLdsAtoms = 4096;
+constexpr int kSysCells = 1024;
+
+size_t neigh_sys_lds_bytes(int max_sys) {
+    return (size_t)max_sys * (3 * sizeof(double) + 2 * sizeof(uint16_t)) + (2 * kSysCells + 1) * sizeof(int) + 16;
+}
+
+__global__ void __launch_bounds__(1024) k_neigh_sys(int N, const int *__restrict__ off, const double *__restrict__ box,
+                                                    const double *__restrict__ x, double rc2,
+                                                    const int4 *__restrict__ cells, int *__restrict__ nbr,
+                                                    int *__restrict__ cnt, int *__restrict__ status,
+                                                    const int *__restrict__ flag, double *__restrict__ xref) {
+    if (*flag == 0) return;
+    extern __shared__ double sm[];
+    const int s = blockIdx.x, j0 = off[s], ns = off[s + 1] - j0;
+    if (ns <= 0) return;
+    const int tid = threadIdx.x, T = blockDim.x;
+    double *xs = sm;                                                 // [3][ns]
+    int *ccnt = reinterpret_cast<int *>(xs + 3 * ns);                // [kSysCells] counts / fill pointers
+    int *cstart = ccnt + kSysCells;                                  // [kSysCells + 1]
+    uint16_t *catom = reinterpret_cast<uint16_t *>(cstart + kSysCells + 1);  // [ns]
+    uint16_t *cid = catom + ns;                                      // [ns]
+    const double Lx = box[3 * s], Ly = box[3 * s + 1], Lz = box[3 * s + 2];
+    const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
+    for (int q = tid; q < ns; q += T) {
+        xs[q] = x[j0 + q];
+        xs[ns + q] = x[N + j0 + q];
+        xs[2 * ns + q] = x[2 * N + j0 + q];
+    }
+    const int4 ci = cells ? cells[s] : make_int4(0, 0, 0, 0);
+    const int NC = ci.x * ci.y * ci.z;
+    const bool use_cells = ci.x >= 3 && ci.y >= 3 && ci.z >= 3 && NC <= kSysCells;
+    __syncthreads();
+    if (use_cells) {
+        for (int c = tid; c < NC; c += T) ccnt[c] = 0;
+        __syncthreads();
+        for (int q = tid; q < ns; q += T) {
+            int k3[3];
+            const double v[3] = {xs[q] * iLx, xs[ns + q] * iLy, xs[2 * ns + q] * iLz};
+            const int n3[3] = {ci.x, ci.y, ci.z};
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                const double fr = v[al] - floor(v[al]);
+                const int k = (int)(fr * n3[al]);
+                k3[al] = k < 0 ? 0 : (k >= n3[al] ? n3[al] - 1 : k);
+            }
+            const int c = (k3[0] * ci.y + k3[1]) * ci.z + k3[2];
+            cid[q] = (uint16_t)c;
+            atomicAdd(&ccnt[c], 1);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            constexpr int per = kSysCells / 64;
+            int loc[per], sum = 0;
+#pragma unroll
+            for (int k = 0; k < per; ++k) {
+                const int c = tid * per + k;
+                loc[k] = c < NC ? ccnt[c] : 0;
+                sum += loc[k];
+            }
+            int incl = sum;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(incl, o, 64);
+                if (tid >= o) incl += v;
+            }
+            int run = incl - sum;
+#pragma unroll
+            for (int k = 0; k < per; ++k) {
+                const int c = tid * per + k;
+                if (c < NC) {
+                    cstart[c] = run;
+                    ccnt[c] = run;
+                }
+                run += loc[k];
+            }
+            if (tid == 63) cstart[NC] = incl;
+        }
+        __syncthreads();
+        for (int q = tid; q < ns; q += T) catom[atomicAdd(&ccnt[cid[q]], 1)] = (uint16_t)q;
+        __syncthreads();
+        for (int c = tid; c < NC; c += T) {
+            const int b = cstart[c], e = cstart[c + 1];
+            for (int q = b + 1; q < e; ++q) {
+                const uint16_t v = catom[q];
+                int r = q - 1;
+                while (r >= b && catom[r] > v) {
+                    catom[r + 1] = catom[r];
+                    --r;
+                }
+                catom[r + 1] = v;
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = tid; q < ns; q += T) {
+        const int i = j0 + q;
+        const double xi = xs[q], yi = xs[ns + q], zi = xs[2 * ns + q];
+        int c = 0;
+        auto try_j = [&](int jl) {
+            const double dx = mimg(xs[jl] - xi, Lx, iLx), dy = mimg(xs[ns + jl] - yi, Ly, iLy),
+                         dz = mimg(xs[2 * ns + jl] - zi, Lz, iLz);
+            if (dx * dx + dy * dy + dz * dz < rc2) {
+                if (c < kMaxNeigh) nbr[(size_t)i * kMaxNeigh + c] = j0 + jl;
+                ++c;
+            }
+        };
+        if (use_cells) {
+            const int me = cid[q];
+            const int iz = me % ci.z, iy = (me / ci.z) % ci.y, ix = me / (ci.z * ci.y);
+            for (int ax = -1; ax <= 1; ++ax) {
+                const int cx = (ix + ax + ci.x) % ci.x;
+                for (int ay = -1; ay <= 1; ++ay) {
+                    const int cy = (iy + ay + ci.y) % ci.y;
+                    for (int az = -1; az <= 1; ++az) {
+                        const int cc = (cx * ci.y + cy) * ci.z + (iz + az + ci.z) % ci.z;
+                        for (int qq = cstart[cc]; qq < cstart[cc + 1]; ++qq) {
+                            const int jl = catom[qq];
+                            if (jl != q) try_j(jl);
+                        }
+                    }
+                }
+            }
+        } else {
+            for (int jl = 0; jl < ns; ++jl)
+                if (jl != q) try_j(jl);
+        }
+        if (c > kMaxNeigh) {
+            atomicOr(status, 1);
+            c = kMaxNeigh;
+        }
+        cnt[i] = c;
+        xref[i] = xi;
+        xref[N + i] = yi;
+        xref[2 * N + i] = zi;
+    }
+}
+
+void neigh_init_attributes() {
+    (void)hipFuncSetAttribute((const void *)k_neigh_sys, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)neigh_sys_lds_bytes(kSysLdsAtoms));
+}
+
 // Cell binning (only when a rebuild is requested): cells[s] = (nx, ny, nz, first cell)
 // with nx = 0 for systems searched by brute force.
 __global__ void k_cell_zero(int C, int *__restrict__ cnt, int *__restrict__ fill, const int *__restrict__ flag) {
@@ -762,7 +909,12 @@ void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, h
                            w.flag);
     }
     const double rl = rc + skin;
-    if (bd.cells && bd.n_cells > 0) {
+    if (bd.max_sys > 0 && bd.max_sys <= kSysLdsAtoms) {
+        // small systems: the whole build in one kernel, one workgroup per system
+        hipLaunchKernelGGL(k_neigh_sys, dim3(bd.n_sys), dim3(1024), neigh_sys_lds_bytes(bd.max_sys), st, N, bd.off,
+                           bd.box, x, rl * rl, (bd.cells && bd.n_cells > 0) ? bd.cells : nullptr, w.nbr, w.cnt,
+                           w.status, w.flag, w.xref);
+    } else if (bd.cells && bd.n_cells > 0) {
         const int C = bd.n_cells;
         hipLaunchKernelGGL(k_cell_zero, dim3(nblk(C, 256)), dim3(256), 0, st, C, w.cell_cnt, w.cell_fill, w.flag);
         hipLaunchKernelGGL(k_cell_assign, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
@@ -772,9 +924,10 @@ void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, h
                            w.cell_atoms, w.flag);
         hipLaunchKernelGGL(k_cell_sort, dim3(nblk(C, 256)), dim3(256), 0, st, C, w.cell_start, w.cell_atoms, w.flag);
     }
-    hipLaunchKernelGGL(k_neigh_build, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, rl * rl,
-                       w.nbr, w.cnt, w.status, w.flag, w.xref, (bd.cells && bd.n_cells > 0) ? bd.cells : nullptr,
-                       w.cell_of, w.cell_start, w.cell_atoms);
+    if (!(bd.max_sys > 0 && bd.max_sys <= kSysLdsAtoms))
+        hipLaunchKernelGGL(k_neigh_build, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
+                           rl * rl, w.nbr, w.cnt, w.status, w.flag, w.xref,
+                           (bd.cells && bd.n_cells > 0) ? bd.cells : nullptr, w.cell_of, w.cell_start, w.cell_atoms);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, N, w.cnt, w.poff, w.flag);
     hipLaunchKernelGGL(k_compact, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.nbr, w.cnt, w.poff, w.pair_i, w.pair_j,
                        w.flag);
