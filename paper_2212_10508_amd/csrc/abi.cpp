@@ -353,9 +353,9 @@ constexpr double kSweepSkin = 0.5;  // Verlet skin of the LDS-resident coarse sw
 // Chunk sizes of a parareal iteration over S slabs of N atoms.  The SNAP adjoint runs
 // one 64-atom workgroup per CU at a time, so a chunk costs whole rounds: m_r = the most
 // slabs that fit r rounds, counting two CUs per chiplet as taken by the work running
-// beside the propagation (the sweep's workgroups).  Chunks of m_2 slabs, ending with two of m_1 and the
-// remainder, so that the sweep (which starts after the first chunk) keeps pace and the
-// part of it left after the last propagation is short.  Where that gives a single chunk,
+// beside the propagation (the sweep's workgroups).  Chunks of m_2 slabs, then the rest
+// split so that the last chunk has m_1 - 1 slabs: the sweep (which starts after the first
+// chunk) keeps pace and the part of it left after the last propagation is short.  Where that gives a single chunk,
 // sizes in the ratio 4 : 3 : 2 : 1 are used instead.
 std::vector<int> chunk_plan(int S, int N, int cus) {
     const long per = (long)std::max(cus - 16, 8) * 64;
@@ -366,14 +366,16 @@ std::vector<int> chunk_plan(int S, int N, int cus) {
         sz.push_back(std::min(left, m2));
         left -= sz.back();
     }
-    while (left > m2 + 2 * m1) {
+    while (left > m2 + m1) {
         sz.push_back(m2);
         left -= m2;
     }
-    while (left > 0) {
-        sz.push_back(std::min(left, m1));
-        left -= sz.back();
+    const int last = std::max(1, m1 - 1);
+    if (left > last) {
+        sz.push_back(left - last);
+        left = last;
     }
+    if (left > 0) sz.push_back(left);
     if (sz.size() > 1 || S < 2) return sz;
     const int G = std::min(S, 4);
     const int W = G * (G + 1) / 2;
