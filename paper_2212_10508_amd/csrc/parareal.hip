@@ -198,13 +198,13 @@ __device__ __forceinline__ bool swl_pair(const SweepArgs &a, const double *__res
 // (list entries of atom i: col[t * ns], t = 0, 1, ..)
 __device__ __forceinline__ int swl_build_thread(const SweepArgs &a, const double *__restrict__ xs,
                                                 uint16_t *__restrict__ col, int ns, const SwCells &cl, int i,
-                                                double rcl2, int &overflow) {
+                                                double rcl2, int &overflow, int h = 0, int H = 1) {
     const int N = a.N;
     const double xi = xs[i], yi = xs[N + i], zi = xs[2 * N + i];
     int c = 0;
     if (a.ncx > 0) {  // the 27 cells around i's cell, atoms of a cell in ascending order
         const int ci = cl.cid[i];
-        for (int o = 0; o < 27; ++o) {
+        for (int o = h; o < 27; o += H) {
             const int cc = swl_stencil(a, ci, o);
             for (int q = cl.start[cc]; q < cl.start[cc + 1]; ++q) {
                 const int j = cl.atom[q];
@@ -215,7 +215,7 @@ __device__ __forceinline__ int swl_build_thread(const SweepArgs &a, const double
             }
         }
     } else {
-        for (int j = 0; j < N; ++j) {
+        for (int j = h * N / H; j < (h + 1) * N / H; ++j) {
             if (j != i && swl_pair(a, xs, N, j, xi, yi, zi, rcl2)) {
                 if (c < kSweepLdsNeigh) col[c * ns] = (uint16_t)j;
                 ++c;
@@ -271,9 +271,9 @@ __device__ __forceinline__ int swl_build_wave(const SweepArgs &a, const double *
 // the force cutoff (positions do not change before the force pass of the same step).
 // The unrolled body is branch-free (entries past the count repeat the last one and
 // add nothing) so that the LDS reads of four neighbours are in flight together.
-__device__ __forceinline__ uint64_t swl_rho_thread(const SweepArgs &a, const double *__restrict__ xs,
-                                                   double *__restrict__ dfe, const uint16_t *__restrict__ col, int ns,
-                                                   int i, int c) {
+__device__ __forceinline__ uint64_t swl_rho_acc(const SweepArgs &a, const double *__restrict__ xs,
+                                                const uint16_t *__restrict__ col, int ns, int i, int c,
+                                                double &acc_out) {
     const int N = a.N;
     const FsParams fp = a.fp;
     const double d2c = fp.d * fp.d, rc2f = fmax(fp.d, fp.c) * fmax(fp.d, fp.c);
@@ -295,7 +295,18 @@ __device__ __forceinline__ uint64_t swl_rho_thread(const SweepArgs &a, const dou
             acc += (valid && r2 < d2c) ? (r - fp.d) * (r - fp.d) : 0.0;
         }
     }
-    dfe[i] = acc > 0.0 ? -fp.A / (2.0 * sqrt(acc)) : 0.0;
+    acc_out = acc;
+    return mk;
+}
+__device__ __forceinline__ double swl_dfe(const FsParams &fp, double acc) {
+    return acc > 0.0 ? -fp.A / (2.0 * sqrt(acc)) : 0.0;
+}
+__device__ __forceinline__ uint64_t swl_rho_thread(const SweepArgs &a, const double *__restrict__ xs,
+                                                   double *__restrict__ dfe, const uint16_t *__restrict__ col, int ns,
+                                                   int i, int c) {
+    double acc;
+    const uint64_t mk = swl_rho_acc(a, xs, col, ns, i, c, acc);
+    dfe[i] = swl_dfe(a.fp, acc);
     return mk;
 }
 
@@ -728,18 +739,21 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
     const int N = a.N, K = a.K, A = a.A;
     const int w = blockIdx.x, a0 = w * A, na = min(N, a0 + A) - a0;
     const int tid = threadIdx.x;
-    const bool own = tid < na;
-    const int i = a0 + tid;
+    // two lanes per atom: lane 2k + h holds atom a0 + k (state kept identically in both
+    // lanes) and the half of its list built from stencil cells o = h, h + 2, ..
+    const int k = tid >> 1, h = tid & 1;
+    const bool own = k < na, lead = own && h == 0;
+    const int i = a0 + k;
     double *xs = sm;                                       // [3][N]
     double *dfe = xs + 3 * N;                              // [N]
     int *flag = reinterpret_cast<int *>(dfe + N);          // [2]
     uint16_t *nb = reinterpret_cast<uint16_t *>(flag + 2); // [kSweepNbRows][A]
     SwCells cl;
-    cl.cnt = reinterpret_cast<int *>(nb + (size_t)kSweepNbRows * A + ((kSweepNbRows * A) & 1));
+    cl.cnt = reinterpret_cast<int *>(nb + (size_t)kSweepNbRows * 2 * A);
     cl.start = cl.cnt + kSweepMaxCells;
     cl.atom = reinterpret_cast<uint16_t *>(cl.start + kSweepMaxCells + 1);
     cl.cid = cl.atom + N;
-    uint16_t *col = nb + tid;
+    uint16_t *col = nb + tid;  // rows of stride 2A
     const int NC = a.ncx * a.ncy * a.ncz;
     const double rcl = fmax(a.fp.d, a.fp.c) + a.skin, rcl2 = rcl * rcl;
     const size_t SN = (size_t)(a.n_fi - a.n_in) * N;
@@ -759,7 +773,7 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
     bool built = false, alive = true;
     // exchange: publish own positions (and partials), barrier, gather all positions
     auto exchange_x = [&](double p0, double p1, double p2, double p3) -> bool {
-        if (own)
+        if (lead)
 #pragma unroll
             for (int al = 0; al < 3; ++al) st_dev(a.gx + ((size_t)par * 3 + al) * N + i, xo[al]);
         if (tid == 0) {
@@ -863,19 +877,28 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
                     __syncthreads();
                 }
                 if (own) {
-                    cn = swl_build_thread(a, xs, col, A, cl, i, rcl2, overflow);
+                    cn = swl_build_thread(a, xs, col, 2 * A, cl, i, rcl2, overflow, h, 2);
 #pragma unroll
                     for (int al = 0; al < 3; ++al) xr[al] = xo[al];
                 }
                 built = true;
                 __syncthreads();
             }
-            if (own) mk = swl_rho_thread(a, xs, dfe, col, A, i, cn);
-            if (own) st_dev(a.gdfe + (size_t)par * N + i, dfe[i]);
+            double acc = 0.0;
+            if (own) mk = swl_rho_acc(a, xs, col, 2 * A, i, cn, acc);
+            acc += __shfl_xor(acc, 1, 64);  // both halves of the list (same sum in both lanes)
+            if (lead) {
+                const double d = swl_dfe(a.fp, acc);
+                dfe[i] = d;
+                st_dev(a.gdfe + (size_t)par * N + i, d);
+            }
             if (!mc_barrier(a, b++, flag)) { alive = false; break; }
             mc_copy(dfe, a.gdfe + (size_t)par * N, N);
             __syncthreads();
-            if (own) swl_force_thread(a, xs, dfe, col, A, i, mk, fr);
+            double fh[3] = {0.0, 0.0, 0.0};
+            if (own) swl_force_thread(a, xs, dfe, col, 2 * A, i, mk, fh);
+#pragma unroll
+            for (int al = 0; al < 3; ++al) fr[al] = fh[al] + __shfl_xor(fh[al], 1, 64);
             if (l >= 0)
 #pragma unroll
                 for (int al = 0; al < 3; ++al) pr[al] = pr[al] + hk * fr[al];
@@ -894,14 +917,18 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
                     xq += a.jq[al * SN + s * N + i];
                     pq += a.jp[al * SN + s * N + i];
                     const double pv = a.q_prev[((size_t)(n + 1) * 3 + al) * N + i];
-                    d2 += (xq - pv) * (xq - pv);
-                    p2 += pv * pv;
+                    if (lead) {
+                        d2 += (xq - pv) * (xq - pv);
+                        p2 += pv * pv;
+                    }
                 }
-                fin += xq * 0.0 + pq * 0.0;  // NaN/Inf propagate into fin
+                if (lead) fin += xq * 0.0 + pq * 0.0;  // NaN/Inf propagate into fin
                 xo[al] = xq;
                 pr[al] = pq;
-                a.q_cur[((size_t)(n + 1) * 3 + al) * N + i] = xq;
-                a.p_cur[((size_t)(n + 1) * 3 + al) * N + i] = pq;
+                if (lead) {
+                    a.q_cur[((size_t)(n + 1) * 3 + al) * N + i] = xq;
+                    a.p_cur[((size_t)(n + 1) * 3 + al) * N + i] = pq;
+                }
             }
         {
             const double v0 = wave_sum(d2), v1 = wave_sum(p2), v2 = wave_sum(fin);
@@ -955,7 +982,7 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
 }
 
 size_t sweep_mc_lds_bytes(int N, int A) {
-    return (size_t)N * 4 * sizeof(double) + 2 * sizeof(int) + (size_t)kSweepNbRows * A * sizeof(uint16_t) + 4 +
+    return (size_t)N * 4 * sizeof(double) + 2 * sizeof(int) + (size_t)kSweepNbRows * 2 * A * sizeof(uint16_t) + 4 +
            (2 * kSweepMaxCells + 1) * sizeof(int) + (size_t)N * 2 * sizeof(uint16_t) + 8;
 }
 
@@ -1030,11 +1057,12 @@ bool sweep_fits_lds(int N) { return N <= kSweepLdsMaxAtoms && sweep_lds_bytes(N)
 
 // workgroups of the multi-workgroup sweep for N atoms (0: not used)
 int sweep_mc_workgroups(int N) {
-    constexpr int K = 8;
-    if (N < 512) return 0;
-    const int A = (N + K - 1) / K;
-    if (A > 512 || N > 65535 || sweep_mc_lds_bytes(N, A) > 160 * 1024) return 0;
-    return K;
+    if (N < 512 || N > 65535) return 0;
+    for (int K : {8, 16}) {  // two lanes per atom: at most 256 atoms per workgroup of 512 threads
+        const int A = (N + K - 1) / K;
+        if (A <= 256 && sweep_mc_lds_bytes(N, A) <= 160 * 1024) return K;
+    }
+    return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1093,7 +1121,7 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     if (s.K > 0) {
         // at least 81 KB of LDS so that no two of the workgroups share a CU
         const size_t lds = std::max<size_t>(sweep_mc_lds_bytes(s.N, s.A), 81 * 1024);
-        const int T = (s.A + 63) / 64 * 64;
+        const int T = (2 * s.A + 63) / 64 * 64;
         hipLaunchKernelGGL(k_coarse_sweep_mc, dim3(s.K), dim3(T), lds, st, a);
     } else {
         hipLaunchKernelGGL(k_coarse_sweep_lds, dim3(1), dim3(kSweepThreads), sweep_lds_bytes(s.N), st, a);
