@@ -173,3 +173,42 @@ def test_sweep_sizes_match_oracle(S, cells, dumbbell):
     ctx.langevin_steps(S.POT_FS_SNAP, xf, pf, [0, n], box, L, step0=0, J=J, beta=beta, **kw)
     scale = torch.max(torch.abs(xf)).item()
     assert torch.max(torch.abs(q[1] - xf)).item() < 1e-12 * scale
+
+
+def test_bench_configuration_sampled(S):
+    """One corrected iteration in the benchmark's launch configuration (64 slabs of the
+    1025-atom cell, twojmax 8, L = 100, slab chunks with the sweep beside them), checked on
+    sampled slabs against the oracle: slab 1 becomes F(cur_0), and a slab of the last
+    chunk obeys cur_{n+1} = C(cur_n) + F(prev_n) - C(prev_n)."""
+    J, NS, L = 8, 64, 100
+    wl = W.slabs_1025(n_slabs=1, seed=1, J=J)
+    x0, p0, box, beta = wl["xs"][0], wl["ps"][0], wl["box"], wl["beta"]
+    n = x0.shape[1]
+    kw = dict(dt=wl["dt"], gamma=wl["gamma"], mass=wl["mass"], T=wl["T"], seed=1, noise_id=0, fs=W.FS_W)
+    ctx = S.context()
+    q = torch.zeros((NS + 1, 3, n), dtype=torch.float64, device="cuda")
+    pp, qp, ppv = torch.zeros_like(q), torch.zeros_like(q), torch.zeros_like(q)
+    q[0], pp[0] = dev(x0), dev(p0)
+    ctx.parareal_iterate(None, None, q, pp, box, L, 0, NS, 1e300, **kw)
+    d, nfi = ctx.parareal_iterate(qp, ppv, q, pp, box, L, 0, NS, 1e300, J=J, beta=beta, **kw)
+    assert nfi == NS and np.isfinite(d) and d > 0.0
+    snap = dict(J=J, beta=beta, rcut=W.SNAP_RCUT, rfac0=W.SNAP_RFAC0, rmin0=0.0)
+    prop = OPR.Propagators(box=box, L=L, dt=wl["dt"], gamma=wl["gamma"], mass=wl["mass"], T=wl["T"], seed=1,
+                           noise_id=0, snap=snap, fs=W.FS_W)
+    qh, ph, qph, pph = q.cpu().numpy(), pp.cpu().numpy(), qp.cpu().numpy(), ppv.cpu().numpy()
+    # window initialisation: prev_1 = C(cur_0)
+    c1 = prop.C((x0, p0), 0)
+    assert np.abs(qph[1] - c1[0]).max() < QTOL
+    # slab 1 after one iteration = F(cur_0)
+    f0 = prop.F((x0, p0), 0)
+    assert np.abs(qh[1] - f0[0]).max() < QTOL
+    assert np.abs(ph[1] - f0[1]).max() < QTOL * np.abs(f0[1]).max()
+    # a slab of the last chunk
+    m = 60
+    cn = prop.C((qh[m], ph[m]), m)
+    fo = prop.F((qph[m], pph[m]), m)
+    co = prop.C((qph[m], pph[m]), m)
+    ref_q = cn[0] + fo[0] - co[0]
+    ref_p = cn[1] + fo[1] - co[1]
+    assert np.abs(qh[m + 1] - ref_q).max() < QTOL
+    assert np.abs(ph[m + 1] - ref_p).max() < QTOL * np.abs(ref_p).max()
