@@ -78,6 +78,7 @@ struct Work {
     double *rho = nullptr;
     double *geo = nullptr;  // [20][Pcap]
     double *ell = nullptr;  // [5][kMaxNeigh][N] a, b, f_c by (list slot, atom)
+    int *nbr_t = nullptr;   // [kMaxNeigh][N] neighbour j by (list slot, atom)
     double *dedr = nullptr; // [3][Pcap]
     double2 *u = nullptr, *ytil = nullptr;  // [nh][N]
 };

@@ -5,12 +5,12 @@
 //                image) -> k_scan (prefix sums) -> k_compact (atom-major pair list,
 //                CSR) -> k_reverse (index of the opposite pair)
 //   FS EAM     : k_fs_rho -> k_fs_force (deterministic gather over the full list)
-//   SNAP       : k_pair_geo (Cayley-Klein parameters, switching function and their
-//                gradients, once per pair; a, b, f_c also by list slot) -> k_density<J>
-//                (u, lane = atom, one column chain of the Wigner-D polynomials per wave) -> k_adjoint (Y by the coupling
-//                program, energy by Euler's identity) -> k_dedr<J> (per pair
-//                dE_i/dr_ij = Re sum conj(Y~) d(f_c P)) -> k_gather (F_k = sum over
-//                pairs (g_kj - g_jk), no atomics, deterministic)
+//   SNAP       : k_pair_ell (a, b, f_c once per pair, slot-major) -> k_density<J>
+//                (u, lane = atom, one column chain of the Wigner-D polynomials per wave)
+//                -> k_adjoint (Y by the coupling program, energy by Euler's identity)
+//                -> k_dedr<J> (per pair dE_i/dr_ij = Re sum conj(Y~) d(f_c P), geometry
+//                again from the positions) -> k_gather (F_k = sum over pairs
+//                (g_kj - g_jk), no atomics, deterministic)
 //   BAOAB      : k_baoab_pre (B A O A with Philox4x64-10 Gaussians) / k_baoab_post (B)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -342,14 +342,16 @@ __global__ void __launch_bounds__(1024) k_scan(int N, const int *__restrict__ cn
 
 __global__ void k_compact(int N, const int *__restrict__ nbr, const int *__restrict__ cnt,
                           const int *__restrict__ poff, int *__restrict__ pair_i, int *__restrict__ pair_j,
-                          const int *__restrict__ flag) {
+                          int *__restrict__ nbr_t, const int *__restrict__ flag) {
     if (*flag == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int p0 = poff[i], c = cnt[i];
     for (int t = 0; t < c; ++t) {
+        const int j = nbr[(size_t)i * kMaxNeigh + t];
         pair_i[p0 + t] = i;
-        pair_j[p0 + t] = nbr[(size_t)i * kMaxNeigh + t];
+        pair_j[p0 + t] = j;
+        if (nbr_t) nbr_t[(size_t)t * N + i] = j;  // slot-major copy for the SNAP density (lane = atom)
     }
 }
 
@@ -447,20 +449,11 @@ __global__ void k_fs_force(int N, int n_sys, const int *__restrict__ off, const 
 // geo layout (SoA, stride Pcap): 0 ar, 1 ai, 2 br, 3 bi, 4 fc,
 //   5..7 d(ar)/dx_al, 8..10 d(ai), 11..13 d(br), 14..16 d(bi), 17..19 d(fc)
 // ---------------------------------------------------------------------------
-__global__ void k_pair_geo(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
-                           const double *__restrict__ x, const int *__restrict__ poff,
-                           const int *__restrict__ pair_i, const int *__restrict__ pair_j, SnapGeoParams sp,
-                           double *__restrict__ geo, size_t Pcap, double *__restrict__ ell) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= poff[N]) return;
-    const int i = pair_i[p], j = pair_j[p];
-    const int s = sys_of(off, n_sys, i);
-    double d[3];
-    d[0] = mimg(x[j] - x[i], box[3 * s], 1.0 / box[3 * s]);
-    d[1] = mimg(x[N + j] - x[N + i], box[3 * s + 1], 1.0 / box[3 * s + 1]);
-    d[2] = mimg(x[2 * N + j] - x[2 * N + i], box[3 * s + 2], 1.0 / box[3 * s + 2]);
+// Geometry of a pair at separation d (x_j - x_i): g[0..3] = a, b (re, im), g[4] = f_c,
+// g[5..19] their gradients with respect to d (layout above); pairs at or beyond the
+// cutoff get a = 1, b = 0, f_c = 0 and zero gradients.
+__device__ __forceinline__ void snap_geo(const double (&d)[3], const SnapGeoParams &sp, double (&g)[20]) {
     const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    double g[20];
 #pragma unroll
     for (int q = 0; q < 20; ++q) g[q] = 0.0;
     g[0] = 1.0;
@@ -489,13 +482,49 @@ __global__ void k_pair_geo(int N, int n_sys, const int *__restrict__ off, const 
             g[17 + al] = dfdr * u;
         }
     }
+}
+// a, b and f_c only (same expressions as snap_geo)
+__device__ __forceinline__ void snap_geo_abf(const double (&d)[3], const SnapGeoParams &sp, double2 &a, double2 &b,
+                                             double &fc) {
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    a = make_double2(1.0, 0.0);
+    b = make_double2(0.0, 0.0);
+    fc = 0.0;
+    if (r < sp.rcut) {
+        const double w = M_PI / (sp.rcut - sp.rmin0);
+        const double c = sp.rfac0 * w;
+        double sth, cth, sph, cph;
+        sincos(c * (r - sp.rmin0), &sth, &cth);
+        sincos(w * (r - sp.rmin0), &sph, &cph);
+        const double sr = sth * (1.0 / r);
+        a = make_double2(cth, -d[2] * sr);
+        b = make_double2(d[1] * sr, -d[0] * sr);
+        fc = 0.5 * (cph + 1.0);
+    }
+}
+// minimum-image separation x_j - x_i in system s
+__device__ __forceinline__ void pair_sep(const double *__restrict__ x, int N, const double *__restrict__ box, int s,
+                                         int i, int j, double (&d)[3]) {
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        const double L = box[3 * s + al];
+        d[al] = mimg(x[al * N + j] - x[al * N + i], L, 1.0 / L);
+    }
+}
+
+// pair geometry in CSR order (for the coefficient-gradient passes)
+__global__ void k_pair_geo(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
+                           const double *__restrict__ x, const int *__restrict__ poff,
+                           const int *__restrict__ pair_i, const int *__restrict__ pair_j, SnapGeoParams sp,
+                           double *__restrict__ geo, size_t Pcap) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= poff[N]) return;
+    const int i = pair_i[p], j = pair_j[p];
+    double d[3], g[20];
+    pair_sep(x, N, box, sys_of(off, n_sys, i), i, j, d);
+    snap_geo(d, sp, g);
 #pragma unroll
     for (int q = 0; q < 20; ++q) geo[q * Pcap + p] = g[q];
-    // a, b, f_c again in slot-major layout ell[f][t][i] (t = rank of the pair in i's
-    // list) for the density pass, where lane = atom reads slot t of 64 atoms at once
-    const size_t t = (size_t)(p - poff[i]);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) ell[((size_t)q * kMaxNeigh + t) * N + i] = g[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -571,6 +600,28 @@ __device__ __forceinline__ void staircase(double2 (&P)[J + 1], double2 b, double
     }
 }
 
+// a, b and f_c of every listed pair in slot-major layout ell[f][t][i] (t = rank of the
+// pair in i's list), one thread per (slot, atom) with the atom fastest, so that the
+// density pass (lane = atom) reads slot t of 64 atoms with one coalesced load per field.
+__global__ void k_pair_ell(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
+                           const double *__restrict__ x, const int *__restrict__ poff,
+                           const int *__restrict__ nbr_t, SnapGeoParams sp, double *__restrict__ ell) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = (int)(q / (size_t)N), i = (int)(q - (size_t)t * N);
+    if (t >= kMaxNeigh || t >= poff[i + 1] - poff[i]) return;
+    double d[3];
+    pair_sep(x, N, box, sys_of(off, n_sys, i), i, nbr_t[q], d);
+    double2 a, b;
+    double fc;
+    snap_geo_abf(d, sp, a, b, fc);
+    const size_t sN = (size_t)kMaxNeigh * N;
+    ell[q] = a.x;
+    ell[sN + q] = a.y;
+    ell[2 * sN + q] = b.x;
+    ell[3 * sN + q] = b.y;
+    ell[4 * sN + q] = fc;
+}
+
 // u (half storage, [e][N] double2) for column C: one wave per tile of 64 atoms, lane =
 // atom.  Step t reads slot t of the 64 atoms' lists from the slot-major copy of a, b
 // and f_c (one coalesced load per field); slots past an atom's count add nothing.
@@ -606,9 +657,9 @@ __device__ void density_lane(int N, const int *__restrict__ poff, const double *
 #pragma unroll
         for (int k = 0; k <= n; ++k) {
             const int e = half_idx(n, k, C);
-            const double s = nrm[e];
+            const double sc = nrm[e];
             const double2 v = acc[chain_acc_idx(C, n, k)];
-            u[(size_t)e * N + i] = make_double2((k == C ? 1.0 : 0.0) + s * v.x, s * v.y);
+            u[(size_t)e * N + i] = make_double2((k == C ? 1.0 : 0.0) + sc * v.x, sc * v.y);
         }
 }
 
@@ -752,19 +803,19 @@ __device__ __forceinline__ void dedr_chain(double2 (&P)[J + 1], double2 (&dP)[3]
 constexpr int kDedrAtoms = 6;
 
 template <int J>
-__device__ __forceinline__ void dedr_pair(int p, size_t Pcap, const double *__restrict__ geo,
+__device__ __forceinline__ void dedr_pair(int p, size_t Pcap, const double (&g)[20],
                                           const double2 *__restrict__ yt, int ystride, double *__restrict__ dedr) {
-    const double fc = geo[4 * Pcap + p];
-    const double2 a = make_double2(geo[p], geo[Pcap + p]);
-    const double2 b = make_double2(geo[2 * Pcap + p], geo[3 * Pcap + p]);
+    const double fc = g[4];
+    const double2 a = make_double2(g[0], g[1]);
+    const double2 b = make_double2(g[2], g[3]);
     const double2 ab = cconj(a);
     double2 db[3], dab[3];
     double dfc[3];
 #pragma unroll
     for (int al = 0; al < 3; ++al) {
-        dab[al] = make_double2(geo[(5 + al) * Pcap + p], -geo[(8 + al) * Pcap + p]);
-        db[al] = make_double2(geo[(11 + al) * Pcap + p], geo[(14 + al) * Pcap + p]);
-        dfc[al] = geo[(17 + al) * Pcap + p];
+        dab[al] = make_double2(g[5 + al], -g[8 + al]);
+        db[al] = make_double2(g[11 + al], g[14 + al]);
+        dfc[al] = g[17 + al];
     }
     double2 P[J + 1], dP[3][J + 1], sP[J + 1], sdP[3][J + 1];
     double S0 = 0.0, S[3] = {0.0, 0.0, 0.0};
@@ -774,8 +825,10 @@ __device__ __forceinline__ void dedr_pair(int p, size_t Pcap, const double *__re
 }
 
 template <int J>
-__global__ void __launch_bounds__(64) k_dedr(int N, const int *__restrict__ poff, const int *__restrict__ pair_i,
-                                             const double *__restrict__ geo, size_t Pcap,
+__global__ void __launch_bounds__(64) k_dedr(int N, int n_sys, const int *__restrict__ off,
+                                             const double *__restrict__ box, const double *__restrict__ x,
+                                             const int *__restrict__ poff, const int *__restrict__ pair_i,
+                                             const int *__restrict__ pair_j, SnapGeoParams sp, size_t Pcap,
                                              const double2 *__restrict__ ytil, double *__restrict__ dedr) {
     constexpr int NH = n_half(J);
     __shared__ double2 ys[kDedrAtoms * NH];
@@ -786,16 +839,23 @@ __global__ void __launch_bounds__(64) k_dedr(int N, const int *__restrict__ poff
     const int i0 = pair_i[p0], na = pair_i[min(p0 + 63, P - 1)] - i0 + 1;
     const bool live = p < P;
     const int i = live ? pair_i[p] : i0;
-    const double fc = live ? geo[4 * Pcap + p] : 0.0;
+    // geometry of the pair from the positions
+    double g[20];
+    {
+        double d[3] = {1.0, 0.0, 0.0};
+        if (live) pair_sep(x, N, box, sys_of(off, n_sys, i), i, pair_j[p], d);
+        snap_geo(d, sp, g);
+    }
+    const double fc = live ? g[4] : 0.0;
     if (na <= kDedrAtoms) {
         for (int q = lane; q < na * NH; q += 64) {
             const int e = q / na, at = q - e * na;
             ys[q] = ytil[(size_t)e * N + i0 + at];
         }
         __syncthreads();
-        if (fc != 0.0) dedr_pair<J>(p, Pcap, geo, ys + (i - i0), na, dedr);
+        if (fc != 0.0) dedr_pair<J>(p, Pcap, g, ys + (i - i0), na, dedr);
     } else {
-        if (fc != 0.0) dedr_pair<J>(p, Pcap, geo, ytil + i, N, dedr);
+        if (fc != 0.0) dedr_pair<J>(p, Pcap, g, ytil + i, N, dedr);
     }
     if (live && fc == 0.0) {
         dedr[p] = 0.0;
@@ -930,7 +990,7 @@ void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, h
                            (bd.cells && bd.n_cells > 0) ? bd.cells : nullptr, w.cell_of, w.cell_start, w.cell_atoms);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, N, w.cnt, w.poff, w.flag);
     hipLaunchKernelGGL(k_compact, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.nbr, w.cnt, w.poff, w.pair_i, w.pair_j,
-                       w.flag);
+                       w.nbr_t, w.flag);
     hipLaunchKernelGGL(k_reverse, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, w.poff, w.pair_i,
                        w.pair_j, w.rev, w.status, w.flag);
     if (!clear_in_fs) hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, st, w.flag, 0);
@@ -951,8 +1011,8 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     const int N = bd.N;
     KernelProf dummy;
     KernelProf &pf = prof ? *prof : dummy;
-    hipLaunchKernelGGL(k_pair_geo, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
-                       w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap, w.ell);
+    hipLaunchKernelGGL(k_pair_ell, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box,
+                       x, w.poff, w.nbr_t, sd.gp, w.ell);
     pf.begin(PROF_DENSITY, st);
     hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 64), J / 2 + 1), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u);
     pf.end(st);
@@ -960,8 +1020,8 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     launch_adjoint(J, sd.adj, N, w.u, sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate, st);
     pf.end(st);
     pf.begin(PROF_DEDR, st);
-    hipLaunchKernelGGL(k_dedr<J>, dim3(nblk((size_t)N * kMaxNeigh, 64)), dim3(64), 0, st, N, w.poff, w.pair_i, w.geo, w.Pcap,
-                       w.ytil, w.dedr);
+    hipLaunchKernelGGL(k_dedr<J>, dim3(nblk((size_t)N * kMaxNeigh, 64)), dim3(64), 0, st, N, bd.n_sys, bd.off, bd.box,
+                       x, w.poff, w.pair_i, w.pair_j, sd.gp, w.Pcap, w.ytil, w.dedr);
     pf.end(st);
     if (join) (void)hipStreamWaitEvent(st, join, 0);  // f written by work on another stream
     hipLaunchKernelGGL(k_gather, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.poff, w.rev, w.dedr, w.Pcap, f,
@@ -982,7 +1042,9 @@ void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, 
 void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st) {
     const int N = bd.N;
     hipLaunchKernelGGL(k_pair_geo, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
-                       w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap, w.ell);
+                       w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
+    hipLaunchKernelGGL(k_pair_ell, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box,
+                       x, w.poff, w.nbr_t, sd.gp, w.ell);
     switch (J) {
         case 2: hipLaunchKernelGGL(k_density<2>, dim3(nblk(N, 64), 2), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u); break;
         case 4: hipLaunchKernelGGL(k_density<4>, dim3(nblk(N, 64), 3), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u); break;
