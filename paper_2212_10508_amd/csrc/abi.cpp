@@ -451,9 +451,11 @@ int neighbors(snapmd_ctx *ctx, Work &w, const BatchDev &bd0, const double *x, do
 
 // Forces of a propagation step (e_atom not wanted).  For FS + SNAP the Finnis-Sinclair
 // pass runs on a second stream beside the SNAP chain, joined before the SNAP gather adds
-// into f.
+// into f.  With p_kick the closing half kick of the step is applied too (by the SNAP
+// gather, or by a kernel of its own after the Finnis-Sinclair force).
 void enqueue_forces(snapmd_ctx *ctx, Work &w, int potential, const BatchDev &bd, const double *x,
-                    const FsParams *fp, const SnapDev *sd, double *f, hipStream_t st, bool fresh = true) {
+                    const FsParams *fp, const SnapDev *sd, double *f, hipStream_t st, bool fresh = true,
+                    double *p_kick = nullptr, double dt = 0.0) {
     double rc = 0.0;
     if (fp) rc = std::max(fp->d, fp->c);
     if (potential == SNAPMD_POT_FS_SNAP) rc = std::max(rc, sd->gp.rcut);
@@ -465,10 +467,13 @@ void enqueue_forces(snapmd_ctx *ctx, Work &w, int potential, const BatchDev &bd,
         (void)hipStreamWaitEvent(ctx->fork_st, ctx->ev_fork, 0);
         launch_fs(bd, x, *fp, w, f, nullptr, 0, ctx->fork_st, true);
         (void)hipEventRecord(ctx->ev_join, ctx->fork_st);
-        launch_snap(sd->J, bd, x, *sd, w, f, nullptr, 1, st, &ctx->prof, ctx->ev_join);
+        launch_snap(sd->J, bd, x, *sd, w, f, nullptr, 1, st, &ctx->prof, ctx->ev_join, p_kick, dt);
     } else {
         launch_fs(bd, x, *fp, w, f, nullptr, 0, st, true);
-        if (potential == SNAPMD_POT_FS_SNAP) launch_snap(sd->J, bd, x, *sd, w, f, nullptr, 1, st, &ctx->prof);
+        if (potential == SNAPMD_POT_FS_SNAP)
+            launch_snap(sd->J, bd, x, *sd, w, f, nullptr, 1, st, &ctx->prof, nullptr, p_kick, dt);
+        else if (p_kick)
+            launch_baoab_post(bd, p_kick, f, dt, st);
     }
 }
 
@@ -479,8 +484,7 @@ void run_langevin(snapmd_ctx *ctx, Work &w, double *f, int potential, const Batc
     enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st);
     for (int s = 0; s < n_steps; ++s) {
         launch_baoab_pre(bd, x, p, f, ld, s, w, kSkin, st);
-        enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st, false);
-        launch_baoab_post(bd, p, f, ld.dt, st);
+        enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st, false, p, ld.dt);
     }
 }
 

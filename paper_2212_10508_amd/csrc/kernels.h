@@ -160,10 +160,11 @@ void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, h
 void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w, double *f, double *e_atom,
                int accumulate, hipStream_t st, bool clear_flag = false);
 // join (nullable): an event the gather waits for (the Finnis-Sinclair force written into f
-// on another stream)
+// on another stream); p_kick (nullable): momenta that receive the closing half kick
+// p += (dt/2) f of a BAOAB step from the gather
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
                  double *e_atom, int accumulate, hipStream_t st, KernelProf *prof = nullptr,
-                 hipEvent_t join = nullptr);
+                 hipEvent_t join = nullptr, double *p_kick = nullptr, double dt = 0.0);
 void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st);
 void adjoint_tables(int J, const double *beta, AdjointHost &A);
 void adjoint_init_attributes();

@@ -864,23 +864,44 @@ __global__ void __launch_bounds__(64) k_dedr(int N, int n_sys, const int *__rest
     }
 }
 
-// F_k (+)= sum_{p in pairs(k)} (g_p - g_rev(p))
-__global__ void k_gather(int N, const int *__restrict__ poff, const int *__restrict__ rev,
-                         const double *__restrict__ dedr, size_t Pcap, double *__restrict__ f, int accumulate) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
-    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-    for (int p = poff[k]; p < poff[k + 1]; ++p) {
-        const int q = rev[p];
-        g0 += dedr[p] - dedr[q];
-        g1 += dedr[Pcap + p] - dedr[Pcap + q];
-        g2 += dedr[2 * Pcap + p] - dedr[2 * Pcap + q];
+// F_k (+)= sum_{p in pairs(k)} (g_p - g_rev(p)), optionally followed by the closing half
+// kick p_k += (dt/2) F_k of a BAOAB step (pk non-null).  A workgroup takes 64 atoms;
+// their pairs are one contiguous range of the list, read in windows of kGatherWin pairs
+// by all 256 threads (coalesced, one reverse index each), differences staged in LDS.
+// Wave c then sums component c of each atom's differences in list order, so the sum
+// is the same sequence of additions as a loop over the atom's pairs.
+constexpr int kGatherWin = 2048;
+__global__ void __launch_bounds__(256) k_gather(int N, const int *__restrict__ poff, const int *__restrict__ rev,
+                                                const double *__restrict__ dedr, size_t Pcap,
+                                                double *__restrict__ f, int accumulate, double *__restrict__ pk,
+                                                double dt) {
+    __shared__ double dg[3][kGatherWin];
+    const int k0 = blockIdx.x * 64, k1 = min(k0 + 64, N);
+    const int tid = threadIdx.x, c = tid >> 6, k = k0 + (tid & 63);
+    const bool own = c < 3 && k < k1;
+    const int P0 = poff[k0], P1 = poff[k1];
+    const int pb = own ? poff[k] : 0, pe = own ? poff[k + 1] : 0;
+    double g = 0.0;
+    for (int w0 = P0; w0 < P1; w0 += kGatherWin) {
+        const int n = min(kGatherWin, P1 - w0);
+        for (int q = tid; q < n; q += 256) {
+            const int p = w0 + q, r = rev[p];
+            dg[0][q] = dedr[p] - dedr[r];
+            dg[1][q] = dedr[Pcap + p] - dedr[Pcap + r];
+            dg[2][q] = dedr[2 * Pcap + p] - dedr[2 * Pcap + r];
+        }
+        __syncthreads();
+        if (own) {
+            const int a = max(pb, w0), b = min(pe, w0 + n);
+            for (int p = a; p < b; ++p) g += dg[c][p - w0];
+        }
+        __syncthreads();
     }
-    if (accumulate) {
-        f[k] += g0; f[N + k] += g1; f[2 * N + k] += g2;
-    } else {
-        f[k] = g0; f[N + k] = g1; f[2 * N + k] = g2;
-    }
+    if (!own) return;
+    const size_t o = (size_t)c * N + k;
+    const double fk = accumulate ? f[o] + g : g;
+    f[o] = fk;
+    if (pk) pk[o] = fma(0.5 * dt / MVV2E, fk, pk[o]);
 }
 
 // ---------------------------------------------------------------------------
@@ -948,7 +969,7 @@ __global__ void k_baoab_pre(int N, int n_sys, const int *__restrict__ off, doubl
 __global__ void k_baoab_post(int N, double *__restrict__ p, const double *__restrict__ f, double dt) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= 3 * N) return;
-    p[q] = p[q] + (0.5 * dt / MVV2E) * f[q];
+    p[q] = fma(0.5 * dt / MVV2E, f[q], p[q]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1007,7 +1028,8 @@ void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w,
 
 template <int J>
 static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
-                          double *e_atom, int accumulate, hipStream_t st, KernelProf *prof, hipEvent_t join) {
+                          double *e_atom, int accumulate, hipStream_t st, KernelProf *prof, hipEvent_t join,
+                          double *p_kick, double dt) {
     const int N = bd.N;
     KernelProf dummy;
     KernelProf &pf = prof ? *prof : dummy;
@@ -1024,17 +1046,18 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
                        x, w.poff, w.pair_i, w.pair_j, sd.gp, w.Pcap, w.ytil, w.dedr);
     pf.end(st);
     if (join) (void)hipStreamWaitEvent(st, join, 0);  // f written by work on another stream
-    hipLaunchKernelGGL(k_gather, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.poff, w.rev, w.dedr, w.Pcap, f,
-                       accumulate);
+    hipLaunchKernelGGL(k_gather, dim3(nblk(N, 64)), dim3(256), 0, st, N, w.poff, w.rev, w.dedr, w.Pcap, f,
+                       accumulate, p_kick, dt);
 }
 
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
-                 double *e_atom, int accumulate, hipStream_t st, KernelProf *prof, hipEvent_t join) {
+                 double *e_atom, int accumulate, hipStream_t st, KernelProf *prof, hipEvent_t join, double *p_kick,
+                 double dt) {
     switch (J) {
-        case 2: launch_snap_J<2>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join); break;
-        case 4: launch_snap_J<4>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join); break;
-        case 6: launch_snap_J<6>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join); break;
-        case 8: launch_snap_J<8>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join); break;
+        case 2: launch_snap_J<2>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt); break;
+        case 4: launch_snap_J<4>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt); break;
+        case 6: launch_snap_J<6>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt); break;
+        case 8: launch_snap_J<8>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt); break;
         default: break;
     }
 }
