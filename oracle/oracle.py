@@ -57,6 +57,11 @@ def lib():
         L.ora_philox4x64_10.argtypes = [P, P, P]
         L.ora_gauss3.restype = None
         L.ora_gauss3.argtypes = [u64, u64, u64, u64, P]
+        L.ora_gauss3t.restype = None
+        L.ora_gauss3t.argtypes = [u64, u64, u64, u64, u64, P]
+        L.ora_bbk.restype = i
+        L.ora_bbk.argtypes = ([i, i, d, d, d, P, d, d, d, d, d, d, i, i, P, d, d, d, d, d, d,
+                               u64, u64, i64, P, i, P, P, P, P, P])
         L.ora_langevin.restype = i
         L.ora_langevin.argtypes = ([i, i, d, d, d, P, d, d, d, d, d, d, i, i, P, d, d, d, d,
                                     u64, u64, i64, i, P, P, P, P, P])
@@ -193,6 +198,45 @@ def langevin(x, p, box, *, potential, nsteps, dt, gamma, mass, T, seed, noise_id
                             noise_id, step0, nsteps, _p(x), _p(p), _p(f), _p(tx), _p(tp))
     if rc != 0:
         raise FloatingPointError("non-finite energy or neighbour overflow in oracle Langevin run")
+    out = dict(x=x, p=p, f=f)
+    if want_traj:
+        out["traj_x"] = tx
+        out["traj_p"] = tp
+    return out
+
+
+def gauss3t(seed, noise_id, step, atom, tag):
+    g = np.zeros(3)
+    lib().ora_gauss3t(seed, noise_id, step & 0xFFFFFFFFFFFFFFFF, atom, tag, _p(g))
+    return g
+
+
+def bbk(x, p, box, *, potential, nsteps, dt, gamma, mass, T, cT=(1.0, 1.0), seed=0, noise_id=0, step0=0,
+        G=None, snap=None, fs=None, maxn=64, want_traj=False):
+    """One application of nsteps iterates of the paper's modified BBK scheme (eq:scheme_debut,
+    eq:scheme; with cT = (C_0, C_l>=1) the temperature schedule of eq:scheme_corrected_debut,
+    eq:scheme_corrected) to one system; inputs are copied.  G: optional [nsteps+1, 3, N]
+    Gaussians G_0..G_L (else drawn from Philox, see ora_bbk).  Returns dict(x, p, f[, traj_x,
+    traj_p]) with traj_* of shape [nsteps+1, 3, N] (q_l, p_l)."""
+    x = _c64(x).copy()
+    p = _c64(p).copy()
+    N = x.shape[1]
+    snap = snap or dict(J=0, beta=np.zeros(1), rcut=4.73, rfac0=0.99363, rmin0=0.0)
+    fs = fs or dict(A=0, d=0, c=0, c0=0, c1=0, c2=0)
+    beta = _c64(snap["beta"])
+    if G is not None:
+        G = _c64(G)
+        if G.shape != (nsteps + 1, 3, N):
+            raise ValueError("G must have shape (nsteps + 1, 3, N)")
+    f = np.zeros((3, N))
+    tx = np.zeros((nsteps + 1, 3, N)) if want_traj else None
+    tp = np.zeros((nsteps + 1, 3, N)) if want_traj else None
+    rc = lib().ora_bbk(potential, snap["J"], snap.get("rcut", 4.73), snap.get("rfac0", 0.99363),
+                       snap.get("rmin0", 0.0), _p(beta), fs["A"], fs["d"], fs["c"], fs["c0"], fs["c1"], fs["c2"],
+                       maxn, N, _p(_c64(box)), dt, gamma, mass, T, float(cT[0]), float(cT[1]), seed, noise_id,
+                       step0, _p(G), nsteps, _p(x), _p(p), _p(f), _p(tx), _p(tp))
+    if rc != 0:
+        raise FloatingPointError("non-finite energy or neighbour overflow in oracle BBK run")
     out = dict(x=x, p=p, f=f)
     if want_traj:
         out["traj_x"] = tx

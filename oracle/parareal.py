@@ -10,7 +10,8 @@ explosion threshold; Algorithm "Adaptive parareal algorithm").
 
 Propagators: F and C both take L Langevin steps of length dt from (q, p) on slab n,
 with the same noise (global steps n*L .. n*L+L-1 of one noise stream), F on the
-fine potential (Finnis-Sinclair + SNAP), C on the coarse one (Finnis-Sinclair).
+fine potential (Finnis-Sinclair + SNAP), C on the coarse one (Finnis-Sinclair); the
+steps are BAOAB, or one application of L iterates of the paper's BBK scheme.
 
 Readings where the paper leaves room:
 * Relative error E(prev, cur, n_in, n) = sum_{m=n_in+1}^{n} |cur_m - prev_m| /
@@ -28,18 +29,25 @@ from . import oracle as O
 class Propagators:
     """F and C of one trajectory (one noise stream) for the oracle."""
 
-    def __init__(self, *, box, L, dt, gamma, mass, T, seed, noise_id, snap, fs, maxn=64):
+    def __init__(self, *, box, L, dt, gamma, mass, T, seed, noise_id, snap, fs, maxn=64, scheme="baoab",
+                 cT=(1.0, 1.0)):
         self.kw = dict(dt=dt, gamma=gamma, mass=mass, T=T, seed=seed, noise_id=noise_id,
                        snap=snap, fs=fs, maxn=maxn)
         self.box = box
         self.L = L
+        self.scheme = scheme  # "baoab", or "bbk": the paper's scheme, one application per slab
+        self.cT = cT
         self.n_fine = 0
         self.n_coarse = 0
 
     def _run(self, state, n, potential):
         q, p = state
-        r = O.langevin(q, p, self.box, potential=potential, nsteps=self.L, step0=n * self.L,
-                       **self.kw)
+        if self.scheme == "bbk":
+            r = O.bbk(q, p, self.box, potential=potential, nsteps=self.L, step0=n * self.L, cT=self.cT,
+                      **self.kw)
+        else:
+            r = O.langevin(q, p, self.box, potential=potential, nsteps=self.L, step0=n * self.L,
+                           **self.kw)
         return (r["x"], r["p"])
 
     def F(self, state, n):

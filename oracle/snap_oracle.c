@@ -24,6 +24,9 @@
  *   - Philox4x64-10 (Salmon et al., SC'11) and Box-Muller Gaussians.
  *   - BAOAB Langevin steps (discretisation of the Langevin equation of the
  *     paper's "Algorithm" section, with masses), one force evaluation per step.
+ *   - The paper's own integrator: the modified BBK scheme (eq:scheme_debut,
+ *     eq:scheme) with the temperature schedule of eq:scheme_corrected_debut,
+ *     eq:scheme_corrected, one call = one application of L iterates.
  */
 #include <complex.h>
 #include <math.h>
@@ -569,9 +572,10 @@ void ora_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint6
     memcpy(out, c, sizeof(c));
 }
 
-/* Three standard Gaussians for (seed, noise stream, global step, atom). */
-void ora_gauss3(uint64_t seed, uint64_t noise_id, uint64_t step, uint64_t atom, double g[3]) {
-    uint64_t ctr[4] = {noise_id, step, atom, 0}, key[2] = {seed, 0}, w[4];
+/* Three standard Gaussians for (seed, noise stream, global step, atom, tag); the tag is
+ * the fourth counter word (0 for BAOAB, 1 and 2 for the BBK scheme). */
+void ora_gauss3t(uint64_t seed, uint64_t noise_id, uint64_t step, uint64_t atom, uint64_t tag, double g[3]) {
+    uint64_t ctr[4] = {noise_id, step, atom, tag}, key[2] = {seed, 0}, w[4];
     ora_philox4x64_10(ctr, key, w);
     const double two53 = 1.0 / 9007199254740992.0;
     double u1 = 1.0 - (double)(w[0] >> 11) * two53; /* (0, 1] */
@@ -582,6 +586,11 @@ void ora_gauss3(uint64_t seed, uint64_t noise_id, uint64_t step, uint64_t atom, 
     g[0] = r1 * cos(2.0 * ORA_PI * u2);
     g[1] = r1 * sin(2.0 * ORA_PI * u2);
     g[2] = r2 * cos(2.0 * ORA_PI * u4);
+}
+
+/* Three standard Gaussians for (seed, noise stream, global step, atom). */
+void ora_gauss3(uint64_t seed, uint64_t noise_id, uint64_t step, uint64_t atom, double g[3]) {
+    ora_gauss3t(seed, noise_id, step, atom, 0, g);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -650,4 +659,73 @@ int ora_langevin(int potential, int J, double rcut, double rfac0, double rmin0,
     free(f);
     free(tmp);
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Modified BBK scheme (the paper's integrator)                                 */
+/* ------------------------------------------------------------------------- */
+/* One application of L = nsteps iterates of the paper's scheme to one system, in place,
+ * with masses and metal units (F in eV/A enters dp/dt as F / mvv2e; q' = p / m):
+ *   iterate 0 (eq:scheme_corrected_debut) and l >= 1 (eq:scheme_corrected):
+ *     p_{l+1/2} = p_l + (dt/2) F(q_l) - (dt/2) gamma p_{l-1/2} + s_l G_l,
+ *                 with p_{-1/2} replaced by p_0 in iterate 0,
+ *     q_{l+1}   = q_l + dt p_{l+1/2} / m,
+ *     p_{l+1}   = p_{l+1/2} + (dt/2) F(q_{l+1}) - (dt/2) gamma p_{l+1/2} + s_{l+1} G_{l+1},
+ *   s_l = (1/2) sqrt(2 gamma m kB T_l dt / mvv2e), T_l = C_l T with C_0 = cT0 and
+ *   C_l = cT1 for l >= 1 (cT0 = cT1 = 1 is eq:scheme_debut / eq:scheme).
+ * G: [nsteps+1][3][N] Gaussians G_0 .. G_L, or NULL: then G_l is drawn with counter
+ * (noise_id, step0 + l, atom, 1) for l < L and G_L with (noise_id, step0 + L, atom, 2),
+ * so that G_L of one call and G_0 of the call that starts at step0 + L differ.
+ * traj_x, traj_p (nullable): [nsteps+1][3][N] (q_l, p_l); f_out: the last force. */
+int ora_bbk(int potential, int J, double rcut, double rfac0, double rmin0, const double *beta,
+            double A, double dd, double cc, double c0, double c1, double c2, int maxn, int N,
+            const double box[3], double dt, double gamma, double mass, double T, double cT0,
+            double cT1, uint64_t seed, uint64_t noise_id, int64_t step0, const double *G,
+            int nsteps, double *x, double *p, double *f_out, double *traj_x, double *traj_p) {
+    ora_pot P = {potential, J, rcut, rfac0, rmin0, beta, A, dd, cc, c0, c1, c2, maxn};
+    const size_t n3 = (size_t)3 * N;
+    double *f = malloc(sizeof(double) * n3), *tmp = malloc(sizeof(double) * n3);
+    double *prev = malloc(sizeof(double) * n3), *half = malloc(sizeof(double) * n3);
+    double *gl = malloc(sizeof(double) * n3);
+    int rc = 0;
+    total_forces(&P, N, x, box, f, tmp);
+    memcpy(prev, p, sizeof(double) * n3); /* p_{-1/2} := p_0 */
+    if (traj_x) memcpy(traj_x, x, sizeof(double) * n3);
+    if (traj_p) memcpy(traj_p, p, sizeof(double) * n3);
+    for (int l = 0; l <= nsteps && rc == 0; l++) {
+        /* G_l and s_l */
+        if (G) {
+            memcpy(gl, G + (size_t)l * n3, sizeof(double) * n3);
+        } else {
+            for (int i = 0; i < N; i++) {
+                double g[3];
+                ora_gauss3t(seed, noise_id, (uint64_t)(step0 + l), (uint64_t)i, l < nsteps ? 1 : 2, g);
+                for (int al = 0; al < 3; al++) gl[al * N + i] = g[al];
+            }
+        }
+        const double Tl = (l == 0 ? cT0 : cT1) * T;
+        const double sl = 0.5 * sqrt(2.0 * gamma * mass * ORA_KB * Tl * dt / ORA_MVV2E);
+        if (l > 0) {
+            /* last line of iterate l-1: p_l from p_{l-1/2} (in half) and F(q_l) (in f) */
+            for (size_t q = 0; q < n3; q++)
+                p[q] = half[q] + 0.5 * dt * f[q] / ORA_MVV2E - 0.5 * dt * gamma * half[q] + sl * gl[q];
+            memcpy(prev, half, sizeof(double) * n3);
+            if (traj_x) memcpy(traj_x + (size_t)l * n3, x, sizeof(double) * n3);
+            if (traj_p) memcpy(traj_p + (size_t)l * n3, p, sizeof(double) * n3);
+        }
+        if (l == nsteps) break;
+        /* first two lines of iterate l */
+        for (size_t q = 0; q < n3; q++)
+            half[q] = p[q] + 0.5 * dt * f[q] / ORA_MVV2E - 0.5 * dt * gamma * prev[q] + sl * gl[q];
+        for (size_t q = 0; q < n3; q++) x[q] += dt * half[q] / mass;
+        const double e = total_forces(&P, N, x, box, f, tmp);
+        if (!isfinite(e)) rc = -1;
+    }
+    if (f_out && rc == 0) memcpy(f_out, f, sizeof(double) * n3);
+    free(f);
+    free(tmp);
+    free(prev);
+    free(half);
+    free(gl);
+    return rc;
 }
