@@ -101,12 +101,28 @@ typedef struct {
 } snapmd_fs;
 
 /* Langevin integration (the equation of the paper's "Algorithm" section with masses:
- * dq = p/m dt, dp = -grad V dt - gamma p dt + sqrt(2 gamma m kB T) dW), discretised
- * by BAOAB: half kick, half drift, exact Ornstein-Uhlenbeck step, half drift, force,
- * half kick -- one force evaluation per step.  The Gaussian increment of atom i
- * (local index within its system) at global step n is drawn from Philox4x64-10
- * with key (seed, 0) and counter (noise_id[s], n, i, 0) through Box-Muller, so a fine
- * and a coarse run of the same slab see identical noise (paper, "Parareal method"). */
+ * dq = p/m dt, dp = -grad V dt - gamma p dt + sqrt(2 gamma m kB T) dW), one force
+ * evaluation per step, by one of two schemes:
+ *
+ * SNAPMD_SCHEME_BAOAB: half kick, half drift, exact Ornstein-Uhlenbeck step, half
+ *   drift, force, half kick.  The Gaussian increment of atom i (local index within its
+ *   system) at global step n is drawn from Philox4x64-10 with key (seed, 0) and counter
+ *   (noise_id[s], n, i, 0) through Box-Muller, so a fine and a coarse run of the same
+ *   slab see identical noise (paper, "Parareal method").  Splitting a run into several
+ *   calls gives the same trajectory.
+ *
+ * SNAPMD_SCHEME_BBK: the paper's modified BBK scheme (eq:scheme_debut, eq:scheme) with
+ *   the temperature schedule of eq:scheme_corrected_debut / eq:scheme_corrected.  ONE
+ *   call is one application of L = n_steps iterates: iterate 0 uses p_0 in place of
+ *   p_{-1/2}; the Gaussians G_0 .. G_L of the call are drawn with counters
+ *   (noise_id[s], step0 + l, i, 1) for l < L and (noise_id[s], step0 + L, i, 2) for G_L
+ *   (so G_L of one call and G_0 of the call starting at step0 + L differ), G_l with
+ *   temperature C_l T: C_0 = bbk_c0, C_l = bbk_c1 for l >= 1.  bbk_c0 = bbk_c1 = 1 is
+ *   the uncorrected scheme, (3, 1) the schedule valid for every L (eq:robust), (2, 2)
+ *   the one for L = 1 (eq:choix_L_egal_1).  Unlike BAOAB, two calls of L/2 steps are
+ *   not one call of L steps (the first iterate differs; the paper's point). */
+enum { SNAPMD_SCHEME_BAOAB = 0, SNAPMD_SCHEME_BBK = 1 };
+
 typedef struct {
     double dt;                     /* ps, > 0                           */
     double gamma;                  /* 1/ps, >= 0                        */
@@ -115,7 +131,9 @@ typedef struct {
     uint64_t seed;
     const int64_t *step0_sys;      /* host [n_sys] global step of the first step */
     const int32_t *noise_id_sys;   /* host [n_sys] noise stream ids (>= 0)       */
-    int32_t scheme;                /* 0 = BAOAB (only value accepted)            */
+    int32_t scheme;                /* SNAPMD_SCHEME_BAOAB or SNAPMD_SCHEME_BBK   */
+    double bbk_c0;                 /* BBK: temperature factor C_0 of G_0 (> 0)   */
+    double bbk_c1;                 /* BBK: temperature factor C_l, l >= 1 (> 0)  */
 } snapmd_langevin;
 
 enum { SNAPMD_POT_FS = 0, SNAPMD_POT_FS_SNAP = 1 };
@@ -162,7 +180,10 @@ int langevin_steps(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, cons
  * window of the adaptive algorithm): pass q_prev = p_prev = NULL; then only
  * cur_{n+1} := C(cur_n) for n_in <= n < *n_fi is done, *delta_out = 0, snap may be NULL.
  * The coarse sweep keeps a Verlet list with a 0.5 A skin and stores each listed
- * pair's periodic image: max(d, c) + 1.0 must be below half the smallest box edge. */
+ * pair's periodic image: max(d, c) + 1.0 must be below half the smallest box edge.
+ * With SNAPMD_SCHEME_BBK every slab is one application of the scheme (L iterates) for
+ * both propagators, and the sequential sweep runs slab by slab from the host (one small
+ * synchronisation per slab) instead of in one persistent kernel. */
 int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs,
                      const snapmd_batch *batch, const snapmd_langevin *lang, int32_t L,
                      int32_t n_in, int32_t *n_fi, double *q_prev, double *p_prev, double *q_cur,

@@ -58,7 +58,7 @@ struct snapmd_ctx {
     Work w, wc;                                   // SNAP / second-stream Finnis-Sinclair workspaces
     double *d_f = nullptr, *d_fc = nullptr;       // their force scratch [3][N]
     // per-system Langevin arrays
-    DBuf<double> d_sig;
+    DBuf<double> d_sig, d_sb0, d_sb1;
     DBuf<int64_t> d_step0;
     DBuf<int> d_noise;
     std::map<int, SnapDevTables> snap;
@@ -171,6 +171,7 @@ int ensure_atoms(snapmd_ctx *ctx, size_t N) {
     if ((rc = dalloc(ctx, &w.geo, 20 * w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.ell, 5 * w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.nbr_t, w.Pcap))) return rc;
+    if ((rc = dalloc(ctx, &w.ph, 3 * cap))) return rc;
     if ((rc = dalloc(ctx, &w.dedr, 3 * w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.u, (size_t)n_half(kMaxJ) * cap))) return rc;
     if ((rc = dalloc(ctx, &w.ytil, (size_t)n_half(kMaxJ) * cap))) return rc;
@@ -200,7 +201,7 @@ int ensure_atoms_coarse(snapmd_ctx *ctx, size_t N) {
         (rc = dalloc(ctx, &w.pair_j, w.Pcap)) || (rc = dalloc(ctx, &w.rev, w.Pcap)) ||
         (rc = dalloc(ctx, &w.rho, cap)) || (rc = dalloc(ctx, &ctx->d_fc, 3 * cap)) ||
         (rc = dalloc(ctx, &w.xref, 3 * cap)) || (rc = dalloc(ctx, &w.cell_of, cap)) ||
-        (rc = dalloc(ctx, &w.cell_atoms, cap)))
+        (rc = dalloc(ctx, &w.cell_atoms, cap)) || (rc = dalloc(ctx, &w.ph, 3 * cap)))
         return rc;
     ctx->cap_atoms_c = cap;
     return SNAPMD_OK;
@@ -483,8 +484,14 @@ void run_langevin(snapmd_ctx *ctx, Work &w, double *f, int potential, const Batc
                   const SnapDev &sd, const LangevinDev &ld, int n_steps, double *x, double *p, hipStream_t st) {
     enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st);
     for (int s = 0; s < n_steps; ++s) {
-        launch_baoab_pre(bd, x, p, f, ld, s, w, kSkin, st);
-        enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st, false, p, ld.dt);
+        if (ld.scheme == SNAPMD_SCHEME_BBK) {
+            launch_bbk_pre(bd, x, p, f, ld, s, w, kSkin, st);
+            enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st, false);
+            launch_bbk_post(bd, p, f, ld, s + 1, n_steps, st);
+        } else {
+            launch_baoab_pre(bd, x, p, f, ld, s, w, kSkin, st);
+            enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st, false, p, ld.dt);
+        }
     }
 }
 
@@ -516,7 +523,8 @@ int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const
     std::vector<uint64_t> key{(uint64_t)potential, (uint64_t)bd.N, (uint64_t)bd.n_sys, u(bd.off), u(bd.box),
                               u(bd.cells), (uint64_t)bd.n_cells, (uint64_t)n_steps, u(x), u(p), u(f),
                               u(w.nbr), u(w.geo), u(w.u), u(w.ytil), u(w.xref), u(w.cell_cnt), u(w.flag), d(fp.A), d(fp.d), d(fp.c), d(fp.c0), d(fp.c1), d(fp.c2),
-                              d(ld.dt), d(ld.c1), d(ld.mass), ld.seed, u(ld.sig), u(ld.step0), u(ld.noise_id)};
+                              d(ld.dt), d(ld.c1), d(ld.mass), ld.seed, u(ld.sig), u(ld.step0), u(ld.noise_id),
+                              (uint64_t)ld.scheme, d(ld.gamma), u(ld.sb0), u(ld.sb1), u(w.ph)};
     if (potential == SNAPMD_POT_FS_SNAP) {
         const uint64_t sk[] = {(uint64_t)sd.J, d(sd.gp.rcut), d(sd.gp.rfac0), d(sd.gp.rmin0), d(sd.beta0),
                                u(sd.nrm), u(sd.adj.coef), u(sd.adj.cgm), u(sd.adj.roles)};
@@ -559,15 +567,28 @@ int prepare_langevin(snapmd_ctx *ctx, const snapmd_langevin *lang, int S, const 
                      const std::vector<int64_t> &step0, const std::vector<int> &nid, LangevinDev &ld,
                      hipStream_t st) {
     const double c1 = std::exp(-lang->gamma * lang->dt);
-    std::vector<double> sig(S);
-    for (int s = 0; s < S; ++s) sig[s] = std::sqrt((1.0 - c1 * c1) * lang->mass * kKB * T[s] / kMVV2E);
+    std::vector<double> sig(S), sb0(S), sb1(S);
+    for (int s = 0; s < S; ++s) {
+        sig[s] = std::sqrt((1.0 - c1 * c1) * lang->mass * kKB * T[s] / kMVV2E);
+        // BBK: (1/2) sqrt(2 gamma m kB T_l dt / mvv2e) with T_0 = C_0 T, T_l = C_l T
+        const double base = 2.0 * lang->gamma * lang->mass * kKB * T[s] * lang->dt / kMVV2E;
+        sb0[s] = 0.5 * std::sqrt(base * (lang->scheme == SNAPMD_SCHEME_BBK ? lang->bbk_c0 : 1.0));
+        sb1[s] = 0.5 * std::sqrt(base * (lang->scheme == SNAPMD_SCHEME_BBK ? lang->bbk_c1 : 1.0));
+    }
     int rc;
-    if ((rc = ensure(ctx, ctx->d_sig, S)) || (rc = ensure(ctx, ctx->d_step0, S)) || (rc = ensure(ctx, ctx->d_noise, S)))
+    if ((rc = ensure(ctx, ctx->d_sig, S)) || (rc = ensure(ctx, ctx->d_step0, S)) || (rc = ensure(ctx, ctx->d_noise, S)) ||
+        (rc = ensure(ctx, ctx->d_sb0, S)) || (rc = ensure(ctx, ctx->d_sb1, S)))
         return rc;
     if ((rc = upload(ctx, ctx->d_sig.p, sig.data(), S, st))) return rc;
     if ((rc = upload(ctx, ctx->d_step0.p, step0.data(), S, st))) return rc;
     if ((rc = upload(ctx, ctx->d_noise.p, nid.data(), S, st))) return rc;
+    if ((rc = upload(ctx, ctx->d_sb0.p, sb0.data(), S, st))) return rc;
+    if ((rc = upload(ctx, ctx->d_sb1.p, sb1.data(), S, st))) return rc;
     ld = LangevinDev{lang->dt, c1, lang->mass, lang->seed, ctx->d_sig.p, ctx->d_step0.p, ctx->d_noise.p};
+    ld.scheme = lang->scheme;
+    ld.gamma = lang->gamma;
+    ld.sb0 = ctx->d_sb0.p;
+    ld.sb1 = ctx->d_sb1.p;
     return SNAPMD_OK;
 }
 
@@ -586,7 +607,11 @@ int launch_noise_sweep(snapmd_ctx *ctx, int n_in, int S, int L, int N, const sna
 
 int check_lang(snapmd_ctx *ctx, const snapmd_langevin *lang) {
     if (!lang) return fail(ctx, SNAPMD_EINVAL, "lang is NULL");
-    if (lang->scheme != 0) return fail(ctx, SNAPMD_EINVAL, "only scheme 0 (BAOAB) is supported");
+    if (lang->scheme != SNAPMD_SCHEME_BAOAB && lang->scheme != SNAPMD_SCHEME_BBK)
+        return fail(ctx, SNAPMD_EINVAL, "scheme must be SNAPMD_SCHEME_BAOAB or SNAPMD_SCHEME_BBK (got %d)", lang->scheme);
+    if (lang->scheme == SNAPMD_SCHEME_BBK &&
+        !(lang->bbk_c0 > 0.0 && lang->bbk_c1 > 0.0 && std::isfinite(lang->bbk_c0) && std::isfinite(lang->bbk_c1)))
+        return fail(ctx, SNAPMD_EINVAL, "the BBK temperature factors bbk_c0, bbk_c1 must be finite and > 0");
     if (!(lang->dt > 0.0) || !(lang->gamma >= 0.0) || !(lang->mass > 0.0))
         return fail(ctx, SNAPMD_EINVAL, "need dt > 0, gamma >= 0, mass > 0");
     if (!lang->T_sys || !lang->step0_sys || !lang->noise_id_sys)
@@ -767,7 +792,9 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     const size_t SN3 = 3 * (size_t)S * N;
     // sweep scratch
     if ((rc = ensure(ctx, ctx->sw_out, 8))) return rc;
-    if (!sweep_fits_lds(N) &&
+    // the on-device sweeps integrate BAOAB; the BBK scheme takes the host-driven sweep
+    const bool bbk = lang->scheme == SNAPMD_SCHEME_BBK;
+    if ((bbk || !sweep_fits_lds(N)) &&
         ((rc = ensure(ctx, ctx->sw_x, 3 * (size_t)N)) || (rc = ensure(ctx, ctx->sw_p, 3 * (size_t)N))))
         return rc;
     if (!ctx->h_out) HIPCHK(hipHostMalloc((void **)&ctx->h_out, 16 * sizeof(double), hipHostMallocDefault));
@@ -816,8 +843,8 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     }
     // the sweep on the device: several workgroups exchanging through device memory, or
     // one LDS-resident workgroup; else driven from the host
-    const int mcK = sweep_mc_workgroups(N);
-    const bool lds_sweep = mcK > 0 || sweep_fits_lds(N);
+    const int mcK = bbk ? 0 : sweep_mc_workgroups(N);
+    const bool lds_sweep = !bbk && (mcK > 0 || sweep_fits_lds(N));
     if (mcK > 0) {
         sw.K = mcK;
         sw.A = (N + mcK - 1) / mcK;
@@ -896,6 +923,8 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
             lc.sig += s0;
             lc.step0 += s0;
             lc.noise_id += s0;
+            lc.sb0 += s0;
+            lc.sb1 += s0;
             return nc;
         };
         HIPCHK(hipEventRecord(ctx->pipe_ev[ne + 1], st));

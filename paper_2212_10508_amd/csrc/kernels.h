@@ -64,6 +64,10 @@ struct LangevinDev {
     const double *sig = nullptr;       // [n_sys] sqrt((1 - c1^2) m kB T / mvv2e)
     const int64_t *step0 = nullptr;    // [n_sys]
     const int *noise_id = nullptr;     // [n_sys]
+    int scheme = 0;                    // 0 BAOAB, 1 the paper's modified BBK
+    double gamma = 0.0;
+    const double *sb0 = nullptr;       // [n_sys] BBK noise amplitude of G_0: (1/2) sqrt(2 gamma m kB C_0 T dt / mvv2e)
+    const double *sb1 = nullptr;       // [n_sys] the same with C_l (l >= 1)
 };
 
 // Per-evaluation scratch (owned by the context).
@@ -79,6 +83,7 @@ struct Work {
     double *geo = nullptr;  // [20][Pcap]
     double *ell = nullptr;  // [5][kMaxNeigh][N] a, b, f_c by (list slot, atom)
     int *nbr_t = nullptr;   // [kMaxNeigh][N] neighbour j by (list slot, atom)
+    double *ph = nullptr;   // [3][N] BBK: p_{l-1/2} of the running call
     double *dedr = nullptr; // [3][Pcap]
     double2 *u = nullptr, *ytil = nullptr;  // [nh][N]
 };
@@ -180,5 +185,10 @@ void launch_set_value(double *p, double v, hipStream_t st);
 void launch_baoab_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
                       const Work &w, double skin, hipStream_t st);
 void launch_baoab_post(const BatchDev &bd, double *p, const double *f, double dt, hipStream_t st);
+void launch_bbk_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
+                    const Work &w, double skin, hipStream_t st);
+// s1 = l + 1 (1 .. n_steps)
+void launch_bbk_post(const BatchDev &bd, double *p, const double *f, const LangevinDev &ld, int s1, int n_steps,
+                     hipStream_t st);
 
 }  // namespace snapmd

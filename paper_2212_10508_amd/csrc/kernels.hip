@@ -12,6 +12,7 @@
 //                again from the positions) -> k_gather (F_k = sum over pairs
 //                (g_kj - g_jk), no atomics, deterministic)
 //   BAOAB      : k_baoab_pre (B A O A with Philox4x64-10 Gaussians) / k_baoab_post (B)
+//   BBK        : k_bbk_pre / k_bbk_post (the paper's modified BBK scheme)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -920,9 +921,10 @@ __device__ __forceinline__ void philox4x64_10(uint64_t (&c)[4], uint64_t k0, uin
     }
 }
 
+// tag: fourth counter word (0: BAOAB; 1 and 2: the BBK scheme's G_l, l < L, and G_L)
 __device__ __forceinline__ void gauss3(uint64_t seed, uint64_t noise_id, uint64_t step, uint64_t atom,
-                                       double &g0, double &g1, double &g2) {
-    uint64_t c[4] = {noise_id, step, atom, 0};
+                                       double &g0, double &g1, double &g2, uint64_t tag = 0) {
+    uint64_t c[4] = {noise_id, step, atom, tag};
     philox4x64_10(c, seed, 0);
     const double two53 = 1.0 / 9007199254740992.0;
     const double u1 = 1.0 - (double)(c[0] >> 11) * two53;
@@ -970,6 +972,59 @@ __global__ void k_baoab_post(int N, double *__restrict__ p, const double *__rest
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= 3 * N) return;
     p[q] = fma(0.5 * dt / MVV2E, f[q], p[q]);
+}
+
+// The paper's modified BBK scheme, one call = one application of L iterates.  First half
+// of iterate l (s_step): p_{l+1/2} = p_l + (dt/2) F_l - (dt/2) gamma p_{l-1/2} + s_l G_l
+// (p_{-1/2} := p_0 at l = 0), q_{l+1} = q_l + dt p_{l+1/2} / m.  p then holds p_{l+1/2},
+// and ph keeps a copy for the friction term of iterate l + 1.  G_l: counter
+// (noise_id, step0 + l, atom, 1).  Also the Verlet-list displacement test of k_baoab_pre.
+__global__ void k_bbk_pre(int N, int n_sys, const int *__restrict__ off, double *__restrict__ x,
+                          double *__restrict__ p, double *__restrict__ ph, const double *__restrict__ f,
+                          LangevinDev ld, int s_step, const double *__restrict__ xref, double lim2,
+                          int *__restrict__ flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int s = sys_of(off, n_sys, i);
+    double g[3];
+    gauss3(ld.seed, (uint64_t)ld.noise_id[s], (uint64_t)(ld.step0[s] + s_step), (uint64_t)(i - off[s]), g[0], g[1],
+           g[2], 1);
+    const double hk = 0.5 * ld.dt / MVV2E, hg = 0.5 * ld.dt * ld.gamma, dm = ld.dt / ld.mass;
+    const double sig = s_step == 0 ? ld.sb0[s] : ld.sb1[s];
+    double d2 = 0.0;
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        const size_t q = (size_t)al * N + i;
+        const double pl = p[q];
+        const double prev = s_step == 0 ? pl : ph[q];
+        const double half = pl + hk * f[q] - hg * prev + sig * g[al];
+        const double xx = x[q] + dm * half;
+        p[q] = half;
+        ph[q] = half;
+        x[q] = xx;
+        const double dd = xx - xref[q];
+        d2 += dd * dd;
+    }
+    if (!(d2 <= lim2)) atomicOr(flag, 1);  // NaN also rebuilds
+}
+
+// Second half of iterate l: p_{l+1} = p_{l+1/2} + (dt/2) F_{l+1} - (dt/2) gamma p_{l+1/2}
+// + s_{l+1} G_{l+1} (s1 = l + 1 >= 1); G_L of the call (s1 == L) uses tag 2.
+__global__ void k_bbk_post(int N, int n_sys, const int *__restrict__ off, double *__restrict__ p,
+                           const double *__restrict__ f, LangevinDev ld, int s1, int last) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int s = sys_of(off, n_sys, i);
+    double g[3];
+    gauss3(ld.seed, (uint64_t)ld.noise_id[s], (uint64_t)(ld.step0[s] + s1), (uint64_t)(i - off[s]), g[0], g[1], g[2],
+           last ? 2 : 1);
+    const double hk = 0.5 * ld.dt / MVV2E, hg = 0.5 * ld.dt * ld.gamma, sig = ld.sb1[s];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        const size_t q = (size_t)al * N + i;
+        const double half = p[q];
+        p[q] = half + hk * f[q] - hg * half + sig * g[al];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1091,6 +1146,18 @@ void launch_baoab_pre(const BatchDev &bd, double *x, double *p, const double *f,
 
 void launch_baoab_post(const BatchDev &bd, double *p, const double *f, double dt, hipStream_t st) {
     hipLaunchKernelGGL(k_baoab_post, dim3(nblk(3 * (size_t)bd.N, 256)), dim3(256), 0, st, bd.N, p, f, dt);
+}
+
+void launch_bbk_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
+                    const Work &w, double skin, hipStream_t st) {
+    hipLaunchKernelGGL(k_bbk_pre, dim3(nblk(bd.N, 256)), dim3(256), 0, st, bd.N, bd.n_sys, bd.off, x, p, w.ph, f, ld,
+                       s_step, w.xref, 0.25 * skin * skin, w.flag);
+}
+
+void launch_bbk_post(const BatchDev &bd, double *p, const double *f, const LangevinDev &ld, int s1, int n_steps,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_bbk_post, dim3(nblk(bd.N, 256)), dim3(256), 0, st, bd.N, bd.n_sys, bd.off, p, f, ld, s1,
+                       s1 == n_steps ? 1 : 0);
 }
 
 }  // namespace snapmd

@@ -44,7 +44,7 @@ class Langevin(C.Structure):
     _fields_ = [("dt", C.c_double), ("gamma", C.c_double), ("mass", C.c_double),
                 ("T_sys", C.POINTER(C.c_double)), ("seed", C.c_uint64),
                 ("step0_sys", C.POINTER(C.c_int64)), ("noise_id_sys", C.POINTER(C.c_int32)),
-                ("scheme", C.c_int32)]
+                ("scheme", C.c_int32), ("bbk_c0", C.c_double), ("bbk_c1", C.c_double)]
 
 
 _lib = None
@@ -141,12 +141,18 @@ def make_fs(fs):
     return Fs(fs["A"], fs["d"], fs["c"], fs["c0"], fs["c1"], fs["c2"])
 
 
-def make_langevin(keep, n_sys, dt, gamma, mass, T, seed, step0, noise_id):
+SCHEMES = {"baoab": 0, "bbk": 1}
+
+
+def make_langevin(keep, n_sys, dt, gamma, mass, T, seed, step0, noise_id, scheme="baoab", cT=(1.0, 1.0)):
     T = np.broadcast_to(np.asarray(T, np.float64), (n_sys,))
     step0 = np.broadcast_to(np.asarray(step0, np.int64), (n_sys,))
     noise_id = np.broadcast_to(np.asarray(noise_id, np.int32), (n_sys,))
+    if scheme not in SCHEMES:
+        raise ValueError("scheme must be one of %s" % sorted(SCHEMES))
     return Langevin(dt, gamma, mass, keep.arr(T, np.float64, C.c_double), seed,
-                    keep.arr(step0, np.int64, C.c_int64), keep.arr(noise_id, np.int32, C.c_int32), 0)
+                    keep.arr(step0, np.int64, C.c_int64), keep.arr(noise_id, np.int32, C.c_int32),
+                    SCHEMES[scheme], float(cT[0]), float(cT[1]))
 
 
 # ----------------------------------------------------------------------------
@@ -218,14 +224,16 @@ class Context:
     # -- dynamics ----------------------------------------------------------
     def langevin_steps(self, potential, x, p, offset, box, n_steps, *, dt, gamma, mass, T, seed, step0,
                        noise_id, fs, J=None, beta=None, f_out=None, rcut=4.73, rfac0=0.99363, rmin0=0.0,
-                       stream=None):
+                       scheme="baoab", cT=(1.0, 1.0), stream=None):
+        """scheme "bbk": one call is one application of n_steps iterates of the paper's
+        scheme with temperature factors cT = (C_0, C_l>=1)."""
         N = int(offset[-1])
         S = len(offset) - 1
         k = _Keep()
         b = make_batch(k, offset, box)
         s = make_snap(k, J, beta, rcut, rfac0, rmin0) if potential == POT_FS_SNAP else None
         p_fs = make_fs(fs)
-        lg = make_langevin(k, S, dt, gamma, mass, T, seed, step0, noise_id)
+        lg = make_langevin(k, S, dt, gamma, mass, T, seed, step0, noise_id, scheme, cT)
         self._check(lib().langevin_steps(self.h, potential, C.byref(s) if s is not None else None,
                                          C.byref(p_fs), C.byref(b), C.byref(lg), int(n_steps),
                                          _dev(x, "x", (3, N)), _dev(p, "p", (3, N)),
@@ -233,14 +241,14 @@ class Context:
 
     def parareal_iterate(self, q_prev, p_prev, q_cur, p_cur, box, L, n_in, n_fi, delta_expl, *, dt, gamma,
                          mass, T, seed, noise_id, fs, J=None, beta=None, rcut=4.73, rfac0=0.99363, rmin0=0.0,
-                         stream=None):
+                         scheme="baoab", cT=(1.0, 1.0), stream=None):
         """Returns (delta, n_fi_after).  q_prev = p_prev = None: window initialisation."""
         nslots, three, N = q_cur.shape
         k = _Keep()
         b = make_batch(k, [0, N], box)
         s = make_snap(k, J, beta, rcut, rfac0, rmin0) if beta is not None else None
         p_fs = make_fs(fs)
-        lg = make_langevin(k, 1, dt, gamma, mass, T, seed, 0, noise_id)
+        lg = make_langevin(k, 1, dt, gamma, mass, T, seed, 0, noise_id, scheme, cT)
         nfi = C.c_int32(int(n_fi))
         delta = C.c_double(0.0)
         shape = (nslots, 3, N)
