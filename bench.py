@@ -186,12 +186,20 @@ def main():
         Xb = q_start[:S_slabs].permute(1, 0, 2).reshape(3, S_slabs * n).contiguous()
         Pb = p_start[:S_slabs].permute(1, 0, 2).reshape(3, S_slabs * n).contiguous()
         step0 = np.arange(S_slabs) * L
-        xb, pb = Xb.clone(), Pb.clone()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.langevin_steps(S.POT_FS_SNAP, xb, pb, off, boxes, L, step0=step0, **kw)
-        torch.cuda.synchronize()
-        t_fine = time.perf_counter() - t0
+
+        def fine_batch(**scheme):
+            # one untimed call (captures the launch sequence), then one timed call
+            for timed in (False, True):
+                xb, pb = Xb.clone(), Pb.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.langevin_steps(S.POT_FS_SNAP, xb, pb, off, boxes, L, step0=step0, **kw, **scheme)
+                torch.cuda.synchronize()
+            return time.perf_counter() - t0
+
+        t_fine = fine_batch()
+        # the paper's own integrator (modified BBK, robust temperature schedule), same batch
+        t_fine_bbk = fine_batch(scheme="bbk", cT=(3.0, 1.0))
         ns = min(args.per_slab_sample, S_slabs)
         xs, ps = q_start[0].clone(), p_start[0].clone()
         torch.cuda.synchronize()
@@ -203,6 +211,7 @@ def main():
         torch.cuda.synchronize()
         t_slab = (time.perf_counter() - t0) / ns
         extras = {"fine_batch_atom_steps_per_s": fine_atom_steps / t_fine,
+                  "fine_batch_bbk_atom_steps_per_s": fine_atom_steps / t_fine_bbk,
                   "per_slab_atom_steps_per_s": n * L / t_slab,
                   "batched_vs_per_slab": (fine_atom_steps / t_fine) / (n * L / t_slab)}
 
