@@ -88,6 +88,55 @@ def summarize_trace(path, top=16):
                                                     100 * sum(v) / tot))
 
 
+def pmc_probe(S, W, J, S_slabs):
+    """Two SNAP force evaluations of the batch (distinct 1025-atom slab states) and a plain
+    512 MiB device copy whose byte counters calibrate FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    wl = W.slabs_1025(n_slabs=S_slabs, seed=1, J=J)
+    n = wl["xs"][0].shape[1]
+    X = torch.tensor(np.concatenate(wl["xs"], axis=1), device="cuda")
+    off = np.arange(S_slabs + 1, dtype=np.int32) * n
+    boxes = np.tile(wl["box"], (S_slabs, 1))
+    ctx = S.context(0)
+    for _ in range(2):
+        ctx.snap_forces(X, off, boxes, J, wl["beta"])
+    torch.cuda.synchronize()
+    ctx.bispectrum(X, off, boxes, J, wl["beta"])
+    pairs = ctx.pair_count()
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"atoms": S_slabs * n, "pairs": pairs, "copy_bytes": a.numel() * 8}), flush=True)
+
+
+# HBM traffic per unit of the SNAP kernels, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# passes over `bench.py --pmc-probe` (per dispatch, 64 x 1025 atoms, 1.71 M pairs), each
+# scaled by what the counter reads for a 512 MiB device copy in the same process (FETCH
+# x 2.0, WRITE x 1.0).  A figure holds only for the kernel source it was taken on (sha256
+# of the file); after a change the traffic is reported as null until it is measured again.
+TRAFFIC = {
+    "adjoint": ("paper_2212_10508_amd/csrc/adjoint.hip",
+                "adb0e5866e03e9d5c8f6ee0a9ef34c004b054ba23a024de9ea409a7f4825cd9a", 4939.7, "atom"),
+    "dedr": ("paper_2212_10508_amd/csrc/kernels.hip",
+             "adf182ee2072cca4737f00dc4f51bec8bf20ced3a67dbe16b5235cf641b5a22e", 448.5, "pair"),
+    "density": ("paper_2212_10508_amd/csrc/kernels.hip",
+                "adf182ee2072cca4737f00dc4f51bec8bf20ced3a67dbe16b5235cf641b5a22e", 300.4, "pair"),
+}
+
+
+def traffic_per_unit(kernel):
+    import hashlib
+    path, sha, per_unit, unit = TRAFFIC[kernel]
+    try:
+        with open(os.path.join(ROOT, path), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != sha:
+                return None, unit
+    except OSError:
+        return None, unit
+    return per_unit, unit
+
+
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--summarize-trace":
         summarize_trace(sys.argv[2])
@@ -100,6 +149,9 @@ def main():
     ap.add_argument("--L", type=int, default=100)
     ap.add_argument("--per-slab-sample", type=int, default=4, help="slabs timed one by one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only run two SNAP force evaluations of the 64 x 1025-atom batch and a 512 MiB device "
+                         "copy (the calibration of the HBM byte counters), for a rocprofv3 --pmc pass")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fine-batch-alone and per-slab timings (then every SNAP launch of the "
                          "process belongs to a parareal iteration, e.g. for a kernel-trace profile)")
@@ -115,6 +167,9 @@ def main():
 
     J = 8
     S_slabs, L = args.slabs, args.L
+    if args.pmc_probe:
+        pmc_probe(S, W, J, S_slabs)
+        return
     wl = W.slabs_1025(n_slabs=1, seed=1, J=J)
     x0, p0, box, beta = wl["xs"][0], wl["ps"][0], wl["box"], wl["beta"]
     n = x0.shape[1]
@@ -179,6 +234,9 @@ def main():
                    "tflops": (flops[k] / (prof[k][0] * 1e-3) / 1e12) if k in flops else None}
                for k in prof}
     achieved = kernels[dom]["tflops"]
+    per_unit, unit = traffic_per_unit(dom)
+    units_per_launch = (atoms if unit == "atom" else n_pairs) * evals / max(kernels[dom]["launches"], 1)
+    traffic = per_unit * units_per_launch if per_unit is not None else None
 
     extras = {}
     if not args.no_extras:
@@ -233,7 +291,8 @@ def main():
                    "atoms": n, "slabs": S_slabs, "L": L, "twojmax": J, "pairs": n_pairs,
                    "mean_neighbours": n_pairs / atoms},
         "roofline": {"bound": "alu", "kernel": kname[dom], "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                     "traffic_bytes_per_" + unit: per_unit,
                      "avg_launch_ms": kernels[dom]["avg_ms"], "gflop_per_launch": kernels[dom]["gflop_per_launch"]},
         "kernels": kernels,
     }
