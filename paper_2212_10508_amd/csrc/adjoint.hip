@@ -135,13 +135,21 @@ __device__ __forceinline__ void do_block(int tm, const double2 *__restrict__ lds
     const double *cg = cgm + MO;
     int off = coef_off[(tm + J) * NB + BI];
     for (int tm1 = lo; tm1 <= hi; tm1 += 2, off += NCP) {
+        // The motif's coupling constants are loop-invariant; left to itself the compiler
+        // hoists them out of this loop, runs out of scalar registers and parks them in
+        // vector-register lanes (two v_readlane per constant, one per FMA pair).  An
+        // offset the compiler cannot see through keeps the scalar loads inside the loop,
+        // so every FMA takes its constant straight from a scalar register.
+        int opq = 0;
+        asm volatile("" : "+s"(opq));
+        const double *cgi = cg + opq;
         double2 r1[N1 + 1], r2[N2 + 1];
         load_row<N1>(lds, (tm1 + N1) / 2, r1);
         load_row<N2>(lds, (tm - tm1 + N2) / 2, r2);
         double2 c[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) c[q] = make_double2(0.0, 0.0);
-        motif<J, N1, N2>(r1, r2, cg, c);
+        motif<J, N1, N2>(r1, r2, cgi, c);
 #pragma unroll
         for (int n = cpl_lo(N1, N2); n <= cpl_hi(J, N1, N2); n += 2) {
             const double w = coef[off + (n - cpl_lo(N1, N2)) / 2];
