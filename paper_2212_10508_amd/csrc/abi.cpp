@@ -9,8 +9,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
 #include <map>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/snapmd.h"
@@ -88,13 +91,15 @@ struct snapmd_ctx {
         hipGraphExec_t exec;
         uint64_t last_use;
     };
-    std::vector<GraphEntry> graphs;
-    hipStream_t cap_stream = nullptr;
+    std::vector<GraphEntry> graphs[2];   // one cache per workspace (w, wc): the two may be
+    hipStream_t cap_stream[2] = {};      // launched from different host threads
+    std::mutex err_mu;
     hipStream_t sweep_stream = nullptr;  // the coarse sweep, overlapping the batched propagation
+    hipStream_t coarse_stream = nullptr; // the batched coarse propagation of a parareal iteration
     hipStream_t fork_st = nullptr;       // Finnis-Sinclair pass beside the SNAP chain
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<hipEvent_t> pipe_ev;
-    uint64_t graph_clock = 0;
+    uint64_t graph_clock[2] = {};
 };
 
 namespace {
@@ -105,7 +110,10 @@ int fail(snapmd_ctx *c, int code, const char *fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    if (c) c->err = buf;
+    if (c) {
+        std::lock_guard<std::mutex> lk(c->err_mu);
+        c->err = buf;
+    }
     return code;
 }
 
@@ -117,8 +125,10 @@ int fail(snapmd_ctx *c, int code, const char *fmt, ...) {
     } while (0)
 
 void drop_graphs(snapmd_ctx *ctx) {
-    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
-    ctx->graphs.clear();
+    for (auto &c : ctx->graphs) {
+        for (auto &g : c) (void)hipGraphExecDestroy(g.exec);
+        c.clear();
+    }
 }
 
 // (Re)allocate a device buffer.  Freeing one invalidates every captured graph.
@@ -495,6 +505,16 @@ void run_langevin(snapmd_ctx *ctx, Work &w, double *f, int potential, const Batc
     }
 }
 
+// Cell grids (and their buffers) of the neighbour lists a propagation of the batch uses;
+// set up outside any capture.  Once set up for a batch and cutoff this does nothing.
+int prepare_propagation_cells(snapmd_ctx *ctx, Work &w, int potential, const BatchDev &bd, const FsParams &fp,
+                              const SnapDev &sd, hipStream_t st) {
+    BatchDev bc = bd;
+    const double rl = (potential == SNAPMD_POT_FS_SNAP ? std::max(sd.gp.rcut, std::max(fp.d, fp.c))
+                                                       : std::max(fp.d, fp.c)) + kSkin;
+    return prepare_cells(ctx, w, bc, rl, st);
+}
+
 // run_langevin through a cached hipGraph: the whole launch sequence of n_steps steps is
 // captured once per key (pointers, sizes, parameters baked into the kernel arguments)
 // and replayed afterwards.  The captured sequence contains kernels only.
@@ -507,12 +527,8 @@ int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const
         return SNAPMD_OK;
     }
     {
-        // cell grids and their buffers are set up outside any capture
-        BatchDev bc = bd;
-        const double rl = (potential == SNAPMD_POT_FS_SNAP ? std::max(sd.gp.rcut, std::max(fp.d, fp.c))
-                                                           : std::max(fp.d, fp.c)) + kSkin;
         int rc;
-        if ((rc = prepare_cells(ctx, w, bc, rl, st))) return rc;
+        if ((rc = prepare_propagation_cells(ctx, w, potential, bd, fp, sd, st))) return rc;
     }
     auto u = [](const void *q) { return (uint64_t)(uintptr_t)q; };
     auto d = [](double v) {
@@ -530,34 +546,36 @@ int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const
                                u(sd.nrm), u(sd.adj.coef), u(sd.adj.cgm), u(sd.adj.roles)};
         key.insert(key.end(), sk, sk + 9);
     }
-    ++ctx->graph_clock;
-    for (auto &g : ctx->graphs)
+    const int ci = (&w == &ctx->wc) ? 1 : 0;
+    auto &cache = ctx->graphs[ci];
+    const uint64_t now = ++ctx->graph_clock[ci];
+    for (auto &g : cache)
         if (g.key == key) {
-            g.last_use = ctx->graph_clock;
+            g.last_use = now;
             HIPCHK(hipGraphLaunch(g.exec, st));
             return SNAPMD_OK;
         }
     // captured on a stream of the context (the caller's may be the null stream), then
     // launched on the caller's stream
-    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipStream_t &cs = ctx->cap_stream[ci];
+    if (!cs) HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipGraph_t graph;
-    HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-    const int prof_on = ctx->prof.enabled;
-    ctx->prof.enabled = 0;  // no event records inside a graph
-    run_langevin(ctx, w, f, potential, bd, fp, sd, ld, n_steps, x, p, ctx->cap_stream);
-    ctx->prof.enabled = prof_on;
-    HIPCHK(hipStreamEndCapture(ctx->cap_stream, &graph));
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    ++KernelProf::suppress;  // no event records inside a graph
+    run_langevin(ctx, w, f, potential, bd, fp, sd, ld, n_steps, x, p, cs);
+    --KernelProf::suppress;
+    HIPCHK(hipStreamEndCapture(cs, &graph));
     hipGraphExec_t exec;
     hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(ctx, SNAPMD_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
-    if (ctx->graphs.size() >= 32) {
-        auto it = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+    if (cache.size() >= 32) {
+        auto it = std::min_element(cache.begin(), cache.end(),
                                    [](const auto &a, const auto &b) { return a.last_use < b.last_use; });
         (void)hipGraphExecDestroy(it->exec);
-        ctx->graphs.erase(it);
+        cache.erase(it);
     }
-    ctx->graphs.push_back({key, exec, ctx->graph_clock});
+    cache.push_back({key, exec, now});
     HIPCHK(hipGraphLaunch(exec, st));
     return SNAPMD_OK;
 }
@@ -661,8 +679,10 @@ void snapmd_destroy(snapmd_ctx *ctx) {
     for (void *p : ctx->allocs) (void)hipFree(p);
     if (ctx->h_out) (void)hipHostFree(ctx->h_out);
     drop_graphs(ctx);
-    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    for (hipStream_t c : ctx->cap_stream)
+        if (c) (void)hipStreamDestroy(c);
     if (ctx->sweep_stream) (void)hipStreamDestroy(ctx->sweep_stream);
+    if (ctx->coarse_stream) (void)hipStreamDestroy(ctx->coarse_stream);
     if (ctx->fork_st) (void)hipStreamDestroy(ctx->fork_st);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
@@ -902,8 +922,11 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         // as soon as the SNAP propagation of chunk c is done, overlapping the later chunks.
         const std::vector<int> plan = lds_sweep ? chunk_plan(S, N, ctx->n_cus) : std::vector<int>{S};
         if (!ctx->sweep_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->sweep_stream, hipStreamNonBlocking));
-        const int ne = (int)plan.size();  // events: one per chunk, start, end
-        for (int c = (int)ctx->pipe_ev.size(); c < ne + 2; ++c) {
+        if (!ctx->coarse_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->coarse_stream, hipStreamNonBlocking));
+        // events: fine chunk c done [0, ne), sweep done (ne), start (ne + 1), coarse chunk c
+        // done [ne + 2, 2 ne + 2)
+        const int ne = (int)plan.size();
+        for (int c = (int)ctx->pipe_ev.size(); c < 2 * ne + 2; ++c) {
             hipEvent_t e;
             HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
             ctx->pipe_ev.push_back(e);
@@ -927,44 +950,122 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
             lc.sb1 += s0;
             return nc;
         };
+        hipStream_t s3 = ctx->coarse_stream;
         HIPCHK(hipEventRecord(ctx->pipe_ev[ne + 1], st));
         HIPCHK(hipStreamWaitEvent(s2, ctx->pipe_ev[ne + 1], 0));
-        for (int c = 0, s0 = 0; c < (int)plan.size(); s0 += plan[c], ++c) {  // coarse (second stream)
-            BatchDev bc;
-            LangevinDev lc;
-            const int nc = chunk_of(c, s0, bc, lc);
-            const size_t o = 3 * (size_t)N * s0;
-            launch_slabs_to_batch(nc, N, qs + s0 * slot, ctx->pr_xc.p + o, s2);
-            launch_slabs_to_batch(nc, N, ps + s0 * slot, ctx->pr_pc.p + o, s2);
-            if ((rc = run_langevin_graph(ctx, ctx->wc, ctx->d_fc, SNAPMD_POT_FS, bc, fp, sd, lc, L, ctx->pr_xc.p + o,
-                                         ctx->pr_pc.p + o, s2)))
-                return rc;
-        }
-        for (int c = 0, s0 = 0; c < (int)plan.size(); s0 += plan[c], ++c) {
+        HIPCHK(hipStreamWaitEvent(s3, ctx->pipe_ev[ne + 1], 0));
+        // Three streams, each fed by its own host thread: the fine propagation of the
+        // chunks (caller's stream, this thread), their coarse propagation (s3) and the
+        // jumps and sweep of chunk c once both propagations of chunk c are done (s2).  A
+        // replay of a long captured launch sequence can hold the calling thread until the
+        // device has worked through most of it, so no stream's queueing may wait behind
+        // another's.  Everything the replays need (buffers, cell grids) is set up here
+        // first: neither helper allocates (an allocation drops the captured graphs).
+        if ((rc = prepare_propagation_cells(ctx, ctx->w, SNAPMD_POT_FS_SNAP, bd, fp, sd, st)) ||
+            (rc = prepare_propagation_cells(ctx, ctx->wc, SNAPMD_POT_FS, bd, fp, sd, st)))
+            return rc;
+        std::mutex mu;
+        std::condition_variable cv;
+        int done_f = 0, done_c = 0;  // chunks whose fine / coarse propagation is queued
+        bool stop = false;           // a thread failed: the others queue nothing more
+        auto publish = [&](int &counter, int value) {
+            std::lock_guard<std::mutex> lk(mu);
+            counter = value;
+            cv.notify_all();
+        };
+        auto halt = [&]() {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+            cv.notify_all();
+        };
+        struct Quiet {  // kernel timing covers the caller's stream only
+            Quiet() { ++KernelProf::suppress; }
+            ~Quiet() { --KernelProf::suppress; }
+        };
+        auto coarse_side = [&]() -> int {
+            HIPCHK(hipSetDevice(ctx->device));
+            Quiet quiet;
+            int r;
+            for (int c = 0, s0 = 0; c < (int)plan.size(); s0 += plan[c], ++c) {
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    if (stop) return SNAPMD_OK;
+                }
+                BatchDev bc;
+                LangevinDev lc;
+                const int nc = chunk_of(c, s0, bc, lc);
+                const size_t o = 3 * (size_t)N * s0;
+                launch_slabs_to_batch(nc, N, qs + s0 * slot, ctx->pr_xc.p + o, s3);
+                launch_slabs_to_batch(nc, N, ps + s0 * slot, ctx->pr_pc.p + o, s3);
+                if ((r = run_langevin_graph(ctx, ctx->wc, ctx->d_fc, SNAPMD_POT_FS, bc, fp, sd, lc, L,
+                                            ctx->pr_xc.p + o, ctx->pr_pc.p + o, s3)))
+                    return r;
+                HIPCHK(hipEventRecord(ctx->pipe_ev[ne + 2 + c], s3));
+                publish(done_c, c + 1);
+            }
+            return SNAPMD_OK;
+        };
+        auto sweep_side = [&]() -> int {
+            HIPCHK(hipSetDevice(ctx->device));
+            Quiet quiet;
+            int r;
+            for (int c = 0, s0 = 0; c < (int)plan.size(); s0 += plan[c], ++c) {
+                {
+                    std::unique_lock<std::mutex> lk(mu);
+                    cv.wait(lk, [&] { return stop || (done_f > c && done_c > c); });
+                    if (stop) return SNAPMD_OK;
+                }
+                const int nc = plan[c];
+                const size_t o = 3 * (size_t)N * s0;
+                HIPCHK(hipStreamWaitEvent(s2, ctx->pipe_ev[c], 0));
+                HIPCHK(hipStreamWaitEvent(s2, ctx->pipe_ev[ne + 2 + c], 0));
+                launch_jumps(3 * (size_t)nc * N, ctx->pr_xf.p + o, ctx->pr_xc.p + o, s2);
+                launch_jumps(3 * (size_t)nc * N, ctx->pr_pf.p + o, ctx->pr_pc.p + o, s2);
+                if (lds_sweep) {
+                    SweepLaunch sc = sw;
+                    sc.n_in = n_in + s0;
+                    sc.n_fi = n_in + s0 + nc;
+                    sc.jq = ctx->pr_xf.p + o;
+                    sc.jp = ctx->pr_pf.p + o;
+                    sc.noise = sw.noise + (size_t)s0 * L * 3 * N;
+                    if ((r = sweep_launch(sc, s2))) return r;
+                }
+            }
+            HIPCHK(hipEventRecord(ctx->pipe_ev[ne], s2));
+            return SNAPMD_OK;
+        };
+        int rc1 = SNAPMD_OK, rc2 = SNAPMD_OK, rc3 = SNAPMD_OK;
+        std::thread t_coarse([&] {
+            rc3 = coarse_side();
+            if (rc3) halt();
+        });
+        std::thread t_sweep([&] {
+            rc2 = sweep_side();
+            if (rc2) halt();
+        });
+        for (int c = 0, s0 = 0; c < (int)plan.size(); s0 += plan[c], ++c) {  // fine (caller's stream)
             BatchDev bc;
             LangevinDev lc;
             const int nc = chunk_of(c, s0, bc, lc);
             const size_t o = 3 * (size_t)N * s0;
             launch_slabs_to_batch(nc, N, qs + s0 * slot, ctx->pr_xf.p + o, st);
             launch_slabs_to_batch(nc, N, ps + s0 * slot, ctx->pr_pf.p + o, st);
-            if ((rc = run_langevin_graph(ctx, ctx->w, ctx->d_f, SNAPMD_POT_FS_SNAP, bc, fp, sd, lc, L,
-                                         ctx->pr_xf.p + o, ctx->pr_pf.p + o, st)))
-                return rc;
-            HIPCHK(hipEventRecord(ctx->pipe_ev[c], st));
-            HIPCHK(hipStreamWaitEvent(s2, ctx->pipe_ev[c], 0));
-            launch_jumps(3 * (size_t)nc * N, ctx->pr_xf.p + o, ctx->pr_xc.p + o, s2);
-            launch_jumps(3 * (size_t)nc * N, ctx->pr_pf.p + o, ctx->pr_pc.p + o, s2);
-            if (lds_sweep) {
-                SweepLaunch sc = sw;
-                sc.n_in = n_in + s0;
-                sc.n_fi = n_in + s0 + nc;
-                sc.jq = ctx->pr_xf.p + o;
-                sc.jp = ctx->pr_pf.p + o;
-                sc.noise = sw.noise + (size_t)s0 * L * 3 * N;
-                if ((rc = sweep_launch(sc, s2))) return rc;
+            if ((rc1 = run_langevin_graph(ctx, ctx->w, ctx->d_f, SNAPMD_POT_FS_SNAP, bc, fp, sd, lc, L,
+                                          ctx->pr_xf.p + o, ctx->pr_pf.p + o, st)))
+                break;
+            const hipError_t e = hipEventRecord(ctx->pipe_ev[c], st);
+            if (e != hipSuccess) {
+                rc1 = fail(ctx, SNAPMD_EHIP, "hipEventRecord failed: %s", hipGetErrorString(e));
+                break;
             }
+            publish(done_f, c + 1);
         }
-        HIPCHK(hipEventRecord(ctx->pipe_ev[ne], s2));
+        if (rc1) halt();
+        t_coarse.join();
+        t_sweep.join();
+        if (rc1) return rc1;
+        if (rc3) return rc3;
+        if (rc2) return rc2;
         HIPCHK(hipStreamWaitEvent(st, ctx->pipe_ev[ne], 0));
         sw.jq = ctx->pr_xf.p;
         sw.jp = ctx->pr_pf.p;

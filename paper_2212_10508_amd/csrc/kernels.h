@@ -92,6 +92,9 @@ struct Work {
 enum { PROF_DEDR = 0, PROF_ADJOINT = 1, PROF_DENSITY = 2, PROF_NEIGH = 3, PROF_N = 4 };
 struct KernelProf {
     int enabled = 0;
+    // nonzero on a thread that must not record (graph capture, or a thread launching
+    // beside the one being timed)
+    static inline thread_local int suppress = 0;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     std::vector<int> ids;
@@ -105,14 +108,14 @@ struct KernelProf {
         return pool[used++];
     }
     void begin(int id, hipStream_t st) {
-        if (!enabled) return;
+        if (!enabled || suppress) return;
         hipEvent_t e = get();
         (void)hipEventRecord(e, st);
         ids.push_back(id);
         ev0.push_back(e);
     }
     void end(hipStream_t st) {
-        if (!enabled) return;
+        if (!enabled || suppress) return;
         hipEvent_t e = get();
         (void)hipEventRecord(e, st);
         ev1.push_back(e);
