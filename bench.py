@@ -143,12 +143,13 @@ def main():
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--slabs", type=int, default=64)
     ap.add_argument("--L", type=int, default=100)
     ap.add_argument("--per-slab-sample", type=int, default=4, help="slabs timed one by one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in slab chunk plan")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run two SNAP force evaluations of the 64 x 1025-atom batch and a 512 MiB device "
                          "copy (the calibration of the HBM byte counters), for a rocprofv3 --pmc pass")
@@ -201,6 +202,24 @@ def main():
     for w in range(args.warmup):
         d = iteration()
         log("warmup %d: delta %.3e" % (w, d))
+    # slab chunks of the pipelined iteration, timed on this workload (untimed setup)
+    n_cus = torch.cuda.get_device_properties(0).multi_processor_count
+    builtin_plan = ctx.chunk_plan(S_slabs, n)
+    autotune = None
+    if not args.no_tune:
+        from paper_2212_10508_amd import tune
+
+        def timed_iteration():
+            iteration()
+            torch.cuda.synchronize()
+
+        plan, times = tune.tune_chunk_plan(ctx, timed_iteration, S_slabs, n, n_cus, log=log)
+        autotune = {"plans_timed": len(times), "builtin_plan": builtin_plan,
+                    "builtin_ms": times[tuple(builtin_plan)] * 1e3, "best_plan": plan,
+                    "best_ms": times[tuple(plan)] * 1e3}
+        log("chunk plan: %s (%.2f ms; built-in %s %.2f ms)" % (plan, autotune["best_ms"], builtin_plan,
+                                                              autotune["builtin_ms"]))
+    chunk_plan = ctx.chunk_plan(S_slabs, n)
     q_cur.copy_(q_start)
     p_cur.copy_(p_start)
     torch.cuda.synchronize()
@@ -289,7 +308,7 @@ def main():
         "config": {"workload": "parareal iteration, 64 slabs x 1025-atom W bcc + <111> SIA, SNAP twojmax 8 "
                                "+ Finnis-Sinclair fine / FS coarse, L=100 BAOAB steps, 1 fs, 1000 K",
                    "atoms": n, "slabs": S_slabs, "L": L, "twojmax": J, "pairs": n_pairs,
-                   "mean_neighbours": n_pairs / atoms},
+                   "mean_neighbours": n_pairs / atoms, "chunk_plan": chunk_plan},
         "roofline": {"bound": "alu", "kernel": kname[dom], "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "traffic_bytes_per_" + unit: per_unit,
@@ -297,6 +316,8 @@ def main():
         "kernels": kernels,
     }
     out.update(extras)
+    if autotune:
+        out["autotune"] = autotune
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(W.slabs_1025(n_slabs=1, seed=1, J=J), J)

@@ -209,11 +209,24 @@ int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_bat
 /* Launch mode of langevin_steps and of the fine and coarse propagation of
  * parareal_iterate.  enable = 1 (the default): the n_steps launch sequence is captured
  * once into a hipGraph, cached per context (keyed by sizes, parameters and device
- * pointers; at most 32 kept, least recently used dropped; every cached graph is dropped
+ * pointers; at most 96 kept per workspace, least recently used dropped; every cached graph is dropped
  * when the context reallocates a work buffer) and replayed on the caller's stream.
  * enable = 0: kernels are launched one by one.  Results are identical either way.
  * While snapmd_profile is on, SNAP propagation is launched one by one. */
 int snapmd_use_graphs(snapmd_ctx *ctx, int enable);
+
+/* Slab chunks of parareal_iterate (tuning, not part of the method).  The pipelined path
+ * of parareal_iterate (systems the on-device sweep handles, BAOAB) propagates the S slabs
+ * of a window in chunks of consecutive slabs: the SNAP propagation of chunk c runs while
+ * the sweep works through chunk c - 1.  snapmd_set_chunk_plan(ctx, sizes, n) makes every
+ * later window of exactly sizes[0] + .. + sizes[n-1] slabs use those chunks, in order;
+ * windows of other lengths, and n = 0 (sizes ignored), use the built-in plan (chunks of
+ * whole adjoint rounds).  1 <= n <= 64 and every size >= 1, else SNAPMD_EINVAL.
+ * snapmd_chunk_plan writes the plan that a window of S slabs of N atoms would use into
+ * sizes[0 .. *n) (sizes holds at least 64 entries).  The results of parareal_iterate do
+ * not depend on the plan (tested); its run time does. */
+int snapmd_set_chunk_plan(snapmd_ctx *ctx, const int32_t *sizes, int32_t n);
+int snapmd_chunk_plan(snapmd_ctx *ctx, int32_t S, int32_t N, int32_t *sizes, int32_t *n);
 
 /* Measurement support (not part of the propagation):
  * snapmd_profile(ctx, 1) starts recording HIP events around the SNAP kernels and the

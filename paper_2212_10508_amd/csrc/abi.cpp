@@ -100,6 +100,7 @@ struct snapmd_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<hipEvent_t> pipe_ev;
     uint64_t graph_clock[2] = {};
+    std::vector<int> chunk_override;     // slab chunks set by snapmd_set_chunk_plan (empty: built in)
 };
 
 namespace {
@@ -403,6 +404,15 @@ std::vector<int> chunk_plan(int S, int N, int cus) {
     return sz;
 }
 
+// The chunks of a window of S slabs: the plan set by snapmd_set_chunk_plan when it covers
+// exactly S slabs, else the built-in one.
+std::vector<int> window_plan(const snapmd_ctx *ctx, int S, int N) {
+    int tot = 0;
+    for (int v : ctx->chunk_override) tot += v;
+    if (!ctx->chunk_override.empty() && tot == S) return ctx->chunk_override;
+    return chunk_plan(S, N, ctx->n_cus);
+}
+
 // Cell grids (cell edge >= list cutoff rl, >= 3 cells per edge, else brute force) of the
 // current batch; rebuilt when the batch or the cutoff changes.
 int prepare_cells(snapmd_ctx *ctx, Work &w, BatchDev &bd, double rl, hipStream_t st) {
@@ -515,6 +525,8 @@ int prepare_propagation_cells(snapmd_ctx *ctx, Work &w, int potential, const Bat
     return prepare_cells(ctx, w, bc, rl, st);
 }
 
+constexpr size_t kGraphCache = 96;  // captured launch sequences kept per workspace
+
 // run_langevin through a cached hipGraph: the whole launch sequence of n_steps steps is
 // captured once per key (pointers, sizes, parameters baked into the kernel arguments)
 // and replayed afterwards.  The captured sequence contains kernels only.
@@ -569,7 +581,7 @@ int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const
     hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(ctx, SNAPMD_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
-    if (cache.size() >= 32) {
+    if (cache.size() >= kGraphCache) {
         auto it = std::min_element(cache.begin(), cache.end(),
                                    [](const auto &a, const auto &b) { return a.last_use < b.last_use; });
         (void)hipGraphExecDestroy(it->exec);
@@ -920,7 +932,7 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         // chunks runs on the caller's stream; the Finnis-Sinclair propagation, the jumps
         // and (LDS-resident case) the sweep run on a second stream, the sweep over chunk c
         // as soon as the SNAP propagation of chunk c is done, overlapping the later chunks.
-        const std::vector<int> plan = lds_sweep ? chunk_plan(S, N, ctx->n_cus) : std::vector<int>{S};
+        const std::vector<int> plan = lds_sweep ? window_plan(ctx, S, N) : std::vector<int>{S};
         if (!ctx->sweep_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->sweep_stream, hipStreamNonBlocking));
         if (!ctx->coarse_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->coarse_stream, hipStreamNonBlocking));
         // events: fine chunk c done [0, ne), sweep done (ne), start (ne + 1), coarse chunk c
@@ -1131,6 +1143,26 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         *n_fi = nfi_new;
         return SNAPMD_OK;
     }
+}
+
+int snapmd_set_chunk_plan(snapmd_ctx *ctx, const int32_t *sizes, int32_t n) {
+    if (!ctx) return SNAPMD_EINVAL;
+    if (n < 0 || n > 64) return fail(ctx, SNAPMD_EINVAL, "chunk plan: need 0 <= n <= 64 (got %d)", n);
+    if (n > 0 && !sizes) return fail(ctx, SNAPMD_EINVAL, "chunk plan: sizes is null");
+    for (int c = 0; c < n; ++c)
+        if (sizes[c] < 1) return fail(ctx, SNAPMD_EINVAL, "chunk plan: size %d of chunk %d", sizes[c], c);
+    ctx->chunk_override.assign(sizes, sizes + n);
+    return SNAPMD_OK;
+}
+
+int snapmd_chunk_plan(snapmd_ctx *ctx, int32_t S, int32_t N, int32_t *sizes, int32_t *n) {
+    if (!ctx) return SNAPMD_EINVAL;
+    if (S < 1 || N < 1 || !sizes || !n) return fail(ctx, SNAPMD_EINVAL, "chunk plan: need S, N >= 1 and outputs");
+    const std::vector<int> plan = window_plan(ctx, S, N);
+    if (plan.size() > 64) return fail(ctx, SNAPMD_EINVAL, "chunk plan: more than 64 chunks");
+    for (size_t c = 0; c < plan.size(); ++c) sizes[c] = plan[c];
+    *n = (int32_t)plan.size();
+    return SNAPMD_OK;
 }
 
 int snapmd_use_graphs(snapmd_ctx *ctx, int enable) {

@@ -90,6 +90,10 @@ def lib():
     L.snapmd_profile_read.restype = C.c_int
     L.snapmd_pair_count.argtypes = [P, C.POINTER(C.c_int64)]
     L.snapmd_pair_count.restype = C.c_int
+    L.snapmd_set_chunk_plan.argtypes = [P, C.POINTER(i32), i32]
+    L.snapmd_set_chunk_plan.restype = C.c_int
+    L.snapmd_chunk_plan.argtypes = [P, i32, i32, C.POINTER(i32), C.POINTER(i32)]
+    L.snapmd_chunk_plan.restype = C.c_int
     _lib = L
     return L
 
@@ -277,6 +281,20 @@ class Context:
         n = C.c_int64(0)
         self._check(lib().snapmd_profile_read(self.h, int(kernel), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def set_chunk_plan(self, sizes):
+        """Slab chunks of parareal_iterate for windows of sum(sizes) slabs (None or []:
+        the built-in plan)."""
+        sizes = list(sizes or [])
+        arr = (C.c_int32 * max(len(sizes), 1))(*sizes)
+        self._check(lib().snapmd_set_chunk_plan(self.h, arr, len(sizes)))
+
+    def chunk_plan(self, S, N):
+        """The chunks parareal_iterate uses for a window of S slabs of N atoms."""
+        arr = (C.c_int32 * 64)()
+        n = C.c_int32(0)
+        self._check(lib().snapmd_chunk_plan(self.h, int(S), int(N), arr, C.byref(n)))
+        return list(arr[:n.value])
 
     def pair_count(self):
         n = C.c_int64(0)

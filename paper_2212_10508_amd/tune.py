@@ -1,0 +1,104 @@
+"""Autotuner of the slab chunks of parareal_iterate.
+
+The pipelined parareal iteration propagates the S slabs of a window in chunks of
+consecutive slabs; the sequential coarse sweep over chunk c overlaps the SNAP
+propagation of chunk c + 1, so only the sweep of the last chunk is exposed.  Small
+chunks expose less sweep but fill the device worse (the SNAP adjoint runs one
+64-atom workgroup per compute unit, so a chunk costs about as much as the whole
+adjoint rounds it occupies).  The best split depends on the atom count, the number
+of compute units and the relative speed of the sweep, so it is measured: every
+candidate plan is timed on the caller's own iteration and the fastest is kept.
+"""
+import time
+
+
+def candidate_plans(S, N, n_cus, builtin=None, max_chunks=4, limit=24):
+    """Chunk plans to time for a window of S slabs of N atoms: chunks of whole adjoint
+    rounds (R slabs fill one round of 64-atom workgroups on the compute units left
+    to the SNAP pass), or one or two slabs short of them, in non-increasing order, and
+    a last chunk of at most R slabs."""
+    R = max(1, ((n_cus - 16) * 64) // max(N, 1))
+    sizes = sorted({v for k in (1, 2, 3) for v in (k * R - 2, k * R - 1, k * R) if 1 <= v < S}, reverse=True)
+    plans = []
+
+    def rec(prefix, left):
+        if len(plans) >= 4 * limit:
+            return
+        if 1 <= left <= R and prefix:
+            plans.append(prefix + [left])
+        if len(prefix) + 1 >= max_chunks:
+            return
+        for v in sizes:
+            if v < left and (not prefix or v <= prefix[-1]):
+                rec(prefix + [v], left - v)
+
+    rec([], S)
+    # prefer few chunks and a small last chunk; keep the built-in plan
+    plans.sort(key=lambda p: (len(p), p[-1]))
+    out = []
+    if builtin:
+        out.append(list(builtin))
+    for p in plans:
+        if p not in out:
+            out.append(p)
+        if len(out) >= limit:
+            break
+    return out
+
+
+def tune_chunk_plan(ctx, run_iteration, S, N, n_cus, passes=2, limit=16, log=None):
+    """Time run_iteration() (one parareal iteration over a window of S slabs, synchronised
+    by the caller) under each candidate plan, refine the best by moving one slab between
+    neighbouring chunks, and keep it only if it beats the built-in plan when the two are
+    timed alternately.  Every plan runs once untimed first (its launch sequences are
+    captured then), and candidates are timed in interleaved passes, so a slow drift of
+    the device's speed does not favour the plans timed last.  Sets the chosen plan on ctx
+    and returns (plan, {tuple(plan): seconds})."""
+    builtin = list(ctx.chunk_plan(S, N))
+    times = {}
+
+    def once(plan):
+        ctx.set_chunk_plan(list(plan))
+        t0 = time.perf_counter()
+        run_iteration()
+        return time.perf_counter() - t0
+
+    def record(plan, t):
+        key = tuple(plan)
+        times[key] = min(times.get(key, float("inf")), t)
+
+    cands = [tuple(p) for p in candidate_plans(S, N, n_cus, builtin=builtin, limit=limit)]
+    for p in cands:
+        once(p)
+    for _ in range(passes):
+        for p in cands:
+            record(p, once(p))
+    best = min(times, key=times.get)
+    improved = True
+    while improved:
+        improved = False
+        for c in range(len(best) - 1):
+            for d in (1, -1):
+                p = list(best)
+                p[c] += d
+                p[c + 1] -= d
+                if min(p) < 1 or tuple(p) in times:
+                    continue
+                once(p)
+                for _ in range(passes):
+                    record(p, once(p))
+                if times[tuple(p)] < times[best]:
+                    best, improved = tuple(p), True
+    # final check against the built-in plan, timed alternately
+    tb = tn = float("inf")
+    for _ in range(passes + 1):
+        tb = min(tb, once(best))
+        tn = min(tn, once(builtin))
+    times[best] = min(times[best], tb)
+    times[tuple(builtin)] = min(times[tuple(builtin)], tn)
+    chosen = list(best) if tb < tn else builtin
+    if log:
+        for p in sorted(times, key=times.get):
+            log("chunk plan %s: %.2f ms" % (list(p), times[p] * 1e3))
+    ctx.set_chunk_plan(chosen)
+    return chosen, times

@@ -212,3 +212,38 @@ def test_bench_configuration_sampled(S):
     ref_p = cn[1] + fo[1] - co[1]
     assert np.abs(qh[m + 1] - ref_q).max() < QTOL
     assert np.abs(ph[m + 1] - ref_p).max() < QTOL * np.abs(ref_p).max()
+
+
+def test_chunk_plans_give_identical_iterates(S):
+    """The slab chunks of the pipelined iteration (tuning only) do not change its results:
+    one corrected iteration under several plans, bitwise against the built-in plan."""
+    x, p, box, kw, prop = _setup(J=4, seed=8)
+    N, L = 8, 3
+    n = x.shape[1]
+    ctx = S.context()
+    q0 = torch.zeros((N + 1, 3, n), dtype=torch.float64, device="cuda")
+    p0 = torch.zeros_like(q0)
+    q0[0], p0[0] = dev(x), dev(p)
+    ctx.parareal_iterate(None, None, q0, p0, box, L, 0, N, 1e100, **kw)
+    results = []
+    for plan in (None, [8], [4, 4], [5, 2, 1], [1] * 8):
+        ctx.set_chunk_plan(plan)
+        if plan:
+            assert ctx.chunk_plan(N, n) == plan
+        q, pp = q0.clone(), p0.clone()
+        qp, ppv = torch.zeros_like(q), torch.zeros_like(q)
+        d, nfi = ctx.parareal_iterate(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
+        torch.cuda.synchronize()
+        results.append((d, nfi, q.cpu().numpy(), pp.cpu().numpy()))
+    ctx.set_chunk_plan(None)
+    d0, n0, qa, pa = results[0]
+    for d, nfi, qb, pb in results[1:]:
+        assert nfi == n0 and d == d0
+        assert np.array_equal(qa, qb) and np.array_equal(pa, pb)
+    # a plan that does not cover the window is ignored; invalid plans are refused
+    builtin = ctx.chunk_plan(N, n)
+    ctx.set_chunk_plan([3, 3])
+    assert ctx.chunk_plan(N, n) == builtin and ctx.chunk_plan(6, n) == [3, 3]
+    with pytest.raises(S.SnapmdError):
+        ctx.set_chunk_plan([2, 0])
+    ctx.set_chunk_plan(None)
