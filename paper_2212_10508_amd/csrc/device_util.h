@@ -13,6 +13,13 @@ __device__ __forceinline__ double2 cmul2(double2 a, double2 b, double2 c, double
     return make_double2(fma(a.x, b.x, fma(-a.y, b.y, fma(c.x, d.x, -c.y * d.y))),
                         fma(a.x, b.y, fma(a.y, b.x, fma(c.x, d.y, c.y * d.x))));
 }
+// a*b + c*d + e*f + g*h as one FMA chain per component (no separate products or adds)
+__device__ __forceinline__ double2 cmul4(double2 a, double2 b, double2 c, double2 d, double2 e, double2 f,
+                                         double2 g, double2 h) {
+    return make_double2(
+        fma(a.x, b.x, fma(-a.y, b.y, fma(c.x, d.x, fma(-c.y, d.y, fma(e.x, f.x, fma(-e.y, f.y, fma(g.x, h.x, -g.y * h.y))))))),
+        fma(a.x, b.y, fma(a.y, b.x, fma(c.x, d.y, fma(c.y, d.x, fma(e.x, f.y, fma(e.y, f.x, fma(g.x, h.y, g.y * h.x))))))));
+}
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
 // 1/sqrt(r2) for a normal r2 > 0: the hardware estimate (about 24 bits) refined by two
