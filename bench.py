@@ -88,6 +88,104 @@ def summarize_trace(path, top=16):
                                                     100 * sum(v) / tot))
 
 
+def other_configs(S, W, log):
+    """Throughput of the other workloads of the method (secondary measurements, each after
+    an untimed call that captures its launch sequence): the 129-atom case, 256 replicas
+    of uneven size, force matching over 512 configurations, and the fine batch of a
+    16001-atom trajectory's 32 slabs."""
+    import torch
+
+    def dev(a):
+        return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    kw0 = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, fs=W.FS_W)
+    out = {}
+    # 129 atoms (4x4x4 bcc + dumbbell), twojmax 6: one force evaluation + 100 BAOAB steps
+    wl = W.tiny_129()
+    x0, p0, n = dev(wl["x"]), dev(wl["p"]), wl["x"].shape[1]
+    xw, pw = x0.clone(), p0.clone()  # fixed buffers: the captured sequence is replayed
+
+    def c1():
+        xw.copy_(x0)
+        pw.copy_(p0)
+        S.langevin_steps(S.POT_FS_SNAP, xw, pw, [0, n], wl["box"], 100, T=1000.0, seed=1,
+                         step0=0, noise_id=0, J=6, beta=wl["beta"], **kw0)
+
+    t = timed(c1, reps=3)
+    out["tiny_129_snap6_100_steps"] = {"atom_steps_per_s": n * 100 / t, "ms": t * 1e3}
+    log("129 atoms: %.2f ms per 100 steps" % (t * 1e3))
+    # 256 replicas of 129 / 433 / 1025 atoms, own temperatures in [600, 1500] K, 1000 steps
+    wl = W.replicas_mixed(n_rep=256, seed=2)
+    X, off, B = W.pack(wl["xs"], wl["boxes"])
+    xr, pr = dev(X), dev(np.concatenate(wl["ps"], axis=1))
+    xw, pw = xr.clone(), pr.clone()
+    nid = np.arange(256)
+
+    def c3():
+        xw.copy_(xr)
+        pw.copy_(pr)
+        S.langevin_steps(S.POT_FS_SNAP, xw, pw, off, B, 1000, T=wl["T"], seed=8, step0=0,
+                         noise_id=nid, J=8, beta=wl["beta"], **kw0)
+
+    t = timed(c3, reps=1)
+    out["replicas_256_mixed_1000_steps"] = {"atoms": int(off[-1]), "atom_steps_per_s": int(off[-1]) * 1000 / t,
+                                            "s": t}
+    log("256 replicas: %.2f s per 1000 steps" % t)
+    del xr, pr, xw, pw
+    # 512 configurations (129 / 433 / 1025 atoms, 0.1 A thermal jitter), twojmax 8: energy,
+    # forces and the gradient of a force-matching loss with respect to the 56 coefficients
+    from paper_2212_10508_amd.autograd import snap_energy_forces
+    parts = [W.bcc_sia((4, 6, 8)[q % 3], jitter=0.1, seed=5000 + q) for q in range(512)]
+    X, off, B = W.pack([q[0] for q in parts], [q[1] for q in parts])
+    xg = dev(X)
+    fref = S.snap_forces(xg, off, B, 8, W.snap_beta(8, seed=1))
+    beta_t = torch.tensor(W.snap_beta(8, seed=2), dtype=torch.float64, requires_grad=True)
+
+    def c4():
+        beta_t.grad = None
+        E, F = snap_energy_forces(beta_t, xg, off, B, 8)
+        loss = ((F - fref) ** 2).sum() / F.numel()
+        loss.backward()
+
+    t = timed(c4, reps=3)
+    out["force_matching_512_configs"] = {"atoms": int(off[-1]), "configs_per_s": 512 / t, "ms": t * 1e3}
+    log("512 configurations: %.2f ms per energy + forces + dL/dbeta" % (t * 1e3))
+    del xg, fref
+    # fine batch of a 16001-atom trajectory: 32 slabs x 200 steps in one launch sequence
+    xs, ps = [], []
+    for s in range(32):
+        x, box = W.bcc_sia(20, jitter=0.05, seed=7000 + s)
+        xs.append(x)
+        ps.append(W.maxwell_momenta(x.shape[1], 1000.0, seed=7000 + s))
+    X, off, B = W.pack(xs, [box] * 32)
+    xf, pf = dev(X), dev(np.concatenate(ps, axis=1))
+    xw, pw = xf.clone(), pf.clone()
+    beta5 = W.snap_beta(8, seed=3)
+
+    def c5():
+        xw.copy_(xf)
+        pw.copy_(pf)
+        S.langevin_steps(S.POT_FS_SNAP, xw, pw, off, B, 200, T=1000.0, seed=9,
+                         step0=np.arange(32) * 200, noise_id=0, J=8, beta=beta5, **kw0)
+
+    t = timed(c5, reps=1)
+    out["fine_batch_16001x32_200_steps"] = {"atoms": int(off[-1]), "atom_steps_per_s": int(off[-1]) * 200 / t,
+                                            "s": t}
+    log("16001 atoms x 32 slabs: %.2f s per 200 steps" % t)
+    return out
+
+
 def pmc_probe(S, W, J, S_slabs):
     """Two SNAP force evaluations of the batch (distinct 1025-atom slab states) and a plain
     512 MiB device copy whose byte counters calibrate FETCH_SIZE / WRITE_SIZE."""
@@ -150,6 +248,7 @@ def main():
     ap.add_argument("--per-slab-sample", type=int, default=4, help="slabs timed one by one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in slab chunk plan")
+    ap.add_argument("--no-configs", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run two SNAP force evaluations of the 64 x 1025-atom batch and a 512 MiB device "
                          "copy (the calibration of the HBM byte counters), for a rocprofv3 --pmc pass")
@@ -316,6 +415,8 @@ def main():
         "kernels": kernels,
     }
     out.update(extras)
+    if not args.no_configs:
+        out["other_workloads"] = other_configs(S, W, log)
     if autotune:
         out["autotune"] = autotune
     if not args.no_cpu_baseline:

@@ -734,7 +734,7 @@ int snap_forces(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *ba
     if ((rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
     if (bd.N == 0) return SNAPMD_OK;
     if ((rc = neighbors(ctx, ctx->w, bd, x, snap->rcut, true, st))) return rc;
-    launch_snap(sd.J, bd, x, sd, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st);
+    launch_snap(sd.J, bd, x, sd, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st, &ctx->prof);
     return check_launch(ctx);
 }
 
