@@ -181,7 +181,6 @@ int ensure_atoms(snapmd_ctx *ctx, size_t N) {
     if ((rc = dalloc(ctx, &w.rho, cap))) return rc;
     if ((rc = dalloc(ctx, &w.geo, 20 * w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.ell, 5 * w.Pcap))) return rc;
-    if ((rc = dalloc(ctx, &w.dsep, 3 * w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.nbr_t, w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.ph, 3 * cap))) return rc;
     if ((rc = dalloc(ctx, &w.dedr, 3 * w.Pcap))) return rc;

@@ -82,7 +82,6 @@ struct Work {
     double *rho = nullptr;
     double *geo = nullptr;  // [20][Pcap]
     double *ell = nullptr;  // [5][kMaxNeigh][N] a, b, f_c by (list slot, atom)
-    double *dsep = nullptr; // [3][Pcap] minimum-image separation r_j - r_i of each pair, CSR order
     int *nbr_t = nullptr;   // [kMaxNeigh][N] neighbour j by (list slot, atom)
     double *ph = nullptr;   // [3][N] BBK: p_{l-1/2} of the running call
     double *dedr = nullptr; // [3][Pcap]

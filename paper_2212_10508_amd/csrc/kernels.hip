@@ -604,21 +604,14 @@ __device__ __forceinline__ void staircase(double2 (&P)[J + 1], double2 b, double
 // a, b and f_c of every listed pair in slot-major layout ell[f][t][i] (t = rank of the
 // pair in i's list), one thread per (slot, atom) with the atom fastest, so that the
 // density pass (lane = atom) reads slot t of 64 atoms with one coalesced load per field.
-// The pair's separation also goes to dsep in CSR order (index poff[i] + t), where the
-// dE/dr pass reads it with one coalesced load instead of a chain of dependent ones.
 __global__ void k_pair_ell(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
                            const double *__restrict__ x, const int *__restrict__ poff,
-                           const int *__restrict__ nbr_t, SnapGeoParams sp, double *__restrict__ ell,
-                           double *__restrict__ dsep, size_t Pcap) {
+                           const int *__restrict__ nbr_t, SnapGeoParams sp, double *__restrict__ ell) {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int t = (int)(q / (size_t)N), i = (int)(q - (size_t)t * N);
-    if (t >= kMaxNeigh) return;
-    const int pb = poff[i];
-    if (t >= poff[i + 1] - pb) return;
+    if (t >= kMaxNeigh || t >= poff[i + 1] - poff[i]) return;
     double d[3];
     pair_sep(x, N, box, sys_of(off, n_sys, i), i, nbr_t[q], d);
-#pragma unroll
-    for (int al = 0; al < 3; ++al) dsep[al * Pcap + pb + t] = d[al];
     double2 a, b;
     double fc;
     snap_geo_abf(d, sp, a, b, fc);
@@ -836,7 +829,7 @@ template <int J>
 __global__ void __launch_bounds__(64) k_dedr(int N, int n_sys, const int *__restrict__ off,
                                              const double *__restrict__ box, const double *__restrict__ x,
                                              const int *__restrict__ poff, const int *__restrict__ pair_i,
-                                             const double *__restrict__ dsep, SnapGeoParams sp, size_t Pcap,
+                                             const int *__restrict__ pair_j, SnapGeoParams sp, size_t Pcap,
                                              const double2 *__restrict__ ytil, double *__restrict__ dedr) {
     constexpr int NH = n_half(J);
     __shared__ double2 ys[kDedrAtoms * NH];
@@ -847,13 +840,11 @@ __global__ void __launch_bounds__(64) k_dedr(int N, int n_sys, const int *__rest
     const int i0 = pair_i[p0], na = pair_i[min(p0 + 63, P - 1)] - i0 + 1;
     const bool live = p < P;
     const int i = live ? pair_i[p] : i0;
-    // geometry of the pair from its separation (stored by the pair pass)
+    // geometry of the pair from the positions
     double g[20];
     {
         double d[3] = {1.0, 0.0, 0.0};
-        if (live)
-#pragma unroll
-            for (int al = 0; al < 3; ++al) d[al] = dsep[al * Pcap + p];
+        if (live) pair_sep(x, N, box, sys_of(off, n_sys, i), i, pair_j[p], d);
         snap_geo(d, sp, g);
     }
     const double fc = live ? g[4] : 0.0;
@@ -1098,7 +1089,7 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     KernelProf dummy;
     KernelProf &pf = prof ? *prof : dummy;
     hipLaunchKernelGGL(k_pair_ell, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box,
-                       x, w.poff, w.nbr_t, sd.gp, w.ell, w.dsep, w.Pcap);
+                       x, w.poff, w.nbr_t, sd.gp, w.ell);
     pf.begin(PROF_DENSITY, st);
     hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 64), J / 2 + 1), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u);
     pf.end(st);
@@ -1107,7 +1098,7 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     pf.end(st);
     pf.begin(PROF_DEDR, st);
     hipLaunchKernelGGL(k_dedr<J>, dim3(nblk((size_t)N * kMaxNeigh, 64)), dim3(64), 0, st, N, bd.n_sys, bd.off, bd.box,
-                       x, w.poff, w.pair_i, w.dsep, sd.gp, w.Pcap, w.ytil, w.dedr);
+                       x, w.poff, w.pair_i, w.pair_j, sd.gp, w.Pcap, w.ytil, w.dedr);
     pf.end(st);
     if (join) (void)hipStreamWaitEvent(st, join, 0);  // f written by work on another stream
     hipLaunchKernelGGL(k_gather, dim3(nblk(N, 64)), dim3(256), 0, st, N, w.poff, w.rev, w.dedr, w.Pcap, f,
@@ -1131,7 +1122,7 @@ void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapD
     hipLaunchKernelGGL(k_pair_geo, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
                        w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
     hipLaunchKernelGGL(k_pair_ell, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box,
-                       x, w.poff, w.nbr_t, sd.gp, w.ell, w.dsep, w.Pcap);
+                       x, w.poff, w.nbr_t, sd.gp, w.ell);
     switch (J) {
         case 2: hipLaunchKernelGGL(k_density<2>, dim3(nblk(N, 64), 2), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u); break;
         case 4: hipLaunchKernelGGL(k_density<4>, dim3(nblk(N, 64), 3), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u); break;
