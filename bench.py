@@ -215,11 +215,11 @@ def pmc_probe(S, W, J, S_slabs):
 # of the file); after a change the traffic is reported as null until it is measured again.
 TRAFFIC = {
     "adjoint": ("paper_2212_10508_amd/csrc/adjoint.hip",
-                "adb0e5866e03e9d5c8f6ee0a9ef34c004b054ba23a024de9ea409a7f4825cd9a", 4939.7, "atom"),
+                "28237c58665b365c803e4e9f14e9d2280dee307101bc75398dd014fed491aee1", 4860.4, "atom"),
     "dedr": ("paper_2212_10508_amd/csrc/kernels.hip",
-             "adf182ee2072cca4737f00dc4f51bec8bf20ced3a67dbe16b5235cf641b5a22e", 448.5, "pair"),
+             "a7bba27061de622a7f582aaa6300e03d50a5c4429bad170ad28fefa13f4516a4", 447.6, "pair"),
     "density": ("paper_2212_10508_amd/csrc/kernels.hip",
-                "adf182ee2072cca4737f00dc4f51bec8bf20ced3a67dbe16b5235cf641b5a22e", 300.4, "pair"),
+                "a7bba27061de622a7f582aaa6300e03d50a5c4429bad170ad28fefa13f4516a4", 300.3, "pair"),
 }
 
 
