@@ -4,8 +4,10 @@
 // (half storage, [element][64] double2) in LDS.  Its waves own disjoint sets of
 // output rows m (2m in -J..J, balanced by cost on the host); control flow and all
 // coupling coefficients are wave-uniform.  For output row m, coupling block
-// (j1 >= j2) and left index m1 (m2 = m - m1), the two full rows u^{j1}[m1][.] and
-// u^{j2}[m2][.] are read from LDS and a compile-time-unrolled "row-pair motif" forms
+// (j1 >= j2) and left index m1 (m2 = m - m1), the row u^{j2}[m2][.] is read from LDS
+// into registers, the entries of u^{j1}[m1][.] are taken from LDS one at a time (so the
+// kernel fits 168 registers: three waves per SIMD), and a compile-time-unrolled
+// "row-pair motif" forms
 //   c_j[m'] = sum_{m1'+m2'=m'} C^{j m'}_{j1 m1', j2 m2'} u^{j1}[m1][m1'] u^{j2}[m2][m2']
 // for every coupled level j and m' <= 0 (each product u u shared by all j), then
 //   Y^j[m][m'] += beta~(j1,j2,j) C^{j m}_{j1 m1, j2 m2} c_j[m'].
@@ -97,17 +99,27 @@ __device__ __forceinline__ void load_row(const double2 *__restrict__ lds, int k,
     }
 }
 
+template <int N>
+__device__ __forceinline__ double2 load_entry(const double2 *__restrict__ lds, int k, int l) {
+    constexpr int h0 = half_off(N);
+    if (2 * l <= N) return lds[(h0 + l * (N + 1) + k) * 64];
+    const double2 v = lds[(h0 + (N - l) * (N + 1) + (N - k)) * 64];
+    const double s = ((k - l) & 1) ? -1.0 : 1.0;
+    return make_double2(s * v.x, -s * v.y);
+}
+
 template <int J, int N1, int N2>
-__device__ __forceinline__ void motif(const double2 (&r1)[N1 + 1], const double2 (&r2)[N2 + 1],
+__device__ __forceinline__ void motif(const double2 *__restrict__ lds, int k1, const double2 (&r2)[N2 + 1],
                                       const double *__restrict__ cg, double2 (&c)[c_size(J, N1, N2)]) {
     int t = 0;
 #pragma unroll
     for (int l1 = 0; l1 <= N1; ++l1) {
+        const double2 r1l = load_entry<N1>(lds, k1, l1);
 #pragma unroll
         for (int l2 = 0; l2 <= N2; ++l2) {
             const int tmp = (2 * l1 - N1) + (2 * l2 - N2);
             if (tmp > 0) continue;
-            const double2 P = cmul(r1[l1], r2[l2]);
+            const double2 P = cmul(r1l, r2[l2]);
 #pragma unroll
             for (int n = cpl_lo(N1, N2); n <= cpl_hi(J, N1, N2); n += 2) {
                 if (-tmp > n) continue;
@@ -143,13 +155,12 @@ __device__ __forceinline__ void do_block(int tm, const double2 *__restrict__ lds
         int opq = 0;
         asm volatile("" : "+s"(opq));
         const double *cgi = cg + opq;
-        double2 r1[N1 + 1], r2[N2 + 1];
-        load_row<N1>(lds, (tm1 + N1) / 2, r1);
+        double2 r2[N2 + 1];
         load_row<N2>(lds, (tm - tm1 + N2) / 2, r2);
         double2 c[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) c[q] = make_double2(0.0, 0.0);
-        motif<J, N1, N2>(r1, r2, cgi, c);
+        motif<J, N1, N2>(lds, (tm1 + N1) / 2, r2, cgi, c);
 #pragma unroll
         for (int n = cpl_lo(N1, N2); n <= cpl_hi(J, N1, N2); n += 2) {
             const double w = coef[off + (n - cpl_lo(N1, N2)) / 2];
@@ -205,7 +216,7 @@ __device__ __forceinline__ double process_row(int tm, int atom, int N, const dou
 }
 
 template <int J>
-__global__ void __launch_bounds__(512) k_adjoint_lds(int N, const double2 *__restrict__ u,
+__global__ void __launch_bounds__(768) k_adjoint_lds(int N, const double2 *__restrict__ u,
                                                      const double *__restrict__ cgm, const double *__restrict__ coef,
                                                      const int *__restrict__ coef_off, const int *__restrict__ roles,
                                                      int role_len, const double *__restrict__ nrm,
@@ -214,8 +225,7 @@ __global__ void __launch_bounds__(512) k_adjoint_lds(int N, const double2 *__res
                                                      int accumulate_e) {
     extern __shared__ double2 lds[];
     constexpr int NH = n_half(J);
-    constexpr int R = 8;
-    double *epart = reinterpret_cast<double *>(lds + NH * 64);  // [R][64]
+    constexpr int R = 12;  // waves: three per SIMD (the LDS tile allows one workgroup per CU)
     const int a0 = blockIdx.x * 64;
     for (int idx = threadIdx.x; idx < NH * 64; idx += 64 * R) {
         const int e = idx >> 6, a = idx & 63;
@@ -234,6 +244,8 @@ __global__ void __launch_bounds__(512) k_adjoint_lds(int N, const double2 *__res
         else
             esum += process_row<J, 1>(tm, a0 + lane, N, my, cgm, coef, coef_off, nrm, ymult, ytil);
     }
+    __syncthreads();  // every wave is done with the u tile: reuse it for the energy partials
+    double *epart = reinterpret_cast<double *>(lds);  // [R][64]
     epart[wave * 64 + lane] = esum;
     __syncthreads();
     if (wave == 0 && e_atom && a0 + lane < N) {
@@ -248,7 +260,7 @@ __global__ void __launch_bounds__(512) k_adjoint_lds(int N, const double2 *__res
 // ---------------------------------------------------------------------------
 // host side: tables and launch
 // ---------------------------------------------------------------------------
-constexpr int kAdjWaves = 8;
+constexpr int kAdjWaves = 12;
 
 void adjoint_tables(int J, const double *beta, AdjointHost &A) {
     const SnapTables &T = snap_tables(J);
@@ -324,7 +336,9 @@ void adjoint_tables(int J, const double *beta, AdjointHost &A) {
     A.coef_changed = true;
 }
 
-size_t adjoint_lds_bytes(int J) { return (size_t)n_half(J) * 64 * sizeof(double2) + kAdjWaves * 64 * sizeof(double); }
+size_t adjoint_lds_bytes(int J) {
+    return std::max((size_t)n_half(J) * 64 * sizeof(double2), (size_t)kAdjWaves * 64 * sizeof(double));
+}
 
 template <int J>
 static void launch_adj(const AdjointDev &ad, int N, const double2 *u, const double *nrm, const double *ymult,
