@@ -189,6 +189,19 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
                      int32_t n_in, int32_t *n_fi, double *q_prev, double *p_prev, double *q_cur,
                      double *p_cur, double delta_expl, double *delta_out, void *stream);
 
+/* Coarse propagator of parareal_iterate.  By default it is Finnis-Sinclair alone (the
+ * paper's strategy II: an EAM coarse potential).  snapmd_set_coarse_snap(ctx, coarse)
+ * makes it Finnis-Sinclair + the SNAP model `coarse`, a low-twojmax SNAP beside the
+ * fine one: the paper's strategy I (section "Numerical results", SNAP-6 as the coarse
+ * potential for a larger SNAP fine one).  coarse is copied (beta included);
+ * coarse = NULL restores Finnis-Sinclair alone.  Its twojmax must be in {2, 4, 6, 8},
+ * n_coeff must match, and parareal_iterate refuses (SNAPMD_EINVAL) a coarse twojmax equal
+ * to the fine one.  With a SNAP coarse potential the coarse propagation of the slabs is
+ * batched like the fine one, and the sequential sweep is driven from the host (one
+ * launch sequence and one small synchronisation per slab).  Errors: SNAPMD_EINVAL,
+ * SNAPMD_EUNSUPPORTED. */
+int snapmd_set_coarse_snap(snapmd_ctx *ctx, const snapmd_snap *coarse);
+
 /* Gradients of the SNAP model with respect to its coefficients beta (for a
  * force-matching fit; the loss is the caller's):
  *   dEdbeta[k]  = sum_i B_k(i)                    (k = 1..K; dEdbeta[0] = n_atoms)

@@ -10,8 +10,10 @@ explosion threshold; Algorithm "Adaptive parareal algorithm").
 
 Propagators: F and C both take L Langevin steps of length dt from (q, p) on slab n,
 with the same noise (global steps n*L .. n*L+L-1 of one noise stream), F on the
-fine potential (Finnis-Sinclair + SNAP), C on the coarse one (Finnis-Sinclair); the
-steps are BAOAB, or one application of L iterates of the paper's BBK scheme.
+fine potential (Finnis-Sinclair + SNAP), C on the coarse one (Finnis-Sinclair, the
+paper's strategy II with an EAM coarse potential, or Finnis-Sinclair + a second,
+smaller SNAP model, its strategy I); the steps are BAOAB, or one application of L
+iterates of the paper's BBK scheme.
 
 Readings where the paper leaves room:
 * Relative error E(prev, cur, n_in, n) = sum_{m=n_in+1}^{n} |cur_m - prev_m| /
@@ -30,24 +32,26 @@ class Propagators:
     """F and C of one trajectory (one noise stream) for the oracle."""
 
     def __init__(self, *, box, L, dt, gamma, mass, T, seed, noise_id, snap, fs, maxn=64, scheme="baoab",
-                 cT=(1.0, 1.0)):
+                 cT=(1.0, 1.0), coarse_snap=None):
         self.kw = dict(dt=dt, gamma=gamma, mass=mass, T=T, seed=seed, noise_id=noise_id,
                        snap=snap, fs=fs, maxn=maxn)
         self.box = box
         self.L = L
         self.scheme = scheme  # "baoab", or "bbk": the paper's scheme, one application per slab
         self.cT = cT
+        self.coarse_snap = coarse_snap  # None: C on Finnis-Sinclair alone
         self.n_fine = 0
         self.n_coarse = 0
 
-    def _run(self, state, n, potential):
+    def _run(self, state, n, potential, snap=None):
         q, p = state
+        kw = dict(self.kw)
+        if snap is not None:
+            kw["snap"] = snap
         if self.scheme == "bbk":
-            r = O.bbk(q, p, self.box, potential=potential, nsteps=self.L, step0=n * self.L, cT=self.cT,
-                      **self.kw)
+            r = O.bbk(q, p, self.box, potential=potential, nsteps=self.L, step0=n * self.L, cT=self.cT, **kw)
         else:
-            r = O.langevin(q, p, self.box, potential=potential, nsteps=self.L, step0=n * self.L,
-                           **self.kw)
+            r = O.langevin(q, p, self.box, potential=potential, nsteps=self.L, step0=n * self.L, **kw)
         return (r["x"], r["p"])
 
     def F(self, state, n):
@@ -56,6 +60,8 @@ class Propagators:
 
     def C(self, state, n):
         self.n_coarse += 1
+        if self.coarse_snap is not None:
+            return self._run(state, n, O.POT_FS_SNAP, self.coarse_snap)
         return self._run(state, n, O.POT_FS)
 
 

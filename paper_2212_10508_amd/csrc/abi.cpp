@@ -57,7 +57,7 @@ struct snapmd_ctx {
     std::vector<int> h_off;
     std::vector<double> h_box;
     // workspace
-    size_t cap_atoms = 0, cap_atoms_c = 0;
+    size_t cap_atoms = 0, cap_atoms_c = 0, cap_atoms_cs = 0;  // fine, coarse lists, coarse SNAP
     Work w, wc;                                   // SNAP / second-stream Finnis-Sinclair workspaces
     double *d_f = nullptr, *d_fc = nullptr;       // their force scratch [3][N]
     // per-system Langevin arrays
@@ -101,6 +101,10 @@ struct snapmd_ctx {
     std::vector<hipEvent_t> pipe_ev;
     uint64_t graph_clock[2] = {};
     std::vector<int> chunk_override;     // slab chunks set by snapmd_set_chunk_plan (empty: built in)
+    // coarse propagator of parareal_iterate: Finnis-Sinclair, plus SNAP when set
+    bool coarse_snap_on = false;
+    snapmd_snap coarse_snap{};
+    std::vector<double> coarse_beta;
 };
 
 namespace {
@@ -196,7 +200,7 @@ int ensure_atoms(snapmd_ctx *ctx, size_t N) {
 
 // Workspace of the Finnis-Sinclair propagation that runs beside the SNAP one (its own
 // neighbour lists and force buffer; the error bits are shared).
-int ensure_atoms_coarse(snapmd_ctx *ctx, size_t N) {
+int ensure_atoms_coarse(snapmd_ctx *ctx, size_t N, bool snap = false) {
     Work &w = ctx->wc;
     w.status = ctx->w.status;
     int rc;
@@ -204,17 +208,33 @@ int ensure_atoms_coarse(snapmd_ctx *ctx, size_t N) {
         if ((rc = dalloc(ctx, &w.flag, 1))) return rc;
         HIPCHK(hipMemset(w.flag, 0, sizeof(int)));
     }
-    if (N <= ctx->cap_atoms_c) return SNAPMD_OK;
-    size_t cap = std::max<size_t>(N, 64);
-    w.Pcap = cap * kMaxNeigh;
-    if ((rc = dalloc(ctx, &w.nbr, cap * kMaxNeigh)) || (rc = dalloc(ctx, &w.cnt, cap)) ||
-        (rc = dalloc(ctx, &w.poff, cap + 1)) || (rc = dalloc(ctx, &w.pair_i, w.Pcap)) ||
-        (rc = dalloc(ctx, &w.pair_j, w.Pcap)) || (rc = dalloc(ctx, &w.rev, w.Pcap)) ||
-        (rc = dalloc(ctx, &w.rho, cap)) || (rc = dalloc(ctx, &ctx->d_fc, 3 * cap)) ||
-        (rc = dalloc(ctx, &w.xref, 3 * cap)) || (rc = dalloc(ctx, &w.cell_of, cap)) ||
-        (rc = dalloc(ctx, &w.cell_atoms, cap)) || (rc = dalloc(ctx, &w.ph, 3 * cap)))
-        return rc;
-    ctx->cap_atoms_c = cap;
+    // the SNAP passes (a coarse potential with SNAP) index their pair buffers with the
+    // list's pair capacity, so both sets share one atom capacity
+    const size_t need = std::max<size_t>(N, 64);
+    const bool grow_list = need > ctx->cap_atoms_c;
+    const bool grow_snap = snap && (need > ctx->cap_atoms_cs || ctx->cap_atoms_cs < ctx->cap_atoms_c);
+    if (!grow_list && !grow_snap) return SNAPMD_OK;
+    const size_t cap = std::max(need, ctx->cap_atoms_c);
+    if (grow_list) {
+        w.Pcap = cap * kMaxNeigh;
+        if ((rc = dalloc(ctx, &w.nbr, cap * kMaxNeigh)) || (rc = dalloc(ctx, &w.cnt, cap)) ||
+            (rc = dalloc(ctx, &w.poff, cap + 1)) || (rc = dalloc(ctx, &w.pair_i, w.Pcap)) ||
+            (rc = dalloc(ctx, &w.pair_j, w.Pcap)) || (rc = dalloc(ctx, &w.rev, w.Pcap)) ||
+            (rc = dalloc(ctx, &w.rho, cap)) || (rc = dalloc(ctx, &ctx->d_fc, 3 * cap)) ||
+            (rc = dalloc(ctx, &w.xref, 3 * cap)) || (rc = dalloc(ctx, &w.cell_of, cap)) ||
+            (rc = dalloc(ctx, &w.cell_atoms, cap)) || (rc = dalloc(ctx, &w.ph, 3 * cap)))
+            return rc;
+        ctx->cap_atoms_c = cap;
+    }
+    if (snap || (ctx->cap_atoms_cs > 0 && grow_list)) {
+        const size_t Pc = cap * kMaxNeigh;
+        if ((rc = dalloc(ctx, &w.geo, 20 * Pc)) || (rc = dalloc(ctx, &w.ell, 5 * Pc)) ||
+            (rc = dalloc(ctx, &w.nbr_t, Pc)) || (rc = dalloc(ctx, &w.dedr, 3 * Pc)) ||
+            (rc = dalloc(ctx, &w.u, (size_t)n_half(kMaxJ) * cap)) ||
+            (rc = dalloc(ctx, &w.ytil, (size_t)n_half(kMaxJ) * cap)))
+            return rc;
+        ctx->cap_atoms_cs = cap;
+    }
     return SNAPMD_OK;
 }
 
@@ -483,7 +503,9 @@ void enqueue_forces(snapmd_ctx *ctx, Work &w, int potential, const BatchDev &bd,
     ctx->prof.begin(PROF_NEIGH, st);
     (void)neighbors(ctx, w, bd, x, rc, fresh, st, true);
     ctx->prof.end(st);
-    if (potential == SNAPMD_POT_FS_SNAP && ctx->fork_st) {
+    // the fork stream and its events belong to the fine workspace (the coarse one may be
+    // queued from another host thread at the same time)
+    if (potential == SNAPMD_POT_FS_SNAP && ctx->fork_st && &w == &ctx->w) {
         (void)hipEventRecord(ctx->ev_fork, st);
         (void)hipStreamWaitEvent(ctx->fork_st, ctx->ev_fork, 0);
         launch_fs(bd, x, *fp, w, f, nullptr, 0, ctx->fork_st, true);
@@ -826,7 +848,20 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     if ((rc = ensure(ctx, ctx->sw_out, 8))) return rc;
     // the on-device sweeps integrate BAOAB; the BBK scheme takes the host-driven sweep
     const bool bbk = lang->scheme == SNAPMD_SCHEME_BBK;
-    if ((bbk || !sweep_fits_lds(N)) &&
+    // coarse potential: Finnis-Sinclair, plus SNAP when snapmd_set_coarse_snap set one (the
+    // paper's strategy I); the on-device sweeps integrate Finnis-Sinclair only
+    const bool csnap = ctx->coarse_snap_on;
+    const int potC = csnap ? SNAPMD_POT_FS_SNAP : SNAPMD_POT_FS;
+    SnapDev sdc;
+    if (csnap) {
+        snapmd_snap cs = ctx->coarse_snap;
+        cs.beta = ctx->coarse_beta.data();
+        if (snap && !init && snap->twojmax == cs.twojmax)
+            return fail(ctx, SNAPMD_EINVAL, "the coarse SNAP needs a twojmax other than the fine one (%d)",
+                        cs.twojmax);
+        if ((rc = prepare_snap(ctx, &cs, mh, sdc, st))) return rc;
+    }
+    if ((bbk || csnap || !sweep_fits_lds(N)) &&
         ((rc = ensure(ctx, ctx->sw_x, 3 * (size_t)N)) || (rc = ensure(ctx, ctx->sw_p, 3 * (size_t)N))))
         return rc;
     if (!ctx->h_out) HIPCHK(hipHostMalloc((void **)&ctx->h_out, 16 * sizeof(double), hipHostMallocDefault));
@@ -875,8 +910,8 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     }
     // the sweep on the device: several workgroups exchanging through device memory, or
     // one LDS-resident workgroup; else driven from the host
-    const int mcK = bbk ? 0 : sweep_mc_workgroups(N);
-    const bool lds_sweep = !bbk && (mcK > 0 || sweep_fits_lds(N));
+    const int mcK = (bbk || csnap) ? 0 : sweep_mc_workgroups(N);
+    const bool lds_sweep = !bbk && !csnap && (mcK > 0 || sweep_fits_lds(N));
     if (mcK > 0) {
         sw.K = mcK;
         sw.A = (N + mcK - 1) / mcK;
@@ -926,7 +961,7 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         if ((rc = ensure(ctx, ctx->pr_xf, SN3)) || (rc = ensure(ctx, ctx->pr_pf, SN3)) ||
             (rc = ensure(ctx, ctx->pr_xc, SN3)) || (rc = ensure(ctx, ctx->pr_pc, SN3)))
             return rc;
-        if ((rc = ensure_atoms_coarse(ctx, (size_t)S * N))) return rc;
+        if ((rc = ensure_atoms_coarse(ctx, (size_t)S * N, csnap))) return rc;
         // The slabs are propagated in chunks of consecutive slabs (chunk c occupies
         // [3][S_c N] at offset 3 N s0 of the batch buffers).  The SNAP propagation of the
         // chunks runs on the caller's stream; the Finnis-Sinclair propagation, the jumps
@@ -974,7 +1009,7 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         // another's.  Everything the replays need (buffers, cell grids) is set up here
         // first: neither helper allocates (an allocation drops the captured graphs).
         if ((rc = prepare_propagation_cells(ctx, ctx->w, SNAPMD_POT_FS_SNAP, bd, fp, sd, st)) ||
-            (rc = prepare_propagation_cells(ctx, ctx->wc, SNAPMD_POT_FS, bd, fp, sd, st)))
+            (rc = prepare_propagation_cells(ctx, ctx->wc, potC, bd, fp, sdc, st)))
             return rc;
         std::mutex mu;
         std::condition_variable cv;
@@ -1009,7 +1044,7 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
                 const size_t o = 3 * (size_t)N * s0;
                 launch_slabs_to_batch(nc, N, qs + s0 * slot, ctx->pr_xc.p + o, s3);
                 launch_slabs_to_batch(nc, N, ps + s0 * slot, ctx->pr_pc.p + o, s3);
-                if ((r = run_langevin_graph(ctx, ctx->wc, ctx->d_fc, SNAPMD_POT_FS, bc, fp, sd, lc, L,
+                if ((r = run_langevin_graph(ctx, ctx->wc, ctx->d_fc, potC, bc, fp, sdc, lc, L,
                                             ctx->pr_xc.p + o, ctx->pr_pc.p + o, s3)))
                     return r;
                 HIPCHK(hipEventRecord(ctx->pipe_ev[ne + 2 + c], s3));
@@ -1120,7 +1155,7 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
             std::vector<int> id1(1, lang->noise_id_sys[0]);
             LangevinDev ld1;
             if ((rc = prepare_langevin(ctx, lang, 1, T1, s1, id1, ld1, st))) return rc;
-            run_langevin(ctx, ctx->w, ctx->d_f, SNAPMD_POT_FS, bd1, fp, sd, ld1, L, wx, wp, st);
+            run_langevin(ctx, ctx->w, ctx->d_f, potC, bd1, fp, sdc, ld1, L, wx, wp, st);
             launch_slab_end(N, init ? 0 : 1, SN3 / 3, (size_t)(n - n_in), wx, wp, sw.jq, sw.jp,
                             init ? nullptr : q_prev + (size_t)(n + 1) * slot, q_cur + (size_t)(n + 1) * slot,
                             p_cur + (size_t)(n + 1) * slot, ctx->sw_out.p, st);
@@ -1143,6 +1178,27 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         *n_fi = nfi_new;
         return SNAPMD_OK;
     }
+}
+
+int snapmd_set_coarse_snap(snapmd_ctx *ctx, const snapmd_snap *coarse) {
+    if (!ctx) return SNAPMD_EINVAL;
+    if (!coarse) {
+        ctx->coarse_snap_on = false;
+        ctx->coarse_beta.clear();
+        return SNAPMD_OK;
+    }
+    const int J = coarse->twojmax;
+    if (J != 2 && J != 4 && J != 6 && J != 8)
+        return fail(ctx, SNAPMD_EUNSUPPORTED, "coarse twojmax must be one of 2, 4, 6, 8 (got %d)", J);
+    if (coarse->n_coeff != snap_tables(J).K)
+        return fail(ctx, SNAPMD_EINVAL, "coarse n_coeff must be %d for twojmax %d (got %d)", snap_tables(J).K, J,
+                    coarse->n_coeff);
+    if (!coarse->beta) return fail(ctx, SNAPMD_EINVAL, "coarse beta is NULL");
+    ctx->coarse_snap = *coarse;
+    ctx->coarse_beta.assign(coarse->beta, coarse->beta + coarse->n_coeff + 1);
+    ctx->coarse_snap.beta = nullptr;
+    ctx->coarse_snap_on = true;
+    return SNAPMD_OK;
 }
 
 int snapmd_set_chunk_plan(snapmd_ctx *ctx, const int32_t *sizes, int32_t n) {

@@ -90,6 +90,8 @@ def lib():
     L.snapmd_profile_read.restype = C.c_int
     L.snapmd_pair_count.argtypes = [P, C.POINTER(C.c_int64)]
     L.snapmd_pair_count.restype = C.c_int
+    L.snapmd_set_coarse_snap.argtypes = [P, C.POINTER(Snap)]
+    L.snapmd_set_coarse_snap.restype = C.c_int
     L.snapmd_set_chunk_plan.argtypes = [P, C.POINTER(i32), i32]
     L.snapmd_set_chunk_plan.restype = C.c_int
     L.snapmd_chunk_plan.argtypes = [P, i32, i32, C.POINTER(i32), C.POINTER(i32)]
@@ -281,6 +283,16 @@ class Context:
         n = C.c_int64(0)
         self._check(lib().snapmd_profile_read(self.h, int(kernel), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def set_coarse_snap(self, J=None, beta=None, rcut=4.73, rfac0=0.99363, rmin0=0.0):
+        """Coarse propagator of parareal_iterate: Finnis-Sinclair + SNAP(J, beta) (the
+        paper's strategy I), or Finnis-Sinclair alone with J=None."""
+        if J is None:
+            self._check(lib().snapmd_set_coarse_snap(self.h, None))
+            return
+        k = _Keep()
+        s = make_snap(k, J, beta, rcut, rfac0, rmin0)
+        self._check(lib().snapmd_set_coarse_snap(self.h, C.byref(s)))
 
     def set_chunk_plan(self, sizes):
         """Slab chunks of parareal_iterate for windows of sum(sizes) slabs (None or []:

@@ -247,3 +247,43 @@ def test_chunk_plans_give_identical_iterates(S):
     with pytest.raises(S.SnapmdError):
         ctx.set_chunk_plan([2, 0])
     ctx.set_chunk_plan(None)
+
+
+def test_strategy_one_snap_coarse_matches_oracle(S):
+    """Strategy I (coarse = Finnis-Sinclair + a twojmax-2 SNAP, fine = FS + twojmax-4 SNAP):
+    classical parareal on the GPU (batched coarse SNAP propagation, host-driven sweep)
+    against the oracle's literal driver, and the k-iteration exactness."""
+    from paper_2212_10508_amd import parareal as PR
+    x, p, box, kw, _ = _setup(J=4, seed=12)
+    N, L = 4, 4
+    beta_c = W.snap_beta(2, seed=13, scale=2e-2)
+    coarse = dict(J=2, beta=beta_c, rcut=W.SNAP_RCUT, rfac0=W.SNAP_RFAC0, rmin0=0.0)
+    snap = dict(J=4, beta=kw["beta"], rcut=W.SNAP_RCUT, rfac0=W.SNAP_RFAC0, rmin0=0.0)
+    prop = OPR.Propagators(box=box, L=L, dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=99, noise_id=1,
+                           snap=snap, fs=W.FS_W, coarse_snap=coarse)
+    ctx = S.context()
+    ctx.set_coarse_snap(2, beta_c)
+    try:
+        with pytest.raises(S.SnapmdError):  # a coarse twojmax equal to the fine one is refused
+            ctx.set_coarse_snap(4, kw["beta"])
+            qq = torch.zeros((N + 1, 3, x.shape[1]), dtype=torch.float64, device="cuda")
+            ctx.parareal_iterate(torch.zeros_like(qq), torch.zeros_like(qq), qq, torch.zeros_like(qq), box, L,
+                                 0, N, 1e100, **kw)
+        ctx.set_coarse_snap(2, beta_c)
+        q, _, nad, kc = PR.adaptive_parareal(ctx, dev(x), dev(p), box, N, L, 1e-10, 1e100, **kw)
+        tref, k_ref, iters = OPR.parareal_classic(prop, x, p, N, delta_conv=1e-10)
+        assert nad == 1 and kc == [k_ref]
+        qh = q.cpu().numpy()
+        for n in range(N + 1):
+            assert np.abs(qh[n] - tref[n][0]).max() < QTOL
+        # the coarse initialisation (window start) equals the oracle's coarse sweep
+        n = x.shape[1]
+        q0 = torch.zeros((N + 1, 3, n), dtype=torch.float64, device="cuda")
+        p0 = torch.zeros_like(q0)
+        q0[0], p0[0] = dev(x), dev(p)
+        ctx.parareal_iterate(None, None, q0, p0, box, L, 0, N, 1e100,
+                             **{k: v for k, v in kw.items() if k not in ("J", "beta")})
+        for m in range(N + 1):
+            assert np.abs(q0[m].cpu().numpy() - iters[0][m][0]).max() < QTOL
+    finally:
+        ctx.set_coarse_snap(None)

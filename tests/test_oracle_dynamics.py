@@ -181,3 +181,23 @@ def test_adaptive_shortening_still_reaches_reference():
             cost += (N - it["n_in"]) * Cc
         cost += Cf + Cc + (it["n_fi"] - it["n_in"]) * Cc
     assert PR.adaptive_cost(log, N, Cf, Cc) == pytest.approx(cost)
+
+
+def test_strategy_one_snap_coarse_is_exact_after_k_iterations():
+    """Strategy I: the coarse propagator is Finnis-Sinclair + a smaller SNAP model.  The
+    parareal property (slabs 0..k exact after k iterations) holds for any coarse
+    propagator, and the coarse trajectory differs from both the FS-only one and the fine
+    one (the coarse SNAP term is really in C)."""
+    N = 3
+    prop, x, p = _props()
+    coarse = dict(J=2, beta=W.snap_beta(2, seed=9, scale=2e-2), rcut=W.SNAP_RCUT, rfac0=W.SNAP_RFAC0,
+                  rmin0=0.0)
+    prop1 = PR.Propagators(box=prop.box, L=prop.L, coarse_snap=coarse, scheme=prop.scheme, **prop.kw)
+    ref = PR.sequential_fine(prop1, x, p, N)
+    _, _, iters = PR.parareal_classic(prop1, x, p, N, delta_conv=0.0, max_iter=N)
+    scale = np.abs(ref[-1][0]).max()
+    for k in range(1, N + 1):
+        for n in range(k + 1):
+            assert np.abs(iters[k][n][0] - ref[n][0]).max() < 1e-12 * scale
+    c1, c2, f = prop1.C((x, p), 0)[0], prop.C((x, p), 0)[0], prop1.F((x, p), 0)[0]
+    assert np.abs(c1 - c2).max() > 1e-9 and np.abs(c1 - f).max() > 1e-9
