@@ -183,6 +183,29 @@ def other_configs(S, W, log):
     out["fine_batch_16001x32_200_steps"] = {"atoms": int(off[-1]), "atom_steps_per_s": int(off[-1]) * 200 / t,
                                             "s": t}
     log("16001 atoms x 32 slabs: %.2f s per 200 steps" % t)
+    del xw, pw, xf, pf
+    # the paper's strategy I: coarse = Finnis-Sinclair + a twojmax-2 SNAP, one corrected
+    # parareal iteration over 64 slabs of the 1025-atom system (host-driven sweep)
+    wl = W.slabs_1025(n_slabs=1, seed=1, J=8)
+    n = wl["xs"][0].shape[1]
+    kw = dict(dt=wl["dt"], gamma=wl["gamma"], mass=wl["mass"], T=wl["T"], seed=1, noise_id=0, fs=W.FS_W)
+    ctx = S.context(0)
+    ctx.set_coarse_snap(2, W.snap_beta(2, seed=4))
+    try:
+        q = torch.zeros((65, 3, n), dtype=torch.float64, device="cuda")
+        pq, qp, pp = torch.zeros_like(q), torch.zeros_like(q), torch.zeros_like(q)
+        q[0], pq[0] = dev(wl["xs"][0]), dev(wl["ps"][0])
+        ctx.parareal_iterate(None, None, q, pq, wl["box"], 100, 0, 64, 1e300, **kw)
+
+        def it1():
+            ctx.parareal_iterate(qp, pp, q, pq, wl["box"], 100, 0, 64, 1e300, J=8, beta=wl["beta"], **kw)
+
+        t = timed(it1, reps=1)
+    finally:
+        ctx.set_coarse_snap(None)
+    out["strategy_one_parareal_64x1025"] = {"coarse": "Finnis-Sinclair + SNAP twojmax 2", "ms_per_iteration": t * 1e3,
+                                            "fine_atom_steps_per_s": 64 * n * 100 / t}
+    log("strategy I: %.1f ms per parareal iteration" % (t * 1e3))
     return out
 
 

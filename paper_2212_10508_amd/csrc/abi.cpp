@@ -1155,7 +1155,9 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
             std::vector<int> id1(1, lang->noise_id_sys[0]);
             LangevinDev ld1;
             if ((rc = prepare_langevin(ctx, lang, 1, T1, s1, id1, ld1, st))) return rc;
-            run_langevin(ctx, ctx->w, ctx->d_f, potC, bd1, fp, sdc, ld1, L, wx, wp, st);
+            // one captured launch sequence serves every slab: the step offset of the slab
+            // is read from device memory (uploaded above) when the sequence runs
+            if ((rc = run_langevin_graph(ctx, ctx->w, ctx->d_f, potC, bd1, fp, sdc, ld1, L, wx, wp, st))) return rc;
             launch_slab_end(N, init ? 0 : 1, SN3 / 3, (size_t)(n - n_in), wx, wp, sw.jq, sw.jp,
                             init ? nullptr : q_prev + (size_t)(n + 1) * slot, q_cur + (size_t)(n + 1) * slot,
                             p_cur + (size_t)(n + 1) * slot, ctx->sw_out.p, st);
