@@ -228,6 +228,32 @@ int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_bat
  * While snapmd_profile is on, SNAP propagation is launched one by one. */
 int snapmd_use_graphs(snapmd_ctx *ctx, int enable);
 
+/* Wigner-Seitz analysis of a bcc lattice (to follow the interstitial between its
+ * metastable states; stands in for the Voronoi analysis the paper runs with OVITO,
+ * section "Numerical results").  Every box edge of every system must be a whole number
+ * n of cubic cells of edge a (lattice constant, A).  The sites of system s are the cube
+ * corners and centres of its cells, numbered first_s + 2 (ix ny nz + iy nz + iz) + b
+ * (b = 0 corner (ix, iy, iz) a, b = 1 centre), first_s = sum over earlier systems of
+ * 2 nx ny nz.  site[i] (device, [N]) receives the site nearest to atom i (positions may
+ * be unwrapped; of two equally near sites the corner wins) and occ (device, [n_occ],
+ * n_occ >= total number of sites) the number of atoms of each site: a site holding two
+ * atoms is an interstitial dumbbell, an empty one a vacancy.  Asynchronous on stream.
+ * Errors: SNAPMD_EINVAL (a box edge not a whole number of cells, occ too small). */
+int snapmd_ws_sites(snapmd_ctx *ctx, const snapmd_batch *batch, const double *x, double a, int32_t *site,
+                    int32_t *occ, int32_t n_occ, void *stream);
+
+/* Energy minimisation by steepest descent (the first step of the paper's equilibration,
+ * section "Numerical results": insert the interstitial, minimise the energy, then
+ * thermalise): x <- x + F_i min(alpha, dmax / |F_i|) per atom (alpha in A^2/eV, dmax in
+ * A), with the forces of `potential` (SNAPMD_POT_FS, or SNAPMD_POT_FS_SNAP with snap).
+ * Stops when max_i |F_i| < ftol (eV/A), tested every 20 steps, or after max_iter steps.
+ * x (device, [3][N]) is updated in place; *fmax_out (host) receives max_i |F_i| at the
+ * last test and *iters_out the steps taken.  Synchronises the stream.  Errors:
+ * SNAPMD_EINVAL, SNAPMD_ENONFINITE (forces became non-finite). */
+int snapmd_relax(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, const snapmd_fs *fs,
+                 const snapmd_batch *batch, double *x, int32_t max_iter, double ftol, double alpha, double dmax,
+                 double *fmax_out, int32_t *iters_out, void *stream);
+
 /* Slab chunks of parareal_iterate (tuning, not part of the method).  The pipelined path
  * of parareal_iterate (systems the on-device sweep handles, BAOAB) propagates the S slabs
  * of a window in chunks of consecutive slabs: the SNAP propagation of chunk c runs while

@@ -17,7 +17,7 @@ ARCH = "gfx950"
 # Packed FP32 instructions are disabled for every HIP source of this library.
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]
-SOURCES = [("kernels.hip", ["-x", "hip"]), ("adjoint.hip", ["-x", "hip"]), ("parareal.hip", ["-x", "hip"]), ("grad.hip", ["-x", "hip"]),
+SOURCES = [("kernels.hip", ["-x", "hip"]), ("adjoint.hip", ["-x", "hip"]), ("parareal.hip", ["-x", "hip"]), ("grad.hip", ["-x", "hip"]), ("analysis.hip", ["-x", "hip"]),
            ("abi.cpp", ["-x", "hip"]),
            ("tables.cpp", [])]
 

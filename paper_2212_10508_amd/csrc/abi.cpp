@@ -101,6 +101,8 @@ struct snapmd_ctx {
     std::vector<hipEvent_t> pipe_ev;
     uint64_t graph_clock[2] = {};
     std::vector<int> chunk_override;     // slab chunks set by snapmd_set_chunk_plan (empty: built in)
+    DBuf<int4> d_ws;                     // Wigner-Seitz lattice of each system
+    DBuf<unsigned long long> d_fmax;     // max |F|^2 of the relaxation
     // coarse propagator of parareal_iterate: Finnis-Sinclair, plus SNAP when set
     bool coarse_snap_on = false;
     snapmd_snap coarse_snap{};
@@ -1180,6 +1182,81 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         *n_fi = nfi_new;
         return SNAPMD_OK;
     }
+}
+
+int snapmd_ws_sites(snapmd_ctx *ctx, const snapmd_batch *batch, const double *x, double a, int32_t *site,
+                    int32_t *occ, int32_t n_occ, void *stream) {
+    if (!ctx) return SNAPMD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!x || !site || !occ) return fail(ctx, SNAPMD_EINVAL, "x, site and occ must be device pointers");
+    if (!(a > 0.0)) return fail(ctx, SNAPMD_EINVAL, "the lattice constant must be > 0 (got %g)", a);
+    BatchDev bd;
+    double mh;
+    int rc;
+    if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
+    std::vector<int4> ws(batch->n_sys);
+    long total = 0;
+    for (int s = 0; s < batch->n_sys; ++s) {
+        int n[3];
+        for (int al = 0; al < 3; ++al) {
+            const double c = batch->box[3 * s + al] / a;
+            n[al] = (int)std::lround(c);
+            if (n[al] < 1 || std::fabs(c - n[al]) > 1e-9 * c)
+                return fail(ctx, SNAPMD_EINVAL, "box edge %d of system %d is not a whole number of cells of %g A",
+                            al, s, a);
+        }
+        ws[s] = make_int4(n[0], n[1], n[2], (int)total);
+        total += 2L * n[0] * n[1] * n[2];
+    }
+    if (total > n_occ) return fail(ctx, SNAPMD_EINVAL, "occ holds %d sites, the batch has %ld", n_occ, total);
+    if ((rc = ensure(ctx, ctx->d_ws, (size_t)batch->n_sys))) return rc;
+    if ((rc = upload(ctx, ctx->d_ws.p, ws.data(), ws.size(), st))) return rc;
+    launch_ws_sites(bd, ctx->d_ws.p, (int)total, a, x, site, occ, st);
+    return check_launch(ctx);
+}
+
+int snapmd_relax(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, const snapmd_fs *fs,
+                 const snapmd_batch *batch, double *x, int32_t max_iter, double ftol, double alpha, double dmax,
+                 double *fmax_out, int32_t *iters_out, void *stream) {
+    if (!ctx) return SNAPMD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (potential != SNAPMD_POT_FS && potential != SNAPMD_POT_FS_SNAP)
+        return fail(ctx, SNAPMD_EINVAL, "potential must be SNAPMD_POT_FS or SNAPMD_POT_FS_SNAP");
+    if (!x) return fail(ctx, SNAPMD_EINVAL, "x must be a device pointer");
+    if (!fmax_out || !iters_out) return fail(ctx, SNAPMD_EINVAL, "fmax_out and iters_out must be host pointers");
+    if (max_iter < 0 || !(ftol > 0.0) || !(alpha > 0.0) || !(dmax > 0.0))
+        return fail(ctx, SNAPMD_EINVAL, "need max_iter >= 0 and ftol, alpha, dmax > 0");
+    BatchDev bd;
+    double mh;
+    FsParams fp;
+    SnapDev sd;
+    int rc;
+    if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
+    if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
+    if (potential == SNAPMD_POT_FS_SNAP && (rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
+    if ((rc = ensure(ctx, ctx->d_fmax, 1))) return rc;
+    if (!ctx->h_out) HIPCHK(hipHostMalloc((void **)&ctx->h_out, 16 * sizeof(double), hipHostMallocDefault));
+    const int N = bd.N;
+    int it = 0;
+    double fmax = 0.0;
+    for (;;) {
+        enqueue_forces(ctx, ctx->w, potential, bd, x, &fp, &sd, ctx->d_f, st);
+        if (it % 20 == 0 || it == max_iter) {
+            launch_fmax2(N, ctx->d_f, ctx->d_fmax.p, st);
+            HIPCHK(hipMemcpyAsync(ctx->h_out, ctx->d_fmax.p, sizeof(double), hipMemcpyDeviceToHost, st));
+            if ((rc = snapmd_sync(ctx, stream))) return rc;
+            fmax = std::sqrt(ctx->h_out[0]);
+            if (!std::isfinite(fmax)) return fail(ctx, SNAPMD_ENONFINITE, "forces became non-finite at step %d", it);
+            if (fmax < ftol || it == max_iter) break;
+        }
+        launch_descent_step(N, x, ctx->d_f, alpha, dmax, st);
+        ++it;
+    }
+    *fmax_out = fmax;
+    *iters_out = it;
+    return check_launch(ctx);
 }
 
 int snapmd_set_coarse_snap(snapmd_ctx *ctx, const snapmd_snap *coarse) {

@@ -170,6 +170,12 @@ void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w,
 // join (nullable): an event the gather waits for (the Finnis-Sinclair force written into f
 // on another stream); p_kick (nullable): momenta that receive the closing half kick
 // p += (dt/2) f of a BAOAB step from the gather
+// analysis.hip
+void launch_ws_sites(const BatchDev &bd, const int4 *ws, int n_sites, double a, const double *x, int *site,
+                     int *occ, hipStream_t st);
+void launch_descent_step(int N, double *x, const double *f, double alpha, double dmax, hipStream_t st);
+void launch_fmax2(int N, const double *f, unsigned long long *out, hipStream_t st);
+
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
                  double *e_atom, int accumulate, hipStream_t st, KernelProf *prof = nullptr,
                  hipEvent_t join = nullptr, double *p_kick = nullptr, double dt = 0.0);

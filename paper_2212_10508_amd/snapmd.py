@@ -90,6 +90,11 @@ def lib():
     L.snapmd_profile_read.restype = C.c_int
     L.snapmd_pair_count.argtypes = [P, C.POINTER(C.c_int64)]
     L.snapmd_pair_count.restype = C.c_int
+    L.snapmd_ws_sites.argtypes = [P, C.POINTER(Batch), P, d, P, P, i32, P]
+    L.snapmd_ws_sites.restype = C.c_int
+    L.snapmd_relax.argtypes = [P, C.c_int, C.POINTER(Snap), C.POINTER(Fs), C.POINTER(Batch), P, i32, d, d, d,
+                               C.POINTER(d), C.POINTER(i32), P]
+    L.snapmd_relax.restype = C.c_int
     L.snapmd_set_coarse_snap.argtypes = [P, C.POINTER(Snap)]
     L.snapmd_set_coarse_snap.restype = C.c_int
     L.snapmd_set_chunk_plan.argtypes = [P, C.POINTER(i32), i32]
@@ -283,6 +288,35 @@ class Context:
         n = C.c_int64(0)
         self._check(lib().snapmd_profile_read(self.h, int(kernel), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def ws_sites(self, x, offset, box, a, stream=None):
+        """Wigner-Seitz site of every atom on the bcc lattice of constant a, and the number
+        of atoms of every site: (site int32 [N], occ int32 [n_sites]) device tensors."""
+        N = int(offset[-1])
+        box = np.asarray(box, np.float64).reshape(-1, 3)
+        n_sites = int(sum(2 * np.prod(np.rint(b / a)) for b in box))
+        site = torch.empty(N, dtype=torch.int32, device=x.device)
+        occ = torch.empty(max(n_sites, 1), dtype=torch.int32, device=x.device)
+        k = _Keep()
+        b = make_batch(k, offset, box)
+        self._check(lib().snapmd_ws_sites(self.h, C.byref(b), _dev(x, "x", (3, N)), float(a),
+                                          _dev(site, "site", (N,), torch.int32),
+                                          _dev(occ, "occ", None, torch.int32), int(occ.numel()), _stream(stream)))
+        return site, occ[:n_sites]
+
+    def relax(self, potential, x, offset, box, fs, J=None, beta=None, max_iter=5000, ftol=1e-4, alpha=0.01,
+              dmax=0.02, rcut=4.73, rfac0=0.99363, rmin0=0.0, stream=None):
+        """Steepest descent of the energy in place; returns (max |F| in eV/A, steps)."""
+        N = int(offset[-1])
+        k = _Keep()
+        b = make_batch(k, offset, box)
+        s = make_snap(k, J, beta, rcut, rfac0, rmin0) if potential == POT_FS_SNAP else None
+        fm = C.c_double(0.0)
+        its = C.c_int32(0)
+        self._check(lib().snapmd_relax(self.h, potential, C.byref(s) if s is not None else None, C.byref(make_fs(fs)),
+                                       C.byref(b), _dev(x, "x", (3, N)), int(max_iter), float(ftol), float(alpha),
+                                       float(dmax), C.byref(fm), C.byref(its), _stream(stream)))
+        return fm.value, its.value
 
     def set_coarse_snap(self, J=None, beta=None, rcut=4.73, rfac0=0.99363, rmin0=0.0):
         """Coarse propagator of parareal_iterate: Finnis-Sinclair + SNAP(J, beta) (the
