@@ -206,6 +206,29 @@ def other_configs(S, W, log):
     out["strategy_one_parareal_64x1025"] = {"coarse": "Finnis-Sinclair + SNAP twojmax 2", "ms_per_iteration": t * 1e3,
                                             "fine_atom_steps_per_s": 64 * n * 100 / t}
     log("strategy I: %.1f ms per parareal iteration" % (t * 1e3))
+    # the interstitial between its metastable states: 129 atoms, minimised, thermalised
+    # (paper's scheme), then 2000 BAOAB steps at 2000 K with the defect's site after each
+    from paper_2212_10508_amd import analysis as A
+    x, box = W.bcc_sia(4, jitter=0.0, seed=5)
+    n = x.shape[1]
+    J, beta = 6, W.snap_beta(6, seed=5)
+    xd, pd = dev(x), dev(W.maxwell_momenta(n, 2000.0, seed=5))
+    log("interstitial: minimisation and 10000 thermalising steps ...")
+    fmax, _ = A.equilibrate(ctx, xd, pd, box, W.FS_W, J=J, beta=beta, relax_iter=20000, thermal_steps=10000,
+                            T=2000.0, seed=5)
+    log("interstitial: equilibrated (max |F| after minimisation %.1e eV/A); 2000 steps ..." % fmax)
+    hist = []
+    t0 = time.perf_counter()
+    for step in range(2000):
+        S.langevin_steps(S.POT_FS_SNAP, xd, pd, [0, n], box, 1, dt=1e-3, gamma=1.0, mass=W.MASS_W, T=2000.0,
+                         seed=6, step0=step, noise_id=0, fs=W.FS_W, J=J, beta=beta)
+        hist.append(A.interstitial_site(ctx.ws_sites(xd, [0, n], box, W.A_W)[1]))
+    t = time.perf_counter() - t0
+    runs = A.residence_times(hist)
+    m, ci = A.mean_with_ci(runs[:-1])
+    out["interstitial_129_2000K_2000_steps"] = {"hops": len(runs) - 1, "mean_residence_steps": m, "ci95": ci,
+                                                "relaxed_fmax": fmax, "s": t}
+    log("interstitial: %d hops in 2000 steps, mean residence %.1f steps" % (len(runs) - 1, m))
     return out
 
 

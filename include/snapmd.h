@@ -224,7 +224,8 @@ int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_bat
  * once into a hipGraph, cached per context (keyed by sizes, parameters and device
  * pointers; at most 96 kept per workspace, least recently used dropped; every cached graph is dropped
  * when the context reallocates a work buffer) and replayed on the caller's stream.
- * enable = 0: kernels are launched one by one.  Results are identical either way.
+ * enable = 0: kernels are launched one by one.  Calls of more than 1000 steps are always
+ * launched one by one.  Results are identical either way.
  * While snapmd_profile is on, SNAP propagation is launched one by one. */
 int snapmd_use_graphs(snapmd_ctx *ctx, int enable);
 

@@ -550,6 +550,7 @@ int prepare_propagation_cells(snapmd_ctx *ctx, Work &w, int potential, const Bat
 }
 
 constexpr size_t kGraphCache = 96;  // captured launch sequences kept per workspace
+constexpr int kGraphMaxSteps = 1000;  // longest call captured into one graph
 
 // run_langevin through a cached hipGraph: the whole launch sequence of n_steps steps is
 // captured once per key (pointers, sizes, parameters baked into the kernel arguments)
@@ -557,8 +558,12 @@ constexpr size_t kGraphCache = 96;  // captured launch sequences kept per worksp
 int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
                        const SnapDev &sd, const LangevinDev &ld, int n_steps, double *x, double *p,
                        hipStream_t st) {
-    // SNAP propagation stays eager while kernel timing is on (the events time each launch)
-    if (!ctx->use_graphs || (ctx->prof.enabled && potential == SNAPMD_POT_FS_SNAP)) {
+    // SNAP propagation stays eager while kernel timing is on (the events time each launch).
+    // Calls of more than kGraphMaxSteps steps are launched one by one too: a capture is
+    // one chain of about 16 nodes per step, and such chains are kept to the lengths the
+    // runtime has been exercised with here (10,000 steps, 160,000 nodes, ended the
+    // process).
+    if (!ctx->use_graphs || (ctx->prof.enabled && potential == SNAPMD_POT_FS_SNAP) || n_steps > kGraphMaxSteps) {
         run_langevin(ctx, w, f, potential, bd, fp, sd, ld, n_steps, x, p, st);
         return SNAPMD_OK;
     }

@@ -21,6 +21,10 @@ def S():
     return snapmd
 
 
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
 def _batch(n_sys=3, seed=11):
     xs, ps = [], []
     for s in range(n_sys):
@@ -88,3 +92,21 @@ def test_graph_parareal_iterations_match_eager(S):
     for (d0, q0, p0), (d1, q1, p1) in zip(out[False], out[True]):
         assert d0 == d1
         assert torch.equal(q0, q1) and torch.equal(p0, p1)
+
+
+def test_long_call_runs_uncaptured_and_equals_split_calls(S):
+    """A call of more than 1000 steps is launched kernel by kernel (not captured); BAOAB
+    splits exactly, so 1200 steps in one call equal two calls of 600 (captured)."""
+    x, box = W.bcc_sia(4, jitter=0.05, seed=41)
+    n = x.shape[1]
+    p = W.maxwell_momenta(n, 1000.0, seed=41)
+    kw = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=3, noise_id=0, fs=W.FS_W)
+    ctx = S.context()
+    xa, pa = dev(x), dev(p)
+    ctx.langevin_steps(S.POT_FS, xa, pa, [0, n], box, 1200, step0=0, **kw)
+    xb, pb = dev(x), dev(p)
+    ctx.langevin_steps(S.POT_FS, xb, pb, [0, n], box, 600, step0=0, **kw)
+    ctx.langevin_steps(S.POT_FS, xb, pb, [0, n], box, 600, step0=600, **kw)
+    torch.cuda.synchronize()
+    assert torch.max(torch.abs(xa - xb)).item() < 1e-9
+    assert torch.max(torch.abs(pa - pb)).item() < 1e-9 * torch.max(torch.abs(pb)).item()
