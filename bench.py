@@ -261,7 +261,7 @@ def pmc_probe(S, W, J, S_slabs):
 # of the file); after a change the traffic is reported as null until it is measured again.
 TRAFFIC = {
     "adjoint": ("paper_2212_10508_amd/csrc/adjoint.hip",
-                "28237c58665b365c803e4e9f14e9d2280dee307101bc75398dd014fed491aee1", 4860.4, "atom"),
+                "b213ae4ad852068155c19b9c3e32d3e1c660a037de09948fab4e59a3dcfe1fd4", 5187.9, "atom"),
     "dedr": ("paper_2212_10508_amd/csrc/kernels.hip",
              "a7bba27061de622a7f582aaa6300e03d50a5c4429bad170ad28fefa13f4516a4", 447.6, "pair"),
     "density": ("paper_2212_10508_amd/csrc/kernels.hip",
