@@ -55,6 +55,28 @@ def snap_counts(J):
     return nUh, nZel, nZt
 
 
+def dedr_flops(J):
+    """FP64 FLOPs (FMA = 2) per pair of the dE/dr pass as implemented: the column chains of
+    the unnormalised Wigner-D coefficients P (one level: 12 + 14 n), per stored element
+    the terms of S0 = sum Re(conj(Y~) P[k]) (4), of Q0 (7), Qp (10) and Qm (10) (the
+    derivatives come from the su(2) generators, three neighbours in a column), and per
+    direction the combination S = Re(X11 Q0 + X21 Qp + X12 Qm), g = dfc S0 + fc S (33).
+    The derivative recursion this replaces counts 136 per pair and element."""
+    adv = lambda N: 12 + 14 * N
+    f = 0
+    for C in range(J // 2 + 1):
+        if C > 0:
+            f += adv(2 * C - 1)
+        for N in range(2 * C, J + 1):
+            if N > 2 * C:
+                f += adv(N - 1)
+            for k in range(N + 1):
+                if 2 * C == N and 2 * k > N:
+                    continue
+                f += 4 + (7 if 2 * k != N else 0) + (10 if k + 1 <= N else 0) + (10 if k >= 1 else 0)
+    return f + 3 * 33
+
+
 def cpu_baseline(wl, J, nsteps=40):
     from oracle import oracle as O
     from paper_2212_10508_amd import workloads as W
@@ -388,9 +410,9 @@ def main():
     nUh, nZel, nZt = snap_counts(J)
     atoms = S_slabs * n
     evals = args.steps * (L + 1)
-    flops = {"dedr": 136.0 * nUh * n_pairs * evals, "adjoint": (8.0 * nZt + 4.0 * nZel) * atoms * evals,
+    flops = {"dedr": float(dedr_flops(J)) * n_pairs * evals, "adjoint": (8.0 * nZt + 4.0 * nZel) * atoms * evals,
              "density": 22.0 * nUh * n_pairs * evals}
-    kname = {"dedr": "k_dedr<8> (SNAP dE/dr, adjoint contraction)",
+    kname = {"dedr": "k_dedr<8> (SNAP dE/dr, su(2)-generator contraction)",
              "adjoint": "k_adjoint_lds<8> (SNAP adjoint Y)", "density": "k_density<8> (SNAP density u)"}
     dom = max(("dedr", "adjoint", "density"), key=lambda k: prof[k][0])
     kernels = {k: {"avg_ms": prof[k][0] / max(prof[k][1], 1), "launches": prof[k][1],

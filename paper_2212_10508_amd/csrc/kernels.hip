@@ -740,68 +740,79 @@ __global__ void __launch_bounds__(256) k_bispectrum(int N, int K, const double2 
 }
 
 // ---------------------------------------------------------------------------
-// dE_i/dr_ij per pair: lane = pair.  Column chains l = 0..J/2 of P and dP/dx_al,
-// the column at level 2l+1 saved as the seed of chain l+1 (mirror).
-//   S0 = sum Re(conj(Y~) P),  S_al = sum Re(conj(Y~) dP_al),  g_al = dfc_al S0 + fc S_al
+// dE_i/dr_ij per pair: lane = pair.  Column chains l = 0..J/2 of P only; the column at
+// level 2l+1 is saved as the (mirrored) seed of chain l+1.
+//
+// The derivatives of P come from the Lie algebra of SU(2) instead of a recursion of their
+// own.  D is a representation, so dD/dr_al = dD(X_al) D with X_al = (dg/dr_al) g^-1 in
+// su(2), and dD(X) acts on the rows of a column as a three-term operator: in the
+// unnormalised coefficients P (D = Nrm P, Nrm(n, k, l) = sqrt(k! (n-k)! / (l! (n-l)!)))
+//   dP[k] = X11 (2k - n) P[k] + X21 (k + 1) P[k+1] + X12 (n - k + 1) P[k-1],
+// X11 = a' conj(a) + b' conj(b), X12 = b' a - a' b, X21 = -conj(X12).  X_al does not depend
+// on the element, so the contraction needs three sums per pair, whatever the direction:
+//   Q0 = sum (2k - n) conj(Y~) P[k],  Qp = sum (k + 1) conj(Y~) P[k+1],
+//   Qm = sum (n - k + 1) conj(Y~) P[k-1],
+// and S_al = Re(X11_al Q0 + X21_al Qp + X12_al Qm), S0 = sum Re(conj(Y~) P[k]),
+// g_al = dfc_al S0 + fc S_al.
 // ---------------------------------------------------------------------------
+struct DedrAcc {
+    double S0 = 0.0;
+    double2 Q0 = {0.0, 0.0}, Qp = {0.0, 0.0}, Qm = {0.0, 0.0};
+};
+
+// acc += w conj(y) v
+__device__ __forceinline__ void cjmac(double2 &acc, double w, double2 y, double2 v) {
+    const double yx = w * y.x, yy = w * y.y;
+    acc.x = fma(yx, v.x, fma(yy, v.y, acc.x));
+    acc.y = fma(yx, v.y, fma(-yy, v.x, acc.y));
+}
+
 template <int J, int C, int N>
-__device__ __forceinline__ void dedr_level(double2 (&P)[J + 1], double2 (&dP)[3][J + 1], double2 (&sP)[J + 1],
-                                           double2 (&sdP)[3][J + 1], double2 b, double2 ab,
-                                           const double2 (&db)[3], const double2 (&dab)[3],
-                                           const double2 *__restrict__ yt, int Natoms, double &S0,
-                                           double (&S)[3]) {
-    if constexpr (N > 2 * C) chain_advance_d<J, N - 1>(P, dP, b, ab, db, dab);
+__device__ __forceinline__ void dedr_level(double2 (&P)[J + 1], double2 (&sP)[J + 1], double2 b, double2 ab,
+                                           const double2 *__restrict__ yt, int Natoms, DedrAcc &A) {
+    if constexpr (N > 2 * C) chain_advance<J, N - 1>(P, b, ab);
 #pragma unroll
     for (int k = 0; k <= N; ++k) {
         if (2 * C == N && 2 * k > N) continue;  // mirrored half of the middle column
         const double2 y = yt[(size_t)half_idx(N, k, C) * Natoms];
-        S0 = fma(y.x, P[k].x, fma(y.y, P[k].y, S0));
-#pragma unroll
-        for (int al = 0; al < 3; ++al) S[al] = fma(y.x, dP[al][k].x, fma(y.y, dP[al][k].y, S[al]));
+        const double tx = fma(y.x, P[k].x, y.y * P[k].y);
+        A.S0 += tx;
+        if (2 * k != N) {
+            const double ty = fma(y.x, P[k].y, -y.y * P[k].x);
+            A.Q0.x = fma((double)(2 * k - N), tx, A.Q0.x);
+            A.Q0.y = fma((double)(2 * k - N), ty, A.Q0.y);
+        }
+        if (k + 1 <= N) cjmac(A.Qp, (double)(k + 1), y, P[k + 1]);
+        if (k >= 1) cjmac(A.Qm, (double)(N - k + 1), y, P[k - 1]);
     }
     if constexpr (N == 2 * C + 1 && 2 * C + 2 <= J) {
 #pragma unroll
-        for (int k = 0; k <= N; ++k) {
-            sP[k] = P[k];
-#pragma unroll
-            for (int al = 0; al < 3; ++al) sdP[al][k] = dP[al][k];
-        }
+        for (int k = 0; k <= N; ++k) sP[k] = P[k];
     }
-    if constexpr (N < J) dedr_level<J, C, N + 1>(P, dP, sP, sdP, b, ab, db, dab, yt, Natoms, S0, S);
+    if constexpr (N < J) dedr_level<J, C, N + 1>(P, sP, b, ab, yt, Natoms, A);
 }
 
 template <int J, int C>
-__device__ __forceinline__ void dedr_chain(double2 (&P)[J + 1], double2 (&dP)[3][J + 1], double2 (&sP)[J + 1],
-                                           double2 (&sdP)[3][J + 1], double2 b, double2 ab,
-                                           const double2 (&db)[3], const double2 (&dab)[3],
-                                           const double2 *__restrict__ yt, int Natoms, double &S0,
-                                           double (&S)[3]) {
+__device__ __forceinline__ void dedr_chain(double2 (&P)[J + 1], double2 (&sP)[J + 1], double2 b, double2 ab,
+                                           const double2 *__restrict__ yt, int Natoms, DedrAcc &A) {
     if constexpr (C == 0) {
         P[0] = make_double2(1.0, 0.0);
-#pragma unroll
-        for (int al = 0; al < 3; ++al) dP[al][0] = make_double2(0.0, 0.0);
     } else {
         constexpr int n = 2 * C - 1;
 #pragma unroll
-        for (int k = 0; k <= n; ++k) {
-            P[k] = sP[k];
-#pragma unroll
-            for (int al = 0; al < 3; ++al) dP[al][k] = sdP[al][k];
-        }
+        for (int k = 0; k <= n; ++k) P[k] = sP[k];
         chain_mirror<J, C>(P);
-#pragma unroll
-        for (int al = 0; al < 3; ++al) chain_mirror<J, C>(dP[al]);
-        chain_advance_d<J, n>(P, dP, b, ab, db, dab);
+        chain_advance<J, n>(P, b, ab);
     }
-    dedr_level<J, C, 2 * C>(P, dP, sP, sdP, b, ab, db, dab, yt, Natoms, S0, S);
-    if constexpr (2 * C + 2 <= J) dedr_chain<J, C + 1>(P, dP, sP, sdP, b, ab, db, dab, yt, Natoms, S0, S);
+    dedr_level<J, C, 2 * C>(P, sP, b, ab, yt, Natoms, A);
+    if constexpr (2 * C + 2 <= J) dedr_chain<J, C + 1>(P, sP, b, ab, yt, Natoms, A);
 }
 
 // One wave of 64 consecutive pairs (CSR order, so a few atoms i).  When the wave's
 // pairs belong to at most kDedrAtoms atoms, their Y~ rows are first copied into LDS
 // (coalesced: consecutive lanes take consecutive atoms of one element) and the chains
 // read Y~ from there; otherwise from global memory.
-constexpr int kDedrAtoms = 6;
+constexpr int kDedrAtoms = 5;
 
 template <int J>
 __device__ __forceinline__ void dedr_pair(int p, size_t Pcap, const double (&g)[20],
@@ -810,19 +821,21 @@ __device__ __forceinline__ void dedr_pair(int p, size_t Pcap, const double (&g)[
     const double2 a = make_double2(g[0], g[1]);
     const double2 b = make_double2(g[2], g[3]);
     const double2 ab = cconj(a);
-    double2 db[3], dab[3];
-    double dfc[3];
+    double2 P[J + 1], sP[J + 1];
+    DedrAcc A;
+    dedr_chain<J, 0>(P, sP, b, ab, yt, ystride, A);
 #pragma unroll
     for (int al = 0; al < 3; ++al) {
-        dab[al] = make_double2(g[5 + al], -g[8 + al]);
-        db[al] = make_double2(g[11 + al], g[14 + al]);
-        dfc[al] = g[17 + al];
+        const double2 da = make_double2(g[5 + al], g[8 + al]);
+        const double2 db = make_double2(g[11 + al], g[14 + al]);
+        // X11 = da conj(a) + db conj(b) (imaginary), X12 = db a - da b, X21 = -conj(X12)
+        const double x11 = fma(da.y, a.x, fma(-da.x, a.y, fma(db.y, b.x, -db.x * b.y)));
+        const double2 x12 = csub(cmul(db, a), cmul(da, b));
+        // Re(i x11 Q0 + X21 Qp + X12 Qm), X21 = (-x12.x, x12.y)
+        const double s = fma(-x11, A.Q0.y, fma(-x12.x, A.Qp.x, fma(-x12.y, A.Qp.y,
+                                                                    fma(x12.x, A.Qm.x, -x12.y * A.Qm.y))));
+        dedr[al * Pcap + p] = fma(g[17 + al], A.S0, fc * s);
     }
-    double2 P[J + 1], dP[3][J + 1], sP[J + 1], sdP[3][J + 1];
-    double S0 = 0.0, S[3] = {0.0, 0.0, 0.0};
-    dedr_chain<J, 0>(P, dP, sP, sdP, b, ab, db, dab, yt, ystride, S0, S);
-#pragma unroll
-    for (int al = 0; al < 3; ++al) dedr[al * Pcap + p] = fma(dfc[al], S0, fc * S[al]);
 }
 
 template <int J>
