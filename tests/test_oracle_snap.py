@@ -285,3 +285,38 @@ def test_fs_forces_finite_difference_and_net_zero():
         xm[al, i] -= h
         fd = -(O.fs_compute(xp, box, W.FS_W)["E"] - O.fs_compute(xm, box, W.FS_W)["E"]) / (2 * h)
         assert abs(fd - f[al, i]) < 1e-7 * np.abs(f).max()
+
+
+def test_wigner_d_derivative_is_generator_action():
+    """D is a representation of SU(2), so along a path g(t): dD/dt = dD(X) D with
+    X = g' g^-1 in su(2), whose action on the rows of a column is three-term:
+    dD[k] = X11 (2k - n) D[k] + X21 sqrt((k+1)(n-k)) D[k+1] + X12 sqrt(k(n-k+1)) D[k-1].
+    Checked against central differences of the defined D along the SNAP map of a moving
+    neighbour (the identity the force pass uses)."""
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        r = rng.normal(size=3)
+        r *= rng.uniform(2.0, 4.5) / np.linalg.norm(r)
+        a, b = defn.su2_from_neighbor(r, RCUT, RFAC0, 0.0)
+        for al in range(3):
+            h = 1e-6
+            e = np.zeros(3)
+            e[al] = h
+            ap, bp = defn.su2_from_neighbor(r + e, RCUT, RFAC0, 0.0)
+            am, bm = defn.su2_from_neighbor(r - e, RCUT, RFAC0, 0.0)
+            da, db = (ap - am) / (2 * h), (bp - bm) / (2 * h)
+            X11 = da * np.conj(a) + db * np.conj(b)
+            X12 = db * a - da * b
+            X21 = -np.conj(X12)
+            assert abs(X11.real) < 1e-9  # su(2): X11 is imaginary
+            for n in (1, 4, 8):
+                D = defn.wigner_d(n, a, b)
+                fd = (defn.wigner_d(n, ap, bp) - defn.wigner_d(n, am, bm)) / (2 * h)
+                G = np.zeros_like(D)
+                for k in range(n + 1):
+                    G[k] = X11 * (2 * k - n) * D[k]
+                    if k < n:
+                        G[k] += X21 * np.sqrt((k + 1) * (n - k)) * D[k + 1]
+                    if k > 0:
+                        G[k] += X12 * np.sqrt(k * (n - k + 1)) * D[k - 1]
+                assert np.abs(G - fd).max() < 1e-8 * max(1.0, np.abs(fd).max())
