@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CUs x 128 FLOP/clk x 2.4 GHz
+PROF_EVERY = 8            # HIP events around every 8th launch of each timed kernel
 
 
 def log(*a):
@@ -316,6 +317,8 @@ def main():
     ap.add_argument("--per-slab-sample", type=int, default=4, help="slabs timed one by one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in slab chunk plan")
+    ap.add_argument("--plan", default=None, help="slab chunks, e.g. 7,29,28 (implies --no-tune)")
+    ap.add_argument("--sweep-workgroups", type=int, default=0, help="coarse sweep width (0: built in)")
     ap.add_argument("--no-configs", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run two SNAP force evaluations of the 64 x 1025-atom batch and a 512 MiB device "
@@ -373,15 +376,21 @@ def main():
     n_cus = torch.cuda.get_device_properties(0).multi_processor_count
     builtin_plan = ctx.chunk_plan(S_slabs, n)
     autotune = None
-    if not args.no_tune:
+    ctx.set_sweep_workgroups(args.sweep_workgroups)
+    if args.plan:
+        ctx.set_chunk_plan([int(v) for v in args.plan.split(",")])
+    elif not args.no_tune:
         from paper_2212_10508_amd import tune
 
         def timed_iteration():
             iteration()
             torch.cuda.synchronize()
 
+        sweep_k, ktimes = tune.tune_sweep_width(ctx, timed_iteration, n, log=log)
         plan, times = tune.tune_chunk_plan(ctx, timed_iteration, S_slabs, n, n_cus, log=log)
-        autotune = {"plans_timed": len(times), "builtin_plan": builtin_plan,
+        autotune = {"sweep_workgroups": sweep_k,
+                    "sweep_ms": {str(k): v * 1e3 for k, v in ktimes.items()},
+                    "plans_timed": len(times), "builtin_plan": builtin_plan,
                     "builtin_ms": times[tuple(builtin_plan)] * 1e3, "best_plan": plan,
                     "best_ms": times[tuple(plan)] * 1e3}
         log("chunk plan: %s (%.2f ms; built-in %s %.2f ms)" % (plan, autotune["best_ms"], builtin_plan,
@@ -390,7 +399,9 @@ def main():
     q_cur.copy_(q_start)
     p_cur.copy_(p_start)
     torch.cuda.synchronize()
-    ctx.profile(True)
+    # HIP events around every PROF_EVERY-th launch of each timed kernel (an event record
+    # idles the device for a few microseconds; a sample keeps that out of the timed run)
+    ctx.profile(True, every=PROF_EVERY)
     t0 = time.perf_counter()
     for k in range(args.steps):
         d = iteration()
@@ -414,14 +425,18 @@ def main():
              "density": 22.0 * nUh * n_pairs * evals}
     kname = {"dedr": "k_dedr<8> (SNAP dE/dr, su(2)-generator contraction)",
              "adjoint": "k_adjoint_lds<8> (SNAP adjoint Y)", "density": "k_density<8> (SNAP density u)"}
-    dom = max(("dedr", "adjoint", "density"), key=lambda k: prof[k][0])
-    kernels = {k: {"avg_ms": prof[k][0] / max(prof[k][1], 1), "launches": prof[k][1],
-                   "gflop_per_launch": (flops[k] / max(prof[k][1], 1) / 1e9) if k in flops else None,
-                   "tflops": (flops[k] / (prof[k][0] * 1e-3) / 1e12) if k in flops else None}
+    # every force evaluation launches each kernel once per slab chunk; the average launch
+    # time comes from the sampled launches
+    launches = len(chunk_plan) * evals
+    avg = {k: prof[k][0] / max(prof[k][1], 1) for k in prof}
+    dom = max(("dedr", "adjoint", "density"), key=lambda k: avg[k])
+    kernels = {k: {"avg_ms": avg[k], "launches": launches, "launches_timed": prof[k][1],
+                   "gflop_per_launch": (flops[k] / launches / 1e9) if k in flops else None,
+                   "tflops": (flops[k] / launches / (avg[k] * 1e-3) / 1e12) if k in flops else None}
                for k in prof}
     achieved = kernels[dom]["tflops"]
     per_unit, unit = traffic_per_unit(dom)
-    units_per_launch = (atoms if unit == "atom" else n_pairs) * evals / max(kernels[dom]["launches"], 1)
+    units_per_launch = (atoms if unit == "atom" else n_pairs) * evals / launches
     traffic = per_unit * units_per_launch if per_unit is not None else None
 
     extras = {}
@@ -475,7 +490,8 @@ def main():
         "config": {"workload": "parareal iteration, 64 slabs x 1025-atom W bcc + <111> SIA, SNAP twojmax 8 "
                                "+ Finnis-Sinclair fine / FS coarse, L=100 BAOAB steps, 1 fs, 1000 K",
                    "atoms": n, "slabs": S_slabs, "L": L, "twojmax": J, "pairs": n_pairs,
-                   "mean_neighbours": n_pairs / atoms, "chunk_plan": chunk_plan},
+                   "mean_neighbours": n_pairs / atoms, "chunk_plan": chunk_plan,
+                   "sweep_workgroups": ctx.sweep_workgroups(n)},
         "roofline": {"bound": "alu", "kernel": kname[dom], "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "traffic_bytes_per_" + unit: per_unit,

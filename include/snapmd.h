@@ -268,9 +268,27 @@ int snapmd_relax(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, const 
 int snapmd_set_chunk_plan(snapmd_ctx *ctx, const int32_t *sizes, int32_t n);
 int snapmd_chunk_plan(snapmd_ctx *ctx, int32_t S, int32_t N, int32_t *sizes, int32_t *n);
 
+/* Width of the on-device coarse sweep (tuning, not part of the method).  Systems of 512 to
+ * 65,535 atoms are swept by K workgroups (one compute unit each) that exchange positions and
+ * embedding derivatives every step; K trades the compute per workgroup against the cost of
+ * the exchanges and against compute units taken from the SNAP propagation running beside
+ * it.  snapmd_set_sweep_workgroups(ctx, K) asks for K workgroups in later calls of
+ * parareal_iterate (0: the built-in choice, 8 or 16); K = 1 asks for the one-workgroup sweep
+ * (positions, embedding derivatives and lists in the local memory of one compute unit, no
+ * exchanges), which fits systems of up to about 1,500 atoms; a K that the system cannot
+ * use (more than 256 atoms per workgroup, or a local-memory tile over 160 KB) falls back to
+ * the built-in choice.  0 <= K <= 64, else SNAPMD_EINVAL.  snapmd_sweep_workgroups writes
+ * the width a system of N atoms would get into *K (1: one workgroup, 0: driven from the
+ * host).  Results do not depend on K beyond the rounding order of the partial sums of the
+ * adaptive criterion, which every K combines in a fixed order. */
+int snapmd_set_sweep_workgroups(snapmd_ctx *ctx, int32_t K);
+int snapmd_sweep_workgroups(snapmd_ctx *ctx, int32_t N, int32_t *K);
+
 /* Measurement support (not part of the propagation):
- * snapmd_profile(ctx, 1) starts recording HIP events around the SNAP kernels and the
- * neighbour build on the stream they are launched on (clears earlier records; 0 stops).
+ * snapmd_profile(ctx, s) with s >= 1 starts recording HIP events around every s-th launch
+ * of each of the SNAP kernels and the neighbour build, on the stream they are launched on
+ * (clears earlier records; 0 stops; s < 0: SNAPMD_EINVAL).  Every event record leaves the
+ * device idle for a few microseconds, so a sample (s > 1) disturbs the measured run less.
  * snapmd_profile_read synchronises the device and returns, for kernel id
  * 0 = SNAP dE/dr, 1 = SNAP adjoint, 2 = SNAP density, 3 = neighbour build,
  * the summed duration (ms) and the number of launches recorded.  Neighbour builds

@@ -96,11 +96,10 @@ struct snapmd_ctx {
     std::mutex err_mu;
     hipStream_t sweep_stream = nullptr;  // the coarse sweep, overlapping the batched propagation
     hipStream_t coarse_stream = nullptr; // the batched coarse propagation of a parareal iteration
-    hipStream_t fork_st = nullptr;       // Finnis-Sinclair pass beside the SNAP chain
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<hipEvent_t> pipe_ev;
     uint64_t graph_clock[2] = {};
     std::vector<int> chunk_override;     // slab chunks set by snapmd_set_chunk_plan (empty: built in)
+    int sweep_k_override = 0;            // sweep workgroups set by snapmd_set_sweep_workgroups (0: built in)
     DBuf<int4> d_ws;                     // Wigner-Seitz lattice of each system
     DBuf<unsigned long long> d_fmax;     // max |F|^2 of the relaxation
     // coarse propagator of parareal_iterate: Finnis-Sinclair, plus SNAP when set
@@ -186,7 +185,7 @@ int ensure_atoms(snapmd_ctx *ctx, size_t N) {
     if ((rc = dalloc(ctx, &w.rev, w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.rho, cap))) return rc;
     if ((rc = dalloc(ctx, &w.geo, 20 * w.Pcap))) return rc;
-    if ((rc = dalloc(ctx, &w.ell, 5 * w.Pcap))) return rc;
+    if ((rc = dalloc(ctx, &w.ell, 6 * w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.nbr_t, w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.ph, 3 * cap))) return rc;
     if ((rc = dalloc(ctx, &w.dedr, 3 * w.Pcap))) return rc;
@@ -230,7 +229,7 @@ int ensure_atoms_coarse(snapmd_ctx *ctx, size_t N, bool snap = false) {
     }
     if (snap || (ctx->cap_atoms_cs > 0 && grow_list)) {
         const size_t Pc = cap * kMaxNeigh;
-        if ((rc = dalloc(ctx, &w.geo, 20 * Pc)) || (rc = dalloc(ctx, &w.ell, 5 * Pc)) ||
+        if ((rc = dalloc(ctx, &w.geo, 20 * Pc)) || (rc = dalloc(ctx, &w.ell, 6 * Pc)) ||
             (rc = dalloc(ctx, &w.nbr_t, Pc)) || (rc = dalloc(ctx, &w.dedr, 3 * Pc)) ||
             (rc = dalloc(ctx, &w.u, (size_t)n_half(kMaxJ) * cap)) ||
             (rc = dalloc(ctx, &w.ytil, (size_t)n_half(kMaxJ) * cap)))
@@ -493,9 +492,10 @@ int neighbors(snapmd_ctx *ctx, Work &w, const BatchDev &bd0, const double *x, do
 }
 
 // Forces of a propagation step (e_atom not wanted).  For FS + SNAP the Finnis-Sinclair
-// pass runs on a second stream beside the SNAP chain, joined before the SNAP gather adds
-// into f.  With p_kick the closing half kick of the step is applied too (by the SNAP
-// gather, or by a kernel of its own after the Finnis-Sinclair force).
+// terms ride along the SNAP passes over the same list (the density term in the slot
+// table, rho and F'(rho) in the density pass, the pair force in the gather), so the step
+// is one chain of kernels.  With p_kick the closing half kick of the step is applied too
+// (by the SNAP gather, or by a kernel of its own after the Finnis-Sinclair force).
 void enqueue_forces(snapmd_ctx *ctx, Work &w, int potential, const BatchDev &bd, const double *x,
                     const FsParams *fp, const SnapDev *sd, double *f, hipStream_t st, bool fresh = true,
                     double *p_kick = nullptr, double dt = 0.0) {
@@ -505,20 +505,11 @@ void enqueue_forces(snapmd_ctx *ctx, Work &w, int potential, const BatchDev &bd,
     ctx->prof.begin(PROF_NEIGH, st);
     (void)neighbors(ctx, w, bd, x, rc, fresh, st, true);
     ctx->prof.end(st);
-    // the fork stream and its events belong to the fine workspace (the coarse one may be
-    // queued from another host thread at the same time)
-    if (potential == SNAPMD_POT_FS_SNAP && ctx->fork_st && &w == &ctx->w) {
-        (void)hipEventRecord(ctx->ev_fork, st);
-        (void)hipStreamWaitEvent(ctx->fork_st, ctx->ev_fork, 0);
-        launch_fs(bd, x, *fp, w, f, nullptr, 0, ctx->fork_st, true);
-        (void)hipEventRecord(ctx->ev_join, ctx->fork_st);
-        launch_snap(sd->J, bd, x, *sd, w, f, nullptr, 1, st, &ctx->prof, ctx->ev_join, p_kick, dt);
+    if (potential == SNAPMD_POT_FS_SNAP) {
+        launch_snap(sd->J, bd, x, *sd, w, f, nullptr, 0, st, &ctx->prof, nullptr, p_kick, dt, fp);
     } else {
         launch_fs(bd, x, *fp, w, f, nullptr, 0, st, true);
-        if (potential == SNAPMD_POT_FS_SNAP)
-            launch_snap(sd->J, bd, x, *sd, w, f, nullptr, 1, st, &ctx->prof, nullptr, p_kick, dt);
-        else if (p_kick)
-            launch_baoab_post(bd, p_kick, f, dt, st);
+        if (p_kick) launch_baoab_post(bd, p_kick, f, dt, st);
     }
 }
 
@@ -699,12 +690,6 @@ int snapmd_create(snapmd_ctx **out, int hip_device) {
     adjoint_init_attributes();
     sweep_init_attributes();
     neigh_init_attributes();
-    if (hipStreamCreateWithFlags(&ctx->fork_st, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
-        snapmd_destroy(ctx);
-        return SNAPMD_EHIP;
-    }
     if (dalloc(ctx, &ctx->w.status, 1) != SNAPMD_OK || hipMemset(ctx->w.status, 0, sizeof(int)) != hipSuccess ||
         dalloc(ctx, &ctx->w.flag, 1) != SNAPMD_OK || hipMemset(ctx->w.flag, 0, sizeof(int)) != hipSuccess) {
         snapmd_destroy(ctx);
@@ -724,9 +709,6 @@ void snapmd_destroy(snapmd_ctx *ctx) {
         if (c) (void)hipStreamDestroy(c);
     if (ctx->sweep_stream) (void)hipStreamDestroy(ctx->sweep_stream);
     if (ctx->coarse_stream) (void)hipStreamDestroy(ctx->coarse_stream);
-    if (ctx->fork_st) (void)hipStreamDestroy(ctx->fork_st);
-    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     for (hipEvent_t e : ctx->pipe_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -917,13 +899,15 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     }
     // the sweep on the device: several workgroups exchanging through device memory, or
     // one LDS-resident workgroup; else driven from the host
-    const int mcK = (bbk || csnap) ? 0 : sweep_mc_workgroups(N);
+    // width 1 asks for the one-workgroup sweep where it fits
+    const bool one_wg = ctx->sweep_k_override == 1 && sweep_fits_lds(N);
+    const int mcK = (bbk || csnap || one_wg) ? 0 : sweep_mc_workgroups(N, ctx->sweep_k_override);
     const bool lds_sweep = !bbk && !csnap && (mcK > 0 || sweep_fits_lds(N));
     if (mcK > 0) {
         sw.K = mcK;
         sw.A = (N + mcK - 1) / mcK;
         if ((rc = ensure(ctx, ctx->sw_gx, 6 * (size_t)N)) || (rc = ensure(ctx, ctx->sw_gdfe, 2 * (size_t)N)) ||
-            (rc = ensure(ctx, ctx->sw_gpart, 8 * (size_t)mcK)) || (rc = ensure(ctx, ctx->sw_bar, 1)) ||
+            (rc = ensure(ctx, ctx->sw_gpart, 8 * (size_t)mcK)) || (rc = ensure(ctx, ctx->sw_bar, (size_t)mcK)) ||
             (rc = ensure(ctx, ctx->sw_abort, 1)))
             return rc;
         sw.gx = ctx->sw_gx.p;
@@ -935,7 +919,7 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     // barrier counters start from zero at every launch of the multi-workgroup sweep
     auto sweep_launch = [&](const SweepLaunch &l, hipStream_t s) -> int {
         if (l.K > 0) {
-            HIPCHK(hipMemsetAsync(l.bar, 0, sizeof(unsigned long long), s));
+            HIPCHK(hipMemsetAsync(l.bar, 0, (size_t)l.K * sizeof(unsigned long long), s));
             HIPCHK(hipMemsetAsync(l.abort, 0, sizeof(int), s));
         }
         launch_coarse_sweep(l, s);
@@ -1295,6 +1279,21 @@ int snapmd_set_chunk_plan(snapmd_ctx *ctx, const int32_t *sizes, int32_t n) {
     return SNAPMD_OK;
 }
 
+int snapmd_set_sweep_workgroups(snapmd_ctx *ctx, int32_t K) {
+    if (!ctx) return SNAPMD_EINVAL;
+    if (K < 0 || K > 64) return fail(ctx, SNAPMD_EINVAL, "sweep workgroups: need 0 <= K <= 64 (got %d)", K);
+    ctx->sweep_k_override = K;
+    return SNAPMD_OK;
+}
+
+int snapmd_sweep_workgroups(snapmd_ctx *ctx, int32_t N, int32_t *K) {
+    if (!ctx || !K) return SNAPMD_EINVAL;
+    const bool one_wg = ctx->sweep_k_override == 1 && sweep_fits_lds(N);
+    *K = one_wg ? 1 : sweep_mc_workgroups(N, ctx->sweep_k_override);
+    if (*K == 0 && sweep_fits_lds(N)) *K = 1;
+    return SNAPMD_OK;
+}
+
 int snapmd_chunk_plan(snapmd_ctx *ctx, int32_t S, int32_t N, int32_t *sizes, int32_t *n) {
     if (!ctx) return SNAPMD_EINVAL;
     if (S < 1 || N < 1 || !sizes || !n) return fail(ctx, SNAPMD_EINVAL, "chunk plan: need S, N >= 1 and outputs");
@@ -1313,7 +1312,9 @@ int snapmd_use_graphs(snapmd_ctx *ctx, int enable) {
 
 int snapmd_profile(snapmd_ctx *ctx, int enable) {
     if (!ctx) return SNAPMD_EINVAL;
+    if (enable < 0) return fail(ctx, SNAPMD_EINVAL, "profile: need enable >= 0 (got %d)", enable);
     ctx->prof.enabled = enable ? 1 : 0;
+    ctx->prof.stride = enable ? enable : 1;
     ctx->prof.reset();
     return SNAPMD_OK;
 }

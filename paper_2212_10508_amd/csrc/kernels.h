@@ -22,6 +22,15 @@ struct FsParams {
     double A, d, c, c0, c1, c2;
 };
 
+// Finnis-Sinclair terms folded into the SNAP passes of a propagation step (on = 0: SNAP
+// alone): phi(r) is stored beside a, b, f_c per list slot, the density pass sums rho_i and
+// writes dF[i] = F'(rho_i), and the gather adds the pair force of the FS energy.
+struct FsFuse {
+    FsParams fp;
+    double *dF;
+    int on;
+};
+
 struct SnapGeoParams {
     double rcut, rfac0, rmin0;
 };
@@ -81,7 +90,7 @@ struct Work {
     double *xref = nullptr; // [3][N] positions at the last build
     double *rho = nullptr;
     double *geo = nullptr;  // [20][Pcap]
-    double *ell = nullptr;  // [5][kMaxNeigh][N] a, b, f_c by (list slot, atom)
+    double *ell = nullptr;  // [6][kMaxNeigh][N] a, b, f_c (and the FS phi) by (list slot, atom)
     int *nbr_t = nullptr;   // [kMaxNeigh][N] neighbour j by (list slot, atom)
     double *ph = nullptr;   // [3][N] BBK: p_{l-1/2} of the running call
     double *dedr = nullptr; // [3][Pcap]
@@ -90,8 +99,14 @@ struct Work {
 
 // Optional per-kernel timing with HIP events on the launch stream (for the roofline).
 enum { PROF_DEDR = 0, PROF_ADJOINT = 1, PROF_DENSITY = 2, PROF_NEIGH = 3, PROF_N = 4 };
+// HIP events around a sample of the launches: every stride-th launch of each kernel id
+// (an event record leaves the device idle for a few microseconds, so recording around
+// every launch would slow the run being measured).
 struct KernelProf {
     int enabled = 0;
+    int stride = 1;
+    long long calls[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool open = false;
     // nonzero on a thread that must not record (graph capture, or a thread launching
     // beside the one being timed)
     static inline thread_local int suppress = 0;
@@ -109,18 +124,23 @@ struct KernelProf {
     }
     void begin(int id, hipStream_t st) {
         if (!enabled || suppress) return;
+        if (calls[id & 7]++ % stride != 0) return;
         hipEvent_t e = get();
         (void)hipEventRecord(e, st);
         ids.push_back(id);
         ev0.push_back(e);
+        open = true;
     }
     void end(hipStream_t st) {
-        if (!enabled || suppress) return;
+        if (!open) return;
+        open = false;
         hipEvent_t e = get();
         (void)hipEventRecord(e, st);
         ev1.push_back(e);
     }
     void reset() {
+        open = false;
+        for (long long &c : calls) c = 0;
         used = 0;
         ids.clear();
         ev0.clear();
@@ -154,7 +174,7 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st);
 void sweep_init_attributes();
 void neigh_init_attributes();
 bool sweep_fits_lds(int N);
-int sweep_mc_workgroups(int N);
+int sweep_mc_workgroups(int N, int want = 0);
 void launch_slab_end(int N, int mode, size_t SN, size_t s, double *xs, double *ps, const double *jq, const double *jp,
                      const double *qprev_next, double *qcur_next, double *pcur_next, double *part, hipStream_t st);
 void launch_noise_table(int S, int L, int N, int n_in, uint64_t seed, uint64_t noise_id, double *noise,
@@ -178,7 +198,7 @@ void launch_fmax2(int N, const double *f, unsigned long long *out, hipStream_t s
 
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
                  double *e_atom, int accumulate, hipStream_t st, KernelProf *prof = nullptr,
-                 hipEvent_t join = nullptr, double *p_kick = nullptr, double dt = 0.0);
+                 hipEvent_t join = nullptr, double *p_kick = nullptr, double dt = 0.0, const FsParams *fuse = nullptr);
 void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st);
 void adjoint_tables(int J, const double *beta, AdjointHost &A);
 void adjoint_init_attributes();

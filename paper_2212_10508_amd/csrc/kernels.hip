@@ -604,10 +604,15 @@ __device__ __forceinline__ void staircase(double2 (&P)[J + 1], double2 b, double
 // a, b and f_c of every listed pair in slot-major layout ell[f][t][i] (t = rank of the
 // pair in i's list), one thread per (slot, atom) with the atom fastest, so that the
 // density pass (lane = atom) reads slot t of 64 atoms with one coalesced load per field.
+// With fs_d > 0 field 5 holds the Finnis-Sinclair density term phi(r) = (r - d)^2 (r < d).
+// clear_flag (non-null): the neighbour pipeline that read the rebuild flag has finished
+// on this stream, so the flag is cleared for the next step.
 __global__ void k_pair_ell(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
                            const double *__restrict__ x, const int *__restrict__ poff,
-                           const int *__restrict__ nbr_t, SnapGeoParams sp, double *__restrict__ ell) {
+                           const int *__restrict__ nbr_t, SnapGeoParams sp, double *__restrict__ ell, double fs_d,
+                           int *__restrict__ clear_flag) {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (clear_flag && q == 0) *clear_flag = 0;
     const int t = (int)(q / (size_t)N), i = (int)(q - (size_t)t * N);
     if (t >= kMaxNeigh || t >= poff[i + 1] - poff[i]) return;
     double d[3];
@@ -621,6 +626,11 @@ __global__ void k_pair_ell(int N, int n_sys, const int *__restrict__ off, const 
     ell[2 * sN + q] = b.x;
     ell[3 * sN + q] = b.y;
     ell[4 * sN + q] = fc;
+    if (fs_d > 0.0) {
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const double r = r2 * rsqrt_nr(r2);
+        ell[5 * sN + q] = r2 < fs_d * fs_d ? (r - fs_d) * (r - fs_d) : 0.0;
+    }
 }
 
 // u (half storage, [e][N] double2) for column C: one wave per tile of 64 atoms, lane =
@@ -628,7 +638,8 @@ __global__ void k_pair_ell(int N, int n_sys, const int *__restrict__ off, const 
 // and f_c (one coalesced load per field); slots past an atom's count add nothing.
 template <int J, int C>
 __device__ void density_lane(int N, const int *__restrict__ poff, const double *__restrict__ ell,
-                             const double *__restrict__ nrm, double2 *__restrict__ u) {
+                             const double *__restrict__ nrm, double2 *__restrict__ u, double fs_A,
+                             double *__restrict__ dF) {
     const int i = blockIdx.x * 64 + threadIdx.x;
     constexpr int NA = chain_acc_idx(C, J + 1, 0);
     double2 acc[NA];
@@ -639,9 +650,12 @@ __device__ void density_lane(int N, const int *__restrict__ poff, const double *
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) tmax = max(tmax, __shfl_xor(tmax, o, 64));
     const size_t sN = (size_t)kMaxNeigh * N;
+    double rho = 0.0;  // Finnis-Sinclair density (column 0 with dF)
     for (int t = 0; t < tmax; ++t) {
         const bool v = t < cnt;
         const size_t q = (size_t)t * N + (v ? i : 0);
+        if constexpr (C == 0)
+            if (dF && v) rho += ell[5 * sN + q];
         // past the count: the identity rotation with zero weight (slot contents unused)
         const double2 a = v ? make_double2(ell[q], ell[sN + q]) : make_double2(1.0, 0.0);
         const double2 b = v ? make_double2(ell[2 * sN + q], ell[3 * sN + q]) : make_double2(0.0, 0.0);
@@ -653,6 +667,8 @@ __device__ void density_lane(int N, const int *__restrict__ poff, const double *
         density_step<J, C, 2 * C>(P, acc, b, ab, fc);
     }
     if (i >= N) return;
+    if constexpr (C == 0)
+        if (dF) dF[i] = rho > 0.0 ? -fs_A / (2.0 * sqrt(rho)) : 0.0;
 #pragma unroll
     for (int n = 2 * C; n <= J; ++n)
 #pragma unroll
@@ -664,15 +680,18 @@ __device__ void density_lane(int N, const int *__restrict__ poff, const double *
         }
 }
 
+// dF non-null: column 0 also sums the Finnis-Sinclair density of field 5 and writes
+// dF[i] = F'(rho_i) = -A / (2 sqrt(rho_i)) (0 for rho_i = 0)
 template <int J>
 __global__ void __launch_bounds__(64) k_density(int N, const int *__restrict__ poff, const double *__restrict__ ell,
-                                                const double *__restrict__ nrm, double2 *__restrict__ u) {
+                                                const double *__restrict__ nrm, double2 *__restrict__ u,
+                                                double fs_A, double *__restrict__ dF) {
     switch (blockIdx.y) {
-        case 0: density_lane<J, 0>(N, poff, ell, nrm, u); break;
-        case 1: if constexpr (J >= 2) density_lane<J, 1>(N, poff, ell, nrm, u); break;
-        case 2: if constexpr (J >= 4) density_lane<J, 2>(N, poff, ell, nrm, u); break;
-        case 3: if constexpr (J >= 6) density_lane<J, 3>(N, poff, ell, nrm, u); break;
-        case 4: if constexpr (J >= 8) density_lane<J, 4>(N, poff, ell, nrm, u); break;
+        case 0: density_lane<J, 0>(N, poff, ell, nrm, u, fs_A, dF); break;
+        case 1: if constexpr (J >= 2) density_lane<J, 1>(N, poff, ell, nrm, u, fs_A, nullptr); break;
+        case 2: if constexpr (J >= 4) density_lane<J, 2>(N, poff, ell, nrm, u, fs_A, nullptr); break;
+        case 3: if constexpr (J >= 6) density_lane<J, 3>(N, poff, ell, nrm, u, fs_A, nullptr); break;
+        case 4: if constexpr (J >= 8) density_lane<J, 4>(N, poff, ell, nrm, u, fs_A, nullptr); break;
         default: break;
     }
 }
@@ -814,9 +833,11 @@ __device__ __forceinline__ void dedr_chain(double2 (&P)[J + 1], double2 (&sP)[J 
 // read Y~ from there; otherwise from global memory.
 constexpr int kDedrAtoms = 5;
 
+// fs (stride 64, or null): a Finnis-Sinclair addend per component
 template <int J>
 __device__ __forceinline__ void dedr_pair(int p, size_t Pcap, const double (&g)[20],
-                                          const double2 *__restrict__ yt, int ystride, double *__restrict__ dedr) {
+                                          const double2 *__restrict__ yt, int ystride, double *__restrict__ dedr,
+                                          const double *fs) {
     const double fc = g[4];
     const double2 a = make_double2(g[0], g[1]);
     const double2 b = make_double2(g[2], g[3]);
@@ -834,18 +855,26 @@ __device__ __forceinline__ void dedr_pair(int p, size_t Pcap, const double (&g)[
         // Re(i x11 Q0 + X21 Qp + X12 Qm), X21 = (-x12.x, x12.y)
         const double s = fma(-x11, A.Q0.y, fma(-x12.x, A.Qp.x, fma(-x12.y, A.Qp.y,
                                                                     fma(x12.x, A.Qm.x, -x12.y * A.Qm.y))));
-        dedr[al * Pcap + p] = fma(g[17 + al], A.S0, fc * s);
+        const double v = fma(g[17 + al], A.S0, fc * s);
+        dedr[al * Pcap + p] = fs ? v + fs[64 * al] : v;
     }
 }
 
+// With fz.on the Finnis-Sinclair part of the same derivative is added: for
+// E_i = F(rho_i) + (1/2) sum_j V(r_ij), dE_i/d(x_j - x_i) = (F'(rho_i) phi'(r) + V'(r)/2) d/r,
+// with F'(rho_i) from the density pass.  (The gather's g_p - g_rev(p) then assembles the
+// pair force (F'(rho_i) + F'(rho_j)) phi' + V'.)  It is staged in LDS so that no register
+// stays live across the SNAP contraction.
 template <int J>
 __global__ void __launch_bounds__(64) k_dedr(int N, int n_sys, const int *__restrict__ off,
                                              const double *__restrict__ box, const double *__restrict__ x,
                                              const int *__restrict__ poff, const int *__restrict__ pair_i,
                                              const int *__restrict__ pair_j, SnapGeoParams sp, size_t Pcap,
-                                             const double2 *__restrict__ ytil, double *__restrict__ dedr) {
+                                             const double2 *__restrict__ ytil, double *__restrict__ dedr,
+                                             FsFuse fz) {
     constexpr int NH = n_half(J);
     __shared__ double2 ys[kDedrAtoms * NH];
+    __shared__ double fsb[3 * 64];
     const int P = poff[N];
     const int p0 = blockIdx.x * 64;
     if (p0 >= P) return;
@@ -858,23 +887,38 @@ __global__ void __launch_bounds__(64) k_dedr(int N, int n_sys, const int *__rest
     {
         double d[3] = {1.0, 0.0, 0.0};
         if (live) pair_sep(x, N, box, sys_of(off, n_sys, i), i, pair_j[p], d);
+        if (fz.on) {
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            const double ir = rsqrt_nr(r2), r = r2 * ir;
+            const FsParams &fp = fz.fp;
+            double dEdr = 0.0;
+            if (r < fp.c) {
+                const double t = r - fp.c, poly = fp.c0 + r * (fp.c1 + r * fp.c2);
+                dEdr += 0.5 * (2.0 * t * poly + t * t * (fp.c1 + 2.0 * fp.c2 * r));
+            }
+            if (r < fp.d) dEdr += fz.dF[i] * 2.0 * (r - fp.d);
+            const double wf = live ? dEdr * ir : 0.0;
+#pragma unroll
+            for (int al = 0; al < 3; ++al) fsb[64 * al + lane] = wf * d[al];
+        }
         snap_geo(d, sp, g);
     }
     const double fc = live ? g[4] : 0.0;
+    const double *fs = fz.on ? fsb + lane : nullptr;
     if (na <= kDedrAtoms) {
         for (int q = lane; q < na * NH; q += 64) {
             const int e = q / na, at = q - e * na;
             ys[q] = ytil[(size_t)e * N + i0 + at];
         }
         __syncthreads();
-        if (fc != 0.0) dedr_pair<J>(p, Pcap, g, ys + (i - i0), na, dedr);
+        if (fc != 0.0) dedr_pair<J>(p, Pcap, g, ys + (i - i0), na, dedr, fs);
     } else {
-        if (fc != 0.0) dedr_pair<J>(p, Pcap, g, ytil + i, N, dedr);
+        if (fc != 0.0) dedr_pair<J>(p, Pcap, g, ytil + i, N, dedr, fs);
     }
     if (live && fc == 0.0) {
-        dedr[p] = 0.0;
-        dedr[Pcap + p] = 0.0;
-        dedr[2 * Pcap + p] = 0.0;
+        dedr[p] = fs ? fs[0] : 0.0;
+        dedr[Pcap + p] = fs ? fs[64] : 0.0;
+        dedr[2 * Pcap + p] = fs ? fs[128] : 0.0;
     }
 }
 
@@ -1097,21 +1141,28 @@ void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w,
 template <int J>
 static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
                           double *e_atom, int accumulate, hipStream_t st, KernelProf *prof, hipEvent_t join,
-                          double *p_kick, double dt) {
+                          double *p_kick, double dt, const FsParams *fuse) {
     const int N = bd.N;
     KernelProf dummy;
     KernelProf &pf = prof ? *prof : dummy;
+    FsFuse fz{};
+    if (fuse) {
+        fz.fp = *fuse;
+        fz.dF = w.rho;
+        fz.on = 1;
+    }
     hipLaunchKernelGGL(k_pair_ell, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box,
-                       x, w.poff, w.nbr_t, sd.gp, w.ell);
+                       x, w.poff, w.nbr_t, sd.gp, w.ell, fuse ? fuse->d : 0.0, fuse ? w.flag : nullptr);
     pf.begin(PROF_DENSITY, st);
-    hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 64), J / 2 + 1), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u);
+    hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 64), J / 2 + 1), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u,
+                       fuse ? fuse->A : 0.0, fuse ? w.rho : nullptr);
     pf.end(st);
     pf.begin(PROF_ADJOINT, st);
     launch_adjoint(J, sd.adj, N, w.u, sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate, st);
     pf.end(st);
     pf.begin(PROF_DEDR, st);
     hipLaunchKernelGGL(k_dedr<J>, dim3(nblk((size_t)N * kMaxNeigh, 64)), dim3(64), 0, st, N, bd.n_sys, bd.off, bd.box,
-                       x, w.poff, w.pair_i, w.pair_j, sd.gp, w.Pcap, w.ytil, w.dedr);
+                       x, w.poff, w.pair_i, w.pair_j, sd.gp, w.Pcap, w.ytil, w.dedr, fz);
     pf.end(st);
     if (join) (void)hipStreamWaitEvent(st, join, 0);  // f written by work on another stream
     hipLaunchKernelGGL(k_gather, dim3(nblk(N, 64)), dim3(256), 0, st, N, w.poff, w.rev, w.dedr, w.Pcap, f,
@@ -1120,12 +1171,12 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
 
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
                  double *e_atom, int accumulate, hipStream_t st, KernelProf *prof, hipEvent_t join, double *p_kick,
-                 double dt) {
+                 double dt, const FsParams *fuse) {
     switch (J) {
-        case 2: launch_snap_J<2>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt); break;
-        case 4: launch_snap_J<4>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt); break;
-        case 6: launch_snap_J<6>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt); break;
-        case 8: launch_snap_J<8>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt); break;
+        case 2: launch_snap_J<2>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
+        case 4: launch_snap_J<4>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
+        case 6: launch_snap_J<6>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
+        case 8: launch_snap_J<8>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
         default: break;
     }
 }
@@ -1135,12 +1186,12 @@ void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapD
     hipLaunchKernelGGL(k_pair_geo, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x,
                        w.poff, w.pair_i, w.pair_j, sd.gp, w.geo, w.Pcap);
     hipLaunchKernelGGL(k_pair_ell, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box,
-                       x, w.poff, w.nbr_t, sd.gp, w.ell);
+                       x, w.poff, w.nbr_t, sd.gp, w.ell, 0.0, nullptr);
     switch (J) {
-        case 2: hipLaunchKernelGGL(k_density<2>, dim3(nblk(N, 64), 2), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u); break;
-        case 4: hipLaunchKernelGGL(k_density<4>, dim3(nblk(N, 64), 3), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u); break;
-        case 6: hipLaunchKernelGGL(k_density<6>, dim3(nblk(N, 64), 4), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u); break;
-        case 8: hipLaunchKernelGGL(k_density<8>, dim3(nblk(N, 64), 5), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u); break;
+        case 2: hipLaunchKernelGGL(k_density<2>, dim3(nblk(N, 64), 2), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u, 0.0, nullptr); break;
+        case 4: hipLaunchKernelGGL(k_density<4>, dim3(nblk(N, 64), 3), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u, 0.0, nullptr); break;
+        case 6: hipLaunchKernelGGL(k_density<6>, dim3(nblk(N, 64), 4), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u, 0.0, nullptr); break;
+        case 8: hipLaunchKernelGGL(k_density<8>, dim3(nblk(N, 64), 5), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u, 0.0, nullptr); break;
         default: break;
     }
 }

@@ -60,7 +60,7 @@ struct SweepArgs {
     double *gx;                   // [2][3][N] positions by step parity
     double *gdfe;                 // [2][N] F'(rho) by step parity
     double *gpart;                // [2][K][4] per-workgroup partials by parity
-    unsigned long long *bar;      // barrier arrivals (zero at launch)
+    unsigned long long *bar;      // [K] barrier arrivals per workgroup (zero at launch)
     int *abort;                   // set when a barrier wait runs out (zero at launch)
     double delta_expl;
     double *q_cur, *p_cur;                 // [slot][3][N]
@@ -677,8 +677,8 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
 // does the force pass.  Shared data are written and read with device-scope accesses
 // (coherent at the device level, so no cache-wide write-back or invalidation is
 // needed); each wave waits for its stores to complete before the workgroup arrives at
-// the barrier, an arrival counter whose wait is bounded (a wait that runs out sets
-// `abort` and every workgroup leaves).  Per-workgroup partial sums are combined in a fixed
+// the barrier, one arrival slot per workgroup whose wait is bounded (a wait that runs
+// out sets `abort` and every workgroup leaves).  Per-workgroup partial sums are combined in a fixed
 // order, so every workgroup takes the same decisions.
 // ---------------------------------------------------------------------------
 constexpr int kMcSpin = 1 << 22;
@@ -690,43 +690,48 @@ __device__ __forceinline__ double ld_dev(const double *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// grid barrier number b (0, 1, ..): returns false when the wait ran out or another
-// workgroup gave up
+// grid barrier number b (0, 1, ..): each workgroup announces its arrival in a slot of its
+// own (bar[w] = b + 1, a device-scope store once its data stores have completed) and
+// waits until every slot holds more than b; lane v of the first wave polls slot v, so one
+// load reads all K <= 64 slots.  Returns false when the wait ran out or another
+// workgroup gave up.
 __device__ __forceinline__ bool mc_barrier(const SweepArgs &a, unsigned long long b, int *flag) {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's device-scope stores have completed
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(a.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long target = (unsigned long long)a.K * (b + 1);
+    if (threadIdx.x < 64) {
+        const int v = threadIdx.x;
+        if (v == 0) __hip_atomic_store(a.bar + blockIdx.x, b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
         for (int spin = 0;; ++spin) {
-            if (__hip_atomic_load(a.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-            if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || spin >= kMcSpin) {
-                __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const bool in = v >= a.K || __hip_atomic_load(a.bar + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > b;
+            if (__all(in)) break;
+            const bool ab = __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            if (__any(ab) || spin >= kMcSpin) {
+                if (v == 0) __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ok = 0;
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        *flag = ok;
+        if (v == 0) *flag = ok;
     }
     __syncthreads();
     return *flag != 0;
 }
 
-// global -> LDS copy of n doubles by the whole workgroup (device-scope loads, 8 per
-// thread in flight)
+// global -> LDS copy of n doubles by the whole workgroup (device-scope loads, 16 per
+// thread in flight: the 3N positions of a 1025-atom system in one round trip)
 __device__ __forceinline__ void mc_copy(double *__restrict__ dst, const double *__restrict__ src, int n) {
     const int T = blockDim.x;
-    for (int base = threadIdx.x; base < n; base += 8 * T) {
-        double v[8];
+    for (int base = threadIdx.x; base < n; base += 16 * T) {
+        double v[16];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < 16; ++k) {
             const int q = base + k * T;
             v[k] = q < n ? ld_dev(src + q) : 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < 16; ++k) {
             const int q = base + k * T;
             if (q < n) dst[q] = v[k];
         }
@@ -1055,13 +1060,17 @@ void launch_slab_end(int N, int mode, size_t SN, size_t s, double *xs, double *p
 
 bool sweep_fits_lds(int N) { return N <= kSweepLdsMaxAtoms && sweep_lds_bytes(N) <= 160 * 1024; }
 
-// workgroups of the multi-workgroup sweep for N atoms (0: not used)
-int sweep_mc_workgroups(int N) {
+// workgroups of the multi-workgroup sweep for N atoms (0: not used); want > 0 asks for
+// that many, granted when they fit (at most 64, at most 256 atoms per workgroup)
+int sweep_mc_workgroups(int N, int want) {
     if (N < 512 || N > 65535) return 0;
-    for (int K : {8, 16}) {  // two lanes per atom: at most 256 atoms per workgroup of 512 threads
+    auto fits = [N](int K) {  // two lanes per atom: at most 256 atoms per workgroup of 512 threads
         const int A = (N + K - 1) / K;
-        if (A <= 256 && sweep_mc_lds_bytes(N, A) <= 160 * 1024) return K;
-    }
+        return K <= 64 && A <= 256 && sweep_mc_lds_bytes(N, A) <= 160 * 1024;
+    };
+    if (want > 0 && fits(want)) return want;
+    for (int K : {8, 16})
+        if (fits(K)) return K;
     return 0;
 }
 

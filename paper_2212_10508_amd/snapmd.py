@@ -101,6 +101,10 @@ def lib():
     L.snapmd_set_chunk_plan.restype = C.c_int
     L.snapmd_chunk_plan.argtypes = [P, i32, i32, C.POINTER(i32), C.POINTER(i32)]
     L.snapmd_chunk_plan.restype = C.c_int
+    L.snapmd_set_sweep_workgroups.argtypes = [P, i32]
+    L.snapmd_set_sweep_workgroups.restype = C.c_int
+    L.snapmd_sweep_workgroups.argtypes = [P, i32, C.POINTER(i32)]
+    L.snapmd_sweep_workgroups.restype = C.c_int
     _lib = L
     return L
 
@@ -279,8 +283,10 @@ class Context:
         """Replay captured hipGraphs of the Langevin launch sequences (default on)."""
         self._check(lib().snapmd_use_graphs(self.h, 1 if enable else 0))
 
-    def profile(self, enable=True):
-        self._check(lib().snapmd_profile(self.h, 1 if enable else 0))
+    def profile(self, enable=True, every=1):
+        """Record HIP events around every `every`-th launch of the SNAP kernels and the
+        neighbour build (enable=False stops)."""
+        self._check(lib().snapmd_profile(self.h, int(every) if enable else 0))
 
     def profile_read(self, kernel):
         """(total ms, launches) of HIP-event-timed launches of `kernel` since profile(True)."""
@@ -341,6 +347,17 @@ class Context:
         n = C.c_int32(0)
         self._check(lib().snapmd_chunk_plan(self.h, int(S), int(N), arr, C.byref(n)))
         return list(arr[:n.value])
+
+    def set_sweep_workgroups(self, K):
+        """Workgroups of the on-device coarse sweep in later parareal_iterate calls (0: the
+        built-in choice)."""
+        self._check(lib().snapmd_set_sweep_workgroups(self.h, int(K)))
+
+    def sweep_workgroups(self, N):
+        """The sweep width a system of N atoms gets (0: one workgroup or host-driven)."""
+        k = C.c_int32(0)
+        self._check(lib().snapmd_sweep_workgroups(self.h, int(N), C.byref(k)))
+        return k.value
 
     def pair_count(self):
         n = C.c_int64(0)

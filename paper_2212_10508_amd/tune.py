@@ -43,6 +43,13 @@ def candidate_plans(S, N, n_cus, builtin=None, max_chunks=4, limit=24):
             out.append(p)
         if len(out) >= limit:
             break
+    # when the sweep is as slow as the SNAP propagation, chunks of one round each start it
+    # early and leave a short last sweep
+    for c in (R - 1, R):
+        if 1 <= c < S:
+            p = [c] * (S // c) + ([S % c] if S % c else [])
+            if p not in out:
+                out.append(p)
     return out
 
 
@@ -102,3 +109,41 @@ def tune_chunk_plan(ctx, run_iteration, S, N, n_cus, passes=2, limit=16, log=Non
             log("chunk plan %s: %.2f ms" % (list(p), times[p] * 1e3))
     ctx.set_chunk_plan(chosen)
     return chosen, times
+
+
+def tune_sweep_width(ctx, run_iteration, N, widths=(1, 8, 16), passes=2, log=None):
+    """Time run_iteration() with the on-device coarse sweep spread over each of the given
+    numbers of workgroups (those the system of N atoms cannot use are skipped), in
+    interleaved passes after one untimed run each, and keep the fastest (1: the
+    one-workgroup sweep, where the system fits in one compute unit).  Wider sweeps do
+    less work per workgroup between exchanges but exchange among more workgroups and take
+    more compute units from the SNAP propagation beside them.  Sets the width on ctx and
+    returns (K, {K: seconds})."""
+    ctx.set_sweep_workgroups(0)
+    builtin = ctx.sweep_workgroups(N)
+    if builtin <= 1:
+        return builtin, {}
+    cands = []
+    for K in [builtin] + list(widths):
+        ctx.set_sweep_workgroups(K)
+        if ctx.sweep_workgroups(N) == K and K not in cands:
+            cands.append(K)
+    times = {}
+
+    def once(K):
+        ctx.set_sweep_workgroups(K)
+        t0 = time.perf_counter()
+        run_iteration()
+        return time.perf_counter() - t0
+
+    for K in cands:
+        once(K)
+    for _ in range(passes):
+        for K in cands:
+            times[K] = min(times.get(K, float("inf")), once(K))
+    best = min(times, key=times.get)
+    if log:
+        for K in sorted(times, key=times.get):
+            log("sweep workgroups %d: %.2f ms" % (K, times[K] * 1e3))
+    ctx.set_sweep_workgroups(best)
+    return best, times

@@ -110,3 +110,23 @@ def test_long_call_runs_uncaptured_and_equals_split_calls(S):
     torch.cuda.synchronize()
     assert torch.max(torch.abs(xa - xb)).item() < 1e-9
     assert torch.max(torch.abs(pa - pb)).item() < 1e-9 * torch.max(torch.abs(pb)).item()
+
+
+def test_profile_samples_every_kth_launch(S):
+    """snapmd_profile(ctx, s) records every s-th launch of each timed kernel: 11 force
+    evaluations (the initial one and 10 steps) give launches 0, 3, 6, 9 at s = 3."""
+    J = 2
+    X, P, off, boxes = _batch(n_sys=2)
+    beta = W.snap_beta(J, seed=3, scale=2e-2)
+    kw = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=5, noise_id=0, fs=W.FS_W, J=J, beta=beta)
+    ctx = S.Context(0)
+    for every, want in ((1, 11), (3, 4)):
+        x, p = torch.tensor(X, device="cuda"), torch.tensor(P, device="cuda")
+        ctx.profile(True, every=every)
+        ctx.langevin_steps(S.POT_FS_SNAP, x, p, off, boxes, 10, step0=0, **kw)
+        for kid in (S.Context.PROF_DEDR, S.Context.PROF_ADJOINT, S.Context.PROF_DENSITY, S.Context.PROF_NEIGH):
+            ms, n = ctx.profile_read(kid)
+            assert n == want and ms > 0.0, (every, kid, n, ms)
+        ctx.profile(False)
+    with pytest.raises(S.SnapmdError):
+        ctx.profile(True, every=-1)

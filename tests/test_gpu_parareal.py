@@ -249,6 +249,50 @@ def test_chunk_plans_give_identical_iterates(S):
     ctx.set_chunk_plan(None)
 
 
+def test_sweep_widths_give_identical_states(S):
+    """The number of workgroups of the on-device sweep (tuning only): every atom's
+    arithmetic is the same at any width of the multi-workgroup sweep, so the states agree
+    bitwise; the relative error sums partials over the workgroups, so it agrees to
+    rounding.  Width 1 selects the one-workgroup kernel."""
+    x, box = W.bcc_sia(7, jitter=0.05, seed=21)
+    n = x.shape[1]
+    p = W.maxwell_momenta(n, 1000.0, seed=21)
+    J = 2
+    kw = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=5, noise_id=1, fs=W.FS_W, J=J,
+              beta=W.snap_beta(J, seed=21, scale=2e-2))
+    kwc = {k: v for k, v in kw.items() if k not in ("J", "beta")}
+    N, L = 4, 3
+    ctx = S.context()
+    results = []
+    for K in (0, 8, 16, 32, 43, 1):
+        ctx.set_sweep_workgroups(K)
+        assert ctx.sweep_workgroups(n) == (K or 8)
+        q = torch.zeros((N + 1, 3, n), dtype=torch.float64, device="cuda")
+        pp = torch.zeros_like(q)
+        q[0], pp[0] = dev(x), dev(p)
+        ctx.parareal_iterate(None, None, q, pp, box, L, 0, N, 1e100, **kwc)
+        qp, ppv = torch.zeros_like(q), torch.zeros_like(q)
+        d, nfi = ctx.parareal_iterate(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
+        torch.cuda.synchronize()
+        results.append((d, nfi, q.cpu().numpy(), pp.cpu().numpy()))
+    ctx.set_sweep_workgroups(0)
+    d0, n0, qa, pa = results[0]
+    assert d0 > 0.0
+    for d, nfi, qb, pb in results[1:-1]:
+        assert nfi == n0 and abs(d - d0) <= 1e-12 * d0
+        assert np.array_equal(qa, qb) and np.array_equal(pa, pb)
+    # the one-workgroup sweep sums each atom's list in another order: equal to rounding
+    d, nfi, qb, pb = results[-1]
+    assert nfi == n0 and abs(d - d0) <= 1e-9 * d0
+    assert np.abs(qa - qb).max() < 1e-10 and np.abs(pa - pb).max() < 1e-10 * np.abs(pa).max()
+    # widths the system cannot use fall back to the built-in one; out of range is refused
+    ctx.set_sweep_workgroups(2)
+    assert ctx.sweep_workgroups(n) == 8
+    with pytest.raises(S.SnapmdError):
+        ctx.set_sweep_workgroups(65)
+    ctx.set_sweep_workgroups(0)
+
+
 def test_strategy_one_snap_coarse_matches_oracle(S):
     """Strategy I (coarse = Finnis-Sinclair + a twojmax-2 SNAP, fine = FS + twojmax-4 SNAP):
     classical parareal on the GPU (batched coarse SNAP propagation, host-driven sweep)
