@@ -256,17 +256,20 @@ def other_configs(S, W, log):
 
 
 def pmc_probe(S, W, J, S_slabs):
-    """Two SNAP force evaluations of the batch (distinct 1025-atom slab states) and a plain
+    """The two force evaluations of one FS + SNAP BAOAB step of the batch (distinct
+    1025-atom slab states; the propagation's kernels, launched one by one) and a plain
     512 MiB device copy whose byte counters calibrate FETCH_SIZE / WRITE_SIZE."""
     import torch
     wl = W.slabs_1025(n_slabs=S_slabs, seed=1, J=J)
     n = wl["xs"][0].shape[1]
     X = torch.tensor(np.concatenate(wl["xs"], axis=1), device="cuda")
+    P = torch.tensor(np.concatenate(wl["ps"], axis=1), device="cuda")
     off = np.arange(S_slabs + 1, dtype=np.int32) * n
     boxes = np.tile(wl["box"], (S_slabs, 1))
     ctx = S.context(0)
-    for _ in range(2):
-        ctx.snap_forces(X, off, boxes, J, wl["beta"])
+    ctx.use_graphs(False)
+    ctx.langevin_steps(S.POT_FS_SNAP, X, P, off, boxes, 1, step0=0, dt=wl["dt"], gamma=wl["gamma"],
+                       mass=wl["mass"], T=wl["T"], seed=1, noise_id=0, fs=W.FS_W, J=J, beta=wl["beta"])
     torch.cuda.synchronize()
     ctx.bispectrum(X, off, boxes, J, wl["beta"])
     pairs = ctx.pair_count()
@@ -278,17 +281,18 @@ def pmc_probe(S, W, J, S_slabs):
 
 
 # HBM traffic per unit of the SNAP kernels, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
-# passes over `bench.py --pmc-probe` (per dispatch, 64 x 1025 atoms, 1.71 M pairs), each
-# scaled by what the counter reads for a 512 MiB device copy in the same process (FETCH
-# x 2.0, WRITE x 1.0).  A figure holds only for the kernel source it was taken on (sha256
-# of the file); after a change the traffic is reported as null until it is measured again.
+# passes over `bench.py --pmc-probe` (per dispatch of the FS + SNAP propagation kernels,
+# 64 x 1025 atoms, 1.71 M pairs), each scaled by what the counter reads for a 512 MiB
+# device copy in the same process (FETCH x 2.0, WRITE x 1.0).  A figure holds only for the
+# kernel source it was taken on (sha256 of the file); after a change the traffic is
+# reported as null until it is measured again.
 TRAFFIC = {
     "adjoint": ("paper_2212_10508_amd/csrc/adjoint.hip",
-                "b213ae4ad852068155c19b9c3e32d3e1c660a037de09948fab4e59a3dcfe1fd4", 5187.9, "atom"),
+                "b213ae4ad852068155c19b9c3e32d3e1c660a037de09948fab4e59a3dcfe1fd4", 5190.6, "atom"),
     "dedr": ("paper_2212_10508_amd/csrc/kernels.hip",
-             "a7bba27061de622a7f582aaa6300e03d50a5c4429bad170ad28fefa13f4516a4", 447.6, "pair"),
+             "f6309a8b82050d59db706dafd806078af38ba49e41aa86204f260832144b89b9", 449.5, "pair"),
     "density": ("paper_2212_10508_amd/csrc/kernels.hip",
-                "a7bba27061de622a7f582aaa6300e03d50a5c4429bad170ad28fefa13f4516a4", 300.3, "pair"),
+                "f6309a8b82050d59db706dafd806078af38ba49e41aa86204f260832144b89b9", 308.9, "pair"),
 }
 
 
@@ -369,17 +373,17 @@ def main():
         assert nfi == S_slabs
         return d
 
+    ctx.set_sweep_workgroups(args.sweep_workgroups)
+    if args.plan:  # set before the warmup, which captures the plan's launch sequences
+        ctx.set_chunk_plan([int(v) for v in args.plan.split(",")])
     for w in range(args.warmup):
         d = iteration()
         log("warmup %d: delta %.3e" % (w, d))
     # slab chunks of the pipelined iteration, timed on this workload (untimed setup)
     n_cus = torch.cuda.get_device_properties(0).multi_processor_count
-    builtin_plan = ctx.chunk_plan(S_slabs, n)
+    builtin_plan = list(ctx.chunk_plan(S_slabs, n)) if not args.plan else None
     autotune = None
-    ctx.set_sweep_workgroups(args.sweep_workgroups)
-    if args.plan:
-        ctx.set_chunk_plan([int(v) for v in args.plan.split(",")])
-    elif not args.no_tune:
+    if not args.plan and not args.no_tune:
         from paper_2212_10508_amd import tune
 
         def timed_iteration():

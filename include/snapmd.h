@@ -291,7 +291,8 @@ int snapmd_sweep_workgroups(snapmd_ctx *ctx, int32_t N, int32_t *K);
  * device idle for a few microseconds, so a sample (s > 1) disturbs the measured run less.
  * snapmd_profile_read synchronises the device and returns, for kernel id
  * 0 = SNAP dE/dr, 1 = SNAP adjoint, 2 = SNAP density, 3 = neighbour build,
- * the summed duration (ms) and the number of launches recorded.  Neighbour builds
+ * the summed duration (ms) and the number of launches recorded (a pair of events the
+ * runtime cannot time is left out).  Neighbour builds
  * replayed from a captured graph (FS-only propagation) are not recorded. */
 int snapmd_profile(snapmd_ctx *ctx, int enable);
 int snapmd_profile_read(snapmd_ctx *ctx, int kernel, double *total_ms, int64_t *launches);

@@ -159,8 +159,7 @@ struct SweepLaunch {
     int L, n_in, n_fi, mode, n_win;
     int ncx, ncy, ncz;  // cell grid of the sweep's list build (0: all pairs)
     int K, A;           // multi-workgroup sweep: K workgroups of A atoms (K = 0: one workgroup)
-    double *gx, *gdfe, *gpart;
-    unsigned long long *bar;
+    unsigned long long *gx, *gdfe, *gpart;  // exchange words: 12 N, 4 N and 16 K, zeroed before launch
     int *abort;
     double delta_expl;
     double *q_cur, *p_cur;

@@ -57,11 +57,11 @@ struct SweepArgs {
     // multi-workgroup sweep: K workgroups own A consecutive atoms each and exchange
     // positions and F'(rho) every step through device memory
     int K, A;
-    double *gx;                   // [2][3][N] positions by step parity
-    double *gdfe;                 // [2][N] F'(rho) by step parity
-    double *gpart;                // [2][K][4] per-workgroup partials by parity
-    unsigned long long *bar;      // [K] barrier arrivals per workgroup (zero at launch)
-    int *abort;                   // set when a barrier wait runs out (zero at launch)
+    // (tagged words, two per value, cleared before the launch)
+    unsigned long long *gx;       // [2][3][N][2] positions by step parity
+    unsigned long long *gdfe;     // [2][N][2] F'(rho) by step parity
+    unsigned long long *gpart;    // [2][4][K][2] per-workgroup partials by parity
+    int *abort;                   // set when a wait runs out (zero at launch)
     double delta_expl;
     double *q_cur, *p_cur;                 // [slot][3][N]
     const double *q_prev, *p_prev;         // [slot][3][N] (mode 1)
@@ -682,60 +682,74 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
 // order, so every workgroup takes the same decisions.
 // ---------------------------------------------------------------------------
 constexpr int kMcSpin = 1 << 22;
+// static LDS of the multi-workgroup sweep (the partial values, 3 x 64 doubles, and the
+// workgroup vote of __syncthreads_or: 1,792 bytes), rounded up
+constexpr size_t kMcStaticLds = 2048;
 
-__device__ __forceinline__ void st_dev(double *p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Tagged words: a published double v of exchange b travels as two 64-bit words
+// (b + 1) << 32 | low half and (b + 1) << 32 | high half, each written with one
+// device-scope store, so a word holds either its old or its new contents and a reader
+// recognises the value of exchange b by the tags.  The buffers are cleared before every
+// launch (no word carries a live tag) and alternate by step parity (a workgroup cannot
+// run two exchanges ahead of a reader, since it needs that reader's next values first).
+__device__ __forceinline__ void put_tagged(unsigned long long *p, double v, unsigned long long b) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v), t = (b + 1) << 32;
+    __hip_atomic_store(p, t | (u & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 1, t | (u >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double ld_dev(const double *p) {
+
+__device__ __forceinline__ unsigned long long ld_word(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// grid barrier number b (0, 1, ..): each workgroup announces its arrival in a slot of its
-// own (bar[w] = b + 1, a device-scope store once its data stores have completed) and
-// waits until every slot holds more than b; lane v of the first wave polls slot v, so one
-// load reads all K <= 64 slots.  Returns false when the wait ran out or another
-// workgroup gave up.
-__device__ __forceinline__ bool mc_barrier(const SweepArgs &a, unsigned long long b, int *flag) {
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's device-scope stores have completed
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int v = threadIdx.x;
-        if (v == 0) __hip_atomic_store(a.bar + blockIdx.x, b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int ok = 1;
-        for (int spin = 0;; ++spin) {
-            const bool in = v >= a.K || __hip_atomic_load(a.bar + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > b;
-            if (__all(in)) break;
-            const bool ab = __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-            if (__any(ab) || spin >= kMcSpin) {
-                if (v == 0) __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
+// Waits until the two words at p carry tag b + 1 and returns the double they hold;
+// false (ok) when the caller's spin budget ran out or another workgroup gave up.
+__device__ __forceinline__ double get_tagged(const unsigned long long *p, unsigned long long lo,
+                                             unsigned long long hi, unsigned long long b, const SweepArgs &a,
+                                             int &spins, bool &ok) {
+    const unsigned long long t = b + 1;
+    while (ok && ((lo >> 32) != t || (hi >> 32) != t)) {
+        ++spins;
+        if (spins > kMcSpin || ((spins & 255) == 0 && __hip_atomic_load(a.abort, __ATOMIC_RELAXED,
+                                                                       __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+            __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+            break;
         }
-        if (v == 0) *flag = ok;
+        __builtin_amdgcn_s_sleep(1);
+        lo = ld_word(p);
+        hi = ld_word(p + 1);
     }
-    __syncthreads();
-    return *flag != 0;
+    return __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
 }
 
-// global -> LDS copy of n doubles by the whole workgroup (device-scope loads, 16 per
-// thread in flight: the 3N positions of a 1025-atom system in one round trip)
-__device__ __forceinline__ void mc_copy(double *__restrict__ dst, const double *__restrict__ src, int n) {
-    const int T = blockDim.x;
-    for (int base = threadIdx.x; base < n; base += 16 * T) {
-        double v[16];
+// Exchange b: the workgroup copies the np partial values parts[q] (tagged words) into pdst
+// and n doubles of src (tagged words) into dst in LDS, 8 values per thread in flight (16
+// were slower, measured).  Ends with a workgroup barrier; returns
+// false in every thread when some wait ran out or another workgroup gave up.
+__device__ bool mc_get(double *__restrict__ dst, const unsigned long long *__restrict__ src, int n,
+                       const unsigned long long *__restrict__ parts, int np, double *__restrict__ pdst,
+                       unsigned long long b, const SweepArgs &a) {
+    const int T = blockDim.x, tid = threadIdx.x;
+    int spins = 0;
+    bool ok = true;
+    for (int q = tid; q < np && ok; q += T)
+        pdst[q] = get_tagged(parts + 2 * q, ld_word(parts + 2 * q), ld_word(parts + 2 * q + 1), b, a, spins, ok);
+    for (int base = tid; base < n && ok; base += 8 * T) {
+        unsigned long long lo[8], hi[8];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
+        for (int k = 0; k < 8; ++k) {
             const int q = base + k * T;
-            v[k] = q < n ? ld_dev(src + q) : 0.0;
+            lo[k] = q < n ? ld_word(src + 2 * q) : 0ull;
+            hi[k] = q < n ? ld_word(src + 2 * q + 1) : 0ull;
         }
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
+        for (int k = 0; k < 8; ++k) {
             const int q = base + k * T;
-            if (q < n) dst[q] = v[k];
+            if (q < n) dst[q] = get_tagged(src + 2 * q, lo[k], hi[k], b, a, spins, ok);
         }
     }
+    return __syncthreads_or(ok ? 0 : 1) == 0;
 }
 
 __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
@@ -751,7 +765,7 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
     const int i = a0 + k;
     double *xs = sm;                                       // [3][N]
     double *dfe = xs + 3 * N;                              // [N]
-    int *flag = reinterpret_cast<int *>(dfe + N);          // [2]
+    int *flag = reinterpret_cast<int *>(dfe + N);          // [2] (spare)
     uint16_t *nb = reinterpret_cast<uint16_t *>(flag + 2); // [kSweepNbRows][A]
     SwCells cl;
     cl.cnt = reinterpret_cast<int *>(nb + (size_t)kSweepNbRows * 2 * A);
@@ -776,25 +790,23 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
     unsigned long long b = 0;
     int par = 0;
     bool built = false, alive = true;
-    // exchange: publish own positions (and partials), barrier, gather all positions
-    auto exchange_x = [&](double p0, double p1, double p2, double p3) -> bool {
+    // partial values of the workgroups: gpart[parity][slot][K] tagged words (slot 0 the
+    // displacement maximum, 1..3 the slab-end sums), received into pv
+    __shared__ double pv[3 * 64];
+    auto gpart = [&](int slot) { return a.gpart + 2 * ((size_t)(par * 4 + slot) * K); };
+    // exchange: publish own positions and displacement maximum, gather all of them
+    auto exchange_x = [&](double wmax) -> bool {
         if (lead)
 #pragma unroll
-            for (int al = 0; al < 3; ++al) st_dev(a.gx + ((size_t)par * 3 + al) * N + i, xo[al]);
-        if (tid == 0) {
-            double *gp = a.gpart + ((size_t)par * K + w) * 4;
-            st_dev(gp, p0);
-            st_dev(gp + 1, p1);
-            st_dev(gp + 2, p2);
-            st_dev(gp + 3, p3);
-        }
-        if (!mc_barrier(a, b++, flag)) return false;
-        mc_copy(xs, a.gx + (size_t)par * 3 * N, 3 * N);
-        return true;
+            for (int al = 0; al < 3; ++al) put_tagged(a.gx + 2 * (((size_t)par * 3 + al) * N + i), xo[al], b);
+        if (tid == 0) put_tagged(gpart(0) + 2 * w, wmax, b);
+        const bool r = mc_get(xs, a.gx + 2 * (size_t)par * 3 * N, 3 * N, gpart(0), K, pv, b, a);
+        ++b;
+        return r;
     };
-    auto partial = [&](int k) {  // sum over workgroups (fixed order) of partial k
+    auto partial = [&](int k) {  // sum over workgroups (fixed order) of slab-end partial k
         double s = 0.0;
-        for (int v = 0; v < K; ++v) s += ld_dev(a.gpart + ((size_t)par * K + v) * 4 + k);
+        for (int v = 0; v < K; ++v) s += pv[(k - 1) * K + v];
         return s;
     };
     for (int n = a.n_in; n < a.n_fi && alive; ++n) {
@@ -823,10 +835,9 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
                 __syncthreads();
                 for (int v = 0; v < (int)(blockDim.x >> 6); ++v) wmax = fmax(wmax, dfe[v]);
             }
-            if (!exchange_x(wmax, 0.0, 0.0, 0.0)) { alive = false; break; }
+            if (!exchange_x(wmax)) { alive = false; break; }
             double gmax = 0.0;
-            for (int v = 0; v < K; ++v) gmax = fmax(gmax, ld_dev(a.gpart + ((size_t)par * K + v) * 4));
-            __syncthreads();  // xs complete
+            for (int v = 0; v < K; ++v) gmax = fmax(gmax, pv[v]);
             if (!built || !(4.0 * gmax <= a.skin * a.skin)) {
                 if (NC > 0) {
                     for (int c = tid; c < NC; c += blockDim.x) cl.cnt[c] = 0;
@@ -892,14 +903,9 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
             double acc = 0.0;
             if (own) mk = swl_rho_acc(a, xs, col, 2 * A, i, cn, acc);
             acc += __shfl_xor(acc, 1, 64);  // both halves of the list (same sum in both lanes)
-            if (lead) {
-                const double d = swl_dfe(a.fp, acc);
-                dfe[i] = d;
-                st_dev(a.gdfe + (size_t)par * N + i, d);
-            }
-            if (!mc_barrier(a, b++, flag)) { alive = false; break; }
-            mc_copy(dfe, a.gdfe + (size_t)par * N, N);
-            __syncthreads();
+            if (lead) put_tagged(a.gdfe + 2 * ((size_t)par * N + i), swl_dfe(a.fp, acc), b);
+            if (!mc_get(dfe, a.gdfe + 2 * (size_t)par * N, N, nullptr, 0, pv, b, a)) { alive = false; break; }
+            ++b;
             double fh[3] = {0.0, 0.0, 0.0};
             if (own) swl_force_thread(a, xs, dfe, col, 2 * A, i, mk, fh);
 #pragma unroll
@@ -950,13 +956,13 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
                 s2 += dfe[3 * v + 2];
             }
             if (tid == 0) {
-                double *gp = a.gpart + ((size_t)par * K + w) * 4;
-                st_dev(gp + 1, s0);
-                st_dev(gp + 2, s1);
-                st_dev(gp + 3, s2);
+                put_tagged(gpart(1) + 2 * w, s0, b);
+                put_tagged(gpart(2) + 2 * w, s1, b);
+                put_tagged(gpart(3) + 2 * w, s2, b);
             }
         }
-        if (!mc_barrier(a, b++, flag)) { alive = false; break; }
+        if (!mc_get(nullptr, nullptr, 0, gpart(1), 3 * K, pv, b, a)) { alive = false; break; }
+        ++b;
         const double sfin = partial(3);
         if (!isfinite(sfin)) {
             bad = n;
@@ -1066,7 +1072,7 @@ int sweep_mc_workgroups(int N, int want) {
     if (N < 512 || N > 65535) return 0;
     auto fits = [N](int K) {  // two lanes per atom: at most 256 atoms per workgroup of 512 threads
         const int A = (N + K - 1) / K;
-        return K <= 64 && A <= 256 && sweep_mc_lds_bytes(N, A) <= 160 * 1024;
+        return K <= 64 && A <= 256 && sweep_mc_lds_bytes(N, A) + kMcStaticLds <= 160 * 1024;
     };
     if (want > 0 && fits(want)) return want;
     for (int K : {8, 16})
@@ -1116,7 +1122,6 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     a.gx = s.gx;
     a.gdfe = s.gdfe;
     a.gpart = s.gpart;
-    a.bar = s.bar;
     a.abort = s.abort;
     a.mode = s.mode;
     a.delta_expl = s.delta_expl;
@@ -1141,7 +1146,7 @@ void sweep_init_attributes() {
     (void)hipFuncSetAttribute((const void *)k_coarse_sweep_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
     (void)hipFuncSetAttribute((const void *)k_coarse_sweep_mc, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
+                              160 * 1024 - kMcStaticLds);
 }
 
 }  // namespace snapmd
