@@ -3,7 +3,7 @@
 // Per force evaluation of a ragged batch (atoms of all systems back to back):
 //   neighbours : k_neigh_build (brute force within the atom's own system, minimum
 //                image) -> k_scan (prefix sums) -> k_compact (atom-major pair list,
-//                CSR) -> k_reverse (index of the opposite pair)
+//                CSR, and the index of the opposite pair)
 //   FS EAM     : k_fs_rho -> k_fs_force (deterministic gather over the full list)
 //   SNAP       : k_pair_ell (a, b, f_c once per pair, slot-major) -> k_density<J>
 //                (u, lane = atom, one column chain of the Wigner-D polynomials per wave)
@@ -341,31 +341,27 @@ __global__ void __launch_bounds__(1024) k_scan(int N, const int *__restrict__ cn
     if (t == 1023) poff[N] = part[1023];
 }
 
+// CSR pair list from the per-atom lists, one thread per (atom i, slot t): pair p =
+// poff[i] + t, its slot-major copy for the SNAP density (lane = atom), and the index of
+// the opposite pair (j, i), which is poff[j] plus the rank of i in j's list (status bit 4
+// when i is missing there).
 __global__ void k_compact(int N, const int *__restrict__ nbr, const int *__restrict__ cnt,
                           const int *__restrict__ poff, int *__restrict__ pair_i, int *__restrict__ pair_j,
-                          int *__restrict__ nbr_t, const int *__restrict__ flag) {
-    if (*flag == 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int p0 = poff[i], c = cnt[i];
-    for (int t = 0; t < c; ++t) {
-        const int j = nbr[(size_t)i * kMaxNeigh + t];
-        pair_i[p0 + t] = i;
-        pair_j[p0 + t] = j;
-        if (nbr_t) nbr_t[(size_t)t * N + i] = j;  // slot-major copy for the SNAP density (lane = atom)
-    }
-}
-
-__global__ void k_reverse(int N, const int *__restrict__ poff, const int *__restrict__ pair_i,
-                          const int *__restrict__ pair_j, int *__restrict__ rev, int *__restrict__ status,
+                          int *__restrict__ nbr_t, int *__restrict__ rev, int *__restrict__ status,
                           const int *__restrict__ flag) {
     if (*flag == 0) return;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= poff[N]) return;
-    const int i = pair_i[p], j = pair_j[p];
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(q / kMaxNeigh), t = (int)(q - (size_t)i * kMaxNeigh);
+    if (i >= N || t >= cnt[i]) return;
+    const int p = poff[i] + t, j = nbr[q];
+    pair_i[p] = i;
+    pair_j[p] = j;
+    if (nbr_t) nbr_t[(size_t)t * N + i] = j;
+    const int *lj = nbr + (size_t)j * kMaxNeigh;
+    const int cj = cnt[j];
     int r = -1;
-    for (int t = poff[j]; t < poff[j + 1]; ++t)
-        if (pair_j[t] == i) { r = t; break; }
+    for (int u = 0; u < cj; ++u)
+        if (lj[u] == i) { r = poff[j] + u; break; }
     if (r < 0) { atomicOr(status, 4); r = p; }
     rev[p] = r;
 }
@@ -1122,10 +1118,8 @@ void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, h
                            rl * rl, w.nbr, w.cnt, w.status, w.flag, w.xref,
                            (bd.cells && bd.n_cells > 0) ? bd.cells : nullptr, w.cell_of, w.cell_start, w.cell_atoms);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, N, w.cnt, w.poff, w.flag);
-    hipLaunchKernelGGL(k_compact, dim3(nblk(N, 256)), dim3(256), 0, st, N, w.nbr, w.cnt, w.poff, w.pair_i, w.pair_j,
-                       w.nbr_t, w.flag);
-    hipLaunchKernelGGL(k_reverse, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, w.poff, w.pair_i,
-                       w.pair_j, w.rev, w.status, w.flag);
+    hipLaunchKernelGGL(k_compact, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, w.nbr, w.cnt, w.poff,
+                       w.pair_i, w.pair_j, w.nbr_t, w.rev, w.status, w.flag);
     if (!clear_in_fs) hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, st, w.flag, 0);
 }
 
