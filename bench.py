@@ -290,9 +290,9 @@ TRAFFIC = {
     "adjoint": ("paper_2212_10508_amd/csrc/adjoint.hip",
                 "b213ae4ad852068155c19b9c3e32d3e1c660a037de09948fab4e59a3dcfe1fd4", 5190.6, "atom"),
     "dedr": ("paper_2212_10508_amd/csrc/kernels.hip",
-             "f6309a8b82050d59db706dafd806078af38ba49e41aa86204f260832144b89b9", 449.5, "pair"),
+             "59b3065dd330c2a1f15ea4733a2bffd1127e249a1c8d87de33a2be0038682962", 449.5, "pair"),
     "density": ("paper_2212_10508_amd/csrc/kernels.hip",
-                "f6309a8b82050d59db706dafd806078af38ba49e41aa86204f260832144b89b9", 308.9, "pair"),
+                "59b3065dd330c2a1f15ea4733a2bffd1127e249a1c8d87de33a2be0038682962", 308.9, "pair"),
 }
 
 
