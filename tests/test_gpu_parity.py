@@ -105,6 +105,38 @@ def test_ragged_batch_snap_and_accumulate(S):
         assert frel(fg[:, off[s]:off[s + 1]], ref) < FTOL
 
 
+@pytest.mark.parametrize("J", [2, 8])
+def test_propagation_forces_fold_fs_into_snap(S, J):
+    """A propagation step evaluates FS + SNAP as one chain (the FS density term in the slot
+    table, rho and F'(rho) in the density pass, the FS half of dE_i/dr in k_dedr).  Its
+    force at the final positions (f_out) against the separate FS and SNAP kernels at the
+    same positions, and against the oracle, on a ragged batch with an empty system and a
+    1025-atom system (cell grid)."""
+    beta = W.snap_beta(J, seed=4, scale=2e-2)
+    parts = [W.bcc_sia(4, jitter=0.08, seed=5), (np.zeros((3, 0)), np.array([12.66, 12.66, 12.66])),
+             W.bcc_sia(8, jitter=0.05, seed=6), W.bcc_sia(6, jitter=0.1, seed=7)]
+    X, off, B = W.pack([p[0] for p in parts], [p[1] for p in parts])
+    N = X.shape[1]
+    P = np.concatenate([W.maxwell_momenta(x.shape[1], 1000.0, seed=8 + s) for s, (x, _) in enumerate(parts)],
+                       axis=1)
+    ctx = S.context()
+    xd, pd = dev(X), dev(P)
+    f = torch.zeros((3, N), dtype=torch.float64, device="cuda")
+    ctx.langevin_steps(S.POT_FS_SNAP, xd, pd, off, B, 1, step0=0, dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0,
+                       seed=3, noise_id=0, fs=W.FS_W, J=J, beta=beta, f_out=f)
+    fg = host(f)
+    ref = S.eam_forces(xd.clone(), off, B, W.FS_W)
+    S.snap_forces(xd.clone(), off, B, J, beta, f=ref, accumulate=True)
+    assert frel(fg, host(ref)) < FTOL
+    xh = host(xd)
+    for s, (x, box) in enumerate(parts):
+        if x.shape[1] == 0:
+            continue
+        xs = xh[:, off[s]:off[s + 1]]
+        fo = O.snap_compute(xs, box, J, beta)["f"] + O.fs_compute(xs, box, W.FS_W)["f"]
+        assert frel(fg[:, off[s]:off[s + 1]], fo) < FTOL, s
+
+
 def test_full_size_slab_batch_sampled(S):
     """64 slabs x 1025 atoms, twojmax 8 (the benchmark launch): systems sampled."""
     J = 8
