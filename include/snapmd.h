@@ -222,7 +222,7 @@ int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_bat
 /* Launch mode of langevin_steps and of the fine and coarse propagation of
  * parareal_iterate.  enable = 1 (the default): the n_steps launch sequence is captured
  * once into a hipGraph, cached per context (keyed by sizes, parameters and device
- * pointers; at most 96 kept per workspace, least recently used dropped; every cached graph is dropped
+ * pointers; at most 256 kept per workspace, least recently used dropped; every cached graph is dropped
  * when the context reallocates a work buffer) and replayed on the caller's stream.
  * enable = 0: kernels are launched one by one.  Calls of more than 1000 steps are always
  * launched one by one.  Results are identical either way.

@@ -539,7 +539,9 @@ int prepare_propagation_cells(snapmd_ctx *ctx, Work &w, int potential, const Bat
     return prepare_cells(ctx, w, bc, rl, st);
 }
 
-constexpr size_t kGraphCache = 96;  // captured launch sequences kept per workspace
+// captured launch sequences kept per workspace (a chunk tuner cycles through about 30
+// plans of up to 5 chunks; fewer slots made it re-capture inside timed runs)
+constexpr size_t kGraphCache = 256;
 constexpr int kGraphMaxSteps = 1000;  // longest call captured into one graph
 
 // run_langevin through a cached hipGraph: the whole launch sequence of n_steps steps is
