@@ -1,0 +1,87 @@
+"""Host-side logic that needs no GPU: the chunk tuner's candidate plans and its
+selection, and the one-GPU guard of bench.py."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from paper_2212_10508_amd import tune
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.parametrize("S,N,cus", [(64, 1025, 256), (32, 16001, 256), (7, 1025, 256), (1, 129, 256),
+                                     (100, 2000, 80)])
+def test_candidate_plans_cover_the_window(S, N, cus):
+    builtin = [S]
+    plans = tune.candidate_plans(S, N, cus, builtin=builtin, limit=24)
+    assert plans[0] == builtin
+    assert len(plans) == len({tuple(p) for p in plans})  # no duplicates
+    for p in plans:
+        assert sum(p) == S and min(p) >= 1, p
+
+
+def test_candidate_plans_include_one_round_chunks():
+    # 64 slabs of 1025 atoms on 256 CUs: rounds of (256 - 16) * 64 atoms hold R = 14 slabs
+    plans = tune.candidate_plans(64, 1025, 256, builtin=[29, 22, 13])
+    assert [14, 14, 14, 14, 8] in plans and [13, 13, 13, 13, 12] in plans
+    # the whole-round plans are non-increasing with a last chunk of at most one round
+    for p in plans[1:]:
+        if len(p) <= 4:
+            assert all(a >= b for a, b in zip(p, p[1:])) and p[-1] <= 14, p
+
+
+class _FakeCtx:
+    """Stands in for a snapmd context: a plan's 'iteration time' is a fixed function of
+    the plan, so the tuner's choice can be checked without a device."""
+
+    def __init__(self, builtin, cost):
+        self.plan, self.builtin, self.cost, self.k = None, builtin, cost, 0
+
+    def chunk_plan(self, S, N):
+        return list(self.plan) if self.plan else list(self.builtin)
+
+    def set_chunk_plan(self, p):
+        self.plan = list(p) if p else None
+
+    def set_sweep_workgroups(self, K):
+        self.k = K
+
+    def sweep_workgroups(self, N):
+        return self.k if self.k in (1, 8, 16) else 8
+
+
+def test_tuner_keeps_the_fastest_plan(monkeypatch):
+    target = (15, 13, 14, 15, 7)
+    cost = lambda p: 0.170 + 0.001 * sum(abs(a - b) for a, b in zip(p + (0,) * 5, target)) + 0.01 * abs(len(p) - 5)
+    ctx = _FakeCtx([29, 22, 13], cost)
+    clock = {"t": 0.0}
+    monkeypatch.setattr(tune.time, "perf_counter", lambda: clock["t"])
+
+    def run():
+        clock["t"] += cost(tuple(ctx.chunk_plan(64, 1025)))
+
+    plan, times = tune.tune_chunk_plan(ctx, run, 64, 1025, 256, passes=1)
+    # the refinement walks from the nearest candidate to the cheapest plan
+    assert tuple(plan) == target and ctx.plan == list(target)
+    assert times[target] == min(times.values())
+
+
+def test_sweep_width_tuner_picks_the_fastest(monkeypatch):
+    ctx = _FakeCtx([29, 22, 13], None)
+    clock = {"t": 0.0}
+    monkeypatch.setattr(tune.time, "perf_counter", lambda: clock["t"])
+    width_cost = {1: 0.30, 8: 0.19, 16: 0.193}
+
+    def run():
+        clock["t"] += width_cost[ctx.k if ctx.k else 8]
+
+    K, times = tune.tune_sweep_width(ctx, run, 1025)
+    assert K == 8 and ctx.k == 8 and set(times) == {1, 8, 16}
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "single GPU" in r.stderr
