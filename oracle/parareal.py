@@ -17,8 +17,15 @@ iterates of the paper's BBK scheme.
 
 Readings where the paper leaves room:
 * Relative error E(prev, cur, n_in, n) = sum_{m=n_in+1}^{n} |cur_m - prev_m| /
-  sum_{m=n_in+1}^{n} |prev_m|, |.| the Euclidean norm of the 3m position vector
-  (the n_in term is equal in both iterates; with n_in = 0 this is the classical E).
+  sum_{m=n_in+1}^{n} |prev_m|, |.| the Euclidean norm of the 3m position vector.  The
+  windowed form printed in "Adaptive parareal method" starts both sums at N_in, while
+  the classical definition (`def:rel-Err`) starts at n = 1; the paper calls the first a
+  natural extension of the second, and the two agree only if the sums start after the
+  window's first index.  That reading is taken here.  It is a choice that changes the
+  value: leaving |prev_{n_in}| out of the denominator makes E about (m + 1)/m times the
+  printed windowed form after m slabs (twice on the first slab), so windows shorten
+  slightly earlier.  Pinned by closed forms of straight-line trajectories
+  (tests/test_oracle_rel_error.py).
 * A shortened window keeps at least one slab: n_fi := max(n, n_in + 1).
 * The tentative window of a new time-slab is [n_in, min(N, n_in + max_window)]
   (max_window = N gives the paper's algorithm).
