@@ -224,8 +224,10 @@ int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_bat
  * once into a hipGraph, cached per context (keyed by sizes, parameters and device
  * pointers; at most 256 kept per workspace, least recently used dropped; every cached graph is dropped
  * when the context reallocates a work buffer) and replayed on the caller's stream.
- * enable = 0: kernels are launched one by one.  Calls of more than 1000 steps are always
- * launched one by one.  Results are identical either way.
+ * enable = 0: kernels are launched one by one.  A call of more than 1000 steps is replayed
+ * as captured segments of 250 steps (the step offsets of the systems are advanced on the
+ * device between segments), so no captured chain holds more than about 4,000 kernels.
+ * Results are identical either way.
  * While snapmd_profile is on, SNAP propagation is launched one by one. */
 int snapmd_use_graphs(snapmd_ctx *ctx, int enable);
 

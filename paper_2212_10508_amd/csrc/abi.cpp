@@ -63,6 +63,7 @@ struct snapmd_ctx {
     // per-system Langevin arrays
     DBuf<double> d_sig, d_sb0, d_sb1;
     DBuf<int64_t> d_step0;
+    DBuf<int64_t> seg_step0[2];                   // step offsets advanced by a segmented replay (per workspace)
     DBuf<int> d_noise;
     std::map<int, SnapDevTables> snap;
     std::vector<void *> allocs;
@@ -81,7 +82,7 @@ struct snapmd_ctx {
         int n_cells = 0;
         bool any = false;
     } cs, csc;
-    std::vector<double> noise_key;                // (n_in, S, L, N, seed, noise_id) it holds
+    std::vector<uint64_t> noise_key;              // (n_in, S, L, N, seed, noise_id) it holds
     KernelProf prof;
     // captured launch sequences of run_langevin, keyed by everything baked into them
     int use_graphs = 1;
@@ -130,6 +131,10 @@ int fail(snapmd_ctx *c, int code, const char *fmt, ...) {
     } while (0)
 
 void drop_graphs(snapmd_ctx *ctx) {
+    // a replay may still be queued on the caller's or the context's streams
+    bool any = false;
+    for (auto &c : ctx->graphs) any = any || !c.empty();
+    if (any) (void)hipDeviceSynchronize();
     for (auto &c : ctx->graphs) {
         for (auto &g : c) (void)hipGraphExecDestroy(g.exec);
         c.clear();
@@ -512,21 +517,30 @@ void enqueue_forces(snapmd_ctx *ctx, Work &w, int potential, const BatchDev &bd,
     }
 }
 
-// n_steps BAOAB steps of the batch in place (force evaluated at the start), with the
-// workspace w and the force buffer f.
-void run_langevin(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
-                  const SnapDev &sd, const LangevinDev &ld, int n_steps, double *x, double *p, hipStream_t st) {
-    enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st);
-    for (int s = 0; s < n_steps; ++s) {
+// Steps s_lo .. s_hi - 1 of a call of the batch in place, with the workspace w and the
+// force buffer f (which holds the force at x unless `initial` asks to evaluate it first).
+// Step s draws the Gaussians of global step step0 + s; with the BBK scheme s = 0 is the
+// call's first iterate and s + 1 == n_last its last.
+void run_langevin_range(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
+                        const SnapDev &sd, const LangevinDev &ld, int s_lo, int s_hi, int n_last, bool initial,
+                        double *x, double *p, hipStream_t st) {
+    if (initial) enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st);
+    for (int s = s_lo; s < s_hi; ++s) {
         if (ld.scheme == SNAPMD_SCHEME_BBK) {
             launch_bbk_pre(bd, x, p, f, ld, s, w, kSkin, st);
             enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st, false);
-            launch_bbk_post(bd, p, f, ld, s + 1, n_steps, st);
+            launch_bbk_post(bd, p, f, ld, s + 1, n_last, st);
         } else {
             launch_baoab_pre(bd, x, p, f, ld, s, w, kSkin, st);
             enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st, false, p, ld.dt);
         }
     }
+}
+
+// n_steps steps of the batch in place (force evaluated at the start).
+void run_langevin(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
+                  const SnapDev &sd, const LangevinDev &ld, int n_steps, double *x, double *p, hipStream_t st) {
+    run_langevin_range(ctx, w, f, potential, bd, fp, sd, ld, 0, n_steps, n_steps, true, x, p, st);
 }
 
 // Cell grids (and their buffers) of the neighbour lists a propagation of the batch uses;
@@ -542,35 +556,28 @@ int prepare_propagation_cells(snapmd_ctx *ctx, Work &w, int potential, const Bat
 // captured launch sequences kept per workspace (a chunk tuner cycles through about 30
 // plans of up to 5 chunks; fewer slots made it re-capture inside timed runs)
 constexpr size_t kGraphCache = 256;
-constexpr int kGraphMaxSteps = 1000;  // longest call captured into one graph
+// Longest call captured into one graph.  A longer call is replayed in segments of
+// kGraphSegSteps steps, so no captured chain exceeds about 16 kGraphSegSteps kernel nodes.
+constexpr int kGraphMaxSteps = 1000;
+constexpr int kGraphSegSteps = 250;
+constexpr int kNoLast = 1 << 30;  // n_last of a segment that holds no call's last step
 
-// run_langevin through a cached hipGraph: the whole launch sequence of n_steps steps is
-// captured once per key (pointers, sizes, parameters baked into the kernel arguments)
-// and replayed afterwards.  The captured sequence contains kernels only.
-int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
-                       const SnapDev &sd, const LangevinDev &ld, int n_steps, double *x, double *p,
-                       hipStream_t st) {
-    // SNAP propagation stays eager while kernel timing is on (the events time each launch).
-    // Calls of more than kGraphMaxSteps steps are launched one by one too: a capture is
-    // one chain of about 16 nodes per step, and such chains are kept to the lengths the
-    // runtime has been exercised with here (10,000 steps, 160,000 nodes, ended the
-    // process).
-    if (!ctx->use_graphs || (ctx->prof.enabled && potential == SNAPMD_POT_FS_SNAP) || n_steps > kGraphMaxSteps) {
-        run_langevin(ctx, w, f, potential, bd, fp, sd, ld, n_steps, x, p, st);
-        return SNAPMD_OK;
-    }
-    {
-        int rc;
-        if ((rc = prepare_propagation_cells(ctx, w, potential, bd, fp, sd, st))) return rc;
-    }
+// Replay (capturing on first use) the launch sequence of run_langevin_range for these
+// arguments.  The key holds everything baked into the kernel arguments and launch
+// shapes: pointers, sizes (including the largest system, which sizes the LDS of the
+// neighbour build), parameters and the step range.
+int replay_range(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
+                 const SnapDev &sd, const LangevinDev &ld, int s_lo, int s_hi, int n_last, bool initial, double *x,
+                 double *p, hipStream_t st) {
     auto u = [](const void *q) { return (uint64_t)(uintptr_t)q; };
     auto d = [](double v) {
         uint64_t b;
         std::memcpy(&b, &v, sizeof b);
         return b;
     };
-    std::vector<uint64_t> key{(uint64_t)potential, (uint64_t)bd.N, (uint64_t)bd.n_sys, u(bd.off), u(bd.box),
-                              u(bd.cells), (uint64_t)bd.n_cells, (uint64_t)n_steps, u(x), u(p), u(f),
+    std::vector<uint64_t> key{(uint64_t)potential, (uint64_t)bd.N, (uint64_t)bd.n_sys, (uint64_t)bd.max_sys, u(bd.off),
+                              u(bd.box), u(bd.cells), (uint64_t)bd.n_cells, (uint64_t)s_lo, (uint64_t)s_hi,
+                              (uint64_t)n_last, (uint64_t)initial, u(x), u(p), u(f),
                               u(w.nbr), u(w.geo), u(w.u), u(w.ytil), u(w.xref), u(w.cell_cnt), u(w.flag), d(fp.A), d(fp.d), d(fp.c), d(fp.c0), d(fp.c1), d(fp.c2),
                               d(ld.dt), d(ld.c1), d(ld.mass), ld.seed, u(ld.sig), u(ld.step0), u(ld.noise_id),
                               (uint64_t)ld.scheme, d(ld.gamma), u(ld.sb0), u(ld.sb1), u(w.ph)};
@@ -595,7 +602,7 @@ int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     ++KernelProf::suppress;  // no event records inside a graph
-    run_langevin(ctx, w, f, potential, bd, fp, sd, ld, n_steps, x, p, cs);
+    run_langevin_range(ctx, w, f, potential, bd, fp, sd, ld, s_lo, s_hi, n_last, initial, x, p, cs);
     --KernelProf::suppress;
     HIPCHK(hipStreamEndCapture(cs, &graph));
     hipGraphExec_t exec;
@@ -605,12 +612,63 @@ int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const
     if (cache.size() >= kGraphCache) {
         auto it = std::min_element(cache.begin(), cache.end(),
                                    [](const auto &a, const auto &b) { return a.last_use < b.last_use; });
+        // the evicted graph may still be queued on some stream: let it finish first
+        HIPCHK(hipDeviceSynchronize());
         (void)hipGraphExecDestroy(it->exec);
         cache.erase(it);
     }
     cache.push_back({key, exec, now});
     HIPCHK(hipGraphLaunch(exec, st));
     return SNAPMD_OK;
+}
+
+// run_langevin through cached hipGraphs.  A call of up to kGraphMaxSteps steps is one
+// captured launch sequence.  A longer one runs as a head segment (the initial force
+// evaluation and steps 0 .. kGraphSegSteps - 1), then segments that are all captured
+// with the step range [kGraphSegSteps, 2 kGraphSegSteps) and replayed with the step
+// offsets of the systems advanced on the device between replays (a copy of the offsets
+// owned by the workspace), then a tail segment of the remaining steps, which holds the
+// call's last step.  Segment s of the call therefore draws exactly the Gaussians that
+// the one-chain launch sequence would, and BBK's first and last iterates stay where
+// they are.  The segments bound the length of every captured chain: a capture of
+// 10,000 steps, one linear chain of about 160,000 kernel nodes, ended the process with
+// a host segmentation fault (see the design notes on graph captures).
+int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
+                       const SnapDev &sd, const LangevinDev &ld, int n_steps, double *x, double *p,
+                       hipStream_t st) {
+    // SNAP propagation stays eager while kernel timing is on (the events time each launch)
+    if (!ctx->use_graphs || (ctx->prof.enabled && potential == SNAPMD_POT_FS_SNAP)) {
+        run_langevin(ctx, w, f, potential, bd, fp, sd, ld, n_steps, x, p, st);
+        return SNAPMD_OK;
+    }
+    int rc;
+    if ((rc = prepare_propagation_cells(ctx, w, potential, bd, fp, sd, st))) return rc;
+    if (n_steps <= kGraphMaxSteps)
+        return replay_range(ctx, w, f, potential, bd, fp, sd, ld, 0, n_steps, n_steps, true, x, p, st);
+    const int ci = (&w == &ctx->wc) ? 1 : 0;
+    DBuf<int64_t> &so = ctx->seg_step0[ci];
+    if (so.n < (size_t)bd.n_sys || !so.p)
+        return fail(ctx, SNAPMD_EINVAL, "segment step offsets not prepared for %d systems", bd.n_sys);
+    constexpr int G = kGraphSegSteps;
+    HIPCHK(hipMemcpyAsync(so.p, ld.step0, (size_t)bd.n_sys * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    LangevinDev lg = ld;
+    lg.step0 = so.p;
+    if ((rc = replay_range(ctx, w, f, potential, bd, fp, sd, lg, 0, G, kNoLast, true, x, p, st))) return rc;
+    // the copy's offsets lead the caller's by `adv`; a segment covering call steps
+    // [g0, g0 + len) is captured as [G, G + len) and needs adv = g0 - G
+    int64_t adv = 0;
+    for (int g0 = G; g0 < n_steps; g0 += G) {
+        const int len = std::min(G, n_steps - g0);
+        const bool last = g0 + len == n_steps;
+        if (g0 - G != adv) {
+            launch_add_i64(bd.n_sys, so.p, (int64_t)(g0 - G) - adv, st);
+            adv = g0 - G;
+        }
+        if ((rc = replay_range(ctx, w, f, potential, bd, fp, sd, lg, G, G + len, last ? G + len : kNoLast, false, x,
+                               p, st)))
+            return rc;
+    }
+    return check_launch(ctx);
 }
 
 // Per-system Langevin arrays (sigma, step offsets, noise ids) uploaded to the context.
@@ -628,7 +686,8 @@ int prepare_langevin(snapmd_ctx *ctx, const snapmd_langevin *lang, int S, const 
     }
     int rc;
     if ((rc = ensure(ctx, ctx->d_sig, S)) || (rc = ensure(ctx, ctx->d_step0, S)) || (rc = ensure(ctx, ctx->d_noise, S)) ||
-        (rc = ensure(ctx, ctx->d_sb0, S)) || (rc = ensure(ctx, ctx->d_sb1, S)))
+        (rc = ensure(ctx, ctx->d_sb0, S)) || (rc = ensure(ctx, ctx->d_sb1, S)) ||
+        (rc = ensure(ctx, ctx->seg_step0[0], S)) || (rc = ensure(ctx, ctx->seg_step0[1], S)))
         return rc;
     if ((rc = upload(ctx, ctx->d_sig.p, sig.data(), S, st))) return rc;
     if ((rc = upload(ctx, ctx->d_step0.p, step0.data(), S, st))) return rc;
@@ -646,8 +705,9 @@ int prepare_langevin(snapmd_ctx *ctx, const snapmd_langevin *lang, int S, const 
 // Gaussians of every (slab, step, atom) of the window for the LDS-resident sweep, kept
 // while the window (and the noise stream) stays the same.
 int launch_noise_sweep(snapmd_ctx *ctx, int n_in, int S, int L, int N, const snapmd_langevin *lang, hipStream_t st) {
-    const std::vector<double> key{(double)n_in, (double)S, (double)L, (double)N, (double)lang->seed,
-                                  (double)lang->noise_id_sys[0]};
+    // exact integers: two 64-bit seeds can round to the same double
+    const std::vector<uint64_t> key{(uint64_t)n_in, (uint64_t)S, (uint64_t)L, (uint64_t)N, lang->seed,
+                                    (uint64_t)lang->noise_id_sys[0]};
     if (key == ctx->noise_key) return SNAPMD_OK;
     int rc;
     if ((rc = ensure(ctx, ctx->sw_noise, (size_t)S * L * 3 * N))) return rc;

@@ -215,6 +215,7 @@ void launch_baoab_pre(const BatchDev &bd, double *x, double *p, const double *f,
 void launch_baoab_post(const BatchDev &bd, double *p, const double *f, double dt, hipStream_t st);
 void launch_bbk_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
                     const Work &w, double skin, hipStream_t st);
+void launch_add_i64(int n, int64_t *v, int64_t delta, hipStream_t st);
 // s1 = l + 1 (1 .. n_steps)
 void launch_bbk_post(const BatchDev &bd, double *p, const double *f, const LangevinDev &ld, int s1, int n_steps,
                      hipStream_t st);

@@ -1212,6 +1212,16 @@ void launch_bbk_pre(const BatchDev &bd, double *x, double *p, const double *f, c
                        s_step, w.xref, 0.25 * skin * skin, w.flag);
 }
 
+// adds delta to n int64 values (the step offsets of a segmented propagation)
+__global__ void k_add_i64(int n, int64_t *__restrict__ v, int64_t delta) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] += delta;
+}
+
+void launch_add_i64(int n, int64_t *v, int64_t delta, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_add_i64, dim3(nblk(n, 256)), dim3(256), 0, st, n, v, delta);
+}
+
 void launch_bbk_post(const BatchDev &bd, double *p, const double *f, const LangevinDev &ld, int s1, int n_steps,
                      hipStream_t st) {
     hipLaunchKernelGGL(k_bbk_post, dim3(nblk(bd.N, 256)), dim3(256), 0, st, bd.N, bd.n_sys, bd.off, p, f, ld, s1,
