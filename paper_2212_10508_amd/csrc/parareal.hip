@@ -63,14 +63,15 @@ struct SweepArgs {
     unsigned long long *gpart;    // [2][4][K][2] per-workgroup partials by parity
     int *abort;                   // set when a wait runs out (zero at launch)
     double delta_expl;
-    double *q_cur, *p_cur;                 // [slot][3][N]
-    const double *q_prev, *p_prev;         // [slot][3][N] (mode 1)
-    const double *jq, *jp;                 // [3][S*N], S = n_fi - n_in (mode 1)
+    double *q_cur, *p_cur;                 // [slot][3][ld] (this system's atoms at 0 .. N-1)
+    const double *q_prev, *p_prev;         // [slot][3][ld] (mode 1)
+    const double *jq, *jp;                 // jump of slab n_in + s, row al, atom i at al jsa + s jss + i (mode 1)
+    size_t ld, jsa, jss;
     // [0] delta, [1] n_fi after, [2] bad slab (-1 none), [3] overflow, [4] sum |cur - prev|,
     // [5] sum |prev|, [6] stopped: carried from one launch to the next over the slabs of a
     // window, initialised by the host
     double *out;
-    const double *noise;                   // [S][L][3][N] Gaussians of slabs n_in .. n_fi-1
+    const double *noise;                   // [S][L][3][N] Gaussians of slabs n_in .. n_fi-1 (or drawn in place)
 };
 
 __device__ __forceinline__ void sweep_gauss3(uint64_t seed, uint64_t noise_id, uint64_t step, uint64_t atom,
@@ -403,7 +404,10 @@ __device__ __forceinline__ void swl_force_wave(const SweepArgs &a, const double 
     f[2] = wave_sum(fz);
 }
 
-__global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
+// Body of the LDS-resident sweep of one system.  Drawn = true: the Gaussians are drawn in
+// place (counter (noise_id, n L + l, atom)) instead of read from a window table.
+template <bool Drawn>
+__device__ __forceinline__ void sweep_lds_body(const SweepArgs &a) {
     extern __shared__ double sm[];
     if (a.out[6] != 0.0) return;  // an earlier launch of the window stopped early
     const int N = a.N;
@@ -427,7 +431,6 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
     const bool own0 = tid < N, own1 = i1 < N;
     double *p1 = s1 + (i1 - kSweepThreads), *f1 = p1 + 3 * NS, *r1 = p1 + 6 * NS;  // [al * NS] (own1 only)
     const double rcl = fmax(a.fp.d, a.fp.c) + a.skin, rcl2 = rcl * rcl;
-    const size_t SN = (size_t)(a.n_fi - a.n_in) * N;
     double pr[3], fr[3], xr[3];
     int cn0 = 0, cn1 = 0;
     uint64_t mk0 = 0, mk1 = 0;
@@ -437,12 +440,12 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
         xr[al] = 0.0;
         pr[al] = 0.0;
         if (own0) {
-            xs[al * N + tid] = a.q_cur[((size_t)a.n_in * 3 + al) * N + tid];
-            pr[al] = a.p_cur[((size_t)a.n_in * 3 + al) * N + tid];
+            xs[al * N + tid] = a.q_cur[((size_t)a.n_in * 3 + al) * a.ld + tid];
+            pr[al] = a.p_cur[((size_t)a.n_in * 3 + al) * a.ld + tid];
         }
         if (own1) {
-            xs[al * N + i1] = a.q_cur[((size_t)a.n_in * 3 + al) * N + i1];
-            p1[al * NS] = a.p_cur[((size_t)a.n_in * 3 + al) * N + i1];
+            xs[al * N + i1] = a.q_cur[((size_t)a.n_in * 3 + al) * a.ld + i1];
+            p1[al * NS] = a.p_cur[((size_t)a.n_in * 3 + al) * a.ld + i1];
             f1[al * NS] = 0.0;
         }
     }
@@ -575,7 +578,13 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
         // The list is rebuilt only if some atom moved more than skin/2 since the last build.
         for (int l = -1; l < a.L; ++l) {
             double d0 = 0.0, d1 = 0.0;
-            const double *gz = a.noise + ((size_t)((n - a.n_in) * a.L + max(l, 0)) * 3) * N;
+            const double *gz = Drawn ? nullptr : a.noise + ((size_t)((n - a.n_in) * a.L + max(l, 0)) * 3) * N;
+            double gd0[3] = {0.0, 0.0, 0.0}, gd1[3] = {0.0, 0.0, 0.0};
+            if (Drawn && l >= 0) {
+                const uint64_t gs = (uint64_t)n * (uint64_t)a.L + (uint64_t)l;
+                if (own0) sweep_gauss3(a.seed, a.noise_id, gs, (uint64_t)tid, gd0[0], gd0[1], gd0[2]);
+                if (own1) sweep_gauss3(a.seed, a.noise_id, gs, (uint64_t)i1, gd1[0], gd1[1], gd1[2]);
+            }
 #pragma unroll
             for (int al = 0; al < 3; ++al) {
                 if (own0) {
@@ -583,7 +592,7 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
                     if (l >= 0) {
                         double pp = pr[al] + hk * fr[al];
                         xx = xx + hd * pp;
-                        pp = a.c1 * pp + a.sig * gz[al * N + tid];
+                        pp = a.c1 * pp + a.sig * (Drawn ? gd0[al] : gz[al * N + tid]);
                         xx = xx + hd * pp;
                         pr[al] = pp;
                         xs[al * N + tid] = xx;
@@ -595,7 +604,7 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
                     if (l >= 0) {
                         double pp = p1[al * NS] + hk * f1[al * NS];
                         xx = xx + hd * pp;
-                        pp = a.c1 * pp + a.sig * gz[al * N + i1];
+                        pp = a.c1 * pp + a.sig * (Drawn ? gd1[al] : gz[al * N + i1]);
                         xx = xx + hd * pp;
                         p1[al * NS] = pp;
                         xs[al * N + i1] = xx;
@@ -627,9 +636,9 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
             for (int al = 0; al < 3; ++al) {
                 double xq = xs[al * N + i], pq = q == 0 ? pr[al] : p1[al * NS];
                 if (a.mode == 1) {
-                    xq += a.jq[al * SN + s * N + i];
-                    pq += a.jp[al * SN + s * N + i];
-                    const double pv = a.q_prev[((size_t)(n + 1) * 3 + al) * N + i];
+                    xq += a.jq[al * a.jsa + s * a.jss + i];
+                    pq += a.jp[al * a.jsa + s * a.jss + i];
+                    const double pv = a.q_prev[((size_t)(n + 1) * 3 + al) * a.ld + i];
                     d2 += (xq - pv) * (xq - pv);
                     p2 += pv * pv;
                 }
@@ -637,8 +646,8 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
                 xs[al * N + i] = xq;
                 if (q == 0) pr[al] = pq;
                 else p1[al * NS] = pq;
-                a.q_cur[((size_t)(n + 1) * 3 + al) * N + i] = xq;
-                a.p_cur[((size_t)(n + 1) * 3 + al) * N + i] = pq;
+                a.q_cur[((size_t)(n + 1) * 3 + al) * a.ld + i] = xq;
+                a.p_cur[((size_t)(n + 1) * 3 + al) * a.ld + i] = pq;
             }
         }
         const double sfin = wg_sum(fin, red);
@@ -666,6 +675,15 @@ __global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) {
         if (bad >= 0) a.out[2] = (double)bad;
         if (nfi_new >= 0 || bad >= 0) a.out[6] = 1.0;
     }
+}
+
+__global__ void __launch_bounds__(1024) k_coarse_sweep_lds(SweepArgs a) { sweep_lds_body<false>(a); }
+
+// The sweeps of several independent systems at once, one workgroup each (tab[blockIdx.x]);
+// the Gaussians are drawn in place.
+__global__ void __launch_bounds__(1024) k_coarse_sweep_lds_multi(const SweepArgs *__restrict__ tab) {
+    const SweepArgs a = tab[blockIdx.x];
+    sweep_lds_body<true>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1025,11 +1043,12 @@ void launch_noise_table(int S, int L, int N, int n_in, uint64_t seed, uint64_t n
 // End of slab n for the host-driven sweep of large systems: cur_{n+1} = state (+ J_n),
 // written to the slab slot and back into the running state; partial sums of
 // |cur - prev|^2, |prev|^2 and a non-finite probe into part[0..2] (one workgroup, fixed
-// reduction order).
-__global__ void __launch_bounds__(1024) k_slab_end(int N, int mode, size_t SN, size_t s, double *__restrict__ xs,
-                                                   double *__restrict__ ps, const double *__restrict__ jq,
-                                                   const double *__restrict__ jp,
-                                                   const double *__restrict__ qprev_next,
+// reduction order).  The running state xs, ps is [3][N]; the slot rows (qprev_next,
+// qcur_next, pcur_next) have stride ld; the jump of row al is at jq[al jsa + s jss + i].
+__global__ void __launch_bounds__(1024) k_slab_end(int N, int mode, size_t jsa, size_t jss, size_t s,
+                                                   double *__restrict__ xs, double *__restrict__ ps,
+                                                   const double *__restrict__ jq, const double *__restrict__ jp,
+                                                   size_t ld, const double *__restrict__ qprev_next,
                                                    double *__restrict__ qcur_next, double *__restrict__ pcur_next,
                                                    double *__restrict__ part) {
     __shared__ double red[kSpillMax];
@@ -1038,17 +1057,17 @@ __global__ void __launch_bounds__(1024) k_slab_end(int N, int mode, size_t SN, s
         for (int al = 0; al < 3; ++al) {
             double xq = xs[al * N + i], pq = ps[al * N + i];
             if (mode == 1) {
-                xq += jq[al * SN + s * N + i];
-                pq += jp[al * SN + s * N + i];
-                const double pv = qprev_next[al * N + i];
+                xq += jq[al * jsa + s * jss + i];
+                pq += jp[al * jsa + s * jss + i];
+                const double pv = qprev_next[al * ld + i];
                 d2 += (xq - pv) * (xq - pv);
                 p2 += pv * pv;
             }
             fin += xq * 0.0 + pq * 0.0;
             xs[al * N + i] = xq;
             ps[al * N + i] = pq;
-            qcur_next[al * N + i] = xq;
-            pcur_next[al * N + i] = pq;
+            qcur_next[al * ld + i] = xq;
+            pcur_next[al * ld + i] = pq;
         }
     const double a = wg_sum(d2, red), b = wg_sum(p2, red), c = wg_sum(fin, red);
     if (threadIdx.x == 0) {
@@ -1058,10 +1077,99 @@ __global__ void __launch_bounds__(1024) k_slab_end(int N, int mode, size_t SN, s
     }
 }
 
-void launch_slab_end(int N, int mode, size_t SN, size_t s, double *xs, double *ps, const double *jq, const double *jp,
-                     const double *qprev_next, double *qcur_next, double *pcur_next, double *part, hipStream_t st) {
-    hipLaunchKernelGGL(k_slab_end, dim3(1), dim3(kSweepThreads), 0, st, N, mode, SN, s, xs, ps, jq, jp, qprev_next,
-                       qcur_next, pcur_next, part);
+void launch_slab_end(int N, int mode, size_t jsa, size_t jss, size_t s, double *xs, double *ps, const double *jq,
+                     const double *jp, size_t ld, const double *qprev_next, double *qcur_next, double *pcur_next,
+                     double *part, hipStream_t st) {
+    hipLaunchKernelGGL(k_slab_end, dim3(1), dim3(kSweepThreads), 0, st, N, mode, jsa, jss, s, xs, ps, jq, jp, ld,
+                       qprev_next, qcur_next, pcur_next, part);
+}
+
+// ---------------------------------------------------------------------------
+// Batches of several systems, each with its own window [n_in_r, n_fi_r] of slabs.  The
+// states of all systems share one slot layout [slot][3][ld] (system r's atoms at columns
+// off[r] .. off[r+1]-1); the batched propagators see entry e = (system r_e, slab n_e) as
+// a system of their own, entries back to back in the chunk's SoA arrays [3][Nc].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_seg(const int *__restrict__ off, int n, int i) {
+    int lo = 0, hi = n;  // largest s with off[s] <= i
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// prev := cur on the slots n_in_r .. n_fi_r of every system r (win[r] = (n_in, n_fi);
+// an empty window, n_in = n_fi, copies nothing)
+__global__ void k_copy_windows(int n_slots, int ld, int n_sys, const int *__restrict__ off,
+                               const int2 *__restrict__ win, const double *__restrict__ q, const double *__restrict__ p,
+                               double *__restrict__ qd, double *__restrict__ pd) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)n_slots * 3 * ld) return;
+    const int col = (int)(e % ld);
+    const int slot = (int)(e / ((size_t)3 * ld));
+    const int r = find_seg(off, n_sys, col);
+    const int2 w = win[r];
+    if (w.x < w.y && slot >= w.x && slot <= w.y) {
+        qd[e] = q[e];
+        pd[e] = p[e];
+    }
+}
+
+// entries -> batch: out[al][j] = state[slot_e][al][col_e + j - off[e]] for the Nc atoms of
+// a chunk of entries (src[e] = (slot_e, col_e), off = the chunk's atom offsets)
+__global__ void k_entries_to_batch(int Nc, int n_ent, const int *__restrict__ off, const int2 *__restrict__ src,
+                                   int ld, const double *__restrict__ state, double *__restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= Nc) return;
+    const int e = find_seg(off, n_ent, j);
+    const int2 sc = src[e];
+    const size_t base = (size_t)sc.x * 3 * ld + sc.y + (j - off[e]);
+#pragma unroll
+    for (int al = 0; al < 3; ++al) out[(size_t)al * Nc + j] = state[base + (size_t)al * ld];
+}
+
+// jumps of a chunk into the slot layout: jump[slot_e][al][col_e + i] = f[al][j] - c[al][j]
+__global__ void k_batch_jumps_to_slots(int Nc, int n_ent, const int *__restrict__ off, const int2 *__restrict__ src,
+                                       int ld, const double *__restrict__ f, const double *__restrict__ c,
+                                       double *__restrict__ jump) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= Nc) return;
+    const int e = find_seg(off, n_ent, j);
+    const int2 sc = src[e];
+    const size_t base = (size_t)sc.x * 3 * ld + sc.y + (j - off[e]);
+#pragma unroll
+    for (int al = 0; al < 3; ++al) jump[base + (size_t)al * ld] = f[(size_t)al * Nc + j] - c[(size_t)al * Nc + j];
+}
+
+void launch_copy_windows(int n_slots, int ld, int n_sys, const int *off, const int2 *win, const double *q,
+                         const double *p, double *qd, double *pd, hipStream_t st) {
+    const size_t tot = (size_t)n_slots * 3 * ld;
+    if (tot == 0) return;
+    hipLaunchKernelGGL(k_copy_windows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n_slots, ld, n_sys, off,
+                       win, q, p, qd, pd);
+}
+
+void launch_entries_to_batch(int Nc, int n_ent, const int *off, const int2 *src, int ld, const double *state,
+                             double *out, hipStream_t st) {
+    if (Nc <= 0) return;
+    hipLaunchKernelGGL(k_entries_to_batch, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, st, Nc, n_ent, off, src,
+                       ld, state, out);
+}
+
+void launch_batch_jumps_to_slots(int Nc, int n_ent, const int *off, const int2 *src, int ld, const double *f,
+                                 const double *c, double *jump, hipStream_t st) {
+    if (Nc <= 0) return;
+    hipLaunchKernelGGL(k_batch_jumps_to_slots, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, st, Nc, n_ent, off,
+                       src, ld, f, c, jump);
+}
+
+// LDS sweeps of n systems at once (tab: device [n] arguments, one workgroup each; every
+// system fits the LDS-resident sweep, max_atoms the largest)
+void launch_coarse_sweep_multi(const SweepArgs *tab, int n, int max_atoms, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_coarse_sweep_lds_multi, dim3(n), dim3(kSweepThreads), sweep_lds_bytes(max_atoms), st, tab);
 }
 
 bool sweep_fits_lds(int N) { return N <= kSweepLdsMaxAtoms && sweep_lds_bytes(N) <= 160 * 1024; }
@@ -1131,6 +1239,9 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     a.p_prev = s.p_prev;
     a.jq = s.jq;
     a.jp = s.jp;
+    a.ld = (size_t)s.N;
+    a.jsa = (size_t)(s.n_fi - s.n_in) * s.N;
+    a.jss = (size_t)s.N;
     a.out = s.out;
     if (s.K > 0) {
         // at least 81 KB of LDS so that no two of the workgroups share a CU
