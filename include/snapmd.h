@@ -12,7 +12,8 @@
  *   snap_forces       SNAP forces (fine potential of the "MD settings" section)
  *   eam_forces        Finnis-Sinclair EAM forces (coarse potential)
  *   langevin_steps    BAOAB Langevin steps for a ragged batch of systems
- *   parareal_iterate  one corrected iteration of adaptive parareal on a window
+ *   parareal_iterate  one corrected iteration of adaptive parareal, every system on
+ *                     a window of its own
  *   snap_beta_grad    dE/dbeta and d(force loss)/dbeta (SNAP coefficient gradients)
  *
  * Conventions (every entry point):
@@ -159,35 +160,49 @@ int langevin_steps(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, cons
                    const snapmd_batch *batch, const snapmd_langevin *lang, int32_t n_steps,
                    double *x, double *p, double *f_out, void *stream);
 
-/* One corrected iteration of (adaptive) parareal for ONE trajectory of n_atoms atoms
- * ("Adaptive parareal method": the body of its inner while loop) on the window
- * [n_in, *n_fi]:
- *   prev_n := cur_n for n_in <= n <= *n_fi;
- *   J_n := F(prev_n) - C(prev_n) for n_in <= n < *n_fi, all slabs at once;
- *   for n = n_in .. *n_fi - 1:  cur_{n+1} := C(cur_n) + J_n;
+/* One corrected iteration of (adaptive) parareal ("Adaptive parareal method": the body
+ * of the inner while loop of its Algorithm "Adaptive parareal algorithm", equation
+ * eq:parareal) for EVERY system r of the batch, each on its own window
+ * [n_in[r], n_fi[r]] of slabs:
+ *   prev_n := cur_n for n_in <= n <= n_fi;
+ *   J_n := F(prev_n) - C(prev_n) for n_in <= n < n_fi, all slabs of all systems at once;
+ *   for n = n_in .. n_fi - 1:  cur_{n+1} := C(cur_n) + J_n;
  *       delta := sum_{m=n_in+1}^{n+1} |cur_m - prev_m| / sum_{m=n_in+1}^{n+1} |prev_m|
- *       (Euclidean norms of the 3 n_atoms position vectors);
- *       if delta > delta_expl: *n_fi := max(n, n_in + 1); stop.
- * Slab n covers global steps n*L .. n*L + L - 1 of noise stream lang->noise_id_sys[0]
- * (lang->step0_sys, T_sys[0] used for every slab; step0_sys is ignored).
- * q_cur, p_cur: device [n_slots][3][n_atoms] (n_slots > *n_fi), states cur_n; read
- * on [n_in, *n_fi], written on (n_in, *n_fi].  q_prev, p_prev: device, same shape,
- * receive prev_n on [n_in, *n_fi].  batch must hold exactly one system (its box).
- * delta_expl = +inf gives the classical algorithm.  Writes *delta_out and possibly
- * *n_fi (host).  Synchronises `stream` once; returns SNAPMD_ENONFINITE if a state
- * became non-finite (the message names the slab).
- * Initialisation of a new time window (the coarse propagation that starts each
- * window of the adaptive algorithm): pass q_prev = p_prev = NULL; then only
- * cur_{n+1} := C(cur_n) for n_in <= n < *n_fi is done, *delta_out = 0, snap may be NULL.
- * The coarse sweep keeps a Verlet list with a 0.5 A skin and stores each listed
- * pair's periodic image: max(d, c) + 1.0 must be below half the smallest box edge.
- * With SNAPMD_SCHEME_BBK every slab is one application of the scheme (L iterates) for
- * both propagators, and the sequential sweep runs slab by slab from the host (one small
- * synchronisation per slab) instead of in one persistent kernel. */
+ *       (Euclidean norms of the 3 n_atoms position vector of the system; the sums start
+ *       after the window's first slab, so that at n_in = 0 this is def:rel-Err);
+ *       if delta > delta_expl: n_fi := max(n, n_in + 1); stop.
+ * Slab n of system r covers global steps n*L .. n*L + L - 1 of noise stream
+ * lang->noise_id_sys[r] at temperature lang->T_sys[r] (lang->step0_sys is ignored).
+ * State layout: q_cur, p_cur, q_prev, p_prev are device [n_slots][3][n_atoms] (n_atoms =
+ * offset[n_sys]); slot n holds every system's state at slab boundary n, system r in
+ * columns offset[r] .. offset[r+1]-1 of each row.  cur is read on [n_in[r], n_fi[r]] and
+ * written on (n_in[r], n_fi[r]]; prev receives cur on [n_in[r], n_fi[r]]; nothing else
+ * is touched.
+ * n_in: host [n_sys]; n_fi: host [n_sys], updated; delta_out: host [n_sys], receives
+ * delta.  Need 0 <= n_in[r] <= n_fi[r] <= n_slots - 1; with more than one system an
+ * empty window (n_in[r] = n_fi[r]) leaves system r out (delta_out[r] = 0), with one
+ * system the window must not be empty.
+ * delta_expl = +inf gives the classical algorithm.  Synchronises `stream` once (plus once
+ * per slab of a sweep driven from the host); returns SNAPMD_ENONFINITE if a state became
+ * non-finite (the message names the system and the slab).
+ * Initialisation of new time windows (the coarse propagation that starts each window of
+ * the adaptive algorithm): pass q_prev = p_prev = NULL; then only cur_{n+1} := C(cur_n)
+ * for n_in[r] <= n < n_fi[r] is done, delta_out = 0, snap may be NULL.
+ * The coarse sweep keeps a Verlet list with a 0.5 A skin and stores each listed pair's
+ * periodic image: max(d, c) + 1.0 must be below half the smallest box edge.
+ * Schedules: one system runs the pipelined path (slab chunks of the fine propagation
+ * overlapping the on-device sweep); several systems run their fine and coarse
+ * propagations as ragged batches of (system, slab) entries, then the sweeps of all
+ * systems of at most ~1,500 atoms in one launch (one workgroup each), larger ones from
+ * the host.  With SNAPMD_SCHEME_BBK, or a SNAP coarse potential, every sweep runs slab by
+ * slab from the host (one small synchronisation per slab) instead of in one persistent
+ * kernel.  Results do not depend on the schedule beyond the rounding of the relative
+ * error's partial sums. */
 int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs,
                      const snapmd_batch *batch, const snapmd_langevin *lang, int32_t L,
-                     int32_t n_in, int32_t *n_fi, double *q_prev, double *p_prev, double *q_cur,
-                     double *p_cur, double delta_expl, double *delta_out, void *stream);
+                     const int32_t *n_in, int32_t *n_fi, int32_t n_slots, double *q_prev,
+                     double *p_prev, double *q_cur, double *p_cur, double delta_expl,
+                     double *delta_out, void *stream);
 
 /* Coarse propagator of parareal_iterate.  By default it is Finnis-Sinclair alone (the
  * paper's strategy II: an EAM coarse potential).  snapmd_set_coarse_snap(ctx, coarse)

@@ -74,6 +74,12 @@ struct snapmd_ctx {
     DBuf<int> sw_abort;
     double *h_out = nullptr;                      // pinned [16]: sweep results [0, 8), sweep init [8, 16)
     DBuf<double> sw_noise;                        // Gaussians of the current window
+    // parareal over several systems: offsets, windows, jumps in the slot layout, entry
+    // sources, sweep arguments and results
+    DBuf<int> m_off;
+    DBuf<int2> m_win, m_src;
+    DBuf<double> m_jq, m_jp, m_out;
+    DBuf<unsigned char> m_tab;
     DBuf<double> gB;                              // [K][N] bispectrum / its variation
     // cell grids of the current batch for the last list cutoff, one set per workspace
     struct CellState {
@@ -732,158 +738,73 @@ int check_lang(snapmd_ctx *ctx, const snapmd_langevin *lang) {
 
 }  // namespace
 
-// ===========================================================================
-extern "C" {
+namespace {
 
-int snapmd_create(snapmd_ctx **out, int hip_device) {
-    if (!out) return SNAPMD_EINVAL;
-    *out = nullptr;
-    int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return SNAPMD_EINVAL;
-    if (hipSetDevice(hip_device) != hipSuccess) return SNAPMD_EHIP;
-    snapmd_ctx *ctx = new snapmd_ctx();
-    ctx->device = hip_device;
-    {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
-            ctx->n_cus = cus;
+// The sequential sweep of one system driven from the host with the batched kernels, one
+// small synchronisation per slab for the relative error and the early stop (systems the
+// on-device sweeps do not take, the BBK scheme, a coarse potential with SNAP).  q_cur,
+// p_cur, q_prev point at the system's first atom in slot 0 of the slot layout [slot][3][ld];
+// the jump of slab n_in + s, row al, atom i is at jq[al jsa + s jss + i].
+int host_sweep(snapmd_ctx *ctx, int potC, const FsParams &fp, const SnapDev &sdc, const snapmd_langevin *lang,
+               double T, int noise_id, int N, const double *box, int L, int n_in, int32_t *n_fi, bool init, size_t ld,
+               double *q_cur, double *p_cur, const double *q_prev, const double *jq, const double *jp, size_t jsa,
+               size_t jss, double delta_expl, double *delta_out, hipStream_t st, void *stream) {
+    int rc;
+    if ((rc = ensure(ctx, ctx->sw_x, 3 * (size_t)N)) || (rc = ensure(ctx, ctx->sw_p, 3 * (size_t)N)) ||
+        (rc = ensure(ctx, ctx->sw_out, 8)))
+        return rc;
+    if (!ctx->h_out) HIPCHK(hipHostMalloc((void **)&ctx->h_out, 16 * sizeof(double), hipHostMallocDefault));
+    double *wx = ctx->sw_x.p, *wp = ctx->sw_p.p;
+    const size_t so = (size_t)n_in * 3 * ld;  // slot n_in
+    HIPCHK(hipMemcpy2DAsync(wx, (size_t)N * sizeof(double), q_cur + so, ld * sizeof(double), (size_t)N * sizeof(double),
+                            3, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpy2DAsync(wp, (size_t)N * sizeof(double), p_cur + so, ld * sizeof(double), (size_t)N * sizeof(double),
+                            3, hipMemcpyDeviceToDevice, st));
+    int off1[2] = {0, N};
+    snapmd_batch b1{1, off1, box};
+    BatchDev bd1;
+    double mh1;
+    if ((rc = prepare_batch(ctx, &b1, bd1, mh1, st))) return rc;
+    double num = 0.0, den = 0.0, delta = 0.0;
+    int nfi_new = *n_fi;
+    for (int n = n_in; n < *n_fi; ++n) {
+        std::vector<double> T1(1, T);
+        std::vector<int64_t> s1(1, (int64_t)n * L);
+        std::vector<int> id1(1, noise_id);
+        LangevinDev ld1;
+        if ((rc = prepare_langevin(ctx, lang, 1, T1, s1, id1, ld1, st))) return rc;
+        // one captured launch sequence serves every slab: the step offset of the slab
+        // is read from device memory (uploaded above) when the sequence runs
+        if ((rc = run_langevin_graph(ctx, ctx->w, ctx->d_f, potC, bd1, fp, sdc, ld1, L, wx, wp, st))) return rc;
+        const size_t nx = (size_t)(n + 1) * 3 * ld;  // slot n + 1
+        launch_slab_end(N, init ? 0 : 1, jsa, jss, (size_t)(n - n_in), wx, wp, jq, jp, ld,
+                        init ? nullptr : q_prev + nx, q_cur + nx, p_cur + nx, ctx->sw_out.p, st);
+        if ((rc = check_launch(ctx))) return rc;
+        HIPCHK(hipMemcpyAsync(ctx->h_out, ctx->sw_out.p, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+        if ((rc = snapmd_sync(ctx, stream))) return rc;
+        if (!std::isfinite(ctx->h_out[2])) return fail(ctx, SNAPMD_ENONFINITE, "state became non-finite in slab %d", n);
+        if (!init) {
+            num += std::sqrt(ctx->h_out[0]);
+            den += std::sqrt(ctx->h_out[1]);
+            delta = den > 0.0 ? num / den : 0.0;
+            if (delta > delta_expl) {
+                nfi_new = std::max(n, n_in + 1);
+                break;
+            }
+        }
     }
-    adjoint_init_attributes();
-    sweep_init_attributes();
-    neigh_init_attributes();
-    if (dalloc(ctx, &ctx->w.status, 1) != SNAPMD_OK || hipMemset(ctx->w.status, 0, sizeof(int)) != hipSuccess ||
-        dalloc(ctx, &ctx->w.flag, 1) != SNAPMD_OK || hipMemset(ctx->w.flag, 0, sizeof(int)) != hipSuccess) {
-        snapmd_destroy(ctx);
-        return SNAPMD_ENOMEM;
-    }
-    *out = ctx;
+    *delta_out = delta;
+    *n_fi = nfi_new;
     return SNAPMD_OK;
 }
 
-void snapmd_destroy(snapmd_ctx *ctx) {
-    if (!ctx) return;
-    (void)hipSetDevice(ctx->device);
-    for (void *p : ctx->allocs) (void)hipFree(p);
-    if (ctx->h_out) (void)hipHostFree(ctx->h_out);
-    drop_graphs(ctx);
-    for (hipStream_t c : ctx->cap_stream)
-        if (c) (void)hipStreamDestroy(c);
-    if (ctx->sweep_stream) (void)hipStreamDestroy(ctx->sweep_stream);
-    if (ctx->coarse_stream) (void)hipStreamDestroy(ctx->coarse_stream);
-    for (hipEvent_t e : ctx->pipe_ev) (void)hipEventDestroy(e);
-    for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
-    delete ctx;
-}
-
-const char *snapmd_last_error(const snapmd_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
-
-int snapmd_sync(snapmd_ctx *ctx, void *stream) {
-    if (!ctx) return SNAPMD_EINVAL;
-    HIPCHK(hipSetDevice(ctx->device));
-    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
-    int st = 0;
-    HIPCHK(hipMemcpy(&st, ctx->w.status, sizeof(int), hipMemcpyDeviceToHost));
-    if (st) {
-        HIPCHK(hipMemset(ctx->w.status, 0, sizeof(int)));
-        if (st & 1) return fail(ctx, SNAPMD_EOVERFLOW, "an atom has more than %d neighbours", kMaxNeigh);
-        return fail(ctx, SNAPMD_EINVAL, "inconsistent neighbour list (status %d)", st);
-    }
-    return SNAPMD_OK;
-}
-
-int snap_forces(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *batch, const double *x, double *f,
-                double *e_atom, uint32_t flags, void *stream) {
-    if (!ctx) return SNAPMD_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
-    HIPCHK(hipSetDevice(ctx->device));
-    if (!x || !f) return fail(ctx, SNAPMD_EINVAL, "x and f must be device pointers");
-    BatchDev bd;
-    double mh;
-    SnapDev sd;
+// One system (its states [slot][3][N]): the pipelined path of the bench workload.
+int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, const snapmd_batch *batch,
+                 const snapmd_langevin *lang, int32_t L, int32_t n_in, int32_t *n_fi, double *q_prev, double *p_prev,
+                 double *q_cur, double *p_cur, double delta_expl, double *delta_out, hipStream_t st, void *stream) {
     int rc;
-    if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
-    if ((rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
-    if (bd.N == 0) return SNAPMD_OK;
-    if ((rc = neighbors(ctx, ctx->w, bd, x, snap->rcut, true, st))) return rc;
-    launch_snap(sd.J, bd, x, sd, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st, &ctx->prof);
-    return check_launch(ctx);
-}
-
-int eam_forces(snapmd_ctx *ctx, const snapmd_fs *fs, const snapmd_batch *batch, const double *x, double *f,
-               double *e_atom, uint32_t flags, void *stream) {
-    if (!ctx) return SNAPMD_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
-    HIPCHK(hipSetDevice(ctx->device));
-    if (!x || !f) return fail(ctx, SNAPMD_EINVAL, "x and f must be device pointers");
-    BatchDev bd;
-    double mh;
-    FsParams fp;
-    int rc;
-    if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
-    if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
-    if (bd.N == 0) return SNAPMD_OK;
-    if ((rc = neighbors(ctx, ctx->w, bd, x, std::max(fp.d, fp.c), true, st))) return rc;
-    launch_fs(bd, x, fp, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st);
-    return check_launch(ctx);
-}
-
-int langevin_steps(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, const snapmd_fs *fs,
-                   const snapmd_batch *batch, const snapmd_langevin *lang, int32_t n_steps, double *x, double *p,
-                   double *f_out, void *stream) {
-    if (!ctx) return SNAPMD_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
-    HIPCHK(hipSetDevice(ctx->device));
-    if (potential != SNAPMD_POT_FS && potential != SNAPMD_POT_FS_SNAP)
-        return fail(ctx, SNAPMD_EINVAL, "potential must be SNAPMD_POT_FS or SNAPMD_POT_FS_SNAP");
-    if (!x || !p) return fail(ctx, SNAPMD_EINVAL, "x and p must be device pointers");
-    if (n_steps < 0) return fail(ctx, SNAPMD_EINVAL, "n_steps must be >= 0");
-    int rc;
-    if ((rc = check_lang(ctx, lang))) return rc;
-    BatchDev bd;
-    double mh;
-    FsParams fp;
-    SnapDev sd;
-    if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
-    if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
-    if (potential == SNAPMD_POT_FS_SNAP && (rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
-    const int S = bd.n_sys;
-    std::vector<double> T(lang->T_sys, lang->T_sys + S);
-    std::vector<int64_t> step0(lang->step0_sys, lang->step0_sys + S);
-    std::vector<int> nid(lang->noise_id_sys, lang->noise_id_sys + S);
-    for (int s = 0; s < S; ++s) {
-        if (!(T[s] >= 0.0)) return fail(ctx, SNAPMD_EINVAL, "T_sys[%d] must be >= 0", s);
-        if (nid[s] < 0) return fail(ctx, SNAPMD_EINVAL, "noise_id_sys[%d] must be >= 0", s);
-    }
-    LangevinDev ld;
-    if ((rc = prepare_langevin(ctx, lang, S, T, step0, nid, ld, st))) return rc;
-    if (bd.N == 0) return SNAPMD_OK;
-    if ((rc = run_langevin_graph(ctx, ctx->w, ctx->d_f, potential, bd, fp, sd, ld, n_steps, x, p, st))) return rc;
-    if (f_out)
-        HIPCHK(hipMemcpyAsync(f_out, ctx->d_f, 3 * (size_t)bd.N * sizeof(double), hipMemcpyDeviceToDevice, st));
-    return check_launch(ctx);
-}
-
-int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, const snapmd_batch *batch,
-                     const snapmd_langevin *lang, int32_t L, int32_t n_in, int32_t *n_fi, double *q_prev,
-                     double *p_prev, double *q_cur, double *p_cur, double delta_expl, double *delta_out,
-                     void *stream) {
-    if (!ctx) return SNAPMD_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
-    HIPCHK(hipSetDevice(ctx->device));
-    int rc;
-    if ((rc = check_lang(ctx, lang))) return rc;
-    if (!batch || batch->n_sys != 1) return fail(ctx, SNAPMD_EINVAL, "parareal_iterate needs a batch of one system");
-    if (!n_fi || !delta_out) return fail(ctx, SNAPMD_EINVAL, "n_fi and delta_out must be host pointers");
-    if (L < 1) return fail(ctx, SNAPMD_EINVAL, "L must be >= 1");
-    if (n_in < 0 || *n_fi <= n_in) return fail(ctx, SNAPMD_EINVAL, "need 0 <= n_in < n_fi (got %d, %d)", n_in, *n_fi);
-    if (!q_cur || !p_cur) return fail(ctx, SNAPMD_EINVAL, "q_cur and p_cur must be device pointers");
     const bool init = (q_prev == nullptr);
-    if (!init && !p_prev) return fail(ctx, SNAPMD_EINVAL, "p_prev must be set with q_prev");
-    if (!(delta_expl >= 0.0)) return fail(ctx, SNAPMD_EINVAL, "delta_expl must be >= 0");
-    if (!(lang->T_sys[0] >= 0.0) || lang->noise_id_sys[0] < 0)
-        return fail(ctx, SNAPMD_EINVAL, "need T_sys[0] >= 0 and noise_id_sys[0] >= 0");
     const int N = batch->offset[1];
-    if (batch->offset[0] != 0 || N < 1) return fail(ctx, SNAPMD_EINVAL, "the system needs at least one atom");
     const int S = *n_fi - n_in;
     const double *box = batch->box;
     double mh = 0.5 * std::min(box[0], std::min(box[1], box[2]));
@@ -1187,51 +1108,406 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
         *n_fi = (int32_t)ctx->h_out[1];
         return SNAPMD_OK;
     }
-    // Large systems: the same sweep driven from the host with the batched kernels, one
-    // small synchronisation per slab for the relative error and the early stop.
-    {
-        const size_t slot = 3 * (size_t)N;
-        double *wx = ctx->sw_x.p, *wp = ctx->sw_p.p;
-        HIPCHK(hipMemcpyAsync(wx, q_cur + n_in * slot, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(wp, p_cur + n_in * slot, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
-        int off1[2] = {0, N};
-        snapmd_batch b1{1, off1, box};
-        BatchDev bd1;
-        double mh1;
-        if ((rc = prepare_batch(ctx, &b1, bd1, mh1, st))) return rc;
-        double num = 0.0, den = 0.0, delta = 0.0;
-        int nfi_new = *n_fi;
-        for (int n = n_in; n < *n_fi; ++n) {
-            std::vector<double> T1(1, lang->T_sys[0]);
-            std::vector<int64_t> s1(1, (int64_t)n * L);
-            std::vector<int> id1(1, lang->noise_id_sys[0]);
-            LangevinDev ld1;
-            if ((rc = prepare_langevin(ctx, lang, 1, T1, s1, id1, ld1, st))) return rc;
-            // one captured launch sequence serves every slab: the step offset of the slab
-            // is read from device memory (uploaded above) when the sequence runs
-            if ((rc = run_langevin_graph(ctx, ctx->w, ctx->d_f, potC, bd1, fp, sdc, ld1, L, wx, wp, st))) return rc;
-            launch_slab_end(N, init ? 0 : 1, SN3 / 3, (size_t)(n - n_in), wx, wp, sw.jq, sw.jp,
-                            init ? nullptr : q_prev + (size_t)(n + 1) * slot, q_cur + (size_t)(n + 1) * slot,
-                            p_cur + (size_t)(n + 1) * slot, ctx->sw_out.p, st);
-            if ((rc = check_launch(ctx))) return rc;
-            HIPCHK(hipMemcpyAsync(ctx->h_out, ctx->sw_out.p, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-            if ((rc = snapmd_sync(ctx, stream))) return rc;
-            if (!std::isfinite(ctx->h_out[2]))
-                return fail(ctx, SNAPMD_ENONFINITE, "state became non-finite in slab %d", n);
-            if (!init) {
-                num += std::sqrt(ctx->h_out[0]);
-                den += std::sqrt(ctx->h_out[1]);
-                delta = den > 0.0 ? num / den : 0.0;
-                if (delta > delta_expl) {
-                    nfi_new = std::max(n, n_in + 1);
-                    break;
-                }
-            }
-        }
-        *delta_out = delta;
-        *n_fi = nfi_new;
-        return SNAPMD_OK;
+    // Large systems: the same sweep driven from the host with the batched kernels.
+    return host_sweep(ctx, potC, fp, sdc, lang, lang->T_sys[0], lang->noise_id_sys[0], N, box, L, n_in, n_fi, init,
+                      (size_t)N, q_cur, p_cur, q_prev, sw.jq, sw.jp, SN3 / 3, (size_t)N, delta_expl, delta_out, st,
+                      stream);
+}
+
+
+// Largest chunk of (system, slab) entries propagated in one launch sequence by the
+// multi-system path (bounds the neighbour-list and SNAP workspace, ~21 KB per atom).
+constexpr long kMultiChunkAtoms = 1L << 20;
+
+// Several systems, each with its own window [n_in[r], n_fi[r]] (n_in[r] = n_fi[r]: none),
+// states in the slot layout [slot][3][N_tot].  The fine and coarse propagations of every
+// (system, slab) entry of every window run as ragged batches (chunks of at most
+// kMultiChunkAtoms atoms, fine then coarse on the caller's stream); the jumps land in the
+// slot layout; the sweeps of all systems that the LDS-resident sweep takes run in one
+// launch (one workgroup each), the others from the host one system after the other.
+int parareal_multi(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, const snapmd_batch *batch,
+                   const snapmd_langevin *lang, int32_t L, const int32_t *n_in, int32_t *n_fi, int32_t n_slots,
+                   double *q_prev, double *p_prev, double *q_cur, double *p_cur, double delta_expl,
+                   double *delta_out, hipStream_t st, void *stream) {
+    int rc;
+    const int R = batch->n_sys;
+    const int *off = batch->offset;
+    const int Nt = off[R];
+    const bool init = q_prev == nullptr;
+    const bool bbk = lang->scheme == SNAPMD_SCHEME_BBK;
+    const bool csnap = ctx->coarse_snap_on;
+    const int potC = csnap ? SNAPMD_POT_FS_SNAP : SNAPMD_POT_FS;
+    const double skin = kSweepSkin;
+    double mh = INFINITY;
+    for (int r = 0; r < R; ++r)
+        for (int a = 0; a < 3; ++a) mh = std::min(mh, 0.5 * batch->box[3 * r + a]);
+    FsParams fp;
+    if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
+    if (!(std::max(fp.d, fp.c) + 2.0 * skin < mh))
+        return fail(ctx, SNAPMD_EINVAL, "FS cutoff + %g A must be < half the smallest box edge", 2.0 * skin);
+    SnapDev sdc;
+    if (csnap) {
+        snapmd_snap cs = ctx->coarse_snap;
+        cs.beta = ctx->coarse_beta.data();
+        if (snap && !init && snap->twojmax == cs.twojmax)
+            return fail(ctx, SNAPMD_EINVAL, "the coarse SNAP needs a twojmax other than the fine one (%d)",
+                        cs.twojmax);
+        if ((rc = prepare_snap(ctx, &cs, mh, sdc, st))) return rc;
     }
+    for (int r = 0; r < R; ++r) delta_out[r] = 0.0;
+    std::vector<int> act;
+    for (int r = 0; r < R; ++r)
+        if (n_fi[r] > n_in[r] && off[r + 1] > off[r]) act.push_back(r);
+    if (act.empty()) return SNAPMD_OK;
+    const double c1 = std::exp(-lang->gamma * lang->dt);
+    // which sweep each system takes; every buffer is sized before the first launch (a
+    // reallocation drops the captured launch sequences)
+    std::vector<int> dev_sys, host_sys;
+    int max_host = 0;
+    for (int r : act) {
+        const int Nr = off[r + 1] - off[r];
+        if (!bbk && !csnap && sweep_fits_lds(Nr)) {
+            dev_sys.push_back(r);
+        } else {
+            host_sys.push_back(r);
+            max_host = std::max(max_host, Nr);
+        }
+    }
+    const size_t ab = sweep_args_bytes();
+    if ((rc = ensure(ctx, ctx->m_out, 8 * dev_sys.size())) || (rc = ensure(ctx, ctx->m_tab, ab * dev_sys.size())) ||
+        (rc = ensure(ctx, ctx->sw_x, 3 * (size_t)max_host)) || (rc = ensure(ctx, ctx->sw_p, 3 * (size_t)max_host)) ||
+        (rc = ensure(ctx, ctx->sw_out, 8)))
+        return rc;
+    if (!ctx->h_out) HIPCHK(hipHostMalloc((void **)&ctx->h_out, 16 * sizeof(double), hipHostMallocDefault));
+    double *jq = nullptr, *jp = nullptr;
+    if (!init) {
+        // prev := cur on every window
+        std::vector<int2> win(R);
+        for (int r = 0; r < R; ++r) win[r] = make_int2(n_in[r], n_fi[r]);
+        if ((rc = ensure(ctx, ctx->m_off, (size_t)R + 1)) || (rc = ensure(ctx, ctx->m_win, (size_t)R))) return rc;
+        const size_t SS = (size_t)n_slots * 3 * Nt;
+        if ((rc = ensure(ctx, ctx->m_jq, SS)) || (rc = ensure(ctx, ctx->m_jp, SS))) return rc;
+        if ((rc = upload(ctx, ctx->m_off.p, off, (size_t)R + 1, st)) ||
+            (rc = upload(ctx, ctx->m_win.p, win.data(), (size_t)R, st)))
+            return rc;
+        launch_copy_windows(n_slots, Nt, R, ctx->m_off.p, ctx->m_win.p, q_cur, p_cur, q_prev, p_prev, st);
+        jq = ctx->m_jq.p;
+        jp = ctx->m_jp.p;
+        // entries (system, slab), cut into chunks
+        struct Ent { int r, n; };
+        std::vector<Ent> ent;
+        for (int r : act)
+            for (int n = n_in[r]; n < n_fi[r]; ++n) ent.push_back({r, n});
+        std::vector<size_t> cut{0};
+        long acc = 0, maxc = 0;
+        for (size_t e = 0; e < ent.size(); ++e) {
+            const long na = off[ent[e].r + 1] - off[ent[e].r];
+            if (acc > 0 && acc + na > kMultiChunkAtoms) {
+                maxc = std::max(maxc, acc);
+                cut.push_back(e);
+                acc = 0;
+            }
+            acc += na;
+        }
+        maxc = std::max(maxc, acc);
+        cut.push_back(ent.size());
+        const size_t M3 = 3 * (size_t)maxc;
+        if ((rc = ensure(ctx, ctx->pr_xf, M3)) || (rc = ensure(ctx, ctx->pr_pf, M3)) ||
+            (rc = ensure(ctx, ctx->pr_xc, M3)) || (rc = ensure(ctx, ctx->pr_pc, M3)) ||
+            (rc = ensure(ctx, ctx->m_src, ent.size())))
+            return rc;
+        if ((rc = ensure_atoms(ctx, (size_t)maxc)) || (rc = ensure_atoms_coarse(ctx, (size_t)maxc, csnap))) return rc;
+        for (size_t c = 0; c + 1 < cut.size(); ++c) {
+            const int ne = (int)(cut[c + 1] - cut[c]);
+            std::vector<int> boff(ne + 1, 0);
+            std::vector<double> boxes(3 * (size_t)ne), T(ne);
+            std::vector<int64_t> step0(ne);
+            std::vector<int> nid(ne);
+            std::vector<int2> src(ne);
+            for (int k = 0; k < ne; ++k) {
+                const Ent &e = ent[cut[c] + k];
+                boff[k + 1] = boff[k] + (off[e.r + 1] - off[e.r]);
+                for (int a = 0; a < 3; ++a) boxes[3 * k + a] = batch->box[3 * e.r + a];
+                T[k] = lang->T_sys[e.r];
+                step0[k] = (int64_t)e.n * L;
+                nid[k] = lang->noise_id_sys[e.r];
+                src[k] = make_int2(e.n, off[e.r]);
+            }
+            const int Nc = boff[ne];
+            snapmd_batch sb{ne, boff.data(), boxes.data()};
+            BatchDev bd;
+            double mh2;
+            SnapDev sd;
+            LangevinDev ldv;
+            if ((rc = prepare_batch(ctx, &sb, bd, mh2, st)) || (rc = prepare_snap(ctx, snap, mh2, sd, st)) ||
+                (rc = prepare_langevin(ctx, lang, ne, T, step0, nid, ldv, st)))
+                return rc;
+            int2 *dsrc = ctx->m_src.p + cut[c];
+            if ((rc = upload(ctx, dsrc, src.data(), (size_t)ne, st))) return rc;
+            launch_entries_to_batch(Nc, ne, bd.off, dsrc, Nt, q_prev, ctx->pr_xf.p, st);
+            launch_entries_to_batch(Nc, ne, bd.off, dsrc, Nt, p_prev, ctx->pr_pf.p, st);
+            HIPCHK(hipMemcpyAsync(ctx->pr_xc.p, ctx->pr_xf.p, 3 * (size_t)Nc * sizeof(double), hipMemcpyDeviceToDevice,
+                                  st));
+            HIPCHK(hipMemcpyAsync(ctx->pr_pc.p, ctx->pr_pf.p, 3 * (size_t)Nc * sizeof(double), hipMemcpyDeviceToDevice,
+                                  st));
+            if ((rc = run_langevin_graph(ctx, ctx->w, ctx->d_f, SNAPMD_POT_FS_SNAP, bd, fp, sd, ldv, L, ctx->pr_xf.p,
+                                         ctx->pr_pf.p, st)) ||
+                (rc = run_langevin_graph(ctx, ctx->wc, ctx->d_fc, potC, bd, fp, sdc, ldv, L, ctx->pr_xc.p,
+                                         ctx->pr_pc.p, st)))
+                return rc;
+            launch_batch_jumps_to_slots(Nc, ne, bd.off, dsrc, Nt, ctx->pr_xf.p, ctx->pr_xc.p, jq, st);
+            launch_batch_jumps_to_slots(Nc, ne, bd.off, dsrc, Nt, ctx->pr_pf.p, ctx->pr_pc.p, jp, st);
+            if ((rc = check_launch(ctx))) return rc;
+        }
+    }
+    // sweeps: the LDS-resident kernel for every system it takes, in one launch
+    if (!dev_sys.empty()) {
+        const int nd = (int)dev_sys.size();
+        std::vector<unsigned char> tab(ab * nd);
+        std::vector<double> out0(8 * (size_t)nd);
+        int maxN = 0;
+        for (int k = 0; k < nd; ++k) {
+            const int r = dev_sys[k], Nr = off[r + 1] - off[r];
+            const double *box = batch->box + 3 * r;
+            maxN = std::max(maxN, Nr);
+            SweepLaunch sw{};
+            sw.N = Nr;
+            for (int a = 0; a < 3; ++a) sw.box[a] = box[a];
+            sw.fp = fp;
+            sw.skin = skin;
+            sw.dt = lang->dt;
+            sw.c1 = c1;
+            sw.mass = lang->mass;
+            sw.sig = std::sqrt((1.0 - c1 * c1) * lang->mass * kKB * lang->T_sys[r] / kMVV2E);
+            sw.seed = lang->seed;
+            sw.noise_id = (uint64_t)lang->noise_id_sys[r];
+            sw.L = L;
+            sw.n_in = n_in[r];
+            sw.n_fi = n_fi[r];
+            sw.mode = init ? 0 : 1;
+            sw.n_win = n_in[r];
+            int nc[3];
+            for (int a = 0; a < 3; ++a) nc[a] = (int)std::floor(box[a] / (std::max(fp.d, fp.c) + skin));
+            while ((long)nc[0] * nc[1] * nc[2] > 512) *std::max_element(nc, nc + 3) -= 1;
+            if (nc[0] < 3 || nc[1] < 3 || nc[2] < 3) nc[0] = nc[1] = nc[2] = 0;
+            sw.ncx = nc[0];
+            sw.ncy = nc[1];
+            sw.ncz = nc[2];
+            sw.delta_expl = delta_expl;
+            sw.q_cur = q_cur + off[r];
+            sw.p_cur = p_cur + off[r];
+            sw.q_prev = init ? nullptr : q_prev + off[r];
+            sw.p_prev = init ? nullptr : p_prev + off[r];
+            sw.jq = init ? nullptr : jq + (size_t)n_in[r] * 3 * Nt + off[r];
+            sw.jp = init ? nullptr : jp + (size_t)n_in[r] * 3 * Nt + off[r];
+            sw.out = ctx->m_out.p + 8 * (size_t)k;
+            sw.noise = nullptr;
+            fill_sweep_args(sw, (size_t)Nt, (size_t)Nt, 3 * (size_t)Nt, tab.data() + ab * k);
+            const double o[8] = {0.0, (double)n_fi[r], -1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            std::copy(o, o + 8, out0.begin() + 8 * k);
+        }
+        if ((rc = upload(ctx, ctx->m_tab.p, tab.data(), tab.size(), st)) ||
+            (rc = upload(ctx, ctx->m_out.p, out0.data(), out0.size(), st)))
+            return rc;
+        launch_coarse_sweep_multi(ctx->m_tab.p, nd, maxN, st);
+        if ((rc = check_launch(ctx))) return rc;
+        HIPCHK(hipMemcpyAsync(out0.data(), ctx->m_out.p, out0.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        if ((rc = snapmd_sync(ctx, stream))) return rc;
+        for (int k = 0; k < nd; ++k) {
+            const int r = dev_sys[k];
+            const double *o = out0.data() + 8 * k;
+            if (o[3] != 0.0)
+                return fail(ctx, SNAPMD_EOVERFLOW, "an atom of the coarse sweep of system %d has more than its list "
+                                                   "capacity of neighbours", r);
+            if (o[2] >= 0.0)
+                return fail(ctx, SNAPMD_ENONFINITE, "state of system %d became non-finite in slab %d", r, (int)o[2]);
+            delta_out[r] = o[0];
+            n_fi[r] = (int32_t)o[1];
+        }
+    }
+    for (int r : host_sys) {
+        const int Nr = off[r + 1] - off[r];
+        const size_t jb = (size_t)n_in[r] * 3 * Nt + off[r];
+        if ((rc = host_sweep(ctx, potC, fp, sdc, lang, lang->T_sys[r], lang->noise_id_sys[r], Nr, batch->box + 3 * r, L,
+                             n_in[r], n_fi + r, init, (size_t)Nt, q_cur + off[r], p_cur + off[r],
+                             init ? nullptr : q_prev + off[r], init ? nullptr : jq + jb, init ? nullptr : jp + jb,
+                             (size_t)Nt, 3 * (size_t)Nt, delta_expl, delta_out + r, st, stream)))
+            return fail(ctx, rc, "system %d: %s", r, std::string(ctx->err).c_str());
+    }
+    return SNAPMD_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+int snapmd_create(snapmd_ctx **out, int hip_device) {
+    if (!out) return SNAPMD_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return SNAPMD_EINVAL;
+    if (hipSetDevice(hip_device) != hipSuccess) return SNAPMD_EHIP;
+    snapmd_ctx *ctx = new snapmd_ctx();
+    ctx->device = hip_device;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
+            ctx->n_cus = cus;
+    }
+    adjoint_init_attributes();
+    sweep_init_attributes();
+    neigh_init_attributes();
+    if (dalloc(ctx, &ctx->w.status, 1) != SNAPMD_OK || hipMemset(ctx->w.status, 0, sizeof(int)) != hipSuccess ||
+        dalloc(ctx, &ctx->w.flag, 1) != SNAPMD_OK || hipMemset(ctx->w.flag, 0, sizeof(int)) != hipSuccess) {
+        snapmd_destroy(ctx);
+        return SNAPMD_ENOMEM;
+    }
+    *out = ctx;
+    return SNAPMD_OK;
+}
+
+void snapmd_destroy(snapmd_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    for (void *p : ctx->allocs) (void)hipFree(p);
+    if (ctx->h_out) (void)hipHostFree(ctx->h_out);
+    drop_graphs(ctx);
+    for (hipStream_t c : ctx->cap_stream)
+        if (c) (void)hipStreamDestroy(c);
+    if (ctx->sweep_stream) (void)hipStreamDestroy(ctx->sweep_stream);
+    if (ctx->coarse_stream) (void)hipStreamDestroy(ctx->coarse_stream);
+    for (hipEvent_t e : ctx->pipe_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+const char *snapmd_last_error(const snapmd_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int snapmd_sync(snapmd_ctx *ctx, void *stream) {
+    if (!ctx) return SNAPMD_EINVAL;
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    int st = 0;
+    HIPCHK(hipMemcpy(&st, ctx->w.status, sizeof(int), hipMemcpyDeviceToHost));
+    if (st) {
+        HIPCHK(hipMemset(ctx->w.status, 0, sizeof(int)));
+        if (st & 1) return fail(ctx, SNAPMD_EOVERFLOW, "an atom has more than %d neighbours", kMaxNeigh);
+        return fail(ctx, SNAPMD_EINVAL, "inconsistent neighbour list (status %d)", st);
+    }
+    return SNAPMD_OK;
+}
+
+int snap_forces(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *batch, const double *x, double *f,
+                double *e_atom, uint32_t flags, void *stream) {
+    if (!ctx) return SNAPMD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!x || !f) return fail(ctx, SNAPMD_EINVAL, "x and f must be device pointers");
+    BatchDev bd;
+    double mh;
+    SnapDev sd;
+    int rc;
+    if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
+    if ((rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
+    if (bd.N == 0) return SNAPMD_OK;
+    if ((rc = neighbors(ctx, ctx->w, bd, x, snap->rcut, true, st))) return rc;
+    launch_snap(sd.J, bd, x, sd, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st, &ctx->prof);
+    return check_launch(ctx);
+}
+
+int eam_forces(snapmd_ctx *ctx, const snapmd_fs *fs, const snapmd_batch *batch, const double *x, double *f,
+               double *e_atom, uint32_t flags, void *stream) {
+    if (!ctx) return SNAPMD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!x || !f) return fail(ctx, SNAPMD_EINVAL, "x and f must be device pointers");
+    BatchDev bd;
+    double mh;
+    FsParams fp;
+    int rc;
+    if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
+    if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
+    if (bd.N == 0) return SNAPMD_OK;
+    if ((rc = neighbors(ctx, ctx->w, bd, x, std::max(fp.d, fp.c), true, st))) return rc;
+    launch_fs(bd, x, fp, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st);
+    return check_launch(ctx);
+}
+
+int langevin_steps(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, const snapmd_fs *fs,
+                   const snapmd_batch *batch, const snapmd_langevin *lang, int32_t n_steps, double *x, double *p,
+                   double *f_out, void *stream) {
+    if (!ctx) return SNAPMD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (potential != SNAPMD_POT_FS && potential != SNAPMD_POT_FS_SNAP)
+        return fail(ctx, SNAPMD_EINVAL, "potential must be SNAPMD_POT_FS or SNAPMD_POT_FS_SNAP");
+    if (!x || !p) return fail(ctx, SNAPMD_EINVAL, "x and p must be device pointers");
+    if (n_steps < 0) return fail(ctx, SNAPMD_EINVAL, "n_steps must be >= 0");
+    int rc;
+    if ((rc = check_lang(ctx, lang))) return rc;
+    BatchDev bd;
+    double mh;
+    FsParams fp;
+    SnapDev sd;
+    if ((rc = prepare_batch(ctx, batch, bd, mh, st))) return rc;
+    if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
+    if (potential == SNAPMD_POT_FS_SNAP && (rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
+    const int S = bd.n_sys;
+    std::vector<double> T(lang->T_sys, lang->T_sys + S);
+    std::vector<int64_t> step0(lang->step0_sys, lang->step0_sys + S);
+    std::vector<int> nid(lang->noise_id_sys, lang->noise_id_sys + S);
+    for (int s = 0; s < S; ++s) {
+        if (!(T[s] >= 0.0)) return fail(ctx, SNAPMD_EINVAL, "T_sys[%d] must be >= 0", s);
+        if (nid[s] < 0) return fail(ctx, SNAPMD_EINVAL, "noise_id_sys[%d] must be >= 0", s);
+    }
+    LangevinDev ld;
+    if ((rc = prepare_langevin(ctx, lang, S, T, step0, nid, ld, st))) return rc;
+    if (bd.N == 0) return SNAPMD_OK;
+    if ((rc = run_langevin_graph(ctx, ctx->w, ctx->d_f, potential, bd, fp, sd, ld, n_steps, x, p, st))) return rc;
+    if (f_out)
+        HIPCHK(hipMemcpyAsync(f_out, ctx->d_f, 3 * (size_t)bd.N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return check_launch(ctx);
+}
+
+int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, const snapmd_batch *batch,
+                     const snapmd_langevin *lang, int32_t L, const int32_t *n_in, int32_t *n_fi, int32_t n_slots,
+                     double *q_prev, double *p_prev, double *q_cur, double *p_cur, double delta_expl,
+                     double *delta_out, void *stream) {
+    if (!ctx) return SNAPMD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc;
+    if ((rc = check_lang(ctx, lang))) return rc;
+    if (!batch || batch->n_sys < 1 || !batch->offset || !batch->box)
+        return fail(ctx, SNAPMD_EINVAL, "parareal_iterate needs a batch of at least one system");
+    if (!n_in || !n_fi || !delta_out) return fail(ctx, SNAPMD_EINVAL, "n_in, n_fi and delta_out must be host arrays");
+    if (L < 1) return fail(ctx, SNAPMD_EINVAL, "L must be >= 1");
+    if (!q_cur || !p_cur) return fail(ctx, SNAPMD_EINVAL, "q_cur and p_cur must be device pointers");
+    if (q_prev && !p_prev) return fail(ctx, SNAPMD_EINVAL, "p_prev must be set with q_prev");
+    if (!(delta_expl >= 0.0)) return fail(ctx, SNAPMD_EINVAL, "delta_expl must be >= 0");
+    const int R = batch->n_sys;
+    if (batch->offset[0] != 0) return fail(ctx, SNAPMD_EINVAL, "batch.offset[0] must be 0");
+    for (int r = 0; r < R; ++r) {
+        if (batch->offset[r + 1] < batch->offset[r])
+            return fail(ctx, SNAPMD_EINVAL, "batch.offset must be nondecreasing (system %d)", r);
+        for (int a = 0; a < 3; ++a)
+            if (!(batch->box[3 * r + a] > 0.0) || !std::isfinite(batch->box[3 * r + a]))
+                return fail(ctx, SNAPMD_EINVAL, "box edge %d of system %d must be finite and > 0", a, r);
+        if (!(lang->T_sys[r] >= 0.0) || lang->noise_id_sys[r] < 0)
+            return fail(ctx, SNAPMD_EINVAL, "need T_sys[%d] >= 0 and noise_id_sys[%d] >= 0", r, r);
+        // a window of one system must lie in the state arrays; in a batch of several an
+        // empty window (n_in = n_fi) leaves the system out
+        if (n_in[r] < 0 || n_fi[r] < n_in[r] || (R == 1 && n_fi[r] == n_in[r]) || n_fi[r] > n_slots - 1)
+            return fail(ctx, SNAPMD_EINVAL, "system %d: need 0 <= n_in < n_fi <= n_slots - 1 (got %d, %d, %d slots)", r,
+                        n_in[r], n_fi[r], n_slots);
+    }
+    if (batch->offset[R] < 1) return fail(ctx, SNAPMD_EINVAL, "the batch needs at least one atom");
+    if (R == 1)
+        return parareal_one(ctx, snap, fs, batch, lang, L, n_in[0], n_fi, q_prev, p_prev, q_cur, p_cur, delta_expl,
+                            delta_out, st, stream);
+    return parareal_multi(ctx, snap, fs, batch, lang, L, n_in, n_fi, n_slots, q_prev, p_prev, q_cur, p_cur, delta_expl,
+                          delta_out, st, stream);
 }
 
 int snapmd_ws_sites(snapmd_ctx *ctx, const snapmd_batch *batch, const double *x, double a, int32_t *site,

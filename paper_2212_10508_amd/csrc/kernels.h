@@ -174,8 +174,20 @@ void sweep_init_attributes();
 void neigh_init_attributes();
 bool sweep_fits_lds(int N);
 int sweep_mc_workgroups(int N, int want = 0);
-void launch_slab_end(int N, int mode, size_t SN, size_t s, double *xs, double *ps, const double *jq, const double *jp,
-                     const double *qprev_next, double *qcur_next, double *pcur_next, double *part, hipStream_t st);
+void launch_slab_end(int N, int mode, size_t jsa, size_t jss, size_t s, double *xs, double *ps, const double *jq,
+                     const double *jp, size_t ld, const double *qprev_next, double *qcur_next, double *pcur_next,
+                     double *part, hipStream_t st);
+// batches of systems with windows of their own (slot layout [slot][3][ld])
+void launch_copy_windows(int n_slots, int ld, int n_sys, const int *off, const int2 *win, const double *q,
+                         const double *p, double *qd, double *pd, hipStream_t st);
+void launch_entries_to_batch(int Nc, int n_ent, const int *off, const int2 *src, int ld, const double *state,
+                             double *out, hipStream_t st);
+void launch_batch_jumps_to_slots(int Nc, int n_ent, const int *off, const int2 *src, int ld, const double *f,
+                                 const double *c, double *jump, hipStream_t st);
+// the sweep arguments of one system of a batch, in the layout the multi-system sweep reads
+size_t sweep_args_bytes();
+void fill_sweep_args(const SweepLaunch &s, size_t ld, size_t jsa, size_t jss, void *dst);
+void launch_coarse_sweep_multi(const void *tab, int n, int max_atoms, hipStream_t st);
 void launch_noise_table(int S, int L, int N, int n_in, uint64_t seed, uint64_t noise_id, double *noise,
                         hipStream_t st);
 

@@ -1167,9 +1167,10 @@ void launch_batch_jumps_to_slots(int Nc, int n_ent, const int *off, const int2 *
 
 // LDS sweeps of n systems at once (tab: device [n] arguments, one workgroup each; every
 // system fits the LDS-resident sweep, max_atoms the largest)
-void launch_coarse_sweep_multi(const SweepArgs *tab, int n, int max_atoms, hipStream_t st) {
+void launch_coarse_sweep_multi(const void *tab, int n, int max_atoms, hipStream_t st) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_coarse_sweep_lds_multi, dim3(n), dim3(kSweepThreads), sweep_lds_bytes(max_atoms), st, tab);
+    hipLaunchKernelGGL(k_coarse_sweep_lds_multi, dim3(n), dim3(kSweepThreads), sweep_lds_bytes(max_atoms), st,
+                       (const SweepArgs *)tab);
 }
 
 bool sweep_fits_lds(int N) { return N <= kSweepLdsMaxAtoms && sweep_lds_bytes(N) <= 160 * 1024; }
@@ -1200,7 +1201,7 @@ void launch_jumps(size_t n, double *a, const double *b, hipStream_t st) {
     hipLaunchKernelGGL(k_jumps, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, b);
 }
 
-void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
+static SweepArgs sweep_args(const SweepLaunch &s) {
     SweepArgs a;
     a.N = s.N;
     a.Lx = s.box[0];
@@ -1239,10 +1240,26 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     a.p_prev = s.p_prev;
     a.jq = s.jq;
     a.jp = s.jp;
+    // one system: slots [slot][3][N], jumps [3][S N]
     a.ld = (size_t)s.N;
     a.jsa = (size_t)(s.n_fi - s.n_in) * s.N;
     a.jss = (size_t)s.N;
     a.out = s.out;
+    return a;
+}
+
+size_t sweep_args_bytes() { return sizeof(SweepArgs); }
+
+void fill_sweep_args(const SweepLaunch &s, size_t ld, size_t jsa, size_t jss, void *dst) {
+    SweepArgs a = sweep_args(s);
+    a.ld = ld;
+    a.jsa = jsa;
+    a.jss = jss;
+    *(SweepArgs *)dst = a;
+}
+
+void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
+    const SweepArgs a = sweep_args(s);
     if (s.K > 0) {
         // at least 81 KB of LDS so that no two of the workgroups share a CU
         const size_t lds = std::max<size_t>(sweep_mc_lds_bytes(s.N, s.A), 81 * 1024);
@@ -1258,6 +1275,8 @@ void sweep_init_attributes() {
                               160 * 1024);
     (void)hipFuncSetAttribute((const void *)k_coarse_sweep_mc, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024 - kMcStaticLds);
+    (void)hipFuncSetAttribute((const void *)k_coarse_sweep_lds_multi, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
 }
 
 }  // namespace snapmd

@@ -76,7 +76,7 @@ def lib():
                                  C.POINTER(Langevin), i32, P, P, P, P]
     L.langevin_steps.restype = C.c_int
     L.parareal_iterate.argtypes = [P, C.POINTER(Snap), C.POINTER(Fs), C.POINTER(Batch), C.POINTER(Langevin),
-                                   i32, i32, C.POINTER(i32), P, P, P, P, d, C.POINTER(d), P]
+                                   i32, C.POINTER(i32), C.POINTER(i32), i32, P, P, P, P, d, C.POINTER(d), P]
     L.parareal_iterate.restype = C.c_int
     L.snap_beta_grad.argtypes = [P, C.POINTER(Snap), C.POINTER(Batch), P, P, P, P, P]
     L.snap_beta_grad.restype = C.c_int
@@ -173,6 +173,20 @@ def make_langevin(keep, n_sys, dt, gamma, mass, T, seed, step0, noise_id, scheme
 # ----------------------------------------------------------------------------
 # context and entry points
 # ----------------------------------------------------------------------------
+def check_windows(n_in, n_fi, n_slots, n_sys):
+    """Windows of parareal_iterate: 0 <= n_in <= n_fi <= n_slots - 1 per system (the state
+    arrays hold slots 0 .. n_slots - 1), non-empty for a single system."""
+    n_in = np.asarray(n_in).reshape(-1)
+    n_fi = np.asarray(n_fi).reshape(-1)
+    if n_in.shape != (n_sys,) or n_fi.shape != (n_sys,):
+        raise ValueError("n_in and n_fi need one entry per system (%d)" % n_sys)
+    for r in range(n_sys):
+        a, b = int(n_in[r]), int(n_fi[r])
+        if a < 0 or b < a or b > n_slots - 1 or (n_sys == 1 and a == b):
+            raise ValueError("system %d: need 0 <= n_in < n_fi <= n_slots - 1 (got %d, %d with %d slots)"
+                             % (r, a, b, n_slots))
+
+
 class Context:
     """A snapmd context on one HIP device (owns the library workspace)."""
 
@@ -257,24 +271,47 @@ class Context:
     def parareal_iterate(self, q_prev, p_prev, q_cur, p_cur, box, L, n_in, n_fi, delta_expl, *, dt, gamma,
                          mass, T, seed, noise_id, fs, J=None, beta=None, rcut=4.73, rfac0=0.99363, rmin0=0.0,
                          scheme="baoab", cT=(1.0, 1.0), stream=None):
-        """Returns (delta, n_fi_after).  q_prev = p_prev = None: window initialisation."""
+        """One system (states [n_slots, 3, N]).  Returns (delta, n_fi_after).
+        q_prev = p_prev = None: window initialisation."""
+        N = q_cur.shape[2]
+        d, nf = self.parareal_iterate_batch(q_prev, p_prev, q_cur, p_cur, [0, N], [box], L, [n_in], [n_fi],
+                                            delta_expl, dt=dt, gamma=gamma, mass=mass, T=[T], seed=seed,
+                                            noise_id=[noise_id], fs=fs, J=J, beta=beta, rcut=rcut, rfac0=rfac0,
+                                            rmin0=rmin0, scheme=scheme, cT=cT, stream=stream)
+        return float(d[0]), int(nf[0])
+
+    def parareal_iterate_batch(self, q_prev, p_prev, q_cur, p_cur, offset, box, L, n_in, n_fi, delta_expl, *, dt,
+                               gamma, mass, T, seed, noise_id, fs, J=None, beta=None, rcut=4.73, rfac0=0.99363,
+                               rmin0=0.0, scheme="baoab", cT=(1.0, 1.0), stream=None):
+        """Every system r of the batch (offset, box as for langevin_steps) on its own window
+        [n_in[r], n_fi[r]]; states [n_slots, 3, offset[-1]] (system r in columns
+        offset[r]:offset[r+1]).  T and noise_id per system (or one value for all).
+        Returns (delta, n_fi_after) as numpy arrays.  q_prev = p_prev = None: window
+        initialisation."""
         nslots, three, N = q_cur.shape
+        R = len(offset) - 1
+        n_in = np.asarray(n_in, dtype=np.int32).reshape(-1)
+        n_fi = np.asarray(n_fi, dtype=np.int32).reshape(-1)
+        check_windows(n_in, n_fi, nslots, R)
+        if int(offset[-1]) != N:
+            raise ValueError("offset[-1] = %d but the states hold %d atoms" % (int(offset[-1]), N))
         k = _Keep()
-        b = make_batch(k, [0, N], box)
+        b = make_batch(k, offset, box)
         s = make_snap(k, J, beta, rcut, rfac0, rmin0) if beta is not None else None
         p_fs = make_fs(fs)
-        lg = make_langevin(k, 1, dt, gamma, mass, T, seed, 0, noise_id, scheme, cT)
-        nfi = C.c_int32(int(n_fi))
-        delta = C.c_double(0.0)
+        lg = make_langevin(k, R, dt, gamma, mass, T, seed, 0, noise_id, scheme, cT)
+        nin_c = k.arr(n_in, np.int32, C.c_int32)
+        nfi = np.ascontiguousarray(n_fi.copy())
+        delta = np.zeros(R, np.float64)
         shape = (nslots, 3, N)
-        self._check(lib().parareal_iterate(self.h, C.byref(s) if s is not None else None, C.byref(p_fs),
-                                           C.byref(b), C.byref(lg), int(L),
-                                           int(n_in), C.byref(nfi), _dev(q_prev, "q_prev", shape) if q_prev is not None else None,
-                                           _dev(p_prev, "p_prev", shape) if p_prev is not None else None,
-                                           _dev(q_cur, "q_cur", shape),
-                                           _dev(p_cur, "p_cur", shape), float(delta_expl), C.byref(delta),
-                                           _stream(stream)))
-        return delta.value, nfi.value
+        self._check(lib().parareal_iterate(
+            self.h, C.byref(s) if s is not None else None, C.byref(p_fs), C.byref(b), C.byref(lg), int(L), nin_c,
+            nfi.ctypes.data_as(C.POINTER(C.c_int32)), int(nslots),
+            _dev(q_prev, "q_prev", shape) if q_prev is not None else None,
+            _dev(p_prev, "p_prev", shape) if p_prev is not None else None,
+            _dev(q_cur, "q_cur", shape), _dev(p_cur, "p_cur", shape), float(delta_expl),
+            delta.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
+        return delta, nfi
 
     # -- measurement ---------------------------------------------------------
     PROF_DEDR, PROF_ADJOINT, PROF_DENSITY, PROF_NEIGH = 0, 1, 2, 3

@@ -331,3 +331,107 @@ def test_strategy_one_snap_coarse_matches_oracle(S):
             assert np.abs(q0[m].cpu().numpy() - iters[0][m][0]).max() < QTOL
     finally:
         ctx.set_coarse_snap(None)
+
+
+def _replicas(sizes=(4, 6, 8), J=2, seed=30):
+    xs, ps, boxes = [], [], []
+    for k, nc in enumerate(sizes):
+        x, box = W.bcc_sia(nc, jitter=0.05, seed=seed + k)
+        xs.append(x)
+        ps.append(W.maxwell_momenta(x.shape[1], 900.0 + 150.0 * k, seed=seed + k))
+        boxes.append(box)
+    off = np.concatenate([[0], np.cumsum([x.shape[1] for x in xs])]).astype(np.int32)
+    return xs, ps, boxes, off
+
+
+@pytest.mark.parametrize("scheme", ["baoab", "bbk"])
+def test_batch_of_replicas_matches_oracle_per_replica(S, scheme):
+    """Adaptive parareal for a ragged batch of three replicas (129, 433, 1025 atoms; own
+    temperatures and noise streams), every replica on windows of its own, against the
+    oracle's literal adaptive driver run replica by replica: the same window logs, the
+    same iteration counts and the same converged states.  BAOAB sweeps run in one launch
+    (one workgroup per replica); BBK sweeps run from the host replica by replica."""
+    from paper_2212_10508_amd import parareal as PR
+    J, N, L = 2, 5, 4
+    sizes = (4, 6, 8) if scheme == "baoab" else (4, 6)
+    xs, ps, boxes, off = _replicas(sizes, J=J)
+    R = len(xs)
+    beta = W.snap_beta(J, seed=31, scale=2e-2)
+    Ts = [900.0 + 150.0 * k for k in range(R)]
+    nids = [3 + 2 * k for k in range(R)]
+    cT = (3.0, 1.0)
+    conv, expl = 1e-12, 1e-7
+    ctx = S.context()
+    logs = [[] for _ in range(R)]
+    q, pq, nad, kc = PR.adaptive_parareal_batch(
+        ctx, dev(np.concatenate(xs, axis=1)), dev(np.concatenate(ps, axis=1)), off, np.array(boxes), N, L, conv,
+        expl, dt=1e-3, gamma=1.0, mass=W.MASS_W, T=Ts, seed=77, noise_id=nids, fs=W.FS_W, J=J, beta=beta,
+        scheme=scheme, cT=cT, logs=logs)
+    qh = q.cpu().numpy()
+    snap = dict(J=J, beta=beta, rcut=W.SNAP_RCUT, rfac0=W.SNAP_RFAC0, rmin0=0.0)
+    shortened = 0
+    for r in range(R):
+        print("replica %d (%d atoms): windows %s" % (r, xs[r].shape[1],
+                                                     [(a["n_in"], a["n_fi"], a["n_fi_after"]) for a in logs[r]]),
+              flush=True)
+        prop = OPR.Propagators(box=boxes[r], L=L, dt=1e-3, gamma=1.0, mass=W.MASS_W, T=Ts[r], seed=77,
+                               noise_id=nids[r], snap=snap, fs=W.FS_W, scheme=scheme, cT=cT)
+        olog = []
+        tref, nad_ref, kc_ref = OPR.parareal_adaptive(prop, xs[r], ps[r], N, conv, expl, log=olog)
+        assert (nad[r], kc[r]) == (nad_ref, kc_ref), r
+        assert [(a["n_in"], a["n_fi"], a["n_fi_after"]) for a in logs[r]] == \
+               [(a["n_in"], a["n_fi"], a["n_fi_after"]) for a in olog], r
+        for n in range(N + 1):
+            assert np.abs(qh[n][:, off[r]:off[r + 1]] - tref[n][0]).max() < QTOL, (r, n)
+        shortened += any(a["n_fi_after"] < a["n_fi"] for a in olog)
+    assert shortened >= 1     # the threshold really shortened some window
+
+
+def test_batch_iteration_leaves_other_windows_alone(S):
+    """A corrected iteration of a batch touches each system's own window only: slots
+    outside [n_in_r, n_fi_r] of q_prev and q_cur keep their contents, an empty window
+    leaves its system out (delta 0, n_fi unchanged), and each system's result equals the
+    single-system call on its own states."""
+    J, N, L = 2, 4, 3
+    xs, ps, boxes, off = _replicas((4, 4, 6), J=J, seed=40)
+    R = len(xs)
+    beta = W.snap_beta(J, seed=41, scale=2e-2)
+    kw = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, seed=12, fs=W.FS_W, J=J, beta=beta)
+    kwc = {k: v for k, v in kw.items() if k not in ("J", "beta")}
+    Ts, nids = [1000.0, 800.0, 1200.0], [0, 1, 2]
+    n_in, n_fi = [0, 1, 2], [4, 3, 2]           # system 2: empty window
+    ntot = int(off[-1])
+    ctx = S.context()
+    q = torch.zeros((N + 1, 3, ntot), dtype=torch.float64, device="cuda")
+    pq = torch.zeros_like(q)
+    # start states in every slot (each system's window starts at a different slot)
+    for r in range(R):
+        for m in range(N + 1):
+            q[m][:, off[r]:off[r + 1]] = dev(xs[r]) + 0.01 * m
+            pq[m][:, off[r]:off[r + 1]] = dev(ps[r])
+    ctx.parareal_iterate_batch(None, None, q, pq, off, boxes, L, n_in, n_fi, 1e100, T=Ts, noise_id=nids, **kwc)
+    sentinel = 12345.0
+    qp = torch.full_like(q, sentinel)
+    ppv = torch.full_like(q, sentinel)
+    q0 = q.clone()
+    p0 = pq.clone()
+    d, nf = ctx.parareal_iterate_batch(qp, ppv, q, pq, off, boxes, L, n_in, n_fi, 1e100, T=Ts, noise_id=nids, **kw)
+    assert d[2] == 0.0 and nf[2] == n_fi[2] and d[0] > 0.0 and d[1] > 0.0
+    for r in range(R):
+        cols = slice(off[r], off[r + 1])
+        for m in range(N + 1):
+            inside = n_in[r] < n_fi[r] and n_in[r] <= m <= n_fi[r]
+            assert torch.equal(qp[m][:, cols] == sentinel, torch.full_like(qp[m][:, cols], not inside,
+                                                                              dtype=torch.bool)), (r, m)
+            if not (n_in[r] < m <= n_fi[r]):
+                assert torch.equal(q[m][:, cols], q0[m][:, cols]), (r, m)
+    # each system against the single-system call on its own states
+    for r in range(2):
+        cols = slice(off[r], off[r + 1])
+        q1 = q0[:, :, cols].contiguous()
+        p1 = p0[:, :, cols].contiguous()
+        qp1, pp1 = torch.zeros_like(q1), torch.zeros_like(q1)
+        d1, nf1 = ctx.parareal_iterate(qp1, pp1, q1, p1, boxes[r], L, n_in[r], n_fi[r], 1e100, T=Ts[r],
+                                       noise_id=nids[r], **kw)
+        assert nf1 == nf[r] and abs(d1 - d[r]) <= 1e-12 * d1
+        assert torch.max(torch.abs(q1 - q[:, :, cols])).item() < 1e-12 * torch.max(torch.abs(q1)).item()

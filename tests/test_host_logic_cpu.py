@@ -85,3 +85,16 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "single GPU" in r.stderr
+
+
+def test_parareal_windows_are_checked_before_any_call():
+    """Windows must lie inside the state arrays (slots 0 .. n_slots - 1): the binding
+    refuses any other before the library is called (an out-of-range window would make the
+    library copy and write past the arrays)."""
+    from paper_2212_10508_amd.snapmd import check_windows
+    check_windows([0], [4], 5, 1)
+    check_windows([0, 2], [4, 2], 5, 2)          # an empty window leaves a system of a batch out
+    for n_in, n_fi, slots, R in (([0], [5], 5, 1), ([-1], [2], 5, 1), ([3], [2], 5, 1), ([2], [2], 5, 1),
+                                 ([0, 1], [4, 6], 6, 2), ([0], [4], 5, 2)):
+        with pytest.raises(ValueError):
+            check_windows(n_in, n_fi, slots, R)
