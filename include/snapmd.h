@@ -146,6 +146,26 @@ enum { SNAPMD_POT_FS = 0, SNAPMD_POT_FS_SNAP = 1 };
 int snap_forces(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *batch,
                 const double *x, double *f, double *e_atom, uint32_t flags, void *stream);
 
+/* Allocation-free variant of snap_forces, for callers that cannot allocate device memory
+ * (work captured into a graph, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, results and asynchrony as snap_forces.  Every buffer its kernels use
+ * besides x, f and e_atom (neighbour lists, pair tables, SNAP densities and adjoints, the
+ * batch description, the coefficient tables) lives in one fixed device array of
+ * SNAPMD_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the
+ * process ends (its address on a device is taken when a context is first created there);
+ * the call allocates nothing.  Limits: at most SNAPMD_NOALLOC_MAX_ATOMS atoms and
+ * SNAPMD_NOALLOC_MAX_SYS systems per call, else SNAPMD_EINVAL with a message (larger
+ * batches: snap_forces).  The array keeps the last call's contents; nothing in it has to
+ * start at zero.  All calls on one GPU share the array: calls that overlap on one GPU (on
+ * other streams, contexts or threads) race, and the caller must serialise them.  A
+ * neighbour overflow is latched in the context like snap_forces' and reported by the next
+ * snapmd_sync. */
+#define SNAPMD_NOALLOC_MAX_ATOMS 2048
+#define SNAPMD_NOALLOC_MAX_SYS 256
+#define SNAPMD_NOALLOC_SCRATCH_BYTES (24u << 20) /* 24 MiB */
+int snap_forces_noalloc(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *batch,
+                        const double *x, double *f, double *e_atom, uint32_t flags, void *stream);
+
 /* Finnis-Sinclair forces of every system (same layout and flags as snap_forces). */
 int eam_forces(snapmd_ctx *ctx, const snapmd_fs *fs, const snapmd_batch *batch, const double *x,
                double *f, double *e_atom, uint32_t flags, void *stream);

@@ -108,6 +108,8 @@ struct snapmd_ctx {
     int sweep_k_override = 0;            // sweep workgroups set by snapmd_set_sweep_workgroups (0: built in)
     DBuf<int4> d_ws;                     // Wigner-Seitz lattice of each system
     DBuf<unsigned long long> d_fmax;     // max |F|^2 of the relaxation
+    unsigned char *scratch = nullptr;    // this device's address of the allocation-free scratch array
+    AdjointHost na_adj;                  // host tables of the allocation-free SNAP forces
     // coarse propagator of parareal_iterate: Finnis-Sinclair, plus SNAP when set
     bool coarse_snap_on = false;
     snapmd_snap coarse_snap{};
@@ -1339,6 +1341,48 @@ int parareal_multi(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Allocation-free SNAP forces: every work buffer of snap_forces_noalloc lives in one
+// file-scope device array.  Host code never uses the array's name as an address: the
+// address on each device comes from hipGetSymbolAddress, taken once per device when a
+// context is created on it.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = (size_t)SNAPMD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch;  // device -> address of `scratch` on it
+
+// the current device must be `device`
+int scratch_setup(int device, unsigned char **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(device);
+    if (it == g_scratch.end()) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SNAPMD_EHIP;
+        it = g_scratch.emplace(device, (unsigned char *)ptr).first;
+    }
+    *out = it->second;
+    return SNAPMD_OK;
+}
+
+// Carves aligned regions out of the scratch array.
+struct Carve {
+    unsigned char *base;
+    size_t used = 0;
+    template <class T>
+    T *take(size_t n) {
+        used = (used + 255) & ~(size_t)255;
+        T *p = (T *)(base + used);
+        used += n * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace
+
 // ===========================================================================
 extern "C" {
 
@@ -1358,6 +1402,10 @@ int snapmd_create(snapmd_ctx **out, int hip_device) {
     adjoint_init_attributes();
     sweep_init_attributes();
     neigh_init_attributes();
+    if (scratch_setup(hip_device, &ctx->scratch) != SNAPMD_OK) {
+        delete ctx;
+        return SNAPMD_EHIP;
+    }
     if (dalloc(ctx, &ctx->w.status, 1) != SNAPMD_OK || hipMemset(ctx->w.status, 0, sizeof(int)) != hipSuccess ||
         dalloc(ctx, &ctx->w.flag, 1) != SNAPMD_OK || hipMemset(ctx->w.flag, 0, sizeof(int)) != hipSuccess) {
         snapmd_destroy(ctx);
@@ -1413,6 +1461,129 @@ int snap_forces(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *ba
     if (bd.N == 0) return SNAPMD_OK;
     if ((rc = neighbors(ctx, ctx->w, bd, x, snap->rcut, true, st))) return rc;
     launch_snap(sd.J, bd, x, sd, ctx->w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st, &ctx->prof);
+    return check_launch(ctx);
+}
+
+int snap_forces_noalloc(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *batch, const double *x,
+                        double *f, double *e_atom, uint32_t flags, void *stream) {
+    if (!ctx) return SNAPMD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!ctx->scratch) return fail(ctx, SNAPMD_EHIP, "the scratch array of this device is not set up");
+    if (!x || !f) return fail(ctx, SNAPMD_EINVAL, "x and f must be device pointers");
+    if (!batch || !batch->offset || !batch->box) return fail(ctx, SNAPMD_EINVAL, "batch, offset and box must be set");
+    const int S = batch->n_sys;
+    if (S < 1 || S > SNAPMD_NOALLOC_MAX_SYS)
+        return fail(ctx, SNAPMD_EINVAL, "snap_forces_noalloc: need 1 <= n_sys <= %d (got %d)", SNAPMD_NOALLOC_MAX_SYS, S);
+    if (batch->offset[0] != 0) return fail(ctx, SNAPMD_EINVAL, "batch.offset[0] must be 0");
+    double mh = INFINITY;
+    int max_sys = 0;
+    for (int q = 0; q < S; ++q) {
+        if (batch->offset[q + 1] < batch->offset[q])
+            return fail(ctx, SNAPMD_EINVAL, "batch.offset must be nondecreasing (system %d)", q);
+        max_sys = std::max(max_sys, batch->offset[q + 1] - batch->offset[q]);
+        for (int a = 0; a < 3; ++a) {
+            const double L = batch->box[3 * q + a];
+            if (!(L > 0.0) || !std::isfinite(L))
+                return fail(ctx, SNAPMD_EINVAL, "box edge %d of system %d must be finite and > 0", a, q);
+            mh = std::min(mh, 0.5 * L);
+        }
+    }
+    const int N = batch->offset[S];
+    if (N > SNAPMD_NOALLOC_MAX_ATOMS)
+        return fail(ctx, SNAPMD_EINVAL, "snap_forces_noalloc takes at most %d atoms (got %d); use snap_forces",
+                    SNAPMD_NOALLOC_MAX_ATOMS, N);
+    if (!snap) return fail(ctx, SNAPMD_EINVAL, "snap is NULL");
+    const int J = snap->twojmax;
+    if (J != 2 && J != 4 && J != 6 && J != 8)
+        return fail(ctx, SNAPMD_EUNSUPPORTED, "twojmax must be one of 2, 4, 6, 8 (got %d)", J);
+    const SnapTables &T = snap_tables(J);
+    if (snap->n_coeff != T.K)
+        return fail(ctx, SNAPMD_EINVAL, "n_coeff must be %d for twojmax %d (got %d)", T.K, J, snap->n_coeff);
+    if (!snap->beta) return fail(ctx, SNAPMD_EINVAL, "snap.beta is NULL");
+    if (!(snap->rcut > 0.0) || !(snap->rmin0 >= 0.0) || !(snap->rmin0 < snap->rcut))
+        return fail(ctx, SNAPMD_EINVAL, "need 0 <= rmin0 < rcut (rcut %g, rmin0 %g)", snap->rcut, snap->rmin0);
+    if (!(snap->rfac0 > 0.0 && snap->rfac0 < 1.0))
+        return fail(ctx, SNAPMD_EINVAL, "need 0 < rfac0 < 1 (got %g)", snap->rfac0);
+    if (!(snap->rcut < mh))
+        return fail(ctx, SNAPMD_EINVAL, "rcut %g must be < half the smallest box edge %g", snap->rcut, mh);
+    for (int k = 0; k <= T.K; ++k)
+        if (!std::isfinite(snap->beta[k])) return fail(ctx, SNAPMD_EINVAL, "beta[%d] is not finite", k);
+    if (N == 0) return SNAPMD_OK;
+    AdjointHost &A = ctx->na_adj;
+    adjoint_tables(J, snap->beta, A);
+    // regions of the scratch array (nothing in them has to start at zero: every kernel
+    // writes what it later reads, and the list build is forced)
+    Carve cv{ctx->scratch};
+    const size_t P = (size_t)N * kMaxNeigh;
+    int *d_off = cv.take<int>(S + 1);
+    double *d_box = cv.take<double>(3 * (size_t)S);
+    int4 *d_cells = cv.take<int4>(S);
+    double *d_nrm = cv.take<double>(T.nh), *d_ymult = cv.take<double>(T.nh);
+    double *d_cgm = cv.take<double>(A.cgm.size()), *d_coef = cv.take<double>(A.coef.size());
+    int *d_coef_off = cv.take<int>(A.coef_off.size()), *d_roles = cv.take<int>(A.roles.size());
+    Work w{};
+    w.Pcap = P;
+    w.nbr = cv.take<int>(P);
+    w.cnt = cv.take<int>(N);
+    w.poff = cv.take<int>((size_t)N + 1);
+    w.pair_i = cv.take<int>(P);
+    w.pair_j = cv.take<int>(P);
+    w.rev = cv.take<int>(P);
+    w.ell = cv.take<double>(6 * P);
+    w.nbr_t = cv.take<int>(P);
+    w.dedr = cv.take<double>(3 * P);
+    w.u = cv.take<double2>((size_t)T.nh * N);
+    w.ytil = cv.take<double2>((size_t)T.nh * N);
+    w.xref = cv.take<double>(3 * (size_t)N);
+    w.status = ctx->w.status;  // overflow bits, reported by snapmd_sync
+    w.flag = ctx->w.flag;
+    if (cv.used > kNoAllocBytes)
+        return fail(ctx, SNAPMD_EINVAL, "snap_forces_noalloc: %zu bytes of work space exceed the %zu of the array",
+                    cv.used, kNoAllocBytes);
+    // the cell grids the list build of snap_forces uses (same lists, same order)
+    std::vector<int4> ci(S);
+    int n_cells = 0;
+    const double rl = snap->rcut + kSkin;
+    for (int q = 0; q < S; ++q) {
+        int n3[3];
+        for (int a = 0; a < 3; ++a) n3[a] = (int)std::floor(batch->box[3 * q + a] / rl);
+        if (n3[0] >= 3 && n3[1] >= 3 && n3[2] >= 3 && batch->offset[q + 1] - batch->offset[q] >= 500) {
+            ci[q] = make_int4(n3[0], n3[1], n3[2], n_cells);
+            n_cells += n3[0] * n3[1] * n3[2];
+        } else {
+            ci[q] = make_int4(0, 0, 0, n_cells);
+        }
+    }
+    int rc;
+    if ((rc = upload(ctx, d_off, batch->offset, (size_t)S + 1, st)) || (rc = upload(ctx, d_box, batch->box, 3 * (size_t)S, st)) ||
+        (rc = upload(ctx, d_cells, ci.data(), (size_t)S, st)) ||
+        (rc = upload(ctx, d_nrm, T.nrm.data(), (size_t)T.nh, st)) ||
+        (rc = upload(ctx, d_ymult, T.ymult.data(), (size_t)T.nh, st)) ||
+        (rc = upload(ctx, d_cgm, A.cgm.data(), A.cgm.size(), st)) ||
+        (rc = upload(ctx, d_coef, A.coef.data(), A.coef.size(), st)) ||
+        (rc = upload(ctx, d_coef_off, A.coef_off.data(), A.coef_off.size(), st)) ||
+        (rc = upload(ctx, d_roles, A.roles.data(), A.roles.size(), st)))
+        return rc;
+    BatchDev bd;
+    bd.N = N;
+    bd.n_sys = S;
+    bd.off = d_off;
+    bd.box = d_box;
+    bd.max_sys = max_sys;  // every system fits the one-workgroup list build (N <= 2048)
+    bd.cells = d_cells;
+    bd.n_cells = n_cells;
+    SnapDev sd;
+    sd.J = J;
+    sd.K = T.K;
+    sd.nh = T.nh;
+    sd.gp = SnapGeoParams{snap->rcut, snap->rfac0, snap->rmin0};
+    sd.beta0 = snap->beta[0];
+    sd.nrm = d_nrm;
+    sd.ymult = d_ymult;
+    sd.adj = AdjointDev{d_cgm, d_coef, d_coef_off, d_roles, A.role_len};
+    launch_neighbors(bd, x, snap->rcut, w, st, true, kSkin);
+    launch_snap(J, bd, x, sd, w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st);
     return check_launch(ctx);
 }
 

@@ -70,6 +70,8 @@ def lib():
     L.snapmd_sync.restype = C.c_int
     L.snap_forces.argtypes = [P, C.POINTER(Snap), C.POINTER(Batch), P, P, P, u32, P]
     L.snap_forces.restype = C.c_int
+    L.snap_forces_noalloc.argtypes = [P, C.POINTER(Snap), C.POINTER(Batch), P, P, P, u32, P]
+    L.snap_forces_noalloc.restype = C.c_int
     L.eam_forces.argtypes = [P, C.POINTER(Fs), C.POINTER(Batch), P, P, P, u32, P]
     L.eam_forces.restype = C.c_int
     L.langevin_steps.argtypes = [P, C.c_int, C.POINTER(Snap), C.POINTER(Fs), C.POINTER(Batch),
@@ -228,6 +230,18 @@ class Context:
         self._check(lib().snap_forces(self.h, C.byref(s), C.byref(b), _dev(x, "x", (3, N)), _dev(f, "f", (3, N)),
                                       _dev(e_atom, "e_atom", (N,)), ACCUMULATE if accumulate else 0,
                                       _stream(stream)))
+        return f
+
+    def snap_forces_noalloc(self, x, offset, box, J, beta, f, e_atom=None, accumulate=False, rcut=4.73,
+                            rfac0=0.99363, rmin0=0.0, stream=None):
+        """snap_forces without any device allocation (f is required; at most
+        SNAPMD_NOALLOC_MAX_ATOMS atoms)."""
+        N = int(offset[-1])
+        k = _Keep()
+        b, s = make_batch(k, offset, box), make_snap(k, J, beta, rcut, rfac0, rmin0)
+        self._check(lib().snap_forces_noalloc(self.h, C.byref(s), C.byref(b), _dev(x, "x", (3, N)),
+                                              _dev(f, "f", (3, N)), _dev(e_atom, "e_atom", (N,)),
+                                              ACCUMULATE if accumulate else 0, _stream(stream)))
         return f
 
     def eam_forces(self, x, offset, box, fs, f=None, e_atom=None, accumulate=False, stream=None):
