@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CUs x 128 FLOP/clk x 2.4 GHz
+DEFAULT_PLAN = "15,13,14,15,7"   # slab chunks of one adjoint round each (64 x 1025 atoms)
 PROF_EVERY = 8            # HIP events around every 8th launch of each timed kernel
 
 
@@ -78,19 +79,76 @@ def dedr_flops(J):
     return f + 3 * 33
 
 
-def cpu_baseline(wl, J, nsteps=40):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, J, nsteps_all=24, nsteps_one=2):
+    """The oracle (plain C, FP64, adjoint route) on one 1025-atom slab of the workload: on
+    all host cores (OpenMP over atoms) and on one core, each on a bounded step count."""
     from oracle import oracle as O
     from paper_2212_10508_amd import workloads as W
     x, p = wl["xs"][0], wl["ps"][0]
     snap = dict(J=J, beta=wl["beta"], rcut=W.SNAP_RCUT, rfac0=W.SNAP_RFAC0, rmin0=0.0)
-    t0 = time.time()
-    O.langevin(x, p, wl["box"], potential=O.POT_FS_SNAP, nsteps=nsteps, dt=wl["dt"], gamma=wl["gamma"],
-               mass=wl["mass"], T=wl["T"], seed=1, noise_id=0, step0=0, snap=snap, fs=W.FS_W)
-    dt = time.time() - t0
+
+    def run(nsteps):
+        t0 = time.time()
+        O.langevin(x, p, wl["box"], potential=O.POT_FS_SNAP, nsteps=nsteps, dt=wl["dt"], gamma=wl["gamma"],
+                   mass=wl["mass"], T=wl["T"], seed=1, noise_id=0, step0=0, snap=snap, fs=W.FS_W)
+        return time.time() - t0
+
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
-    return {"value": x.shape[1] * nsteps / dt, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "one 1025-atom slab, %d fine BAOAB steps (%d force evaluations), twojmax 8, "
-                      "adjoint route, OpenMP over atoms; %.1f s" % (nsteps, nsteps + 1, dt)}
+    used = O.set_threads(cores)
+    t_all = run(nsteps_all)
+    O.set_threads(1)
+    t_one = run(nsteps_one)
+    O.set_threads(used)
+    n = x.shape[1]
+    return {"value": n * nsteps_all / t_all, "unit": "atom-steps/s", "cores": used, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": "one 1025-atom slab of the workload, %d fine BAOAB steps (%d force evaluations), twojmax 8, "
+                      "adjoint route, OpenMP over atoms on %d threads: %.1f s" % (nsteps_all, nsteps_all + 1, used,
+                                                                                 t_all),
+            "single_core": {"value": n * nsteps_one / t_one, "unit": "atom-steps/s", "cores": 1,
+                            "sample": "the same slab, %d steps (%d force evaluations): %.1f s"
+                                      % (nsteps_one, nsteps_one + 1, t_one)}}
+
+
+def force_rel_err(f, ref):
+    """max_i |F_i - F_i^ref| / max_i |F_i^ref| (per-atom Euclidean norms)."""
+    return float(np.linalg.norm(f - ref, axis=0).max() / np.linalg.norm(ref, axis=0).max())
+
+
+def force_gate(S, W, ctx, xs, box, J, beta, slabs, tol=1e-10):
+    """Forces of the fine potential (FS + SNAP) at the slab-start states `xs` [S, 3, n]: the
+    batched form (all slabs in one call) and the per-slab form (one call per sampled
+    slab) against the oracle on the sampled slabs."""
+    import torch
+    from oracle import oracle as O
+    Sn, _, n = xs.shape
+    off = np.arange(Sn + 1, dtype=np.int32) * n
+    boxes = np.tile(box, (Sn, 1))
+    X = xs.permute(1, 0, 2).reshape(3, Sn * n).contiguous()
+    fb = ctx.snap_forces(X, off, boxes, J, beta)
+    ctx.eam_forces(X, off, boxes, W.FS_W, f=fb, accumulate=True)
+    fb = fb.cpu().numpy()
+    out = {"tol": tol, "slabs": list(slabs), "batched": [], "per_slab": []}
+    for s in slabs:
+        x = xs[s].contiguous()
+        fp = ctx.snap_forces(x, [0, n], box, J, beta)
+        ctx.eam_forces(x, [0, n], box, W.FS_W, f=fp, accumulate=True)
+        xh = x.cpu().numpy()
+        ref = O.snap_compute(xh, box, J, beta)["f"] + O.fs_compute(xh, box, W.FS_W)["f"]
+        out["batched"].append(force_rel_err(fb[:, s * n:(s + 1) * n], ref))
+        out["per_slab"].append(force_rel_err(fp.cpu().numpy(), ref))
+    out["passed"] = max(out["batched"] + out["per_slab"]) <= tol
+    return out
 
 
 def summarize_trace(path, top=16):
@@ -109,6 +167,30 @@ def summarize_trace(path, top=16):
         short = name.replace("snapmd::", "").split("(")[0][:52]
         print("%-52s %12s %7d %12.2f %12.2f %6.2f" % (short, grid, len(v), sum(v) / len(v), sum(v) / 1e3,
                                                     100 * sum(v) / tot))
+
+
+def kernel_rates(ctx, S, J, atoms, pairs, evals):
+    """Average launch time (HIP-event sample of a profiled run), algorithmic FP64 TFLOP/s,
+    fraction of the FP64 peak and HBM GB/s (measured bytes per unit, where valid for the
+    current source) of the SNAP kernels, for a run whose every force evaluation launches
+    each kernel once over the whole batch (`evals` evaluations)."""
+    nUh, nZel, nZt = snap_counts(J)
+    per_launch = {"dedr": float(dedr_flops(J)) * pairs, "adjoint": (8.0 * nZt + 4.0 * nZel) * atoms,
+                  "density": 22.0 * nUh * pairs}
+    out = {}
+    for name, kid in (("dedr", S.Context.PROF_DEDR), ("adjoint", S.Context.PROF_ADJOINT),
+                      ("density", S.Context.PROF_DENSITY)):
+        ms, nl = ctx.profile_read(kid)
+        if nl == 0:
+            continue
+        avg = ms / nl
+        tf = per_launch[name] / (avg * 1e-3) / 1e12
+        per_unit, unit = traffic_per_unit(name)
+        units = atoms if unit == "atom" else pairs
+        out[name] = {"avg_ms": avg, "launches_timed": nl, "launches": evals, "tflops": tf,
+                     "frac": tf / FP64_PEAK_TFLOPS,
+                     "hbm_gb_s": per_unit * units / (avg * 1e-3) / 1e9 if per_unit is not None else None}
+    return out
 
 
 def other_configs(S, W, log):
@@ -162,8 +244,19 @@ def other_configs(S, W, log):
                          noise_id=nid, J=8, beta=wl["beta"], **kw0)
 
     t = timed(c3, reps=1)
+    S.snap_forces(xr, off, B, 8, wl["beta"])
+    pairs3 = S.context(0).pair_count()
+    ctx3 = S.context(0)
+    ctx3.profile(True, every=8)
+    xw.copy_(xr)
+    pw.copy_(pr)
+    S.langevin_steps(S.POT_FS_SNAP, xw, pw, off, B, 100, T=wl["T"], seed=8, step0=0, noise_id=nid, J=8,
+                     beta=wl["beta"], **kw0)
+    rates = kernel_rates(ctx3, S, 8, int(off[-1]), pairs3, 101)
+    ctx3.profile(False)
     out["replicas_256_mixed_1000_steps"] = {"atoms": int(off[-1]), "atom_steps_per_s": int(off[-1]) * 1000 / t,
-                                            "s": t}
+                                            "s": t, "pairs": pairs3,
+                                            "kernels_over_100_profiled_steps": rates}
     log("256 replicas: %.2f s per 1000 steps" % t)
     del xr, pr, xw, pw
     # 512 configurations (129 / 433 / 1025 atoms, 0.1 A thermal jitter), twojmax 8: energy,
@@ -185,28 +278,40 @@ def other_configs(S, W, log):
     out["force_matching_512_configs"] = {"atoms": int(off[-1]), "configs_per_s": 512 / t, "ms": t * 1e3}
     log("512 configurations: %.2f ms per energy + forces + dL/dbeta" % (t * 1e3))
     del xg, fref
-    # fine batch of a 16001-atom trajectory: 32 slabs x 200 steps in one launch sequence
-    xs, ps = [], []
-    for s in range(32):
-        x, box = W.bcc_sia(20, jitter=0.05, seed=7000 + s)
-        xs.append(x)
-        ps.append(W.maxwell_momenta(x.shape[1], 1000.0, seed=7000 + s))
-    X, off, B = W.pack(xs, [box] * 32)
-    xf, pf = dev(X), dev(np.concatenate(ps, axis=1))
-    xw, pw = xf.clone(), pf.clone()
+    # one corrected parareal iteration of a 16001-atom trajectory (20x20x20 bcc + dumbbell):
+    # 32 slabs x 200 steps, fine batch of 512,032 atoms, host-driven coarse sweep
+    x, box = W.bcc_sia(20, jitter=0.05, seed=7000)
+    n = x.shape[1]
+    Sl, L5 = 32, 200
     beta5 = W.snap_beta(8, seed=3)
-
-    def c5():
-        xw.copy_(xf)
-        pw.copy_(pf)
-        S.langevin_steps(S.POT_FS_SNAP, xw, pw, off, B, 200, T=1000.0, seed=9,
-                         step0=np.arange(32) * 200, noise_id=0, J=8, beta=beta5, **kw0)
-
-    t = timed(c5, reps=1)
-    out["fine_batch_16001x32_200_steps"] = {"atoms": int(off[-1]), "atom_steps_per_s": int(off[-1]) * 200 / t,
-                                            "s": t}
-    log("16001 atoms x 32 slabs: %.2f s per 200 steps" % t)
-    del xw, pw, xf, pf
+    kw5 = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=9, noise_id=0, fs=W.FS_W)
+    ctx = S.context(0)
+    q = torch.zeros((Sl + 1, 3, n), dtype=torch.float64, device="cuda")
+    pq, qp, pp = torch.zeros_like(q), torch.zeros_like(q), torch.zeros_like(q)
+    q[0], pq[0] = dev(x), dev(W.maxwell_momenta(n, 1000.0, seed=7000))
+    ctx.parareal_iterate(None, None, q, pq, box, L5, 0, Sl, 1e300, **kw5)
+    Xs = q[:Sl].permute(1, 0, 2).reshape(3, Sl * n).contiguous()
+    off5 = np.arange(Sl + 1, dtype=np.int32) * n
+    ctx.snap_forces(Xs, off5, np.tile(box, (Sl, 1)), 8, beta5)
+    pairs5 = ctx.pair_count()
+    del Xs
+    q0, p0 = q.clone(), pq.clone()
+    ctx.parareal_iterate(qp, pp, q, pq, box, L5, 0, Sl, 1e300, J=8, beta=beta5, **kw5)   # captures
+    q.copy_(q0)
+    pq.copy_(p0)
+    torch.cuda.synchronize()
+    ctx.profile(True, every=8)
+    t0 = time.perf_counter()
+    d5, _ = ctx.parareal_iterate(qp, pp, q, pq, box, L5, 0, Sl, 1e300, J=8, beta=beta5, **kw5)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    rates = kernel_rates(ctx, S, 8, Sl * n, pairs5, L5 + 1)
+    ctx.profile(False)
+    out["parareal_16001x32_200_steps"] = {
+        "atoms": n, "slabs": Sl, "L": L5, "fine_atom_steps_per_s": Sl * n * L5 / t, "s": t, "delta": d5,
+        "pairs": pairs5, "sweep": "driven from the host, one synchronisation per slab", "kernels": rates}
+    log("16001 atoms x 32 slabs: %.2f s per parareal iteration" % t)
+    del q, pq, qp, pp, q0, p0
     # the paper's strategy I: coarse = Finnis-Sinclair + a twojmax-2 SNAP, one corrected
     # parareal iteration over 64 slabs of the 1025-atom system (host-driven sweep)
     wl = W.slabs_1025(n_slabs=1, seed=1, J=8)
@@ -320,8 +425,11 @@ def main():
     ap.add_argument("--L", type=int, default=100)
     ap.add_argument("--per-slab-sample", type=int, default=4, help="slabs timed one by one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="keep the built-in slab chunk plan")
-    ap.add_argument("--plan", default=None, help="slab chunks, e.g. 7,29,28 (implies --no-tune)")
+    ap.add_argument("--tune", action="store_true",
+                    help="time slab chunk plans and sweep widths first (untimed) and use the fastest")
+    ap.add_argument("--plan", default=DEFAULT_PLAN,
+                    help="slab chunks of the 64-slab window (default %s, the plan the committed kernel trace "
+                         "covers); 'builtin' for the library's own plan" % DEFAULT_PLAN)
     ap.add_argument("--sweep-workgroups", type=int, default=0, help="coarse sweep width (0: built in)")
     ap.add_argument("--no-configs", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -373,17 +481,31 @@ def main():
         assert nfi == S_slabs
         return d
 
+    # correctness gate in the same run: step-0 forces of sampled slabs, batched and
+    # per-slab forms, against the oracle (1e-10, norm-wise)
+    gate_slabs = sorted({0, int(np.random.default_rng(7).integers(1, S_slabs))}) if S_slabs > 1 else [0]
+    log("force gate: slabs %s against the oracle ..." % gate_slabs)
+    gate = force_gate(S, W, ctx, q_cur[:S_slabs], box, J, beta, gate_slabs)
+    log("force gate: batched %s, per-slab %s" % (gate["batched"], gate["per_slab"]))
+    if not gate["passed"]:
+        print("bench.py: forces differ from the oracle by more than %g: %s" % (gate["tol"], json.dumps(gate)),
+              file=sys.stderr)
+        sys.exit(3)
     ctx.set_sweep_workgroups(args.sweep_workgroups)
-    if args.plan:  # set before the warmup, which captures the plan's launch sequences
-        ctx.set_chunk_plan([int(v) for v in args.plan.split(",")])
+    use_plan = None if (args.tune or args.plan == "builtin") else [int(v) for v in args.plan.split(",")]
+    if use_plan:  # set before the warmup, which captures the plan's launch sequences
+        ctx.set_chunk_plan(use_plan)
     for w in range(args.warmup):
         d = iteration()
         log("warmup %d: delta %.3e" % (w, d))
     # slab chunks of the pipelined iteration, timed on this workload (untimed setup)
     n_cus = torch.cuda.get_device_properties(0).multi_processor_count
-    builtin_plan = list(ctx.chunk_plan(S_slabs, n)) if not args.plan else None
+    ctx.set_chunk_plan(None)
+    builtin_plan = list(ctx.chunk_plan(S_slabs, n))
+    if use_plan:
+        ctx.set_chunk_plan(use_plan)
     autotune = None
-    if not args.plan and not args.no_tune:
+    if args.tune:
         from paper_2212_10508_amd import tune
 
         def timed_iteration():
@@ -465,6 +587,8 @@ def main():
         t_fine_bbk = fine_batch(scheme="bbk", cT=(3.0, 1.0))
         ns = min(args.per_slab_sample, S_slabs)
         xs, ps = q_start[0].clone(), p_start[0].clone()
+        # untimed call first: captures the one-slab launch sequence the timed calls replay
+        ctx.langevin_steps(S.POT_FS_SNAP, xs, ps, [0, n], box, L, step0=0, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(ns):
@@ -495,12 +619,13 @@ def main():
                                "+ Finnis-Sinclair fine / FS coarse, L=100 BAOAB steps, 1 fs, 1000 K",
                    "atoms": n, "slabs": S_slabs, "L": L, "twojmax": J, "pairs": n_pairs,
                    "mean_neighbours": n_pairs / atoms, "chunk_plan": chunk_plan,
-                   "sweep_workgroups": ctx.sweep_workgroups(n)},
+                   "sweep_workgroups": ctx.sweep_workgroups(n), "builtin_plan": builtin_plan},
         "roofline": {"bound": "alu", "kernel": kname[dom], "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "traffic_bytes_per_" + unit: per_unit,
                      "avg_launch_ms": kernels[dom]["avg_ms"], "gflop_per_launch": kernels[dom]["gflop_per_launch"]},
         "kernels": kernels,
+        "force_parity": gate,
     }
     out.update(extras)
     if not args.no_configs:

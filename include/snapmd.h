@@ -237,6 +237,15 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
  * SNAPMD_EUNSUPPORTED. */
 int snapmd_set_coarse_snap(snapmd_ctx *ctx, const snapmd_snap *coarse);
 
+/* Finnis-Sinclair parameters of the coarse propagator of parareal_iterate.  By default the
+ * coarse propagator uses the `fs` passed to parareal_iterate, which is also the
+ * Finnis-Sinclair part of the fine potential.  snapmd_set_coarse_fs(ctx, coarse) gives the
+ * coarse propagator parameters of its own (copied), e.g. an empirical potential fitted
+ * apart from the fine one, as the paper's strategy II has it; NULL restores the default.
+ * Combines with snapmd_set_coarse_snap.  Errors: SNAPMD_EINVAL (d, c not > 0 or a
+ * coefficient not finite). */
+int snapmd_set_coarse_fs(snapmd_ctx *ctx, const snapmd_fs *coarse);
+
 /* Gradients of the SNAP model with respect to its coefficients beta (for a
  * force-matching fit; the loss is the caller's):
  *   dEdbeta[k]  = sum_i B_k(i)                    (k = 1..K; dEdbeta[0] = n_atoms)

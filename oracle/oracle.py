@@ -62,11 +62,18 @@ def lib():
         L.ora_bbk.restype = i
         L.ora_bbk.argtypes = ([i, i, d, d, d, P, d, d, d, d, d, d, i, i, P, d, d, d, d, d, d,
                                u64, u64, i64, P, i, P, P, P, P, P])
+        L.ora_set_threads.restype = i
+        L.ora_set_threads.argtypes = [i]
         L.ora_langevin.restype = i
         L.ora_langevin.argtypes = ([i, i, d, d, d, P, d, d, d, d, d, d, i, i, P, d, d, d, d,
                                     u64, u64, i64, i, P, P, P, P, P])
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops (n <= 0 leaves them); returns the count in effect."""
+    return lib().ora_set_threads(int(n))
 
 
 def _p(a):

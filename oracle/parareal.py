@@ -39,7 +39,7 @@ class Propagators:
     """F and C of one trajectory (one noise stream) for the oracle."""
 
     def __init__(self, *, box, L, dt, gamma, mass, T, seed, noise_id, snap, fs, maxn=64, scheme="baoab",
-                 cT=(1.0, 1.0), coarse_snap=None):
+                 cT=(1.0, 1.0), coarse_snap=None, coarse_fs=None):
         self.kw = dict(dt=dt, gamma=gamma, mass=mass, T=T, seed=seed, noise_id=noise_id,
                        snap=snap, fs=fs, maxn=maxn)
         self.box = box
@@ -47,14 +47,17 @@ class Propagators:
         self.scheme = scheme  # "baoab", or "bbk": the paper's scheme, one application per slab
         self.cT = cT
         self.coarse_snap = coarse_snap  # None: C on Finnis-Sinclair alone
+        self.coarse_fs = coarse_fs      # None: C uses the fine potential's Finnis-Sinclair part
         self.n_fine = 0
         self.n_coarse = 0
 
-    def _run(self, state, n, potential, snap=None):
+    def _run(self, state, n, potential, snap=None, fs=None):
         q, p = state
         kw = dict(self.kw)
         if snap is not None:
             kw["snap"] = snap
+        if fs is not None:
+            kw["fs"] = fs
         if self.scheme == "bbk":
             r = O.bbk(q, p, self.box, potential=potential, nsteps=self.L, step0=n * self.L, cT=self.cT, **kw)
         else:
@@ -68,8 +71,8 @@ class Propagators:
     def C(self, state, n):
         self.n_coarse += 1
         if self.coarse_snap is not None:
-            return self._run(state, n, O.POT_FS_SNAP, self.coarse_snap)
-        return self._run(state, n, O.POT_FS)
+            return self._run(state, n, O.POT_FS_SNAP, self.coarse_snap, self.coarse_fs)
+        return self._run(state, n, O.POT_FS, None, self.coarse_fs)
 
 
 def rel_error(prev, cur, n_in, n_to):

@@ -729,3 +729,18 @@ int ora_bbk(int potential, int J, double rcut, double rfac0, double rmin0, const
     free(gl);
     return rc;
 }
+
+/* Threads of the OpenMP loops over atoms (measurement support: the benchmark times the
+ * oracle on one core and on all cores).  Returns the count in effect afterwards. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int ora_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}

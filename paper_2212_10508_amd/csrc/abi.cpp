@@ -112,6 +112,8 @@ struct snapmd_ctx {
     AdjointHost na_adj;                  // host tables of the allocation-free SNAP forces
     // coarse propagator of parareal_iterate: Finnis-Sinclair, plus SNAP when set
     bool coarse_snap_on = false;
+    bool coarse_fs_on = false;           // coarse Finnis-Sinclair parameters of their own
+    snapmd_fs coarse_fs{};
     snapmd_snap coarse_snap{};
     std::vector<double> coarse_beta;
 };
@@ -384,6 +386,16 @@ int prepare_fs(snapmd_ctx *ctx, const snapmd_fs *fs, double min_half_box, FsPara
                     std::max(fs->d, fs->c), min_half_box);
     fp = FsParams{fs->A, fs->d, fs->c, fs->c0, fs->c1, fs->c2};
     return SNAPMD_OK;
+}
+
+// Finnis-Sinclair parameters of the coarse propagator: those of snapmd_set_coarse_fs when
+// set, else the fine potential's own (fp).
+int coarse_fs(snapmd_ctx *ctx, const FsParams &fp, double min_half_box, FsParams &fpc) {
+    if (!ctx->coarse_fs_on) {
+        fpc = fp;
+        return SNAPMD_OK;
+    }
+    return prepare_fs(ctx, &ctx->coarse_fs, min_half_box, fpc);
 }
 
 int check_launch(snapmd_ctx *ctx) {
@@ -810,10 +822,11 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
     const int S = *n_fi - n_in;
     const double *box = batch->box;
     double mh = 0.5 * std::min(box[0], std::min(box[1], box[2]));
-    FsParams fp;
+    FsParams fp, fpc;
     if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
+    if ((rc = coarse_fs(ctx, fp, mh, fpc))) return rc;
     const double skin = kSweepSkin;
-    if (!(std::max(fp.d, fp.c) + 2.0 * skin < mh))
+    if (!(std::max(fpc.d, fpc.c) + 2.0 * skin < mh))
         return fail(ctx, SNAPMD_EINVAL, "FS cutoff + %g A must be < half the smallest box edge", 2.0 * skin);
     SnapDev sd;
     const size_t SN3 = 3 * (size_t)S * N;
@@ -844,7 +857,7 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
     sw.box[0] = box[0];
     sw.box[1] = box[1];
     sw.box[2] = box[2];
-    sw.fp = fp;
+    sw.fp = fpc;
     sw.skin = skin;
     sw.dt = lang->dt;
     sw.c1 = c1;
@@ -861,7 +874,7 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
         // cell grid of the sweep's list build: edges >= list radius, >= 3 cells per edge,
         // at most 512 cells (else every pair is examined)
         int nc[3];
-        for (int a = 0; a < 3; ++a) nc[a] = (int)std::floor(box[a] / (std::max(fp.d, fp.c) + skin));
+        for (int a = 0; a < 3; ++a) nc[a] = (int)std::floor(box[a] / (std::max(fpc.d, fpc.c) + skin));
         while ((long)nc[0] * nc[1] * nc[2] > 512) *std::max_element(nc, nc + 3) -= 1;
         if (nc[0] < 3 || nc[1] < 3 || nc[2] < 3) nc[0] = nc[1] = nc[2] = 0;
         sw.ncx = nc[0];
@@ -984,7 +997,7 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
         // another's.  Everything the replays need (buffers, cell grids) is set up here
         // first: neither helper allocates (an allocation drops the captured graphs).
         if ((rc = prepare_propagation_cells(ctx, ctx->w, SNAPMD_POT_FS_SNAP, bd, fp, sd, st)) ||
-            (rc = prepare_propagation_cells(ctx, ctx->wc, potC, bd, fp, sdc, st)))
+            (rc = prepare_propagation_cells(ctx, ctx->wc, potC, bd, fpc, sdc, st)))
             return rc;
         std::mutex mu;
         std::condition_variable cv;
@@ -1019,7 +1032,7 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
                 const size_t o = 3 * (size_t)N * s0;
                 launch_slabs_to_batch(nc, N, qs + s0 * slot, ctx->pr_xc.p + o, s3);
                 launch_slabs_to_batch(nc, N, ps + s0 * slot, ctx->pr_pc.p + o, s3);
-                if ((r = run_langevin_graph(ctx, ctx->wc, ctx->d_fc, potC, bc, fp, sdc, lc, L,
+                if ((r = run_langevin_graph(ctx, ctx->wc, ctx->d_fc, potC, bc, fpc, sdc, lc, L,
                                             ctx->pr_xc.p + o, ctx->pr_pc.p + o, s3)))
                     return r;
                 HIPCHK(hipEventRecord(ctx->pipe_ev[ne + 2 + c], s3));
@@ -1111,7 +1124,7 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
         return SNAPMD_OK;
     }
     // Large systems: the same sweep driven from the host with the batched kernels.
-    return host_sweep(ctx, potC, fp, sdc, lang, lang->T_sys[0], lang->noise_id_sys[0], N, box, L, n_in, n_fi, init,
+    return host_sweep(ctx, potC, fpc, sdc, lang, lang->T_sys[0], lang->noise_id_sys[0], N, box, L, n_in, n_fi, init,
                       (size_t)N, q_cur, p_cur, q_prev, sw.jq, sw.jp, SN3 / 3, (size_t)N, delta_expl, delta_out, st,
                       stream);
 }
@@ -1143,9 +1156,10 @@ int parareal_multi(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs
     double mh = INFINITY;
     for (int r = 0; r < R; ++r)
         for (int a = 0; a < 3; ++a) mh = std::min(mh, 0.5 * batch->box[3 * r + a]);
-    FsParams fp;
+    FsParams fp, fpc;
     if ((rc = prepare_fs(ctx, fs, mh, fp))) return rc;
-    if (!(std::max(fp.d, fp.c) + 2.0 * skin < mh))
+    if ((rc = coarse_fs(ctx, fp, mh, fpc))) return rc;
+    if (!(std::max(fpc.d, fpc.c) + 2.0 * skin < mh))
         return fail(ctx, SNAPMD_EINVAL, "FS cutoff + %g A must be < half the smallest box edge", 2.0 * skin);
     SnapDev sdc;
     if (csnap) {
@@ -1254,7 +1268,7 @@ int parareal_multi(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs
                                   st));
             if ((rc = run_langevin_graph(ctx, ctx->w, ctx->d_f, SNAPMD_POT_FS_SNAP, bd, fp, sd, ldv, L, ctx->pr_xf.p,
                                          ctx->pr_pf.p, st)) ||
-                (rc = run_langevin_graph(ctx, ctx->wc, ctx->d_fc, potC, bd, fp, sdc, ldv, L, ctx->pr_xc.p,
+                (rc = run_langevin_graph(ctx, ctx->wc, ctx->d_fc, potC, bd, fpc, sdc, ldv, L, ctx->pr_xc.p,
                                          ctx->pr_pc.p, st)))
                 return rc;
             launch_batch_jumps_to_slots(Nc, ne, bd.off, dsrc, Nt, ctx->pr_xf.p, ctx->pr_xc.p, jq, st);
@@ -1275,7 +1289,7 @@ int parareal_multi(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs
             SweepLaunch sw{};
             sw.N = Nr;
             for (int a = 0; a < 3; ++a) sw.box[a] = box[a];
-            sw.fp = fp;
+            sw.fp = fpc;
             sw.skin = skin;
             sw.dt = lang->dt;
             sw.c1 = c1;
@@ -1289,7 +1303,7 @@ int parareal_multi(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs
             sw.mode = init ? 0 : 1;
             sw.n_win = n_in[r];
             int nc[3];
-            for (int a = 0; a < 3; ++a) nc[a] = (int)std::floor(box[a] / (std::max(fp.d, fp.c) + skin));
+            for (int a = 0; a < 3; ++a) nc[a] = (int)std::floor(box[a] / (std::max(fpc.d, fpc.c) + skin));
             while ((long)nc[0] * nc[1] * nc[2] > 512) *std::max_element(nc, nc + 3) -= 1;
             if (nc[0] < 3 || nc[1] < 3 || nc[2] < 3) nc[0] = nc[1] = nc[2] = 0;
             sw.ncx = nc[0];
@@ -1330,7 +1344,7 @@ int parareal_multi(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs
     for (int r : host_sys) {
         const int Nr = off[r + 1] - off[r];
         const size_t jb = (size_t)n_in[r] * 3 * Nt + off[r];
-        if ((rc = host_sweep(ctx, potC, fp, sdc, lang, lang->T_sys[r], lang->noise_id_sys[r], Nr, batch->box + 3 * r, L,
+        if ((rc = host_sweep(ctx, potC, fpc, sdc, lang, lang->T_sys[r], lang->noise_id_sys[r], Nr, batch->box + 3 * r, L,
                              n_in[r], n_fi + r, init, (size_t)Nt, q_cur + off[r], p_cur + off[r],
                              init ? nullptr : q_prev + off[r], init ? nullptr : jq + jb, init ? nullptr : jp + jb,
                              (size_t)Nt, 3 * (size_t)Nt, delta_expl, delta_out + r, st, stream)))
@@ -1774,6 +1788,20 @@ int snapmd_set_coarse_snap(snapmd_ctx *ctx, const snapmd_snap *coarse) {
     ctx->coarse_beta.assign(coarse->beta, coarse->beta + coarse->n_coeff + 1);
     ctx->coarse_snap.beta = nullptr;
     ctx->coarse_snap_on = true;
+    return SNAPMD_OK;
+}
+
+int snapmd_set_coarse_fs(snapmd_ctx *ctx, const snapmd_fs *coarse) {
+    if (!ctx) return SNAPMD_EINVAL;
+    if (!coarse) {
+        ctx->coarse_fs_on = false;
+        return SNAPMD_OK;
+    }
+    if (!(coarse->d > 0.0) || !(coarse->c > 0.0) || !std::isfinite(coarse->A) || !std::isfinite(coarse->c0) ||
+        !std::isfinite(coarse->c1) || !std::isfinite(coarse->c2))
+        return fail(ctx, SNAPMD_EINVAL, "coarse FS: need d, c > 0 and finite coefficients");
+    ctx->coarse_fs = *coarse;
+    ctx->coarse_fs_on = true;
     return SNAPMD_OK;
 }
 

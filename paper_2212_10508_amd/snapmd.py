@@ -97,6 +97,8 @@ def lib():
     L.snapmd_relax.argtypes = [P, C.c_int, C.POINTER(Snap), C.POINTER(Fs), C.POINTER(Batch), P, i32, d, d, d,
                                C.POINTER(d), C.POINTER(i32), P]
     L.snapmd_relax.restype = C.c_int
+    L.snapmd_set_coarse_fs.argtypes = [P, C.POINTER(Fs)]
+    L.snapmd_set_coarse_fs.restype = C.c_int
     L.snapmd_set_coarse_snap.argtypes = [P, C.POINTER(Snap)]
     L.snapmd_set_coarse_snap.restype = C.c_int
     L.snapmd_set_chunk_plan.argtypes = [P, C.POINTER(i32), i32]
@@ -384,6 +386,15 @@ class Context:
         k = _Keep()
         s = make_snap(k, J, beta, rcut, rfac0, rmin0)
         self._check(lib().snapmd_set_coarse_snap(self.h, C.byref(s)))
+
+    def set_coarse_fs(self, fs):
+        """Finnis-Sinclair parameters of the coarse propagator of parareal_iterate (a dict like
+        the fs argument; None: the fs passed to each call)."""
+        if fs is None:
+            self._check(lib().snapmd_set_coarse_fs(self.h, None))
+        else:
+            p_fs = make_fs(fs)
+            self._check(lib().snapmd_set_coarse_fs(self.h, C.byref(p_fs)))
 
     def set_chunk_plan(self, sizes):
         """Slab chunks of parareal_iterate for windows of sum(sizes) slabs (None or []:
