@@ -14,6 +14,7 @@
  *   langevin_steps    BAOAB Langevin steps for a ragged batch of systems
  *   parareal_iterate  one corrected iteration of adaptive parareal, every system on
  *                     a window of its own
+ *   parareal_adaptive the whole adaptive algorithm for many replicas, decided on the device
  *   snap_beta_grad    dE/dbeta and d(force loss)/dbeta (SNAP coefficient gradients)
  *
  * Conventions (every entry point):
@@ -223,6 +224,46 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
                      const int32_t *n_in, int32_t *n_fi, int32_t n_slots, double *q_prev,
                      double *p_prev, double *q_cur, double *p_cur, double delta_expl,
                      double *delta_out, void *stream);
+
+/* Iteration log of parareal_adaptive (host arrays owned by the caller): entry t of system
+ * r (index r * max_log + t) describes its t-th corrected iteration: the window
+ * [n_in, n_fi] it ran on, the window end after it (shorter when the relative error passed
+ * delta_expl) and the relative error delta at its end.  n_log[r] receives the number of
+ * iterations of system r (entries beyond max_log are counted but not stored). */
+typedef struct {
+    int32_t max_log;
+    int32_t *n_log;                         /* host [n_sys]            */
+    int32_t *n_in, *n_fi, *n_fi_after;      /* host [n_sys * max_log]  */
+    double *delta;                          /* host [n_sys * max_log]  */
+} snapmd_parareal_log;
+
+/* The whole adaptive parareal algorithm ("Adaptive parareal method", Algorithm "Adaptive
+ * parareal algorithm") for every system of the batch at once, with its branch logic and
+ * window bookkeeping on the device: each system r runs the algorithm on its own sequence
+ * of windows (tentative window [n_in, min(N, n_in + max_window)], initialised by a coarse
+ * sweep, corrected until delta < delta_conv, shortened when delta > delta_expl, as
+ * parareal_iterate does one iteration) over N slabs of L steps, with noise stream
+ * lang->noise_id_sys[r] at temperature lang->T_sys[r].
+ * q, p: device [N+1][3][n_atoms] (the slot layout of parareal_iterate); slot 0 holds the
+ * initial states on entry; on return every slot holds the converged trajectory.
+ * The call enqueues rounds of one fixed launch sequence (start of new windows,
+ * initialisation sweeps, the corrected iteration of every running system with max_window
+ * slabs per system in the batched propagation (slabs beyond a shortened window are
+ * propagated and discarded, keeping the launch shapes fixed), the sweeps, the
+ * algorithm's decisions) and synchronises only every rounds_per_check rounds to see which
+ * systems are done (those leave the batch) and to report errors; it returns when every
+ * system has reached slab N, or fails after max_rounds rounds.  *rounds_out and
+ * *checks_out receive the rounds enqueued and the synchronisations made.
+ * Needs BAOAB, a Finnis-Sinclair coarse potential (snapmd_set_coarse_fs applies) and
+ * systems that fit the on-device sweep (else SNAPMD_EUNSUPPORTED); 0 <= delta_conv <
+ * delta_expl < inf.  Errors: SNAPMD_EINVAL, SNAPMD_ENONFINITE (names the system and
+ * slab), SNAPMD_EOVERFLOW. */
+int parareal_adaptive(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs,
+                      const snapmd_batch *batch, const snapmd_langevin *lang, int32_t L, int32_t N,
+                      int32_t max_window, double delta_conv, double delta_expl,
+                      int32_t rounds_per_check, int32_t max_rounds, double *q, double *p,
+                      snapmd_parareal_log *log, int32_t *rounds_out, int32_t *checks_out,
+                      void *stream);
 
 /* Coarse propagator of parareal_iterate.  By default it is Finnis-Sinclair alone (the
  * paper's strategy II: an EAM coarse potential).  snapmd_set_coarse_snap(ctx, coarse)

@@ -77,9 +77,17 @@ struct snapmd_ctx {
     // parareal over several systems: offsets, windows, jumps in the slot layout, entry
     // sources, sweep arguments and results
     DBuf<int> m_off;
-    DBuf<int2> m_win, m_src;
+    DBuf<int2> m_win;
+    DBuf<int4> m_src;
     DBuf<double> m_jq, m_jp, m_out;
     DBuf<unsigned char> m_tab;
+    // device-resident adaptive driver
+    DBuf<double> dr_qprev, dr_pprev, dr_out_init, dr_out_it, dr_sig, dr_sb, dr_box, dr_logd;
+    DBuf<DrvState> dr_st;
+    DBuf<int> dr_act, dr_roff, dr_eoff, dr_noise, dr_err;
+    DBuf<int4> dr_ent, dr_cells, dr_logi;
+    DBuf<int64_t> dr_step0;
+    DBuf<unsigned char> dr_tab_init, dr_tab_it;
     DBuf<double> gB;                              // [K][N] bispectrum / its variation
     // cell grids of the current batch for the last list cutoff, one set per workspace
     struct CellState {
@@ -508,7 +516,7 @@ int neighbors(snapmd_ctx *ctx, Work &w, const BatchDev &bd0, const double *x, do
               hipStream_t st, bool in_step = false) {
     BatchDev bd = bd0;
     int r;
-    if ((r = prepare_cells(ctx, w, bd, rc + kSkin, st))) return r;
+    if (!bd.cells_given && (r = prepare_cells(ctx, w, bd, rc + kSkin, st))) return r;
     // within a propagation step the displacement test ran in k_baoab_pre and k_fs_rho
     // clears the rebuild flag
     launch_neighbors(bd, x, rc, w, st, force, kSkin, in_step && !force, in_step);
@@ -653,16 +661,16 @@ int replay_range(snapmd_ctx *ctx, Work &w, double *f, int potential, const Batch
 // they are.  The segments bound the length of every captured chain: a capture of
 // 10,000 steps, one linear chain of about 160,000 kernel nodes, ended the process with
 // a host segmentation fault (see the design notes on graph captures).
-int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
-                       const SnapDev &sd, const LangevinDev &ld, int n_steps, double *x, double *p,
-                       hipStream_t st) {
+// The same with the batch's cell grids already in bd (set up by the caller).
+int run_langevin_prepared(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
+                          const SnapDev &sd, const LangevinDev &ld, int n_steps, double *x, double *p,
+                          hipStream_t st) {
     // SNAP propagation stays eager while kernel timing is on (the events time each launch)
     if (!ctx->use_graphs || (ctx->prof.enabled && potential == SNAPMD_POT_FS_SNAP)) {
         run_langevin(ctx, w, f, potential, bd, fp, sd, ld, n_steps, x, p, st);
         return SNAPMD_OK;
     }
     int rc;
-    if ((rc = prepare_propagation_cells(ctx, w, potential, bd, fp, sd, st))) return rc;
     if (n_steps <= kGraphMaxSteps)
         return replay_range(ctx, w, f, potential, bd, fp, sd, ld, 0, n_steps, n_steps, true, x, p, st);
     const int ci = (&w == &ctx->wc) ? 1 : 0;
@@ -689,6 +697,16 @@ int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const
             return rc;
     }
     return check_launch(ctx);
+}
+
+int run_langevin_graph(snapmd_ctx *ctx, Work &w, double *f, int potential, const BatchDev &bd, const FsParams &fp,
+                       const SnapDev &sd, const LangevinDev &ld, int n_steps, double *x, double *p,
+                       hipStream_t st) {
+    if (ctx->use_graphs && !(ctx->prof.enabled && potential == SNAPMD_POT_FS_SNAP)) {
+        int rc;
+        if ((rc = prepare_propagation_cells(ctx, w, potential, bd, fp, sd, st))) return rc;
+    }
+    return run_langevin_prepared(ctx, w, f, potential, bd, fp, sd, ld, n_steps, x, p, st);
 }
 
 // Per-system Langevin arrays (sigma, step offsets, noise ids) uploaded to the context.
@@ -1239,7 +1257,7 @@ int parareal_multi(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs
             std::vector<double> boxes(3 * (size_t)ne), T(ne);
             std::vector<int64_t> step0(ne);
             std::vector<int> nid(ne);
-            std::vector<int2> src(ne);
+            std::vector<int4> src(ne);
             for (int k = 0; k < ne; ++k) {
                 const Ent &e = ent[cut[c] + k];
                 boff[k + 1] = boff[k] + (off[e.r + 1] - off[e.r]);
@@ -1247,7 +1265,7 @@ int parareal_multi(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs
                 T[k] = lang->T_sys[e.r];
                 step0[k] = (int64_t)e.n * L;
                 nid[k] = lang->noise_id_sys[e.r];
-                src[k] = make_int2(e.n, off[e.r]);
+                src[k] = make_int4(e.n, off[e.r], e.n, 0);
             }
             const int Nc = boff[ne];
             snapmd_batch sb{ne, boff.data(), boxes.data()};
@@ -1258,7 +1276,7 @@ int parareal_multi(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs
             if ((rc = prepare_batch(ctx, &sb, bd, mh2, st)) || (rc = prepare_snap(ctx, snap, mh2, sd, st)) ||
                 (rc = prepare_langevin(ctx, lang, ne, T, step0, nid, ldv, st)))
                 return rc;
-            int2 *dsrc = ctx->m_src.p + cut[c];
+            int4 *dsrc = ctx->m_src.p + cut[c];
             if ((rc = upload(ctx, dsrc, src.data(), (size_t)ne, st))) return rc;
             launch_entries_to_batch(Nc, ne, bd.off, dsrc, Nt, q_prev, ctx->pr_xf.p, st);
             launch_entries_to_batch(Nc, ne, bd.off, dsrc, Nt, p_prev, ctx->pr_pf.p, st);
@@ -1693,6 +1711,294 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
                             delta_out, st, stream);
     return parareal_multi(ctx, snap, fs, batch, lang, L, n_in, n_fi, n_slots, q_prev, p_prev, q_cur, p_cur, delta_expl,
                           delta_out, st, stream);
+}
+
+// Device-resident adaptive parareal over a batch of replicas (the paper's Algorithm
+// "Adaptive parareal algorithm" for every replica at once).  The host enqueues rounds of a
+// fixed launch sequence and synchronises only every rounds_per_check rounds; between
+// checks every decision is taken on the device.
+int parareal_adaptive(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, const snapmd_batch *batch,
+                      const snapmd_langevin *lang, int32_t L, int32_t N, int32_t max_window, double delta_conv,
+                      double delta_expl, int32_t rounds_per_check, int32_t max_rounds, double *q, double *p,
+                      snapmd_parareal_log *log, int32_t *rounds_out, int32_t *checks_out, void *stream) {
+    if (!ctx) return SNAPMD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc;
+    if ((rc = check_lang(ctx, lang))) return rc;
+    if (!batch || batch->n_sys < 1 || !batch->offset || !batch->box)
+        return fail(ctx, SNAPMD_EINVAL, "parareal_adaptive needs a batch of at least one system");
+    if (!q || !p) return fail(ctx, SNAPMD_EINVAL, "q and p must be device pointers");
+    if (!log || !log->n_log || log->max_log < 0 ||
+        (log->max_log > 0 && (!log->n_in || !log->n_fi || !log->n_fi_after || !log->delta)))
+        return fail(ctx, SNAPMD_EINVAL, "log and its host arrays must be set");
+    if (!rounds_out || !checks_out) return fail(ctx, SNAPMD_EINVAL, "rounds_out and checks_out must be host pointers");
+    if (L < 1 || N < 1 || max_window < 1 || rounds_per_check < 1 || max_rounds < 1)
+        return fail(ctx, SNAPMD_EINVAL, "need L, N, max_window, rounds_per_check, max_rounds >= 1");
+    if (!(delta_conv >= 0.0) || !(delta_expl > delta_conv) || !std::isfinite(delta_expl))
+        return fail(ctx, SNAPMD_EINVAL, "need 0 <= delta_conv < delta_expl < inf");
+    if (lang->scheme != SNAPMD_SCHEME_BAOAB || ctx->coarse_snap_on)
+        return fail(ctx, SNAPMD_EUNSUPPORTED, "parareal_adaptive runs BAOAB with a Finnis-Sinclair coarse potential");
+    const int R = batch->n_sys;
+    const int *off = batch->offset;
+    if (off[0] != 0) return fail(ctx, SNAPMD_EINVAL, "batch.offset[0] must be 0");
+    double mh = INFINITY;
+    int maxN = 0;
+    for (int r = 0; r < R; ++r) {
+        const int Nr = off[r + 1] - off[r];
+        if (Nr < 1) return fail(ctx, SNAPMD_EINVAL, "system %d has no atoms", r);
+        if (!sweep_fits_lds(Nr))
+            return fail(ctx, SNAPMD_EUNSUPPORTED, "system %d (%d atoms) is too large for the on-device sweep", r, Nr);
+        if (!(lang->T_sys[r] >= 0.0) || lang->noise_id_sys[r] < 0)
+            return fail(ctx, SNAPMD_EINVAL, "need T_sys[%d] >= 0 and noise_id_sys[%d] >= 0", r, r);
+        maxN = std::max(maxN, Nr);
+        for (int a = 0; a < 3; ++a) {
+            const double b = batch->box[3 * r + a];
+            if (!(b > 0.0) || !std::isfinite(b))
+                return fail(ctx, SNAPMD_EINVAL, "box edge %d of system %d must be finite and > 0", a, r);
+            mh = std::min(mh, 0.5 * b);
+        }
+    }
+    const int Nt = off[R];
+    FsParams fp, fpc;
+    if ((rc = prepare_fs(ctx, fs, mh, fp)) || (rc = coarse_fs(ctx, fp, mh, fpc))) return rc;
+    const double skin = kSweepSkin;
+    if (!(std::max(fpc.d, fpc.c) + 2.0 * skin < mh))
+        return fail(ctx, SNAPMD_EINVAL, "FS cutoff + %g A must be < half the smallest box edge", 2.0 * skin);
+    SnapDev sd, sdc;
+    if ((rc = prepare_snap(ctx, snap, mh, sd, st))) return rc;
+    const int W = std::min(max_window, N);
+    const size_t SS = (size_t)(N + 1) * 3 * Nt, RW = (size_t)R * W;
+    const size_t ab = sweep_args_bytes();
+    const int ML = log->max_log;
+    // every buffer before the first round (an allocation drops the captured sequences)
+    long max_chunk = 0;
+    {
+        long acc = 0;
+        for (int r = 0; r < R; ++r)
+            for (int s2 = 0; s2 < W; ++s2) {
+                const long na = off[r + 1] - off[r];
+                if (acc > 0 && acc + na > kMultiChunkAtoms) {
+                    max_chunk = std::max(max_chunk, acc);
+                    acc = 0;
+                }
+                acc += na;
+            }
+        max_chunk = std::max(max_chunk, acc);
+    }
+    const size_t M3 = 3 * (size_t)max_chunk;
+    if ((rc = ensure(ctx, ctx->dr_qprev, SS)) || (rc = ensure(ctx, ctx->dr_pprev, SS)) ||
+        (rc = ensure(ctx, ctx->m_jq, SS)) || (rc = ensure(ctx, ctx->m_jp, SS)) ||
+        (rc = ensure(ctx, ctx->dr_st, (size_t)R)) || (rc = ensure(ctx, ctx->dr_act, (size_t)R)) ||
+        (rc = ensure(ctx, ctx->dr_roff, (size_t)R + 1)) || (rc = ensure(ctx, ctx->m_win, (size_t)R)) ||
+        (rc = ensure(ctx, ctx->dr_tab_init, ab * R)) || (rc = ensure(ctx, ctx->dr_tab_it, ab * R)) ||
+        (rc = ensure(ctx, ctx->dr_out_init, 8 * (size_t)R)) || (rc = ensure(ctx, ctx->dr_out_it, 8 * (size_t)R)) ||
+        (rc = ensure(ctx, ctx->dr_ent, RW)) || (rc = ensure(ctx, ctx->dr_step0, RW)) ||
+        (rc = ensure(ctx, ctx->dr_sig, RW)) || (rc = ensure(ctx, ctx->dr_sb, RW)) ||
+        (rc = ensure(ctx, ctx->dr_noise, RW)) || (rc = ensure(ctx, ctx->dr_eoff, RW + (size_t)R * W + 1)) ||
+        (rc = ensure(ctx, ctx->dr_box, 3 * RW)) || (rc = ensure(ctx, ctx->dr_cells, RW)) ||
+        (rc = ensure(ctx, ctx->dr_logi, (size_t)R * std::max(ML, 1))) ||
+        (rc = ensure(ctx, ctx->dr_logd, (size_t)R * std::max(ML, 1))) || (rc = ensure(ctx, ctx->dr_err, 1)) ||
+        (rc = ensure(ctx, ctx->pr_xf, M3)) || (rc = ensure(ctx, ctx->pr_pf, M3)) ||
+        (rc = ensure(ctx, ctx->pr_xc, M3)) || (rc = ensure(ctx, ctx->pr_pc, M3)) ||
+        (rc = ensure(ctx, ctx->seg_step0[0], RW)) || (rc = ensure(ctx, ctx->seg_step0[1], RW)))
+        return rc;
+    if ((rc = ensure_atoms(ctx, (size_t)max_chunk)) || (rc = ensure_atoms_coarse(ctx, (size_t)max_chunk, false)))
+        return rc;
+    // initial state of every replica: a new window starts at slab 0
+    {
+        std::vector<DrvState> s0(R);
+        for (auto &v : s0) v = DrvState{DRV_NEW, 0, 0, 0, 0.0, 0, -1};
+        const int zero = 0;
+        if ((rc = upload(ctx, ctx->dr_st.p, s0.data(), (size_t)R, st)) || (rc = upload(ctx, ctx->dr_err.p, &zero, 1, st)) ||
+            (rc = upload(ctx, ctx->dr_roff.p, off, (size_t)R + 1, st)))
+            return rc;
+    }
+    const double c1 = std::exp(-lang->gamma * lang->dt);
+    std::vector<DrvState> hs(R);
+    std::vector<int> act;
+    for (int r = 0; r < R; ++r) act.push_back(r);
+    int rounds = 0, checks = 0;
+    struct Chunk {
+        BatchDev bd;
+        LangevinDev ld;
+        int e0, ne, Nc;
+    };
+    while (!act.empty()) {
+        // tables of the replicas still running: their sweep arguments, and the W entries
+        // of each in the batch, cut into chunks
+        const int Ra = (int)act.size();
+        std::vector<unsigned char> tin(ab * Ra), tit(ab * Ra);
+        std::vector<int> eoff;
+        std::vector<double> sig(Ra * (size_t)W), sb(Ra * (size_t)W, 0.0), bx(3 * (size_t)Ra * W);
+        std::vector<int> nid(Ra * (size_t)W);
+        std::vector<int4> cells(Ra * (size_t)W);
+        std::vector<Chunk> chunks;
+        const double rl = std::max(std::max(fp.d, fp.c), sd.gp.rcut) + kSkin;
+        const double rlc = std::max(fpc.d, fpc.c) + kSkin;
+        Chunk cur{};
+        auto close_chunk = [&](int e_end) {
+            if (cur.ne == 0) return;
+            chunks.push_back(cur);
+            (void)e_end;
+            cur = Chunk{};
+        };
+        std::vector<int> chunk_first_off;  // start of each chunk's relative offsets in eoff
+        for (int k = 0; k < Ra; ++k) {
+            const int r = act[k], Nr = off[r + 1] - off[r];
+            const double *box = batch->box + 3 * r;
+            SweepLaunch sw{};
+            sw.N = Nr;
+            for (int a = 0; a < 3; ++a) sw.box[a] = box[a];
+            sw.fp = fpc;
+            sw.skin = skin;
+            sw.dt = lang->dt;
+            sw.c1 = c1;
+            sw.mass = lang->mass;
+            sw.sig = std::sqrt((1.0 - c1 * c1) * lang->mass * kKB * lang->T_sys[r] / kMVV2E);
+            sw.seed = lang->seed;
+            sw.noise_id = (uint64_t)lang->noise_id_sys[r];
+            sw.L = L;
+            sw.delta_expl = delta_expl;
+            int nc[3];
+            for (int a = 0; a < 3; ++a) nc[a] = (int)std::floor(box[a] / (std::max(fpc.d, fpc.c) + skin));
+            while ((long)nc[0] * nc[1] * nc[2] > 512) *std::max_element(nc, nc + 3) -= 1;
+            if (nc[0] < 3 || nc[1] < 3 || nc[2] < 3) nc[0] = nc[1] = nc[2] = 0;
+            sw.ncx = nc[0];
+            sw.ncy = nc[1];
+            sw.ncz = nc[2];
+            sw.q_cur = q + off[r];
+            sw.p_cur = p + off[r];
+            sw.noise = nullptr;
+            sw.mode = 0;
+            sw.out = ctx->dr_out_init.p + 8 * (size_t)k;
+            fill_sweep_args(sw, (size_t)Nt, (size_t)Nt, 3 * (size_t)Nt, tin.data() + ab * k);
+            sw.mode = 1;
+            sw.q_prev = ctx->dr_qprev.p + off[r];
+            sw.p_prev = ctx->dr_pprev.p + off[r];
+            sw.out = ctx->dr_out_it.p + 8 * (size_t)k;
+            fill_sweep_args(sw, (size_t)Nt, (size_t)Nt, 3 * (size_t)Nt, tit.data() + ab * k);
+            // entries of replica r: k W .. k W + W - 1
+            int n3[3];
+            for (int a = 0; a < 3; ++a) n3[a] = (int)std::floor(box[a] / std::max(rl, rlc));
+            const bool use_cells = n3[0] >= 3 && n3[1] >= 3 && n3[2] >= 3 && Nr >= 500;
+            for (int s2 = 0; s2 < W; ++s2) {
+                const int e = k * W + s2;
+                if (cur.ne > 0 && (long)cur.Nc + Nr > kMultiChunkAtoms) close_chunk(e);
+                if (cur.ne == 0) {
+                    cur.e0 = e;
+                    chunk_first_off.push_back((int)eoff.size());
+                    eoff.push_back(0);
+                }
+                cur.ne += 1;
+                cur.Nc += Nr;
+                eoff.push_back(cur.Nc);
+                cur.bd.max_sys = std::max(cur.bd.max_sys, Nr);
+                sig[e] = sw.sig;
+                nid[e] = lang->noise_id_sys[r];
+                for (int a = 0; a < 3; ++a) bx[3 * (size_t)e + a] = box[a];
+                cells[e] = use_cells ? make_int4(n3[0], n3[1], n3[2], 0) : make_int4(0, 0, 0, 0);
+                if (use_cells) cur.bd.n_cells += n3[0] * n3[1] * n3[2];
+            }
+        }
+        close_chunk(Ra * W);
+        if ((rc = upload(ctx, ctx->dr_act.p, act.data(), (size_t)Ra, st)) ||
+            (rc = upload(ctx, ctx->dr_tab_init.p, tin.data(), tin.size(), st)) ||
+            (rc = upload(ctx, ctx->dr_tab_it.p, tit.data(), tit.size(), st)) ||
+            (rc = upload(ctx, ctx->dr_eoff.p, eoff.data(), eoff.size(), st)) ||
+            (rc = upload(ctx, ctx->dr_sig.p, sig.data(), sig.size(), st)) ||
+            (rc = upload(ctx, ctx->dr_sb.p, sb.data(), sb.size(), st)) ||
+            (rc = upload(ctx, ctx->dr_noise.p, nid.data(), nid.size(), st)) ||
+            (rc = upload(ctx, ctx->dr_box.p, bx.data(), bx.size(), st)) ||
+            (rc = upload(ctx, ctx->dr_cells.p, cells.data(), cells.size(), st)))
+            return rc;
+        for (size_t c = 0; c < chunks.size(); ++c) {
+            Chunk &ch = chunks[c];
+            BatchDev &b = ch.bd;
+            b.N = ch.Nc;
+            b.n_sys = ch.ne;
+            b.off = ctx->dr_eoff.p + chunk_first_off[c];
+            b.box = ctx->dr_box.p + 3 * (size_t)ch.e0;
+            b.cells = ctx->dr_cells.p + ch.e0;
+            b.cells_given = 1;
+            LangevinDev &l = ch.ld;
+            l.dt = lang->dt;
+            l.c1 = c1;
+            l.mass = lang->mass;
+            l.seed = lang->seed;
+            l.sig = ctx->dr_sig.p + ch.e0;
+            l.step0 = ctx->dr_step0.p + ch.e0;
+            l.noise_id = ctx->dr_noise.p + ch.e0;
+            l.scheme = SNAPMD_SCHEME_BAOAB;
+            l.gamma = lang->gamma;
+            l.sb0 = l.sb1 = ctx->dr_sb.p + ch.e0;
+        }
+        for (int it = 0; it < rounds_per_check && rounds < max_rounds; ++it, ++rounds) {
+            launch_drv_start(Ra, ctx->dr_act.p, ctx->dr_st.p, N, W, ctx->dr_tab_init.p, ctx->dr_out_init.p, st);
+            launch_coarse_sweep_multi(ctx->dr_tab_init.p, Ra, maxN, st);
+            launch_drv_iter(Ra, ctx->dr_act.p, R, ctx->dr_st.p, W, L, (size_t)Nt, ctx->dr_roff.p, ctx->dr_ent.p,
+                            ctx->dr_step0.p, ctx->dr_tab_it.p, ctx->dr_out_it.p, ctx->m_win.p, ctx->m_jq.p, ctx->m_jp.p,
+                            st);
+            launch_copy_windows(N + 1, Nt, R, ctx->dr_roff.p, ctx->m_win.p, q, p, ctx->dr_qprev.p, ctx->dr_pprev.p, st);
+            for (const Chunk &ch : chunks) {
+                const int4 *ent = ctx->dr_ent.p + ch.e0;
+                launch_entries_to_batch(ch.Nc, ch.ne, ch.bd.off, ent, Nt, ctx->dr_qprev.p, ctx->pr_xf.p, st);
+                launch_entries_to_batch(ch.Nc, ch.ne, ch.bd.off, ent, Nt, ctx->dr_pprev.p, ctx->pr_pf.p, st);
+                HIPCHK(hipMemcpyAsync(ctx->pr_xc.p, ctx->pr_xf.p, 3 * (size_t)ch.Nc * sizeof(double),
+                                      hipMemcpyDeviceToDevice, st));
+                HIPCHK(hipMemcpyAsync(ctx->pr_pc.p, ctx->pr_pf.p, 3 * (size_t)ch.Nc * sizeof(double),
+                                      hipMemcpyDeviceToDevice, st));
+                if ((rc = run_langevin_prepared(ctx, ctx->w, ctx->d_f, SNAPMD_POT_FS_SNAP, ch.bd, fp, sd, ch.ld, L,
+                                                ctx->pr_xf.p, ctx->pr_pf.p, st)) ||
+                    (rc = run_langevin_prepared(ctx, ctx->wc, ctx->d_fc, SNAPMD_POT_FS, ch.bd, fpc, sdc, ch.ld, L,
+                                                ctx->pr_xc.p, ctx->pr_pc.p, st)))
+                    return rc;
+                launch_batch_jumps_to_slots(ch.Nc, ch.ne, ch.bd.off, ent, Nt, ctx->pr_xf.p, ctx->pr_xc.p, ctx->m_jq.p,
+                                            st);
+                launch_batch_jumps_to_slots(ch.Nc, ch.ne, ch.bd.off, ent, Nt, ctx->pr_pf.p, ctx->pr_pc.p, ctx->m_jp.p,
+                                            st);
+            }
+            launch_coarse_sweep_multi(ctx->dr_tab_it.p, Ra, maxN, st);
+            launch_drv_update(Ra, ctx->dr_act.p, ctx->dr_st.p, ctx->dr_out_it.p, delta_conv, delta_expl, N, ML,
+                              ctx->dr_logi.p, ctx->dr_logd.p, ctx->dr_err.p, st);
+            if ((rc = check_launch(ctx))) return rc;
+        }
+        // check: the replicas' states (one synchronisation per rounds_per_check rounds)
+        HIPCHK(hipMemcpyAsync(hs.data(), ctx->dr_st.p, (size_t)R * sizeof(DrvState), hipMemcpyDeviceToHost, st));
+        if ((rc = snapmd_sync(ctx, stream))) return rc;
+        ++checks;
+        for (int r = 0; r < R; ++r) {
+            if (hs[r].err & 1)
+                return fail(ctx, SNAPMD_EOVERFLOW, "system %d: an atom of the coarse sweep has more than its list "
+                                                   "capacity of neighbours", r);
+            if (hs[r].err & 2)
+                return fail(ctx, SNAPMD_ENONFINITE, "state of system %d became non-finite in slab %d", r,
+                            hs[r].bad_slab);
+        }
+        act.clear();
+        for (int r = 0; r < R; ++r)
+            if (hs[r].phase != DRV_DONE) act.push_back(r);
+        if (!act.empty() && rounds >= max_rounds)
+            return fail(ctx, SNAPMD_EINVAL, "parareal_adaptive: %zu systems not converged after %d rounds",
+                        act.size(), rounds);
+    }
+    // the iteration logs
+    if (ML > 0) {
+        std::vector<int4> li((size_t)R * ML);
+        std::vector<double> ld((size_t)R * ML);
+        HIPCHK(hipMemcpy(li.data(), ctx->dr_logi.p, li.size() * sizeof(int4), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(ld.data(), ctx->dr_logd.p, ld.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (size_t q2 = 0; q2 < li.size(); ++q2) {
+            log->n_in[q2] = li[q2].x;
+            log->n_fi[q2] = li[q2].y;
+            log->n_fi_after[q2] = li[q2].z;
+            log->delta[q2] = ld[q2];
+        }
+    }
+    for (int r = 0; r < R; ++r) log->n_log[r] = hs[r].nlog;
+    *rounds_out = rounds;
+    *checks_out = checks;
+    return SNAPMD_OK;
 }
 
 int snapmd_ws_sites(snapmd_ctx *ctx, const snapmd_batch *batch, const double *x, double a, int32_t *site,

@@ -16,6 +16,7 @@ struct BatchDev {
     const int4 *cells = nullptr;  // [n_sys] (nx, ny, nz, first cell); nx = 0: brute force
     int n_cells = 0;
     int max_sys = 0;              // atoms of the largest system
+    int cells_given = 0;          // cells / n_cells set by the caller (no grid set-up from the context)
 };
 
 struct FsParams {
@@ -180,10 +181,23 @@ void launch_slab_end(int N, int mode, size_t jsa, size_t jss, size_t s, double *
 // batches of systems with windows of their own (slot layout [slot][3][ld])
 void launch_copy_windows(int n_slots, int ld, int n_sys, const int *off, const int2 *win, const double *q,
                          const double *p, double *qd, double *pd, hipStream_t st);
-void launch_entries_to_batch(int Nc, int n_ent, const int *off, const int2 *src, int ld, const double *state,
+void launch_entries_to_batch(int Nc, int n_ent, const int *off, const int4 *src, int ld, const double *state,
                              double *out, hipStream_t st);
-void launch_batch_jumps_to_slots(int Nc, int n_ent, const int *off, const int2 *src, int ld, const double *f,
+void launch_batch_jumps_to_slots(int Nc, int n_ent, const int *off, const int4 *src, int ld, const double *f,
                                  const double *c, double *jump, hipStream_t st);
+// device-resident adaptive driver: per-replica state of the adaptive algorithm
+enum { DRV_NEW = 0, DRV_ITER = 1, DRV_DONE = 2 };
+struct DrvState {
+    int phase, n_in, n_fi, nlog;
+    double delta;
+    int err, bad_slab;
+};
+void launch_drv_start(int Ra, const int *act, DrvState *st, int N, int W, void *tab, double *out, hipStream_t s);
+void launch_drv_iter(int Ra, const int *act, int R_all, const DrvState *st, int W, int L, size_t ld, const int *roff,
+                     int4 *ent, int64_t *step0, void *tab, double *out, int2 *win, const double *jq, const double *jp,
+                     hipStream_t s);
+void launch_drv_update(int Ra, const int *act, DrvState *st, const double *out, double dconv, double dexpl, int N,
+                       int max_log, int4 *logi, double *logd, int *err, hipStream_t s);
 // the sweep arguments of one system of a batch, in the layout the multi-system sweep reads
 size_t sweep_args_bytes();
 void fill_sweep_args(const SweepLaunch &s, size_t ld, size_t jsa, size_t jss, void *dst);

@@ -1118,27 +1118,30 @@ __global__ void k_copy_windows(int n_slots, int ld, int n_sys, const int *__rest
 }
 
 // entries -> batch: out[al][j] = state[slot_e][al][col_e + j - off[e]] for the Nc atoms of
-// a chunk of entries (src[e] = (slot_e, col_e), off = the chunk's atom offsets)
-__global__ void k_entries_to_batch(int Nc, int n_ent, const int *__restrict__ off, const int2 *__restrict__ src,
+// a chunk of entries (src[e] = (slot_e, col_e, slot its jump goes to or -1, -), off = the
+// chunk's atom offsets)
+__global__ void k_entries_to_batch(int Nc, int n_ent, const int *__restrict__ off, const int4 *__restrict__ src,
                                    int ld, const double *__restrict__ state, double *__restrict__ out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= Nc) return;
     const int e = find_seg(off, n_ent, j);
-    const int2 sc = src[e];
+    const int4 sc = src[e];
     const size_t base = (size_t)sc.x * 3 * ld + sc.y + (j - off[e]);
 #pragma unroll
     for (int al = 0; al < 3; ++al) out[(size_t)al * Nc + j] = state[base + (size_t)al * ld];
 }
 
-// jumps of a chunk into the slot layout: jump[slot_e][al][col_e + i] = f[al][j] - c[al][j]
-__global__ void k_batch_jumps_to_slots(int Nc, int n_ent, const int *__restrict__ off, const int2 *__restrict__ src,
+// jumps of a chunk into the slot layout: jump[dst_e][al][col_e + i] = f[al][j] - c[al][j]
+// (entries with dst_e < 0 were propagated only to keep the launch shape fixed)
+__global__ void k_batch_jumps_to_slots(int Nc, int n_ent, const int *__restrict__ off, const int4 *__restrict__ src,
                                        int ld, const double *__restrict__ f, const double *__restrict__ c,
                                        double *__restrict__ jump) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= Nc) return;
     const int e = find_seg(off, n_ent, j);
-    const int2 sc = src[e];
-    const size_t base = (size_t)sc.x * 3 * ld + sc.y + (j - off[e]);
+    const int4 sc = src[e];
+    if (sc.z < 0) return;
+    const size_t base = (size_t)sc.z * 3 * ld + sc.y + (j - off[e]);
 #pragma unroll
     for (int al = 0; al < 3; ++al) jump[base + (size_t)al * ld] = f[(size_t)al * Nc + j] - c[(size_t)al * Nc + j];
 }
@@ -1151,18 +1154,148 @@ void launch_copy_windows(int n_slots, int ld, int n_sys, const int *off, const i
                        win, q, p, qd, pd);
 }
 
-void launch_entries_to_batch(int Nc, int n_ent, const int *off, const int2 *src, int ld, const double *state,
+void launch_entries_to_batch(int Nc, int n_ent, const int *off, const int4 *src, int ld, const double *state,
                              double *out, hipStream_t st) {
     if (Nc <= 0) return;
     hipLaunchKernelGGL(k_entries_to_batch, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, st, Nc, n_ent, off, src,
                        ld, state, out);
 }
 
-void launch_batch_jumps_to_slots(int Nc, int n_ent, const int *off, const int2 *src, int ld, const double *f,
+void launch_batch_jumps_to_slots(int Nc, int n_ent, const int *off, const int4 *src, int ld, const double *f,
                                  const double *c, double *jump, hipStream_t st) {
     if (Nc <= 0) return;
     hipLaunchKernelGGL(k_batch_jumps_to_slots, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, st, Nc, n_ent, off,
                        src, ld, f, c, jump);
+}
+
+// ---------------------------------------------------------------------------
+// Device-resident adaptive driver: the branch logic and window bookkeeping of the
+// adaptive algorithm for every replica, in device memory, between the launches of a
+// round (start windows -> initialisation sweeps -> entries and windows of the corrected
+// iteration -> ... -> corrected sweeps -> update).  act[k] is the replica of active slot
+// k; tab_* and out_* are indexed by k, the state by replica.
+// ---------------------------------------------------------------------------
+// Window starts: a replica that needs a new time window gets [n_fi, min(N, n_fi + W)] and
+// an initialisation sweep over it; the others get an empty sweep.
+__global__ void k_drv_start(int Ra, const int *__restrict__ act, DrvState *__restrict__ st, int N, int W,
+                            SweepArgs *__restrict__ tab, double *__restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Ra) return;
+    const int r = act[k];
+    DrvState s = st[r];
+    SweepArgs &a = tab[k];
+    if (s.phase == DRV_NEW) {
+        s.n_in = s.n_fi;
+        s.n_fi = min(N, s.n_in + W);
+        s.phase = DRV_ITER;
+        st[r] = s;
+        a.n_in = s.n_in;
+        a.n_fi = s.n_fi;
+    } else {
+        a.n_in = a.n_fi = s.n_in;
+    }
+    a.n_win = a.n_in;
+    double *o = out + 8 * (size_t)k;
+    o[0] = 0.0;
+    o[1] = (double)a.n_fi;
+    o[2] = -1.0;
+    for (int q = 3; q < 8; ++q) o[q] = 0.0;
+}
+
+// Corrected iteration of every iterating replica: its window (for the prev := cur copy),
+// its sweep arguments, and the W entries (replica, slab) of its slot in the batch: slab
+// n_in + s for s < n_fi - n_in, else a filler (slab n_in, jump discarded) that keeps the
+// batch's shape fixed.  Threads: Ra * W entries, then R_all windows.
+__global__ void k_drv_iter(int Ra, const int *__restrict__ act, int R_all, const DrvState *__restrict__ st, int W,
+                           int L, size_t ld, const int *__restrict__ roff, int4 *__restrict__ ent,
+                           int64_t *__restrict__ step0, SweepArgs *__restrict__ tab, double *__restrict__ out,
+                           int2 *__restrict__ win, const double *__restrict__ jq, const double *__restrict__ jp) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < Ra * W) {
+        const int k = t / W, sl = t % W, r = act[k];
+        const DrvState s = st[r];
+        const bool live = s.phase == DRV_ITER && s.n_in + sl < s.n_fi;
+        const int slab = live ? s.n_in + sl : s.n_in;
+        ent[t] = make_int4(slab, roff[r], live ? slab : -1, 0);
+        step0[t] = (int64_t)slab * L;
+        if (sl == 0) {
+            SweepArgs &a = tab[k];
+            a.n_in = s.n_in;
+            a.n_fi = s.phase == DRV_ITER ? s.n_fi : s.n_in;
+            a.n_win = s.n_in;
+            a.jq = jq + (size_t)s.n_in * 3 * ld + roff[r];
+            a.jp = jp + (size_t)s.n_in * 3 * ld + roff[r];
+            double *o = out + 8 * (size_t)k;
+            o[0] = 0.0;
+            o[1] = (double)a.n_fi;
+            o[2] = -1.0;
+            for (int q = 3; q < 8; ++q) o[q] = 0.0;
+        }
+    } else if (t < Ra * W + R_all) {
+        const int r = t - Ra * W;
+        const DrvState s = st[r];
+        win[r] = s.phase == DRV_ITER ? make_int2(s.n_in, s.n_fi) : make_int2(0, 0);
+    }
+}
+
+// After the corrected sweeps: log the iteration and take the adaptive algorithm's next
+// step (stay on the window while delta_conv <= delta <= delta_expl; otherwise the run is
+// over at n_fi = N, a converged window starts the next one, and an exploded one was
+// shortened by the sweep and is iterated again).  A non-finite state or a list overflow
+// stops the replica and is recorded in err (bit 1 overflow, bit 2 non-finite).
+__global__ void k_drv_update(int Ra, const int *__restrict__ act, DrvState *__restrict__ st,
+                             const double *__restrict__ out, double dconv, double dexpl, int N, int max_log,
+                             int4 *__restrict__ logi, double *__restrict__ logd, int *__restrict__ err) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Ra) return;
+    const int r = act[k];
+    DrvState s = st[r];
+    if (s.phase != DRV_ITER) return;
+    const double *o = out + 8 * (size_t)k;
+    if (o[3] != 0.0 || o[2] >= 0.0) {
+        s.err = o[3] != 0.0 ? 1 : 2;
+        s.bad_slab = o[2] >= 0.0 ? (int)o[2] : -1;
+        s.phase = DRV_DONE;
+        atomicOr(err, s.err);
+        st[r] = s;
+        return;
+    }
+    const double delta = o[0];
+    const int window = s.n_fi, after = (int)o[1];
+    if (s.nlog < max_log) {
+        logi[(size_t)r * max_log + s.nlog] = make_int4(s.n_in, window, after, 0);
+        logd[(size_t)r * max_log + s.nlog] = delta;
+    }
+    ++s.nlog;
+    s.n_fi = after;
+    s.delta = delta;
+    if (!(dconv <= delta && delta <= dexpl)) {
+        if (s.n_fi >= N) s.phase = DRV_DONE;
+        else if (delta < dexpl) s.phase = DRV_NEW;
+        // else: the window was shortened; iterate on it again
+    }
+    st[r] = s;
+}
+
+void launch_drv_start(int Ra, const int *act, DrvState *st, int N, int W, void *tab, double *out, hipStream_t st_) {
+    if (Ra <= 0) return;
+    hipLaunchKernelGGL(k_drv_start, dim3((Ra + 63) / 64), dim3(64), 0, st_, Ra, act, st, N, W, (SweepArgs *)tab, out);
+}
+
+void launch_drv_iter(int Ra, const int *act, int R_all, const DrvState *st, int W, int L, size_t ld, const int *roff,
+                     int4 *ent, int64_t *step0, void *tab, double *out, int2 *win, const double *jq, const double *jp,
+                     hipStream_t s_) {
+    const int tot = Ra * W + R_all;
+    if (tot <= 0) return;
+    hipLaunchKernelGGL(k_drv_iter, dim3((tot + 255) / 256), dim3(256), 0, s_, Ra, act, R_all, st, W, L, ld, roff, ent,
+                       step0, (SweepArgs *)tab, out, win, jq, jp);
+}
+
+void launch_drv_update(int Ra, const int *act, DrvState *st, const double *out, double dconv, double dexpl, int N,
+                       int max_log, int4 *logi, double *logd, int *err, hipStream_t s_) {
+    if (Ra <= 0) return;
+    hipLaunchKernelGGL(k_drv_update, dim3((Ra + 63) / 64), dim3(64), 0, s_, Ra, act, st, out, dconv, dexpl, N,
+                       max_log, logi, logd, err);
 }
 
 // LDS sweeps of n systems at once (tab: device [n] arguments, one workgroup each; every

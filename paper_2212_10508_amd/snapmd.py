@@ -47,6 +47,12 @@ class Langevin(C.Structure):
                 ("scheme", C.c_int32), ("bbk_c0", C.c_double), ("bbk_c1", C.c_double)]
 
 
+class ParaLog(C.Structure):
+    _fields_ = [("max_log", C.c_int32), ("n_log", C.POINTER(C.c_int32)), ("n_in", C.POINTER(C.c_int32)),
+                ("n_fi", C.POINTER(C.c_int32)), ("n_fi_after", C.POINTER(C.c_int32)),
+                ("delta", C.POINTER(C.c_double))]
+
+
 _lib = None
 
 
@@ -80,6 +86,10 @@ def lib():
     L.parareal_iterate.argtypes = [P, C.POINTER(Snap), C.POINTER(Fs), C.POINTER(Batch), C.POINTER(Langevin),
                                    i32, C.POINTER(i32), C.POINTER(i32), i32, P, P, P, P, d, C.POINTER(d), P]
     L.parareal_iterate.restype = C.c_int
+    L.parareal_adaptive.argtypes = [P, C.POINTER(Snap), C.POINTER(Fs), C.POINTER(Batch), C.POINTER(Langevin),
+                                    i32, i32, i32, d, d, i32, i32, P, P, C.POINTER(ParaLog), C.POINTER(i32),
+                                    C.POINTER(i32), P]
+    L.parareal_adaptive.restype = C.c_int
     L.snap_beta_grad.argtypes = [P, C.POINTER(Snap), C.POINTER(Batch), P, P, P, P, P]
     L.snap_beta_grad.restype = C.c_int
     L.snapmd_bispectrum.argtypes = [P, C.POINTER(Snap), C.POINTER(Batch), P, P, P]
@@ -328,6 +338,49 @@ class Context:
             _dev(q_cur, "q_cur", shape), _dev(p_cur, "p_cur", shape), float(delta_expl),
             delta.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
         return delta, nfi
+
+    def parareal_adaptive(self, q, p, offset, box, N, L, delta_conv, delta_expl, *, dt, gamma, mass, T, seed,
+                          noise_id, fs, J, beta, max_window=None, rounds_per_check=4, max_rounds=10000,
+                          max_log=256, rcut=4.73, rfac0=0.99363, rmin0=0.0, stream=None):
+        """The adaptive algorithm for every system of the batch, decided on the device.
+        q, p: device [N+1, 3, offset[-1]] with the initial states in slot 0; on return they
+        hold the converged trajectories.  Returns dict(logs (per system, one dict per
+        iteration: n_in, n_fi, n_fi_after, delta), n_ad, kconv, rounds, checks)."""
+        R = len(offset) - 1
+        nt = int(offset[-1])
+        k = _Keep()
+        b = make_batch(k, offset, box)
+        s = make_snap(k, J, beta, rcut, rfac0, rmin0)
+        p_fs = make_fs(fs)
+        lg = make_langevin(k, R, dt, gamma, mass, T, seed, 0, noise_id, "baoab")
+        ML = int(max_log)
+        n_log = np.zeros(R, np.int32)
+        a_in = np.zeros(R * max(ML, 1), np.int32)
+        a_fi = np.zeros_like(a_in)
+        a_af = np.zeros_like(a_in)
+        a_d = np.zeros(R * max(ML, 1), np.float64)
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        lgs = ParaLog(ML, ip(n_log), ip(a_in), ip(a_fi), ip(a_af), a_d.ctypes.data_as(C.POINTER(C.c_double)))
+        rounds, checks = C.c_int32(0), C.c_int32(0)
+        shape = (int(N) + 1, 3, nt)
+        self._check(lib().parareal_adaptive(
+            self.h, C.byref(s), C.byref(p_fs), C.byref(b), C.byref(lg), int(L), int(N),
+            int(max_window if max_window is not None else N), float(delta_conv), float(delta_expl),
+            int(rounds_per_check), int(max_rounds), _dev(q, "q", shape), _dev(p, "p", shape), C.byref(lgs),
+            C.byref(rounds), C.byref(checks), _stream(stream)))
+        logs, n_ad, kconv = [], [], []
+        for r in range(R):
+            rows = [dict(n_in=int(a_in[r * ML + t]), n_fi=int(a_fi[r * ML + t]), n_fi_after=int(a_af[r * ML + t]),
+                         delta=float(a_d[r * ML + t])) for t in range(min(int(n_log[r]), ML))]
+            logs.append(rows)
+            kc = []
+            for t, row in enumerate(rows):
+                if t == 0 or row["n_in"] != rows[t - 1]["n_in"]:
+                    kc.append(0)
+                kc[-1] += 1
+            n_ad.append(len(kc))
+            kconv.append(kc)
+        return dict(logs=logs, n_ad=n_ad, kconv=kconv, rounds=rounds.value, checks=checks.value)
 
     # -- measurement ---------------------------------------------------------
     PROF_DEDR, PROF_ADJOINT, PROF_DENSITY, PROF_NEIGH = 0, 1, 2, 3

@@ -435,3 +435,49 @@ def test_batch_iteration_leaves_other_windows_alone(S):
                                        noise_id=nids[r], **kw)
         assert nf1 == nf[r] and abs(d1 - d[r]) <= 1e-12 * d1
         assert torch.max(torch.abs(q1 - q[:, :, cols])).item() < 1e-12 * torch.max(torch.abs(q1)).item()
+
+
+@pytest.mark.parametrize("check_every", [1, 3])
+def test_device_resident_driver_matches_oracle_and_host_driver(S, check_every):
+    """The whole adaptive algorithm decided on the device for three replicas (129, 433,
+    1025 atoms; own temperatures and noise streams): the same window logs, iteration
+    counts and converged states as the oracle's literal driver run replica by replica and
+    as the host driver over parareal_iterate; the host synchronises only every
+    check_every rounds."""
+    from paper_2212_10508_amd import parareal as PR
+    J, N, L = 2, 5, 4
+    xs, ps, boxes, off = _replicas((4, 6, 8), J=J)
+    R = len(xs)
+    beta = W.snap_beta(J, seed=31, scale=2e-2)
+    Ts = [900.0 + 150.0 * k for k in range(R)]
+    nids = [3 + 2 * k for k in range(R)]
+    conv, expl = 1e-12, 1e-7
+    kw = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=Ts, seed=77, noise_id=nids, fs=W.FS_W, J=J, beta=beta)
+    ctx = S.Context(0)
+    q = torch.zeros((N + 1, 3, int(off[-1])), dtype=torch.float64, device="cuda")
+    pq = torch.zeros_like(q)
+    q[0] = dev(np.concatenate(xs, axis=1))
+    pq[0] = dev(np.concatenate(ps, axis=1))
+    res = ctx.parareal_adaptive(q, pq, off, np.array(boxes), N, L, conv, expl, rounds_per_check=check_every, **kw)
+    print("device driver: %d rounds, %d checks; windows %s" % (
+        res["rounds"], res["checks"], [[(a["n_in"], a["n_fi"], a["n_fi_after"]) for a in lg] for lg in res["logs"]]),
+        flush=True)
+    assert res["checks"] <= -(-res["rounds"] // check_every)
+    logs = [[] for _ in range(R)]
+    qh_host, _, nad_h, kc_h = PR.adaptive_parareal_batch(
+        ctx, dev(np.concatenate(xs, axis=1)), dev(np.concatenate(ps, axis=1)), off, np.array(boxes), N, L, conv,
+        expl, logs=logs, **kw)
+    assert res["n_ad"] == nad_h and res["kconv"] == kc_h
+    assert torch.max(torch.abs(q - qh_host)).item() <= 1e-12 * torch.max(torch.abs(q)).item()
+    qh = q.cpu().numpy()
+    snap = dict(J=J, beta=beta, rcut=W.SNAP_RCUT, rfac0=W.SNAP_RFAC0, rmin0=0.0)
+    for r in range(R):
+        assert [(a["n_in"], a["n_fi"], a["n_fi_after"]) for a in res["logs"][r]] == \
+               [(a["n_in"], a["n_fi"], a["n_fi_after"]) for a in logs[r]]
+        prop = OPR.Propagators(box=boxes[r], L=L, dt=1e-3, gamma=1.0, mass=W.MASS_W, T=Ts[r], seed=77,
+                               noise_id=nids[r], snap=snap, fs=W.FS_W)
+        olog = []
+        tref, nad_ref, kc_ref = OPR.parareal_adaptive(prop, xs[r], ps[r], N, conv, expl, log=olog)
+        assert (res["n_ad"][r], res["kconv"][r]) == (nad_ref, kc_ref)
+        for n in range(N + 1):
+            assert np.abs(qh[n][:, off[r]:off[r + 1]] - tref[n][0]).max() < QTOL, (r, n)
