@@ -312,6 +312,37 @@ def other_configs(S, W, log):
         "pairs": pairs5, "sweep": "driven from the host, one synchronisation per slab", "kernels": rates}
     log("16001 atoms x 32 slabs: %.2f s per parareal iteration" % t)
     del q, pq, qp, pp, q0, p0
+    # the paper's SNAP-205 size (twojmax 14, 204 coefficients; its cost table): the fine
+    # batch of all 64 slabs of the 129-atom system, 10 steps, with the kernels' rates
+    xs14, ps14 = [], []
+    for s_ in range(64):
+        x, box14 = W.bcc_sia(4, jitter=0.05, seed=900 + s_)
+        xs14.append(x)
+        ps14.append(W.maxwell_momenta(x.shape[1], 1000.0, seed=900 + s_))
+    X14, off14, B14 = W.pack(xs14, [box14] * 64)
+    beta14 = W.snap_beta(14, seed=1)
+    x14, p14 = dev(X14), dev(np.concatenate(ps14, axis=1))
+    ctx14 = S.context(0)
+    ctx14.snap_forces(x14, off14, B14, 14, beta14)
+    pairs14 = ctx14.pair_count()
+    kw14 = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=9, noise_id=0, fs=W.FS_W, J=14, beta=beta14)
+
+    def c14():
+        xw14, pw14 = x14.clone(), p14.clone()
+        ctx14.langevin_steps(S.POT_FS_SNAP, xw14, pw14, off14, B14, 10, step0=0, **kw14)
+
+    t = timed(c14, reps=1)
+    ctx14.profile(True, every=1)
+    c14()
+    torch.cuda.synchronize()
+    rates = kernel_rates(ctx14, S, 14, int(off14[-1]), pairs14, 11)
+    ctx14.profile(False)
+    out["snap205_fine_batch_64x129_10_steps"] = {
+        "twojmax": 14, "atoms": int(off14[-1]), "pairs": pairs14, "atom_steps_per_s": int(off14[-1]) * 10 / t,
+        "s": t, "kernels": rates,
+        "note": "adjoint above twojmax 8: coupling program over (64-atom tile, element chunk), u read from memory"}
+    log("SNAP-205 size, 64 x 129 atoms: %.1f ms per 10 steps" % (t * 1e3))
+    del x14, p14
     # the paper's strategy I: coarse = Finnis-Sinclair + a twojmax-2 SNAP, one corrected
     # parareal iteration over 64 slabs of the 1025-atom system (host-driven sweep)
     wl = W.slabs_1025(n_slabs=1, seed=1, J=8)

@@ -51,7 +51,7 @@ enum {
     SNAPMD_EINVAL = -1,       /* invalid argument (message names it)            */
     SNAPMD_ENOMEM = -2,       /* device allocation failed                       */
     SNAPMD_EHIP = -3,         /* HIP runtime error                              */
-    SNAPMD_EUNSUPPORTED = -4, /* twojmax outside {2, 4, 6, 8}                   */
+    SNAPMD_EUNSUPPORTED = -4, /* twojmax outside {2, ..., 14}, or a feature's limit */
     SNAPMD_ENONFINITE = -5,   /* NaN/Inf in a propagated state (message: slab)  */
     SNAPMD_EOVERFLOW = -6     /* an atom has more than SNAPMD_MAX_NEIGH neighbours */
 };
@@ -84,8 +84,12 @@ typedef struct {
  *   0 <= 2j2 <= 2j1 <= 2j <= twojmax (lexicographic order), B_k the bispectrum of
  *   the neighbour density of atom i within rcut (switching function
  *   (cos(pi (r - rmin0)/(rcut - rmin0)) + 1)/2, self term and unit weights).
- * Requirements: twojmax in {2, 4, 6, 8}; n_coeff = number of canonical triples
- * (5, 14, 30, 55); 0 < rfac0 < 1; 0 <= rmin0 < rcut; rcut < min(box)/2. */
+ * Requirements: twojmax in {2, 4, ..., 14} (14: the paper's SNAP-205 size); n_coeff =
+ * number of canonical triples (5, 14, 30, 55, 91, 140, 204); 0 < rfac0 < 1;
+ * 0 <= rmin0 < rcut; rcut < min(box)/2.  Above twojmax 8 the adjoint pass reads the
+ * densities from device memory (a 64-atom tile no longer fits the local memory), so the
+ * cost per atom grows faster than the operation count; snap_beta_grad and
+ * snap_forces_noalloc take twojmax <= 8. */
 typedef struct {
     int32_t twojmax;
     double rcut, rfac0, rmin0;
@@ -270,7 +274,7 @@ int parareal_adaptive(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs 
  * makes it Finnis-Sinclair + the SNAP model `coarse`, a low-twojmax SNAP beside the
  * fine one: the paper's strategy I (section "Numerical results", SNAP-6 as the coarse
  * potential for a larger SNAP fine one).  coarse is copied (beta included);
- * coarse = NULL restores Finnis-Sinclair alone.  Its twojmax must be in {2, 4, 6, 8},
+ * coarse = NULL restores Finnis-Sinclair alone.  Its twojmax must be in {2, 4, ..., 14},
  * n_coeff must match, and parareal_iterate refuses (SNAPMD_EINVAL) a coarse twojmax equal
  * to the fine one.  With a SNAP coarse potential the coarse propagation of the slabs is
  * batched like the fine one, and the sequential sweep is driven from the host (one

@@ -36,7 +36,8 @@ struct DBuf {
 struct SnapDevTables {
     int J = -1;
     double *nrm = nullptr, *ymult = nullptr, *ycoef = nullptr, *bcg = nullptr;
-    int *ystart = nullptr, *bstart = nullptr, *bel = nullptr;
+    int *ystart = nullptr, *bstart = nullptr, *bel = nullptr, *ychunk = nullptr;
+    int n_ychunk = 0;
     uint32_t *yidx = nullptr, *bidx = nullptr;
     std::vector<double> beta;  // coefficients ycoef was built for
     std::vector<double> ycoef_host;
@@ -213,6 +214,7 @@ int ensure_atoms(snapmd_ctx *ctx, size_t N) {
     if ((rc = dalloc(ctx, &w.dedr, 3 * w.Pcap))) return rc;
     if ((rc = dalloc(ctx, &w.u, (size_t)n_half(kMaxJ) * cap))) return rc;
     if ((rc = dalloc(ctx, &w.ytil, (size_t)n_half(kMaxJ) * cap))) return rc;
+    if ((rc = dalloc(ctx, &w.epart, (size_t)kMaxYChunks * cap))) return rc;
     if ((rc = dalloc(ctx, &ctx->d_f, 3 * cap))) return rc;
     if ((rc = dalloc(ctx, &w.xref, 3 * cap))) return rc;
     if ((rc = dalloc(ctx, &w.cell_of, cap))) return rc;
@@ -254,7 +256,8 @@ int ensure_atoms_coarse(snapmd_ctx *ctx, size_t N, bool snap = false) {
         if ((rc = dalloc(ctx, &w.geo, 20 * Pc)) || (rc = dalloc(ctx, &w.ell, 6 * Pc)) ||
             (rc = dalloc(ctx, &w.nbr_t, Pc)) || (rc = dalloc(ctx, &w.dedr, 3 * Pc)) ||
             (rc = dalloc(ctx, &w.u, (size_t)n_half(kMaxJ) * cap)) ||
-            (rc = dalloc(ctx, &w.ytil, (size_t)n_half(kMaxJ) * cap)))
+            (rc = dalloc(ctx, &w.ytil, (size_t)n_half(kMaxJ) * cap)) ||
+            (rc = dalloc(ctx, &w.epart, (size_t)kMaxYChunks * cap)))
             return rc;
         ctx->cap_atoms_cs = cap;
     }
@@ -307,8 +310,8 @@ int prepare_batch(snapmd_ctx *ctx, const snapmd_batch *batch, BatchDev &bd, doub
 int prepare_snap(snapmd_ctx *ctx, const snapmd_snap *s, double min_half_box, SnapDev &sd, hipStream_t st) {
     if (!s) return fail(ctx, SNAPMD_EINVAL, "snap is NULL");
     const int J = s->twojmax;
-    if (J != 2 && J != 4 && J != 6 && J != 8)
-        return fail(ctx, SNAPMD_EUNSUPPORTED, "twojmax must be one of 2, 4, 6, 8 (got %d)", J);
+    if (J < 2 || J > kMaxJ || (J & 1))
+        return fail(ctx, SNAPMD_EUNSUPPORTED, "twojmax must be one of 2, 4, ..., 14 (got %d)", J);
     const SnapTables &T = snap_tables(J);
     if (s->n_coeff != T.K)
         return fail(ctx, SNAPMD_EINVAL, "n_coeff must be %d for twojmax %d (got %d)", T.K, J, s->n_coeff);
@@ -333,6 +336,18 @@ int prepare_snap(snapmd_ctx *ctx, const snapmd_snap *s, double min_half_box, Sna
         HIPCHK(hipMemcpy(D.nrm, T.nrm.data(), T.nh * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(D.ymult, T.ymult.data(), T.nh * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(D.ystart, T.ystart.data(), T.ystart.size() * sizeof(int), hipMemcpyHostToDevice));
+        {
+            // output-element chunks of about equal term counts for the chunked adjoint
+            const int nc = std::min(kMaxYChunks, T.nh);
+            const double per = (double)T.ystart[T.nh] / nc;
+            std::vector<int> ch{0};
+            for (int e = 0; e < T.nh && (int)ch.size() < nc; ++e)
+                if (T.ystart[e + 1] >= per * (double)ch.size() && e + 1 > ch.back()) ch.push_back(e + 1);
+            if (ch.back() != T.nh) ch.push_back(T.nh);
+            D.n_ychunk = (int)ch.size() - 1;
+            if ((rc = dalloc(ctx, &D.ychunk, ch.size()))) return rc;
+            HIPCHK(hipMemcpy(D.ychunk, ch.data(), ch.size() * sizeof(int), hipMemcpyHostToDevice));
+        }
         HIPCHK(hipMemcpy(D.yidx, T.yidx.data(), T.yidx.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(D.bstart, T.bstart.data(), T.bstart.size() * sizeof(int), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(D.bidx, T.bidx.data(), T.bidx.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -349,7 +364,7 @@ int prepare_snap(snapmd_ctx *ctx, const snapmd_snap *s, double min_half_box, Sna
         }
         if ((rc = upload(ctx, D.ycoef, D.ycoef_host.data(), D.ycoef_host.size(), st))) return rc;
     }
-    {
+    if (J <= kMaxJLds) {  // the LDS-tiled adjoint's tables (above, the coupling program serves)
         AdjointHost &A = D.adj;
         const int oldJ = A.J;
         adjoint_tables(J, s->beta, A);
@@ -377,6 +392,8 @@ int prepare_snap(snapmd_ctx *ctx, const snapmd_snap *s, double min_half_box, Sna
     sd.nrm = D.nrm;
     sd.ymult = D.ymult;
     sd.ystart = D.ystart;
+    sd.ychunk = D.ychunk;
+    sd.n_ychunk = D.n_ychunk;
     sd.yidx = D.yidx;
     sd.ycoef = D.ycoef;
     sd.bstart = D.bstart;
@@ -1527,8 +1544,8 @@ int snap_forces_noalloc(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_b
                     SNAPMD_NOALLOC_MAX_ATOMS, N);
     if (!snap) return fail(ctx, SNAPMD_EINVAL, "snap is NULL");
     const int J = snap->twojmax;
-    if (J != 2 && J != 4 && J != 6 && J != 8)
-        return fail(ctx, SNAPMD_EUNSUPPORTED, "twojmax must be one of 2, 4, 6, 8 (got %d)", J);
+    if (J < 2 || J > kMaxJLds || (J & 1))
+        return fail(ctx, SNAPMD_EUNSUPPORTED, "snap_forces_noalloc takes twojmax 2, 4, 6 or 8 (got %d)", J);
     const SnapTables &T = snap_tables(J);
     if (snap->n_coeff != T.K)
         return fail(ctx, SNAPMD_EINVAL, "n_coeff must be %d for twojmax %d (got %d)", T.K, J, snap->n_coeff);
@@ -2084,8 +2101,8 @@ int snapmd_set_coarse_snap(snapmd_ctx *ctx, const snapmd_snap *coarse) {
         return SNAPMD_OK;
     }
     const int J = coarse->twojmax;
-    if (J != 2 && J != 4 && J != 6 && J != 8)
-        return fail(ctx, SNAPMD_EUNSUPPORTED, "coarse twojmax must be one of 2, 4, 6, 8 (got %d)", J);
+    if (J < 2 || J > kMaxJ || (J & 1))
+        return fail(ctx, SNAPMD_EUNSUPPORTED, "coarse twojmax must be one of 2, 4, ..., 14 (got %d)", J);
     if (coarse->n_coeff != snap_tables(J).K)
         return fail(ctx, SNAPMD_EINVAL, "coarse n_coeff must be %d for twojmax %d (got %d)", snap_tables(J).K, J,
                     coarse->n_coeff);
@@ -2203,6 +2220,8 @@ int snap_beta_grad(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch 
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
     if (!x || !w || !dEdbeta || !gradF) return fail(ctx, SNAPMD_EINVAL, "x, w, dEdbeta and gradF must be device pointers");
+    if (snap && snap->twojmax > kMaxJLds)
+        return fail(ctx, SNAPMD_EUNSUPPORTED, "snap_beta_grad takes twojmax up to %d (got %d)", kMaxJLds, snap->twojmax);
     BatchDev bd;
     double mh;
     SnapDev sd;

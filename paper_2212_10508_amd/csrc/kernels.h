@@ -60,6 +60,8 @@ struct SnapDev {
     double beta0 = 0.0;
     const double *nrm = nullptr, *ymult = nullptr;
     const int *ystart = nullptr;
+    const int *ychunk = nullptr;    // [n_ychunk + 1] output-element chunks of the coupling program
+    int n_ychunk = 0;
     const uint32_t *yidx = nullptr;
     const double *ycoef = nullptr;  // CG product * beta tilde
     const int *bstart = nullptr, *bel = nullptr;
@@ -96,7 +98,9 @@ struct Work {
     double *ph = nullptr;   // [3][N] BBK: p_{l-1/2} of the running call
     double *dedr = nullptr; // [3][Pcap]
     double2 *u = nullptr, *ytil = nullptr;  // [nh][N]
+    double *epart = nullptr;                // [kMaxYChunks][N] energy parts of the chunked adjoint
 };
+constexpr int kMaxYChunks = 64;
 
 // Optional per-kernel timing with HIP events on the launch stream (for the roofline).
 enum { PROF_DEDR = 0, PROF_ADJOINT = 1, PROF_DENSITY = 2, PROF_NEIGH = 3, PROF_N = 4 };

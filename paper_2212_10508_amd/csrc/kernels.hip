@@ -575,16 +575,22 @@ __host__ __device__ constexpr int chain_acc_idx(int C, int n, int k) {
     return n * (n + 1) / 2 - C * (2 * C + 1) + k;
 }
 
-template <int J, int C, int N>
-__device__ __forceinline__ void density_step(double2 (&P)[J + 1], double2 (&acc)[chain_acc_idx(C, J + 1, 0)],
-                                             double2 b, double2 ab, double fc) {
+// Levels N .. N1 of column chain C; the elements of levels N0 .. N1 are accumulated
+// (acc index relative to level N0), the lower levels only advance the chain.
+template <int J, int C, int N0, int N1, int N>
+__device__ __forceinline__ void density_step(
+    double2 (&P)[J + 1], double2 (&acc)[chain_acc_idx(C, N1 + 1, 0) - chain_acc_idx(C, N0, 0)], double2 b,
+    double2 ab, double fc) {
     if constexpr (N > 2 * C) chain_advance<J, N - 1>(P, b, ab);
+    if constexpr (N >= N0) {
+        constexpr int a0 = chain_acc_idx(C, N0, 0);
 #pragma unroll
-    for (int k = 0; k <= N; ++k) {
-        acc[chain_acc_idx(C, N, k)].x = fma(fc, P[k].x, acc[chain_acc_idx(C, N, k)].x);
-        acc[chain_acc_idx(C, N, k)].y = fma(fc, P[k].y, acc[chain_acc_idx(C, N, k)].y);
+        for (int k = 0; k <= N; ++k) {
+            acc[chain_acc_idx(C, N, k) - a0].x = fma(fc, P[k].x, acc[chain_acc_idx(C, N, k) - a0].x);
+            acc[chain_acc_idx(C, N, k) - a0].y = fma(fc, P[k].y, acc[chain_acc_idx(C, N, k) - a0].y);
+        }
     }
-    if constexpr (N < J) density_step<J, C, N + 1>(P, acc, b, ab, fc);
+    if constexpr (N < N1) density_step<J, C, N0, N1, N + 1>(P, acc, b, ab, fc);
 }
 
 template <int J, int C, int c>  // staircase: column c at level 2c -> column c+1 at level 2c+2
@@ -629,15 +635,15 @@ __global__ void k_pair_ell(int N, int n_sys, const int *__restrict__ off, const 
     }
 }
 
-// u (half storage, [e][N] double2) for column C: one wave per tile of 64 atoms, lane =
-// atom.  Step t reads slot t of the 64 atoms' lists from the slot-major copy of a, b
-// and f_c (one coalesced load per field); slots past an atom's count add nothing.
-template <int J, int C>
+// u (half storage, [e][N] double2) for column C, levels N0 .. N1: one wave per tile of 64
+// atoms, lane = atom.  Step t reads slot t of the 64 atoms' lists from the slot-major copy
+// of a, b and f_c (one coalesced load per field); slots past an atom's count add nothing.
+template <int J, int C, int N0, int N1>
 __device__ void density_lane(int N, const int *__restrict__ poff, const double *__restrict__ ell,
                              const double *__restrict__ nrm, double2 *__restrict__ u, double fs_A,
                              double *__restrict__ dF) {
     const int i = blockIdx.x * 64 + threadIdx.x;
-    constexpr int NA = chain_acc_idx(C, J + 1, 0);
+    constexpr int NA = chain_acc_idx(C, N1 + 1, 0) - chain_acc_idx(C, N0, 0);
     double2 acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = make_double2(0.0, 0.0);
@@ -650,7 +656,7 @@ __device__ void density_lane(int N, const int *__restrict__ poff, const double *
     for (int t = 0; t < tmax; ++t) {
         const bool v = t < cnt;
         const size_t q = (size_t)t * N + (v ? i : 0);
-        if constexpr (C == 0)
+        if constexpr (C == 0 && N0 == 0)
             if (dF && v) rho += ell[5 * sN + q];
         // past the count: the identity rotation with zero weight (slot contents unused)
         const double2 a = v ? make_double2(ell[q], ell[sN + q]) : make_double2(1.0, 0.0);
@@ -660,36 +666,77 @@ __device__ void density_lane(int N, const int *__restrict__ poff, const double *
         double2 P[J + 1];
         P[0] = make_double2(1.0, 0.0);
         staircase<J, C, 0>(P, b, ab);
-        density_step<J, C, 2 * C>(P, acc, b, ab, fc);
+        density_step<J, C, N0, N1, 2 * C>(P, acc, b, ab, fc);
     }
     if (i >= N) return;
-    if constexpr (C == 0)
+    if constexpr (C == 0 && N0 == 0)
         if (dF) dF[i] = rho > 0.0 ? -fs_A / (2.0 * sqrt(rho)) : 0.0;
 #pragma unroll
-    for (int n = 2 * C; n <= J; ++n)
+    for (int n = N0; n <= N1; ++n)
 #pragma unroll
         for (int k = 0; k <= n; ++k) {
             const int e = half_idx(n, k, C);
             const double sc = nrm[e];
-            const double2 v = acc[chain_acc_idx(C, n, k)];
+            const double2 v = acc[chain_acc_idx(C, n, k) - chain_acc_idx(C, N0, 0)];
             u[(size_t)e * N + i] = make_double2((k == C ? 1.0 : 0.0) + sc * v.x, sc * v.y);
         }
 }
 
+// Work split of the density pass: segment s = (column C, levels N0 .. N1) with at most
+// kDensAcc accumulated elements each (the register budget of one lane; at twojmax <= 8
+// every column chain is one segment).  A segment above a column's first level recomputes
+// the chain's lower levels without accumulating them.
+constexpr int kDensAcc = 45;
+struct DensSeg {
+    int C, N0, N1;
+};
+__host__ __device__ constexpr int dens_segments(int J) {
+    int n = 0;
+    for (int C = 0; 2 * C <= J; ++C) {
+        int lev = 2 * C;
+        while (lev <= J) {
+            int acc = 0, top = lev;
+            while (top <= J && acc + top + 1 <= kDensAcc) acc += ++top;  // adds level top - 1
+            ++n;
+            lev = top;
+        }
+    }
+    return n;
+}
+__host__ __device__ constexpr DensSeg dens_segment(int J, int s) {
+    int n = 0;
+    for (int C = 0; 2 * C <= J; ++C) {
+        int lev = 2 * C;
+        while (lev <= J) {
+            int acc = 0, top = lev;
+            while (top <= J && acc + top + 1 <= kDensAcc) acc += ++top;
+            if (n == s) return DensSeg{C, lev, top - 1};
+            ++n;
+            lev = top;
+        }
+    }
+    return DensSeg{0, 0, 0};
+}
+
+template <int J, int S>
+__device__ __forceinline__ void density_dispatch(int y, int N, const int *__restrict__ poff,
+                                                 const double *__restrict__ ell, const double *__restrict__ nrm,
+                                                 double2 *__restrict__ u, double fs_A, double *__restrict__ dF) {
+    if (y == S) {
+        constexpr DensSeg g = dens_segment(J, S);
+        density_lane<J, g.C, g.N0, g.N1>(N, poff, ell, nrm, u, fs_A, (g.C == 0 && g.N0 == 0) ? dF : nullptr);
+    } else if constexpr (S + 1 < dens_segments(J)) {
+        density_dispatch<J, S + 1>(y, N, poff, ell, nrm, u, fs_A, dF);
+    }
+}
+
 // dF non-null: column 0 also sums the Finnis-Sinclair density of field 5 and writes
-// dF[i] = F'(rho_i) = -A / (2 sqrt(rho_i)) (0 for rho_i = 0)
+// dF[i] = F'(rho_i) = -A / (2 sqrt(rho_i)) (0 for rho_i = 0).  blockIdx.y = segment.
 template <int J>
 __global__ void __launch_bounds__(64) k_density(int N, const int *__restrict__ poff, const double *__restrict__ ell,
                                                 const double *__restrict__ nrm, double2 *__restrict__ u,
                                                 double fs_A, double *__restrict__ dF) {
-    switch (blockIdx.y) {
-        case 0: density_lane<J, 0>(N, poff, ell, nrm, u, fs_A, dF); break;
-        case 1: if constexpr (J >= 2) density_lane<J, 1>(N, poff, ell, nrm, u, fs_A, nullptr); break;
-        case 2: if constexpr (J >= 4) density_lane<J, 2>(N, poff, ell, nrm, u, fs_A, nullptr); break;
-        case 3: if constexpr (J >= 6) density_lane<J, 3>(N, poff, ell, nrm, u, fs_A, nullptr); break;
-        case 4: if constexpr (J >= 8) density_lane<J, 4>(N, poff, ell, nrm, u, fs_A, nullptr); break;
-        default: break;
-    }
+    density_dispatch<J, 0>(blockIdx.y, N, poff, ell, nrm, u, fs_A, dF);
 }
 
 // ---------------------------------------------------------------------------
@@ -729,6 +776,61 @@ __global__ void __launch_bounds__(256) k_adjoint(int N, int nh, const double2 *_
         const double en = beta0 + esum / 3.0;
         e_atom[i] = accumulate_e ? e_atom[i] + en : en;
     }
+}
+
+// The coupling program split over (64-atom tile, chunk of output elements) workgroups, so
+// that a batch of a few thousand atoms still gives every CU several waves to hide the
+// latency of the u loads (twojmax above 8, where u stays in device memory).  Chunk c
+// covers the output elements ychunk[c] .. ychunk[c+1]-1 (balanced by term count on the
+// host).  Workgroup w runs on chiplet w mod 8 (the dispatcher's round robin); the
+// mapping keeps every chunk of a tile on one chiplet, so the tile's u rows are read
+// through one L2.  epart[c][i]: the chunk's part of the Euler sum (null: no energies).
+__global__ void __launch_bounds__(64) k_adjoint_chunks(int N, int n_tiles, int n_chunks,
+                                                       const int *__restrict__ ychunk, const double2 *__restrict__ u,
+                                                       const int *__restrict__ ystart,
+                                                       const uint32_t *__restrict__ yidx,
+                                                       const double *__restrict__ ycoef, const double *__restrict__ nrm,
+                                                       const double *__restrict__ ymult, double2 *__restrict__ ytil,
+                                                       double *__restrict__ epart) {
+    const int w = blockIdx.x, xcd = w & 7, loc = w >> 3;
+    const int tile = (loc / n_chunks) * 8 + xcd, c = loc % n_chunks;
+    if (tile >= n_tiles) return;
+    const int i = tile * 64 + threadIdx.x;
+    const bool own = i < N;
+    const int ii = own ? i : N - 1;
+    double esum = 0.0;
+    for (int e = ychunk[c]; e < ychunk[c + 1]; ++e) {
+        const int t0 = ystart[e], t1 = ystart[e + 1];
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+        for (int t = t0; t < t1; ++t) {
+            const uint32_t wd = yidx[t];
+            double2 a = u[(size_t)(wd & 0xfffu) * N + ii];
+            double2 b = u[(size_t)((wd >> 12) & 0xfffu) * N + ii];
+            if (wd & (1u << 24)) a.y = -a.y;
+            if (wd & (1u << 25)) b.y = -b.y;
+            const double cf = ycoef[t];
+            acc.x = fma(cf, a.x * b.x - a.y * b.y, acc.x);
+            acc.y = fma(cf, a.x * b.y + a.y * b.x, acc.y);
+        }
+        const double m = ymult[e];
+        const double2 ue = u[(size_t)e * N + ii];
+        esum += m * (acc.x * ue.x + acc.y * ue.y);
+        const double sc = m * nrm[e];
+        if (own) ytil[(size_t)e * N + i] = make_double2(sc * acc.x, sc * acc.y);
+    }
+    if (epart && own) epart[(size_t)c * N + i] = esum;
+}
+
+// E_i = beta0 + (1/3) sum_c epart[c][i], summed in chunk order (deterministic)
+__global__ void k_energy_chunks(int N, int n_chunks, const double *__restrict__ epart, double beta0,
+                                double *__restrict__ e_atom, int accumulate) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s = 0.0;
+    for (int c = 0; c < n_chunks; ++c) s += epart[(size_t)c * N + i];
+    const double en = beta0 + s / 3.0;
+    e_atom[i] = accumulate ? e_atom[i] + en : en;
 }
 
 // Bispectrum by the coupling program (lane = atom): B[t][i].
@@ -869,7 +971,10 @@ __global__ void __launch_bounds__(64) k_dedr(int N, int n_sys, const int *__rest
                                              const double2 *__restrict__ ytil, double *__restrict__ dedr,
                                              FsFuse fz) {
     constexpr int NH = n_half(J);
-    __shared__ double2 ys[kDedrAtoms * NH];
+    // the Y~ rows of the wave's atoms are staged in LDS up to twojmax 8 (above, 5 atoms'
+    // rows would take most of the LDS and cut the waves per CU; they are read from memory)
+    constexpr bool kStage = J <= 8;
+    __shared__ double2 ys[kStage ? kDedrAtoms * NH : 1];
     __shared__ double fsb[3 * 64];
     const int P = poff[N];
     const int p0 = blockIdx.x * 64;
@@ -901,7 +1006,7 @@ __global__ void __launch_bounds__(64) k_dedr(int N, int n_sys, const int *__rest
     }
     const double fc = live ? g[4] : 0.0;
     const double *fs = fz.on ? fsb + lane : nullptr;
-    if (na <= kDedrAtoms) {
+    if (kStage && na <= kDedrAtoms) {
         for (int q = lane; q < na * NH; q += 64) {
             const int e = q / na, at = q - e * na;
             ys[q] = ytil[(size_t)e * N + i0 + at];
@@ -1148,11 +1253,24 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     hipLaunchKernelGGL(k_pair_ell, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box,
                        x, w.poff, w.nbr_t, sd.gp, w.ell, fuse ? fuse->d : 0.0, fuse ? w.flag : nullptr);
     pf.begin(PROF_DENSITY, st);
-    hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 64), J / 2 + 1), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u,
-                       fuse ? fuse->A : 0.0, fuse ? w.rho : nullptr);
+    hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 64), dens_segments(J)), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm,
+                       w.u, fuse ? fuse->A : 0.0, fuse ? w.rho : nullptr);
     pf.end(st);
     pf.begin(PROF_ADJOINT, st);
-    launch_adjoint(J, sd.adj, N, w.u, sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate, st);
+    if constexpr (J <= 8) {
+        launch_adjoint(J, sd.adj, N, w.u, sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate, st);
+    } else {
+        // above twojmax 8 a 64-atom tile of u no longer fits the LDS: the coupling program
+        // reads u from memory (lane = atom, coefficients wave-uniform), split over
+        // chunks of output elements
+        const int tiles = (int)nblk(N, 64), t8 = (tiles + 7) / 8;
+        hipLaunchKernelGGL(k_adjoint_chunks, dim3(t8 * 8 * sd.n_ychunk), dim3(64), 0, st, N, tiles, sd.n_ychunk,
+                           sd.ychunk, w.u, sd.ystart, sd.yidx, sd.ycoef, sd.nrm, sd.ymult, w.ytil,
+                           e_atom ? w.epart : nullptr);
+        if (e_atom)
+            hipLaunchKernelGGL(k_energy_chunks, dim3(nblk(N, 256)), dim3(256), 0, st, N, sd.n_ychunk, w.epart,
+                               sd.beta0, e_atom, accumulate);
+    }
     pf.end(st);
     pf.begin(PROF_DEDR, st);
     hipLaunchKernelGGL(k_dedr<J>, dim3(nblk((size_t)N * kMaxNeigh, 64)), dim3(64), 0, st, N, bd.n_sys, bd.off, bd.box,
@@ -1171,8 +1289,17 @@ void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, 
         case 4: launch_snap_J<4>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
         case 6: launch_snap_J<6>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
         case 8: launch_snap_J<8>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
+        case 10: launch_snap_J<10>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
+        case 12: launch_snap_J<12>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
+        case 14: launch_snap_J<14>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
         default: break;
     }
+}
+
+template <int J>
+static void density_launch(int N, Work &w, const SnapDev &sd, hipStream_t st) {
+    hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 64), dens_segments(J)), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm,
+                       w.u, 0.0, nullptr);
 }
 
 void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st) {
@@ -1182,10 +1309,13 @@ void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapD
     hipLaunchKernelGGL(k_pair_ell, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box,
                        x, w.poff, w.nbr_t, sd.gp, w.ell, 0.0, nullptr);
     switch (J) {
-        case 2: hipLaunchKernelGGL(k_density<2>, dim3(nblk(N, 64), 2), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u, 0.0, nullptr); break;
-        case 4: hipLaunchKernelGGL(k_density<4>, dim3(nblk(N, 64), 3), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u, 0.0, nullptr); break;
-        case 6: hipLaunchKernelGGL(k_density<6>, dim3(nblk(N, 64), 4), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u, 0.0, nullptr); break;
-        case 8: hipLaunchKernelGGL(k_density<8>, dim3(nblk(N, 64), 5), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm, w.u, 0.0, nullptr); break;
+        case 2: density_launch<2>(N, w, sd, st); break;
+        case 4: density_launch<4>(N, w, sd, st); break;
+        case 6: density_launch<6>(N, w, sd, st); break;
+        case 8: density_launch<8>(N, w, sd, st); break;
+        case 10: density_launch<10>(N, w, sd, st); break;
+        case 12: density_launch<12>(N, w, sd, st); break;
+        case 14: density_launch<14>(N, w, sd, st); break;
         default: break;
     }
 }

@@ -21,7 +21,8 @@
 
 namespace snapmd {
 
-constexpr int kMaxJ = 8;
+constexpr int kMaxJ = 14;     // largest twojmax (SNAP-205)
+constexpr int kMaxJLds = 8;   // largest twojmax of the LDS-tiled adjoint
 constexpr int kMaxNeigh = 64;
 
 // half_off(n) = sum_{m<n} (m+1)(floor(m/2)+1), in closed form so that it folds to a

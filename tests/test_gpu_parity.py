@@ -214,7 +214,10 @@ def test_invalid_arguments_rejected(S):
     assert e.value.code == S.EINVAL
     x, box = W.bcc_sia(4)
     with pytest.raises(S.SnapmdError) as e:
-        S.snap_forces(dev(x), [0, x.shape[1]], box, 10, np.zeros(92))
+        S.snap_forces(dev(x), [0, x.shape[1]], box, 16, np.zeros(2))   # beyond SNAP-205's twojmax 14
+    assert e.value.code == S.EUNSUPPORTED
+    with pytest.raises(S.SnapmdError) as e:
+        S.snap_forces(dev(x), [0, x.shape[1]], box, 7, np.zeros(2))    # odd twojmax
     assert e.value.code == S.EUNSUPPORTED
     with pytest.raises(S.SnapmdError) as e:
         S.snap_forces(dev(x), [0, x.shape[1]], box, 6, np.zeros(20))
