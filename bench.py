@@ -312,6 +312,18 @@ def other_configs(S, W, log):
         "pairs": pairs5, "sweep": "driven from the host, one synchronisation per slab", "kernels": rates}
     log("16001 atoms x 32 slabs: %.2f s per parareal iteration" % t)
     del q, pq, qp, pp, q0, p0
+    # the statistical test of the paper's "Statistical analyses" at 16001 atoms: 8 replicas
+    # at 2000 K, sequential fine trajectories against adaptive parareal ones (other noise
+    # streams, delta_conv 1e-3), 16 slabs x 50 steps each; pooled residence times
+    from paper_2212_10508_amd import analysis as A
+    x, box = W.bcc_sia(20, jitter=0.0, seed=5)
+    t0 = time.perf_counter()
+    rs = A.residence_study(S.context(0), dev(x), box, R=8, N=16, L=50, J=8, beta=W.snap_beta(8, seed=5), fs=W.FS_W,
+                           T=2000.0, delta_conv=1e-3, seed=3, mass=W.MASS_W)
+    rs["s"] = time.perf_counter() - t0
+    out["residence_16001_8x800_steps_2000K"] = rs
+    log("residence times at 16001 atoms: sequential %.1f, parareal %.1f steps (CIs overlap: %s)"
+        % (rs["sequential"]["mean_steps"], rs["parareal"]["mean_steps"], rs["ci_overlap"]))
     # the paper's SNAP-205 size (twojmax 14, 204 coefficients; its cost table): the fine
     # batch of all 64 slabs of the 129-atom system, 10 steps, with the kernels' rates
     xs14, ps14 = [], []

@@ -99,3 +99,25 @@ def test_defect_history_of_converged_parareal_equals_sequential(S):
         hist.append(A.interstitial_site(ctx.ws_sites(xr, [0, n], box, W.A_W)[1]))
     assert A.residence_times(hist) == OA.residence_times(hist)
     assert sum(A.residence_times(hist)) == 200
+
+
+def test_residence_study_reproduces_sequential_histories(S):
+    """The statistical study's machinery on two 129-atom replicas: with the sequential runs'
+    noise streams and a tight threshold, the parareal trajectories rebuilt step by step from
+    their converged slab states (the fine propagation of every slab at once) have the same
+    interstitial site after every step as the sequential trajectories, hence the same
+    residence times; every step of every replica is accounted for."""
+    from paper_2212_10508_amd import analysis as A
+    x, box = W.bcc_sia(4, jitter=0.0, seed=5)
+    ctx = S.context()
+    N, L, R = 4, 25, 2
+    r = A.residence_study(ctx, dev(x), box, R=R, N=N, L=L, J=4, beta=W.snap_beta(4, seed=5, scale=2e-2),
+                          fs=W.FS_W, T=2000.0, delta_conv=1e-10, thermal_steps=500, seed=3, mass=W.MASS_W,
+                          same_noise=True, keep_histories=True)
+    hs, hp = r["histories"]["sequential"], r["histories"]["parareal"]
+    assert hs.shape == hp.shape == (R, N * L)
+    assert np.array_equal(hs, hp)
+    assert (hs >= 0).all()                  # the dumbbell is found after every step
+    assert r["sequential"]["hops"] == r["parareal"]["hops"]
+    for k in range(R):
+        assert sum(A.residence_times(list(hs[k]))) == N * L
