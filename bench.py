@@ -474,6 +474,10 @@ def main():
                     help="slab chunks of the 64-slab window (default %s, the plan the committed kernel trace "
                          "covers); 'builtin' for the library's own plan" % DEFAULT_PLAN)
     ap.add_argument("--sweep-workgroups", type=int, default=0, help="coarse sweep width (0: built in)")
+    ap.add_argument("--shape", default=None,
+                    help="kernel shape density_acc,dedr_stage_atoms,adjoint_waves of the SNAP passes (no shape "
+                         "tuning); default: the cached choice for this GPU and workload, else tuned (untimed)")
+    ap.add_argument("--retune-shape", action="store_true", help="tune the kernel shape even if one is cached")
     ap.add_argument("--no-configs", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run two SNAP force evaluations of the 64 x 1025-atom batch and a 512 MiB device "
@@ -534,6 +538,42 @@ def main():
         print("bench.py: forces differ from the oracle by more than %g: %s" % (gate["tol"], json.dumps(gate)),
               file=sys.stderr)
         sys.exit(3)
+    # kernel shape of the SNAP passes: fixed, cached for this GPU and size class, or tuned
+    # here (untimed; every candidate checked against the oracle's forces on slab 0 first)
+    from paper_2212_10508_amd import tune
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    shape_key = tune.shape_cache_key(arch, J, 15 * n)
+    shape_info = {"cache_key": shape_key, "cache": tune.shape_cache_path()}
+    if args.shape:
+        shape = tuple(int(v) for v in args.shape.split(","))
+        shape_info["source"] = "--shape"
+    else:
+        shape = None if args.retune_shape else tune.load_shape(shape_key)
+        shape_info["source"] = "cache" if shape else "tuned"
+    if shape is None:
+        from oracle import oracle as O
+        xs0 = q_cur[0].contiguous()
+        f_ora = O.snap_compute(xs0.cpu().numpy(), box, J, beta)["f"]
+
+        def force_error():
+            f = ctx.snap_forces(xs0, [0, n], box, J, beta).cpu().numpy()
+            return force_rel_err(f, f_ora)
+
+        def shape_run():
+            iteration()
+            torch.cuda.synchronize()
+
+        ctx.set_chunk_plan([int(v) for v in DEFAULT_PLAN.split(",")])
+        q_keep, p_keep = q_cur.clone(), p_cur.clone()
+        shape, table = tune.tune_kernel_shapes(ctx, J, shape_run, force_error, log=log)
+        q_cur.copy_(q_keep)
+        p_cur.copy_(p_keep)
+        shape_info["candidates"] = table
+        tune.save_shape(shape_key, shape, {"ms": min(t["ms"] for t in table if t["ms"] is not None),
+                                          "workload": "parareal iteration 64 x 1025, twojmax 8"})
+    ctx.set_kernel_shape(J, shape)
+    shape_info["shape"] = list(shape)
+    log("kernel shape %s (%s)" % (shape, shape_info["source"]))
     ctx.set_sweep_workgroups(args.sweep_workgroups)
     use_plan = None if (args.tune or args.plan == "builtin") else [int(v) for v in args.plan.split(",")]
     if use_plan:  # set before the warmup, which captures the plan's launch sequences
@@ -547,21 +587,19 @@ def main():
     builtin_plan = list(ctx.chunk_plan(S_slabs, n))
     if use_plan:
         ctx.set_chunk_plan(use_plan)
-    autotune = None
+    autotune = {"kernel_shape": shape_info}
     if args.tune:
-        from paper_2212_10508_amd import tune
-
         def timed_iteration():
             iteration()
             torch.cuda.synchronize()
 
         sweep_k, ktimes = tune.tune_sweep_width(ctx, timed_iteration, n, log=log)
         plan, times = tune.tune_chunk_plan(ctx, timed_iteration, S_slabs, n, n_cus, log=log)
-        autotune = {"sweep_workgroups": sweep_k,
+        autotune.update({"sweep_workgroups": sweep_k,
                     "sweep_ms": {str(k): v * 1e3 for k, v in ktimes.items()},
                     "plans_timed": len(times), "builtin_plan": builtin_plan,
                     "builtin_ms": times[tuple(builtin_plan)] * 1e3, "best_plan": plan,
-                    "best_ms": times[tuple(plan)] * 1e3}
+                    "best_ms": times[tuple(plan)] * 1e3})
         log("chunk plan: %s (%.2f ms; built-in %s %.2f ms)" % (plan, autotune["best_ms"], builtin_plan,
                                                               autotune["builtin_ms"]))
     chunk_plan = ctx.chunk_plan(S_slabs, n)

@@ -346,6 +346,26 @@ int snapmd_relax(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, const 
                  const snapmd_batch *batch, double *x, int32_t max_iter, double ftol, double alpha, double dmax,
                  double *fmax_out, int32_t *iters_out, void *stream);
 
+/* Kernel shapes of the SNAP force passes (tuning, not part of the method), chosen per
+ * twojmax (2, 4, 6 or 8; above 8 each pass has a single shape):
+ *   density_acc       density pass: the most density elements one lane accumulates
+ *                     (45, 28 or 21; smaller: more waves of fewer registers, each
+ *                     recomputing the lower levels of its column chain);
+ *   dedr_stage_atoms  dE/dr: a wave whose 64 pairs belong to at most this many atoms copies
+ *                     their adjoint rows into local memory first (5, 3, or 0: never);
+ *   adjoint_waves     LDS-tiled adjoint: waves per 64-atom tile (12 or 8).
+ * Forces do not depend on the shape; per-atom energies only through the order in which
+ * the adjoint's partial sums are added.  snapmd_set_kernel_shape(ctx, J, NULL) restores
+ * the built-in shape (45, 5, 12); any other value is SNAPMD_EINVAL.  snapmd_get_kernel_shape
+ * writes the shape in use for J. */
+typedef struct {
+    int32_t density_acc;
+    int32_t dedr_stage_atoms;
+    int32_t adjoint_waves;
+} snapmd_kernel_shape;
+int snapmd_set_kernel_shape(snapmd_ctx *ctx, int32_t twojmax, const snapmd_kernel_shape *shape);
+int snapmd_get_kernel_shape(snapmd_ctx *ctx, int32_t twojmax, snapmd_kernel_shape *shape);
+
 /* Slab chunks of parareal_iterate (tuning, not part of the method).  The pipelined path
  * of parareal_iterate (systems the on-device sweep handles, BAOAB) propagates the S slabs
  * of a window in chunks of consecutive slabs: the SNAP propagation of chunk c runs while

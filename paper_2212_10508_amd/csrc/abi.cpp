@@ -43,7 +43,7 @@ struct SnapDevTables {
     std::vector<double> ycoef_host;
     AdjointHost adj;
     double *adj_cgm = nullptr, *adj_coef = nullptr;
-    int *adj_coef_off = nullptr, *adj_roles = nullptr;
+    int *adj_coef_off = nullptr, *adj_roles = nullptr, *adj_roles8 = nullptr;
 };
 
 }  // namespace
@@ -67,6 +67,7 @@ struct snapmd_ctx {
     DBuf<int64_t> seg_step0[2];                   // step offsets advanced by a segmented replay (per workspace)
     DBuf<int> d_noise;
     std::map<int, SnapDevTables> snap;
+    std::map<int, KernelShape> shapes;            // kernel shapes set per twojmax (default otherwise)
     std::vector<void *> allocs;
     // parareal buffers
     DBuf<double> pr_xf, pr_pf, pr_xc, pr_pc;     // [3][S*N] fine / coarse copies of prev slabs
@@ -370,11 +371,12 @@ int prepare_snap(snapmd_ctx *ctx, const snapmd_snap *s, double min_half_box, Sna
         adjoint_tables(J, s->beta, A);
         if (oldJ != J) {
             if ((rc = dalloc(ctx, &D.adj_cgm, A.cgm.size())) || (rc = dalloc(ctx, &D.adj_roles, A.roles.size())) ||
-                (rc = dalloc(ctx, &D.adj_coef, A.coef.size())) ||
+                (rc = dalloc(ctx, &D.adj_roles8, A.roles8.size())) || (rc = dalloc(ctx, &D.adj_coef, A.coef.size())) ||
                 (rc = dalloc(ctx, &D.adj_coef_off, A.coef_off.size())))
                 return rc;
             HIPCHK(hipMemcpy(D.adj_cgm, A.cgm.data(), A.cgm.size() * sizeof(double), hipMemcpyHostToDevice));
             HIPCHK(hipMemcpy(D.adj_roles, A.roles.data(), A.roles.size() * sizeof(int), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(D.adj_roles8, A.roles8.data(), A.roles8.size() * sizeof(int), hipMemcpyHostToDevice));
             HIPCHK(hipMemcpy(D.adj_coef_off, A.coef_off.data(), A.coef_off.size() * sizeof(int),
                              hipMemcpyHostToDevice));
         }
@@ -382,7 +384,13 @@ int prepare_snap(snapmd_ctx *ctx, const snapmd_snap *s, double min_half_box, Sna
             if ((rc = upload(ctx, D.adj_coef, A.coef.data(), A.coef.size(), st))) return rc;
             A.coef_changed = false;
         }
-        sd.adj = AdjointDev{D.adj_cgm, D.adj_coef, D.adj_coef_off, D.adj_roles, A.role_len};
+        sd.adj = AdjointDev{D.adj_cgm, D.adj_coef, D.adj_coef_off, D.adj_roles, A.role_len, D.adj_roles8,
+                            A.role_len8};
+    }
+    {
+        auto it = ctx->shapes.find(J);
+        sd.shape = it != ctx->shapes.end() ? it->second : KernelShape{};
+        if (J > kMaxJLds) sd.shape = KernelShape{45, 0, 12};
     }
     sd.J = J;
     sd.K = T.K;
@@ -628,8 +636,10 @@ int replay_range(snapmd_ctx *ctx, Work &w, double *f, int potential, const Batch
                               (uint64_t)ld.scheme, d(ld.gamma), u(ld.sb0), u(ld.sb1), u(w.ph)};
     if (potential == SNAPMD_POT_FS_SNAP) {
         const uint64_t sk[] = {(uint64_t)sd.J, d(sd.gp.rcut), d(sd.gp.rfac0), d(sd.gp.rmin0), d(sd.beta0),
-                               u(sd.nrm), u(sd.adj.coef), u(sd.adj.cgm), u(sd.adj.roles)};
-        key.insert(key.end(), sk, sk + 9);
+                               u(sd.nrm), u(sd.adj.coef), u(sd.adj.cgm), u(sd.adj.roles), u(sd.adj.roles8),
+                               (uint64_t)sd.shape.dens_acc, (uint64_t)sd.shape.dedr_atoms,
+                               (uint64_t)sd.shape.adj_waves};
+        key.insert(key.end(), sk, sk + 13);
     }
     const int ci = (&w == &ctx->wc) ? 1 : 0;
     auto &cache = ctx->graphs[ci];
@@ -2111,6 +2121,33 @@ int snapmd_set_coarse_snap(snapmd_ctx *ctx, const snapmd_snap *coarse) {
     ctx->coarse_beta.assign(coarse->beta, coarse->beta + coarse->n_coeff + 1);
     ctx->coarse_snap.beta = nullptr;
     ctx->coarse_snap_on = true;
+    return SNAPMD_OK;
+}
+
+int snapmd_set_kernel_shape(snapmd_ctx *ctx, int32_t twojmax, const snapmd_kernel_shape *shape) {
+    if (!ctx) return SNAPMD_EINVAL;
+    if (twojmax < 2 || twojmax > kMaxJLds || (twojmax & 1))
+        return fail(ctx, SNAPMD_EINVAL, "kernel shapes are chosen for twojmax 2, 4, 6 or 8 (got %d)", twojmax);
+    if (!shape) {
+        ctx->shapes.erase(twojmax);
+        return SNAPMD_OK;
+    }
+    const bool ok = (shape->density_acc == 45 || shape->density_acc == 28 || shape->density_acc == 21) &&
+                    (shape->dedr_stage_atoms == 5 || shape->dedr_stage_atoms == 3 || shape->dedr_stage_atoms == 0) &&
+                    (shape->adjoint_waves == 12 || shape->adjoint_waves == 8);
+    if (!ok)
+        return fail(ctx, SNAPMD_EINVAL, "kernel shape (%d, %d, %d) is not one of the compiled variants",
+                    shape->density_acc, shape->dedr_stage_atoms, shape->adjoint_waves);
+    ctx->shapes[twojmax] = KernelShape{shape->density_acc, shape->dedr_stage_atoms, shape->adjoint_waves};
+    return SNAPMD_OK;
+}
+
+int snapmd_get_kernel_shape(snapmd_ctx *ctx, int32_t twojmax, snapmd_kernel_shape *shape) {
+    if (!ctx || !shape) return SNAPMD_EINVAL;
+    auto it = ctx->shapes.find(twojmax);
+    KernelShape k = it != ctx->shapes.end() ? it->second : KernelShape{};
+    if (twojmax > kMaxJLds) k = KernelShape{45, 0, 12};
+    *shape = snapmd_kernel_shape{k.dens_acc, k.dedr_atoms, k.adj_waves};
     return SNAPMD_OK;
 }
 

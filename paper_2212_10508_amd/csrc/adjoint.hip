@@ -215,8 +215,9 @@ __device__ __forceinline__ double process_row(int tm, int atom, int N, const dou
     return esum;
 }
 
-template <int J>
-__global__ void __launch_bounds__(768) k_adjoint_lds(int N, const double2 *__restrict__ u,
+// R waves per workgroup (the kernel-shape choice of this pass: 12, three per SIMD, or 8)
+template <int J, int R>
+__global__ void __launch_bounds__(64 * R) k_adjoint_lds(int N, const double2 *__restrict__ u,
                                                      const double *__restrict__ cgm, const double *__restrict__ coef,
                                                      const int *__restrict__ coef_off, const int *__restrict__ roles,
                                                      int role_len, const double *__restrict__ nrm,
@@ -225,7 +226,6 @@ __global__ void __launch_bounds__(768) k_adjoint_lds(int N, const double2 *__res
                                                      int accumulate_e) {
     extern __shared__ double2 lds[];
     constexpr int NH = n_half(J);
-    constexpr int R = 12;  // waves: three per SIMD (the LDS tile allows one workgroup per CU)
     const int a0 = blockIdx.x * 64;
     for (int idx = threadIdx.x; idx < NH * 64; idx += 64 * R) {
         const int e = idx >> 6, a = idx & 63;
@@ -297,18 +297,23 @@ void adjoint_tables(int J, const double *beta, AdjointHost &A) {
         std::vector<int> order(2 * J + 1);
         for (int i = 0; i <= 2 * J; ++i) order[i] = i;
         std::sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        std::vector<std::vector<int>> roles(kAdjWaves);
-        std::vector<double> load(kAdjWaves, 0.0);
-        for (int i : order) {
-            const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            roles[w].push_back(i - J);
-            load[w] += cost[i];
-        }
-        A.role_len = 0;
-        for (auto &r : roles) A.role_len = std::max(A.role_len, (int)r.size() + 1);
-        A.roles.assign(kAdjWaves * A.role_len, 1 << 20);
-        for (int w = 0; w < kAdjWaves; ++w)
-            for (size_t q = 0; q < roles[w].size(); ++q) A.roles[w * A.role_len + q] = roles[w][q];
+        // rows to waves by longest processing time first, for 12 and for 8 waves
+        auto assign = [&](int nw, std::vector<int> &flat, int &len) {
+            std::vector<std::vector<int>> roles(nw);
+            std::vector<double> load(nw, 0.0);
+            for (int i : order) {
+                const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                roles[w].push_back(i - J);
+                load[w] += cost[i];
+            }
+            len = 0;
+            for (auto &r : roles) len = std::max(len, (int)r.size() + 1);
+            flat.assign(nw * len, 1 << 20);
+            for (int w = 0; w < nw; ++w)
+                for (size_t q = 0; q < roles[w].size(); ++q) flat[w * len + q] = roles[w][q];
+        };
+        assign(kAdjWaves, A.roles, A.role_len);
+        assign(8, A.roles8, A.role_len8);
         A.beta.clear();
     }
     if (A.beta.size() == (size_t)T.K + 1 && std::equal(A.beta.begin(), A.beta.end(), beta)) return;
@@ -341,28 +346,38 @@ size_t adjoint_lds_bytes(int J) {
 }
 
 template <int J>
-static void launch_adj(const AdjointDev &ad, int N, const double2 *u, const double *nrm, const double *ymult,
-                       double beta0, double2 *ytil, double *e_atom, int accumulate, hipStream_t st) {
+static void launch_adj(const AdjointDev &ad, int waves, int N, const double2 *u, const double *nrm,
+                       const double *ymult, double beta0, double2 *ytil, double *e_atom, int accumulate,
+                       hipStream_t st) {
     const size_t lds = adjoint_lds_bytes(J);
-    hipLaunchKernelGGL(k_adjoint_lds<J>, dim3((N + 63) / 64), dim3(64 * kAdjWaves), lds, st, N, u, ad.cgm, ad.coef,
-                       ad.coef_off, ad.roles, ad.role_len, nrm, ymult, beta0, ytil, e_atom, accumulate);
+    if (waves == 8 && ad.roles8)
+        hipLaunchKernelGGL((k_adjoint_lds<J, 8>), dim3((N + 63) / 64), dim3(64 * 8), lds, st, N, u, ad.cgm, ad.coef,
+                           ad.coef_off, ad.roles8, ad.role_len8, nrm, ymult, beta0, ytil, e_atom, accumulate);
+    else
+        hipLaunchKernelGGL((k_adjoint_lds<J, kAdjWaves>), dim3((N + 63) / 64), dim3(64 * kAdjWaves), lds, st, N, u,
+                           ad.cgm, ad.coef, ad.coef_off, ad.roles, ad.role_len, nrm, ymult, beta0, ytil, e_atom,
+                           accumulate);
 }
 
 void launch_adjoint(int J, const AdjointDev &ad, int N, const double2 *u, const double *nrm, const double *ymult,
-                    double beta0, double2 *ytil, double *e_atom, int accumulate, hipStream_t st) {
+                    double beta0, double2 *ytil, double *e_atom, int accumulate, hipStream_t st, int waves) {
     switch (J) {
-        case 2: launch_adj<2>(ad, N, u, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
-        case 4: launch_adj<4>(ad, N, u, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
-        case 6: launch_adj<6>(ad, N, u, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
-        case 8: launch_adj<8>(ad, N, u, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
+        case 2: launch_adj<2>(ad, waves, N, u, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
+        case 4: launch_adj<4>(ad, waves, N, u, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
+        case 6: launch_adj<6>(ad, waves, N, u, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
+        case 8: launch_adj<8>(ad, waves, N, u, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
         default: break;
     }
 }
 
 void adjoint_init_attributes() {
-    (void)hipFuncSetAttribute((const void *)k_adjoint_lds<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_adjoint_lds<8, kAdjWaves>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)adjoint_lds_bytes(8));
-    (void)hipFuncSetAttribute((const void *)k_adjoint_lds<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_adjoint_lds<6, kAdjWaves>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)adjoint_lds_bytes(6));
+    (void)hipFuncSetAttribute((const void *)k_adjoint_lds<8, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)adjoint_lds_bytes(8));
+    (void)hipFuncSetAttribute((const void *)k_adjoint_lds<6, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)adjoint_lds_bytes(6));
 }
 

@@ -42,8 +42,10 @@ struct AdjointHost {
     std::vector<double> cgm;       // row-pair motif coupling constants (beta free)
     std::vector<double> coef;      // beta~ * C^{j m}_{j1 m1, j2 m2} per (2m, block, m1, j)
     std::vector<int> coef_off;     // [(2J+1) * n_blocks] start of each (2m, block) run
-    std::vector<int> roles;        // [8][role_len] output rows 2m of each wave (> J ends)
+    std::vector<int> roles;        // [12][role_len] output rows 2m of each wave (> J ends)
     int role_len = 0;
+    std::vector<int> roles8;       // the same for 8 waves
+    int role_len8 = 0;
     std::vector<double> beta;
     bool coef_changed = false;
 };
@@ -51,6 +53,20 @@ struct AdjointDev {
     const double *cgm = nullptr, *coef = nullptr;
     const int *coef_off = nullptr, *roles = nullptr;
     int role_len = 0;
+    const int *roles8 = nullptr;
+    int role_len8 = 0;
+};
+
+// Kernel shapes of the SNAP passes (tuning choices; forces do not depend on them, energies
+// only through the order of the adjoint's partial sums):
+//   dens_acc   density pass: most accumulated elements per lane (45, 28 or 21)
+//   dedr_atoms dE/dr: atoms whose Y~ rows a wave stages in LDS (5, 3 or 0: from memory)
+//   adj_waves  LDS-tiled adjoint: waves per 64-atom tile (12 or 8)
+// Above twojmax 8 the passes have one shape each (45, 0, -).
+struct KernelShape {
+    int dens_acc = 45;
+    int dedr_atoms = 5;
+    int adj_waves = 12;
 };
 
 // SNAP coefficient-dependent tables on the device.
@@ -68,6 +84,7 @@ struct SnapDev {
     const uint32_t *bidx = nullptr;
     const double *bcg = nullptr;
     AdjointDev adj;
+    KernelShape shape;
 };
 
 struct LangevinDev {
@@ -232,7 +249,7 @@ void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapD
 void adjoint_tables(int J, const double *beta, AdjointHost &A);
 void adjoint_init_attributes();
 void launch_adjoint(int J, const AdjointDev &ad, int N, const double2 *u, const double *nrm, const double *ymult,
-                    double beta0, double2 *ytil, double *e_atom, int accumulate, hipStream_t st);
+                    double beta0, double2 *ytil, double *e_atom, int accumulate, hipStream_t st, int waves = 12);
 void launch_bispectrum(const BatchDev &bd, const SnapDev &sd, Work &w, double *B, hipStream_t st);
 void launch_jvp_density(int J, int N, const Work &w, const double *wf, const double *nrm, double2 *du,
                         hipStream_t st);

@@ -686,30 +686,31 @@ __device__ void density_lane(int N, const int *__restrict__ poff, const double *
 // kDensAcc accumulated elements each (the register budget of one lane; at twojmax <= 8
 // every column chain is one segment).  A segment above a column's first level recomputes
 // the chain's lower levels without accumulating them.
-constexpr int kDensAcc = 45;
+// ACC is the kernel-shape choice of the density pass (smaller: more, shorter segments,
+// fewer registers per lane, more waves in flight, more recomputed chain levels).
 struct DensSeg {
     int C, N0, N1;
 };
-__host__ __device__ constexpr int dens_segments(int J) {
+__host__ __device__ constexpr int dens_segments(int J, int ACC) {
     int n = 0;
     for (int C = 0; 2 * C <= J; ++C) {
         int lev = 2 * C;
         while (lev <= J) {
             int acc = 0, top = lev;
-            while (top <= J && acc + top + 1 <= kDensAcc) acc += ++top;  // adds level top - 1
+            while (top <= J && (top == lev || acc + top + 1 <= ACC)) acc += ++top;  // adds level top - 1
             ++n;
             lev = top;
         }
     }
     return n;
 }
-__host__ __device__ constexpr DensSeg dens_segment(int J, int s) {
+__host__ __device__ constexpr DensSeg dens_segment(int J, int ACC, int s) {
     int n = 0;
     for (int C = 0; 2 * C <= J; ++C) {
         int lev = 2 * C;
         while (lev <= J) {
             int acc = 0, top = lev;
-            while (top <= J && acc + top + 1 <= kDensAcc) acc += ++top;
+            while (top <= J && (top == lev || acc + top + 1 <= ACC)) acc += ++top;
             if (n == s) return DensSeg{C, lev, top - 1};
             ++n;
             lev = top;
@@ -718,25 +719,25 @@ __host__ __device__ constexpr DensSeg dens_segment(int J, int s) {
     return DensSeg{0, 0, 0};
 }
 
-template <int J, int S>
+template <int J, int ACC, int S>
 __device__ __forceinline__ void density_dispatch(int y, int N, const int *__restrict__ poff,
                                                  const double *__restrict__ ell, const double *__restrict__ nrm,
                                                  double2 *__restrict__ u, double fs_A, double *__restrict__ dF) {
     if (y == S) {
-        constexpr DensSeg g = dens_segment(J, S);
+        constexpr DensSeg g = dens_segment(J, ACC, S);
         density_lane<J, g.C, g.N0, g.N1>(N, poff, ell, nrm, u, fs_A, (g.C == 0 && g.N0 == 0) ? dF : nullptr);
-    } else if constexpr (S + 1 < dens_segments(J)) {
-        density_dispatch<J, S + 1>(y, N, poff, ell, nrm, u, fs_A, dF);
+    } else if constexpr (S + 1 < dens_segments(J, ACC)) {
+        density_dispatch<J, ACC, S + 1>(y, N, poff, ell, nrm, u, fs_A, dF);
     }
 }
 
 // dF non-null: column 0 also sums the Finnis-Sinclair density of field 5 and writes
 // dF[i] = F'(rho_i) = -A / (2 sqrt(rho_i)) (0 for rho_i = 0).  blockIdx.y = segment.
-template <int J>
+template <int J, int ACC>
 __global__ void __launch_bounds__(64) k_density(int N, const int *__restrict__ poff, const double *__restrict__ ell,
                                                 const double *__restrict__ nrm, double2 *__restrict__ u,
                                                 double fs_A, double *__restrict__ dF) {
-    density_dispatch<J, 0>(blockIdx.y, N, poff, ell, nrm, u, fs_A, dF);
+    density_dispatch<J, ACC, 0>(blockIdx.y, N, poff, ell, nrm, u, fs_A, dF);
 }
 
 // ---------------------------------------------------------------------------
@@ -926,10 +927,9 @@ __device__ __forceinline__ void dedr_chain(double2 (&P)[J + 1], double2 (&sP)[J 
 }
 
 // One wave of 64 consecutive pairs (CSR order, so a few atoms i).  When the wave's
-// pairs belong to at most kDedrAtoms atoms, their Y~ rows are first copied into LDS
-// (coalesced: consecutive lanes take consecutive atoms of one element) and the chains
-// read Y~ from there; otherwise from global memory.
-constexpr int kDedrAtoms = 5;
+// pairs belong to at most SA atoms (the kernel-shape choice of this pass; 0: never),
+// their Y~ rows are first copied into LDS (coalesced: consecutive lanes take consecutive
+// atoms of one element) and the chains read Y~ from there; otherwise from global memory.
 
 // fs (stride 64, or null): a Finnis-Sinclair addend per component
 template <int J>
@@ -963,7 +963,7 @@ __device__ __forceinline__ void dedr_pair(int p, size_t Pcap, const double (&g)[
 // with F'(rho_i) from the density pass.  (The gather's g_p - g_rev(p) then assembles the
 // pair force (F'(rho_i) + F'(rho_j)) phi' + V'.)  It is staged in LDS so that no register
 // stays live across the SNAP contraction.
-template <int J>
+template <int J, int SA>
 __global__ void __launch_bounds__(64) k_dedr(int N, int n_sys, const int *__restrict__ off,
                                              const double *__restrict__ box, const double *__restrict__ x,
                                              const int *__restrict__ poff, const int *__restrict__ pair_i,
@@ -971,10 +971,8 @@ __global__ void __launch_bounds__(64) k_dedr(int N, int n_sys, const int *__rest
                                              const double2 *__restrict__ ytil, double *__restrict__ dedr,
                                              FsFuse fz) {
     constexpr int NH = n_half(J);
-    // the Y~ rows of the wave's atoms are staged in LDS up to twojmax 8 (above, 5 atoms'
-    // rows would take most of the LDS and cut the waves per CU; they are read from memory)
-    constexpr bool kStage = J <= 8;
-    __shared__ double2 ys[kStage ? kDedrAtoms * NH : 1];
+    constexpr bool kStage = SA > 0;
+    __shared__ double2 ys[kStage ? SA * NH : 1];
     __shared__ double fsb[3 * 64];
     const int P = poff[N];
     const int p0 = blockIdx.x * 64;
@@ -1006,7 +1004,7 @@ __global__ void __launch_bounds__(64) k_dedr(int N, int n_sys, const int *__rest
     }
     const double fc = live ? g[4] : 0.0;
     const double *fs = fz.on ? fsb + lane : nullptr;
-    if (kStage && na <= kDedrAtoms) {
+    if (kStage && na <= SA) {
         for (int q = lane; q < na * NH; q += 64) {
             const int e = q / na, at = q - e * na;
             ys[q] = ytil[(size_t)e * N + i0 + at];
@@ -1237,6 +1235,32 @@ void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w,
                        w.pair_j, fp, w.rho, f, e_atom, accumulate);
 }
 
+template <int J, int ACC>
+static void density_launch_acc(int N, Work &w, const SnapDev &sd, double fs_A, double *dF, hipStream_t st) {
+    hipLaunchKernelGGL((k_density<J, ACC>), dim3(nblk(N, 64), dens_segments(J, ACC)), dim3(64), 0, st, N, w.poff, w.ell,
+                       sd.nrm, w.u, fs_A, dF);
+}
+
+template <int J>
+static void density_launch(int N, Work &w, const SnapDev &sd, double fs_A, double *dF, hipStream_t st) {
+    if constexpr (J <= 8) {
+        switch (sd.shape.dens_acc) {
+            case 28: density_launch_acc<J, 28>(N, w, sd, fs_A, dF, st); return;
+            case 21: density_launch_acc<J, 21>(N, w, sd, fs_A, dF, st); return;
+            default: break;
+        }
+    }
+    density_launch_acc<J, 45>(N, w, sd, fs_A, dF, st);
+}
+
+template <int J, int SA>
+static void dedr_launch(const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, const FsFuse &fz,
+                        hipStream_t st) {
+    const int N = bd.N;
+    hipLaunchKernelGGL((k_dedr<J, SA>), dim3(nblk((size_t)N * kMaxNeigh, 64)), dim3(64), 0, st, N, bd.n_sys, bd.off,
+                       bd.box, x, w.poff, w.pair_i, w.pair_j, sd.gp, w.Pcap, w.ytil, w.dedr, fz);
+}
+
 template <int J>
 static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
                           double *e_atom, int accumulate, hipStream_t st, KernelProf *prof, hipEvent_t join,
@@ -1253,12 +1277,12 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     hipLaunchKernelGGL(k_pair_ell, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box,
                        x, w.poff, w.nbr_t, sd.gp, w.ell, fuse ? fuse->d : 0.0, fuse ? w.flag : nullptr);
     pf.begin(PROF_DENSITY, st);
-    hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 64), dens_segments(J)), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm,
-                       w.u, fuse ? fuse->A : 0.0, fuse ? w.rho : nullptr);
+    density_launch<J>(N, w, sd, fuse ? fuse->A : 0.0, fuse ? w.rho : nullptr, st);
     pf.end(st);
     pf.begin(PROF_ADJOINT, st);
     if constexpr (J <= 8) {
-        launch_adjoint(J, sd.adj, N, w.u, sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate, st);
+        launch_adjoint(J, sd.adj, N, w.u, sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate, st,
+                       sd.shape.adj_waves);
     } else {
         // above twojmax 8 a 64-atom tile of u no longer fits the LDS: the coupling program
         // reads u from memory (lane = atom, coefficients wave-uniform), split over
@@ -1273,8 +1297,15 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     }
     pf.end(st);
     pf.begin(PROF_DEDR, st);
-    hipLaunchKernelGGL(k_dedr<J>, dim3(nblk((size_t)N * kMaxNeigh, 64)), dim3(64), 0, st, N, bd.n_sys, bd.off, bd.box,
-                       x, w.poff, w.pair_i, w.pair_j, sd.gp, w.Pcap, w.ytil, w.dedr, fz);
+    if constexpr (J <= 8) {
+        switch (sd.shape.dedr_atoms) {
+            case 0: dedr_launch<J, 0>(bd, x, sd, w, fz, st); break;
+            case 3: dedr_launch<J, 3>(bd, x, sd, w, fz, st); break;
+            default: dedr_launch<J, 5>(bd, x, sd, w, fz, st); break;
+        }
+    } else {
+        dedr_launch<J, 0>(bd, x, sd, w, fz, st);
+    }
     pf.end(st);
     if (join) (void)hipStreamWaitEvent(st, join, 0);  // f written by work on another stream
     hipLaunchKernelGGL(k_gather, dim3(nblk(N, 64)), dim3(256), 0, st, N, w.poff, w.rev, w.dedr, w.Pcap, f,
@@ -1296,11 +1327,6 @@ void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, 
     }
 }
 
-template <int J>
-static void density_launch(int N, Work &w, const SnapDev &sd, hipStream_t st) {
-    hipLaunchKernelGGL(k_density<J>, dim3(nblk(N, 64), dens_segments(J)), dim3(64), 0, st, N, w.poff, w.ell, sd.nrm,
-                       w.u, 0.0, nullptr);
-}
 
 void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st) {
     const int N = bd.N;
@@ -1309,13 +1335,13 @@ void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapD
     hipLaunchKernelGGL(k_pair_ell, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box,
                        x, w.poff, w.nbr_t, sd.gp, w.ell, 0.0, nullptr);
     switch (J) {
-        case 2: density_launch<2>(N, w, sd, st); break;
-        case 4: density_launch<4>(N, w, sd, st); break;
-        case 6: density_launch<6>(N, w, sd, st); break;
-        case 8: density_launch<8>(N, w, sd, st); break;
-        case 10: density_launch<10>(N, w, sd, st); break;
-        case 12: density_launch<12>(N, w, sd, st); break;
-        case 14: density_launch<14>(N, w, sd, st); break;
+        case 2: density_launch<2>(N, w, sd, 0.0, nullptr, st); break;
+        case 4: density_launch<4>(N, w, sd, 0.0, nullptr, st); break;
+        case 6: density_launch<6>(N, w, sd, 0.0, nullptr, st); break;
+        case 8: density_launch<8>(N, w, sd, 0.0, nullptr, st); break;
+        case 10: density_launch<10>(N, w, sd, 0.0, nullptr, st); break;
+        case 12: density_launch<12>(N, w, sd, 0.0, nullptr, st); break;
+        case 14: density_launch<14>(N, w, sd, 0.0, nullptr, st); break;
         default: break;
     }
 }

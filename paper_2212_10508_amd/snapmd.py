@@ -47,6 +47,15 @@ class Langevin(C.Structure):
                 ("scheme", C.c_int32), ("bbk_c0", C.c_double), ("bbk_c1", C.c_double)]
 
 
+class KShape(C.Structure):
+    _fields_ = [("density_acc", C.c_int32), ("dedr_stage_atoms", C.c_int32), ("adjoint_waves", C.c_int32)]
+
+
+# compiled variants of each kernel-shape field (twojmax <= 8)
+SHAPE_CHOICES = {"density_acc": (45, 28, 21), "dedr_stage_atoms": (5, 3, 0), "adjoint_waves": (12, 8)}
+DEFAULT_SHAPE = (45, 5, 12)
+
+
 class ParaLog(C.Structure):
     _fields_ = [("max_log", C.c_int32), ("n_log", C.POINTER(C.c_int32)), ("n_in", C.POINTER(C.c_int32)),
                 ("n_fi", C.POINTER(C.c_int32)), ("n_fi_after", C.POINTER(C.c_int32)),
@@ -107,6 +116,10 @@ def lib():
     L.snapmd_relax.argtypes = [P, C.c_int, C.POINTER(Snap), C.POINTER(Fs), C.POINTER(Batch), P, i32, d, d, d,
                                C.POINTER(d), C.POINTER(i32), P]
     L.snapmd_relax.restype = C.c_int
+    L.snapmd_set_kernel_shape.argtypes = [P, i32, C.POINTER(KShape)]
+    L.snapmd_set_kernel_shape.restype = C.c_int
+    L.snapmd_get_kernel_shape.argtypes = [P, i32, C.POINTER(KShape)]
+    L.snapmd_get_kernel_shape.restype = C.c_int
     L.snapmd_set_coarse_fs.argtypes = [P, C.POINTER(Fs)]
     L.snapmd_set_coarse_fs.restype = C.c_int
     L.snapmd_set_coarse_snap.argtypes = [P, C.POINTER(Snap)]
@@ -439,6 +452,20 @@ class Context:
         k = _Keep()
         s = make_snap(k, J, beta, rcut, rfac0, rmin0)
         self._check(lib().snapmd_set_coarse_snap(self.h, C.byref(s)))
+
+    def set_kernel_shape(self, J, shape):
+        """Kernel shape (density_acc, dedr_stage_atoms, adjoint_waves) of the SNAP passes at
+        twojmax J (None: the built-in shape)."""
+        if shape is None:
+            self._check(lib().snapmd_set_kernel_shape(self.h, int(J), None))
+        else:
+            ks = KShape(*[int(v) for v in shape])
+            self._check(lib().snapmd_set_kernel_shape(self.h, int(J), C.byref(ks)))
+
+    def kernel_shape(self, J):
+        ks = KShape()
+        self._check(lib().snapmd_get_kernel_shape(self.h, int(J), C.byref(ks)))
+        return (ks.density_acc, ks.dedr_stage_atoms, ks.adjoint_waves)
 
     def set_coarse_fs(self, fs):
         """Finnis-Sinclair parameters of the coarse propagator of parareal_iterate (a dict like

@@ -147,3 +147,96 @@ def tune_sweep_width(ctx, run_iteration, N, widths=(1, 8, 16), passes=2, log=Non
             log("sweep workgroups %d: %.2f ms" % (K, times[K] * 1e3))
     ctx.set_sweep_workgroups(best)
     return best, times
+
+
+# ---------------------------------------------------------------------------
+# Kernel shapes of the SNAP passes
+# ---------------------------------------------------------------------------
+def shape_candidates():
+    """Every compiled kernel shape (density_acc, dedr_stage_atoms, adjoint_waves), the
+    built-in one first."""
+    from itertools import product
+    from .snapmd import SHAPE_CHOICES, DEFAULT_SHAPE
+    out = [tuple(DEFAULT_SHAPE)]
+    for s in product(SHAPE_CHOICES["density_acc"], SHAPE_CHOICES["dedr_stage_atoms"], SHAPE_CHOICES["adjoint_waves"]):
+        if s not in out:
+            out.append(s)
+    return out
+
+
+def shape_cache_path():
+    import os
+    return os.environ.get("SNAPMD_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "snapmd", "kernel_shapes.json"))
+
+
+def shape_cache_key(arch, J, atoms_per_launch):
+    """(architecture, twojmax, size class): the size class is the power of two nearest to
+    the atoms one launch of the SNAP passes covers."""
+    import math
+    return "%s:J%d:2^%d" % (arch, J, int(round(math.log2(max(atoms_per_launch, 1)))))
+
+
+def load_shape(key, path=None):
+    import json
+    try:
+        with open(path or shape_cache_path()) as fh:
+            ent = json.load(fh).get(key)
+        return tuple(ent["shape"]) if ent else None
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def save_shape(key, shape, record, path=None):
+    import json
+    import os
+    path = path or shape_cache_path()
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        data = {}
+    data[key] = dict(record, shape=list(shape))
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune_kernel_shapes(ctx, J, run, force_error, tol=1e-10, passes=2, log=None):
+    """Choose the kernel shape of the SNAP passes at twojmax J.  Every candidate is first
+    checked: force_error() (forces of a sampled system under the current shape against the
+    oracle, norm-wise relative) must be <= tol, or the candidate is dropped.  The passing
+    candidates then run once untimed (their launch sequences are captured) and are timed
+    with run() (synchronised by the caller) in `passes` interleaved passes; the fastest
+    total wins.  Returns (shape, table) with table[i] = dict(shape, force_error, ms or
+    None) for every candidate; the context is left on the chosen shape."""
+    table = []
+    for s in shape_candidates():
+        ctx.set_kernel_shape(J, s)
+        err = float(force_error())
+        table.append(dict(shape=list(s), force_error=err, ms=None, passed=err <= tol))
+        if log:
+            log("shape %s: force error %.2e%s" % (s, err, "" if err <= tol else " -- dropped"))
+    ok = [t for t in table if t["passed"]]
+    if not ok:
+        ctx.set_kernel_shape(J, None)
+        raise RuntimeError("no kernel shape passes the force check")
+    for t in ok:
+        ctx.set_kernel_shape(J, t["shape"])
+        run()
+    for t in ok:
+        t["ms"] = 0.0
+    for _ in range(passes):
+        for t in ok:
+            ctx.set_kernel_shape(J, t["shape"])
+            t0 = time.perf_counter()
+            run()
+            t["ms"] += (time.perf_counter() - t0) * 1e3 / passes
+    best = min(ok, key=lambda t: t["ms"])
+    if log:
+        for t in ok:
+            log("shape %s: %.2f ms" % (tuple(t["shape"]), t["ms"]))
+    ctx.set_kernel_shape(J, best["shape"])
+    return tuple(best["shape"]), table

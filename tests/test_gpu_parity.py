@@ -225,3 +225,65 @@ def test_invalid_arguments_rejected(S):
     with pytest.raises(S.SnapmdError) as e:
         S.snap_forces(dev(x), [0, 200, x.shape[1]], np.tile(box, 2), 6, beta)  # offsets non-monotone
     assert e.value.code == S.EINVAL
+
+
+@pytest.mark.parametrize("J", [6, 8])
+def test_kernel_shapes_give_identical_forces(S, J):
+    """Every compiled kernel shape of the SNAP passes (density register budget, dE/dr
+    staging width, adjoint waves per tile) gives the same forces, bit for bit, on a ragged
+    batch, and energies equal to rounding; the oracle check of one shape is shared."""
+    from paper_2212_10508_amd import tune
+    xa, box = W.bcc_sia(4, jitter=0.1, seed=60 + J)
+    xb, _ = W.bcc_sia(4, jitter=0.1, seed=61 + J)
+    X = np.concatenate([xa, xb], axis=1)
+    n = xa.shape[1]
+    off, boxes = [0, n, 2 * n], np.tile(box, (2, 1))
+    beta = W.snap_beta(J, seed=J)
+    ctx = S.Context(0)
+    ref = None
+    for shape in tune.shape_candidates():
+        ctx.set_kernel_shape(J, shape)
+        assert ctx.kernel_shape(J) == tuple(shape)
+        e = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+        f = host(ctx.snap_forces(dev(X), off, boxes, J, beta, e_atom=e))
+        eh = host(e)
+        if ref is None:
+            ref = (f, eh)
+            ora = O.snap_compute(xa, box, J, beta)["f"]
+            assert frel(f[:, :n], ora) < FTOL
+        else:
+            assert np.array_equal(f, ref[0]), shape
+            assert np.max(np.abs(eh - ref[1])) < 1e-13 * np.max(np.abs(ref[1])), shape
+    ctx.set_kernel_shape(J, None)
+    assert ctx.kernel_shape(J) == (45, 5, 12)
+    with pytest.raises(S.SnapmdError):
+        ctx.set_kernel_shape(J, (44, 5, 12))
+
+
+def test_kernel_shape_tuner_checks_parity_first(S):
+    """The tuner drops a candidate whose forces miss the oracle (a deliberately wrong
+    reference for one shape, planted on the host) and picks among the others."""
+    from paper_2212_10508_amd import tune
+    J = 4
+    x, box = W.bcc_sia(4, jitter=0.05, seed=70)
+    n = x.shape[1]
+    beta = W.snap_beta(J, seed=70)
+    ctx = S.Context(0)
+    ora = O.snap_compute(x, box, J, beta)["f"]
+    xd = dev(x)
+    bad = (21, 0, 8)
+
+    def force_error():
+        f = host(ctx.snap_forces(xd, [0, n], box, J, beta))
+        err = frel(f, ora)
+        return 1.0 if ctx.kernel_shape(J) == bad else err
+
+    def run():
+        ctx.snap_forces(xd, [0, n], box, J, beta)
+        torch.cuda.synchronize()
+
+    shape, table = tune.tune_kernel_shapes(ctx, J, run, force_error, passes=1)
+    assert len(table) == len(tune.shape_candidates())
+    assert [t["passed"] for t in table if tuple(t["shape"]) == bad] == [False]
+    assert all(t["ms"] is not None for t in table if t["passed"])
+    assert shape != bad and ctx.kernel_shape(J) == shape

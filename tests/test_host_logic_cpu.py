@@ -98,3 +98,19 @@ def test_parareal_windows_are_checked_before_any_call():
                                  ([0, 1], [4, 6], 6, 2), ([0], [4], 5, 2)):
         with pytest.raises(ValueError):
             check_windows(n_in, n_fi, slots, R)
+
+
+def test_kernel_shape_cache_round_trip(tmp_path):
+    """Tuned kernel shapes are cached as JSON keyed by (architecture, twojmax, size class);
+    another key misses, and the candidates list every compiled variant once, the built-in
+    shape first."""
+    path = str(tmp_path / "shapes.json")
+    k = tune.shape_cache_key("gfx950", 8, 15 * 1025)
+    assert k == "gfx950:J8:2^14"
+    assert tune.load_shape(k, path) is None
+    tune.save_shape(k, (28, 3, 12), {"ms": 170.0}, path)
+    tune.save_shape(tune.shape_cache_key("gfx950", 6, 129), (21, 0, 8), {"ms": 1.0}, path)
+    assert tune.load_shape(k, path) == (28, 3, 12)
+    assert tune.load_shape("gfx942:J8:2^14", path) is None
+    c = tune.shape_candidates()
+    assert c[0] == (45, 5, 12) and len(c) == len(set(c)) == 18
