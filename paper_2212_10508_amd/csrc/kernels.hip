@@ -350,54 +350,77 @@ __global__ void k_compact(int N, const int *__restrict__ nbr, const int *__restr
                           int *__restrict__ nbr_t, int *__restrict__ rev, int *__restrict__ status,
                           const int *__restrict__ flag) {
     if (*flag == 0) return;
-    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = (int)(q / kMaxNeigh), t = (int)(q - (size_t)i * kMaxNeigh);
-    if (i >= N || t >= cnt[i]) return;
-    const int p = poff[i] + t, j = nbr[q];
-    pair_i[p] = i;
-    pair_j[p] = j;
-    if (nbr_t) nbr_t[(size_t)t * N + i] = j;
-    const int *lj = nbr + (size_t)j * kMaxNeigh;
-    const int cj = cnt[j];
-    int r = -1;
-    for (int u = 0; u < cj; ++u)
-        if (lj[u] == i) { r = poff[j] + u; break; }
-    if (r < 0) { atomicOr(status, 4); r = p; }
-    rev[p] = r;
+    // grid-stride over the N * kMaxNeigh list slots (a bounded grid keeps the launch cheap
+    // on the steps where no rebuild is due)
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < (size_t)N * kMaxNeigh;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q / kMaxNeigh), t = (int)(q - (size_t)i * kMaxNeigh);
+        if (t >= cnt[i]) continue;
+        const int p = poff[i] + t, j = nbr[q];
+        pair_i[p] = i;
+        pair_j[p] = j;
+        if (nbr_t) nbr_t[(size_t)t * N + i] = j;
+        const int *lj = nbr + (size_t)j * kMaxNeigh;
+        const int cj = cnt[j];
+        int r = -1;
+        for (int u = 0; u < cj; ++u)
+            if (lj[u] == i) { r = poff[j] + u; break; }
+        if (r < 0) { atomicOr(status, 4); r = p; }
+        rev[p] = r;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Finnis-Sinclair EAM
 // ---------------------------------------------------------------------------
-__global__ void k_fs_rho(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
-                         const double *__restrict__ x, const int *__restrict__ poff,
-                         const int *__restrict__ pair_j, double d, double *__restrict__ rho,
-                         int *__restrict__ clear_flag) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Finnis-Sinclair passes, kFsLanes consecutive lanes per atom: lane q takes the atom's
+// list entries q, q + kFsLanes, ...; the partial sums are combined by a fixed butterfly,
+// so the result does not depend on the launch (deterministic).  Several lanes per atom
+// keep enough waves in flight to hide the latency of the neighbours' position loads.
+constexpr int kFsLanes = 4;
+
+__device__ __forceinline__ double fs_lane_sum(double v) {
+#pragma unroll
+    for (int o = 1; o < kFsLanes; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_fs_rho(int N, int n_sys, const int *__restrict__ off,
+                                                const double *__restrict__ box, const double *__restrict__ x,
+                                                const int *__restrict__ poff, const int *__restrict__ pair_j,
+                                                double d, double *__restrict__ rho, int *__restrict__ clear_flag) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
     // the neighbour pipeline that read the rebuild flag has finished: clear it for the next step
-    if (clear_flag && i == 0) *clear_flag = 0;
-    if (i >= N) return;
+    if (clear_flag && g == 0) *clear_flag = 0;
+    const int i0 = g / kFsLanes, q = g % kFsLanes;
+    const bool own = i0 < N;
+    const int i = own ? i0 : N - 1;
     const int s = sys_of(off, n_sys, i);
     const double Lx = box[3 * s], Ly = box[3 * s + 1], Lz = box[3 * s + 2];
     const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
     const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
     double acc = 0.0;
-    for (int p = poff[i]; p < poff[i + 1]; ++p) {
+    const int pe = own ? poff[i + 1] : 0;
+    for (int p = poff[i] + q; p < pe; p += kFsLanes) {
         const int j = pair_j[p];
         const double dx = mimg(x[j] - xi, Lx, iLx), dy = mimg(x[N + j] - yi, Ly, iLy), dz = mimg(x[2 * N + j] - zi, Lz, iLz);
         const double r2 = dx * dx + dy * dy + dz * dz;
         const double r = r2 * rsqrt_nr(r2);
         if (r2 < d * d) acc += (r - d) * (r - d);
     }
-    rho[i] = acc;
+    acc = fs_lane_sum(acc);
+    if (own && q == 0) rho[i] = acc;
 }
 
-__global__ void k_fs_force(int N, int n_sys, const int *__restrict__ off, const double *__restrict__ box,
-                           const double *__restrict__ x, const int *__restrict__ poff,
-                           const int *__restrict__ pair_j, FsParams fp, const double *__restrict__ rho,
-                           double *__restrict__ f, double *__restrict__ e_atom, int accumulate) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+__global__ void __launch_bounds__(256) k_fs_force(int N, int n_sys, const int *__restrict__ off,
+                                                  const double *__restrict__ box, const double *__restrict__ x,
+                                                  const int *__restrict__ poff, const int *__restrict__ pair_j,
+                                                  FsParams fp, const double *__restrict__ rho, double *__restrict__ f,
+                                                  double *__restrict__ e_atom, int accumulate) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i0 = g / kFsLanes, q = g % kFsLanes;
+    const bool own = i0 < N;
+    const int i = own ? i0 : N - 1;
     const int s = sys_of(off, n_sys, i);
     const double Lx = box[3 * s], Ly = box[3 * s + 1], Lz = box[3 * s + 2];
     const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
@@ -405,7 +428,8 @@ __global__ void k_fs_force(int N, int n_sys, const int *__restrict__ off, const 
     const double ri = rho[i];
     const double dFi = ri > 0.0 ? -fp.A / (2.0 * sqrt(ri)) : 0.0;
     double fx = 0.0, fy = 0.0, fz = 0.0, ep = 0.0;
-    for (int p = poff[i]; p < poff[i + 1]; ++p) {
+    const int pe = own ? poff[i + 1] : 0;
+    for (int p = poff[i] + q; p < pe; p += kFsLanes) {
         const int j = pair_j[p];
         const double dx = mimg(x[j] - xi, Lx, iLx), dy = mimg(x[N + j] - yi, Ly, iLy), dz = mimg(x[2 * N + j] - zi, Lz, iLz);
         const double r2 = dx * dx + dy * dy + dz * dz;
@@ -428,6 +452,11 @@ __global__ void k_fs_force(int N, int n_sys, const int *__restrict__ off, const 
             fz += w * dz;
         }
     }
+    fx = fs_lane_sum(fx);
+    fy = fs_lane_sum(fy);
+    fz = fs_lane_sum(fz);
+    ep = fs_lane_sum(ep);
+    if (!own || q != 0) return;
     if (accumulate) {
         f[i] += fx; f[N + i] += fy; f[2 * N + i] += fz;
     } else {
@@ -1221,7 +1250,8 @@ void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, h
                            rl * rl, w.nbr, w.cnt, w.status, w.flag, w.xref,
                            (bd.cells && bd.n_cells > 0) ? bd.cells : nullptr, w.cell_of, w.cell_start, w.cell_atoms);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, N, w.cnt, w.poff, w.flag);
-    hipLaunchKernelGGL(k_compact, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, w.nbr, w.cnt, w.poff,
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)std::min<size_t>(nblk((size_t)N * kMaxNeigh, 256), 1024)), dim3(256), 0,
+                       st, N, w.nbr, w.cnt, w.poff,
                        w.pair_i, w.pair_j, w.nbr_t, w.rev, w.status, w.flag);
     if (!clear_in_fs) hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, st, w.flag, 0);
 }
@@ -1229,9 +1259,9 @@ void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, h
 void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w, double *f, double *e_atom,
                int accumulate, hipStream_t st, bool clear_flag) {
     const int N = bd.N;
-    hipLaunchKernelGGL(k_fs_rho, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, w.poff,
+    hipLaunchKernelGGL(k_fs_rho, dim3(nblk((size_t)N * kFsLanes, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, w.poff,
                        w.pair_j, fp.d, w.rho, clear_flag ? w.flag : nullptr);
-    hipLaunchKernelGGL(k_fs_force, dim3(nblk(N, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, w.poff,
+    hipLaunchKernelGGL(k_fs_force, dim3(nblk((size_t)N * kFsLanes, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, w.poff,
                        w.pair_j, fp, w.rho, f, e_atom, accumulate);
 }
 
