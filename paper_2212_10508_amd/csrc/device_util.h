@@ -6,8 +6,11 @@ namespace snapmd {
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// Products as explicit FMAs: left to contraction, which of the two products is fused
+// follows the compiler's operand order, which changes with the surrounding code (so two
+// kernel shapes of one pass would round differently).
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
 // a*b + c*d
 __device__ __forceinline__ double2 cmul2(double2 a, double2 b, double2 c, double2 d) {

@@ -667,8 +667,8 @@ __global__ void k_pair_ell(int N, int n_sys, const int *__restrict__ off, const 
 // u (half storage, [e][N] double2) for column C, levels N0 .. N1: one wave per tile of 64
 // atoms, lane = atom.  Step t reads slot t of the 64 atoms' lists from the slot-major copy
 // of a, b and f_c (one coalesced load per field); slots past an atom's count add nothing.
-template <int J, int C, int N0, int N1>
-__device__ void density_lane(int N, const int *__restrict__ poff, const double *__restrict__ ell,
+template <int J, int C, int N0, int N1, bool AHEAD>
+__device__ __forceinline__ void density_lane(int N, const int *__restrict__ poff, const double *__restrict__ ell,
                              const double *__restrict__ nrm, double2 *__restrict__ u, double fs_A,
                              double *__restrict__ dF) {
     const int i = blockIdx.x * 64 + threadIdx.x;
@@ -681,16 +681,38 @@ __device__ void density_lane(int N, const int *__restrict__ poff, const double *
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) tmax = max(tmax, __shfl_xor(tmax, o, 64));
     const size_t sN = (size_t)kMaxNeigh * N;
-    double rho = 0.0;  // Finnis-Sinclair density (column 0 with dF)
-    for (int t = 0; t < tmax; ++t) {
+    constexpr bool kRho = C == 0 && N0 == 0;
+    constexpr int NF = kRho ? 6 : 5;
+    // Fields of slot t: a, b, f_c (and phi); past the count the identity rotation with
+    // zero weight (slot contents unused).
+    auto fetch = [&](int t, double (&f)[NF]) {
         const bool v = t < cnt;
         const size_t q = (size_t)t * N + (v ? i : 0);
-        if constexpr (C == 0 && N0 == 0)
-            if (dF && v) rho += ell[5 * sN + q];
-        // past the count: the identity rotation with zero weight (slot contents unused)
-        const double2 a = v ? make_double2(ell[q], ell[sN + q]) : make_double2(1.0, 0.0);
-        const double2 b = v ? make_double2(ell[2 * sN + q], ell[3 * sN + q]) : make_double2(0.0, 0.0);
-        const double fc = v ? ell[4 * sN + q] : 0.0;
+        f[0] = v ? ell[q] : 1.0;
+        f[1] = v ? ell[sN + q] : 0.0;
+        f[2] = v ? ell[2 * sN + q] : 0.0;
+        f[3] = v ? ell[3 * sN + q] : 0.0;
+        f[4] = v ? ell[4 * sN + q] : 0.0;
+        if constexpr (kRho) f[NF - 1] = (dF && v) ? ell[5 * sN + q] : 0.0;
+    };
+    // AHEAD: slot t + 1 is in flight while slot t is computed (at two waves per SIMD too
+    // few other waves hide the load latency).
+    double nx[NF];
+    if (AHEAD && tmax > 0) fetch(0, nx);
+    double rho = 0.0;  // Finnis-Sinclair density (column 0 with dF)
+    for (int t = 0; t < tmax; ++t) {
+        double f[NF];
+        if constexpr (AHEAD) {
+#pragma unroll
+            for (int m = 0; m < NF; ++m) f[m] = nx[m];
+            if (t + 1 < tmax) fetch(t + 1, nx);
+        } else {
+            fetch(t, f);
+        }
+        if constexpr (kRho) rho += f[NF - 1];
+        const double2 a = make_double2(f[0], f[1]);
+        const double2 b = make_double2(f[2], f[3]);
+        const double fc = f[4];
         const double2 ab = cconj(a);
         double2 P[J + 1];
         P[0] = make_double2(1.0, 0.0);
@@ -707,7 +729,7 @@ __device__ void density_lane(int N, const int *__restrict__ poff, const double *
             const int e = half_idx(n, k, C);
             const double sc = nrm[e];
             const double2 v = acc[chain_acc_idx(C, n, k) - chain_acc_idx(C, N0, 0)];
-            u[(size_t)e * N + i] = make_double2((k == C ? 1.0 : 0.0) + sc * v.x, sc * v.y);
+            u[(size_t)e * N + i] = make_double2(fma(sc, v.x, k == C ? 1.0 : 0.0), sc * v.y);
         }
 }
 
@@ -748,13 +770,20 @@ __host__ __device__ constexpr DensSeg dens_segment(int J, int ACC, int s) {
     return DensSeg{0, 0, 0};
 }
 
+// Least waves per SIMD that the compiler is held to for a register budget: the budget of
+// 28 elements fits three waves (at most 168 registers) only when held to it; the budget
+// of 45 takes up to 256 registers (two waves), that of 21 at most 128 (four) by itself.
+// Only the budget of 45 loads one slot ahead.
+__host__ __device__ constexpr int dens_waves(int ACC) { return ACC == 28 ? 3 : 1; }
+__host__ __device__ constexpr bool dens_ahead(int ACC) { return ACC > 28; }
+
 template <int J, int ACC, int S>
 __device__ __forceinline__ void density_dispatch(int y, int N, const int *__restrict__ poff,
                                                  const double *__restrict__ ell, const double *__restrict__ nrm,
                                                  double2 *__restrict__ u, double fs_A, double *__restrict__ dF) {
     if (y == S) {
         constexpr DensSeg g = dens_segment(J, ACC, S);
-        density_lane<J, g.C, g.N0, g.N1>(N, poff, ell, nrm, u, fs_A, (g.C == 0 && g.N0 == 0) ? dF : nullptr);
+        density_lane<J, g.C, g.N0, g.N1, dens_ahead(ACC)>(N, poff, ell, nrm, u, fs_A, (g.C == 0 && g.N0 == 0) ? dF : nullptr);
     } else if constexpr (S + 1 < dens_segments(J, ACC)) {
         density_dispatch<J, ACC, S + 1>(y, N, poff, ell, nrm, u, fs_A, dF);
     }
@@ -763,7 +792,7 @@ __device__ __forceinline__ void density_dispatch(int y, int N, const int *__rest
 // dF non-null: column 0 also sums the Finnis-Sinclair density of field 5 and writes
 // dF[i] = F'(rho_i) = -A / (2 sqrt(rho_i)) (0 for rho_i = 0).  blockIdx.y = segment.
 template <int J, int ACC>
-__global__ void __launch_bounds__(64) k_density(int N, const int *__restrict__ poff, const double *__restrict__ ell,
+__global__ void __launch_bounds__(64, dens_waves(ACC)) k_density(int N, const int *__restrict__ poff, const double *__restrict__ ell,
                                                 const double *__restrict__ nrm, double2 *__restrict__ u,
                                                 double fs_A, double *__restrict__ dF) {
     density_dispatch<J, ACC, 0>(blockIdx.y, N, poff, ell, nrm, u, fs_A, dF);
