@@ -137,7 +137,11 @@ template <int J, int P, int N1, int N2>
 __device__ __forceinline__ void do_block(int tm, const double2 *__restrict__ lds, const double *__restrict__ cgm,
                                          const double *__restrict__ coef, const int *__restrict__ coef_off,
                                          double2 (&Y)[y_size(J, P)]) {
-    const int lo = max(-N1, tm - N2), hi = min(N1, tm + N2);
+    // A diagonal block (N1 == N2) pairs row m1 with m2 = m - m1 and row m2 with m1: the two
+    // give the same contribution (the CG symmetry under exchange of the two couplings,
+    // applied to both coefficients, with equal signs), so only 2 m1 <= m is visited and the
+    // host table carries the doubled coefficient for 2 m1 < m.
+    const int lo = max(-N1, tm - N2), hi = (N1 == N2) ? min(N1, tm / 2) : min(N1, tm + N2);
     if (lo > hi) return;
     constexpr int NCP = cpl_n(J, N1, N2);
     constexpr int NC = c_size(J, N1, N2);
@@ -292,7 +296,8 @@ void adjoint_tables(int J, const double *beta, AdjointHost &A) {
                     const int lo = std::max(-n1, tm - n2), hi = std::min(n1, tm + n2);
                     if (lo > hi) continue;
                     const double mt = motif_terms(J, n1, n2);
-                    cost[tm + J] += ((hi - lo) / 2 + 1) * (3.0 * mt + 2.0 * (n1 + n2 + 2) + 2.0 * c_size(J, n1, n2));
+                    const int hk = n1 == n2 ? std::min(hi, tm / 2) : hi;  // diagonal blocks: half the rows
+                    cost[tm + J] += ((hk - lo) / 2 + 1) * (3.0 * mt + 2.0 * (n1 + n2 + 2) + 2.0 * c_size(J, n1, n2));
                 }
         std::vector<int> order(2 * J + 1);
         for (int i = 0; i <= 2 * J; ++i) order[i] = i;
@@ -327,13 +332,16 @@ void adjoint_tables(int J, const double *beta, AdjointHost &A) {
                 const int lo = std::max(-n1, tm - n2), hi = std::min(n1, tm + n2);
                 if (lo > hi) continue;
                 A.coef_off[(tm + J) * NB + blk_index(n1, n2)] = (int)A.coef.size();
-                for (int tm1 = lo; tm1 <= hi; tm1 += 2)
+                // diagonal blocks: m1 <= m - m1 only, the pair (m1, m - m1) counted twice
+                const int hk = n1 == n2 ? std::min(hi, tm / 2) : hi;
+                for (int tm1 = lo; tm1 <= hk; tm1 += 2)
                     for (int n = n1 - n2; n <= std::min(J, n1 + n2); n += 2) {
                         double v = 0.0;
                         if (std::abs(tm) <= n) {
                             const int b = zb(n1, n2, n);
                             const double bt = T.zb_wt[b] * A.beta[1 + T.zb_canon[b]];
                             v = bt * cg_coeff(n1, (tm1 + n1) / 2, n2, (tm - tm1 + n2) / 2, n, (tm + n) / 2);
+                            if (n1 == n2 && 2 * tm1 < tm) v *= 2.0;
                         }
                         A.coef.push_back(v);
                     }
