@@ -229,8 +229,11 @@ __global__ void __launch_bounds__(64 * R) k_adjoint_lds(int N, const double2 *__
                                                      double2 *__restrict__ ytil, double *__restrict__ e_atom,
                                                      int accumulate_e) {
     extern __shared__ double2 lds[];
+    __shared__ int simd_waves[4];
     constexpr int NH = n_half(J);
+    constexpr int PER = R / 4;  // waves per SIMD (one workgroup fills the compute unit)
     const int a0 = blockIdx.x * 64;
+    if (threadIdx.x < 4) simd_waves[threadIdx.x] = 0;
     for (int idx = threadIdx.x; idx < NH * 64; idx += 64 * R) {
         const int e = idx >> 6, a = idx & 63;
         lds[idx] = (a0 + a < N) ? u[(size_t)e * N + a0 + a] : make_double2(0.0, 0.0);
@@ -238,10 +241,20 @@ __global__ void __launch_bounds__(64 * R) k_adjoint_lds(int N, const double2 *__
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    // The roles are balanced per SIMD (the waves of one SIMD share its FP64 unit): a wave
+    // takes role PER * simd + (its arrival rank on that SIMD), whatever order the hardware
+    // placed the waves in.  If the waves are not spread PER to a SIMD, role = wave index.
+    const int simd = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_s_getreg((1 << 11) | (4 << 6) | 4));
+    int slot = 0;
+    if (lane == 0) slot = atomicAdd(&simd_waves[simd], 1);
+    slot = __builtin_amdgcn_readfirstlane(slot);
+    __syncthreads();
+    const bool spread = simd_waves[0] == PER && simd_waves[1] == PER && simd_waves[2] == PER && simd_waves[3] == PER;
+    const int role = spread ? simd * PER + slot : wave;
     const double2 *my = lds + lane;
     double esum = 0.0;
     for (int q = 0; q < role_len; ++q) {
-        const int tm = roles[wave * role_len + q];
+        const int tm = roles[role * role_len + q];
         if (tm > J) break;
         if ((tm & 1) == 0)
             esum += process_row<J, 0>(tm, a0 + lane, N, my, cgm, coef, coef_off, nrm, ymult, ytil);
@@ -249,8 +262,8 @@ __global__ void __launch_bounds__(64 * R) k_adjoint_lds(int N, const double2 *__
             esum += process_row<J, 1>(tm, a0 + lane, N, my, cgm, coef, coef_off, nrm, ymult, ytil);
     }
     __syncthreads();  // every wave is done with the u tile: reuse it for the energy partials
-    double *epart = reinterpret_cast<double *>(lds);  // [R][64]
-    epart[wave * 64 + lane] = esum;
+    double *epart = reinterpret_cast<double *>(lds);  // [R][64], by role (a fixed summation order)
+    epart[role * 64 + lane] = esum;
     __syncthreads();
     if (wave == 0 && e_atom && a0 + lane < N) {
         double s = 0.0;
@@ -265,6 +278,58 @@ __global__ void __launch_bounds__(64 * R) k_adjoint_lds(int N, const double2 *__
 // host side: tables and launch
 // ---------------------------------------------------------------------------
 constexpr int kAdjWaves = 12;
+
+// Items (indices into cost, in decreasing cost order) to nb bins with the largest bin load
+// as small as possible: branch and bound seeded with the longest-processing-time-first
+// assignment, bins of equal load tried once, at most 4e6 nodes.  Returns the bin of each
+// item (in the order given).
+static std::vector<int> partition_rows(const std::vector<double> &cost, const std::vector<int> &items, int nb) {
+    const size_t n = items.size();
+    std::vector<int> best(n), cur(n);
+    std::vector<double> load(nb, 0.0);
+    for (size_t k = 0; k < n; ++k) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        best[k] = b;
+        load[b] += cost[items[k]];
+    }
+    double bound = *std::max_element(load.begin(), load.end());
+    std::fill(load.begin(), load.end(), 0.0);
+    long nodes = 0;
+    std::vector<int> stack_bin(n, -1);  // iterative depth-first search
+    size_t k = 0;
+    while (true) {
+        if (k == n) {
+            const double m = *std::max_element(load.begin(), load.end());
+            if (m < bound) {
+                bound = m;
+                best = cur;
+            }
+            if (k == 0) break;
+            --k;
+            load[cur[k]] -= cost[items[k]];
+            continue;
+        }
+        int b = stack_bin[k] + 1;
+        const double c = cost[items[k]];
+        for (; b < nb; ++b) {
+            bool dup = false;  // a bin with the load of an earlier one gives the same subtrees
+            for (int e = 0; e < b && !dup; ++e) dup = load[e] == load[b];
+            if (!dup && load[b] + c < bound) break;
+        }
+        if (b >= nb || ++nodes > 4000000) {
+            stack_bin[k] = -1;
+            if (k == 0 || nodes > 4000000) break;
+            --k;
+            load[cur[k]] -= cost[items[k]];
+            continue;
+        }
+        stack_bin[k] = b;
+        cur[k] = b;
+        load[b] += c;
+        ++k;
+    }
+    return best;
+}
 
 void adjoint_tables(int J, const double *beta, AdjointHost &A) {
     const SnapTables &T = snap_tables(J);
@@ -302,14 +367,17 @@ void adjoint_tables(int J, const double *beta, AdjointHost &A) {
         std::vector<int> order(2 * J + 1);
         for (int i = 0; i <= 2 * J; ++i) order[i] = i;
         std::sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        // rows to waves by longest processing time first, for 12 and for 8 waves
+        // rows to SIMDs, then each SIMD's rows to its waves (12 waves: three per SIMD, 8: two)
         auto assign = [&](int nw, std::vector<int> &flat, int &len) {
+            const int per = nw / 4;
             std::vector<std::vector<int>> roles(nw);
-            std::vector<double> load(nw, 0.0);
-            for (int i : order) {
-                const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-                roles[w].push_back(i - J);
-                load[w] += cost[i];
+            const std::vector<int> simd_of = partition_rows(cost, order, 4);
+            for (int sd = 0; sd < 4; ++sd) {
+                std::vector<int> mine;
+                for (size_t q = 0; q < order.size(); ++q)
+                    if (simd_of[q] == sd) mine.push_back(order[q]);
+                const std::vector<int> wave_of = partition_rows(cost, mine, per);
+                for (size_t q = 0; q < mine.size(); ++q) roles[sd * per + wave_of[q]].push_back(mine[q] - J);
             }
             len = 0;
             for (auto &r : roles) len = std::max(len, (int)r.size() + 1);
