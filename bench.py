@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CUs x 128 FLOP/clk x 2.4 GHz
 DEFAULT_PLAN = "15,13,14,15,7"   # slab chunks of one adjoint round each (64 x 1025 atoms)
-PROF_EVERY = 8            # HIP events around every 8th launch of each timed kernel
+PROF_EVERY = 4            # HIP events around every 4th launch of each timed kernel
 
 
 def log(*a):
@@ -462,7 +462,7 @@ def main():
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--slabs", type=int, default=64)
     ap.add_argument("--L", type=int, default=100)
@@ -475,7 +475,8 @@ def main():
                          "covers); 'builtin' for the library's own plan" % DEFAULT_PLAN)
     ap.add_argument("--sweep-workgroups", type=int, default=0, help="coarse sweep width (0: built in)")
     ap.add_argument("--shape", default=None,
-                    help="kernel shape density_acc,dedr_stage_atoms,adjoint_waves of the SNAP passes (no shape "
+                    help="kernel shape density_acc,dedr_stage_atoms,adjoint_waves[,density_parts] of the SNAP passes "
+                         "(no shape "
                          "tuning); default: the cached choice for this GPU and workload, else tuned (untimed)")
     ap.add_argument("--retune-shape", action="store_true", help="tune the kernel shape even if one is cached")
     ap.add_argument("--no-configs", action="store_true", help="skip the secondary workloads")
@@ -606,13 +607,17 @@ def main():
     q_cur.copy_(q_start)
     p_cur.copy_(p_start)
     torch.cuda.synchronize()
-    # HIP events around every PROF_EVERY-th launch of each timed kernel (an event record
-    # idles the device for a few microseconds; a sample keeps that out of the timed run)
-    ctx.profile(True, every=PROF_EVERY)
+    # HIP events around every PROF_EVERY-th launch of each timed kernel, in the last timed
+    # iteration only: with kernel timing on, the SNAP propagation is launched one by one
+    # (the event records sit between the launches), which costs about 5 % of an
+    # iteration against the replayed graphs of the others
     t0 = time.perf_counter()
     for k in range(args.steps):
+        if k == args.steps - 1:
+            ctx.profile(True, every=PROF_EVERY)
+        t1 = time.perf_counter()
         d = iteration()
-        log("step %d: delta %.3e" % (k, d))
+        log("step %d: delta %.3e, %.2f ms" % (k, d, (time.perf_counter() - t1) * 1e3))
     torch.cuda.synchronize()
     t_it = (time.perf_counter() - t0) / args.steps
     prof = {name: ctx.profile_read(kid) for name, kid in

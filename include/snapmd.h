@@ -353,15 +353,20 @@ int snapmd_relax(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, const 
  *                     recomputing the lower levels of its column chain);
  *   dedr_stage_atoms  dE/dr: a wave whose 64 pairs belong to at most this many atoms copies
  *                     their adjoint rows into local memory first (5, 3, or 0: never);
- *   adjoint_waves     LDS-tiled adjoint: waves per 64-atom tile (12 or 8).
- * Forces do not depend on the shape; per-atom energies only through the order in which
- * the adjoint's partial sums are added.  snapmd_set_kernel_shape(ctx, J, NULL) restores
- * the built-in shape (45, 5, 12); any other value is SNAPMD_EINVAL.  snapmd_get_kernel_shape
- * writes the shape in use for J. */
+ *   adjoint_waves     LDS-tiled adjoint: waves per 64-atom tile (12 or 8);
+ *   density_parts     density pass of a force evaluation: the neighbour slots of a tile are
+ *                     split over this many waves (1 or 2), whose partial densities the
+ *                     adjoint adds as it loads them (more, shorter waves).
+ * With the same density_parts, forces do not depend on the shape and per-atom energies
+ * only through the order in which the adjoint's partial sums are added; the two
+ * density_parts values differ by the rounding of the density sum.
+ * snapmd_set_kernel_shape(ctx, J, NULL) restores the built-in shape (45, 5, 12, 1); any
+ * other value is SNAPMD_EINVAL.  snapmd_get_kernel_shape writes the shape in use for J. */
 typedef struct {
     int32_t density_acc;
     int32_t dedr_stage_atoms;
     int32_t adjoint_waves;
+    int32_t density_parts;
 } snapmd_kernel_shape;
 int snapmd_set_kernel_shape(snapmd_ctx *ctx, int32_t twojmax, const snapmd_kernel_shape *shape);
 int snapmd_get_kernel_shape(snapmd_ctx *ctx, int32_t twojmax, snapmd_kernel_shape *shape);

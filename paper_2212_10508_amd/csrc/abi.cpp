@@ -638,7 +638,7 @@ int replay_range(snapmd_ctx *ctx, Work &w, double *f, int potential, const Batch
         const uint64_t sk[] = {(uint64_t)sd.J, d(sd.gp.rcut), d(sd.gp.rfac0), d(sd.gp.rmin0), d(sd.beta0),
                                u(sd.nrm), u(sd.adj.coef), u(sd.adj.cgm), u(sd.adj.roles), u(sd.adj.roles8),
                                (uint64_t)sd.shape.dens_acc, (uint64_t)sd.shape.dedr_atoms,
-                               (uint64_t)sd.shape.adj_waves};
+                               (uint64_t)sd.shape.adj_waves, (uint64_t)sd.shape.dens_parts};
         key.insert(key.end(), sk, sk + 13);
     }
     const int ci = (&w == &ctx->wc) ? 1 : 0;
@@ -2134,11 +2134,13 @@ int snapmd_set_kernel_shape(snapmd_ctx *ctx, int32_t twojmax, const snapmd_kerne
     }
     const bool ok = (shape->density_acc == 45 || shape->density_acc == 28 || shape->density_acc == 21) &&
                     (shape->dedr_stage_atoms == 5 || shape->dedr_stage_atoms == 3 || shape->dedr_stage_atoms == 0) &&
-                    (shape->adjoint_waves == 12 || shape->adjoint_waves == 8);
+                    (shape->adjoint_waves == 12 || shape->adjoint_waves == 8) &&
+                    (shape->density_parts == 1 || shape->density_parts == 2);
     if (!ok)
-        return fail(ctx, SNAPMD_EINVAL, "kernel shape (%d, %d, %d) is not one of the compiled variants",
-                    shape->density_acc, shape->dedr_stage_atoms, shape->adjoint_waves);
-    ctx->shapes[twojmax] = KernelShape{shape->density_acc, shape->dedr_stage_atoms, shape->adjoint_waves};
+        return fail(ctx, SNAPMD_EINVAL, "kernel shape (%d, %d, %d, %d) is not one of the compiled variants",
+                    shape->density_acc, shape->dedr_stage_atoms, shape->adjoint_waves, shape->density_parts);
+    ctx->shapes[twojmax] =
+        KernelShape{shape->density_acc, shape->dedr_stage_atoms, shape->adjoint_waves, shape->density_parts};
     return SNAPMD_OK;
 }
 
@@ -2146,8 +2148,8 @@ int snapmd_get_kernel_shape(snapmd_ctx *ctx, int32_t twojmax, snapmd_kernel_shap
     if (!ctx || !shape) return SNAPMD_EINVAL;
     auto it = ctx->shapes.find(twojmax);
     KernelShape k = it != ctx->shapes.end() ? it->second : KernelShape{};
-    if (twojmax > kMaxJLds) k = KernelShape{45, 0, 12};
-    *shape = snapmd_kernel_shape{k.dens_acc, k.dedr_atoms, k.adj_waves};
+    if (twojmax > kMaxJLds) k = KernelShape{45, 0, 12, 1};
+    *shape = snapmd_kernel_shape{k.dens_acc, k.dedr_atoms, k.adj_waves, k.dens_parts};
     return SNAPMD_OK;
 }
 

@@ -220,8 +220,10 @@ __device__ __forceinline__ double process_row(int tm, int atom, int N, const dou
 }
 
 // R waves per workgroup (the kernel-shape choice of this pass: 12, three per SIMD, or 8)
+// u2 non-null: the density comes in two parts (u + u2), added as the tile is loaded.
 template <int J, int R>
 __global__ void __launch_bounds__(64 * R) k_adjoint_lds(int N, const double2 *__restrict__ u,
+                                                     const double2 *__restrict__ u2,
                                                      const double *__restrict__ cgm, const double *__restrict__ coef,
                                                      const int *__restrict__ coef_off, const int *__restrict__ roles,
                                                      int role_len, const double *__restrict__ nrm,
@@ -236,7 +238,12 @@ __global__ void __launch_bounds__(64 * R) k_adjoint_lds(int N, const double2 *__
     if (threadIdx.x < 4) simd_waves[threadIdx.x] = 0;
     for (int idx = threadIdx.x; idx < NH * 64; idx += 64 * R) {
         const int e = idx >> 6, a = idx & 63;
-        lds[idx] = (a0 + a < N) ? u[(size_t)e * N + a0 + a] : make_double2(0.0, 0.0);
+        double2 v = make_double2(0.0, 0.0);
+        if (a0 + a < N) {
+            v = u[(size_t)e * N + a0 + a];
+            if (u2) v = cadd(v, u2[(size_t)e * N + a0 + a]);
+        }
+        lds[idx] = v;
     }
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -422,26 +429,27 @@ size_t adjoint_lds_bytes(int J) {
 }
 
 template <int J>
-static void launch_adj(const AdjointDev &ad, int waves, int N, const double2 *u, const double *nrm,
+static void launch_adj(const AdjointDev &ad, int waves, int N, const double2 *u, const double2 *u2, const double *nrm,
                        const double *ymult, double beta0, double2 *ytil, double *e_atom, int accumulate,
                        hipStream_t st) {
     const size_t lds = adjoint_lds_bytes(J);
     if (waves == 8 && ad.roles8)
-        hipLaunchKernelGGL((k_adjoint_lds<J, 8>), dim3((N + 63) / 64), dim3(64 * 8), lds, st, N, u, ad.cgm, ad.coef,
+        hipLaunchKernelGGL((k_adjoint_lds<J, 8>), dim3((N + 63) / 64), dim3(64 * 8), lds, st, N, u, u2, ad.cgm, ad.coef,
                            ad.coef_off, ad.roles8, ad.role_len8, nrm, ymult, beta0, ytil, e_atom, accumulate);
     else
         hipLaunchKernelGGL((k_adjoint_lds<J, kAdjWaves>), dim3((N + 63) / 64), dim3(64 * kAdjWaves), lds, st, N, u,
-                           ad.cgm, ad.coef, ad.coef_off, ad.roles, ad.role_len, nrm, ymult, beta0, ytil, e_atom,
+                           u2, ad.cgm, ad.coef, ad.coef_off, ad.roles, ad.role_len, nrm, ymult, beta0, ytil, e_atom,
                            accumulate);
 }
 
-void launch_adjoint(int J, const AdjointDev &ad, int N, const double2 *u, const double *nrm, const double *ymult,
-                    double beta0, double2 *ytil, double *e_atom, int accumulate, hipStream_t st, int waves) {
+void launch_adjoint(int J, const AdjointDev &ad, int N, const double2 *u, const double2 *u2, const double *nrm,
+                    const double *ymult, double beta0, double2 *ytil, double *e_atom, int accumulate, hipStream_t st,
+                    int waves) {
     switch (J) {
-        case 2: launch_adj<2>(ad, waves, N, u, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
-        case 4: launch_adj<4>(ad, waves, N, u, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
-        case 6: launch_adj<6>(ad, waves, N, u, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
-        case 8: launch_adj<8>(ad, waves, N, u, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
+        case 2: launch_adj<2>(ad, waves, N, u, u2, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
+        case 4: launch_adj<4>(ad, waves, N, u, u2, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
+        case 6: launch_adj<6>(ad, waves, N, u, u2, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
+        case 8: launch_adj<8>(ad, waves, N, u, u2, nrm, ymult, beta0, ytil, e_atom, accumulate, st); break;
         default: break;
     }
 }

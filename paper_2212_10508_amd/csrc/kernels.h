@@ -62,11 +62,14 @@ struct AdjointDev {
 //   dens_acc   density pass: most accumulated elements per lane (45, 28 or 21)
 //   dedr_atoms dE/dr: atoms whose Y~ rows a wave stages in LDS (5, 3 or 0: from memory)
 //   adj_waves  LDS-tiled adjoint: waves per 64-atom tile (12 or 8)
-// Above twojmax 8 the passes have one shape each (45, 0, -).
+//   dens_parts density pass of a force evaluation: waves over which a tile's neighbour
+//              slots are split (1 or 2); part p writes u + p nh N, the adjoint adds them
+// Above twojmax 8 the passes have one shape each (45, 0, -, 1).
 struct KernelShape {
     int dens_acc = 45;
     int dedr_atoms = 5;
     int adj_waves = 12;
+    int dens_parts = 1;
 };
 
 // SNAP coefficient-dependent tables on the device.
@@ -248,8 +251,10 @@ void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, 
 void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st);
 void adjoint_tables(int J, const double *beta, AdjointHost &A);
 void adjoint_init_attributes();
-void launch_adjoint(int J, const AdjointDev &ad, int N, const double2 *u, const double *nrm, const double *ymult,
-                    double beta0, double2 *ytil, double *e_atom, int accumulate, hipStream_t st, int waves = 12);
+// u2: the second part of the density (null: u is whole)
+void launch_adjoint(int J, const AdjointDev &ad, int N, const double2 *u, const double2 *u2, const double *nrm,
+                    const double *ymult, double beta0, double2 *ytil, double *e_atom, int accumulate, hipStream_t st,
+                    int waves = 12);
 void launch_bispectrum(const BatchDev &bd, const SnapDev &sd, Work &w, double *B, hipStream_t st);
 void launch_jvp_density(int J, int N, const Work &w, const double *wf, const double *nrm, double2 *du,
                         hipStream_t st);

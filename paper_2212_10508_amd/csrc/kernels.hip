@@ -667,6 +667,10 @@ __global__ void k_pair_ell(int N, int n_sys, const int *__restrict__ off, const 
 // u (half storage, [e][N] double2) for column C, levels N0 .. N1: one wave per tile of 64
 // atoms, lane = atom.  Step t reads slot t of the 64 atoms' lists from the slot-major copy
 // of a, b and f_c (one coalesced load per field); slots past an atom's count add nothing.
+// With gridDim.z = parts > 1 the slots are split into parts (blockIdx.z = part), each
+// writing its partial sum to u + part nh N (nh = half elements); the identity term of
+// level 0 goes with part 0, and the Finnis-Sinclair density (dF non-null, column 0) is
+// summed over all slots by part 0.
 template <int J, int C, int N0, int N1, bool AHEAD>
 __device__ __forceinline__ void density_lane(int N, const int *__restrict__ poff, const double *__restrict__ ell,
                              const double *__restrict__ nrm, double2 *__restrict__ u, double fs_A,
@@ -680,9 +684,16 @@ __device__ __forceinline__ void density_lane(int N, const int *__restrict__ poff
     int tmax = cnt;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) tmax = max(tmax, __shfl_xor(tmax, o, 64));
+    const int part = blockIdx.z, parts = gridDim.z;
+    const int tb = (part * tmax + parts - 1) / parts, te = ((part + 1) * tmax + parts - 1) / parts;
     const size_t sN = (size_t)kMaxNeigh * N;
     constexpr bool kRho = C == 0 && N0 == 0;
     constexpr int NF = kRho ? 6 : 5;
+    const bool rho_here = kRho && dF && part == 0;
+    const bool rho_apart = rho_here && parts > 1;  // all slots, in a loop of its own
+    double rho = 0.0;  // Finnis-Sinclair density (column 0 with dF)
+    if (rho_apart)
+        for (int t = 0; t < cnt; ++t) rho += ell[5 * sN + (size_t)t * N + i];
     // Fields of slot t: a, b, f_c (and phi); past the count the identity rotation with
     // zero weight (slot contents unused).
     auto fetch = [&](int t, double (&f)[NF]) {
@@ -693,19 +704,18 @@ __device__ __forceinline__ void density_lane(int N, const int *__restrict__ poff
         f[2] = v ? ell[2 * sN + q] : 0.0;
         f[3] = v ? ell[3 * sN + q] : 0.0;
         f[4] = v ? ell[4 * sN + q] : 0.0;
-        if constexpr (kRho) f[NF - 1] = (dF && v) ? ell[5 * sN + q] : 0.0;
+        if constexpr (kRho) f[NF - 1] = (rho_here && !rho_apart && v) ? ell[5 * sN + q] : 0.0;
     };
     // AHEAD: slot t + 1 is in flight while slot t is computed (at two waves per SIMD too
     // few other waves hide the load latency).
     double nx[NF];
-    if (AHEAD && tmax > 0) fetch(0, nx);
-    double rho = 0.0;  // Finnis-Sinclair density (column 0 with dF)
-    for (int t = 0; t < tmax; ++t) {
+    if (AHEAD && tb < te) fetch(tb, nx);
+    for (int t = tb; t < te; ++t) {
         double f[NF];
         if constexpr (AHEAD) {
 #pragma unroll
             for (int m = 0; m < NF; ++m) f[m] = nx[m];
-            if (t + 1 < tmax) fetch(t + 1, nx);
+            if (t + 1 < te) fetch(t + 1, nx);
         } else {
             fetch(t, f);
         }
@@ -720,8 +730,9 @@ __device__ __forceinline__ void density_lane(int N, const int *__restrict__ poff
         density_step<J, C, N0, N1, 2 * C>(P, acc, b, ab, fc);
     }
     if (i >= N) return;
-    if constexpr (C == 0 && N0 == 0)
-        if (dF) dF[i] = rho > 0.0 ? -fs_A / (2.0 * sqrt(rho)) : 0.0;
+    if (rho_here) dF[i] = rho > 0.0 ? -fs_A / (2.0 * sqrt(rho)) : 0.0;
+    double2 *up = u + (size_t)part * n_half(J) * N;
+    const double one = part == 0 ? 1.0 : 0.0;
 #pragma unroll
     for (int n = N0; n <= N1; ++n)
 #pragma unroll
@@ -729,7 +740,7 @@ __device__ __forceinline__ void density_lane(int N, const int *__restrict__ poff
             const int e = half_idx(n, k, C);
             const double sc = nrm[e];
             const double2 v = acc[chain_acc_idx(C, n, k) - chain_acc_idx(C, N0, 0)];
-            u[(size_t)e * N + i] = make_double2(fma(sc, v.x, k == C ? 1.0 : 0.0), sc * v.y);
+            up[(size_t)e * N + i] = make_double2(fma(sc, v.x, k == C ? one : 0.0), sc * v.y);
         }
 }
 
@@ -772,7 +783,8 @@ __host__ __device__ constexpr DensSeg dens_segment(int J, int ACC, int s) {
 
 // Least waves per SIMD that the compiler is held to for a register budget: the budget of
 // 28 elements fits three waves (at most 168 registers) only when held to it; the budget
-// of 45 takes up to 256 registers (two waves), that of 21 at most 128 (four) by itself.
+// of 45 takes up to 256 registers (two waves), that of 21 about 130 (three; held to four
+// waves it spills).
 // Only the budget of 45 loads one slot ahead.
 __host__ __device__ constexpr int dens_waves(int ACC) { return ACC == 28 ? 3 : 1; }
 __host__ __device__ constexpr bool dens_ahead(int ACC) { return ACC > 28; }
@@ -1295,21 +1307,25 @@ void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w,
 }
 
 template <int J, int ACC>
-static void density_launch_acc(int N, Work &w, const SnapDev &sd, double fs_A, double *dF, hipStream_t st) {
-    hipLaunchKernelGGL((k_density<J, ACC>), dim3(nblk(N, 64), dens_segments(J, ACC)), dim3(64), 0, st, N, w.poff, w.ell,
+static void density_launch_acc(int N, Work &w, const SnapDev &sd, double fs_A, double *dF, hipStream_t st,
+                               int parts) {
+    hipLaunchKernelGGL((k_density<J, ACC>), dim3(nblk(N, 64), dens_segments(J, ACC), parts), dim3(64), 0, st, N,
+                       w.poff, w.ell,
                        sd.nrm, w.u, fs_A, dF);
 }
 
+// parts: the slot split of the pass (1: u whole; 2: partial sums at u and u + nh N)
 template <int J>
-static void density_launch(int N, Work &w, const SnapDev &sd, double fs_A, double *dF, hipStream_t st) {
+static void density_launch(int N, Work &w, const SnapDev &sd, double fs_A, double *dF, hipStream_t st,
+                           int parts = 1) {
     if constexpr (J <= 8) {
         switch (sd.shape.dens_acc) {
-            case 28: density_launch_acc<J, 28>(N, w, sd, fs_A, dF, st); return;
-            case 21: density_launch_acc<J, 21>(N, w, sd, fs_A, dF, st); return;
+            case 28: density_launch_acc<J, 28>(N, w, sd, fs_A, dF, st, parts); return;
+            case 21: density_launch_acc<J, 21>(N, w, sd, fs_A, dF, st, parts); return;
             default: break;
         }
     }
-    density_launch_acc<J, 45>(N, w, sd, fs_A, dF, st);
+    density_launch_acc<J, 45>(N, w, sd, fs_A, dF, st, parts);
 }
 
 template <int J, int SA>
@@ -1335,13 +1351,15 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     }
     hipLaunchKernelGGL(k_pair_ell, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box,
                        x, w.poff, w.nbr_t, sd.gp, w.ell, fuse ? fuse->d : 0.0, fuse ? w.flag : nullptr);
+    // the LDS-tiled adjoint adds the two parts of a split density as it loads its tile
+    const int parts = (J <= 8 && sd.shape.dens_parts == 2) ? 2 : 1;
     pf.begin(PROF_DENSITY, st);
-    density_launch<J>(N, w, sd, fuse ? fuse->A : 0.0, fuse ? w.rho : nullptr, st);
+    density_launch<J>(N, w, sd, fuse ? fuse->A : 0.0, fuse ? w.rho : nullptr, st, parts);
     pf.end(st);
     pf.begin(PROF_ADJOINT, st);
     if constexpr (J <= 8) {
-        launch_adjoint(J, sd.adj, N, w.u, sd.nrm, sd.ymult, sd.beta0, w.ytil, e_atom, accumulate, st,
-                       sd.shape.adj_waves);
+        launch_adjoint(J, sd.adj, N, w.u, parts == 2 ? w.u + (size_t)n_half(J) * N : nullptr, sd.nrm, sd.ymult,
+                       sd.beta0, w.ytil, e_atom, accumulate, st, sd.shape.adj_waves);
     } else {
         // above twojmax 8 a 64-atom tile of u no longer fits the LDS: the coupling program
         // reads u from memory (lane = atom, coefficients wave-uniform), split over

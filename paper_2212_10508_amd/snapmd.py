@@ -48,12 +48,14 @@ class Langevin(C.Structure):
 
 
 class KShape(C.Structure):
-    _fields_ = [("density_acc", C.c_int32), ("dedr_stage_atoms", C.c_int32), ("adjoint_waves", C.c_int32)]
+    _fields_ = [("density_acc", C.c_int32), ("dedr_stage_atoms", C.c_int32), ("adjoint_waves", C.c_int32),
+                ("density_parts", C.c_int32)]
 
 
 # compiled variants of each kernel-shape field (twojmax <= 8)
-SHAPE_CHOICES = {"density_acc": (45, 28, 21), "dedr_stage_atoms": (5, 3, 0), "adjoint_waves": (12, 8)}
-DEFAULT_SHAPE = (45, 5, 12)
+SHAPE_CHOICES = {"density_acc": (45, 28, 21), "dedr_stage_atoms": (5, 3, 0), "adjoint_waves": (12, 8),
+                 "density_parts": (1, 2)}
+DEFAULT_SHAPE = (45, 5, 12, 1)
 
 
 class ParaLog(C.Structure):
@@ -454,18 +456,24 @@ class Context:
         self._check(lib().snapmd_set_coarse_snap(self.h, C.byref(s)))
 
     def set_kernel_shape(self, J, shape):
-        """Kernel shape (density_acc, dedr_stage_atoms, adjoint_waves) of the SNAP passes at
-        twojmax J (None: the built-in shape)."""
+        """Kernel shape (density_acc, dedr_stage_atoms, adjoint_waves, density_parts) of the
+        SNAP passes at twojmax J (None: the built-in shape; a shape of three values has
+        density_parts 1)."""
         if shape is None:
             self._check(lib().snapmd_set_kernel_shape(self.h, int(J), None))
         else:
-            ks = KShape(*[int(v) for v in shape])
+            v = [int(q) for q in shape]
+            if len(v) == 3:
+                v.append(1)
+            if len(v) != 4:
+                raise ValueError("a kernel shape has 3 or 4 values (got %d)" % len(v))
+            ks = KShape(*v)
             self._check(lib().snapmd_set_kernel_shape(self.h, int(J), C.byref(ks)))
 
     def kernel_shape(self, J):
         ks = KShape()
         self._check(lib().snapmd_get_kernel_shape(self.h, int(J), C.byref(ks)))
-        return (ks.density_acc, ks.dedr_stage_atoms, ks.adjoint_waves)
+        return (ks.density_acc, ks.dedr_stage_atoms, ks.adjoint_waves, ks.density_parts)
 
     def set_coarse_fs(self, fs):
         """Finnis-Sinclair parameters of the coarse propagator of parareal_iterate (a dict like

@@ -153,12 +153,13 @@ def tune_sweep_width(ctx, run_iteration, N, widths=(1, 8, 16), passes=2, log=Non
 # Kernel shapes of the SNAP passes
 # ---------------------------------------------------------------------------
 def shape_candidates():
-    """Every compiled kernel shape (density_acc, dedr_stage_atoms, adjoint_waves), the
-    built-in one first."""
+    """Every compiled kernel shape (density_acc, dedr_stage_atoms, adjoint_waves,
+    density_parts), the built-in one first."""
     from itertools import product
     from .snapmd import SHAPE_CHOICES, DEFAULT_SHAPE
     out = [tuple(DEFAULT_SHAPE)]
-    for s in product(SHAPE_CHOICES["density_acc"], SHAPE_CHOICES["dedr_stage_atoms"], SHAPE_CHOICES["adjoint_waves"]):
+    for s in product(SHAPE_CHOICES["density_acc"], SHAPE_CHOICES["dedr_stage_atoms"], SHAPE_CHOICES["adjoint_waves"],
+                     SHAPE_CHOICES["density_parts"]):
         if s not in out:
             out.append(s)
     return out

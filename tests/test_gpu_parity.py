@@ -231,7 +231,8 @@ def test_invalid_arguments_rejected(S):
 def test_kernel_shapes_give_identical_forces(S, J):
     """Every compiled kernel shape of the SNAP passes (density register budget, dE/dr
     staging width, adjoint waves per tile) gives the same forces, bit for bit, on a ragged
-    batch, and energies equal to rounding; the oracle check of one shape is shared."""
+    batch, and energies equal to rounding, for each slot split of the density pass; the
+    two splits agree to rounding; the oracle check of one shape per split is shared."""
     from paper_2212_10508_amd import tune
     xa, box = W.bcc_sia(4, jitter=0.1, seed=60 + J)
     xb, _ = W.bcc_sia(4, jitter=0.1, seed=61 + J)
@@ -240,24 +241,30 @@ def test_kernel_shapes_give_identical_forces(S, J):
     off, boxes = [0, n, 2 * n], np.tile(box, (2, 1))
     beta = W.snap_beta(J, seed=J)
     ctx = S.Context(0)
-    ref = None
+    ref = {}
+    ora = O.snap_compute(xa, box, J, beta)["f"]
     for shape in tune.shape_candidates():
         ctx.set_kernel_shape(J, shape)
         assert ctx.kernel_shape(J) == tuple(shape)
         e = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
         f = host(ctx.snap_forces(dev(X), off, boxes, J, beta, e_atom=e))
         eh = host(e)
-        if ref is None:
-            ref = (f, eh)
-            ora = O.snap_compute(xa, box, J, beta)["f"]
+        parts = shape[3]
+        if parts not in ref:
+            ref[parts] = (f, eh)
             assert frel(f[:, :n], ora) < FTOL
         else:
-            assert np.array_equal(f, ref[0]), shape
-            assert np.max(np.abs(eh - ref[1])) < 1e-13 * np.max(np.abs(ref[1])), shape
+            assert np.array_equal(f, ref[parts][0]), shape
+            assert np.max(np.abs(eh - ref[parts][1])) < 1e-13 * np.max(np.abs(ref[parts][1])), shape
+    assert frel(ref[2][0], ref[1][0]) < 1e-13
+    assert np.max(np.abs(ref[2][1] - ref[1][1])) < 1e-13 * np.max(np.abs(ref[1][1]))
     ctx.set_kernel_shape(J, None)
-    assert ctx.kernel_shape(J) == (45, 5, 12)
-    with pytest.raises(S.SnapmdError):
-        ctx.set_kernel_shape(J, (44, 5, 12))
+    assert ctx.kernel_shape(J) == (45, 5, 12, 1)
+    ctx.set_kernel_shape(J, (28, 3, 8))   # three values: density_parts 1
+    assert ctx.kernel_shape(J) == (28, 3, 8, 1)
+    for bad in ((44, 5, 12, 1), (45, 5, 12, 3)):
+        with pytest.raises(S.SnapmdError):
+            ctx.set_kernel_shape(J, bad)
 
 
 def test_kernel_shape_tuner_checks_parity_first(S):
@@ -271,7 +278,7 @@ def test_kernel_shape_tuner_checks_parity_first(S):
     ctx = S.Context(0)
     ora = O.snap_compute(x, box, J, beta)["f"]
     xd = dev(x)
-    bad = (21, 0, 8)
+    bad = (21, 0, 8, 1)
 
     def force_error():
         f = host(ctx.snap_forces(xd, [0, n], box, J, beta))

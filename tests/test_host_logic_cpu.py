@@ -108,9 +108,9 @@ def test_kernel_shape_cache_round_trip(tmp_path):
     k = tune.shape_cache_key("gfx950", 8, 15 * 1025)
     assert k == "gfx950:J8:2^14"
     assert tune.load_shape(k, path) is None
-    tune.save_shape(k, (28, 3, 12), {"ms": 170.0}, path)
-    tune.save_shape(tune.shape_cache_key("gfx950", 6, 129), (21, 0, 8), {"ms": 1.0}, path)
-    assert tune.load_shape(k, path) == (28, 3, 12)
+    tune.save_shape(k, (28, 3, 12, 2), {"ms": 170.0}, path)
+    tune.save_shape(tune.shape_cache_key("gfx950", 6, 129), (21, 0, 8, 1), {"ms": 1.0}, path)
+    assert tune.load_shape(k, path) == (28, 3, 12, 2)
     assert tune.load_shape("gfx942:J8:2^14", path) is None
     c = tune.shape_candidates()
-    assert c[0] == (45, 5, 12) and len(c) == len(set(c)) == 18
+    assert c[0] == (45, 5, 12, 1) and len(c) == len(set(c)) == 36
