@@ -92,17 +92,21 @@ __global__ void k_neigh_build(int N, int n_sys, const int *__restrict__ off, con
 }
 
 // Full lists of every atom of a batch of small systems (at most kSysLdsAtoms atoms each):
-// one workgroup per system copies its positions to LDS, bins them into the system's cell
-// grid in LDS (cells[s] = (nx, ny, nz, .), nx = 0 or too many cells: all pairs) with
-// atoms ascending in each cell, and builds each atom's list from the 27-cell stencil.
+// the workgroups (s, g) of system s (blockIdx.x = s, blockIdx.y = g) each copy the
+// system's positions to LDS and bin them into its cell grid in LDS (cells[s] = (nx, ny,
+// nz, .), nx = 0 or too many cells: all pairs) with atoms ascending in each cell; then
+// workgroup g builds the lists of the system's atoms g T .. g T + T - 1 (T threads, one
+// atom each) from the 27-cell stencil.  Several workgroups per system keep the rebuild
+// short when a batch holds only a few systems.
 constexpr int kSysLdsAtoms = 4096;
 constexpr int kSysCells = 1024;
+constexpr int kNeighSysThreads = 256;
 
 size_t neigh_sys_lds_bytes(int max_sys) {
     return (size_t)max_sys * (3 * sizeof(double) + 2 * sizeof(uint16_t)) + (2 * kSysCells + 1) * sizeof(int) + 16;
 }
 
-__global__ void __launch_bounds__(1024) k_neigh_sys(int N, const int *__restrict__ off, const double *__restrict__ box,
+__global__ void __launch_bounds__(kNeighSysThreads) k_neigh_sys(int N, const int *__restrict__ off, const double *__restrict__ box,
                                                     const double *__restrict__ x, double rc2,
                                                     const int4 *__restrict__ cells, int *__restrict__ nbr,
                                                     int *__restrict__ cnt, int *__restrict__ status,
@@ -110,8 +114,9 @@ __global__ void __launch_bounds__(1024) k_neigh_sys(int N, const int *__restrict
     if (*flag == 0) return;
     extern __shared__ double sm[];
     const int s = blockIdx.x, j0 = off[s], ns = off[s + 1] - j0;
-    if (ns <= 0) return;
     const int tid = threadIdx.x, T = blockDim.x;
+    const int q_me = blockIdx.y * T + tid;  // the atom this thread builds the list of
+    if (blockIdx.y * T >= ns) return;
     double *xs = sm;                                                 // [3][ns]
     int *ccnt = reinterpret_cast<int *>(xs + 3 * ns);                // [kSysCells] counts / fill pointers
     int *cstart = ccnt + kSysCells;                                  // [kSysCells + 1]
@@ -190,7 +195,8 @@ __global__ void __launch_bounds__(1024) k_neigh_sys(int N, const int *__restrict
         }
         __syncthreads();
     }
-    for (int q = tid; q < ns; q += T) {
+    if (q_me < ns) {
+        const int q = q_me;
         const int i = j0 + q;
         const double xi = xs[q], yi = xs[ns + q], zi = xs[2 * ns + q];
         int c = 0;
@@ -211,9 +217,25 @@ __global__ void __launch_bounds__(1024) k_neigh_sys(int N, const int *__restrict
                     const int cy = (iy + ay + ci.y) % ci.y;
                     for (int az = -1; az <= 1; ++az) {
                         const int cc = (cx * ci.y + cy) * ci.z + (iz + az + ci.z) % ci.z;
-                        for (int qq = cstart[cc]; qq < cstart[cc + 1]; ++qq) {
-                            const int jl = catom[qq];
-                            if (jl != q) try_j(jl);
+                        // four candidates per step: their loads and distances are
+                        // independent, the list keeps the cell's ascending order
+                        for (int qq = cstart[cc], qe = cstart[cc + 1]; qq < qe; qq += 4) {
+                            int jl[4];
+                            double r2[4];
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) jl[k] = qq + k < qe ? (int)catom[qq + k] : q;
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                const double dx = mimg(xs[jl[k]] - xi, Lx, iLx), dy = mimg(xs[ns + jl[k]] - yi, Ly, iLy),
+                                             dz = mimg(xs[2 * ns + jl[k]] - zi, Lz, iLz);
+                                r2[k] = dx * dx + dy * dy + dz * dz;
+                            }
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                if (jl[k] != q && r2[k] < rc2) {
+                                    if (c < kMaxNeigh) nbr[(size_t)i * kMaxNeigh + c] = j0 + jl[k];
+                                    ++c;
+                                }
                         }
                     }
                 }
@@ -324,6 +346,8 @@ __global__ void __launch_bounds__(1024) k_scan(int N, const int *__restrict__ cn
     const int chunk = (N + 1023) / 1024;
     const int b = t * chunk, e = min(N, b + chunk);
     int s = 0;
+    // unrolled so that several of the thread's loads are in flight at once
+#pragma unroll 8
     for (int i = b; i < e; ++i) s += cnt[i];
     part[t] = s;
     __syncthreads();
@@ -334,6 +358,7 @@ __global__ void __launch_bounds__(1024) k_scan(int N, const int *__restrict__ cn
         __syncthreads();
     }
     int run = part[t] - s;  // exclusive
+#pragma unroll 8
     for (int i = b; i < e; ++i) {
         poff[i] = run;
         run += cnt[i];
@@ -360,11 +385,19 @@ __global__ void k_compact(int N, const int *__restrict__ nbr, const int *__restr
         pair_i[p] = i;
         pair_j[p] = j;
         if (nbr_t) nbr_t[(size_t)t * N + i] = j;
-        const int *lj = nbr + (size_t)j * kMaxNeigh;
+        // rank of i in j's list: eight entries (two 16-byte loads) per step, the entries
+        // past j's count ignored (they hold an earlier build's neighbours)
+        const int4 *lj4 = reinterpret_cast<const int4 *>(nbr + (size_t)j * kMaxNeigh);
         const int cj = cnt[j];
         int r = -1;
-        for (int u = 0; u < cj; ++u)
-            if (lj[u] == i) { r = poff[j] + u; break; }
+        for (int u = 0; u < cj && r < 0; u += 8) {
+            const int4 a = lj4[u / 4], b = lj4[u / 4 + 1];
+            const int v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int k = 7; k >= 0; --k)
+                if (v[k] == i && u + k < cj) r = u + k;
+        }
+        if (r >= 0) r += poff[j];
         if (r < 0) { atomicOr(status, 4); r = p; }
         rev[p] = r;
     }
@@ -1273,7 +1306,8 @@ void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, h
     const double rl = rc + skin;
     if (bd.max_sys > 0 && bd.max_sys <= kSysLdsAtoms) {
         // small systems: the whole build in one kernel, one workgroup per system
-        hipLaunchKernelGGL(k_neigh_sys, dim3(bd.n_sys), dim3(1024), neigh_sys_lds_bytes(bd.max_sys), st, N, bd.off,
+        hipLaunchKernelGGL(k_neigh_sys, dim3(bd.n_sys, nblk(bd.max_sys, kNeighSysThreads)), dim3(kNeighSysThreads),
+                           neigh_sys_lds_bytes(bd.max_sys), st, N, bd.off,
                            bd.box, x, rl * rl, (bd.cells && bd.n_cells > 0) ? bd.cells : nullptr, w.nbr, w.cnt,
                            w.status, w.flag, w.xref);
     } else if (bd.cells && bd.n_cells > 0) {

@@ -743,7 +743,8 @@ __device__ __forceinline__ double get_tagged(const unsigned long long *p, unsign
 
 // Exchange b: the workgroup copies the np partial values parts[q] (tagged words) into pdst
 // and n doubles of src (tagged words) into dst in LDS, 8 values per thread in flight (16
-// were slower, measured).  Ends with a workgroup barrier; returns
+// were slower, measured); the words of the eight not yet tagged b are reloaded together
+// until all are.  Ends with a workgroup barrier; returns
 // false in every thread when some wait ran out or another workgroup gave up.
 __device__ bool mc_get(double *__restrict__ dst, const unsigned long long *__restrict__ src, int n,
                        const unsigned long long *__restrict__ parts, int np, double *__restrict__ pdst,
@@ -753,18 +754,42 @@ __device__ bool mc_get(double *__restrict__ dst, const unsigned long long *__res
     bool ok = true;
     for (int q = tid; q < np && ok; q += T)
         pdst[q] = get_tagged(parts + 2 * q, ld_word(parts + 2 * q), ld_word(parts + 2 * q + 1), b, a, spins, ok);
+    const unsigned long long tg = b + 1;
     for (int base = tid; base < n && ok; base += 8 * T) {
         unsigned long long lo[8], hi[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int q = base + k * T;
-            lo[k] = q < n ? ld_word(src + 2 * q) : 0ull;
-            hi[k] = q < n ? ld_word(src + 2 * q + 1) : 0ull;
+            lo[k] = q < n ? ld_word(src + 2 * q) : tg << 32;
+            hi[k] = q < n ? ld_word(src + 2 * q + 1) : tg << 32;
         }
+        // words not yet carrying the tag are loaded again together (one round trip per
+        // retry for all eight, not one per word)
+        while (true) {
+            bool ready = true;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) ready = ready && (lo[k] >> 32) == tg && (hi[k] >> 32) == tg;
+            if (ready) break;
+            ++spins;
+            if (spins > kMcSpin ||
+                ((spins & 255) == 0 && __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+                __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int q = base + k * T;
+                if ((lo[k] >> 32) != tg) lo[k] = ld_word(src + 2 * q);
+                if ((hi[k] >> 32) != tg) hi[k] = ld_word(src + 2 * q + 1);
+            }
+        }
+        if (!ok) break;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int q = base + k * T;
-            if (q < n) dst[q] = get_tagged(src + 2 * q, lo[k], hi[k], b, a, spins, ok);
+            if (q < n) dst[q] = __longlong_as_double((long long)((hi[k] << 32) | (lo[k] & 0xffffffffull)));
         }
     }
     return __syncthreads_or(ok ? 0 : 1) == 0;
@@ -827,9 +852,17 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
         for (int v = 0; v < K; ++v) s += pv[(k - 1) * K + v];
         return s;
     };
+    // the Gaussians of step l of slab n, loaded one step ahead (the load is off the
+    // sequential chain of steps)
+    auto noise_of = [&](int n, int l, double (&z)[3]) {
+        const double *gz = a.noise + ((size_t)((n - a.n_in) * a.L + l) * 3) * N;
+#pragma unroll
+        for (int al = 0; al < 3; ++al) z[al] = gz[al * N + i];
+    };
+    double nz[3] = {0.0, 0.0, 0.0};
     for (int n = a.n_in; n < a.n_fi && alive; ++n) {
+        if (own) noise_of(n, 0, nz);
         for (int l = -1; l < a.L; ++l) {
-            const double *gz = a.noise + ((size_t)((n - a.n_in) * a.L + max(l, 0)) * 3) * N;
             double d2m = 0.0;
             if (own) {
 #pragma unroll
@@ -837,13 +870,14 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
                     if (l >= 0) {
                         double pp = pr[al] + hk * fr[al];
                         double xx = xo[al] + hd * pp;
-                        pp = a.c1 * pp + a.sig * gz[al * N + i];
+                        pp = a.c1 * pp + a.sig * nz[al];
                         xx = xx + hd * pp;
                         pr[al] = pp;
                         xo[al] = xx;
                     }
                     d2m += (xo[al] - xr[al]) * (xo[al] - xr[al]);
                 }
+                if (l >= 0 && l + 1 < a.L) noise_of(n, l + 1, nz);
             }
             const double m = wave_max(d2m);
             double wmax = 0.0;
