@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CUs x 128 FLOP/clk x 2.4 GHz
-DEFAULT_PLAN = "15,13,14,15,7"   # slab chunks of one adjoint round each (64 x 1025 atoms)
+DEFAULT_PLAN = "15,13,14,14,8"   # slab chunks of one adjoint round each (64 x 1025 atoms)
 PROF_EVERY = 4            # HIP events around every 4th launch of each timed kernel
 
 
@@ -185,7 +185,7 @@ def kernel_rates(ctx, S, J, atoms, pairs, evals):
             continue
         avg = ms / nl
         tf = per_launch[name] / (avg * 1e-3) / 1e12
-        per_unit, unit = traffic_per_unit(name)
+        per_unit, unit = traffic_per_unit(name, ctx.kernel_shape(J))
         units = atoms if unit == "atom" else pairs
         out[name] = {"avg_ms": avg, "launches_timed": nl, "launches": evals, "tflops": tf,
                      "frac": tf / FP64_PEAK_TFLOPS,
@@ -403,10 +403,11 @@ def other_configs(S, W, log):
     return out
 
 
-def pmc_probe(S, W, J, S_slabs):
+def pmc_probe(S, W, J, S_slabs, shape=None):
     """The two force evaluations of one FS + SNAP BAOAB step of the batch (distinct
-    1025-atom slab states; the propagation's kernels, launched one by one) and a plain
-    512 MiB device copy whose byte counters calibrate FETCH_SIZE / WRITE_SIZE."""
+    1025-atom slab states; the propagation's kernels, launched one by one, in the given
+    kernel shape) and a plain 512 MiB device copy whose byte counters calibrate
+    FETCH_SIZE / WRITE_SIZE."""
     import torch
     wl = W.slabs_1025(n_slabs=S_slabs, seed=1, J=J)
     n = wl["xs"][0].shape[1]
@@ -416,6 +417,8 @@ def pmc_probe(S, W, J, S_slabs):
     boxes = np.tile(wl["box"], (S_slabs, 1))
     ctx = S.context(0)
     ctx.use_graphs(False)
+    if shape:
+        ctx.set_kernel_shape(J, shape)
     ctx.langevin_steps(S.POT_FS_SNAP, X, P, off, boxes, 1, step0=0, dt=wl["dt"], gamma=wl["gamma"],
                        mass=wl["mass"], T=wl["T"], seed=1, noise_id=0, fs=W.FS_W, J=J, beta=wl["beta"])
     torch.cuda.synchronize()
@@ -429,31 +432,35 @@ def pmc_probe(S, W, J, S_slabs):
 
 
 # HBM traffic per unit of the SNAP kernels, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
-# passes over `bench.py --pmc-probe` (per dispatch of the FS + SNAP propagation kernels,
-# 64 x 1025 atoms, 1.71 M pairs), each scaled by what the counter reads for a 512 MiB
-# device copy in the same process (FETCH x 2.0, WRITE x 1.0).  A figure holds only for the
-# kernel source it was taken on (sha256 of the file); after a change the traffic is
-# reported as null until it is measured again.
+# passes over `bench.py --pmc-probe --shape ...` (per dispatch of the FS + SNAP propagation
+# kernels, 64 x 1025 atoms, 1.71 M pairs), each scaled by what the counter reads for a
+# 512 MiB device copy in the same process (FETCH x 2.0, WRITE x 1.0).  A figure holds only
+# for the kernel source it was taken on (sha256 of the file) and the kernel shape it was
+# measured in; otherwise the traffic is reported as null.
+_ADJ_SHA = "68c4b49b7e00b758b4222b6720aebb5031bb3fd6fcf2c24e5568892801b662e6"
+_KER_SHA = "45cfe45071b8cb54c09a6ede8a3b00baea62d2b111a04b606a20975dfd9db8de"
 TRAFFIC = {
-    "adjoint": ("paper_2212_10508_amd/csrc/adjoint.hip",
-                "b213ae4ad852068155c19b9c3e32d3e1c660a037de09948fab4e59a3dcfe1fd4", 5190.6, "atom"),
-    "dedr": ("paper_2212_10508_amd/csrc/kernels.hip",
-             "59b3065dd330c2a1f15ea4733a2bffd1127e249a1c8d87de33a2be0038682962", 449.5, "pair"),
-    "density": ("paper_2212_10508_amd/csrc/kernels.hip",
-                "59b3065dd330c2a1f15ea4733a2bffd1127e249a1c8d87de33a2be0038682962", 308.9, "pair"),
+    "adjoint": ("paper_2212_10508_amd/csrc/adjoint.hip", _ADJ_SHA, "atom",
+                {(45, 0, 12, 1): 5359.1, (45, 0, 12, 2): 7839.5}),
+    "dedr": ("paper_2212_10508_amd/csrc/kernels.hip", _KER_SHA, "pair",
+             {(45, 0, 12, 1): 419.7, (45, 0, 12, 2): 419.7}),
+    "density": ("paper_2212_10508_amd/csrc/kernels.hip", _KER_SHA, "pair",
+                {(45, 0, 12, 1): 308.9, (45, 0, 12, 2): 405.1}),
 }
 
 
-def traffic_per_unit(kernel):
+def traffic_per_unit(kernel, shape):
+    """(bytes per unit, unit) of a SNAP kernel in the given kernel shape; bytes None where
+    no measurement of the current source in that shape exists."""
     import hashlib
-    path, sha, per_unit, unit = TRAFFIC[kernel]
+    path, sha, unit, per_shape = TRAFFIC[kernel]
     try:
         with open(os.path.join(ROOT, path), "rb") as fh:
             if hashlib.sha256(fh.read()).hexdigest() != sha:
                 return None, unit
     except OSError:
         return None, unit
-    return per_unit, unit
+    return per_shape.get(tuple(shape)), unit
 
 
 def main():
@@ -499,7 +506,7 @@ def main():
     J = 8
     S_slabs, L = args.slabs, args.L
     if args.pmc_probe:
-        pmc_probe(S, W, J, S_slabs)
+        pmc_probe(S, W, J, S_slabs, tuple(int(v) for v in args.shape.split(",")) if args.shape else None)
         return
     wl = W.slabs_1025(n_slabs=1, seed=1, J=J)
     x0, p0, box, beta = wl["xs"][0], wl["ps"][0], wl["box"], wl["beta"]
@@ -647,7 +654,7 @@ def main():
                    "tflops": (flops[k] / launches / (avg[k] * 1e-3) / 1e12) if k in flops else None}
                for k in prof}
     achieved = kernels[dom]["tflops"]
-    per_unit, unit = traffic_per_unit(dom)
+    per_unit, unit = traffic_per_unit(dom, ctx.kernel_shape(J))
     units_per_launch = (atoms if unit == "atom" else n_pairs) * evals / launches
     traffic = per_unit * units_per_launch if per_unit is not None else None
 

@@ -360,7 +360,7 @@ int snapmd_relax(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, const 
  * With the same density_parts, forces do not depend on the shape and per-atom energies
  * only through the order in which the adjoint's partial sums are added; the two
  * density_parts values differ by the rounding of the density sum.
- * snapmd_set_kernel_shape(ctx, J, NULL) restores the built-in shape (45, 5, 12, 1); any
+ * snapmd_set_kernel_shape(ctx, J, NULL) restores the built-in shape (45, 0, 12, 1); any
  * other value is SNAPMD_EINVAL.  snapmd_get_kernel_shape writes the shape in use for J. */
 typedef struct {
     int32_t density_acc;

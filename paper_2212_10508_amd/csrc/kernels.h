@@ -67,7 +67,7 @@ struct AdjointDev {
 // Above twojmax 8 the passes have one shape each (45, 0, -, 1).
 struct KernelShape {
     int dens_acc = 45;
-    int dedr_atoms = 5;
+    int dedr_atoms = 0;
     int adj_waves = 12;
     int dens_parts = 1;
 };

@@ -55,7 +55,7 @@ class KShape(C.Structure):
 # compiled variants of each kernel-shape field (twojmax <= 8)
 SHAPE_CHOICES = {"density_acc": (45, 28, 21), "dedr_stage_atoms": (5, 3, 0), "adjoint_waves": (12, 8),
                  "density_parts": (1, 2)}
-DEFAULT_SHAPE = (45, 5, 12, 1)
+DEFAULT_SHAPE = (45, 0, 12, 1)
 
 
 class ParaLog(C.Structure):

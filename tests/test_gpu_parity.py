@@ -259,7 +259,7 @@ def test_kernel_shapes_give_identical_forces(S, J):
     assert frel(ref[2][0], ref[1][0]) < 1e-13
     assert np.max(np.abs(ref[2][1] - ref[1][1])) < 1e-13 * np.max(np.abs(ref[1][1]))
     ctx.set_kernel_shape(J, None)
-    assert ctx.kernel_shape(J) == (45, 5, 12, 1)
+    assert ctx.kernel_shape(J) == (45, 0, 12, 1)
     ctx.set_kernel_shape(J, (28, 3, 8))   # three values: density_parts 1
     assert ctx.kernel_shape(J) == (28, 3, 8, 1)
     for bad in ((44, 5, 12, 1), (45, 5, 12, 3)):
