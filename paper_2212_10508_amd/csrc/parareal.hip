@@ -795,15 +795,28 @@ __device__ bool mc_get(double *__restrict__ dst, const unsigned long long *__res
     return __syncthreads_or(ok ? 0 : 1) == 0;
 }
 
+// kMcLanes lanes per atom: at most 512 / kMcLanes atoms per workgroup of at most 512 threads
+constexpr int kMcLanes = 4;
+constexpr int kMcMaxAtoms = 512 / kMcLanes;
+
+// sum over the kMcLanes lanes of an atom (every lane gets the same value)
+__device__ __forceinline__ double mc_lane_sum(double v) {
+#pragma unroll
+    for (int o = 1; o < kMcLanes; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
     extern __shared__ double sm[];
     if (a.out[6] != 0.0) return;  // an earlier launch of the window stopped early
     const int N = a.N, K = a.K, A = a.A;
     const int w = blockIdx.x, a0 = w * A, na = min(N, a0 + A) - a0;
     const int tid = threadIdx.x;
-    // two lanes per atom: lane 2k + h holds atom a0 + k (state kept identically in both
-    // lanes) and the half of its list built from stencil cells o = h, h + 2, ..
-    const int k = tid >> 1, h = tid & 1;
+    // kMcLanes lanes per atom: lane kMcLanes k + h holds atom a0 + k (state kept
+    // identically in all of them) and the part of its list built from stencil cells
+    // o = h, h + kMcLanes, .. (the short per-lane lists keep the passes' dependent chains
+    // short; with one or two waves per SIMD nothing else hides their latency)
+    const int k = tid / kMcLanes, h = tid % kMcLanes;
     const bool own = k < na, lead = own && h == 0;
     const int i = a0 + k;
     double *xs = sm;                                       // [3][N]
@@ -811,11 +824,11 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
     int *flag = reinterpret_cast<int *>(dfe + N);          // [2] (spare)
     uint16_t *nb = reinterpret_cast<uint16_t *>(flag + 2); // [kSweepNbRows][A]
     SwCells cl;
-    cl.cnt = reinterpret_cast<int *>(nb + (size_t)kSweepNbRows * 2 * A);
+    cl.cnt = reinterpret_cast<int *>(nb + (size_t)kSweepNbRows * kMcLanes * A);
     cl.start = cl.cnt + kSweepMaxCells;
     cl.atom = reinterpret_cast<uint16_t *>(cl.start + kSweepMaxCells + 1);
     cl.cid = cl.atom + N;
-    uint16_t *col = nb + tid;  // rows of stride 2A
+    uint16_t *col = nb + tid;  // rows of stride kMcLanes A
     const int NC = a.ncx * a.ncy * a.ncz;
     const double rcl = fmax(a.fp.d, a.fp.c) + a.skin, rcl2 = rcl * rcl;
     const size_t SN = (size_t)(a.n_fi - a.n_in) * N;
@@ -945,7 +958,7 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
                     __syncthreads();
                 }
                 if (own) {
-                    cn = swl_build_thread(a, xs, col, 2 * A, cl, i, rcl2, overflow, h, 2);
+                    cn = swl_build_thread(a, xs, col, kMcLanes * A, cl, i, rcl2, overflow, h, kMcLanes);
 #pragma unroll
                     for (int al = 0; al < 3; ++al) xr[al] = xo[al];
                 }
@@ -953,15 +966,15 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
                 __syncthreads();
             }
             double acc = 0.0;
-            if (own) mk = swl_rho_acc(a, xs, col, 2 * A, i, cn, acc);
-            acc += __shfl_xor(acc, 1, 64);  // both halves of the list (same sum in both lanes)
+            if (own) mk = swl_rho_acc(a, xs, col, kMcLanes * A, i, cn, acc);
+            acc = mc_lane_sum(acc);  // all parts of the list (the same sum in every lane)
             if (lead) put_tagged(a.gdfe + 2 * ((size_t)par * N + i), swl_dfe(a.fp, acc), b);
             if (!mc_get(dfe, a.gdfe + 2 * (size_t)par * N, N, nullptr, 0, pv, b, a)) { alive = false; break; }
             ++b;
             double fh[3] = {0.0, 0.0, 0.0};
-            if (own) swl_force_thread(a, xs, dfe, col, 2 * A, i, mk, fh);
+            if (own) swl_force_thread(a, xs, dfe, col, kMcLanes * A, i, mk, fh);
 #pragma unroll
-            for (int al = 0; al < 3; ++al) fr[al] = fh[al] + __shfl_xor(fh[al], 1, 64);
+            for (int al = 0; al < 3; ++al) fr[al] = mc_lane_sum(fh[al]);
             if (l >= 0)
 #pragma unroll
                 for (int al = 0; al < 3; ++al) pr[al] = pr[al] + hk * fr[al];
@@ -1045,7 +1058,7 @@ __global__ void __launch_bounds__(512) k_coarse_sweep_mc(SweepArgs a) {
 }
 
 size_t sweep_mc_lds_bytes(int N, int A) {
-    return (size_t)N * 4 * sizeof(double) + 2 * sizeof(int) + (size_t)kSweepNbRows * 2 * A * sizeof(uint16_t) + 4 +
+    return (size_t)N * 4 * sizeof(double) + 2 * sizeof(int) + (size_t)kSweepNbRows * kMcLanes * A * sizeof(uint16_t) + 4 +
            (2 * kSweepMaxCells + 1) * sizeof(int) + (size_t)N * 2 * sizeof(uint16_t) + 8;
 }
 
@@ -1343,15 +1356,16 @@ void launch_coarse_sweep_multi(const void *tab, int n, int max_atoms, hipStream_
 bool sweep_fits_lds(int N) { return N <= kSweepLdsMaxAtoms && sweep_lds_bytes(N) <= 160 * 1024; }
 
 // workgroups of the multi-workgroup sweep for N atoms (0: not used); want > 0 asks for
-// that many, granted when they fit (at most 64, at most 256 atoms per workgroup)
+// that many, granted when they fit (at most 64, at most kMcMaxAtoms atoms per workgroup);
+// built in: the fewest from 8 up that fit
 int sweep_mc_workgroups(int N, int want) {
     if (N < 512 || N > 65535) return 0;
-    auto fits = [N](int K) {  // two lanes per atom: at most 256 atoms per workgroup of 512 threads
+    auto fits = [N](int K) {
         const int A = (N + K - 1) / K;
-        return K <= 64 && A <= 256 && sweep_mc_lds_bytes(N, A) + kMcStaticLds <= 160 * 1024;
+        return K <= 64 && A <= kMcMaxAtoms && sweep_mc_lds_bytes(N, A) + kMcStaticLds <= 160 * 1024;
     };
     if (want > 0 && fits(want)) return want;
-    for (int K : {8, 16})
+    for (int K = 8; K <= 64; ++K)
         if (fits(K)) return K;
     return 0;
 }
@@ -1430,7 +1444,7 @@ void launch_coarse_sweep(const SweepLaunch &s, hipStream_t st) {
     if (s.K > 0) {
         // at least 81 KB of LDS so that no two of the workgroups share a CU
         const size_t lds = std::max<size_t>(sweep_mc_lds_bytes(s.N, s.A), 81 * 1024);
-        const int T = (2 * s.A + 63) / 64 * 64;
+        const int T = (kMcLanes * s.A + 63) / 64 * 64;
         hipLaunchKernelGGL(k_coarse_sweep_mc, dim3(s.K), dim3(T), lds, st, a);
     } else {
         hipLaunchKernelGGL(k_coarse_sweep_lds, dim3(1), dim3(kSweepThreads), sweep_lds_bytes(s.N), st, a);

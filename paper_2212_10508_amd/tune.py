@@ -111,7 +111,7 @@ def tune_chunk_plan(ctx, run_iteration, S, N, n_cus, passes=2, limit=16, log=Non
     return chosen, times
 
 
-def tune_sweep_width(ctx, run_iteration, N, widths=(1, 5, 6, 8, 16), passes=2, log=None):
+def tune_sweep_width(ctx, run_iteration, N, widths=(1, 9, 12, 16), passes=2, log=None):
     """Time run_iteration() with the on-device coarse sweep spread over each of the given
     numbers of workgroups (those the system of N atoms cannot use are skipped), in
     interleaved passes after one untimed run each, and keep the fastest (1: the
