@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <iterator>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -639,7 +640,7 @@ int replay_range(snapmd_ctx *ctx, Work &w, double *f, int potential, const Batch
                                u(sd.nrm), u(sd.adj.coef), u(sd.adj.cgm), u(sd.adj.roles), u(sd.adj.roles8),
                                (uint64_t)sd.shape.dens_acc, (uint64_t)sd.shape.dedr_atoms,
                                (uint64_t)sd.shape.adj_waves, (uint64_t)sd.shape.dens_parts};
-        key.insert(key.end(), sk, sk + 13);
+        key.insert(key.end(), std::begin(sk), std::end(sk));
     }
     const int ci = (&w == &ctx->wc) ? 1 : 0;
     auto &cache = ctx->graphs[ci];

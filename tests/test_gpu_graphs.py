@@ -161,6 +161,33 @@ def test_graph_key_tells_apart_batches_with_other_largest_system(S):
         assert torch.equal(xg, xr) and torch.equal(pg, pr), sizes
 
 
+def test_graph_key_holds_every_kernel_shape_field(S):
+    """Every field of the kernel shape is part of the captured sequence's key: after a
+    capture with one slot split of the density pass, the other split captures anew (its
+    trajectory equals the kernel-by-kernel run with that split, and differs in the last
+    bits from the first split's)."""
+    J = 8
+    X, P, off, boxes = _batch(n_sys=2)
+    kw = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=5, noise_id=0, fs=W.FS_W, J=J,
+              beta=W.snap_beta(J, seed=2, scale=2e-2))
+    ctx = S.Context(0)
+    ref = S.Context(0)
+    ref.use_graphs(False)
+    out = {}
+    for parts in (1, 2):
+        ctx.set_kernel_shape(J, (45, 0, 12, parts))
+        ref.set_kernel_shape(J, (45, 0, 12, parts))
+        xg, pg = dev(X), dev(P)
+        ctx.langevin_steps(S.POT_FS_SNAP, xg, pg, off, boxes, 10, step0=0, **kw)
+        xr, pr = dev(X), dev(P)
+        ref.langevin_steps(S.POT_FS_SNAP, xr, pr, off, boxes, 10, step0=0, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xr) and torch.equal(pg, pr), parts
+        out[parts] = xg
+    assert not torch.equal(out[1], out[2])
+    assert torch.max(torch.abs(out[1] - out[2])).item() < 1e-9
+
+
 def test_window_noise_distinguishes_seeds_equal_as_doubles(S):
     """The Gaussians of a window are cached per (window, seed, stream); two 64-bit seeds
     that round to the same double (2^60 and 2^60 + 1) must not share them."""

@@ -114,3 +114,32 @@ def test_kernel_shape_cache_round_trip(tmp_path):
     assert tune.load_shape("gfx942:J8:2^14", path) is None
     c = tune.shape_candidates()
     assert c[0] == (45, 0, 12, 1) and len(c) == len(set(c)) == 36
+
+
+def test_shape_tuner_keeps_builtin_within_noise(monkeypatch):
+    """The kernel-shape tuner keeps the built-in shape unless a candidate beats it by more
+    than 1 %; a candidate failing the force check is never chosen."""
+    clock = {"t": 0.0}
+    monkeypatch.setattr(tune.time, "perf_counter", lambda: clock["t"])
+    builtin = tune.shape_candidates()[0]
+
+    class Ctx:
+        shape = None
+
+        def set_kernel_shape(self, J, s):
+            self.shape = tuple(s) if s is not None else None
+
+        def kernel_shape(self, J):
+            return self.shape
+
+    for gain, want_builtin in ((0.005, True), (0.02, False)):
+        ctx = Ctx()
+        fast = tune.shape_candidates()[5]
+        bad = tune.shape_candidates()[6]
+
+        def run():
+            clock["t"] += 0.100 * (1.0 - (gain if ctx.shape == fast else 0.0) - (0.5 if ctx.shape == bad else 0.0))
+
+        shape, table = tune.tune_kernel_shapes(ctx, 8, run, lambda: 1.0 if ctx.shape == bad else 0.0, passes=1)
+        assert shape == (builtin if want_builtin else fast) and ctx.shape == shape
+        assert [t["passed"] for t in table if tuple(t["shape"]) == bad] == [False]
