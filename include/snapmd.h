@@ -229,6 +229,33 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
                      double *p_prev, double *q_cur, double *p_cur, double delta_expl,
                      double *delta_out, void *stream);
 
+/* Pipelined corrected iterations of one system ("Parareal method": iterations of
+ * eq:parareal run back to back).  parareal_iterate_async does what parareal_iterate does
+ * for a batch of one system with the window [n_in, n_fi], but returns once the work is
+ * enqueued on `stream`; snapmd_parareal_collect returns the results of the iterations in
+ * the order they were enqueued: delta_out and n_fi_out (host) as parareal_iterate's
+ * delta_out[0] and n_fi[0], and the status codes parareal_iterate would return (an error
+ * found while enqueueing is returned by parareal_iterate_async itself).  At most 3
+ * iterations may wait to be collected (SNAPMD_EINVAL beyond).
+ * Overlap: a corrected iteration that follows a pipelined one with the same window,
+ * state buffers, box, potentials, Langevin parameters, slab chunks and sweep width copies
+ * prev := cur chunk by chunk, each as soon as the previous iteration's on-device sweep
+ * has passed that chunk, so its fine propagation starts while the previous sweep finishes
+ * its last chunks.  The results are bitwise those of the same parareal_iterate calls.
+ * cur and prev of an iteration are complete when its result has been collected (the
+ * collect makes `stream` wait for them).  Any other call (another window or parameter
+ * set, and every other entry point of the library except the getters, snapmd_profile,
+ * snapmd_use_graphs and snapmd_parareal_collect) first waits on the host for the
+ * pipelined iterations in flight; their results stay queued.  Window initialisations and sweeps driven from the
+ * host are not pipelined: they complete at the call and queue their result.  Use one
+ * stream for a chain.  The caller owns the speculation: an iteration enqueued before the
+ * previous result was collected used the window given at its call. */
+int parareal_iterate_async(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs,
+                           const snapmd_batch *batch, const snapmd_langevin *lang, int32_t L, int32_t n_in,
+                           int32_t n_fi, int32_t n_slots, double *q_prev, double *p_prev, double *q_cur,
+                           double *p_cur, double delta_expl, void *stream);
+int snapmd_parareal_collect(snapmd_ctx *ctx, double *delta_out, int32_t *n_fi_out, void *stream);
+
 /* Iteration log of parareal_adaptive (host arrays owned by the caller): entry t of system
  * r (index r * max_log + t) describes its t-th corrected iteration: the window
  * [n_in, n_fi] it ran on, the window end after it (shorter when the relative error passed

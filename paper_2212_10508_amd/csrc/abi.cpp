@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <condition_variable>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
@@ -76,6 +77,25 @@ struct snapmd_ctx {
     DBuf<unsigned long long> sw_gx, sw_gdfe, sw_gpart;  // multi-workgroup sweep exchange words
     DBuf<int> sw_abort;
     double *h_out = nullptr;                      // pinned [16]: sweep results [0, 8), sweep init [8, 16)
+    // pipelined parareal iterations (parareal_iterate_async) whose results are not collected
+    static constexpr int kAsyncSlots = 4;
+    DBuf<double> sw_out_ring;                     // [kAsyncSlots][8] sweep state of each iteration in flight
+    static constexpr int kAsyncStride = 24;
+    double *h_async = nullptr;                    // pinned [kAsyncSlots][24]: results [0, 8), init [8, 16),
+                                                  // neighbour-list status (an int) at 16
+    hipEvent_t async_ev[kAsyncSlots] = {};        // result of slot j copied to the host
+    struct AsyncIt {
+        int slot;                                 // -1: finished at the call (result below)
+        int rc;
+        double delta;
+        int32_t n_fi;
+    };
+    std::deque<AsyncIt> async_q;
+    uint64_t async_seq = 0;
+    std::vector<hipEvent_t> sweep_chunk_ev;       // the last iteration's sweep of chunk c enqueued up to its end
+    std::vector<uint64_t> chain_key;              // window, parameters and buffers of the last pipelined iteration
+    hipEvent_t chain_end = nullptr;               // the last pipelined iteration done (one of async_ev)
+    std::vector<uint64_t> lang_key;               // the per-system Langevin arrays last uploaded
     DBuf<double> sw_noise;                        // Gaussians of the current window
     // parareal over several systems: offsets, windows, jumps in the slot layout, entry
     // sources, sweep arguments and results
@@ -150,6 +170,21 @@ int fail(snapmd_ctx *c, int code, const char *fmt, ...) {
         if (e_ != hipSuccess)                                                                 \
             return fail(ctx, SNAPMD_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));   \
     } while (0)
+
+// Wait (on the host) for every pipelined parareal iteration in flight; their results stay
+// queued for snapmd_parareal_collect.  Every entry point that may reallocate, rewrite or
+// drop what such an iteration uses calls this first.
+int drain(snapmd_ctx *ctx) {
+    if (ctx->chain_end) {
+        const hipError_t e = hipEventSynchronize(ctx->chain_end);
+        ctx->chain_end = nullptr;
+        ctx->chain_key.clear();
+        if (e != hipSuccess)
+            return fail(ctx, SNAPMD_EHIP, "waiting for a pipelined parareal iteration failed: %s",
+                        hipGetErrorString(e));
+    }
+    return SNAPMD_OK;
+}
 
 void drop_graphs(snapmd_ctx *ctx) {
     // a replay may still be queued on the caller's or the context's streams
@@ -755,11 +790,31 @@ int prepare_langevin(snapmd_ctx *ctx, const snapmd_langevin *lang, int S, const 
         (rc = ensure(ctx, ctx->d_sb0, S)) || (rc = ensure(ctx, ctx->d_sb1, S)) ||
         (rc = ensure(ctx, ctx->seg_step0[0], S)) || (rc = ensure(ctx, ctx->seg_step0[1], S)))
         return rc;
-    if ((rc = upload(ctx, ctx->d_sig.p, sig.data(), S, st))) return rc;
-    if ((rc = upload(ctx, ctx->d_step0.p, step0.data(), S, st))) return rc;
-    if ((rc = upload(ctx, ctx->d_noise.p, nid.data(), S, st))) return rc;
-    if ((rc = upload(ctx, ctx->d_sb0.p, sb0.data(), S, st))) return rc;
-    if ((rc = upload(ctx, ctx->d_sb1.p, sb1.data(), S, st))) return rc;
+    // uploaded only when they change (a pipelined parareal iteration must not rewrite
+    // arrays the previous one still reads on another stream)
+    std::vector<uint64_t> key{(uint64_t)S, (uint64_t)(uintptr_t)ctx->d_sig.p, (uint64_t)(uintptr_t)ctx->d_step0.p,
+                              (uint64_t)(uintptr_t)ctx->d_noise.p, (uint64_t)(uintptr_t)ctx->d_sb0.p,
+                              (uint64_t)(uintptr_t)ctx->d_sb1.p};
+    auto bits = [](double v) {
+        uint64_t b;
+        std::memcpy(&b, &v, sizeof b);
+        return b;
+    };
+    for (int s = 0; s < S; ++s) {
+        key.push_back(bits(sig[s]));
+        key.push_back((uint64_t)step0[s]);
+        key.push_back((uint64_t)nid[s]);
+        key.push_back(bits(sb0[s]));
+        key.push_back(bits(sb1[s]));
+    }
+    if (key != ctx->lang_key) {
+        if ((rc = upload(ctx, ctx->d_sig.p, sig.data(), S, st))) return rc;
+        if ((rc = upload(ctx, ctx->d_step0.p, step0.data(), S, st))) return rc;
+        if ((rc = upload(ctx, ctx->d_noise.p, nid.data(), S, st))) return rc;
+        if ((rc = upload(ctx, ctx->d_sb0.p, sb0.data(), S, st))) return rc;
+        if ((rc = upload(ctx, ctx->d_sb1.p, sb1.data(), S, st))) return rc;
+        ctx->lang_key = key;
+    }
     ld = LangevinDev{lang->dt, c1, lang->mass, lang->seed, ctx->d_sig.p, ctx->d_step0.p, ctx->d_noise.p};
     ld.scheme = lang->scheme;
     ld.gamma = lang->gamma;
@@ -859,9 +914,12 @@ int host_sweep(snapmd_ctx *ctx, int potC, const FsParams &fp, const SnapDev &sdc
 }
 
 // One system (its states [slot][3][N]): the pipelined path of the bench workload.
+// async: a pipelined iteration (parareal_iterate_async): the call returns once the work is
+// enqueued and the result is queued for snapmd_parareal_collect.
 int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, const snapmd_batch *batch,
                  const snapmd_langevin *lang, int32_t L, int32_t n_in, int32_t *n_fi, double *q_prev, double *p_prev,
-                 double *q_cur, double *p_cur, double delta_expl, double *delta_out, hipStream_t st, void *stream) {
+                 double *q_cur, double *p_cur, double delta_expl, double *delta_out, hipStream_t st, void *stream,
+                 bool async = false) {
     int rc;
     const bool init = (q_prev == nullptr);
     const int N = batch->offset[1];
@@ -932,20 +990,65 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
     sw.p_cur = p_cur;
     sw.q_prev = q_prev;
     sw.p_prev = p_prev;
-    sw.out = ctx->sw_out.p;
-    {
-        // sweep state carried over the launches of this call
-        double *h0 = ctx->h_out + 8;
-        const double init_out[8] = {0.0, (double)*n_fi, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        std::memcpy(h0, init_out, sizeof init_out);
-        HIPCHK(hipMemcpyAsync(ctx->sw_out.p, h0, 8 * sizeof(double), hipMemcpyHostToDevice, st));
-    }
     // the sweep on the device: several workgroups exchanging through device memory, or
     // one LDS-resident workgroup; else driven from the host
     // width 1 asks for the one-workgroup sweep where it fits
     const bool one_wg = ctx->sweep_k_override == 1 && sweep_fits_lds(N);
     const int mcK = (bbk || csnap || one_wg) ? 0 : sweep_mc_workgroups(N, ctx->sweep_k_override);
     const bool lds_sweep = !bbk && !csnap && (mcK > 0 || sweep_fits_lds(N));
+    // A pipelined iteration (on-device sweep, corrected iteration) overlaps the previous
+    // pipelined iteration when everything the two share is the same (chain_key: window,
+    // chunk plan, state buffers, box, potentials, Langevin parameters, sweep width), so
+    // neither allocates nor rewrites what the other reads; every other call first waits
+    // for all pipelined iterations in flight.
+    const bool pipelined = async && !init && lds_sweep;
+    const std::vector<int> plan = init ? std::vector<int>{} : lds_sweep ? window_plan(ctx, S, N) : std::vector<int>{S};
+    std::vector<uint64_t> key;
+    bool chained = false;
+    if (pipelined) {
+        auto u = [](const void *q) { return (uint64_t)(uintptr_t)q; };
+        auto d = [](double v) {
+            uint64_t b;
+            std::memcpy(&b, &v, sizeof b);
+            return b;
+        };
+        key = {(uint64_t)n_in, (uint64_t)S, (uint64_t)L, (uint64_t)N, u(q_prev), u(p_prev), u(q_cur), u(p_cur),
+               d(box[0]), d(box[1]), d(box[2]), d(fp.A), d(fp.d), d(fp.c), d(fp.c0), d(fp.c1), d(fp.c2),
+               d(fpc.A), d(fpc.d), d(fpc.c), d(fpc.c0), d(fpc.c1), d(fpc.c2), (uint64_t)mcK, d(lang->dt),
+               d(lang->gamma), d(lang->mass), d(lang->T_sys[0]), lang->seed, (uint64_t)lang->noise_id_sys[0],
+               (uint64_t)lang->scheme, snap ? (uint64_t)snap->twojmax : 0, snap ? d(snap->rcut) : 0};
+        for (int v : plan) key.push_back((uint64_t)v);
+        chained = ctx->chain_end && key == ctx->chain_key;
+    }
+    if (!chained && (rc = drain(ctx))) return rc;
+    ctx->chain_key.clear();  // set again once a pipelined iteration is fully enqueued
+    int aslot = -1;
+    double *h0 = ctx->h_out + 8;  // the sweep state's initial values (pinned host)
+    sw.out = ctx->sw_out.p;
+    if (pipelined) {
+        if ((int)ctx->async_q.size() >= snapmd_ctx::kAsyncSlots - 1)
+            return fail(ctx, SNAPMD_EINVAL, "at most %d pipelined iterations may wait to be collected",
+                        snapmd_ctx::kAsyncSlots - 1);
+        if ((rc = ensure(ctx, ctx->sw_out_ring, 8 * (size_t)snapmd_ctx::kAsyncSlots))) return rc;
+        if (!ctx->h_async)
+            HIPCHK(hipHostMalloc((void **)&ctx->h_async,
+                                 snapmd_ctx::kAsyncStride * snapmd_ctx::kAsyncSlots * sizeof(double),
+                                 hipHostMallocDefault));
+        for (hipEvent_t &e : ctx->async_ev)
+            if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        // slot of this iteration: at most kAsyncSlots - 1 are uncollected, and the one
+        // kAsyncSlots iterations back was collected (its device work done)
+        aslot = (int)(ctx->async_seq % snapmd_ctx::kAsyncSlots);
+        sw.out = ctx->sw_out_ring.p + 8 * aslot;
+        h0 = ctx->h_async + snapmd_ctx::kAsyncStride * aslot + 8;
+    }
+    {
+        // sweep state carried over the launches of this call (a pipelined iteration resets
+        // its slot on the sweep stream, behind the sweeps in flight)
+        const double init_out[8] = {0.0, (double)*n_fi, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        std::memcpy(h0, init_out, sizeof init_out);
+        if (!pipelined) HIPCHK(hipMemcpyAsync(ctx->sw_out.p, h0, 8 * sizeof(double), hipMemcpyHostToDevice, st));
+    }
     if (mcK > 0) {
         sw.K = mcK;
         sw.A = (N + mcK - 1) / mcK;
@@ -969,12 +1072,14 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
         return check_launch(ctx);
     };
     if (!init) {
-        // prev_n := cur_n on [n_in, n_fi]
+        // prev_n := cur_n on [n_in, n_fi] (a pipelined iteration copies chunk by chunk below)
         const size_t slot = 3 * (size_t)N;
-        HIPCHK(hipMemcpyAsync(q_prev + n_in * slot, q_cur + n_in * slot, (S + 1) * slot * sizeof(double),
-                              hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(p_prev + n_in * slot, p_cur + n_in * slot, (S + 1) * slot * sizeof(double),
-                              hipMemcpyDeviceToDevice, st));
+        if (!pipelined) {
+            HIPCHK(hipMemcpyAsync(q_prev + n_in * slot, q_cur + n_in * slot, (S + 1) * slot * sizeof(double),
+                                  hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(p_prev + n_in * slot, p_cur + n_in * slot, (S + 1) * slot * sizeof(double),
+                                  hipMemcpyDeviceToDevice, st));
+        }
         // the batch: S copies of the system, slab s starting at global step (n_in + s) L
         std::vector<int> off(S + 1);
         std::vector<double> boxes(3 * S);
@@ -1001,16 +1106,22 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
         // chunks runs on the caller's stream; the Finnis-Sinclair propagation, the jumps
         // and (LDS-resident case) the sweep run on a second stream, the sweep over chunk c
         // as soon as the SNAP propagation of chunk c is done, overlapping the later chunks.
-        const std::vector<int> plan = lds_sweep ? window_plan(ctx, S, N) : std::vector<int>{S};
         if (!ctx->sweep_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->sweep_stream, hipStreamNonBlocking));
         if (!ctx->coarse_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->coarse_stream, hipStreamNonBlocking));
         // events: fine chunk c done [0, ne), sweep done (ne), start (ne + 1), coarse chunk c
-        // done [ne + 2, 2 ne + 2)
+        // done [ne + 2, 2 ne + 2), prev := cur of chunk c done (pipelined) [2 ne + 2, 3 ne + 2),
+        // list status read (pipelined) 3 ne + 2; sweep of chunk c enqueued up to its end:
+        // sweep_chunk_ev[c]
         const int ne = (int)plan.size();
-        for (int c = (int)ctx->pipe_ev.size(); c < 2 * ne + 2; ++c) {
+        for (int c = (int)ctx->pipe_ev.size(); c < 3 * ne + 3; ++c) {
             hipEvent_t e;
             HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
             ctx->pipe_ev.push_back(e);
+        }
+        for (int c = (int)ctx->sweep_chunk_ev.size(); c < ne; ++c) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            ctx->sweep_chunk_ev.push_back(e);
         }
         hipStream_t s2 = ctx->sweep_stream;
         if (lds_sweep) {
@@ -1035,6 +1146,7 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
         HIPCHK(hipEventRecord(ctx->pipe_ev[ne + 1], st));
         HIPCHK(hipStreamWaitEvent(s2, ctx->pipe_ev[ne + 1], 0));
         HIPCHK(hipStreamWaitEvent(s3, ctx->pipe_ev[ne + 1], 0));
+        if (pipelined) HIPCHK(hipMemcpyAsync(sw.out, h0, 8 * sizeof(double), hipMemcpyHostToDevice, s2));
         // Three streams, each fed by its own host thread: the fine propagation of the
         // chunks (caller's stream, this thread), their coarse propagation (s3) and the
         // jumps and sweep of chunk c once both propagations of chunk c are done (s2).  A
@@ -1048,6 +1160,7 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
         std::mutex mu;
         std::condition_variable cv;
         int done_f = 0, done_c = 0;  // chunks whose fine / coarse propagation is queued
+        int done_copy = 0;           // chunks whose prev := cur copy is queued (pipelined)
         bool stop = false;           // a thread failed: the others queue nothing more
         auto publish = [&](int &counter, int value) {
             std::lock_guard<std::mutex> lk(mu);
@@ -1072,10 +1185,16 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
                     std::lock_guard<std::mutex> lk(mu);
                     if (stop) return SNAPMD_OK;
                 }
+                if (pipelined) {
+                    std::unique_lock<std::mutex> lk(mu);
+                    cv.wait(lk, [&] { return stop || done_copy > c; });
+                    if (stop) return SNAPMD_OK;
+                }
                 BatchDev bc;
                 LangevinDev lc;
                 const int nc = chunk_of(c, s0, bc, lc);
                 const size_t o = 3 * (size_t)N * s0;
+                if (pipelined) HIPCHK(hipStreamWaitEvent(s3, ctx->pipe_ev[2 * ne + 2 + c], 0));
                 launch_slabs_to_batch(nc, N, qs + s0 * slot, ctx->pr_xc.p + o, s3);
                 launch_slabs_to_batch(nc, N, ps + s0 * slot, ctx->pr_pc.p + o, s3);
                 if ((r = run_langevin_graph(ctx, ctx->wc, ctx->d_fc, potC, bc, fpc, sdc, lc, L,
@@ -1110,6 +1229,7 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
                     sc.jp = ctx->pr_pf.p + o;
                     sc.noise = sw.noise + (size_t)s0 * L * 3 * N;
                     if ((r = sweep_launch(sc, s2))) return r;
+                    HIPCHK(hipEventRecord(ctx->sweep_chunk_ev[c], s2));
                 }
             }
             HIPCHK(hipEventRecord(ctx->pipe_ev[ne], s2));
@@ -1129,6 +1249,18 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
             LangevinDev lc;
             const int nc = chunk_of(c, s0, bc, lc);
             const size_t o = 3 * (size_t)N * s0;
+            if (pipelined) {
+                // prev := cur on the window slots s0 .. s0 + nc (s0 + 1 .. for c > 0: slot s0
+                // came with the previous chunk): all written by the previous iteration's
+                // sweep up to the end of its chunk c
+                if (chained) HIPCHK(hipStreamWaitEvent(st, ctx->sweep_chunk_ev[c], 0));
+                const int a = c == 0 ? 0 : s0 + 1, b = s0 + nc;
+                const size_t first = (size_t)(n_in + a) * slot, len = (size_t)(b - a + 1) * slot * sizeof(double);
+                HIPCHK(hipMemcpyAsync(q_prev + first, q_cur + first, len, hipMemcpyDeviceToDevice, st));
+                HIPCHK(hipMemcpyAsync(p_prev + first, p_cur + first, len, hipMemcpyDeviceToDevice, st));
+                HIPCHK(hipEventRecord(ctx->pipe_ev[2 * ne + 2 + c], st));
+                publish(done_copy, c + 1);
+            }
             launch_slabs_to_batch(nc, N, qs + s0 * slot, ctx->pr_xf.p + o, st);
             launch_slabs_to_batch(nc, N, ps + s0 * slot, ctx->pr_pf.p + o, st);
             if ((rc1 = run_langevin_graph(ctx, ctx->w, ctx->d_f, SNAPMD_POT_FS_SNAP, bc, fp, sd, lc, L,
@@ -1141,12 +1273,36 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
             }
             publish(done_f, c + 1);
         }
+        if (pipelined && !rc1) {
+            // the neighbour-list error bits once the fine propagation is done (sticky: set by
+            // the kernels, cleared by snapmd_sync and snapmd_parareal_collect on an error)
+            double *h = ctx->h_async + snapmd_ctx::kAsyncStride * aslot;
+            hipError_t e = hipMemcpyAsync(reinterpret_cast<int *>(h + 16), ctx->w.status, sizeof(int),
+                                          hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipEventRecord(ctx->pipe_ev[3 * ne + 2], st);
+            if (e != hipSuccess) rc1 = fail(ctx, SNAPMD_EHIP, "reading the list status failed: %s", hipGetErrorString(e));
+        }
         if (rc1) halt();
         t_coarse.join();
         t_sweep.join();
+        if (pipelined && (rc1 || rc2 || rc3)) (void)hipDeviceSynchronize();  // nothing left in flight
         if (rc1) return rc1;
         if (rc3) return rc3;
         if (rc2) return rc2;
+        if (pipelined) {
+            // the result (sweep state, neighbour-list status) reaches the pinned slot on the
+            // sweep stream; the caller's stream does not wait for the sweep
+            double *h = ctx->h_async + snapmd_ctx::kAsyncStride * aslot;
+            HIPCHK(hipMemcpyAsync(h, sw.out, 8 * sizeof(double), hipMemcpyDeviceToHost, s2));
+            HIPCHK(hipStreamWaitEvent(s2, ctx->pipe_ev[3 * ne + 2], 0));  // the list status read
+            HIPCHK(hipEventRecord(ctx->async_ev[aslot], s2));
+            ctx->chain_end = ctx->async_ev[aslot];
+            ctx->chain_key = key;
+            ctx->async_q.push_back({aslot, SNAPMD_OK, 0.0, 0});
+            ++ctx->async_seq;
+            *delta_out = 0.0;
+            return SNAPMD_OK;
+        }
         HIPCHK(hipStreamWaitEvent(st, ctx->pipe_ev[ne], 0));
         sw.jq = ctx->pr_xf.p;
         sw.jp = ctx->pr_pf.p;
@@ -1478,8 +1634,13 @@ int snapmd_create(snapmd_ctx **out, int hip_device) {
 void snapmd_destroy(snapmd_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
+    (void)drain(ctx);
     for (void *p : ctx->allocs) (void)hipFree(p);
     if (ctx->h_out) (void)hipHostFree(ctx->h_out);
+    if (ctx->h_async) (void)hipHostFree(ctx->h_async);
+    for (hipEvent_t e : ctx->async_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->sweep_chunk_ev) (void)hipEventDestroy(e);
     drop_graphs(ctx);
     for (hipStream_t c : ctx->cap_stream)
         if (c) (void)hipStreamDestroy(c);
@@ -1495,6 +1656,7 @@ const char *snapmd_last_error(const snapmd_ctx *ctx) { return ctx ? ctx->err.c_s
 int snapmd_sync(snapmd_ctx *ctx, void *stream) {
     if (!ctx) return SNAPMD_EINVAL;
     HIPCHK(hipSetDevice(ctx->device));
+    if (const int rc_ = drain(ctx)) return rc_;
     HIPCHK(hipStreamSynchronize((hipStream_t)stream));
     int st = 0;
     HIPCHK(hipMemcpy(&st, ctx->w.status, sizeof(int), hipMemcpyDeviceToHost));
@@ -1511,6 +1673,7 @@ int snap_forces(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *ba
     if (!ctx) return SNAPMD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
+    if (const int rc_ = drain(ctx)) return rc_;
     if (!x || !f) return fail(ctx, SNAPMD_EINVAL, "x and f must be device pointers");
     BatchDev bd;
     double mh;
@@ -1529,6 +1692,7 @@ int snap_forces_noalloc(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_b
     if (!ctx) return SNAPMD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
+    if (const int rc_ = drain(ctx)) return rc_;
     if (!ctx->scratch) return fail(ctx, SNAPMD_EHIP, "the scratch array of this device is not set up");
     if (!x || !f) return fail(ctx, SNAPMD_EINVAL, "x and f must be device pointers");
     if (!batch || !batch->offset || !batch->box) return fail(ctx, SNAPMD_EINVAL, "batch, offset and box must be set");
@@ -1652,6 +1816,7 @@ int eam_forces(snapmd_ctx *ctx, const snapmd_fs *fs, const snapmd_batch *batch, 
     if (!ctx) return SNAPMD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
+    if (const int rc_ = drain(ctx)) return rc_;
     if (!x || !f) return fail(ctx, SNAPMD_EINVAL, "x and f must be device pointers");
     BatchDev bd;
     double mh;
@@ -1671,6 +1836,7 @@ int langevin_steps(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, cons
     if (!ctx) return SNAPMD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
+    if (const int rc_ = drain(ctx)) return rc_;
     if (potential != SNAPMD_POT_FS && potential != SNAPMD_POT_FS_SNAP)
         return fail(ctx, SNAPMD_EINVAL, "potential must be SNAPMD_POT_FS or SNAPMD_POT_FS_SNAP");
     if (!x || !p) return fail(ctx, SNAPMD_EINVAL, "x and p must be device pointers");
@@ -1701,10 +1867,11 @@ int langevin_steps(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, cons
     return check_launch(ctx);
 }
 
-int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, const snapmd_batch *batch,
-                     const snapmd_langevin *lang, int32_t L, const int32_t *n_in, int32_t *n_fi, int32_t n_slots,
-                     double *q_prev, double *p_prev, double *q_cur, double *p_cur, double delta_expl,
-                     double *delta_out, void *stream) {
+namespace {
+int parareal_entry(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, const snapmd_batch *batch,
+                   const snapmd_langevin *lang, int32_t L, const int32_t *n_in, int32_t *n_fi, int32_t n_slots,
+                   double *q_prev, double *p_prev, double *q_cur, double *p_cur, double delta_expl,
+                   double *delta_out, void *stream, bool async) {
     if (!ctx) return SNAPMD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
@@ -1736,9 +1903,70 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
     if (batch->offset[R] < 1) return fail(ctx, SNAPMD_EINVAL, "the batch needs at least one atom");
     if (R == 1)
         return parareal_one(ctx, snap, fs, batch, lang, L, n_in[0], n_fi, q_prev, p_prev, q_cur, p_cur, delta_expl,
-                            delta_out, st, stream);
+                            delta_out, st, stream, async);
+    if ((rc = drain(ctx))) return rc;
     return parareal_multi(ctx, snap, fs, batch, lang, L, n_in, n_fi, n_slots, q_prev, p_prev, q_cur, p_cur, delta_expl,
                           delta_out, st, stream);
+}
+}  // namespace
+
+int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, const snapmd_batch *batch,
+                     const snapmd_langevin *lang, int32_t L, const int32_t *n_in, int32_t *n_fi, int32_t n_slots,
+                     double *q_prev, double *p_prev, double *q_cur, double *p_cur, double delta_expl,
+                     double *delta_out, void *stream) {
+    return parareal_entry(ctx, snap, fs, batch, lang, L, n_in, n_fi, n_slots, q_prev, p_prev, q_cur, p_cur, delta_expl,
+                          delta_out, stream, false);
+}
+
+int parareal_iterate_async(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, const snapmd_batch *batch,
+                           const snapmd_langevin *lang, int32_t L, int32_t n_in, int32_t n_fi, int32_t n_slots,
+                           double *q_prev, double *p_prev, double *q_cur, double *p_cur, double delta_expl,
+                           void *stream) {
+    if (!ctx) return SNAPMD_EINVAL;
+    if (!batch || batch->n_sys != 1)
+        return fail(ctx, SNAPMD_EINVAL, "parareal_iterate_async takes a batch of one system");
+    if ((int)ctx->async_q.size() >= snapmd_ctx::kAsyncSlots - 1)
+        return fail(ctx, SNAPMD_EINVAL, "at most %d pipelined iterations may wait to be collected",
+                    snapmd_ctx::kAsyncSlots - 1);
+    const size_t queued = ctx->async_q.size();
+    int32_t nf = n_fi;
+    double delta = 0.0;
+    const int rc = parareal_entry(ctx, snap, fs, batch, lang, L, &n_in, &nf, n_slots, q_prev, p_prev, q_cur, p_cur,
+                                  delta_expl, &delta, stream, true);
+    if (rc) return rc;
+    // not pipelined (window initialisation, host-driven sweep): finished at the call
+    if (ctx->async_q.size() == queued) ctx->async_q.push_back({-1, SNAPMD_OK, delta, nf});
+    return SNAPMD_OK;
+}
+
+int snapmd_parareal_collect(snapmd_ctx *ctx, double *delta_out, int32_t *n_fi_out, void *stream) {
+    if (!ctx || !delta_out || !n_fi_out) return SNAPMD_EINVAL;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (ctx->async_q.empty()) return fail(ctx, SNAPMD_EINVAL, "no pipelined parareal iteration to collect");
+    const snapmd_ctx::AsyncIt it = ctx->async_q.front();
+    ctx->async_q.pop_front();
+    if (it.slot < 0) {
+        *delta_out = it.delta;
+        *n_fi_out = it.n_fi;
+        return it.rc;
+    }
+    HIPCHK(hipEventSynchronize(ctx->async_ev[it.slot]));
+    HIPCHK(hipStreamWaitEvent((hipStream_t)stream, ctx->async_ev[it.slot], 0));
+    const double *h = ctx->h_async + snapmd_ctx::kAsyncStride * it.slot;
+    const int status = *reinterpret_cast<const int *>(h + 16);
+    if (status) {
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemset(ctx->w.status, 0, sizeof(int)));
+        if (status & 1) return fail(ctx, SNAPMD_EOVERFLOW, "an atom has more than %d neighbours", kMaxNeigh);
+        return fail(ctx, SNAPMD_EINVAL, "inconsistent neighbour list (status %d)", status);
+    }
+    if (h[3] != 0.0)
+        return fail(ctx, SNAPMD_EOVERFLOW, "an atom of the coarse sweep has more than its list capacity of neighbours");
+    if (h[7] != 0.0) return fail(ctx, SNAPMD_EHIP, "the workgroups of the coarse sweep did not meet at a barrier in time");
+    if (h[2] >= 0.0) return fail(ctx, SNAPMD_ENONFINITE, "state became non-finite in slab %d", (int)h[2]);
+    *delta_out = h[0];
+    *n_fi_out = (int32_t)h[1];
+    return SNAPMD_OK;
 }
 
 // Device-resident adaptive parareal over a batch of replicas (the paper's Algorithm
@@ -1753,6 +1981,7 @@ int parareal_adaptive(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs 
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
     int rc;
+    if ((rc = drain(ctx))) return rc;
     if ((rc = check_lang(ctx, lang))) return rc;
     if (!batch || batch->n_sys < 1 || !batch->offset || !batch->box)
         return fail(ctx, SNAPMD_EINVAL, "parareal_adaptive needs a batch of at least one system");
@@ -2034,6 +2263,7 @@ int snapmd_ws_sites(snapmd_ctx *ctx, const snapmd_batch *batch, const double *x,
     if (!ctx) return SNAPMD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
+    if (const int rc_ = drain(ctx)) return rc_;
     if (!x || !site || !occ) return fail(ctx, SNAPMD_EINVAL, "x, site and occ must be device pointers");
     if (!(a > 0.0)) return fail(ctx, SNAPMD_EINVAL, "the lattice constant must be > 0 (got %g)", a);
     BatchDev bd;
@@ -2067,6 +2297,7 @@ int snapmd_relax(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, const 
     if (!ctx) return SNAPMD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
+    if (const int rc_ = drain(ctx)) return rc_;
     if (potential != SNAPMD_POT_FS && potential != SNAPMD_POT_FS_SNAP)
         return fail(ctx, SNAPMD_EINVAL, "potential must be SNAPMD_POT_FS or SNAPMD_POT_FS_SNAP");
     if (!x) return fail(ctx, SNAPMD_EINVAL, "x must be a device pointer");
@@ -2106,6 +2337,7 @@ int snapmd_relax(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, const 
 
 int snapmd_set_coarse_snap(snapmd_ctx *ctx, const snapmd_snap *coarse) {
     if (!ctx) return SNAPMD_EINVAL;
+    if (const int rc_ = drain(ctx)) return rc_;
     if (!coarse) {
         ctx->coarse_snap_on = false;
         ctx->coarse_beta.clear();
@@ -2127,6 +2359,7 @@ int snapmd_set_coarse_snap(snapmd_ctx *ctx, const snapmd_snap *coarse) {
 
 int snapmd_set_kernel_shape(snapmd_ctx *ctx, int32_t twojmax, const snapmd_kernel_shape *shape) {
     if (!ctx) return SNAPMD_EINVAL;
+    if (const int rc_ = drain(ctx)) return rc_;
     if (twojmax < 2 || twojmax > kMaxJLds || (twojmax & 1))
         return fail(ctx, SNAPMD_EINVAL, "kernel shapes are chosen for twojmax 2, 4, 6 or 8 (got %d)", twojmax);
     if (!shape) {
@@ -2156,6 +2389,7 @@ int snapmd_get_kernel_shape(snapmd_ctx *ctx, int32_t twojmax, snapmd_kernel_shap
 
 int snapmd_set_coarse_fs(snapmd_ctx *ctx, const snapmd_fs *coarse) {
     if (!ctx) return SNAPMD_EINVAL;
+    if (const int rc_ = drain(ctx)) return rc_;
     if (!coarse) {
         ctx->coarse_fs_on = false;
         return SNAPMD_OK;
@@ -2170,6 +2404,7 @@ int snapmd_set_coarse_fs(snapmd_ctx *ctx, const snapmd_fs *coarse) {
 
 int snapmd_set_chunk_plan(snapmd_ctx *ctx, const int32_t *sizes, int32_t n) {
     if (!ctx) return SNAPMD_EINVAL;
+    if (const int rc_ = drain(ctx)) return rc_;
     if (n < 0 || n > 64) return fail(ctx, SNAPMD_EINVAL, "chunk plan: need 0 <= n <= 64 (got %d)", n);
     if (n > 0 && !sizes) return fail(ctx, SNAPMD_EINVAL, "chunk plan: sizes is null");
     for (int c = 0; c < n; ++c)
@@ -2180,6 +2415,7 @@ int snapmd_set_chunk_plan(snapmd_ctx *ctx, const int32_t *sizes, int32_t n) {
 
 int snapmd_set_sweep_workgroups(snapmd_ctx *ctx, int32_t K) {
     if (!ctx) return SNAPMD_EINVAL;
+    if (const int rc_ = drain(ctx)) return rc_;
     if (K < 0 || K > 64) return fail(ctx, SNAPMD_EINVAL, "sweep workgroups: need 0 <= K <= 64 (got %d)", K);
     ctx->sweep_k_override = K;
     return SNAPMD_OK;
@@ -2244,6 +2480,7 @@ int snapmd_profile_read(snapmd_ctx *ctx, int kernel, double *total_ms, int64_t *
 int snapmd_pair_count(snapmd_ctx *ctx, int64_t *n_pairs) {
     if (!ctx || !n_pairs) return SNAPMD_EINVAL;
     HIPCHK(hipSetDevice(ctx->device));
+    if (const int rc_ = drain(ctx)) return rc_;
     HIPCHK(hipDeviceSynchronize());
     int v = 0;
     if (ctx->cap_atoms && !ctx->h_off.empty()) {
@@ -2259,6 +2496,7 @@ int snap_beta_grad(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch 
     if (!ctx) return SNAPMD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
+    if (const int rc_ = drain(ctx)) return rc_;
     if (!x || !w || !dEdbeta || !gradF) return fail(ctx, SNAPMD_EINVAL, "x, w, dEdbeta and gradF must be device pointers");
     if (snap && snap->twojmax > kMaxJLds)
         return fail(ctx, SNAPMD_EUNSUPPORTED, "snap_beta_grad takes twojmax up to %d (got %d)", kMaxJLds, snap->twojmax);
@@ -2294,6 +2532,7 @@ int snapmd_bispectrum(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_bat
     if (!ctx) return SNAPMD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
+    if (const int rc_ = drain(ctx)) return rc_;
     if (!x || !B) return fail(ctx, SNAPMD_EINVAL, "x and B must be device pointers");
     BatchDev bd;
     double mh;

@@ -97,6 +97,11 @@ def lib():
     L.parareal_iterate.argtypes = [P, C.POINTER(Snap), C.POINTER(Fs), C.POINTER(Batch), C.POINTER(Langevin),
                                    i32, C.POINTER(i32), C.POINTER(i32), i32, P, P, P, P, d, C.POINTER(d), P]
     L.parareal_iterate.restype = C.c_int
+    L.parareal_iterate_async.argtypes = [P, C.POINTER(Snap), C.POINTER(Fs), C.POINTER(Batch), C.POINTER(Langevin),
+                                         i32, i32, i32, i32, P, P, P, P, d, P]
+    L.parareal_iterate_async.restype = C.c_int
+    L.snapmd_parareal_collect.argtypes = [P, C.POINTER(d), C.POINTER(i32), P]
+    L.snapmd_parareal_collect.restype = C.c_int
     L.parareal_adaptive.argtypes = [P, C.POINTER(Snap), C.POINTER(Fs), C.POINTER(Batch), C.POINTER(Langevin),
                                     i32, i32, i32, d, d, i32, i32, P, P, C.POINTER(ParaLog), C.POINTER(i32),
                                     C.POINTER(i32), P]
@@ -320,6 +325,34 @@ class Context:
                                             noise_id=[noise_id], fs=fs, J=J, beta=beta, rcut=rcut, rfac0=rfac0,
                                             rmin0=rmin0, scheme=scheme, cT=cT, stream=stream)
         return float(d[0]), int(nf[0])
+
+    def parareal_iterate_async(self, q_prev, p_prev, q_cur, p_cur, box, L, n_in, n_fi, delta_expl, *, dt, gamma,
+                               mass, T, seed, noise_id, fs, J=None, beta=None, rcut=4.73, rfac0=0.99363, rmin0=0.0,
+                               scheme="baoab", cT=(1.0, 1.0), stream=None):
+        """parareal_iterate of one system, enqueued (pipelined with the previous iteration of
+        the same window); its (delta, n_fi_after) come from parareal_collect()."""
+        nslots, three, N = q_cur.shape
+        check_windows(np.array([n_in], np.int32), np.array([n_fi], np.int32), nslots, 1)
+        k = _Keep()
+        b = make_batch(k, [0, N], [box])
+        s = make_snap(k, J, beta, rcut, rfac0, rmin0) if beta is not None else None
+        p_fs = make_fs(fs)
+        lg = make_langevin(k, 1, dt, gamma, mass, [T], seed, 0, [noise_id], scheme, cT)
+        shape = (nslots, 3, N)
+        self._check(lib().parareal_iterate_async(
+            self.h, C.byref(s) if s is not None else None, C.byref(p_fs), C.byref(b), C.byref(lg), int(L),
+            int(n_in), int(n_fi), int(nslots),
+            _dev(q_prev, "q_prev", shape) if q_prev is not None else None,
+            _dev(p_prev, "p_prev", shape) if p_prev is not None else None,
+            _dev(q_cur, "q_cur", shape), _dev(p_cur, "p_cur", shape), float(delta_expl), _stream(stream)))
+
+    def parareal_collect(self, stream=None):
+        """(delta, n_fi_after) of the oldest uncollected parareal_iterate_async call; its
+        states are complete once this returns (`stream` waits for them)."""
+        d = C.c_double(0.0)
+        nf = C.c_int32(0)
+        self._check(lib().snapmd_parareal_collect(self.h, C.byref(d), C.byref(nf), _stream(stream)))
+        return d.value, nf.value
 
     def parareal_iterate_batch(self, q_prev, p_prev, q_cur, p_cur, offset, box, L, n_in, n_fi, delta_expl, *, dt,
                                gamma, mass, T, seed, noise_id, fs, J=None, beta=None, rcut=4.73, rfac0=0.99363,

@@ -481,3 +481,78 @@ def test_device_resident_driver_matches_oracle_and_host_driver(S, check_every):
         assert (res["n_ad"][r], res["kconv"][r]) == (nad_ref, kc_ref)
         for n in range(N + 1):
             assert np.abs(qh[n][:, off[r]:off[r + 1]] - tref[n][0]).max() < QTOL, (r, n)
+
+
+def test_pipelined_iterations_match_synchronous(S):
+    """Corrected iterations enqueued back to back (parareal_iterate_async: the next one's
+    prev := cur copies and fine propagation start chunk by chunk while the previous sweep
+    finishes) give bitwise the states and errors of the same parareal_iterate calls, under
+    several slab chunk plans and sweep widths; the queue bound, an empty collect, a window
+    initialisation through the queue and a synchronous call in the middle of a chain."""
+    x, box = W.bcc_sia(7, jitter=0.05, seed=23)
+    n = x.shape[1]
+    p = W.maxwell_momenta(n, 1000.0, seed=23)
+    J = 4
+    kw = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=7, noise_id=2, fs=W.FS_W, J=J,
+              beta=W.snap_beta(J, seed=23, scale=2e-2))
+    kwc = {k: v for k, v in kw.items() if k not in ("J", "beta")}
+    N, L, K = 8, 3, 5
+    ctx = S.context()
+
+    def fresh():
+        q = torch.zeros((N + 1, 3, n), dtype=torch.float64, device="cuda")
+        pp = torch.zeros_like(q)
+        q[0], pp[0] = dev(x), dev(p)
+        ctx.parareal_iterate(None, None, q, pp, box, L, 0, N, 1e100, **kwc)
+        return q, pp, torch.zeros_like(q), torch.zeros_like(q)
+
+    def host(*ts):
+        torch.cuda.synchronize()
+        return [t.cpu().numpy() for t in ts]
+
+    for plan, width in ((None, 0), ([3, 3, 2], 0), ([2, 2, 2, 2], 16), ([1] * 8, 9)):
+        ctx.set_chunk_plan(plan)
+        ctx.set_sweep_workgroups(width)
+        q, pp, qp, ppv = fresh()
+        ref = []
+        for _ in range(K):
+            ref.append(ctx.parareal_iterate(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw))
+        want = host(q, pp, qp, ppv)
+        q, pp, qp, ppv = fresh()
+        got = []
+        ctx.parareal_iterate_async(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
+        for k in range(1, K):
+            ctx.parareal_iterate_async(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
+            got.append(ctx.parareal_collect())
+        got.append(ctx.parareal_collect())
+        have = host(q, pp, qp, ppv)
+        assert got == ref, (plan, width, got, ref)
+        for a, b in zip(want, have):
+            assert np.array_equal(a, b), (plan, width)
+    ctx.set_chunk_plan(None)
+    ctx.set_sweep_workgroups(0)
+
+    q, pp, qp, ppv = fresh()
+    with pytest.raises(S.SnapmdError):
+        ctx.parareal_collect()  # nothing queued
+    # at most three iterations wait to be collected
+    for _ in range(3):
+        ctx.parareal_iterate_async(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
+    with pytest.raises(S.SnapmdError):
+        ctx.parareal_iterate_async(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
+    # a synchronous iteration waits for the three in flight; their results stay queued
+    d4 = ctx.parareal_iterate(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
+    chain = [ctx.parareal_collect() for _ in range(3)]
+    q2, pp2, qp2, ppv2 = fresh()
+    ref = [ctx.parareal_iterate(qp2, ppv2, q2, pp2, box, L, 0, N, 1e100, **kw) for _ in range(4)]
+    assert chain + [d4] == ref
+    for a, b in zip(host(q, pp, qp, ppv), host(q2, pp2, qp2, ppv2)):
+        assert np.array_equal(a, b)
+    # a window initialisation through the queue completes at the call
+    q3 = torch.zeros_like(q)
+    p3 = torch.zeros_like(q)
+    q3[0], p3[0] = dev(x), dev(p)
+    ctx.parareal_iterate_async(None, None, q3, p3, box, L, 0, N, 1e100, **kwc)
+    assert ctx.parareal_collect() == (0.0, N)
+    for a, b in zip(host(q3, p3), host(*fresh()[:2])):
+        assert np.array_equal(a, b)
