@@ -30,7 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CUs x 128 FLOP/clk x 2.4 GHz
-DEFAULT_PLAN = "15,13,14,14,8"   # slab chunks of one adjoint round each (64 x 1025 atoms)
+# slab chunks of the 64 x 1025-atom window: pipelined iterations take chunks of two
+# adjoint rounds (fewer launches; the last chunk's sweep overlaps the next iteration),
+# one call per iteration takes chunks of one round (its last sweep is exposed)
+DEFAULT_PLAN = "26,26,12"
+DEFAULT_PLAN_SYNC = "15,13,14,14,8"
 PROF_EVERY = 4            # HIP events around every 4th launch of each timed kernel
 
 
@@ -497,9 +501,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true",
                     help="time slab chunk plans and sweep widths first (untimed) and use the fastest")
-    ap.add_argument("--plan", default=DEFAULT_PLAN,
+    ap.add_argument("--plan", default=None,
                     help="slab chunks of the 64-slab window (default %s, the plan the committed kernel trace "
-                         "covers); 'builtin' for the library's own plan" % DEFAULT_PLAN)
+                         "covers; %s with --sync); 'builtin' for the library's own plan" % (DEFAULT_PLAN, DEFAULT_PLAN_SYNC))
     ap.add_argument("--sweep-workgroups", type=int, default=0, help="coarse sweep width (0: built in)")
     ap.add_argument("--shape", default=None,
                     help="kernel shape density_acc,dedr_stage_atoms,adjoint_waves[,density_parts] of the SNAP passes "
@@ -516,6 +520,8 @@ def main():
                     help="skip the fine-batch-alone and per-slab timings (then every SNAP launch of the "
                          "process belongs to a parareal iteration, e.g. for a kernel-trace profile)")
     args = ap.parse_args()
+    if args.plan is None:
+        args.plan = DEFAULT_PLAN_SYNC if args.sync else DEFAULT_PLAN
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the propagator runs on a single GPU "
               "(multi-GPU slab sharding is a design note only); use --gpus 1", file=sys.stderr)
@@ -603,7 +609,7 @@ def main():
             iteration()
             torch.cuda.synchronize()
 
-        ctx.set_chunk_plan([int(v) for v in DEFAULT_PLAN.split(",")])
+        ctx.set_chunk_plan([int(v) for v in args.plan.split(",")] if args.plan != "builtin" else None)
         q_keep, p_keep = q_cur.clone(), p_cur.clone()
         shape, table = tune.tune_kernel_shapes(ctx, J, shape_run, force_error, log=log)
         q_cur.copy_(q_keep)
@@ -634,7 +640,15 @@ def main():
     autotune = {"kernel_shape": shape_info}
     if args.tune:
         def timed_iteration():
-            iteration()
+            if args.sync:
+                iteration()
+            else:  # three pipelined iterations (the plan's overlap of consecutive ones)
+                enqueue()
+                enqueue()
+                collect()
+                enqueue()
+                collect()
+                collect()
             torch.cuda.synchronize()
 
         sweep_k, ktimes = tune.tune_sweep_width(ctx, timed_iteration, n, log=log)

@@ -44,8 +44,10 @@ def candidate_plans(S, N, n_cus, builtin=None, max_chunks=4, limit=24):
         if len(out) >= limit:
             break
     # when the sweep is as slow as the SNAP propagation, chunks of one round each start it
-    # early and leave a short last sweep
-    for c in (R - 1, R):
+    # early and leave a short last sweep; pipelined iterations (the last sweep overlaps the
+    # next iteration) favour chunks of two rounds, a little short of them where the
+    # workgroups beside the propagation take more compute units
+    for c in (R - 1, R, 2 * R - 3, 2 * R - 2, 2 * R - 1):
         if 1 <= c < S:
             p = [c] * (S // c) + ([S % c] if S % c else [])
             if p not in out:

@@ -26,6 +26,8 @@ def test_candidate_plans_include_one_round_chunks():
     # 64 slabs of 1025 atoms on 256 CUs: rounds of (256 - 16) * 64 atoms hold R = 14 slabs
     plans = tune.candidate_plans(64, 1025, 256, builtin=[29, 22, 13])
     assert [14, 14, 14, 14, 8] in plans and [13, 13, 13, 13, 12] in plans
+    # and chunks of about two rounds (pipelined iterations)
+    assert [26, 26, 12] in plans and [27, 27, 10] in plans
     # the whole-round plans are non-increasing with a last chunk of at most one round
     for p in plans[1:]:
         if len(p) <= 4:
