@@ -638,11 +638,14 @@ __host__ __device__ constexpr int chain_acc_idx(int C, int n, int k) {
 }
 
 // Levels N .. N1 of column chain C; the elements of levels N0 .. N1 are accumulated
-// (acc index relative to level N0), the lower levels only advance the chain.
-template <int J, int C, int N0, int N1, int N>
+// (acc index relative to level N0), the lower levels only advance the chain.  TAIL: the
+// segment also carries the last column C + 1 = J / 2, whose one level J branches off
+// column C at level J - 1 = 2C + 1 (mirror, then one advance), into tacc: the same
+// operations the column's own staircase performs, without repeating the chain below.
+template <int J, int C, int N0, int N1, int N, bool TAIL>
 __device__ __forceinline__ void density_step(
-    double2 (&P)[J + 1], double2 (&acc)[chain_acc_idx(C, N1 + 1, 0) - chain_acc_idx(C, N0, 0)], double2 b,
-    double2 ab, double fc) {
+    double2 (&P)[J + 1], double2 (&acc)[chain_acc_idx(C, N1 + 1, 0) - chain_acc_idx(C, N0, 0)],
+    double2 (&tacc)[J + 1], double2 b, double2 ab, double fc) {
     if constexpr (N > 2 * C) chain_advance<J, N - 1>(P, b, ab);
     if constexpr (N >= N0) {
         constexpr int a0 = chain_acc_idx(C, N0, 0);
@@ -652,7 +655,20 @@ __device__ __forceinline__ void density_step(
             acc[chain_acc_idx(C, N, k) - a0].y = fma(fc, P[k].y, acc[chain_acc_idx(C, N, k) - a0].y);
         }
     }
-    if constexpr (N < N1) density_step<J, C, N0, N1, N + 1>(P, acc, b, ab, fc);
+    if constexpr (TAIL && N == J - 1) {
+        static_assert(2 * C + 1 == J - 1, "the tail column branches off at level 2C + 1");
+        double2 Q[J + 1];
+#pragma unroll
+        for (int k = 0; k <= N; ++k) Q[k] = P[k];
+        chain_mirror<J, C + 1>(Q);
+        chain_advance<J, J - 1>(Q, b, ab);
+#pragma unroll
+        for (int k = 0; k <= J; ++k) {
+            tacc[k].x = fma(fc, Q[k].x, tacc[k].x);
+            tacc[k].y = fma(fc, Q[k].y, tacc[k].y);
+        }
+    }
+    if constexpr (N < N1) density_step<J, C, N0, N1, N + 1, TAIL>(P, acc, tacc, b, ab, fc);
 }
 
 template <int J, int C, int c>  // staircase: column c at level 2c -> column c+1 at level 2c+2
@@ -704,15 +720,18 @@ __global__ void k_pair_ell(int N, int n_sys, const int *__restrict__ off, const 
 // writing its partial sum to u + part nh N (nh = half elements); the identity term of
 // level 0 goes with part 0, and the Finnis-Sinclair density (dF non-null, column 0) is
 // summed over all slots by part 0.
-template <int J, int C, int N0, int N1, bool AHEAD>
-__device__ __forceinline__ void density_lane(int N, const int *__restrict__ poff, const double *__restrict__ ell,
-                             const double *__restrict__ nrm, double2 *__restrict__ u, double fs_A,
-                             double *__restrict__ dF) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
+template <int J, int C, int N0, int N1, bool AHEAD, bool TAIL>
+__device__ __forceinline__ void density_lane(int tile, int N, const int *__restrict__ poff,
+                                             const double *__restrict__ ell, const double *__restrict__ nrm,
+                                             double2 *__restrict__ u, double fs_A, double *__restrict__ dF) {
+    const int i = tile * 64 + threadIdx.x;
     constexpr int NA = chain_acc_idx(C, N1 + 1, 0) - chain_acc_idx(C, N0, 0);
     double2 acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = make_double2(0.0, 0.0);
+    double2 tacc[J + 1];  // the merged last column (TAIL)
+#pragma unroll
+    for (int q = 0; q <= J; ++q) tacc[q] = make_double2(0.0, 0.0);
     const int cnt = i < N ? poff[i + 1] - poff[i] : 0;
     int tmax = cnt;
 #pragma unroll
@@ -760,7 +779,7 @@ __device__ __forceinline__ void density_lane(int N, const int *__restrict__ poff
         double2 P[J + 1];
         P[0] = make_double2(1.0, 0.0);
         staircase<J, C, 0>(P, b, ab);
-        density_step<J, C, N0, N1, 2 * C>(P, acc, b, ab, fc);
+        density_step<J, C, N0, N1, 2 * C, TAIL>(P, acc, tacc, b, ab, fc);
     }
     if (i >= N) return;
     if (rho_here) dF[i] = rho > 0.0 ? -fs_A / (2.0 * sqrt(rho)) : 0.0;
@@ -775,6 +794,13 @@ __device__ __forceinline__ void density_lane(int N, const int *__restrict__ poff
             const double2 v = acc[chain_acc_idx(C, n, k) - chain_acc_idx(C, N0, 0)];
             up[(size_t)e * N + i] = make_double2(fma(sc, v.x, k == C ? one : 0.0), sc * v.y);
         }
+    if constexpr (TAIL)
+#pragma unroll
+        for (int k = 0; k <= J; ++k) {
+            const int e = half_idx(J, k, C + 1);
+            const double sc = nrm[e];
+            up[(size_t)e * N + i] = make_double2(fma(sc, tacc[k].x, k == C + 1 ? one : 0.0), sc * tacc[k].y);
+        }
 }
 
 // Work split of the density pass: segment s = (column C, levels N0 .. N1) with at most
@@ -783,12 +809,33 @@ __device__ __forceinline__ void density_lane(int N, const int *__restrict__ poff
 // the chain's lower levels without accumulating them.
 // ACC is the kernel-shape choice of the density pass (smaller: more, shorter segments,
 // fewer registers per lane, more waves in flight, more recomputed chain levels).
+// The last column (one level, J + 1 elements) has no segment of its own when it fits the
+// budget of the previous column's last segment (T): its chain is that column's up to
+// level J - 1, so a segment of its own would repeat the whole staircase (at twojmax 8,
+// 576 of its 612 operations per pair).
 struct DensSeg {
     int C, N0, N1;
+    bool T;
 };
+// elements of the last segment of column C
+__host__ __device__ constexpr int dens_last_acc(int J, int ACC, int C) {
+    int lev = 2 * C, acc = 0;
+    while (lev <= J) {
+        int top = lev;
+        acc = 0;
+        while (top <= J && (top == lev || acc + top + 1 <= ACC)) acc += ++top;  // adds level top - 1
+        lev = top;
+    }
+    return acc;
+}
+// (budget: the merged elements plus the branch's own chain copy, J + 1 more registers pairs)
+__host__ __device__ constexpr bool dens_tail_merged(int J, int ACC) {
+    return J >= 2 && dens_last_acc(J, ACC, J / 2 - 1) + 2 * (J + 1) <= ACC;
+}
 __host__ __device__ constexpr int dens_segments(int J, int ACC) {
     int n = 0;
     for (int C = 0; 2 * C <= J; ++C) {
+        if (2 * C == J && dens_tail_merged(J, ACC)) break;
         int lev = 2 * C;
         while (lev <= J) {
             int acc = 0, top = lev;
@@ -802,16 +849,17 @@ __host__ __device__ constexpr int dens_segments(int J, int ACC) {
 __host__ __device__ constexpr DensSeg dens_segment(int J, int ACC, int s) {
     int n = 0;
     for (int C = 0; 2 * C <= J; ++C) {
+        if (2 * C == J && dens_tail_merged(J, ACC)) break;
         int lev = 2 * C;
         while (lev <= J) {
             int acc = 0, top = lev;
             while (top <= J && (top == lev || acc + top + 1 <= ACC)) acc += ++top;
-            if (n == s) return DensSeg{C, lev, top - 1};
+            if (n == s) return DensSeg{C, lev, top - 1, top > J && 2 * C + 2 == J && dens_tail_merged(J, ACC)};
             ++n;
             lev = top;
         }
     }
-    return DensSeg{0, 0, 0};
+    return DensSeg{0, 0, 0, false};
 }
 
 // Least waves per SIMD that the compiler is held to for a register budget: the budget of
@@ -823,24 +871,33 @@ __host__ __device__ constexpr int dens_waves(int ACC) { return ACC == 28 ? 3 : 1
 __host__ __device__ constexpr bool dens_ahead(int ACC) { return ACC > 28; }
 
 template <int J, int ACC, int S>
-__device__ __forceinline__ void density_dispatch(int y, int N, const int *__restrict__ poff,
+__device__ __forceinline__ void density_dispatch(int y, int tile, int N, const int *__restrict__ poff,
                                                  const double *__restrict__ ell, const double *__restrict__ nrm,
                                                  double2 *__restrict__ u, double fs_A, double *__restrict__ dF) {
     if (y == S) {
         constexpr DensSeg g = dens_segment(J, ACC, S);
-        density_lane<J, g.C, g.N0, g.N1, dens_ahead(ACC)>(N, poff, ell, nrm, u, fs_A, (g.C == 0 && g.N0 == 0) ? dF : nullptr);
+        density_lane<J, g.C, g.N0, g.N1, dens_ahead(ACC), g.T>(tile, N, poff, ell, nrm, u, fs_A,
+                                                              (g.C == 0 && g.N0 == 0) ? dF : nullptr);
     } else if constexpr (S + 1 < dens_segments(J, ACC)) {
-        density_dispatch<J, ACC, S + 1>(y, N, poff, ell, nrm, u, fs_A, dF);
+        density_dispatch<J, ACC, S + 1>(y, tile, N, poff, ell, nrm, u, fs_A, dF);
     }
 }
 
 // dF non-null: column 0 also sums the Finnis-Sinclair density of field 5 and writes
-// dF[i] = F'(rho_i) = -A / (2 sqrt(rho_i)) (0 for rho_i = 0).  blockIdx.y = segment.
+// dF[i] = F'(rho_i) = -A / (2 sqrt(rho_i)) (0 for rho_i = 0).
+// Workgroup order: workgroups go to the eight chiplets (each with its own L2) in turn,
+// so the segments of tile x are numbered 8 (S q + y) + r with x = 8 q + r: all S of them
+// run on one chiplet one after the other, and the tile's slot table comes from HBM once
+// instead of once per segment.  Workgroups past the last tile exit at once.
 template <int J, int ACC>
 __global__ void __launch_bounds__(64, dens_waves(ACC)) k_density(int N, const int *__restrict__ poff, const double *__restrict__ ell,
                                                 const double *__restrict__ nrm, double2 *__restrict__ u,
                                                 double fs_A, double *__restrict__ dF) {
-    density_dispatch<J, ACC, 0>(blockIdx.y, N, poff, ell, nrm, u, fs_A, dF);
+    constexpr int S = dens_segments(J, ACC);
+    const int L = blockIdx.x, r = L & 7, w = L >> 3;
+    const int y = w % S, tile = (w / S) * 8 + r;
+    if (tile * 64 >= N) return;
+    density_dispatch<J, ACC, 0>(y, tile, N, poff, ell, nrm, u, fs_A, dF);
 }
 
 // ---------------------------------------------------------------------------
@@ -1343,7 +1400,7 @@ void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w,
 template <int J, int ACC>
 static void density_launch_acc(int N, Work &w, const SnapDev &sd, double fs_A, double *dF, hipStream_t st,
                                int parts) {
-    hipLaunchKernelGGL((k_density<J, ACC>), dim3(nblk(N, 64), dens_segments(J, ACC), parts), dim3(64), 0, st, N,
+    hipLaunchKernelGGL((k_density<J, ACC>), dim3(8 * nblk(N, 512) * dens_segments(J, ACC), 1, parts), dim3(64), 0, st, N,
                        w.poff, w.ell,
                        sd.nrm, w.u, fs_A, dF);
 }
