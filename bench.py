@@ -180,6 +180,7 @@ def kernel_rates(ctx, S, J, atoms, pairs, evals):
     fraction of the FP64 peak and HBM GB/s (measured bytes per unit, where valid for the
     current source) of the SNAP kernels, for a run whose every force evaluation launches
     each kernel once over the whole batch (`evals` evaluations)."""
+    import torch
     nUh, nZel, nZt = snap_counts(J)
     per_launch = {"dedr": float(dedr_flops(J)) * pairs, "adjoint": (8.0 * nZt + 4.0 * nZel) * atoms,
                   "density": 22.0 * nUh * pairs}
@@ -191,11 +192,11 @@ def kernel_rates(ctx, S, J, atoms, pairs, evals):
             continue
         avg = ms / nl
         tf = per_launch[name] / (avg * 1e-3) / 1e12
-        per_unit, unit = traffic_per_unit(name, ctx.kernel_shape(J))
-        units = atoms if unit == "atom" else pairs
+        simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+        nbytes, _ = traffic_per_launch(name, ctx.kernel_shape(J), [atoms], pairs / atoms, simds, J)
         out[name] = {"avg_ms": avg, "launches_timed": nl, "launches": evals, "tflops": tf,
                      "frac": tf / FP64_PEAK_TFLOPS,
-                     "hbm_gb_s": per_unit * units / (avg * 1e-3) / 1e9 if per_unit is not None else None}
+                     "hbm_gb_s": nbytes / (avg * 1e-3) / 1e9 if nbytes is not None else None}
     return out
 
 
@@ -487,6 +488,54 @@ def traffic_per_unit(kernel, shape):
     return per_shape.get(tuple(shape)), unit
 
 
+def dens_segments(J, acc):
+    """Waves per 64-atom tile of the density pass with register budget acc (column
+    chains cut into segments of at most acc elements; the last column rides on the
+    previous column's last segment when it fits with its chain copy)."""
+    def last_acc(C):
+        lev, a = 2 * C, 0
+        while lev <= J:
+            top, a = lev, 0
+            while top <= J and (top == lev or a + top + 1 <= acc):
+                top += 1
+                a += top
+            lev = top
+        return a
+    merged = J >= 2 and last_acc(J // 2 - 1) + 2 * (J + 1) <= acc
+    n = 0
+    for C in range(J // 2 + 1):
+        if 2 * C == J and merged:
+            break
+        lev = 2 * C
+        while lev <= J:
+            top, a = lev, 0
+            while top <= J and (top == lev or a + top + 1 <= acc):
+                top += 1
+                a += top
+            n += 1
+            lev = top
+    return n
+
+
+def traffic_per_launch(kernel, shape, chunk_atoms, units_per_atom, simds, J):
+    """HBM bytes of an average launch of a SNAP kernel over chunks of the given atom
+    counts, from the measured bytes per unit of the shape each launch runs in (density
+    split 0 resolved per chunk: split where the density pass has fewer waves than
+    SIMDs); None where a figure is missing."""
+    shape = tuple(shape)
+    tot = 0.0
+    for a in chunk_atoms:
+        s = shape
+        if shape[3] == 0:
+            split = -(-a // 64) * dens_segments(J, shape[0]) < simds
+            s = shape[:3] + (2 if split else 1,)
+        per_unit, unit = traffic_per_unit(kernel, s)
+        if per_unit is None:
+            return None, unit
+        tot += per_unit * a * (1.0 if unit == "atom" else units_per_atom)
+    return tot / len(chunk_atoms), unit
+
+
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--summarize-trace":
         summarize_trace(sys.argv[2])
@@ -718,9 +767,9 @@ def main():
                    "tflops": (flops[k] / launches / (avg[k] * 1e-3) / 1e12) if k in flops else None}
                for k in prof}
     achieved = kernels[dom]["tflops"]
-    per_unit, unit = traffic_per_unit(dom, ctx.kernel_shape(J))
-    units_per_launch = (atoms if unit == "atom" else n_pairs) * evals / launches
-    traffic = per_unit * units_per_launch if per_unit is not None else None
+    simds = 4 * n_cus
+    traffic, unit = traffic_per_launch(dom, ctx.kernel_shape(J), [v * n for v in chunk_plan], n_pairs / atoms, simds,
+                                       J)
 
     extras = {}
     if not args.no_extras:
@@ -780,7 +829,9 @@ def main():
                    "iterations": "one call each" if args.sync else "pipelined"},
         "roofline": {"bound": "alu", "kernel": kname[dom], "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                     "traffic_bytes_per_" + unit: per_unit,
+                     "traffic_bytes_per_" + unit: (traffic / (atoms / len(chunk_plan)) /
+                                                   (1.0 if unit == "atom" else n_pairs / atoms)
+                                                   if traffic is not None else None),
                      "avg_launch_ms": kernels[dom]["avg_ms"], "gflop_per_launch": kernels[dom]["gflop_per_launch"]},
         "kernels": kernels,
         "force_parity": gate,

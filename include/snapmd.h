@@ -153,7 +153,9 @@ int snap_forces(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_batch *ba
 
 /* Allocation-free variant of snap_forces, for callers that cannot allocate device memory
  * (work captured into a graph, tight serving loops, harnesses that forbid allocation).
- * Same arguments, results and asynchrony as snap_forces.  Every buffer its kernels use
+ * Same arguments and asynchrony as snap_forces; it runs the kernel shape (45, 0, 12, 1)
+ * whatever shape the context holds, so its results are bitwise those of snap_forces in
+ * that shape and equal to rounding otherwise.  Every buffer its kernels use
  * besides x, f and e_atom (neighbour lists, pair tables, SNAP densities and adjoints, the
  * batch description, the coefficient tables) lives in one fixed device array of
  * SNAPMD_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the
@@ -383,11 +385,15 @@ int snapmd_relax(snapmd_ctx *ctx, int potential, const snapmd_snap *snap, const 
  *   adjoint_waves     LDS-tiled adjoint: waves per 64-atom tile (12 or 8);
  *   density_parts     density pass of a force evaluation: the neighbour slots of a tile are
  *                     split over this many waves (1 or 2), whose partial densities the
- *                     adjoint adds as it loads them (more, shorter waves).
- * With the same density_parts, forces do not depend on the shape and per-atom energies
- * only through the order in which the adjoint's partial sums are added; the two
- * density_parts values differ by the rounding of the density sum.
- * snapmd_set_kernel_shape(ctx, J, NULL) restores the built-in shape (45, 0, 12, 1); any
+ *                     adjoint adds as it loads them (more, shorter waves); 0: split (2)
+ *                     a launch whose density pass has fewer waves than the device has
+ *                     SIMDs (a small chunk, where one wave per SIMD leaves the pass
+ *                     latency-bound), else 1.
+ * With the same split, forces do not depend on the shape and per-atom energies only
+ * through the order in which the adjoint's partial sums are added; the two splits differ
+ * by the rounding of the density sum (so with density_parts 0 the rounding depends on how
+ * many atoms a call propagates at once).
+ * snapmd_set_kernel_shape(ctx, J, NULL) restores the built-in shape (45, 0, 12, 0); any
  * other value is SNAPMD_EINVAL.  snapmd_get_kernel_shape writes the shape in use for J. */
 typedef struct {
     int32_t density_acc;

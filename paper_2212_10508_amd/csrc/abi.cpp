@@ -426,7 +426,8 @@ int prepare_snap(snapmd_ctx *ctx, const snapmd_snap *s, double min_half_box, Sna
     {
         auto it = ctx->shapes.find(J);
         sd.shape = it != ctx->shapes.end() ? it->second : KernelShape{};
-        if (J > kMaxJLds) sd.shape = KernelShape{45, 0, 12};
+        sd.simds = 4 * std::max(ctx->n_cus, 1);
+        if (J > kMaxJLds) sd.shape = KernelShape{45, 0, 12, 1};
     }
     sd.J = J;
     sd.K = T.K;
@@ -1806,6 +1807,7 @@ int snap_forces_noalloc(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_b
     sd.nrm = d_nrm;
     sd.ymult = d_ymult;
     sd.adj = AdjointDev{d_cgm, d_coef, d_coef_off, d_roles, A.role_len};
+    sd.shape.dens_parts = 1;  // the scratch array holds one density (no split)
     launch_neighbors(bd, x, snap->rcut, w, st, true, kSkin);
     launch_snap(J, bd, x, sd, w, f, e_atom, (flags & SNAPMD_ACCUMULATE) ? 1 : 0, st);
     return check_launch(ctx);
@@ -2369,7 +2371,7 @@ int snapmd_set_kernel_shape(snapmd_ctx *ctx, int32_t twojmax, const snapmd_kerne
     const bool ok = (shape->density_acc == 45 || shape->density_acc == 28 || shape->density_acc == 21) &&
                     (shape->dedr_stage_atoms == 5 || shape->dedr_stage_atoms == 3 || shape->dedr_stage_atoms == 0) &&
                     (shape->adjoint_waves == 12 || shape->adjoint_waves == 8) &&
-                    (shape->density_parts == 1 || shape->density_parts == 2);
+                    (shape->density_parts >= 0 && shape->density_parts <= 2);
     if (!ok)
         return fail(ctx, SNAPMD_EINVAL, "kernel shape (%d, %d, %d, %d) is not one of the compiled variants",
                     shape->density_acc, shape->dedr_stage_atoms, shape->adjoint_waves, shape->density_parts);

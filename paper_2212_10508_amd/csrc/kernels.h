@@ -63,18 +63,21 @@ struct AdjointDev {
 //   dedr_atoms dE/dr: atoms whose Y~ rows a wave stages in LDS (5, 3 or 0: from memory)
 //   adj_waves  LDS-tiled adjoint: waves per 64-atom tile (12 or 8)
 //   dens_parts density pass of a force evaluation: waves over which a tile's neighbour
-//              slots are split (1 or 2); part p writes u + p nh N, the adjoint adds them
+//              slots are split (1 or 2); part p writes u + p nh N, the adjoint adds them;
+//              0: 2 for a launch with fewer density waves than the device has SIMDs
+//              (one wave per SIMD leaves the pass latency-bound), else 1
 // Above twojmax 8 the passes have one shape each (45, 0, -, 1).
 struct KernelShape {
     int dens_acc = 45;
     int dedr_atoms = 0;
     int adj_waves = 12;
-    int dens_parts = 1;
+    int dens_parts = 0;
 };
 
 // SNAP coefficient-dependent tables on the device.
 struct SnapDev {
     int J = 0, K = 0, nh = 0;
+    int simds = 1024;  // SIMDs of the device (4 per CU): the automatic density split
     SnapGeoParams gp{};
     double beta0 = 0.0;
     const double *nrm = nullptr, *ymult = nullptr;

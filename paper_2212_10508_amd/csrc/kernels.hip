@@ -716,10 +716,12 @@ __global__ void k_pair_ell(int N, int n_sys, const int *__restrict__ off, const 
 // u (half storage, [e][N] double2) for column C, levels N0 .. N1: one wave per tile of 64
 // atoms, lane = atom.  Step t reads slot t of the 64 atoms' lists from the slot-major copy
 // of a, b and f_c (one coalesced load per field); slots past an atom's count add nothing.
-// With gridDim.z = parts > 1 the slots are split into parts (blockIdx.z = part), each
-// writing its partial sum to u + part nh N (nh = half elements); the identity term of
-// level 0 goes with part 0, and the Finnis-Sinclair density (dF non-null, column 0) is
-// summed over all slots by part 0.
+// With gridDim.z = parts > 1 each atom's slots are split into parts (blockIdx.z = part;
+// part p takes slots [p cnt / parts, (p + 1) cnt / parts) of an atom with cnt, rounded
+// up), each writing its partial sum to u + part nh N (nh = half elements): step k then
+// reads slot tb + k of each lane, a few neighbouring rows per load.  The identity term
+// of every level goes with part 0, and the Finnis-Sinclair density (dF non-null, column
+// 0) is summed over all slots by part 0.
 template <int J, int C, int N0, int N1, bool AHEAD, bool TAIL>
 __device__ __forceinline__ void density_lane(int tile, int N, const int *__restrict__ poff,
                                              const double *__restrict__ ell, const double *__restrict__ nrm,
@@ -733,11 +735,13 @@ __device__ __forceinline__ void density_lane(int tile, int N, const int *__restr
 #pragma unroll
     for (int q = 0; q <= J; ++q) tacc[q] = make_double2(0.0, 0.0);
     const int cnt = i < N ? poff[i + 1] - poff[i] : 0;
-    int tmax = cnt;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) tmax = max(tmax, __shfl_xor(tmax, o, 64));
+    // this lane's slots [tb, te): its own list cut into parts, so that a partial density
+    // depends on the atom alone and not on which atoms share its tile
     const int part = blockIdx.z, parts = gridDim.z;
-    const int tb = (part * tmax + parts - 1) / parts, te = ((part + 1) * tmax + parts - 1) / parts;
+    const int tb = (part * cnt + parts - 1) / parts, te = ((part + 1) * cnt + parts - 1) / parts;
+    int kmax = te - tb;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
     const size_t sN = (size_t)kMaxNeigh * N;
     constexpr bool kRho = C == 0 && N0 == 0;
     constexpr int NF = kRho ? 6 : 5;
@@ -746,11 +750,12 @@ __device__ __forceinline__ void density_lane(int tile, int N, const int *__restr
     double rho = 0.0;  // Finnis-Sinclair density (column 0 with dF)
     if (rho_apart)
         for (int t = 0; t < cnt; ++t) rho += ell[5 * sN + (size_t)t * N + i];
-    // Fields of slot t: a, b, f_c (and phi); past the count the identity rotation with
-    // zero weight (slot contents unused).
-    auto fetch = [&](int t, double (&f)[NF]) {
-        const bool v = t < cnt;
-        const size_t q = (size_t)t * N + (v ? i : 0);
+    // Fields of the lane's k-th slot tb + k: a, b, f_c (and phi); past te the identity
+    // rotation with zero weight (slot contents unused).
+    auto fetch = [&](int k, double (&f)[NF]) {
+        const int t = tb + k;
+        const bool v = t < te;
+        const size_t q = v ? (size_t)t * N + i : 0;
         f[0] = v ? ell[q] : 1.0;
         f[1] = v ? ell[sN + q] : 0.0;
         f[2] = v ? ell[2 * sN + q] : 0.0;
@@ -761,15 +766,15 @@ __device__ __forceinline__ void density_lane(int tile, int N, const int *__restr
     // AHEAD: slot t + 1 is in flight while slot t is computed (at two waves per SIMD too
     // few other waves hide the load latency).
     double nx[NF];
-    if (AHEAD && tb < te) fetch(tb, nx);
-    for (int t = tb; t < te; ++t) {
+    if (AHEAD && kmax > 0) fetch(0, nx);
+    for (int k = 0; k < kmax; ++k) {
         double f[NF];
         if constexpr (AHEAD) {
 #pragma unroll
             for (int m = 0; m < NF; ++m) f[m] = nx[m];
-            if (t + 1 < te) fetch(t + 1, nx);
+            if (k + 1 < kmax) fetch(k + 1, nx);
         } else {
-            fetch(t, f);
+            fetch(k, f);
         }
         if constexpr (kRho) rho += f[NF - 1];
         const double2 a = make_double2(f[0], f[1]);
@@ -1443,7 +1448,12 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     hipLaunchKernelGGL(k_pair_ell, dim3(nblk((size_t)N * kMaxNeigh, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box,
                        x, w.poff, w.nbr_t, sd.gp, w.ell, fuse ? fuse->d : 0.0, fuse ? w.flag : nullptr);
     // the LDS-tiled adjoint adds the two parts of a split density as it loads its tile
-    const int parts = (J <= 8 && sd.shape.dens_parts == 2) ? 2 : 1;
+    int parts = 1;
+    if constexpr (J <= 8) {
+        const int acc = sd.shape.dens_acc;
+        const int segs = acc == 28 ? dens_segments(J, 28) : acc == 21 ? dens_segments(J, 21) : dens_segments(J, 45);
+        if (sd.shape.dens_parts == 2 || (sd.shape.dens_parts == 0 && (long)nblk(N, 64) * segs < sd.simds)) parts = 2;
+    }
     pf.begin(PROF_DENSITY, st);
     density_launch<J>(N, w, sd, fuse ? fuse->A : 0.0, fuse ? w.rho : nullptr, st, parts);
     pf.end(st);

@@ -54,8 +54,8 @@ class KShape(C.Structure):
 
 # compiled variants of each kernel-shape field (twojmax <= 8)
 SHAPE_CHOICES = {"density_acc": (45, 28, 21), "dedr_stage_atoms": (5, 3, 0), "adjoint_waves": (12, 8),
-                 "density_parts": (1, 2)}
-DEFAULT_SHAPE = (45, 0, 12, 1)
+                 "density_parts": (1, 2, 0)}
+DEFAULT_SHAPE = (45, 0, 12, 0)
 
 
 class ParaLog(C.Structure):
@@ -491,7 +491,8 @@ class Context:
     def set_kernel_shape(self, J, shape):
         """Kernel shape (density_acc, dedr_stage_atoms, adjoint_waves, density_parts) of the
         SNAP passes at twojmax J (None: the built-in shape; a shape of three values has
-        density_parts 1)."""
+        density_parts 1; density_parts 0 splits the density pass of launches with fewer
+        waves than the device has SIMDs)."""
         if shape is None:
             self._check(lib().snapmd_set_kernel_shape(self.h, int(J), None))
         else:

@@ -249,7 +249,9 @@ def test_kernel_shapes_give_identical_forces(S, J):
         e = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
         f = host(ctx.snap_forces(dev(X), off, boxes, J, beta, e_atom=e))
         eh = host(e)
-        parts = shape[3]
+        # density_parts 0 splits launches with fewer density waves than the device has
+        # SIMDs: this batch of 258 atoms
+        parts = shape[3] or 2
         if parts not in ref:
             ref[parts] = (f, eh)
             assert frel(f[:, :n], ora) < FTOL
@@ -259,12 +261,38 @@ def test_kernel_shapes_give_identical_forces(S, J):
     assert frel(ref[2][0], ref[1][0]) < 1e-13
     assert np.max(np.abs(ref[2][1] - ref[1][1])) < 1e-13 * np.max(np.abs(ref[1][1]))
     ctx.set_kernel_shape(J, None)
-    assert ctx.kernel_shape(J) == (45, 0, 12, 1)
+    assert ctx.kernel_shape(J) == (45, 0, 12, 0)
     ctx.set_kernel_shape(J, (28, 3, 8))   # three values: density_parts 1
     assert ctx.kernel_shape(J) == (28, 3, 8, 1)
     for bad in ((44, 5, 12, 1), (45, 5, 12, 3)):
         with pytest.raises(S.SnapmdError):
             ctx.set_kernel_shape(J, bad)
+
+
+def test_automatic_density_split_follows_the_launch_size(S):
+    """density_parts 0 splits the density pass of a launch with fewer density waves than
+    the device has SIMDs and no other: bitwise the forces of the split shape on one
+    1025-atom system (17 tiles in 4 column segments), of the unsplit shape on a batch of
+    24 (385 tiles: 1,540 density waves)."""
+    J = 8
+    x, box = W.bcc_sia(8, jitter=0.05, seed=80)
+    n = x.shape[1]
+    beta = W.snap_beta(J, seed=80)
+    ctx = S.Context(0)
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    for R in (1, 24):
+        X = dev(np.tile(x, (1, R)))
+        off = np.arange(R + 1) * n
+        boxes = np.tile(box, (R, 1))
+        got = {}
+        for parts in (0, 1, 2):
+            ctx.set_kernel_shape(J, (45, 0, 12, parts))
+            got[parts] = host(ctx.snap_forces(X, off, boxes, J, beta))
+        split = ((R * n + 63) // 64) * 4 < simds
+        assert split == (R == 1)
+        assert np.array_equal(got[0], got[2 if split else 1]), R
+        assert frel(got[1], got[2]) < 1e-13
+    ctx.set_kernel_shape(J, None)
 
 
 def test_kernel_shape_tuner_checks_parity_first(S):

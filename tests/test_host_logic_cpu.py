@@ -115,7 +115,7 @@ def test_kernel_shape_cache_round_trip(tmp_path):
     assert tune.load_shape(k, path) == (28, 3, 12, 2)
     assert tune.load_shape("gfx942:J8:2^14", path) is None
     c = tune.shape_candidates()
-    assert c[0] == (45, 0, 12, 1) and len(c) == len(set(c)) == 36
+    assert c[0] == (45, 0, 12, 0) and len(c) == len(set(c)) == 54
 
 
 def test_shape_tuner_keeps_builtin_within_noise(monkeypatch):

@@ -1,6 +1,7 @@
 """The allocation-free SNAP forces (snap_forces_noalloc) against snap_forces, through
 the C ABI: two calls in a row, the second on a smaller batch, must give the same forces
-and energies; sizes beyond the scratch limits are refused before any launch."""
+and energies (bitwise in the kernel shape the allocation-free path runs, to rounding in
+the built-in one); sizes beyond the scratch limits are refused before any launch."""
 import numpy as np
 import pytest
 
@@ -45,7 +46,11 @@ def test_noalloc_matches_snap_forces_on_two_calls(S, J):
         xd = dev(x)
         f_ref = torch.empty((3, N), dtype=torch.float64, device="cuda")
         e_ref = torch.empty(N, dtype=torch.float64, device="cuda")
+        ctx.set_kernel_shape(J, None)  # built-in shape: the density split of small launches
+        f_def = ctx.snap_forces(xd, off, boxes, J, beta).clone()
+        ctx.set_kernel_shape(J, (45, 0, 12, 1))  # the shape the allocation-free path runs
         ctx.snap_forces(xd, off, boxes, J, beta, f=f_ref, e_atom=e_ref)
+        ctx.set_kernel_shape(J, None)
         f = torch.full((3, N), float("nan"), dtype=torch.float64, device="cuda")
         e = torch.full((N,), float("nan"), dtype=torch.float64, device="cuda")
         ctx.snap_forces_noalloc(xd, off, boxes, J, beta, f, e_atom=e)
@@ -54,6 +59,7 @@ def test_noalloc_matches_snap_forces_on_two_calls(S, J):
         assert torch.max(torch.abs(f - f_ref)).item() <= 1e-12 * fmax
         assert torch.max(torch.abs(e - e_ref)).item() <= 1e-12 * torch.max(torch.abs(e_ref)).item()
         assert torch.equal(f, f_ref) and torch.equal(e, e_ref)   # same kernels, same order
+        assert torch.max(torch.abs(f - f_def)).item() <= 1e-12 * fmax
         # accumulate mode adds onto f
         ctx.snap_forces_noalloc(xd, off, boxes, J, beta, f, accumulate=True)
         ctx.sync()
