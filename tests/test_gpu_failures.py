@@ -88,6 +88,48 @@ def test_nonfinite_in_corrected_iteration_names_the_slab(S):
     assert torch.isfinite(q[:4]).all()
 
 
+def test_nonfinite_in_pipelined_iterations_matches_synchronous(S):
+    """The same planted NaN with two corrected iterations enqueued back to back
+    (parareal_iterate_async): each collect reports what the synchronous calls report, in
+    order (slab 3, then slab 4: the second iteration starts from the first one's states,
+    whose slab-4 start is the non-finite value the first sweep stopped at), and the
+    states end equal bitwise."""
+    J, N, L = 2, 5, 3
+    x, box = W.bcc_sia(4, jitter=0.05, seed=22)
+    p = W.maxwell_momenta(x.shape[1], 1000.0, seed=22)
+    kw = dict(dt=1e-3, gamma=1.0, mass=W.MASS_W, T=1000.0, seed=4, noise_id=0, fs=W.FS_W)
+    beta = W.snap_beta(J, seed=22)
+    ctx = S.Context(0)
+    n = x.shape[1]
+    out = []
+    for pipelined in (False, True):
+        q = torch.zeros((N + 1, 3, n), dtype=torch.float64, device="cuda")
+        pq, qp, pp = torch.zeros_like(q), torch.zeros_like(q), torch.zeros_like(q)
+        q[0], pq[0] = dev(x), dev(p)
+        ctx.parareal_iterate(None, None, q, pq, box, L, 0, N, 1e100, **kw)
+        pq[3, 1, 7] = float("nan")
+        errs = []
+        if pipelined:
+            for _ in range(2):
+                ctx.parareal_iterate_async(qp, pp, q, pq, box, L, 0, N, 1e100, J=J, beta=beta, **kw)
+            for _ in range(2):
+                with pytest.raises(S.SnapmdError) as e:
+                    ctx.parareal_collect()
+                errs.append((e.value.code, str(e.value)))
+        else:
+            for _ in range(2):
+                with pytest.raises(S.SnapmdError) as e:
+                    ctx.parareal_iterate(qp, pp, q, pq, box, L, 0, N, 1e100, J=J, beta=beta, **kw)
+                errs.append((e.value.code, str(e.value)))
+        torch.cuda.synchronize()
+        out.append((errs, [t.cpu().numpy() for t in (q, pq, qp, pp)]))
+    (e0, s0), (e1, s1) = out
+    assert [c for c, _ in e0] == [S.ENONFINITE] * 2 and "slab 3" in e0[0][1] and "slab 4" in e0[1][1]
+    assert e1 == e0
+    for a, b in zip(s0, s1):
+        assert np.array_equal(a, b, equal_nan=True)
+
+
 def test_nonfinite_in_batch_names_system_and_slab(S):
     J, N, L = 2, 4, 3
     xs, ps, boxes = [], [], []
