@@ -592,7 +592,7 @@ int neighbors(snapmd_ctx *ctx, Work &w, const BatchDev &bd0, const double *x, do
 // (by the SNAP gather, or by a kernel of its own after the Finnis-Sinclair force).
 void enqueue_forces(snapmd_ctx *ctx, Work &w, int potential, const BatchDev &bd, const double *x,
                     const FsParams *fp, const SnapDev *sd, double *f, hipStream_t st, bool fresh = true,
-                    double *p_kick = nullptr, double dt = 0.0) {
+                    double *p_kick = nullptr, double dt = 0.0, const StepOpen *open = nullptr) {
     double rc = 0.0;
     if (fp) rc = std::max(fp->d, fp->c);
     if (potential == SNAPMD_POT_FS_SNAP) rc = std::max(rc, sd->gp.rcut);
@@ -600,7 +600,7 @@ void enqueue_forces(snapmd_ctx *ctx, Work &w, int potential, const BatchDev &bd,
     (void)neighbors(ctx, w, bd, x, rc, fresh, st, true);
     ctx->prof.end(st);
     if (potential == SNAPMD_POT_FS_SNAP) {
-        launch_snap(sd->J, bd, x, *sd, w, f, nullptr, 0, st, &ctx->prof, nullptr, p_kick, dt, fp);
+        launch_snap(sd->J, bd, x, *sd, w, f, nullptr, 0, st, &ctx->prof, nullptr, p_kick, dt, fp, open);
     } else {
         launch_fs(bd, x, *fp, w, f, nullptr, 0, st, true);
         if (p_kick) launch_baoab_post(bd, p_kick, f, dt, st);
@@ -615,14 +615,26 @@ void run_langevin_range(snapmd_ctx *ctx, Work &w, double *f, int potential, cons
                         const SnapDev &sd, const LangevinDev &ld, int s_lo, int s_hi, int n_last, bool initial,
                         double *x, double *p, hipStream_t st) {
     if (initial) enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st);
+    // BAOAB with SNAP: the gather of step s also opens step s + 1 within the range (one
+    // launch less per step); the range's first step is opened by k_baoab_pre
+    const bool fuse_open = potential == SNAPMD_POT_FS_SNAP;
+    StepOpen open;
+    open.x = x;
+    open.ld = ld;
+    open.off = bd.off;
+    open.n_sys = bd.n_sys;
+    open.xref = w.xref;
+    open.lim2 = 0.25 * kSkin * kSkin;
+    open.flag = w.flag;
     for (int s = s_lo; s < s_hi; ++s) {
         if (ld.scheme == SNAPMD_SCHEME_BBK) {
             launch_bbk_pre(bd, x, p, f, ld, s, w, kSkin, st);
             enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st, false);
             launch_bbk_post(bd, p, f, ld, s + 1, n_last, st);
         } else {
-            launch_baoab_pre(bd, x, p, f, ld, s, w, kSkin, st);
-            enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st, false, p, ld.dt);
+            if (!fuse_open || s == s_lo) launch_baoab_pre(bd, x, p, f, ld, s, w, kSkin, st);
+            open.open_step = (fuse_open && s + 1 < s_hi) ? s + 1 : -1;
+            enqueue_forces(ctx, w, potential, bd, x, &fp, &sd, f, st, false, p, ld.dt, &open);
         }
     }
 }

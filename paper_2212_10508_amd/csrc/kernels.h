@@ -248,9 +248,23 @@ void launch_ws_sites(const BatchDev &bd, const int4 *ws, int n_sites, double a, 
 void launch_descent_step(int N, double *x, const double *f, double alpha, double dmax, hipStream_t st);
 void launch_fmax2(int N, const double *f, unsigned long long *out, hipStream_t st);
 
+// The opening B A O A of the next BAOAB step, done by the gather after the closing kick
+// (open_step < 0: none): x and p of the batch, the Langevin parameters, the step index and
+// the Verlet-list displacement test of k_baoab_pre.
+struct StepOpen {
+    int open_step = -1;
+    double *x = nullptr;
+    LangevinDev ld{};
+    const int *off = nullptr;
+    int n_sys = 0;
+    const double *xref = nullptr;
+    double lim2 = 0.0;
+    int *flag = nullptr;
+};
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
                  double *e_atom, int accumulate, hipStream_t st, KernelProf *prof = nullptr,
-                 hipEvent_t join = nullptr, double *p_kick = nullptr, double dt = 0.0, const FsParams *fuse = nullptr);
+                 hipEvent_t join = nullptr, double *p_kick = nullptr, double dt = 0.0, const FsParams *fuse = nullptr,
+                 const StepOpen *open = nullptr);
 void launch_snap_density(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, hipStream_t st);
 void adjoint_tables(int J, const double *beta, AdjointHost &A);
 void adjoint_init_attributes();

@@ -1193,10 +1193,18 @@ __global__ void __launch_bounds__(64) k_dedr(int N, int n_sys, const int *__rest
 // Wave c then sums component c of each atom's differences in list order, so the sum
 // is the same sequence of additions as a loop over the atom's pairs.
 constexpr int kGatherWin = 2048;
+__device__ __forceinline__ void baoab_open(int N, int i, int s, int local, const double (&pv)[3],
+                                           const double (&fv)[3], double *__restrict__ x, double *__restrict__ p,
+                                           const LangevinDev &ld, int s_step, const double *__restrict__ xref,
+                                           double lim2, int *__restrict__ flag);
+
+// With open.open_step >= 0 (and pk) the workgroup then also opens step open_step for its
+// 64 atoms, one lane per atom (the three components meet in LDS): the B A O A and the
+// displacement test of k_baoab_pre, through the same function, on the kicked momenta.
 __global__ void __launch_bounds__(256) k_gather(int N, const int *__restrict__ poff, const int *__restrict__ rev,
                                                 const double *__restrict__ dedr, size_t Pcap,
                                                 double *__restrict__ f, int accumulate, double *__restrict__ pk,
-                                                double dt) {
+                                                double dt, StepOpen open) {
     __shared__ double dg[3][kGatherWin];
     const int k0 = blockIdx.x * 64, k1 = min(k0 + 64, N);
     const int tid = threadIdx.x, c = tid >> 6, k = k0 + (tid & 63);
@@ -1219,11 +1227,32 @@ __global__ void __launch_bounds__(256) k_gather(int N, const int *__restrict__ p
         }
         __syncthreads();
     }
-    if (!own) return;
-    const size_t o = (size_t)c * N + k;
-    const double fk = accumulate ? f[o] + g : g;
-    f[o] = fk;
-    if (pk) pk[o] = fma(0.5 * dt / MVV2E, fk, pk[o]);
+    const bool opening = pk && open.open_step >= 0;
+    double fk = 0.0, pn = 0.0;
+    if (own) {
+        const size_t o = (size_t)c * N + k;
+        fk = accumulate ? f[o] + g : g;
+        f[o] = fk;
+        if (pk) {
+            pn = fma(0.5 * dt / MVV2E, fk, pk[o]);
+            if (!opening) pk[o] = pn;
+        }
+    }
+    if (!opening) return;
+    // dg is free: the last window ended with a barrier
+    double *sf = &dg[0][0], *sp = &dg[1][0];
+    if (own) {
+        sf[c * 64 + (tid & 63)] = fk;
+        sp[c * 64 + (tid & 63)] = pn;
+    }
+    __syncthreads();
+    if (tid < 64 && k0 + tid < N) {
+        const int i = k0 + tid, s = sys_of(open.off, open.n_sys, i);
+        const double pv[3] = {sp[tid], sp[64 + tid], sp[128 + tid]};
+        const double fv[3] = {sf[tid], sf[64 + tid], sf[128 + tid]};
+        baoab_open(N, i, s, i - open.off[s], pv, fv, open.x, pk, open.ld, open.open_step, open.xref, open.lim2,
+                   open.flag);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1264,29 +1293,41 @@ __device__ __forceinline__ void gauss3(uint64_t seed, uint64_t noise_id, uint64_
 // B (half kick), A (half drift), O (exact OU), A (half drift)
 // B A O A of one step; also requests a Verlet-list rebuild (flag) when the new position
 // is more than sqrt(lim2) from the one of the last build.
+// B A O A of step s_step for atom i (system s, index `local` in it) from its momentum pv
+// and force fv: writes p and x, and flags a list rebuild past the displacement limit.
+// Explicit FMAs, so that the standalone pass and the one fused into the gather round alike.
+__device__ __forceinline__ void baoab_open(int N, int i, int s, int local, const double (&pv)[3],
+                                           const double (&fv)[3], double *__restrict__ x, double *__restrict__ p,
+                                           const LangevinDev &ld, int s_step, const double *__restrict__ xref,
+                                           double lim2, int *__restrict__ flag) {
+    const uint64_t gstep = (uint64_t)(ld.step0[s] + s_step);
+    double g[3];
+    gauss3(ld.seed, (uint64_t)ld.noise_id[s], gstep, (uint64_t)local, g[0], g[1], g[2]);
+    const double hk = 0.5 * ld.dt / MVV2E, hd = 0.5 * ld.dt / ld.mass, sig = ld.sig[s];
+    double d2 = 0.0;
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        double pp = fma(hk, fv[al], pv[al]);
+        double xx = fma(hd, pp, x[al * N + i]);
+        pp = fma(ld.c1, pp, sig * g[al]);
+        xx = fma(hd, pp, xx);
+        p[al * N + i] = pp;
+        x[al * N + i] = xx;
+        const double dd = xx - xref[al * N + i];
+        d2 = fma(dd, dd, d2);
+    }
+    if (!(d2 <= lim2)) atomicOr(flag, 1);  // NaN also rebuilds
+}
+
 __global__ void k_baoab_pre(int N, int n_sys, const int *__restrict__ off, double *__restrict__ x,
                             double *__restrict__ p, const double *__restrict__ f, LangevinDev ld, int s_step,
                             const double *__restrict__ xref, double lim2, int *__restrict__ flag) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int s = sys_of(off, n_sys, i);
-    const uint64_t gstep = (uint64_t)(ld.step0[s] + s_step);
-    double g[3];
-    gauss3(ld.seed, (uint64_t)ld.noise_id[s], gstep, (uint64_t)(i - off[s]), g[0], g[1], g[2]);
-    const double hk = 0.5 * ld.dt / MVV2E, hd = 0.5 * ld.dt / ld.mass, sig = ld.sig[s];
-    double d2 = 0.0;
-#pragma unroll
-    for (int al = 0; al < 3; ++al) {
-        double pp = p[al * N + i] + hk * f[al * N + i];
-        double xx = x[al * N + i] + hd * pp;
-        pp = ld.c1 * pp + sig * g[al];
-        xx = xx + hd * pp;
-        p[al * N + i] = pp;
-        x[al * N + i] = xx;
-        const double dd = xx - xref[al * N + i];
-        d2 += dd * dd;
-    }
-    if (!(d2 <= lim2)) atomicOr(flag, 1);  // NaN also rebuilds
+    const double pv[3] = {p[i], p[N + i], p[2 * N + i]};
+    const double fv[3] = {f[i], f[N + i], f[2 * N + i]};
+    baoab_open(N, i, s, i - off[s], pv, fv, x, p, ld, s_step, xref, lim2, flag);
 }
 
 __global__ void k_baoab_post(int N, double *__restrict__ p, const double *__restrict__ f, double dt) {
@@ -1435,7 +1476,7 @@ static void dedr_launch(const BatchDev &bd, const double *x, const SnapDev &sd, 
 template <int J>
 static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
                           double *e_atom, int accumulate, hipStream_t st, KernelProf *prof, hipEvent_t join,
-                          double *p_kick, double dt, const FsParams *fuse) {
+                          double *p_kick, double dt, const FsParams *fuse, const StepOpen *open) {
     const int N = bd.N;
     KernelProf dummy;
     KernelProf &pf = prof ? *prof : dummy;
@@ -1487,20 +1528,20 @@ static void launch_snap_J(const BatchDev &bd, const double *x, const SnapDev &sd
     pf.end(st);
     if (join) (void)hipStreamWaitEvent(st, join, 0);  // f written by work on another stream
     hipLaunchKernelGGL(k_gather, dim3(nblk(N, 64)), dim3(256), 0, st, N, w.poff, w.rev, w.dedr, w.Pcap, f,
-                       accumulate, p_kick, dt);
+                       accumulate, p_kick, dt, open ? *open : StepOpen{});
 }
 
 void launch_snap(int J, const BatchDev &bd, const double *x, const SnapDev &sd, Work &w, double *f,
                  double *e_atom, int accumulate, hipStream_t st, KernelProf *prof, hipEvent_t join, double *p_kick,
-                 double dt, const FsParams *fuse) {
+                 double dt, const FsParams *fuse, const StepOpen *open) {
     switch (J) {
-        case 2: launch_snap_J<2>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
-        case 4: launch_snap_J<4>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
-        case 6: launch_snap_J<6>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
-        case 8: launch_snap_J<8>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
-        case 10: launch_snap_J<10>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
-        case 12: launch_snap_J<12>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
-        case 14: launch_snap_J<14>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse); break;
+        case 2: launch_snap_J<2>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse, open); break;
+        case 4: launch_snap_J<4>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse, open); break;
+        case 6: launch_snap_J<6>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse, open); break;
+        case 8: launch_snap_J<8>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse, open); break;
+        case 10: launch_snap_J<10>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse, open); break;
+        case 12: launch_snap_J<12>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse, open); break;
+        case 14: launch_snap_J<14>(bd, x, sd, w, f, e_atom, accumulate, st, prof, join, p_kick, dt, fuse, open); break;
         default: break;
     }
 }
