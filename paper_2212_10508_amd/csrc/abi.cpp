@@ -602,8 +602,7 @@ void enqueue_forces(snapmd_ctx *ctx, Work &w, int potential, const BatchDev &bd,
     if (potential == SNAPMD_POT_FS_SNAP) {
         launch_snap(sd->J, bd, x, *sd, w, f, nullptr, 0, st, &ctx->prof, nullptr, p_kick, dt, fp, open);
     } else {
-        launch_fs(bd, x, *fp, w, f, nullptr, 0, st, true);
-        if (p_kick) launch_baoab_post(bd, p_kick, f, dt, st);
+        launch_fs(bd, x, *fp, w, f, nullptr, 0, st, true, p_kick, dt);
     }
 }
 

@@ -237,8 +237,10 @@ void launch_noise_table(int S, int L, int N, int n_in, uint64_t seed, uint64_t n
 // (launch_fs with clear_flag) instead of a kernel of its own
 void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, hipStream_t st, bool force,
                       double skin, bool checked = false, bool clear_in_fs = false);
+// p_kick (nullable): momenta that receive the closing half kick p += (dt/2) f of a BAOAB
+// step from the force pass
 void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w, double *f, double *e_atom,
-               int accumulate, hipStream_t st, bool clear_flag = false);
+               int accumulate, hipStream_t st, bool clear_flag = false, double *p_kick = nullptr, double dt = 0.0);
 // join (nullable): an event the gather waits for (the Finnis-Sinclair force written into f
 // on another stream); p_kick (nullable): momenta that receive the closing half kick
 // p += (dt/2) f of a BAOAB step from the gather
@@ -281,7 +283,6 @@ void launch_reduce_rows(int rows, int N, const double *in, double scale, double 
 void launch_set_value(double *p, double v, hipStream_t st);
 void launch_baoab_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
                       const Work &w, double skin, hipStream_t st);
-void launch_baoab_post(const BatchDev &bd, double *p, const double *f, double dt, hipStream_t st);
 void launch_bbk_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
                     const Work &w, double skin, hipStream_t st);
 void launch_add_i64(int n, int64_t *v, int64_t delta, hipStream_t st);

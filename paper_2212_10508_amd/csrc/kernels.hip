@@ -11,7 +11,8 @@
 //                -> k_dedr<J> (per pair dE_i/dr_ij = Re sum conj(Y~) d(f_c P), geometry
 //                again from the positions) -> k_gather (F_k = sum over pairs
 //                (g_kj - g_jk), no atomics, deterministic)
-//   BAOAB      : k_baoab_pre (B A O A with Philox4x64-10 Gaussians) / k_baoab_post (B)
+//   BAOAB      : k_baoab_pre (B A O A with Philox4x64-10 Gaussians; the SNAP gather opens
+//                the following steps itself) / closing B in k_gather or k_fs_force
 //   BBK        : k_bbk_pre / k_bbk_post (the paper's modified BBK scheme)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -445,11 +446,15 @@ __global__ void __launch_bounds__(256) k_fs_rho(int N, int n_sys, const int *__r
     if (own && q == 0) rho[i] = acc;
 }
 
+// pk (nullable): momenta that receive the closing half kick p += (dt/2) f of a BAOAB step
+// (the gather's expression).  The next step's opening stays a kernel of its own: it moves
+// x, which the other atoms of this pass still read.
 __global__ void __launch_bounds__(256) k_fs_force(int N, int n_sys, const int *__restrict__ off,
                                                   const double *__restrict__ box, const double *__restrict__ x,
                                                   const int *__restrict__ poff, const int *__restrict__ pair_j,
                                                   FsParams fp, const double *__restrict__ rho, double *__restrict__ f,
-                                                  double *__restrict__ e_atom, int accumulate) {
+                                                  double *__restrict__ e_atom, int accumulate, double *__restrict__ pk,
+                                                  double dt) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int i0 = g / kFsLanes, q = g % kFsLanes;
     const bool own = i0 < N;
@@ -491,9 +496,17 @@ __global__ void __launch_bounds__(256) k_fs_force(int N, int n_sys, const int *_
     ep = fs_lane_sum(ep);
     if (!own || q != 0) return;
     if (accumulate) {
-        f[i] += fx; f[N + i] += fy; f[2 * N + i] += fz;
-    } else {
-        f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
+        fx += f[i];
+        fy += f[N + i];
+        fz += f[2 * N + i];
+    }
+    f[i] = fx;
+    f[N + i] = fy;
+    f[2 * N + i] = fz;
+    if (pk) {
+        pk[i] = fma(0.5 * dt / MVV2E, fx, pk[i]);
+        pk[N + i] = fma(0.5 * dt / MVV2E, fy, pk[N + i]);
+        pk[2 * N + i] = fma(0.5 * dt / MVV2E, fz, pk[2 * N + i]);
     }
     if (e_atom) {
         const double e = -fp.A * sqrt(ri) + ep;
@@ -1330,12 +1343,6 @@ __global__ void k_baoab_pre(int N, int n_sys, const int *__restrict__ off, doubl
     baoab_open(N, i, s, i - off[s], pv, fv, x, p, ld, s_step, xref, lim2, flag);
 }
 
-__global__ void k_baoab_post(int N, double *__restrict__ p, const double *__restrict__ f, double dt) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= 3 * N) return;
-    p[q] = fma(0.5 * dt / MVV2E, f[q], p[q]);
-}
-
 // The paper's modified BBK scheme, one call = one application of L iterates.  First half
 // of iterate l (s_step): p_{l+1/2} = p_l + (dt/2) F_l - (dt/2) gamma p_{l-1/2} + s_l G_l
 // (p_{-1/2} := p_0 at l = 0), q_{l+1} = q_l + dt p_{l+1/2} / m.  p then holds p_{l+1/2},
@@ -1435,12 +1442,12 @@ void launch_neighbors(const BatchDev &bd, const double *x, double rc, Work &w, h
 }
 
 void launch_fs(const BatchDev &bd, const double *x, const FsParams &fp, Work &w, double *f, double *e_atom,
-               int accumulate, hipStream_t st, bool clear_flag) {
+               int accumulate, hipStream_t st, bool clear_flag, double *p_kick, double dt) {
     const int N = bd.N;
     hipLaunchKernelGGL(k_fs_rho, dim3(nblk((size_t)N * kFsLanes, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, w.poff,
                        w.pair_j, fp.d, w.rho, clear_flag ? w.flag : nullptr);
     hipLaunchKernelGGL(k_fs_force, dim3(nblk((size_t)N * kFsLanes, 256)), dim3(256), 0, st, N, bd.n_sys, bd.off, bd.box, x, w.poff,
-                       w.pair_j, fp, w.rho, f, e_atom, accumulate);
+                       w.pair_j, fp, w.rho, f, e_atom, accumulate, p_kick, dt);
 }
 
 template <int J, int ACC>
@@ -1575,10 +1582,6 @@ void launch_baoab_pre(const BatchDev &bd, double *x, double *p, const double *f,
                       const Work &w, double skin, hipStream_t st) {
     hipLaunchKernelGGL(k_baoab_pre, dim3(nblk(bd.N, 256)), dim3(256), 0, st, bd.N, bd.n_sys, bd.off, x, p, f, ld,
                        s_step, w.xref, 0.25 * skin * skin, w.flag);
-}
-
-void launch_baoab_post(const BatchDev &bd, double *p, const double *f, double dt, hipStream_t st) {
-    hipLaunchKernelGGL(k_baoab_post, dim3(nblk(3 * (size_t)bd.N, 256)), dim3(256), 0, st, bd.N, p, f, dt);
 }
 
 void launch_bbk_pre(const BatchDev &bd, double *x, double *p, const double *f, const LangevinDev &ld, int s_step,
