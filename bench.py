@@ -463,14 +463,14 @@ def pmc_probe(S, W, J, S_slabs, shape=None):
 # for the kernel source it was taken on (sha256 of the file) and the kernel shape it was
 # measured in; otherwise the traffic is reported as null.
 _ADJ_SHA = "68c4b49b7e00b758b4222b6720aebb5031bb3fd6fcf2c24e5568892801b662e6"
-_KER_SHA = "c19664ef0c4cc2d9f3bf66c74bf80b0925495b3f9c5922a91715fee59b5b1308"
+_KER_SHA = "dea994712dcb7e9ad2ef45dfff772f3f8d5c8e2ccf1596780e6d74b70b7199bd"
 TRAFFIC = {
     "adjoint": ("paper_2212_10508_amd/csrc/adjoint.hip", _ADJ_SHA, "atom",
                 {(45, 0, 12, 1): 5359.1, (45, 0, 12, 2): 7839.5}),
     "dedr": ("paper_2212_10508_amd/csrc/kernels.hip", _KER_SHA, "pair",
              {(45, 0, 12, 1): 419.7, (45, 0, 12, 2): 419.7}),
     "density": ("paper_2212_10508_amd/csrc/kernels.hip", _KER_SHA, "pair",
-                {(45, 0, 12, 1): 146.1, (45, 0, 12, 2): 256.6}),
+                {(45, 0, 12, 1): 146.3, (45, 0, 12, 2): 257.1}),
 }
 
 
