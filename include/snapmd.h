@@ -240,18 +240,18 @@ int parareal_iterate(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *
  * found while enqueueing is returned by parareal_iterate_async itself).  At most 3
  * iterations may wait to be collected (SNAPMD_EINVAL beyond).
  * Overlap: a corrected iteration that follows a pipelined one with the same window,
- * state buffers, box, potentials, Langevin parameters, slab chunks and sweep width copies
- * prev := cur chunk by chunk, each as soon as the previous iteration's on-device sweep
- * has passed that chunk, so its fine propagation starts while the previous sweep finishes
- * its last chunks.  The results are bitwise those of the same parareal_iterate calls.
- * cur and prev of an iteration are complete when its result has been collected (the
- * collect makes `stream` wait for them).  Any other call (another window or parameter
- * set, and every other entry point of the library except the getters, snapmd_profile,
- * snapmd_use_graphs and snapmd_parareal_collect) first waits on the host for the
- * pipelined iterations in flight; their results stay queued.  Window initialisations and sweeps driven from the
- * host are not pipelined: they complete at the call and queue their result.  Use one
- * stream for a chain.  The caller owns the speculation: an iteration enqueued before the
- * previous result was collected used the window given at its call. */
+ * state buffers, box, potentials, Langevin parameters, slab chunks, sweep width and
+ * stream copies prev := cur chunk by chunk, each as soon as the previous iteration's
+ * on-device sweep has passed that chunk, so its fine propagation starts while the
+ * previous sweep finishes its last chunks.  The results are bitwise those of the same
+ * parareal_iterate calls.  cur and prev of an iteration are complete when its result has
+ * been collected (the collect makes `stream` wait for them).  Any other call (another
+ * window, parameter set or stream, and every other entry point of the library except the
+ * getters, snapmd_profile, snapmd_use_graphs and snapmd_parareal_collect) first waits on
+ * the host for the pipelined iterations in flight; their results stay queued.  Window
+ * initialisations and sweeps driven from the host are not pipelined: they complete at the
+ * call and queue their result.  The caller owns the speculation: an iteration enqueued
+ * before the previous result was collected used the window given at its call. */
 int parareal_iterate_async(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs,
                            const snapmd_batch *batch, const snapmd_langevin *lang, int32_t L, int32_t n_in,
                            int32_t n_fi, int32_t n_slots, double *q_prev, double *p_prev, double *q_cur,

@@ -1010,7 +1010,8 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
     const bool lds_sweep = !bbk && !csnap && (mcK > 0 || sweep_fits_lds(N));
     // A pipelined iteration (on-device sweep, corrected iteration) overlaps the previous
     // pipelined iteration when everything the two share is the same (chain_key: window,
-    // chunk plan, state buffers, box, potentials, Langevin parameters, sweep width), so
+    // chunk plan, state buffers, box, potentials, Langevin parameters, sweep width,
+    // stream), so
     // neither allocates nor rewrites what the other reads; every other call first waits
     // for all pipelined iterations in flight.
     const bool pipelined = async && !init && lds_sweep;
@@ -1028,7 +1029,8 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
                d(box[0]), d(box[1]), d(box[2]), d(fp.A), d(fp.d), d(fp.c), d(fp.c0), d(fp.c1), d(fp.c2),
                d(fpc.A), d(fpc.d), d(fpc.c), d(fpc.c0), d(fpc.c1), d(fpc.c2), (uint64_t)mcK, d(lang->dt),
                d(lang->gamma), d(lang->mass), d(lang->T_sys[0]), lang->seed, (uint64_t)lang->noise_id_sys[0],
-               (uint64_t)lang->scheme, snap ? (uint64_t)snap->twojmax : 0, snap ? d(snap->rcut) : 0};
+               (uint64_t)lang->scheme, snap ? (uint64_t)snap->twojmax : 0, snap ? d(snap->rcut) : 0,
+               u(st)};  // a chain on another stream would share the workspace unordered
         for (int v : plan) key.push_back((uint64_t)v);
         chained = ctx->chain_end && key == ctx->chain_key;
     }

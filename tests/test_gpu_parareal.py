@@ -548,6 +548,18 @@ def test_pipelined_iterations_match_synchronous(S):
     assert chain + [d4] == ref
     for a, b in zip(host(q, pp, qp, ppv), host(q2, pp2, qp2, ppv2)):
         assert np.array_equal(a, b)
+    # a call on another stream starts a new chain (it waits for the one in flight)
+    q, pp, qp, ppv = fresh()
+    side = torch.cuda.Stream()
+    ctx.parareal_iterate_async(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
+    ctx.parareal_iterate_async(qp, ppv, q, pp, box, L, 0, N, 1e100, stream=side, **kw)
+    two = [ctx.parareal_collect(), ctx.parareal_collect(stream=side)]
+    side.synchronize()
+    q2, pp2, qp2, ppv2 = fresh()
+    ref = [ctx.parareal_iterate(qp2, ppv2, q2, pp2, box, L, 0, N, 1e100, **kw) for _ in range(2)]
+    assert two == ref
+    for a, b in zip(host(q, pp, qp, ppv), host(q2, pp2, qp2, ppv2)):
+        assert np.array_equal(a, b)
     # a window initialisation through the queue completes at the call
     q3 = torch.zeros_like(q)
     p3 = torch.zeros_like(q)
