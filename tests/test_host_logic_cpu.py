@@ -145,3 +145,37 @@ def test_shape_tuner_keeps_builtin_within_noise(monkeypatch):
         shape, table = tune.tune_kernel_shapes(ctx, 8, run, lambda: 1.0 if ctx.shape == bad else 0.0, passes=1)
         assert shape == (builtin if want_builtin else fast) and ctx.shape == shape
         assert [t["passed"] for t in table if tuple(t["shape"]) == bad] == [False]
+
+
+def _bench_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_bench_density_segment_count_follows_the_kernel_rule():
+    """Waves per tile of the density pass as the kernel's segment rule gives them (column
+    chains cut at the register budget; the last column rides on the previous column's
+    last segment where it fits with its chain copy): the counts the automatic density
+    split is decided by."""
+    B = _bench_module()
+    want = {(2, 45): 1, (4, 21): 3, (6, 45): 3, (8, 45): 4, (8, 28): 8, (8, 21): 11, (10, 45): 9, (14, 45): 18}
+    for (J, acc), n in want.items():
+        assert B.dens_segments(J, acc) == n, (J, acc)
+
+
+def test_bench_traffic_resolves_the_automatic_split_per_chunk():
+    """With density split 0 each chunk's launches take the measured bytes of the split they
+    run: 26-slab chunks of 1025 atoms (1,668 density waves) unsplit, the 12-slab chunk
+    (772) split, on 1,024 SIMDs."""
+    B = _bench_module()
+    per1, per2 = 5000.0, 7000.0
+    # the per-shape figures (measured, keyed by the source hash) replaced by two constants
+    B.traffic_per_unit = lambda kernel, shape: ({1: per1, 2: per2}.get(tuple(shape)[3]), "atom")
+    chunks = [26 * 1025, 26 * 1025, 12 * 1025]
+    got, _ = B.traffic_per_launch("adjoint", (45, 0, 12, 0), chunks, 26.0, 1024, 8)
+    assert got == pytest.approx((2 * 26 * 1025 * per1 + 12 * 1025 * per2) / 3)
+    got1, _ = B.traffic_per_launch("adjoint", (45, 0, 12, 1), chunks, 26.0, 1024, 8)
+    assert got1 == pytest.approx(64 * 1025 * per1 / 3)
