@@ -554,6 +554,8 @@ def main():
                     help="slab chunks of the 64-slab window (default %s, the plan the committed kernel trace "
                          "covers; %s with --sync); 'builtin' for the library's own plan" % (DEFAULT_PLAN, DEFAULT_PLAN_SYNC))
     ap.add_argument("--sweep-workgroups", type=int, default=0, help="coarse sweep width (0: built in)")
+    ap.add_argument("--fine-streams", type=int, default=2,
+                    help="SNAP streams of an iteration (2: odd slab chunks beside the even ones)")
     ap.add_argument("--shape", default=None,
                     help="kernel shape density_acc,dedr_stage_atoms,adjoint_waves[,density_parts] of the SNAP passes "
                          "(no shape "
@@ -670,6 +672,7 @@ def main():
     shape_info["shape"] = list(shape)
     log("kernel shape %s (%s)" % (shape, shape_info["source"]))
     ctx.set_sweep_workgroups(args.sweep_workgroups)
+    ctx.set_fine_streams(args.fine_streams)
     use_plan = None if (args.tune or args.plan == "builtin") else [int(v) for v in args.plan.split(",")]
     if use_plan:  # set before the warmup, which captures the plan's launch sequences
         ctx.set_chunk_plan(use_plan)
@@ -826,7 +829,8 @@ def main():
                    "atoms": n, "slabs": S_slabs, "L": L, "twojmax": J, "pairs": n_pairs,
                    "mean_neighbours": n_pairs / atoms, "chunk_plan": chunk_plan,
                    "sweep_workgroups": ctx.sweep_workgroups(n), "builtin_plan": builtin_plan,
-                   "iterations": "one call each" if args.sync else "pipelined"},
+                   "iterations": "one call each" if args.sync else "pipelined",
+                   "fine_streams": args.fine_streams},
         "roofline": {"bound": "alu", "kernel": kname[dom], "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "traffic_bytes_per_" + unit: (traffic / (atoms / len(chunk_plan)) /

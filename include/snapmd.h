@@ -422,15 +422,24 @@ int snapmd_chunk_plan(snapmd_ctx *ctx, int32_t S, int32_t N, int32_t *sizes, int
  * embedding derivatives every step; K trades the compute per workgroup against the cost of
  * the exchanges and against compute units taken from the SNAP propagation running beside
  * it.  snapmd_set_sweep_workgroups(ctx, K) asks for K workgroups in later calls of
- * parareal_iterate (0: the built-in choice, 8 or 16); K = 1 asks for the one-workgroup sweep
- * (positions, embedding derivatives and lists in the local memory of one compute unit, no
- * exchanges), which fits systems of up to about 1,500 atoms; a K that the system cannot
- * use (more than 256 atoms per workgroup, or a local-memory tile over 160 KB) falls back to
- * the built-in choice.  0 <= K <= 64, else SNAPMD_EINVAL.  snapmd_sweep_workgroups writes
+ * parareal_iterate (0: the built-in choice, the fewest from 8 up with at most 128 atoms
+ * each); K = 1 asks for the one-workgroup sweep (positions, embedding derivatives and
+ * lists in the local memory of one compute unit, no exchanges), which fits systems of up
+ * to about 1,500 atoms; a K that the system cannot use (more than 128 atoms per
+ * workgroup, or a local-memory tile over 160 KB) falls back to the built-in choice.  0 <= K <= 64, else SNAPMD_EINVAL.  snapmd_sweep_workgroups writes
  * the width a system of N atoms would get into *K (1: one workgroup, 0: driven from the
  * host).  Results do not depend on K beyond the rounding order of the partial sums of the
  * adaptive criterion, which every K combines in a fixed order. */
 int snapmd_set_sweep_workgroups(snapmd_ctx *ctx, int32_t K);
+
+/* SNAP streams of a parareal iteration of one system (tuning, not part of the method):
+ * with 2 (the built-in value) the odd slab chunks run their SNAP propagation on a stream
+ * of their own, with a second workspace, beside the even ones, so that one chunk's small
+ * kernels and partial rounds fill the compute units the other leaves idle; with 1 every
+ * chunk runs on the caller's stream.  Kernel timing (snapmd_profile) runs iterations on
+ * one stream.  n in {1, 2}, else SNAPMD_EINVAL.  Results do not depend on n (every chunk
+ * starts from a freshly built neighbour list in either workspace). */
+int snapmd_set_fine_streams(snapmd_ctx *ctx, int32_t n);
 int snapmd_sweep_workgroups(snapmd_ctx *ctx, int32_t N, int32_t *K);
 
 /* Measurement support (not part of the propagation):

@@ -63,10 +63,17 @@ struct snapmd_ctx {
     size_t cap_atoms = 0, cap_atoms_c = 0, cap_atoms_cs = 0;  // fine, coarse lists, coarse SNAP
     Work w, wc;                                   // SNAP / second-stream Finnis-Sinclair workspaces
     double *d_f = nullptr, *d_fc = nullptr;       // their force scratch [3][N]
+    // the second SNAP workspace of a parareal iteration (its odd slab chunks run on their
+    // own stream beside the even ones); fine_streams 1 runs every chunk on the caller's
+    Work w2;
+    double *d_f2 = nullptr;
+    size_t cap_atoms2 = 0;
+    int fine_streams = 2;
+    hipStream_t fine2_stream = nullptr;
     // per-system Langevin arrays
     DBuf<double> d_sig, d_sb0, d_sb1;
     DBuf<int64_t> d_step0;
-    DBuf<int64_t> seg_step0[2];                   // step offsets advanced by a segmented replay (per workspace)
+    DBuf<int64_t> seg_step0[3];                   // step offsets advanced by a segmented replay (per workspace)
     DBuf<int> d_noise;
     std::map<int, SnapDevTables> snap;
     std::map<int, KernelShape> shapes;            // kernel shapes set per twojmax (default otherwise)
@@ -118,7 +125,7 @@ struct snapmd_ctx {
         std::vector<double> key;
         int n_cells = 0;
         bool any = false;
-    } cs, csc;
+    } cs, csc, cs2;
     std::vector<uint64_t> noise_key;              // (n_in, S, L, N, seed, noise_id) it holds
     KernelProf prof;
     // captured launch sequences of run_langevin, keyed by everything baked into them
@@ -128,13 +135,13 @@ struct snapmd_ctx {
         hipGraphExec_t exec;
         uint64_t last_use;
     };
-    std::vector<GraphEntry> graphs[2];   // one cache per workspace (w, wc): the two may be
-    hipStream_t cap_stream[2] = {};      // launched from different host threads
+    std::vector<GraphEntry> graphs[3];   // one cache per workspace (w, wc, w2): they may be
+    hipStream_t cap_stream[3] = {};      // launched from different host threads
     std::mutex err_mu;
     hipStream_t sweep_stream = nullptr;  // the coarse sweep, overlapping the batched propagation
     hipStream_t coarse_stream = nullptr; // the batched coarse propagation of a parareal iteration
     std::vector<hipEvent_t> pipe_ev;
-    uint64_t graph_clock[2] = {};
+    uint64_t graph_clock[3] = {};
     std::vector<int> chunk_override;     // slab chunks set by snapmd_set_chunk_plan (empty: built in)
     int sweep_k_override = 0;            // sweep workgroups set by snapmd_set_sweep_workgroups (0: built in)
     DBuf<int4> d_ws;                     // Wigner-Seitz lattice of each system
@@ -231,10 +238,10 @@ int upload(snapmd_ctx *ctx, T *dst, const T *src, size_t n, hipStream_t st) {
     return SNAPMD_OK;
 }
 
-int ensure_atoms(snapmd_ctx *ctx, size_t N) {
-    if (N <= ctx->cap_atoms) return SNAPMD_OK;
+// The SNAP workspace w (ctx->w or ctx->w2) with its force buffer f and capacity cap_atoms.
+int ensure_atoms_ws(snapmd_ctx *ctx, Work &w, double *&f, size_t &cap_atoms, size_t N) {
+    if (N <= cap_atoms) return SNAPMD_OK;
     size_t cap = std::max<size_t>(N, 64);
-    Work &w = ctx->w;
     w.Pcap = cap * kMaxNeigh;
     int rc;
     if ((rc = dalloc(ctx, &w.nbr, cap * kMaxNeigh))) return rc;
@@ -252,13 +259,18 @@ int ensure_atoms(snapmd_ctx *ctx, size_t N) {
     if ((rc = dalloc(ctx, &w.u, (size_t)n_half(kMaxJ) * cap))) return rc;
     if ((rc = dalloc(ctx, &w.ytil, (size_t)n_half(kMaxJ) * cap))) return rc;
     if ((rc = dalloc(ctx, &w.epart, (size_t)kMaxYChunks * cap))) return rc;
-    if ((rc = dalloc(ctx, &ctx->d_f, 3 * cap))) return rc;
+    if ((rc = dalloc(ctx, &f, 3 * cap))) return rc;
     if ((rc = dalloc(ctx, &w.xref, 3 * cap))) return rc;
     if ((rc = dalloc(ctx, &w.cell_of, cap))) return rc;
     if ((rc = dalloc(ctx, &w.cell_atoms, cap))) return rc;
-    ctx->cap_atoms = cap;
+    cap_atoms = cap;
     return SNAPMD_OK;
 }
+
+int ensure_atoms(snapmd_ctx *ctx, size_t N) { return ensure_atoms_ws(ctx, ctx->w, ctx->d_f, ctx->cap_atoms, N); }
+
+// Index of a workspace in the per-workspace state (graph caches, cell grids, offsets).
+int ws_index(const snapmd_ctx *ctx, const Work &w) { return &w == &ctx->wc ? 1 : &w == &ctx->w2 ? 2 : 0; }
 
 // Workspace of the Finnis-Sinclair propagation that runs beside the SNAP one (its own
 // neighbour lists and force buffer; the error bits are shared).
@@ -531,7 +543,8 @@ std::vector<int> window_plan(const snapmd_ctx *ctx, int S, int N) {
 // Cell grids (cell edge >= list cutoff rl, >= 3 cells per edge, else brute force) of the
 // current batch; rebuilt when the batch or the cutoff changes.
 int prepare_cells(snapmd_ctx *ctx, Work &w, BatchDev &bd, double rl, hipStream_t st) {
-    snapmd_ctx::CellState &cs = (&w == &ctx->wc) ? ctx->csc : ctx->cs;
+    const int wi = ws_index(ctx, w);
+    snapmd_ctx::CellState &cs = wi == 1 ? ctx->csc : wi == 2 ? ctx->cs2 : ctx->cs;
     std::vector<double> key(ctx->h_box.begin(), ctx->h_box.end());
     key.insert(key.end(), ctx->h_off.begin(), ctx->h_off.end());
     key.push_back(rl);
@@ -689,7 +702,7 @@ int replay_range(snapmd_ctx *ctx, Work &w, double *f, int potential, const Batch
                                (uint64_t)sd.shape.adj_waves, (uint64_t)sd.shape.dens_parts};
         key.insert(key.end(), std::begin(sk), std::end(sk));
     }
-    const int ci = (&w == &ctx->wc) ? 1 : 0;
+    const int ci = ws_index(ctx, w);
     auto &cache = ctx->graphs[ci];
     const uint64_t now = ++ctx->graph_clock[ci];
     for (auto &g : cache)
@@ -748,7 +761,7 @@ int run_langevin_prepared(snapmd_ctx *ctx, Work &w, double *f, int potential, co
     int rc;
     if (n_steps <= kGraphMaxSteps)
         return replay_range(ctx, w, f, potential, bd, fp, sd, ld, 0, n_steps, n_steps, true, x, p, st);
-    const int ci = (&w == &ctx->wc) ? 1 : 0;
+    const int ci = ws_index(ctx, w);
     DBuf<int64_t> &so = ctx->seg_step0[ci];
     if (so.n < (size_t)bd.n_sys || !so.p)
         return fail(ctx, SNAPMD_EINVAL, "segment step offsets not prepared for %d systems", bd.n_sys);
@@ -800,7 +813,8 @@ int prepare_langevin(snapmd_ctx *ctx, const snapmd_langevin *lang, int S, const 
     int rc;
     if ((rc = ensure(ctx, ctx->d_sig, S)) || (rc = ensure(ctx, ctx->d_step0, S)) || (rc = ensure(ctx, ctx->d_noise, S)) ||
         (rc = ensure(ctx, ctx->d_sb0, S)) || (rc = ensure(ctx, ctx->d_sb1, S)) ||
-        (rc = ensure(ctx, ctx->seg_step0[0], S)) || (rc = ensure(ctx, ctx->seg_step0[1], S)))
+        (rc = ensure(ctx, ctx->seg_step0[0], S)) || (rc = ensure(ctx, ctx->seg_step0[1], S)) ||
+        (rc = ensure(ctx, ctx->seg_step0[2], S)))
         return rc;
     // uploaded only when they change (a pipelined parareal iteration must not rewrite
     // arrays the previous one still reads on another stream)
@@ -1171,14 +1185,38 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
         if ((rc = prepare_propagation_cells(ctx, ctx->w, SNAPMD_POT_FS_SNAP, bd, fp, sd, st)) ||
             (rc = prepare_propagation_cells(ctx, ctx->wc, potC, bd, fpc, sdc, st)))
             return rc;
+        // Two SNAP streams (ctx->fine_streams 2, several chunks): the odd chunks run on a
+        // stream of their own with the second workspace, beside the even ones, so that one
+        // chunk's small kernels and partial adjoint round fill the CUs the other leaves
+        // idle.  Not while kernel timing is on (the timed launches are the caller's).
+        const bool two = ctx->fine_streams == 2 && ne > 1 && !ctx->prof.enabled;
+        if (two) {
+            const int maxc = *std::max_element(plan.begin(), plan.end());
+            if ((rc = ensure_atoms_ws(ctx, ctx->w2, ctx->d_f2, ctx->cap_atoms2, (size_t)maxc * N))) return rc;
+            ctx->w2.status = ctx->w.status;
+            if (!ctx->w2.flag) {
+                if ((rc = dalloc(ctx, &ctx->w2.flag, 1))) return rc;
+                HIPCHK(hipMemset(ctx->w2.flag, 0, sizeof(int)));
+            }
+            if (!ctx->fine2_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->fine2_stream, hipStreamNonBlocking));
+            HIPCHK(hipStreamWaitEvent(ctx->fine2_stream, ctx->pipe_ev[ne + 1], 0));
+            if ((rc = prepare_propagation_cells(ctx, ctx->w2, SNAPMD_POT_FS_SNAP, bd, fp, sd, ctx->fine2_stream)))
+                return rc;
+        }
+        auto side_of = [&](int c) { return two && (c & 1) ? 1 : 0; };
         std::mutex mu;
         std::condition_variable cv;
-        int done_f = 0, done_c = 0;  // chunks whose fine / coarse propagation is queued
-        int done_copy = 0;           // chunks whose prev := cur copy is queued (pipelined)
-        bool stop = false;           // a thread failed: the others queue nothing more
+        int done_c = 0;                                // chunks whose coarse propagation is queued
+        std::vector<char> done_f(ne, 0), copied(ne, 0);  // chunk c's fine propagation / prev := cur copy queued
+        bool stop = false;                             // a thread failed: the others queue nothing more
         auto publish = [&](int &counter, int value) {
             std::lock_guard<std::mutex> lk(mu);
             counter = value;
+            cv.notify_all();
+        };
+        auto mark = [&](std::vector<char> &flags, int c) {
+            std::lock_guard<std::mutex> lk(mu);
+            flags[c] = 1;
             cv.notify_all();
         };
         auto halt = [&]() {
@@ -1201,7 +1239,7 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
                 }
                 if (pipelined) {
                     std::unique_lock<std::mutex> lk(mu);
-                    cv.wait(lk, [&] { return stop || done_copy > c; });
+                    cv.wait(lk, [&] { return stop || copied[c]; });
                     if (stop) return SNAPMD_OK;
                 }
                 BatchDev bc;
@@ -1226,7 +1264,7 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
             for (int c = 0, s0 = 0; c < (int)plan.size(); s0 += plan[c], ++c) {
                 {
                     std::unique_lock<std::mutex> lk(mu);
-                    cv.wait(lk, [&] { return stop || (done_f > c && done_c > c); });
+                    cv.wait(lk, [&] { return stop || (done_f[c] && done_c > c); });
                     if (stop) return SNAPMD_OK;
                 }
                 const int nc = plan[c];
@@ -1249,7 +1287,72 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
             HIPCHK(hipEventRecord(ctx->pipe_ev[ne], s2));
             return SNAPMD_OK;
         };
-        int rc1 = SNAPMD_OK, rc2 = SNAPMD_OK, rc3 = SNAPMD_OK;
+        // the SNAP propagation of chunk c on SNAP stream `side` (0: the caller's, 1: the
+        // second), with the prev := cur copy of its window slots first (pipelined)
+        auto fine_chunk = [&](int c, int s0) -> int {
+            const int side = side_of(c);
+            hipStream_t fst = side ? ctx->fine2_stream : st;
+            Work &fw = side ? ctx->w2 : ctx->w;
+            double *ff = side ? ctx->d_f2 : ctx->d_f;
+            BatchDev bc;
+            LangevinDev lc;
+            const int nc = chunk_of(c, s0, bc, lc);
+            const size_t o = 3 * (size_t)N * s0;
+            if (c > 0 && side_of(c - 1) != side) {
+                // slot s0 comes with chunk c - 1's copy, queued on the other SNAP stream
+                if (pipelined) {
+                    std::unique_lock<std::mutex> lk(mu);
+                    cv.wait(lk, [&] { return stop || copied[c - 1]; });
+                    if (stop) return SNAPMD_OK;
+                    lk.unlock();
+                    HIPCHK(hipStreamWaitEvent(fst, ctx->pipe_ev[2 * ne + 2 + c - 1], 0));
+                }
+                // An iteration that does not follow a pipelined one starts its sweep only
+                // when chunk 0 is done: chunk 1 waits for it instead of slowing it down
+                if (c == 1 && !chained) {
+                    std::unique_lock<std::mutex> lk(mu);
+                    cv.wait(lk, [&] { return stop || done_f[0]; });
+                    if (stop) return SNAPMD_OK;
+                    lk.unlock();
+                    HIPCHK(hipStreamWaitEvent(fst, ctx->pipe_ev[0], 0));
+                }
+            }
+            if (pipelined) {
+                // prev := cur on the window slots s0 .. s0 + nc (s0 + 1 .. for c > 0: slot s0
+                // came with the previous chunk): all written by the previous iteration's
+                // sweep up to the end of its chunk c
+                if (chained) HIPCHK(hipStreamWaitEvent(fst, ctx->sweep_chunk_ev[c], 0));
+                const int a = c == 0 ? 0 : s0 + 1, b = s0 + nc;
+                const size_t first = (size_t)(n_in + a) * slot, len = (size_t)(b - a + 1) * slot * sizeof(double);
+                HIPCHK(hipMemcpyAsync(q_prev + first, q_cur + first, len, hipMemcpyDeviceToDevice, fst));
+                HIPCHK(hipMemcpyAsync(p_prev + first, p_cur + first, len, hipMemcpyDeviceToDevice, fst));
+                HIPCHK(hipEventRecord(ctx->pipe_ev[2 * ne + 2 + c], fst));
+                mark(copied, c);
+            }
+            launch_slabs_to_batch(nc, N, qs + s0 * slot, ctx->pr_xf.p + o, fst);
+            launch_slabs_to_batch(nc, N, ps + s0 * slot, ctx->pr_pf.p + o, fst);
+            int r;
+            if ((r = run_langevin_graph(ctx, fw, ff, SNAPMD_POT_FS_SNAP, bc, fp, sd, lc, L, ctx->pr_xf.p + o,
+                                        ctx->pr_pf.p + o, fst)))
+                return r;
+            HIPCHK(hipEventRecord(ctx->pipe_ev[c], fst));
+            mark(done_f, c);
+            return SNAPMD_OK;
+        };
+        // the chunks of one SNAP stream, in order
+        auto fine_side = [&](int side) -> int {
+            for (int c = 0, s0 = 0; c < (int)plan.size(); s0 += plan[c], ++c) {
+                if (side_of(c) != side) continue;
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    if (stop) return SNAPMD_OK;
+                }
+                int r;
+                if ((r = fine_chunk(c, s0))) return r;
+            }
+            return SNAPMD_OK;
+        };
+        int rc1 = SNAPMD_OK, rc2 = SNAPMD_OK, rc3 = SNAPMD_OK, rc4 = SNAPMD_OK;
         std::thread t_coarse([&] {
             rc3 = coarse_side();
             if (rc3) halt();
@@ -1258,49 +1361,36 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
             rc2 = sweep_side();
             if (rc2) halt();
         });
-        for (int c = 0, s0 = 0; c < (int)plan.size(); s0 += plan[c], ++c) {  // fine (caller's stream)
-            BatchDev bc;
-            LangevinDev lc;
-            const int nc = chunk_of(c, s0, bc, lc);
-            const size_t o = 3 * (size_t)N * s0;
-            if (pipelined) {
-                // prev := cur on the window slots s0 .. s0 + nc (s0 + 1 .. for c > 0: slot s0
-                // came with the previous chunk): all written by the previous iteration's
-                // sweep up to the end of its chunk c
-                if (chained) HIPCHK(hipStreamWaitEvent(st, ctx->sweep_chunk_ev[c], 0));
-                const int a = c == 0 ? 0 : s0 + 1, b = s0 + nc;
-                const size_t first = (size_t)(n_in + a) * slot, len = (size_t)(b - a + 1) * slot * sizeof(double);
-                HIPCHK(hipMemcpyAsync(q_prev + first, q_cur + first, len, hipMemcpyDeviceToDevice, st));
-                HIPCHK(hipMemcpyAsync(p_prev + first, p_cur + first, len, hipMemcpyDeviceToDevice, st));
-                HIPCHK(hipEventRecord(ctx->pipe_ev[2 * ne + 2 + c], st));
-                publish(done_copy, c + 1);
-            }
-            launch_slabs_to_batch(nc, N, qs + s0 * slot, ctx->pr_xf.p + o, st);
-            launch_slabs_to_batch(nc, N, ps + s0 * slot, ctx->pr_pf.p + o, st);
-            if ((rc1 = run_langevin_graph(ctx, ctx->w, ctx->d_f, SNAPMD_POT_FS_SNAP, bc, fp, sd, lc, L,
-                                          ctx->pr_xf.p + o, ctx->pr_pf.p + o, st)))
-                break;
-            const hipError_t e = hipEventRecord(ctx->pipe_ev[c], st);
-            if (e != hipSuccess) {
-                rc1 = fail(ctx, SNAPMD_EHIP, "hipEventRecord failed: %s", hipGetErrorString(e));
-                break;
-            }
-            publish(done_f, c + 1);
-        }
+        std::thread t_fine2;
+        if (two)
+            t_fine2 = std::thread([&] {
+                const hipError_t e = hipSetDevice(ctx->device);
+                Quiet quiet;
+                rc4 = e == hipSuccess ? fine_side(1) : fail(ctx, SNAPMD_EHIP, "hipSetDevice failed");
+                if (rc4) halt();
+            });
+        rc1 = fine_side(0);
         if (pipelined && !rc1) {
             // the neighbour-list error bits once the fine propagation is done (sticky: set by
-            // the kernels, cleared by snapmd_sync and snapmd_parareal_collect on an error)
+            // the kernels, cleared by snapmd_sync and snapmd_parareal_collect on an error);
+            // the caller's stream waits for the second SNAP stream's chunks first
+            if (two && t_fine2.joinable()) t_fine2.join();
             double *h = ctx->h_async + snapmd_ctx::kAsyncStride * aslot;
-            hipError_t e = hipMemcpyAsync(reinterpret_cast<int *>(h + 16), ctx->w.status, sizeof(int),
-                                          hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipEventRecord(ctx->pipe_ev[3 * ne + 2], st);
+            hipError_t e = hipSuccess;
+            for (int c = 0; c < ne && e == hipSuccess && !rc4; ++c)
+                if (side_of(c)) e = hipStreamWaitEvent(st, ctx->pipe_ev[c], 0);
+            if (e == hipSuccess && !rc4)
+                e = hipMemcpyAsync(reinterpret_cast<int *>(h + 16), ctx->w.status, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess && !rc4) e = hipEventRecord(ctx->pipe_ev[3 * ne + 2], st);
             if (e != hipSuccess) rc1 = fail(ctx, SNAPMD_EHIP, "reading the list status failed: %s", hipGetErrorString(e));
         }
         if (rc1) halt();
+        if (t_fine2.joinable()) t_fine2.join();
         t_coarse.join();
         t_sweep.join();
-        if (pipelined && (rc1 || rc2 || rc3)) (void)hipDeviceSynchronize();  // nothing left in flight
+        if (pipelined && (rc1 || rc2 || rc3 || rc4)) (void)hipDeviceSynchronize();  // nothing left in flight
         if (rc1) return rc1;
+        if (rc4) return rc4;
         if (rc3) return rc3;
         if (rc2) return rc2;
         if (pipelined) {
@@ -2433,6 +2523,14 @@ int snapmd_set_sweep_workgroups(snapmd_ctx *ctx, int32_t K) {
     if (const int rc_ = drain(ctx)) return rc_;
     if (K < 0 || K > 64) return fail(ctx, SNAPMD_EINVAL, "sweep workgroups: need 0 <= K <= 64 (got %d)", K);
     ctx->sweep_k_override = K;
+    return SNAPMD_OK;
+}
+
+int snapmd_set_fine_streams(snapmd_ctx *ctx, int32_t n) {
+    if (!ctx) return SNAPMD_EINVAL;
+    if (const int rc_ = drain(ctx)) return rc_;
+    if (n != 1 && n != 2) return fail(ctx, SNAPMD_EINVAL, "fine streams: need 1 or 2 (got %d)", n);
+    ctx->fine_streams = n;
     return SNAPMD_OK;
 }
 

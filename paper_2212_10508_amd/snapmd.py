@@ -137,6 +137,8 @@ def lib():
     L.snapmd_chunk_plan.restype = C.c_int
     L.snapmd_set_sweep_workgroups.argtypes = [P, i32]
     L.snapmd_set_sweep_workgroups.restype = C.c_int
+    L.snapmd_set_fine_streams.argtypes = [P, i32]
+    L.snapmd_set_fine_streams.restype = C.c_int
     L.snapmd_sweep_workgroups.argtypes = [P, i32, C.POINTER(i32)]
     L.snapmd_sweep_workgroups.restype = C.c_int
     _lib = L
@@ -536,6 +538,11 @@ class Context:
         """Workgroups of the on-device coarse sweep in later parareal_iterate calls (0: the
         built-in choice)."""
         self._check(lib().snapmd_set_sweep_workgroups(self.h, int(K)))
+
+    def set_fine_streams(self, n):
+        """SNAP streams of a parareal iteration of one system in later calls (2: the odd slab
+        chunks on a second stream beside the even ones; 1: all on the caller's stream)."""
+        self._check(lib().snapmd_set_fine_streams(self.h, int(n)))
 
     def sweep_workgroups(self, N):
         """The sweep width a system of N atoms gets (0: one workgroup or host-driven)."""

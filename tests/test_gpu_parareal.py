@@ -215,8 +215,9 @@ def test_bench_configuration_sampled(S):
 
 
 def test_chunk_plans_give_identical_iterates(S):
-    """The slab chunks of the pipelined iteration (tuning only) do not change its results:
-    one corrected iteration under several plans, bitwise against the built-in plan."""
+    """The slab chunks of the pipelined iteration and the number of SNAP streams they run on
+    (tuning only) do not change its results: one corrected iteration under several plans,
+    on one and on two streams, bitwise against the built-in plan on one."""
     x, p, box, kw, prop = _setup(J=4, seed=8)
     N, L = 8, 3
     n = x.shape[1]
@@ -226,15 +227,21 @@ def test_chunk_plans_give_identical_iterates(S):
     q0[0], p0[0] = dev(x), dev(p)
     ctx.parareal_iterate(None, None, q0, p0, box, L, 0, N, 1e100, **kw)
     results = []
-    for plan in (None, [8], [4, 4], [5, 2, 1], [1] * 8):
-        ctx.set_chunk_plan(plan)
-        if plan:
-            assert ctx.chunk_plan(N, n) == plan
-        q, pp = q0.clone(), p0.clone()
-        qp, ppv = torch.zeros_like(q), torch.zeros_like(q)
-        d, nfi = ctx.parareal_iterate(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
-        torch.cuda.synchronize()
-        results.append((d, nfi, q.cpu().numpy(), pp.cpu().numpy()))
+    # one SNAP stream, or the odd chunks on a second one beside the even ones
+    for streams in (1, 2):
+        ctx.set_fine_streams(streams)
+        for plan in (None, [8], [4, 4], [5, 2, 1], [1] * 8):
+            ctx.set_chunk_plan(plan)
+            if plan:
+                assert ctx.chunk_plan(N, n) == plan
+            q, pp = q0.clone(), p0.clone()
+            qp, ppv = torch.zeros_like(q), torch.zeros_like(q)
+            d, nfi = ctx.parareal_iterate(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
+            torch.cuda.synchronize()
+            results.append((d, nfi, q.cpu().numpy(), pp.cpu().numpy()))
+    with pytest.raises(S.SnapmdError):
+        ctx.set_fine_streams(3)
+    ctx.set_fine_streams(2)
     ctx.set_chunk_plan(None)
     d0, n0, qa, pa = results[0]
     for d, nfi, qb, pb in results[1:]:
@@ -515,9 +522,11 @@ def test_pipelined_iterations_match_synchronous(S):
         ctx.set_sweep_workgroups(width)
         q, pp, qp, ppv = fresh()
         ref = []
+        ctx.set_fine_streams(1)  # the reference on one SNAP stream, the chain on two
         for _ in range(K):
             ref.append(ctx.parareal_iterate(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw))
         want = host(q, pp, qp, ppv)
+        ctx.set_fine_streams(2)
         q, pp, qp, ppv = fresh()
         got = []
         ctx.parareal_iterate_async(qp, ppv, q, pp, box, L, 0, N, 1e100, **kw)
