@@ -1307,14 +1307,16 @@ int parareal_one(snapmd_ctx *ctx, const snapmd_snap *snap, const snapmd_fs *fs, 
                     lk.unlock();
                     HIPCHK(hipStreamWaitEvent(fst, ctx->pipe_ev[2 * ne + 2 + c - 1], 0));
                 }
-                // An iteration that does not follow a pipelined one starts its sweep only
-                // when chunk 0 is done: chunk 1 waits for it instead of slowing it down
-                if (c == 1 && !chained) {
+                // In an iteration that does not follow a pipelined one the sweep waits for
+                // each chunk in turn from the start, so the chunks run one after another:
+                // chunk c waits for chunk c - 1 instead of sharing the device with it and
+                // delaying the sweep of both (only the order of the launches changes)
+                if (!chained) {
                     std::unique_lock<std::mutex> lk(mu);
-                    cv.wait(lk, [&] { return stop || done_f[0]; });
+                    cv.wait(lk, [&] { return stop || done_f[c - 1]; });
                     if (stop) return SNAPMD_OK;
                     lk.unlock();
-                    HIPCHK(hipStreamWaitEvent(fst, ctx->pipe_ev[0], 0));
+                    HIPCHK(hipStreamWaitEvent(fst, ctx->pipe_ev[c - 1], 0));
                 }
             }
             if (pipelined) {
