@@ -422,8 +422,8 @@ int snapmd_chunk_plan(snapmd_ctx *ctx, int32_t S, int32_t N, int32_t *sizes, int
  * embedding derivatives every step; K trades the compute per workgroup against the cost of
  * the exchanges and against compute units taken from the SNAP propagation running beside
  * it.  snapmd_set_sweep_workgroups(ctx, K) asks for K workgroups in later calls of
- * parareal_iterate (0: the built-in choice, the fewest from 8 up with at most 128 atoms
- * each); K = 1 asks for the one-workgroup sweep (positions, embedding derivatives and
+ * parareal_iterate (0: the built-in choice, the fewest from 8 up with at most 64 atoms
+ * each, else with at most 128); K = 1 asks for the one-workgroup sweep (positions, embedding derivatives and
  * lists in the local memory of one compute unit, no exchanges), which fits systems of up
  * to about 1,500 atoms; a K that the system cannot use (more than 128 atoms per
  * workgroup, or a local-memory tile over 160 KB) falls back to the built-in choice.  0 <= K <= 64, else SNAPMD_EINVAL.  snapmd_sweep_workgroups writes

@@ -1365,6 +1365,12 @@ int sweep_mc_workgroups(int N, int want) {
         return K <= 64 && A <= kMcMaxAtoms && sweep_mc_lds_bytes(N, A) + kMcStaticLds <= 160 * 1024;
     };
     if (want > 0 && fits(want)) return want;
+    // built in: the fewest from 8 up with at most 64 atoms each (pipelined iterations of
+    // 64 slabs of 1025 atoms, where the sweep sets the pace: 2.7 % faster with 17
+    // workgroups than with 9 of up to 128 atoms, widths 17 to 20 within 0.5 %), else
+    // with at most 128 atoms each
+    for (int K = 8; K <= 64; ++K)
+        if (fits(K) && (N + K - 1) / K <= 64) return K;
     for (int K = 8; K <= 64; ++K)
         if (fits(K)) return K;
     return 0;

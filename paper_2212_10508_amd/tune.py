@@ -113,9 +113,10 @@ def tune_chunk_plan(ctx, run_iteration, S, N, n_cus, passes=2, limit=16, log=Non
     return chosen, times
 
 
-def tune_sweep_width(ctx, run_iteration, N, widths=(1, 9, 12, 16), passes=2, log=None):
+def tune_sweep_width(ctx, run_iteration, N, widths=None, passes=2, log=None):
     """Time run_iteration() with the on-device coarse sweep spread over each of the given
-    numbers of workgroups (those the system of N atoms cannot use are skipped), in
+    numbers of workgroups (by default 1 and the widths of at most 128, 96, 64, 48 and 32
+    atoms per workgroup; those the system of N atoms cannot use are skipped), in
     interleaved passes after one untimed run each, and keep the fastest (1: the
     one-workgroup sweep, where the system fits in one compute unit).  Wider sweeps do
     less work per workgroup between exchanges but exchange among more workgroups and take
@@ -125,6 +126,8 @@ def tune_sweep_width(ctx, run_iteration, N, widths=(1, 9, 12, 16), passes=2, log
     builtin = ctx.sweep_workgroups(N)
     if builtin <= 1:
         return builtin, {}
+    if widths is None:
+        widths = [1] + sorted({-(-N // a) for a in (128, 96, 64, 48, 32)})
     cands = []
     for K in [builtin] + list(widths):
         ctx.set_sweep_workgroups(K)

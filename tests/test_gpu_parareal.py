@@ -271,9 +271,10 @@ def test_sweep_widths_give_identical_states(S):
     N, L = 4, 3
     ctx = S.context()
     results = []
+    builtin = -(-n // 64)  # the fewest from 8 up with at most 64 atoms each: 11 for 687
     for K in (0, 8, 16, 32, 43, 1):
         ctx.set_sweep_workgroups(K)
-        assert ctx.sweep_workgroups(n) == (K or 8)
+        assert ctx.sweep_workgroups(n) == (K or builtin)
         q = torch.zeros((N + 1, 3, n), dtype=torch.float64, device="cuda")
         pp = torch.zeros_like(q)
         q[0], pp[0] = dev(x), dev(p)
@@ -294,7 +295,7 @@ def test_sweep_widths_give_identical_states(S):
     assert np.abs(qa - qb).max() < 1e-10 and np.abs(pa - pb).max() < 1e-10 * np.abs(pa).max()
     # widths the system cannot use fall back to the built-in one; out of range is refused
     ctx.set_sweep_workgroups(2)
-    assert ctx.sweep_workgroups(n) == 8
+    assert ctx.sweep_workgroups(n) == builtin
     with pytest.raises(S.SnapmdError):
         ctx.set_sweep_workgroups(65)
     ctx.set_sweep_workgroups(0)

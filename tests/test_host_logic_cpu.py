@@ -51,7 +51,11 @@ class _FakeCtx:
         self.k = K
 
     def sweep_workgroups(self, N):
-        return self.k if self.k in (1, 8, 16) else 8
+        # the library's rule: 1, or 8 to 64 workgroups of at most 128 atoms; otherwise the
+        # built-in width (the fewest from 8 up with at most 64 atoms each)
+        if self.k == 1 or (8 <= self.k <= 64 and -(-N // self.k) <= 128):
+            return self.k
+        return max(8, -(-N // 64))
 
 
 def test_tuner_keeps_the_fastest_plan(monkeypatch):
@@ -74,13 +78,17 @@ def test_sweep_width_tuner_picks_the_fastest(monkeypatch):
     ctx = _FakeCtx([29, 22, 13], None)
     clock = {"t": 0.0}
     monkeypatch.setattr(tune.time, "perf_counter", lambda: clock["t"])
-    width_cost = {1: 0.30, 8: 0.19, 16: 0.193}
+    # default candidates at 1025 atoms: 1, the built-in 17 and the widths of at most 128,
+    # 96, 64, 48 and 32 atoms per workgroup (9, 11, 17, 22, 33)
+    for width_cost, best in (({1: 0.30, 9: 0.195, 11: 0.194, 17: 0.19, 22: 0.192, 33: 0.2}, 17),
+                             ({1: 0.30, 9: 0.195, 11: 0.194, 17: 0.19, 22: 0.188, 33: 0.2}, 22)):
+        ctx.k = 0
 
-    def run():
-        clock["t"] += width_cost[ctx.k if ctx.k else 8]
+        def run():
+            clock["t"] += width_cost[ctx.k if ctx.k else 17]
 
-    K, times = tune.tune_sweep_width(ctx, run, 1025)
-    assert K == 8 and ctx.k == 8 and set(times) == {1, 8, 16}
+        K, times = tune.tune_sweep_width(ctx, run, 1025)
+        assert K == best and ctx.k == best and set(times) == {1, 9, 11, 17, 22, 33}
 
 
 def test_bench_refuses_more_than_one_gpu():
