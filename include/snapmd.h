@@ -418,18 +418,19 @@ int snapmd_set_chunk_plan(snapmd_ctx *ctx, const int32_t *sizes, int32_t n);
 int snapmd_chunk_plan(snapmd_ctx *ctx, int32_t S, int32_t N, int32_t *sizes, int32_t *n);
 
 /* Width of the on-device coarse sweep (tuning, not part of the method).  Systems of 512 to
- * 65,535 atoms are swept by K workgroups (one compute unit each) that exchange positions and
- * embedding derivatives every step; K trades the compute per workgroup against the cost of
- * the exchanges and against compute units taken from the SNAP propagation running beside
- * it.  snapmd_set_sweep_workgroups(ctx, K) asks for K workgroups in later calls of
+ * 65,535 atoms are swept by K workgroups (one compute unit each) that exchange positions
+ * and embedding derivatives every step; K trades the compute per workgroup against the
+ * cost of the exchanges and against compute units taken from the SNAP propagation running
+ * beside it.  snapmd_set_sweep_workgroups(ctx, K) asks for K workgroups in later calls of
  * parareal_iterate (0: the built-in choice, the fewest from 8 up with at most 64 atoms
- * each, else with at most 128); K = 1 asks for the one-workgroup sweep (positions, embedding derivatives and
- * lists in the local memory of one compute unit, no exchanges), which fits systems of up
- * to about 1,500 atoms; a K that the system cannot use (more than 128 atoms per
- * workgroup, or a local-memory tile over 160 KB) falls back to the built-in choice.  0 <= K <= 64, else SNAPMD_EINVAL.  snapmd_sweep_workgroups writes
- * the width a system of N atoms would get into *K (1: one workgroup, 0: driven from the
- * host).  Results do not depend on K beyond the rounding order of the partial sums of the
- * adaptive criterion, which every K combines in a fixed order. */
+ * each, else with at most 128); K = 1 asks for the one-workgroup sweep (positions,
+ * embedding derivatives and lists in the local memory of one compute unit, no exchanges),
+ * which fits systems of up to about 1,500 atoms; a K that the system cannot use (more than
+ * 128 atoms per workgroup, or a local-memory tile over 160 KB) falls back to the built-in
+ * choice.  0 <= K <= 64, else SNAPMD_EINVAL.  snapmd_sweep_workgroups writes the width a
+ * system of N atoms would get into *K (1: one workgroup, 0: driven from the host).
+ * Results do not depend on K beyond the rounding order of the partial sums of the adaptive
+ * criterion, which every K combines in a fixed order. */
 int snapmd_set_sweep_workgroups(snapmd_ctx *ctx, int32_t K);
 
 /* SNAP streams of a parareal iteration of one system (tuning, not part of the method):
