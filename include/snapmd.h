@@ -432,16 +432,18 @@ int snapmd_chunk_plan(snapmd_ctx *ctx, int32_t S, int32_t N, int32_t *sizes, int
  * Results do not depend on K beyond the rounding order of the partial sums of the adaptive
  * criterion, which every K combines in a fixed order. */
 int snapmd_set_sweep_workgroups(snapmd_ctx *ctx, int32_t K);
+int snapmd_sweep_workgroups(snapmd_ctx *ctx, int32_t N, int32_t *K);
 
 /* SNAP streams of a parareal iteration of one system (tuning, not part of the method):
  * with 2 (the built-in value) the odd slab chunks run their SNAP propagation on a stream
  * of their own, with a second workspace, beside the even ones, so that one chunk's small
  * kernels and partial rounds fill the compute units the other leaves idle; with 1 every
- * chunk runs on the caller's stream.  Kernel timing (snapmd_profile) runs iterations on
- * one stream.  n in {1, 2}, else SNAPMD_EINVAL.  Results do not depend on n (every chunk
+ * chunk runs on the caller's stream.  An iteration that does not follow a pipelined one
+ * (every synchronous call) runs its chunks one after another on the two streams, since
+ * its sweep waits for each chunk in turn.  Kernel timing (snapmd_profile) runs iterations
+ * on one stream.  n in {1, 2}, else SNAPMD_EINVAL.  Results do not depend on n (every chunk
  * starts from a freshly built neighbour list in either workspace). */
 int snapmd_set_fine_streams(snapmd_ctx *ctx, int32_t n);
-int snapmd_sweep_workgroups(snapmd_ctx *ctx, int32_t N, int32_t *K);
 
 /* Measurement support (not part of the propagation):
  * snapmd_profile(ctx, s) with s >= 1 starts recording HIP events around every s-th launch
